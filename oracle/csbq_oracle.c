@@ -1,0 +1,609 @@
+/*
+ * csbq_oracle.c -- plain, slow FP64 CPU oracle for the Stokes single-layer
+ * (stokeslet) and double-layer (stresslet) velocity potentials of
+ * panel-discretised bodies.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  It shares no code,
+ * header, table or constant with the GPU library; it is the independent
+ * definition the GPU results are compared against.
+ *
+ * What it computes (Section 3.2.1, the element integral and its Nystrom form):
+ *
+ *   u_K(x) = sum_k  int_{I_k} int_0^{2 pi} K(x - y(s,t); n(s,t)) sigma~_k(s,t) J(s,t) dt ds
+ *
+ * with the kernels of Section 2 (single layer S(r) = (I/|r| + r r^T/|r|^3)/(8 pi),
+ * double layer D(r;n) = -(3/(4 pi)) (r.n) r r^T/|r|^5, r = x - y).  The surface
+ * is the paper's Eq. for the surface coordinates, y = x_c + eps (e1 cos t + e2 sin t),
+ * with e2 = (x_c'/|x_c'|) x e1, where x_c, eps, e1 are the degree-(ns-1)
+ * polynomial interpolants of the samples at the panel's Gauss-Legendre nodes
+ * (Section 3.1) and e1 is re-orthonormalised against the tangent wherever it is
+ * evaluated (Section 3.1.1, last paragraph).  J = |dy/ds x dy/dt| and the normal
+ * is normal_sign * (dy/dt x dy/ds)/J.  sigma~ is the tensor interpolant of the
+ * nodal density: polynomial in s, trigonometric in t (Section 3.1; the Nyquist
+ * mode enters as cos(nt t/2), the real part of the paper's one-sided sum).
+ *
+ * How (independent of any method in the paper beyond these definitions):
+ *  - polynomial interpolants are Legendre series whose coefficients come from
+ *    the discrete Legendre transform at the GL nodes;
+ *  - dy/ds is taken by the complex-step derivative of the analytic map
+ *    s -> y(s,t), which is exact to rounding;
+ *  - a (target, element) pair whose distance exceeds the oracle's own
+ *    conservative far test uses the plain tensor rule (GL x trapezoid),
+ *    whose error there is below 1e-16;
+ *  - every other pair is integrated by adaptive tensor Gauss-Legendre on
+ *    parameter cells (20-point rule accepted when it agrees with a 13-point
+ *    rule to an absolute tolerance), and the element that carries an
+ *    on-surface target is split around the target with Duffy maps on the
+ *    cells touching it (the 1/r singularity becomes bounded);
+ *  - element contributions are summed with Neumaier compensation.
+ * A target that coincides with a node contributes nothing through that node
+ * in the plain tensor rule (the self term is defined as zero).
+ */
+#include <complex.h>
+#include <tgmath.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OMAXNS 32
+#define OMAXNT 256
+#define OMAXDEPTH 30
+#define NQ 8 /* six outputs, sum of term magnitudes, rounding bound of the (r.n) factor */
+
+typedef double complex cplx;
+typedef long double complex lcplx;
+
+static const double OPI = 3.14159265358979323846264338327950288;
+
+/* ------------------------------------------------------------------ */
+/* Gauss-Legendre rule on [-1,1] by Newton iteration on P_n            */
+/* ------------------------------------------------------------------ */
+void oracle_gauss_legendre(int n, double* x, double* w)
+{
+    for (int i = 0; i < n; ++i) {
+        long double z = cosl(3.14159265358979323846264338327950288L * (i + 0.75L) / (n + 0.5L));
+        long double pn = 0, pm = 0;
+        for (int it = 0; it < 200; ++it) {
+            long double p0 = 1.0L, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                long double p2 = ((2.0L * k - 1.0L) * z * p1 - (k - 1.0L) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            pn = p1;
+            pm = (n == 1) ? 1.0L : p0;
+            long double dp = n * (z * pn - pm) / (z * z - 1.0L);
+            long double dz = pn / dp;
+            z -= dz;
+            if (fabsl(dz) < 1e-19L) break;
+        }
+        long double p0 = 1.0L, p1 = z;
+        for (int k = 2; k <= n; ++k) {
+            long double p2 = ((2.0L * k - 1.0L) * z * p1 - (k - 1.0L) * p0) / k;
+            p0 = p1;
+            p1 = p2;
+        }
+        pn = p1;
+        pm = (n == 1) ? 1.0L : p0;
+        long double dp = n * (z * pn - pm) / (z * z - 1.0L);
+        x[n - 1 - i] = (double)z;
+        w[n - 1 - i] = (double)(2.0L / ((1.0L - z * z) * dp * dp));
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* element description                                                */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int ns, nt, sign;
+    double a, c;                       /* panel interval in s */
+    double gx[OMAXNS], gw[OMAXNS];     /* GL rule on [-1,1] */
+    /* Legendre coefficients of the centerline data: xc(3), eps(1), e1(3) */
+    double cx[3][OMAXNS], ce[OMAXNS], cf[3][OMAXNS];
+    /* tensor coefficients of the density: [k (Legendre)][l][comp], cos/sin */
+    double *dca, *dcb;                 /* each ns*(nt/2+1)*3 */
+    /* nodes */
+    double *ny, *nn, *nw;              /* [ns*nt][3], [ns*nt][3], [ns*nt] */
+    const double* sig;                 /* nodal density [ns*nt][3] */
+    double ball_c[3], ball_r, eps_max, len, area, sigmax;
+    int64_t node0;                     /* global id of this element's node 0 */
+} oelem;
+
+typedef struct {
+    int n1, n2;
+    double x1[24], w1[24], x2[24], w2[24];
+} orules;
+
+static orules RULES;
+static int rules_ready = 0;
+
+static void rules_init(void)
+{
+    if (rules_ready) return;
+    RULES.n1 = 20;
+    RULES.n2 = 13;
+    oracle_gauss_legendre(RULES.n1, RULES.x1, RULES.w1);
+    oracle_gauss_legendre(RULES.n2, RULES.x2, RULES.w2);
+    rules_ready = 1;
+}
+
+typedef struct {
+    double sum[6], comp[6];
+} nacc; /* Neumaier accumulator */
+
+static void nacc_add(nacc* a, const double v[6])
+{
+    for (int q = 0; q < 6; ++q) {
+        double t = a->sum[q] + v[q];
+        if (fabs(a->sum[q]) >= fabs(v[q]))
+            a->comp[q] += (a->sum[q] - t) + v[q];
+        else
+            a->comp[q] += (v[q] - t) + a->sum[q];
+        a->sum[q] = t;
+    }
+}
+
+/* agreement test of two cell estimates: absolute tolerance, floored by the
+   rounding level of the sums themselves (8e-15 of the summed magnitudes) */
+static int close6(const double a[NQ], const double b[NQ], double tol)
+{
+    double floor_ = 8e-15 * fmax(a[6], b[6]) + 2.0 * fmax(a[7], b[7]);
+    double t = fmax(tol, floor_);
+    for (int q = 0; q < 6; ++q)
+        if (!(fabs(a[q] - b[q]) <= t)) return 0;
+    return 1;
+}
+
+/* physical extents used only to choose which parameter direction to split */
+typedef struct {
+    double sx, tx; /* physical length per unit s and per radian */
+} oaniso;
+
+static const double HSTEP = 1e-30;
+
+#define RT double
+#define CT cplx
+#define SFX(n) n##_d
+#define ULP 1.1102230246251565e-16
+#include "oracle_geom.inc"
+#undef RT
+#undef CT
+#undef SFX
+#undef ULP
+#define RT long double
+#define CT lcplx
+#define SFX(n) n##_l
+#define ULP 5.421010862427522e-20L
+#include "oracle_geom.inc"
+#undef RT
+#undef CT
+#undef SFX
+#undef ULP
+
+/* ------------------------------------------------------------------ */
+/* element set-up                                                      */
+/* ------------------------------------------------------------------ */
+static void elem_setup(oelem* e, int ns, int nt, int sign, double a, double c, const double* xc, const double* ep,
+                       const double* e1, const double* sig, int64_t node0)
+{
+    e->ns = ns;
+    e->nt = nt;
+    e->sign = sign;
+    e->a = a;
+    e->c = c;
+    e->sig = sig;
+    e->node0 = node0;
+    oracle_gauss_legendre(ns, e->gx, e->gw);
+    /* discrete Legendre transform: c_k = (2k+1)/2 sum_i w_i P_k(x_i) f_i */
+    double P[OMAXNS][OMAXNS];
+    for (int i = 0; i < ns; ++i) {
+        cplx p[OMAXNS];
+        legendre_cd_d(ns, e->gx[i], p, 0);
+        for (int k = 0; k < ns; ++k) P[i][k] = creal(p[k]);
+    }
+    for (int k = 0; k < ns; ++k) {
+        double f = 0.5 * (2 * k + 1);
+        double vx[3] = {0, 0, 0}, vf[3] = {0, 0, 0}, ve = 0;
+        for (int i = 0; i < ns; ++i) {
+            double wp = e->gw[i] * P[i][k];
+            for (int d = 0; d < 3; ++d) {
+                vx[d] += wp * xc[i * 3 + d];
+                vf[d] += wp * e1[i * 3 + d];
+            }
+            ve += wp * ep[i];
+        }
+        for (int d = 0; d < 3; ++d) {
+            e->cx[d][k] = f * vx[d];
+            e->cf[d][k] = f * vf[d];
+        }
+        e->ce[k] = f * ve;
+    }
+    /* density: Fourier in t at every s-node, then Legendre in s */
+    int L = nt / 2;
+    e->dca = (double*)calloc((size_t)ns * (L + 1) * 3, sizeof(double));
+    e->dcb = (double*)calloc((size_t)ns * (L + 1) * 3, sizeof(double));
+    double* fa = (double*)calloc((size_t)ns * (L + 1) * 3, sizeof(double));
+    double* fb = (double*)calloc((size_t)ns * (L + 1) * 3, sizeof(double));
+    for (int i = 0; i < ns; ++i)
+        for (int l = 0; l <= L; ++l)
+            for (int d = 0; d < 3; ++d) {
+                long double va = 0, vb = 0;
+                for (int j = 0; j < nt; ++j) {
+                    long double th = 2.0L * 3.14159265358979323846264338327950288L * j / nt;
+                    long double sv = sig[(i * nt + j) * 3 + d];
+                    va += sv * cosl(l * th);
+                    vb += sv * sinl(l * th);
+                }
+                double fac = (l == 0 || l == L) ? 1.0 / nt : 2.0 / nt;
+                fa[(i * (L + 1) + l) * 3 + d] = (double)(fac * va);
+                fb[(i * (L + 1) + l) * 3 + d] = (l == L) ? 0.0 : (double)(fac * vb);
+            }
+    for (int k = 0; k < ns; ++k) {
+        double f = 0.5 * (2 * k + 1);
+        for (int l = 0; l <= L; ++l)
+            for (int d = 0; d < 3; ++d) {
+                double va = 0, vb = 0;
+                for (int i = 0; i < ns; ++i) {
+                    double wp = e->gw[i] * P[i][k];
+                    va += wp * fa[(i * (L + 1) + l) * 3 + d];
+                    vb += wp * fb[(i * (L + 1) + l) * 3 + d];
+                }
+                e->dca[(k * (L + 1) + l) * 3 + d] = f * va;
+                e->dcb[(k * (L + 1) + l) * 3 + d] = f * vb;
+            }
+    }
+    free(fa);
+    free(fb);
+    /* nodes, normals, smooth weights */
+    e->ny = (double*)malloc(sizeof(double) * ns * nt * 3);
+    e->nn = (double*)malloc(sizeof(double) * ns * nt * 3);
+    e->nw = (double*)malloc(sizeof(double) * ns * nt);
+    double hs = 0.5 * (c - a);
+    e->area = 0;
+    e->eps_max = 0;
+    e->len = 0;
+    for (int i = 0; i < ns; ++i) {
+        srow_d row;
+        double s = 0.5 * (a + c) + hs * e->gx[i];
+        srow_make_d(e, s, &row);
+        double ev = fabs(creal(row.E));
+        if (ev > e->eps_max) e->eps_max = ev;
+        for (int j = 0; j < nt; ++j) {
+            double t = 2.0 * OPI * j / nt;
+            double y[3], jn[3], J, sg[3];
+            point_eval_d(e, &row, t, y, jn, &J, sg);
+            int q = i * nt + j;
+            for (int d = 0; d < 3; ++d) {
+                e->ny[q * 3 + d] = y[d];
+                e->nn[q * 3 + d] = jn[d] / J;
+            }
+            e->nw[q] = J * e->gw[i] * hs * 2.0 * OPI / nt;
+            e->area += e->nw[q];
+        }
+        /* centerline speed from the complex-step frame */
+        cplx X[3], E, f1[3], f2[3];
+        frame_at_d(e, s + I * HSTEP, X, &E, f1, f2);
+        double sp = sqrt(pow(cimag(X[0]) / HSTEP, 2) + pow(cimag(X[1]) / HSTEP, 2) + pow(cimag(X[2]) / HSTEP, 2));
+        e->len += sp * e->gw[i] * hs;
+    }
+    /* bounding ball from a fine sample of the interpolated surface */
+    double cen[3] = {0, 0, 0};
+    for (int q = 0; q < ns * nt; ++q)
+        for (int d = 0; d < 3; ++d) cen[d] += e->ny[q * 3 + d] / (ns * nt);
+    double rmax = 0;
+    for (int i = 0; i <= 64; ++i) {
+        srow_d row;
+        srow_make_d(e, a + (c - a) * i / 64.0, &row);
+        for (int j = 0; j < 64; ++j) {
+            double t = 2.0 * OPI * j / 64;
+            double y[3], jn[3], J, sg[3];
+            point_eval_d(e, &row, t, y, jn, &J, sg);
+            double dd = sqrt(pow(y[0] - cen[0], 2) + pow(y[1] - cen[1], 2) + pow(y[2] - cen[2], 2));
+            if (dd > rmax) rmax = dd;
+        }
+    }
+    for (int d = 0; d < 3; ++d) e->ball_c[d] = cen[d];
+    e->ball_r = rmax * 1.05 + 1e-3 * e->eps_max;
+    e->sigmax = 0;
+    for (int q = 0; q < ns * nt * 3; ++q)
+        if (fabs(sig[q]) > e->sigmax) e->sigmax = fabs(sig[q]);
+}
+
+static void elem_free(oelem* e)
+{
+    free(e->dca);
+    free(e->dcb);
+    free(e->ny);
+    free(e->nn);
+    free(e->nw);
+}
+
+/* ------------------------------------------------------------------ */
+/* one (target, element) contribution                                   */
+/* ------------------------------------------------------------------ */
+static void smooth_sum(const oelem* e, const double x[3], nacc* acc)
+{
+    double out[NQ] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int q = 0; q < e->ns * e->nt; ++q) kernel_add_d(x, e->ny + 3 * q, e->nn + 3 * q, e->sig + 3 * q, e->nw[q], out);
+    nacc_add(acc, out);
+}
+
+static double elem_tol(const oelem* e, double rel)
+{
+    double sc = (e->sigmax > 0 ? e->sigmax : 1.0) * e->area / (2.0 * e->ball_r);
+    return rel * sc;
+}
+
+static void elem_adaptive(const oelem* e, const double x[3], double rel, nacc* acc)
+{
+    oaniso an;
+    an.sx = e->len / (e->c - e->a);
+    an.tx = e->eps_max > 0 ? e->eps_max : 1e-300;
+    double tol = elem_tol(e, rel);
+    /* initial cells of roughly unit physical aspect */
+    int nt0 = (int)ceil(2.0 * OPI * an.tx / (e->len > 0 ? e->len : 1.0));
+    if (nt0 < 4) nt0 = 4;
+    if (nt0 > 128) nt0 = 128;
+    int ns0 = (int)ceil(e->len / (2.0 * OPI * an.tx / nt0));
+    if (ns0 < 1) ns0 = 1;
+    if (ns0 > 64) ns0 = 64;
+    for (int i = 0; i < ns0; ++i)
+        for (int j = 0; j < nt0; ++j)
+            adapt_rect_d(e, x, e->a + (e->c - e->a) * i / ns0, e->a + (e->c - e->a) * (i + 1) / ns0,
+                       2.0 * OPI * j / nt0, 2.0 * OPI * (j + 1) / nt0, tol, 0, &an, acc);
+}
+
+/* element that carries the target as its node (i0, j0): the target and every
+   quadrature point are formed in long double, the cells touching the target
+   use Duffy maps */
+static void elem_singular(const oelem* e, int i0, int j0, double rel, nacc* acc)
+{
+    oaniso an;
+    an.sx = e->len / (e->c - e->a);
+    an.tx = e->eps_max > 0 ? e->eps_max : 1e-300;
+    double tol = elem_tol(e, rel);
+    long double s0 = 0.5L * ((long double)e->a + e->c) + 0.5L * ((long double)e->c - e->a) * e->gx[i0];
+    long double t0 = 2.0L * 3.14159265358979323846264338327950288L * j0 / e->nt;
+    srow_l row;
+    srow_make_l(e, s0, &row);
+    long double x[3], jn[3], J;
+    double sg[3];
+    point_eval_l(e, &row, t0, x, jn, &J, sg);
+    double eps0 = fabs((double)creal(row.E));
+    double hmin = fmin((double)(s0 - e->a), (double)(e->c - s0));
+    double dth = hmin * an.sx / (eps0 > 0 ? eps0 : 1e-300);
+    if (dth > 0.5 * OPI) dth = 0.5 * OPI;
+    if (dth < 2.0 * OPI / 256) dth = 2.0 * OPI / 256;
+    int ntc = 2 * (int)ceil(OPI / dth);
+    long double dthl = 2.0L * 3.14159265358979323846264338327950288L / ntc;
+    long double hs = fminl((long double)hmin, dthl * eps0 / an.sx);
+    long double sb[5];
+    int nsb = 0;
+    sb[nsb++] = e->a;
+    if (s0 - hs > (long double)e->a) sb[nsb++] = s0 - hs;
+    sb[nsb++] = s0;
+    if (s0 + hs < (long double)e->c) sb[nsb++] = s0 + hs;
+    sb[nsb++] = e->c;
+    for (int i = 0; i + 1 < nsb; ++i) {
+        long double sa = sb[i], sc = sb[i + 1];
+        if (!(sc > sa)) continue;
+        int touches_s = (sa == s0 || sc == s0);
+        for (int j = 0; j < ntc; ++j) {
+            /* cells [t0-dth,t0] and [t0,t0+dth] touch the target angle */
+            long double ta = t0 + dthl * (j - ntc / 2), tc = ta + dthl;
+            int touches_t = (j == ntc / 2 - 1 || j == ntc / 2);
+            if (!(touches_s && touches_t)) {
+                adapt_rect_l(e, x, sa, sc, ta, tc, tol, 0, &an, acc);
+                continue;
+            }
+            /* rectangle with a corner at the target: two Duffy triangles */
+            long double A[2] = {s0, t0};
+            long double so = (sa == s0) ? sc : sa;
+            long double to = (j == ntc / 2) ? tc : ta;
+            long double P1[2] = {so, t0}, Q1[2] = {so, to};
+            long double P2[2] = {so, to}, Q2[2] = {s0, to};
+            adapt_duffy_l(e, x, A, P1, Q1, 0, 1, 0, 1, tol, 0, acc);
+            adapt_duffy_l(e, x, A, P2, Q2, 0, 1, 0, 1, tol, 0, acc);
+        }
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* geometry building from flat arrays                                  */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int n_elem, ns, nt;
+    oelem* el;
+} ogeom;
+
+static int geom_build(ogeom* g, int n_bodies, const int* n_panels, const int* normal_sign, const double* s_break,
+                      const double* xc, const double* eps, const double* e1, int ns, int nt, const double* sigma)
+{
+    if (ns < 2 || ns > OMAXNS || nt < 2 || nt > OMAXNT || (nt & 1)) return -1;
+    rules_init();
+    int ne = 0;
+    for (int b = 0; b < n_bodies; ++b) ne += n_panels[b];
+    g->n_elem = ne;
+    g->ns = ns;
+    g->nt = nt;
+    g->el = (oelem*)calloc(ne, sizeof(oelem));
+    int k = 0, sbo = 0;
+    int64_t node0 = 0;
+    for (int b = 0; b < n_bodies; ++b) {
+        for (int p = 0; p < n_panels[b]; ++p, ++k) {
+            elem_setup(&g->el[k], ns, nt, normal_sign[b], s_break[sbo + p], s_break[sbo + p + 1],
+                       xc + (size_t)k * ns * 3, eps + (size_t)k * ns, e1 + (size_t)k * ns * 3,
+                       sigma + (size_t)node0 * 3, node0);
+            node0 += ns * nt;
+        }
+        sbo += n_panels[b] + 1;
+    }
+    return 0;
+}
+
+static void geom_free(ogeom* g)
+{
+    for (int k = 0; k < g->n_elem; ++k) elem_free(&g->el[k]);
+    free(g->el);
+}
+
+static int far_test(const oelem* e, const double x[3])
+{
+    double d = sqrt(pow(x[0] - e->ball_c[0], 2) + pow(x[1] - e->ball_c[1], 2) + pow(x[2] - e->ball_c[2], 2)) -
+               e->ball_r;
+    double need = fmax(4.0 * e->len, 8.0 * e->eps_max);
+    return d >= need;
+}
+
+/* ------------------------------------------------------------------ */
+/* public entry points (ctypes)                                        */
+/* ------------------------------------------------------------------ */
+
+/* Nodes, unit normals and smooth weights of every element, node order
+   body, panel, s-node, angle. */
+int oracle_nodes(int n_bodies, const int* n_panels, const int* normal_sign, const double* s_break, const double* xc,
+                 const double* eps, const double* e1, int ns, int nt, double* y, double* nrm, double* w)
+{
+    int ne = 0;
+    for (int b = 0; b < n_bodies; ++b) ne += n_panels[b];
+    double* zero = (double*)calloc((size_t)ne * ns * nt * 3, sizeof(double));
+    ogeom g;
+    if (geom_build(&g, n_bodies, n_panels, normal_sign, s_break, xc, eps, e1, ns, nt, zero)) {
+        free(zero);
+        return -1;
+    }
+    for (int k = 0; k < g.n_elem; ++k) {
+        const oelem* e = &g.el[k];
+        size_t o = (size_t)e->node0;
+        memcpy(y + 3 * o, e->ny, sizeof(double) * 3 * ns * nt);
+        memcpy(nrm + 3 * o, e->nn, sizeof(double) * 3 * ns * nt);
+        memcpy(w + o, e->nw, sizeof(double) * ns * nt);
+    }
+    geom_free(&g);
+    free(zero);
+    return 0;
+}
+
+/* Plain tensor rule over every node (the smooth Nystrom sum of Section 3.2.1),
+   self term zero.  Targets with tgt_node >= 0 sit on that node. */
+int oracle_smooth_sum(int n_bodies, const int* n_panels, const int* normal_sign, const double* s_break,
+                      const double* xc, const double* eps, const double* e1, int ns, int nt, const double* sigma,
+                      int64_t n_tgt, const double* x, const int64_t* tgt_node, double* u_sl, double* u_dl,
+                      int nthreads)
+{
+    ogeom g;
+    if (geom_build(&g, n_bodies, n_panels, normal_sign, s_break, xc, eps, e1, ns, nt, sigma)) return -1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t t = 0; t < n_tgt; ++t) {
+        double xt[3];
+        if (tgt_node && tgt_node[t] >= 0) {
+            int64_t nd = tgt_node[t];
+            const oelem* e = &g.el[nd / (ns * nt)];
+            memcpy(xt, e->ny + 3 * (nd - e->node0), sizeof xt);
+        } else
+            memcpy(xt, x + 3 * t, sizeof xt);
+        nacc acc;
+        memset(&acc, 0, sizeof acc);
+        for (int k = 0; k < g.n_elem; ++k) smooth_sum(&g.el[k], xt, &acc);
+        for (int d = 0; d < 3; ++d) {
+            u_sl[3 * t + d] = acc.sum[d] + acc.comp[d];
+            u_dl[3 * t + d] = acc.sum[3 + d] + acc.comp[3 + d];
+        }
+    }
+    geom_free(&g);
+    return 0;
+}
+
+/* The layer potentials themselves (the element integrals, evaluated to
+   ~rel_tol of each element's scale).  force_adaptive != 0 disables the far
+   test (every pair integrated adaptively). */
+int oracle_eval(int n_bodies, const int* n_panels, const int* normal_sign, const double* s_break, const double* xc,
+                const double* eps, const double* e1, int ns, int nt, const double* sigma, int64_t n_tgt,
+                const double* x, const int64_t* tgt_node, double* u_sl, double* u_dl, double rel_tol,
+                int force_adaptive, int nthreads)
+{
+    ogeom g;
+    if (geom_build(&g, n_bodies, n_panels, normal_sign, s_break, xc, eps, e1, ns, nt, sigma)) return -1;
+    if (!(rel_tol > 0)) rel_tol = 1e-15;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t t = 0; t < n_tgt; ++t) {
+        double xt[3];
+        int own = -1, i0 = -1, j0 = -1;
+        if (tgt_node && tgt_node[t] >= 0) {
+            int64_t nd = tgt_node[t];
+            own = (int)(nd / (ns * nt));
+            const oelem* e = &g.el[own];
+            int64_t q = nd - e->node0;
+            i0 = (int)(q / nt);
+            j0 = (int)(q % nt);
+            memcpy(xt, e->ny + 3 * q, sizeof xt);
+        } else
+            memcpy(xt, x + 3 * t, sizeof xt);
+        nacc acc;
+        memset(&acc, 0, sizeof acc);
+        for (int k = 0; k < g.n_elem; ++k) {
+            const oelem* e = &g.el[k];
+            if (k == own)
+                elem_singular(e, i0, j0, rel_tol, &acc);
+            else if (!force_adaptive && far_test(e, xt))
+                smooth_sum(e, xt, &acc);
+            else
+                elem_adaptive(e, xt, rel_tol, &acc);
+        }
+        for (int d = 0; d < 3; ++d) {
+            u_sl[3 * t + d] = acc.sum[d] + acc.comp[d];
+            u_dl[3 * t + d] = acc.sum[3 + d] + acc.comp[3 + d];
+        }
+    }
+    geom_free(&g);
+    return 0;
+}
+
+/* Interpolated density and surface quantities at arbitrary (s, t) of one
+   element (for pins of the interpolation itself). */
+int oracle_surface_point(int n_bodies, const int* n_panels, const int* normal_sign, const double* s_break,
+                         const double* xc, const double* eps, const double* e1, int ns, int nt, const double* sigma,
+                         int elem, int n_pts, const double* s, const double* t, double* y, double* nrm, double* J,
+                         double* sg)
+{
+    ogeom g;
+    if (geom_build(&g, n_bodies, n_panels, normal_sign, s_break, xc, eps, e1, ns, nt, sigma)) return -1;
+    if (elem < 0 || elem >= g.n_elem) {
+        geom_free(&g);
+        return -2;
+    }
+    const oelem* e = &g.el[elem];
+    for (int p = 0; p < n_pts; ++p) {
+        srow_d row;
+        srow_make_d(e, s[p], &row);
+        double yy[3], jn[3], JJ, ss[3];
+        point_eval_d(e, &row, t[p], yy, jn, &JJ, ss);
+        for (int d = 0; d < 3; ++d) {
+            y[3 * p + d] = yy[d];
+            nrm[3 * p + d] = jn[d] / JJ;
+            sg[3 * p + d] = ss[d];
+        }
+        J[p] = JJ;
+    }
+    geom_free(&g);
+    return 0;
+}
+
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
