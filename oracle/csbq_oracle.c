@@ -109,7 +109,7 @@ typedef struct {
     /* nodes */
     double *ny, *nn, *nw;              /* [ns*nt][3], [ns*nt][3], [ns*nt] */
     const double* sig;                 /* nodal density [ns*nt][3] */
-    double ball_c[3], ball_r, eps_max, len, area, sigmax;
+    double ball_c[3], ball_r, eps_max, len, area, sigmax, sext; /* sext: surface extent along s */
     int64_t node0;                     /* global id of this element's node 0 */
 } oelem;
 
@@ -266,6 +266,7 @@ static void elem_setup(oelem* e, int ns, int nt, int sign, double a, double c, c
     e->area = 0;
     e->eps_max = 0;
     e->len = 0;
+    e->sext = 0;
     for (int i = 0; i < ns; ++i) {
         srow_d row;
         double s = 0.5 * (a + c) + hs * e->gx[i];
@@ -283,6 +284,8 @@ static void elem_setup(oelem* e, int ns, int nt, int sign, double a, double c, c
             }
             e->nw[q] = J * e->gw[i] * hs * 2.0 * OPI / nt;
             e->area += e->nw[q];
+            double ev_ = fabs(creal(row.E));
+            if (ev_ > 0 && J / ev_ * (c - a) > e->sext) e->sext = J / ev_ * (c - a);
         }
         /* centerline speed from the complex-step frame */
         cplx X[3], E, f1[3], f2[3];
@@ -455,7 +458,13 @@ static int far_test(const oelem* e, const double x[3])
 {
     double d = sqrt(pow(x[0] - e->ball_c[0], 2) + pow(x[1] - e->ball_c[1], 2) + pow(x[2] - e->ball_c[2], 2)) -
                e->ball_r;
-    double need = fmax(4.0 * e->len, 8.0 * e->eps_max);
+    /* theta: the trapezoid rule's error ~exp(-(nt - nt/2) a) is below 1e-16
+       beyond ~8 radii of the cross-section circles; s: for a density of full
+       degree ns-1 the Gauss-Legendre error ~rho^-(ns+1), and on a body whose
+       parameterisation closes up (a sphere in polar angle) rho grows only
+       logarithmically with distance, so the smooth rule is trusted only beyond
+       40 surface extents along s */
+    double need = fmax(40.0 * e->sext, 8.0 * e->eps_max);
     return d >= need;
 }
 
