@@ -1,0 +1,126 @@
+#!/usr/bin/env python3
+"""Benchmark: Stokes single- and double-layer potentials at all surface nodes of
+the pipe-with-spheres workload (torus-arc pipe of 100 panels, 200 spheres of
+radius 0.2; 153,600 nodes = sources = on-surface targets), FP64, quadrature
+tolerance 1e-12.
+
+One step = one full evaluation (near-pair search, gate, corrections, smooth
+sum, reduction) with geometry, density and targets already resident in HBM.
+Prints one JSON line.  Only one GPU is supported.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "layer-potential target evals/sec at rel.err 1e-10 (FP64) and 1e-6 (mixed+MLP)"
+FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 vector peak
+FAR_FLOPS_PER_PAIR = 44          # smooth-sum flops per source-target pair (rsqrt counted once)
+THETA_FLOPS = 280                # special quadrature flops per theta-rule node
+SNODE_FLOPS = 2 * 16 * (102 + 17)  # interpolation to one s-node (density coefficients + centerline data)
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(sc, n_sample, seconds):
+    import numpy as np
+    import oracle
+    rng = np.random.default_rng(12345)
+    nwall = sc.bodies[0].n_panels * sc.ns * sc.nt
+    idx = np.concatenate([rng.choice(nwall, n_sample // 3, replace=False),
+                          nwall + rng.choice(sc.n_nodes - nwall, n_sample - n_sample // 3, replace=False)])
+    threads = oracle.num_threads()
+    t0 = time.time()
+    done = 0
+    chunk = max(threads, 8)
+    while done < len(idx) and time.time() - t0 < seconds:
+        sel = idx[done:done + chunk]
+        oracle.evaluate(sc, None, None, sc.tgt_node[sel])
+        done += len(sel)
+    dt = time.time() - t0
+    return dict(value=done / dt, unit="target evals/s", cores=threads, kind="oracle",
+                sample=f"{done} on-surface targets of the same workload (1/3 wall, 2/3 particle), {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not supported"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import synth
+    import paper_2310_00889_amd as pk
+
+    log("bench: building workload")
+    sc = synth.config2()
+    ev = pk.Evaluator(quad_tol=1e-12, precision=a.precision)
+    ev.set_geometry(sc)
+    sig = torch.from_numpy(sc.sigma).cuda()
+    tn = torch.from_numpy(sc.tgt_node).cuda()
+    T = int(tn.shape[0])
+    usl = torch.empty((T, 3), dtype=torch.float64, device="cuda")
+    udl = torch.empty((T, 3), dtype=torch.float64, device="cuda")
+    log(f"bench: {T} targets, {ev.n_nodes} sources; warmup {a.warmup}")
+    for _ in range(a.warmup):
+        ev.eval(sig, None, tn, usl, udl)
+    torch.cuda.synchronize()
+    log(f"bench: timing {a.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(a.steps):
+        ev.eval(sig, None, tn, usl, udl)
+        log(f"bench: step {k + 1}/{a.steps} enqueued")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    # per-phase times of the last timed step (HIP events on the library's stream)
+    counts = ev.stats()
+    phases = counts["ms"]
+    value = T * a.steps / dt
+    # roofline of the dominant kernel, timed with HIP events on the library's stream
+    dom = max(("far", "corr_full"), key=lambda k: phases.get(k, 0.0))
+    if dom == "far":
+        flops = FAR_FLOPS_PER_PAIR * float(T) * ev.n_nodes
+    else:
+        flops = THETA_FLOPS * float(counts.get("theta_nodes", 0)) + SNODE_FLOPS * float(counts.get("s_nodes", 0))
+    achieved = flops / (phases[dom] * 1e-3) / 1e12
+    roof = dict(kernel="k_far" if dom == "far" else "k_corr_full", bound="alu", achieved=achieved,
+                peak=FP64_PEAK_TFLOPS, unit="TFLOP/s", frac=achieved / FP64_PEAK_TFLOPS, traffic=None)
+    far_ach = FAR_FLOPS_PER_PAIR * float(T) * ev.n_nodes / (phases["far"] * 1e-3) / 1e12
+    out = {
+        "metric": METRIC, "value": value, "unit": "target evals/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": 1e3 * dt / a.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if a.precision == "fp64" else "f32+f64", "data": "synthetic",
+        "config": {"workload": "pipe100-spheres200: torus-arc pipe (R=5, r=1, arc pi, 100 panels) + 200 spheres "
+                               "r=0.2, 16x32 nodes per element, 153,600 sources = on-surface targets",
+                   "quad_tol": 1e-12, "precision": a.precision, "targets": T, "sources": ev.n_nodes},
+        "roofline": roof,
+        "far_roofline": dict(kernel="k_far", bound="alu", achieved=far_ach, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
+                             frac=far_ach / FP64_PEAK_TFLOPS),
+        "phases_ms": phases,
+        "pairs": {k: counts.get(k) for k in ("candidates", "pairs_x2", "pairs_x4", "pairs_full", "theta_nodes",
+                                              "s_nodes")},
+    }
+    if not a.no_cpu_baseline:
+        log("bench: timing the CPU oracle on a sample")
+        out["cpu_baseline"] = cpu_baseline(sc, 240, a.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,151 @@
+/*
+ * csbq.h -- C ABI of the MI355X (gfx950) Stokes layer-potential evaluator.
+ *
+ * Computes, at a set of targets x, the Stokes single-layer (stokeslet) and
+ * double-layer (stresslet) velocity potentials of smooth densities given on
+ * panel-discretised bodies (Malhotra & Barnett, "Efficient convergent boundary
+ * integral methods for slender bodies"):
+ *
+ *   u_S(x) = int S(x - y) sigma(y) dS_y,  S(r) = (I/|r| + r r^T/|r|^3) / (8 pi)
+ *   u_D(x) = int D(x - y; n_y) sigma(y) dS_y,  D(r; n) = -(3/(4 pi)) (r.n) r r^T / |r|^5
+ *
+ * (Section 2, single- and double-layer velocity kernels; viscosity 1).  The
+ * two outputs are returned separately; a caller combines them as needed
+ * (Section 3.2.1: the kernel may be any linear combination of S and D).
+ *
+ * Method (Section 3.2): the smooth Nystrom sum over every node (Eq. for the
+ * Nystrom rule without corrections) plus local corrections for every
+ * (target, element) pair inside the element's near region (Eq. for the
+ * Nystrom rule with corrections): upsampled tensor rules, or the special
+ * quadrature of Sections 3.2.2-3.2.4 (theta-integrals by generalised
+ * Chebyshev rules per distance bracket, adaptive Gauss-Legendre panels in s
+ * for near targets, dyadic + log-singular panels in s for on-surface targets).
+ *
+ * Geometry (Section 3.1): a body is a centerline x_c(s), s in its parameter
+ * interval, cross-section radius eps(s) and orientation vector e1(s)
+ * orthogonal to the centerline, all given by their values at the ns
+ * Gauss-Legendre nodes (ascending) of each panel [s_break[k], s_break[k+1]].
+ * The surface is y(s,t) = x_c + eps (e1 cos t + e2 sin t), e2 = t_c x e1 with
+ * t_c the unit tangent and e1 re-orthonormalised against t_c wherever it is
+ * evaluated (Section 3.1.1).  Surface nodes are the ns GL nodes of each panel
+ * times nt angles t_j = 2 pi j / nt, numbered body-major, then panel, s-node,
+ * angle.  The normal is normal_sign * (dy/dt x dy/ds) / J, J = |dy/ds x dy/dt|;
+ * with normal_sign = +1 it points away from the centerline.  A density is
+ * given by its values at the nodes and interpolated polynomially in s and
+ * trigonometrically in t.
+ *
+ * Conventions for every entry point:
+ *  - return value: CSBQ_OK (0) or a negative csbq_status; no C++ exception
+ *    crosses the ABI; csbq_last_error() returns the message of the last error
+ *    of that context (thread-unsafe; one context per thread).
+ *  - mem = CSBQ_HOST: pointers are host memory; the call is synchronous.
+ *    mem = CSBQ_DEVICE: pointers are device memory on the context's device;
+ *    the work is enqueued on the context's stream and the call returns after
+ *    enqueue (call csbq_synchronize or synchronise the stream before reading).
+ *  - the caller owns every array passed in or out; the library copies what
+ *    it keeps.
+ *  - all floating point arrays are IEEE double, C order, contiguous.
+ *  - this build supports ns = 16 and nt = 32 exactly (CSBQ_EINVAL otherwise).
+ */
+#ifndef CSBQ_H
+#define CSBQ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct csbq_ctx csbq_ctx;
+
+typedef enum {
+    CSBQ_OK = 0,
+    CSBQ_EINVAL = -1,   /* bad argument (sizes, NaN, unsupported orders, ...) */
+    CSBQ_ENOMEM = -2,   /* device or host allocation failed */
+    CSBQ_EHIP = -3,     /* a HIP runtime call failed */
+    CSBQ_ETABLE = -4,   /* quadrature tables missing or malformed */
+    CSBQ_ESTATE = -5,   /* call out of order (e.g. eval before set_geometry) */
+    CSBQ_ELIMIT = -6    /* an internal work limit was exceeded */
+} csbq_status;
+
+typedef enum { CSBQ_HOST = 0, CSBQ_DEVICE = 1 } csbq_mem;
+typedef enum { CSBQ_FP64 = 0, CSBQ_MIXED = 1 } csbq_precision;
+typedef enum { CSBQ_GATE_CRITERION = 0, CSBQ_GATE_MLP = 1 } csbq_gate_mode;
+
+typedef struct {
+    double quad_tol;       /* per-element quadrature tolerance (relative); <= 0 selects 1e-12 */
+    int32_t precision;     /* csbq_precision: FP64, or mixed (FP32 far field, FP64 near corrections) */
+    int32_t gate;          /* csbq_gate_mode: the error-estimate criterion, or the learned gate */
+    int32_t device;        /* HIP device ordinal */
+    void* stream;          /* hipStream_t to enqueue on; NULL = a stream owned by the context */
+    const char* table_dir; /* directory holding rules.bin; NULL = the package's tables/ */
+} csbq_options;
+
+/* Fill *opt with defaults (quad_tol 1e-12, FP64, criterion gate, device 0,
+   own stream, packaged tables). */
+void csbq_default_options(csbq_options* opt);
+
+/* Create a context: selects the device, creates/adopts the stream and loads
+   the quadrature tables (theta-rules of Section 3.2.2 and the log rule of
+   Section 3.2.4, generated offline per Appendix B).  *out receives the handle. */
+int csbq_create(const csbq_options* opt, csbq_ctx** out);
+
+/* Release every resource of the context (the adopted stream is not destroyed). */
+int csbq_destroy(csbq_ctx* ctx);
+
+/* Message of the last failed call on this context ("" if none). */
+const char* csbq_last_error(const csbq_ctx* ctx);
+
+/* Define the geometry (Section 3.1) and expand it on the device: nodes,
+   normals, smooth weights w_ij = J_ij w_i^GL 2 pi / nt (Section 3.2.1), and
+   the per-element data used by the near-field corrections.
+     n_bodies            number of bodies (>= 1)
+     n_panels[b]         panels of body b (>= 1)
+     normal_sign[b]      +1 or -1
+     s_break             sum_b (n_panels[b] + 1) increasing panel end points, body-major
+     xc, e1              [sum n_panels][ns][3] centerline and orientation samples
+     eps                 [sum n_panels][ns] radius samples (> 0)
+     ns, nt              16 and 32
+   Arrays are in `mem` (host or device).  Replaces any previous geometry. */
+int csbq_set_geometry(csbq_ctx* ctx, int32_t n_bodies, const int32_t* n_panels, const int32_t* normal_sign,
+                      const double* s_break, const double* xc, const double* eps, const double* e1, int32_t ns,
+                      int32_t nt, int mem);
+
+/* Number of surface nodes of the current geometry. */
+int csbq_num_nodes(const csbq_ctx* ctx, int64_t* n_nodes);
+
+/* Copy out node positions [N][3], unit normals [N][3] and smooth weights [N]
+   (any pointer may be NULL). */
+int csbq_get_nodes(csbq_ctx* ctx, double* y, double* normal, double* weight, int mem);
+
+/* The layer potentials at n_tgt targets (the full hot path: near-pair search,
+   gate, corrections, smooth sum, reduction).
+     sigma     [N][3] nodal density
+     x         [n_tgt][3] target points (may be NULL if every tgt_node >= 0)
+     tgt_node  [n_tgt] node id of an on-surface target, -1 for a free target;
+               NULL means every target is free.  For an on-surface target the
+               node's own position is used and x is ignored.
+     u_sl/u_dl [n_tgt][3] outputs (either may be NULL).
+   Free targets must not lie on a surface (distance below ~1e-12 of the
+   element size is undefined). */
+int csbq_eval(csbq_ctx* ctx, const double* sigma, int64_t n_tgt, const double* x, const int64_t* tgt_node,
+              double* u_sl, double* u_dl, int mem);
+
+/* The smooth Nystrom sum alone (Section 3.2.1, rule without corrections),
+   self term zero; same arguments as csbq_eval.  Runs in the context's
+   precision mode. */
+int csbq_smooth_sum(csbq_ctx* ctx, const double* sigma, int64_t n_tgt, const double* x, const int64_t* tgt_node,
+                    double* u_sl, double* u_dl, int mem);
+
+/* Statistics of the last csbq_eval as a JSON object (phase times in ms from
+   HIP events, pair counts per correction tier).  Writes at most cap bytes
+   including the terminating zero. */
+int csbq_stats(const csbq_ctx* ctx, char* buf, int64_t cap);
+
+/* Block until the context's stream has drained. */
+int csbq_synchronize(csbq_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CSBQ_H */

@@ -1,0 +1,191 @@
+"""MI355X (gfx950) Stokes single/double-layer potential evaluator.
+
+Thin ctypes binding over ``libcsbq.so`` (C ABI in ``include/csbq.h``): the
+binding only marshals arguments; every step of the evaluation runs in the
+library's HIP kernels.  There is no CPU fallback: if the library is missing or
+the device is absent, construction raises.
+
+Arrays may be numpy arrays (host memory; calls are synchronous) or torch CUDA
+tensors (device memory; work is enqueued on the context's stream, which by
+default is torch's current stream).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import json
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcsbq.so")
+TABLE_DIR = os.path.join(HERE, "tables")
+
+CSBQ_HOST, CSBQ_DEVICE = 0, 1
+CSBQ_FP64, CSBQ_MIXED = 0, 1
+_STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ETABLE", -5: "ESTATE", -6: "ELIMIT"}
+
+
+class CsbqError(RuntimeError):
+    pass
+
+
+class _Options(C.Structure):
+    _fields_ = [("quad_tol", C.c_double), ("precision", C.c_int32), ("gate", C.c_int32), ("device", C.c_int32),
+                ("stream", C.c_void_p), ("table_dir", C.c_char_p)]
+
+
+_lib = None
+
+
+def load_library():
+    """Load libcsbq.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2310_00889_amd.build` "
+                          "(there is no CPU fallback)")
+    lib = C.CDLL(LIB_PATH)
+    vp, dp, ip, lp = C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p
+    lib.csbq_default_options.argtypes = [C.POINTER(_Options)]
+    lib.csbq_create.argtypes = [C.POINTER(_Options), C.POINTER(C.c_void_p)]
+    lib.csbq_destroy.argtypes = [vp]
+    lib.csbq_last_error.argtypes = [vp]
+    lib.csbq_last_error.restype = C.c_char_p
+    lib.csbq_set_geometry.argtypes = [vp, C.c_int32, ip, ip, dp, dp, dp, dp, C.c_int32, C.c_int32, C.c_int]
+    lib.csbq_num_nodes.argtypes = [vp, C.POINTER(C.c_int64)]
+    lib.csbq_get_nodes.argtypes = [vp, dp, dp, dp, C.c_int]
+    lib.csbq_eval.argtypes = [vp, dp, C.c_int64, dp, lp, dp, dp, C.c_int]
+    lib.csbq_smooth_sum.argtypes = [vp, dp, C.c_int64, dp, lp, dp, dp, C.c_int]
+    lib.csbq_stats.argtypes = [vp, C.c_char_p, C.c_int64]
+    lib.csbq_synchronize.argtypes = [vp]
+    _lib = lib
+    return lib
+
+
+def _is_torch_cuda(a):
+    return a is not None and type(a).__module__.startswith("torch") and getattr(a, "is_cuda", False)
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if _is_torch_cuda(a):
+        return C.c_void_p(a.data_ptr())
+    return C.c_void_p(a.ctypes.data)
+
+
+class Evaluator:
+    """One library context: geometry, quadrature tables, device buffers."""
+
+    def __init__(self, quad_tol=1e-12, precision="fp64", device=0, stream=None, table_dir=None):
+        lib = load_library()
+        opt = _Options()
+        lib.csbq_default_options(C.byref(opt))
+        opt.quad_tol = float(quad_tol)
+        opt.precision = CSBQ_MIXED if precision == "mixed" else CSBQ_FP64
+        opt.device = int(device)
+        if stream is None:
+            try:
+                import torch
+                if torch.cuda.is_available():
+                    stream = torch.cuda.current_stream(device).cuda_stream
+            except Exception:
+                stream = None
+        opt.stream = stream
+        self._tdir = (table_dir or TABLE_DIR).encode()
+        opt.table_dir = self._tdir
+        h = C.c_void_p()
+        rc = lib.csbq_create(C.byref(opt), C.byref(h))
+        if rc != 0:
+            raise CsbqError(f"csbq_create failed: {_STATUS.get(rc, rc)}")
+        self._h = h
+        self._lib = lib
+        self.n_nodes = 0
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.csbq_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, what):
+        if rc != 0:
+            msg = self._lib.csbq_last_error(self._h).decode(errors="replace")
+            raise CsbqError(f"{what} failed ({_STATUS.get(rc, rc)}): {msg}")
+
+    def set_geometry(self, scene):
+        """Geometry from a scene (see ``synth.Scene``) or a dict of flat arrays."""
+        f = scene.flat() if hasattr(scene, "flat") else scene
+        ns = getattr(scene, "ns", 16)
+        nt = getattr(scene, "nt", 32)
+        arrs = dict(n_panels=np.ascontiguousarray(f["n_panels"], np.int32),
+                    normal_sign=np.ascontiguousarray(f["normal_sign"], np.int32),
+                    s_break=np.ascontiguousarray(f["s_break"], np.float64),
+                    xc=np.ascontiguousarray(f["xc"], np.float64),
+                    eps=np.ascontiguousarray(f["eps"], np.float64),
+                    e1=np.ascontiguousarray(f["e1"], np.float64))
+        rc = self._lib.csbq_set_geometry(self._h, int(f["n_bodies"]), _ptr(arrs["n_panels"]),
+                                         _ptr(arrs["normal_sign"]), _ptr(arrs["s_break"]), _ptr(arrs["xc"]),
+                                         _ptr(arrs["eps"]), _ptr(arrs["e1"]), ns, nt, CSBQ_HOST)
+        self._check(rc, "csbq_set_geometry")
+        n = C.c_int64()
+        self._check(self._lib.csbq_num_nodes(self._h, C.byref(n)), "csbq_num_nodes")
+        self.n_nodes = n.value
+
+    def nodes(self):
+        y = np.zeros((self.n_nodes, 3))
+        nr = np.zeros((self.n_nodes, 3))
+        w = np.zeros(self.n_nodes)
+        self._check(self._lib.csbq_get_nodes(self._h, _ptr(y), _ptr(nr), _ptr(w), CSBQ_HOST), "csbq_get_nodes")
+        return y, nr, w
+
+    def _call(self, fn, name, sigma, x, tgt_node, out_sl, out_dl):
+        dev = _is_torch_cuda(sigma)
+        if dev:
+            import torch
+            T = int(tgt_node.shape[0] if tgt_node is not None else x.shape[0])
+            if out_sl is None:
+                out_sl = torch.empty((T, 3), dtype=torch.float64, device=sigma.device)
+            if out_dl is None:
+                out_dl = torch.empty((T, 3), dtype=torch.float64, device=sigma.device)
+            for a in (sigma, x, tgt_node, out_sl, out_dl):
+                if a is not None and not (_is_torch_cuda(a) and a.is_contiguous()):
+                    raise CsbqError("device calls need contiguous CUDA tensors throughout")
+            rc = fn(self._h, _ptr(sigma), T, _ptr(x), _ptr(tgt_node), _ptr(out_sl), _ptr(out_dl), CSBQ_DEVICE)
+            self._check(rc, name)
+            return out_sl, out_dl
+        sigma = np.ascontiguousarray(sigma, np.float64)
+        if x is not None:
+            x = np.ascontiguousarray(x, np.float64).reshape(-1, 3)
+        if tgt_node is not None:
+            tgt_node = np.ascontiguousarray(tgt_node, np.int64)
+        T = int(tgt_node.shape[0] if tgt_node is not None else x.shape[0])
+        usl = np.zeros((T, 3))
+        udl = np.zeros((T, 3))
+        rc = fn(self._h, _ptr(sigma), T, _ptr(x), _ptr(tgt_node), _ptr(usl), _ptr(udl), CSBQ_HOST)
+        self._check(rc, name)
+        return usl, udl
+
+    def eval(self, sigma, x=None, tgt_node=None, out_sl=None, out_dl=None):
+        """(u_S, u_D) at the targets: the full evaluation."""
+        return self._call(self._lib.csbq_eval, "csbq_eval", sigma, x, tgt_node, out_sl, out_dl)
+
+    def smooth_sum(self, sigma, x=None, tgt_node=None, out_sl=None, out_dl=None):
+        """(u_S, u_D) of the plain smooth Nystrom sum (no corrections)."""
+        return self._call(self._lib.csbq_smooth_sum, "csbq_smooth_sum", sigma, x, tgt_node, out_sl, out_dl)
+
+    def synchronize(self):
+        self._check(self._lib.csbq_synchronize(self._h), "csbq_synchronize")
+
+    def stats(self):
+        buf = C.create_string_buffer(4096)
+        self._check(self._lib.csbq_stats(self._h, buf, 4096), "csbq_stats")
+        return json.loads(buf.value.decode())

@@ -1,0 +1,849 @@
+// csbq_api.cpp -- C ABI of the gfx950 Stokes layer-potential evaluator
+// (declared in include/csbq.h): context, device memory, table loading and the
+// sequencing of the kernels of one evaluation.
+#include <dlfcn.h>
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/csbq.h"
+#include "csbq_common.hpp"
+#include "csbq_kernels.hpp"
+
+using namespace csbq;
+
+namespace {
+
+// grow-only device buffer
+template <typename T>
+struct DBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    hipError_t ensure(size_t m)
+    {
+        if (m <= n && p) return hipSuccess;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+        size_t bytes = (m ? m : 1) * sizeof(T);
+        hipError_t e = hipMalloc((void**)&p, bytes);
+        if (e == hipSuccess) n = m;
+        return e;
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+};
+
+struct Phase {
+    const char* name;
+    hipEvent_t a, b;
+};
+
+const char* kPhaseNames[] = {"prep", "far", "search", "classify", "bucket", "corr_up", "corr_full", "reduce"};
+constexpr int kNPhase = 8;
+
+// Gauss-Legendre nodes by Newton iteration on the Legendre recurrence, with
+// the closed-form barycentric weights (-1)^i sqrt((1-x_i^2) w_i) of the GL
+// nodes and the spectral differentiation matrix built from them.
+void gl_tables(int n, double* x, double* w, double* lam, double* D, double* T)
+{
+    for (int i = 0; i < n; ++i) {
+        // i-th root in ascending order
+        double z = -std::cos(M_PI * (i + 0.75) / (n + 0.5));
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            double dp = n * (p0 - z * p1) / (1.0 - z * z);
+            double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-17) break;
+        }
+        double p0 = 1.0, p1 = z;
+        for (int k = 2; k <= n; ++k) {
+            double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+            p0 = p1;
+            p1 = p2;
+        }
+        double dp = n * (p0 - z * p1) / (1.0 - z * z);
+        x[i] = z;
+        w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+    for (int i = 0; i < n; ++i) lam[i] = ((i % 2) ? -1.0 : 1.0) * std::sqrt((1.0 - x[i] * x[i]) * w[i]);
+    for (int i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int j = 0; j < n; ++j) {
+            if (i == j) continue;
+            double v = (lam[j] / lam[i]) / (x[i] - x[j]);
+            D[i * n + j] = v;
+            s += v;
+        }
+        D[i * n + i] = -s;
+    }
+    for (int i = 0; i < n; ++i) {
+        double p0 = 1.0, p1 = x[i];
+        for (int k = 0; k < n; ++k) {
+            double pk;
+            if (k == 0)
+                pk = 1.0;
+            else if (k == 1)
+                pk = x[i];
+            else {
+                double p2 = ((2 * k - 1) * x[i] * p1 - (k - 1) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+                pk = p2;
+            }
+            T[k * n + i] = 0.5 * (2 * k + 1) * w[i] * pk;
+        }
+    }
+}
+
+void lagrange_row(int n, const double* x, const double* lam, double xi, double* row)
+{
+    double s = 0.0;
+    int hit = -1;
+    for (int i = 0; i < n; ++i) {
+        double d = xi - x[i];
+        if (d == 0.0) hit = i;
+        row[i] = lam[i] / (d == 0.0 ? 1.0 : d);
+        s += row[i];
+    }
+    if (hit >= 0) {
+        for (int i = 0; i < n; ++i) row[i] = (i == hit) ? 1.0 : 0.0;
+        return;
+    }
+    for (int i = 0; i < n; ++i) row[i] /= s;
+}
+
+std::string default_table_dir()
+{
+    Dl_info info;
+    if (dladdr((void*)&csbq_default_options, &info) && info.dli_fname) {
+        std::string p(info.dli_fname);
+        size_t k = p.find_last_of('/');
+        std::string dir = (k == std::string::npos) ? std::string(".") : p.substr(0, k);
+        return dir + "/tables";
+    }
+    return "tables";
+}
+
+}  // namespace
+
+struct csbq_ctx {
+    csbq_options opt{};
+    std::string err;
+    std::string table_dir;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    GateConsts gc{};
+    // quadrature tables
+    DBuf<int> roff;
+    DBuf<double> rth, rw, lx, lw;
+    int nb = 0, nl = 0;
+    double gx[NS], gw[NS], lam[NS];
+    // geometry
+    int E = 0;
+    int64_t N = 0;
+    bool have_geom = false;
+    DBuf<double> g_xc, g_eps, g_e1, g_sa, g_sc;
+    DBuf<int> g_sign, g_body;
+    DBuf<double> clq, circ, ny, nn, nw;
+    DBuf<ElemInfo> info;
+    DBuf<double> cpy[2], cpn[2], cpw[2], Lup[2];
+    int64_t Mtot[2] = {0, 0};
+    // evaluation scratch
+    DBuf<double> sig_d, x_d, usl_d, udl_d;
+    DBuf<int64_t> tn_d;
+    DBuf<double> sw, sh, rnear, xt, part, cls, corr, swf[2];
+    DBuf<int> band, cnt, pe, pt, bcnt, bcur, wave_elem[2], err_d, work;
+    DBuf<int64_t> off, list[2], listf;
+    DBuf<int8_t> tier;
+    DBuf<unsigned char> cub_tmp;
+    // statistics of the last evaluation
+    Phase ph[kNPhase];
+    bool ph_ok = false;
+    int64_t last_T = 0, last_P = 0, last_n2 = 0, last_n4 = 0, last_nf = 0;
+    int last_err_flags = 0;
+
+    int fail(int code, const std::string& msg)
+    {
+        err = msg;
+        return code;
+    }
+};
+
+#define HIPC(call)                                                                             \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return ctx->fail(CSBQ_EHIP, std::string(#call " failed: ") + hipGetErrorString(e_)); \
+    } while (0)
+#define ALLOC(buf, n)                                                                 \
+    do {                                                                              \
+        if ((buf).ensure(n) != hipSuccess) {                                          \
+            (void)hipGetLastError();                                                  \
+            return ctx->fail(CSBQ_ENOMEM, "device allocation failed: " #buf);         \
+        }                                                                             \
+    } while (0)
+#define LCHK(call)                                                                                  \
+    do {                                                                                            \
+        int r_ = (call);                                                                            \
+        if (r_) return ctx->fail(CSBQ_EHIP, std::string(#call " failed: ") +                        \
+                                                hipGetErrorString((hipError_t)r_));                \
+    } while (0)
+
+extern "C" {
+
+void csbq_default_options(csbq_options* opt)
+{
+    if (!opt) return;
+    std::memset(opt, 0, sizeof *opt);
+    opt->quad_tol = 1e-12;
+    opt->precision = CSBQ_FP64;
+    opt->gate = CSBQ_GATE_CRITERION;
+    opt->device = 0;
+    opt->stream = nullptr;
+    opt->table_dir = nullptr;
+}
+
+const char* csbq_last_error(const csbq_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+static int load_tables(csbq_ctx* ctx)
+{
+    std::string path = ctx->table_dir + "/rules.bin";
+    FILE* f = std::fopen(path.c_str(), "rb");
+    if (!f) return ctx->fail(CSBQ_ETABLE, "cannot open " + path);
+    char magic[8];
+    int32_t ver, nb, l0;
+    double tol;
+    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "CSBQRUL1", 8) == 0 &&
+              std::fread(&ver, 4, 1, f) == 1 && std::fread(&nb, 4, 1, f) == 1 && std::fread(&l0, 4, 1, f) == 1 &&
+              std::fread(&tol, 8, 1, f) == 1 && nb > 0 && nb < 64;
+    std::vector<int> off(1, 0);
+    std::vector<double> th, w;
+    for (int b = 0; ok && b < nb; ++b) {
+        int32_t m;
+        ok = std::fread(&m, 4, 1, f) == 1 && m > 0 && m <= MAXRULE;
+        if (!ok) break;
+        size_t o = th.size();
+        th.resize(o + m);
+        w.resize(o + m);
+        ok = std::fread(th.data() + o, 8, m, f) == (size_t)m && std::fread(w.data() + o, 8, m, f) == (size_t)m;
+        off.push_back((int)th.size());
+    }
+    int32_t ml = 0;
+    std::vector<double> lx, lw;
+    if (ok) ok = std::fread(&ml, 4, 1, f) == 1 && ml > 0 && ml <= MAXLOG;
+    if (ok) {
+        lx.resize(ml);
+        lw.resize(ml);
+        ok = std::fread(lx.data(), 8, ml, f) == (size_t)ml && std::fread(lw.data(), 8, ml, f) == (size_t)ml;
+    }
+    std::fclose(f);
+    if (!ok) return ctx->fail(CSBQ_ETABLE, "malformed rule table " + path);
+    ALLOC(ctx->roff, off.size());
+    ALLOC(ctx->rth, th.size());
+    ALLOC(ctx->rw, w.size());
+    ALLOC(ctx->lx, lx.size());
+    ALLOC(ctx->lw, lw.size());
+    HIPC(hipMemcpy(ctx->roff.p, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPC(hipMemcpy(ctx->rth.p, th.data(), th.size() * 8, hipMemcpyHostToDevice));
+    HIPC(hipMemcpy(ctx->rw.p, w.data(), w.size() * 8, hipMemcpyHostToDevice));
+    HIPC(hipMemcpy(ctx->lx.p, lx.data(), lx.size() * 8, hipMemcpyHostToDevice));
+    HIPC(hipMemcpy(ctx->lw.p, lw.data(), lw.size() * 8, hipMemcpyHostToDevice));
+    ctx->nb = nb;
+    ctx->nl = ml;
+    return CSBQ_OK;
+}
+
+int csbq_create(const csbq_options* opt, csbq_ctx** out)
+{
+    if (!out) return CSBQ_EINVAL;
+    *out = nullptr;
+    csbq_ctx* ctx = new (std::nothrow) csbq_ctx();
+    if (!ctx) return CSBQ_ENOMEM;
+    if (opt)
+        ctx->opt = *opt;
+    else
+        csbq_default_options(&ctx->opt);
+    if (!(ctx->opt.quad_tol > 0)) ctx->opt.quad_tol = 1e-12;
+    if (ctx->opt.precision != CSBQ_FP64 && ctx->opt.precision != CSBQ_MIXED) {
+        delete ctx;
+        return CSBQ_EINVAL;
+    }
+    ctx->table_dir = ctx->opt.table_dir ? std::string(ctx->opt.table_dir) : default_table_dir();
+    ctx->opt.table_dir = nullptr;
+    int ndev = 0;
+    hipError_t he = hipGetDeviceCount(&ndev);
+    if (he != hipSuccess || ctx->opt.device < 0 || ctx->opt.device >= ndev) {
+        std::fprintf(stderr, "csbq_create: no usable device (%s, %d devices)\n", hipGetErrorString(he), ndev);
+        (void)hipGetLastError();
+        delete ctx;
+        return CSBQ_EHIP;
+    }
+    if ((he = hipSetDevice(ctx->opt.device)) != hipSuccess) {
+        std::fprintf(stderr, "csbq_create: hipSetDevice: %s\n", hipGetErrorString(he));
+        delete ctx;
+        return CSBQ_EHIP;
+    }
+    if (ctx->opt.stream) {
+        ctx->stream = (hipStream_t)ctx->opt.stream;
+    } else {
+        if ((he = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking)) != hipSuccess) {
+            std::fprintf(stderr, "csbq_create: hipStreamCreate: %s\n", hipGetErrorString(he));
+            delete ctx;
+            return CSBQ_EHIP;
+        }
+        ctx->own_stream = true;
+    }
+    double D[NS * NS], T[NS * NS];
+    gl_tables(NS, ctx->gx, ctx->gw, ctx->lam, D, T);
+    if (int uc = upload_constants(ctx->gx, ctx->gw, ctx->lam, D, T)) {
+        std::fprintf(stderr, "csbq_create: constant upload failed (%d: %s)\n", uc,
+                     hipGetErrorString(hipGetLastError()));
+        csbq_destroy(ctx);
+        return CSBQ_EHIP;
+    }
+    int rc = load_tables(ctx);
+    if (rc) {
+        std::fprintf(stderr, "csbq: %s\n", ctx->err.c_str());
+        csbq_destroy(ctx);
+        return rc;
+    }
+    ctx->gc.tol = ctx->opt.quad_tol;
+    ctx->gc.cs = 10.0;
+    ctx->gc.ct = 10.0;
+    ctx->gc.hmin_fac = 1.0;
+    ctx->gc.extra_modes = 2;
+    // calibration override of the estimate constants: "cs,ct,hmin_fac,extra_modes"
+    if (const char* g = std::getenv("CSBQ_GATE_CONSTS")) {
+        double a = ctx->gc.cs, b = ctx->gc.ct, c = ctx->gc.hmin_fac;
+        int d = ctx->gc.extra_modes;
+        if (std::sscanf(g, "%lf,%lf,%lf,%d", &a, &b, &c, &d) == 4 && a > 0 && b > 0 && c > 0 && d >= 0) {
+            ctx->gc.cs = a;
+            ctx->gc.ct = b;
+            ctx->gc.hmin_fac = c;
+            ctx->gc.extra_modes = d;
+        }
+    }
+    for (int k = 0; k < kNPhase; ++k) {
+        ctx->ph[k].name = kPhaseNames[k];
+        (void)hipEventCreate(&ctx->ph[k].a);
+        (void)hipEventCreate(&ctx->ph[k].b);
+    }
+    *out = ctx;
+    return CSBQ_OK;
+}
+
+int csbq_destroy(csbq_ctx* ctx)
+{
+    if (!ctx) return CSBQ_EINVAL;
+    (void)hipSetDevice(ctx->opt.device);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (int k = 0; k < kNPhase; ++k) {
+        if (ctx->ph[k].a) (void)hipEventDestroy(ctx->ph[k].a);
+        if (ctx->ph[k].b) (void)hipEventDestroy(ctx->ph[k].b);
+    }
+    ctx->roff.release();
+    ctx->rth.release();
+    ctx->rw.release();
+    ctx->lx.release();
+    ctx->lw.release();
+    ctx->g_xc.release();
+    ctx->g_eps.release();
+    ctx->g_e1.release();
+    ctx->g_sa.release();
+    ctx->g_sc.release();
+    ctx->g_sign.release();
+    ctx->g_body.release();
+    ctx->clq.release();
+    ctx->circ.release();
+    ctx->ny.release();
+    ctx->nn.release();
+    ctx->nw.release();
+    ctx->info.release();
+    for (int k = 0; k < 2; ++k) {
+        ctx->cpy[k].release();
+        ctx->cpn[k].release();
+        ctx->cpw[k].release();
+        ctx->Lup[k].release();
+        ctx->swf[k].release();
+        ctx->wave_elem[k].release();
+        ctx->list[k].release();
+    }
+    ctx->sig_d.release();
+    ctx->x_d.release();
+    ctx->usl_d.release();
+    ctx->udl_d.release();
+    ctx->tn_d.release();
+    ctx->sw.release();
+    ctx->sh.release();
+    ctx->rnear.release();
+    ctx->xt.release();
+    ctx->part.release();
+    ctx->cls.release();
+    ctx->corr.release();
+    ctx->band.release();
+    ctx->cnt.release();
+    ctx->pe.release();
+    ctx->pt.release();
+    ctx->bcnt.release();
+    ctx->bcur.release();
+    ctx->err_d.release();
+    ctx->work.release();
+    ctx->off.release();
+    ctx->listf.release();
+    ctx->tier.release();
+    ctx->cub_tmp.release();
+    if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return CSBQ_OK;
+}
+
+int csbq_synchronize(csbq_ctx* ctx)
+{
+    if (!ctx) return CSBQ_EINVAL;
+    HIPC(hipStreamSynchronize(ctx->stream));
+    return CSBQ_OK;
+}
+
+int csbq_num_nodes(const csbq_ctx* ctx, int64_t* n)
+{
+    if (!ctx || !n) return CSBQ_EINVAL;
+    if (!ctx->have_geom) return CSBQ_ESTATE;
+    *n = ctx->N;
+    return CSBQ_OK;
+}
+
+}  // extern "C"
+
+// copy `n` elements from caller memory (host or device) into a device buffer
+template <typename T>
+static int to_device(csbq_ctx* ctx, DBuf<T>& buf, const T* src, size_t n, int mem)
+{
+    ALLOC(buf, n);
+    if (n == 0) return CSBQ_OK;
+    HIPC(hipMemcpyAsync(buf.p, src, n * sizeof(T), mem == CSBQ_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                        ctx->stream));
+    return CSBQ_OK;
+}
+
+extern "C" {
+
+int csbq_set_geometry(csbq_ctx* ctx, int32_t n_bodies, const int32_t* n_panels, const int32_t* normal_sign,
+                      const double* s_break, const double* xc, const double* eps, const double* e1, int32_t ns,
+                      int32_t nt, int mem)
+{
+    if (!ctx) return CSBQ_EINVAL;
+    ctx->err.clear();
+    if (ns != NS || nt != NT) return ctx->fail(CSBQ_EINVAL, "this build supports ns=16, nt=32 only");
+    if (n_bodies < 1 || !n_panels || !normal_sign || !s_break || !xc || !eps || !e1)
+        return ctx->fail(CSBQ_EINVAL, "missing geometry arrays");
+    if (mem != CSBQ_HOST && mem != CSBQ_DEVICE) return ctx->fail(CSBQ_EINVAL, "bad mem flag");
+    HIPC(hipSetDevice(ctx->opt.device));
+    // body tables are small: bring them to the host for validation
+    std::vector<int32_t> np(n_bodies), sg(n_bodies);
+    if (mem == CSBQ_DEVICE) {
+        HIPC(hipMemcpy(np.data(), n_panels, n_bodies * 4, hipMemcpyDeviceToHost));
+        HIPC(hipMemcpy(sg.data(), normal_sign, n_bodies * 4, hipMemcpyDeviceToHost));
+    } else {
+        std::memcpy(np.data(), n_panels, n_bodies * 4);
+        std::memcpy(sg.data(), normal_sign, n_bodies * 4);
+    }
+    int64_t E = 0, nsb = 0;
+    for (int b = 0; b < n_bodies; ++b) {
+        if (np[b] < 1) return ctx->fail(CSBQ_EINVAL, "a body has no panel");
+        if (sg[b] != 1 && sg[b] != -1) return ctx->fail(CSBQ_EINVAL, "normal_sign must be +1 or -1");
+        E += np[b];
+        nsb += np[b] + 1;
+    }
+    if (E > (1 << 26)) return ctx->fail(CSBQ_EINVAL, "too many panels");
+    std::vector<double> sb(nsb), h_eps((size_t)E * NS);
+    if (mem == CSBQ_DEVICE) {
+        HIPC(hipMemcpy(sb.data(), s_break, nsb * 8, hipMemcpyDeviceToHost));
+        HIPC(hipMemcpy(h_eps.data(), eps, h_eps.size() * 8, hipMemcpyDeviceToHost));
+    } else {
+        std::memcpy(sb.data(), s_break, nsb * 8);
+        std::memcpy(h_eps.data(), eps, h_eps.size() * 8);
+    }
+    std::vector<double> sa(E), sc(E);
+    std::vector<int> es(E), eb(E);
+    int64_t k = 0, o = 0;
+    for (int b = 0; b < n_bodies; ++b) {
+        for (int p = 0; p < np[b]; ++p, ++k) {
+            sa[k] = sb[o + p];
+            sc[k] = sb[o + p + 1];
+            if (!(sc[k] > sa[k]) || !std::isfinite(sa[k]) || !std::isfinite(sc[k]))
+                return ctx->fail(CSBQ_EINVAL, "panel end points must increase");
+            es[k] = sg[b];
+            eb[k] = b;
+        }
+        o += np[b] + 1;
+    }
+    for (double v : h_eps)
+        if (!(v > 0) || !std::isfinite(v)) return ctx->fail(CSBQ_EINVAL, "eps must be positive and finite");
+    ctx->E = (int)E;
+    ctx->N = E * NPE;
+    const int64_t N = ctx->N;
+    int rc;
+    if ((rc = to_device(ctx, ctx->g_xc, xc, (size_t)E * NS * 3, mem))) return rc;
+    if ((rc = to_device(ctx, ctx->g_eps, eps, (size_t)E * NS, mem))) return rc;
+    if ((rc = to_device(ctx, ctx->g_e1, e1, (size_t)E * NS * 3, mem))) return rc;
+    if ((rc = to_device(ctx, ctx->g_sa, sa.data(), (size_t)E, CSBQ_HOST))) return rc;
+    if ((rc = to_device(ctx, ctx->g_sc, sc.data(), (size_t)E, CSBQ_HOST))) return rc;
+    if ((rc = to_device(ctx, ctx->g_sign, es.data(), (size_t)E, CSBQ_HOST))) return rc;
+    if ((rc = to_device(ctx, ctx->g_body, eb.data(), (size_t)E, CSBQ_HOST))) return rc;
+    ALLOC(ctx->clq, (size_t)E * CLQ * NS);
+    ALLOC(ctx->circ, (size_t)E * NCIRC * CIRQ);
+    ALLOC(ctx->info, (size_t)E);
+    ALLOC(ctx->ny, (size_t)N * 3);
+    ALLOC(ctx->nn, (size_t)N * 3);
+    ALLOC(ctx->nw, (size_t)N);
+    LCHK(launch_expand(ctx->stream, (int)E, ctx->g_xc.p, ctx->g_eps.p, ctx->g_e1.p, ctx->g_sa.p, ctx->g_sc.p,
+                       ctx->g_sign.p, ctx->g_body.p, ctx->clq.p, ctx->circ.p, ctx->info.p, ctx->ny.p, ctx->nn.p,
+                       ctx->nw.p, N));
+    // upsampled rules (x2, x4) and their interpolation operators
+    for (int ti = 0; ti < 2; ++ti) {
+        int f = ti ? 4 : 2;
+        int64_t Mf = (int64_t)f * f * NPE + NPE;
+        ctx->Mtot[ti] = E * Mf;
+        ALLOC(ctx->cpy[ti], (size_t)ctx->Mtot[ti] * 3);
+        ALLOC(ctx->cpn[ti], (size_t)ctx->Mtot[ti] * 3);
+        ALLOC(ctx->cpw[ti], (size_t)ctx->Mtot[ti]);
+        std::vector<double> L((size_t)f * NS * NS);
+        for (int p = 0; p < f * NS; ++p) {
+            int kk = p / NS, g = p % NS;
+            double xn = -1.0 + (2.0 * kk + 1.0 + ctx->gx[g]) / f;
+            lagrange_row(NS, ctx->gx, ctx->lam, xn, &L[(size_t)p * NS]);
+        }
+        ALLOC(ctx->Lup[ti], L.size());
+        HIPC(hipMemcpyAsync(ctx->Lup[ti].p, L.data(), L.size() * 8, hipMemcpyHostToDevice, ctx->stream));
+        LCHK(launch_expand_up(ctx->stream, (int)E, f, ctx->clq.p, ctx->info.p, ctx->ny.p, ctx->nn.p, ctx->nw.p, N,
+                              ctx->cpy[ti].p, ctx->cpn[ti].p, ctx->cpw[ti].p, ctx->Mtot[ti]));
+    }
+    HIPC(hipStreamSynchronize(ctx->stream));
+    ctx->have_geom = true;
+    return CSBQ_OK;
+}
+
+int csbq_get_nodes(csbq_ctx* ctx, double* y, double* normal, double* weight, int mem)
+{
+    if (!ctx) return CSBQ_EINVAL;
+    if (!ctx->have_geom) return ctx->fail(CSBQ_ESTATE, "no geometry");
+    const int64_t N = ctx->N;
+    std::vector<double> h((size_t)N * 3);
+    auto kind = mem == CSBQ_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    // SoA on the device -> AoS for the caller
+    DBuf<double> tmp;
+    if (tmp.ensure((size_t)N * 3) != hipSuccess) return ctx->fail(CSBQ_ENOMEM, "alloc");
+    const double* srcs[2] = {ctx->ny.p, ctx->nn.p};
+    double* dsts[2] = {y, normal};
+    for (int q = 0; q < 2; ++q) {
+        if (!dsts[q]) continue;
+        std::vector<double> soa((size_t)N * 3);
+        HIPC(hipMemcpy(soa.data(), srcs[q], (size_t)N * 3 * 8, hipMemcpyDeviceToHost));
+        for (int64_t n = 0; n < N; ++n)
+            for (int d = 0; d < 3; ++d) h[n * 3 + d] = soa[d * N + n];
+        HIPC(hipMemcpy(dsts[q], h.data(), (size_t)N * 3 * 8,
+                       mem == CSBQ_DEVICE ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
+    }
+    if (weight) HIPC(hipMemcpy(weight, ctx->nw.p, (size_t)N * 8, kind));
+    tmp.release();
+    return CSBQ_OK;
+}
+
+// common front part: inputs on the device, targets, density preparation
+static int eval_front(csbq_ctx* ctx, const double* sigma, int64_t T, const double* x, const int64_t* tgt_node,
+                      int mem, const double** sig_dev, const int64_t** tn_dev)
+{
+    if (!ctx->have_geom) return ctx->fail(CSBQ_ESTATE, "set_geometry must be called first");
+    if (!sigma || T < 0) return ctx->fail(CSBQ_EINVAL, "missing density or negative target count");
+    if (!x && !tgt_node && T > 0) return ctx->fail(CSBQ_EINVAL, "targets need x or tgt_node");
+    if (mem != CSBQ_HOST && mem != CSBQ_DEVICE) return ctx->fail(CSBQ_EINVAL, "bad mem flag");
+    if (T > (int64_t)INT32_MAX) return ctx->fail(CSBQ_EINVAL, "too many targets");
+    const int64_t N = ctx->N;
+    if (mem == CSBQ_HOST) {
+        for (int64_t i = 0; i < N * 3; ++i)
+            if (!std::isfinite(sigma[i])) return ctx->fail(CSBQ_EINVAL, "density has NaN/Inf");
+        if (tgt_node)
+            for (int64_t t = 0; t < T; ++t)
+                if (tgt_node[t] >= N) return ctx->fail(CSBQ_EINVAL, "tgt_node out of range");
+        if (x)
+            for (int64_t t = 0; t < T; ++t)
+                if ((!tgt_node || tgt_node[t] < 0) &&
+                    !(std::isfinite(x[3 * t]) && std::isfinite(x[3 * t + 1]) && std::isfinite(x[3 * t + 2])))
+                    return ctx->fail(CSBQ_EINVAL, "target has NaN/Inf");
+        if (!x && tgt_node)
+            for (int64_t t = 0; t < T; ++t)
+                if (tgt_node[t] < 0) return ctx->fail(CSBQ_EINVAL, "free target without coordinates");
+        int rc;
+        if ((rc = to_device(ctx, ctx->sig_d, sigma, (size_t)N * 3, CSBQ_HOST))) return rc;
+        *sig_dev = ctx->sig_d.p;
+        if (x) {
+            if ((rc = to_device(ctx, ctx->x_d, x, (size_t)T * 3, CSBQ_HOST))) return rc;
+            x = ctx->x_d.p;
+        }
+        if (tgt_node) {
+            if ((rc = to_device(ctx, ctx->tn_d, tgt_node, (size_t)T, CSBQ_HOST))) return rc;
+            tgt_node = ctx->tn_d.p;
+        }
+    } else {
+        *sig_dev = sigma;
+    }
+    *tn_dev = tgt_node;
+    ALLOC(ctx->err_d, 1);
+    HIPC(hipMemsetAsync(ctx->err_d.p, 0, sizeof(int), ctx->stream));
+    ALLOC(ctx->xt, (size_t)T * 3 + 1);
+    LCHK(launch_targets(ctx->stream, T, x, tgt_node, ctx->ny.p, N, ctx->xt.p, ctx->err_d.p));
+    const int E = ctx->E;
+    ALLOC(ctx->sw, (size_t)N * 3);
+    ALLOC(ctx->sh, (size_t)E * NS * NSH);
+    ALLOC(ctx->band, (size_t)E * 2);
+    ALLOC(ctx->rnear, (size_t)E);
+    LCHK(launch_prep_sigma(ctx->stream, E, *sig_dev, ctx->nw.p, N, ctx->sw.p, ctx->sh.p, ctx->band.p,
+                           0.1 * ctx->gc.tol, ctx->info.p, ctx->gc, ctx->rnear.p));
+    return CSBQ_OK;
+}
+
+static int far_sum(csbq_ctx* ctx, int64_t T, int* nchunk_out)
+{
+    const int64_t N = ctx->N;
+    int64_t tblocks = (T + 255) / 256;
+    int nchunk = (int)std::max<int64_t>(1, std::min<int64_t>((4096 + tblocks - 1) / std::max<int64_t>(tblocks, 1),
+                                                             (N + 4095) / 4096));
+    int64_t chunk = ((N + nchunk - 1) / nchunk + 255) / 256 * 256;
+    nchunk = (int)((N + chunk - 1) / chunk);
+    if (nchunk < 1) nchunk = 1;
+    ALLOC(ctx->part, (size_t)nchunk * 6 * T + 1);
+    if (T > 0) LCHK(launch_far(ctx->stream, T, ctx->xt.p, ctx->ny.p, ctx->nn.p, ctx->sw.p, N, chunk, nchunk, ctx->part.p));
+    *nchunk_out = nchunk;
+    return CSBQ_OK;
+}
+
+static int outputs_back(csbq_ctx* ctx, int64_t T, double* u_sl, double* u_dl, int mem, double** usl_dev,
+                        double** udl_dev)
+{
+    if (mem == CSBQ_DEVICE) {
+        *usl_dev = u_sl;
+        *udl_dev = u_dl;
+        return CSBQ_OK;
+    }
+    ALLOC(ctx->usl_d, (size_t)T * 3 + 1);
+    ALLOC(ctx->udl_d, (size_t)T * 3 + 1);
+    *usl_dev = u_sl ? ctx->usl_d.p : nullptr;
+    *udl_dev = u_dl ? ctx->udl_d.p : nullptr;
+    return CSBQ_OK;
+}
+
+static int finish(csbq_ctx* ctx, int64_t T, double* u_sl, double* u_dl, int mem)
+{
+    int flags = 0;
+    if (mem == CSBQ_HOST) {
+        if (u_sl && T) HIPC(hipMemcpyAsync(u_sl, ctx->usl_d.p, (size_t)T * 3 * 8, hipMemcpyDeviceToHost, ctx->stream));
+        if (u_dl && T) HIPC(hipMemcpyAsync(u_dl, ctx->udl_d.p, (size_t)T * 3 * 8, hipMemcpyDeviceToHost, ctx->stream));
+        HIPC(hipMemcpyAsync(&flags, ctx->err_d.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+        HIPC(hipStreamSynchronize(ctx->stream));
+        ctx->last_err_flags = flags;
+        if (flags & 1) return ctx->fail(CSBQ_EINVAL, "tgt_node out of range");
+    }
+    return CSBQ_OK;
+}
+
+int csbq_smooth_sum(csbq_ctx* ctx, const double* sigma, int64_t T, const double* x, const int64_t* tgt_node,
+                    double* u_sl, double* u_dl, int mem)
+{
+    if (!ctx) return CSBQ_EINVAL;
+    ctx->err.clear();
+    HIPC(hipSetDevice(ctx->opt.device));
+    const double* sig;
+    const int64_t* tn;
+    int rc = eval_front(ctx, sigma, T, x, tgt_node, mem, &sig, &tn);
+    if (rc) return rc;
+    int nchunk = 1;
+    if ((rc = far_sum(ctx, T, &nchunk))) return rc;
+    double *usl, *udl;
+    if ((rc = outputs_back(ctx, T, u_sl, u_dl, mem, &usl, &udl))) return rc;
+    if (T > 0) LCHK(launch_reduce(ctx->stream, T, nchunk, ctx->part.p, nullptr, nullptr, nullptr, usl, udl));
+    return finish(ctx, T, u_sl, u_dl, mem);
+}
+
+int csbq_eval(csbq_ctx* ctx, const double* sigma, int64_t T, const double* x, const int64_t* tgt_node, double* u_sl,
+              double* u_dl, int mem)
+{
+    if (!ctx) return CSBQ_EINVAL;
+    ctx->err.clear();
+    HIPC(hipSetDevice(ctx->opt.device));
+    hipStream_t st = ctx->stream;
+    ctx->ph_ok = false;
+    const double* sig;
+    const int64_t* tn;
+    HIPC(hipEventRecord(ctx->ph[0].a, st));
+    int rc = eval_front(ctx, sigma, T, x, tgt_node, mem, &sig, &tn);
+    if (rc) return rc;
+    HIPC(hipEventRecord(ctx->ph[0].b, st));
+    const int E = ctx->E;
+    const int64_t N = ctx->N;
+    // smooth sum over every source
+    HIPC(hipEventRecord(ctx->ph[1].a, st));
+    int nchunk = 1;
+    if ((rc = far_sum(ctx, T, &nchunk))) return rc;
+    HIPC(hipEventRecord(ctx->ph[1].b, st));
+    // candidate pairs: count, scan, fill
+    HIPC(hipEventRecord(ctx->ph[2].a, st));
+    ALLOC(ctx->cnt, (size_t)T + 1);
+    ALLOC(ctx->off, (size_t)T + 1);
+    HIPC(hipMemsetAsync(ctx->cnt.p, 0, ((size_t)T + 1) * sizeof(int), st));
+    if (T > 0)
+        LCHK(launch_search(st, T, E, ctx->xt.p, tn, ctx->info.p, ctx->rnear.p, nullptr, ctx->cnt.p, nullptr, nullptr));
+    size_t tmpb = 0;
+    HIPC(hipcub::DeviceScan::ExclusiveSum(nullptr, tmpb, ctx->cnt.p, ctx->off.p, (int)(T + 1), st));
+    ALLOC(ctx->cub_tmp, tmpb);
+    HIPC(hipcub::DeviceScan::ExclusiveSum(ctx->cub_tmp.p, tmpb, ctx->cnt.p, ctx->off.p, (int)(T + 1), st));
+    int64_t P = 0;
+    HIPC(hipMemcpyAsync(&P, ctx->off.p + T, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    ALLOC(ctx->pe, (size_t)P + 1);
+    ALLOC(ctx->pt, (size_t)P + 1);
+    ALLOC(ctx->tier, (size_t)P + 1);
+    ALLOC(ctx->cls, (size_t)P * 4 + 1);
+    ALLOC(ctx->corr, (size_t)P * 6 + 1);
+    if (T > 0)
+        LCHK(launch_search(st, T, E, ctx->xt.p, tn, ctx->info.p, ctx->rnear.p, ctx->off.p, nullptr, ctx->pe.p,
+                           ctx->pt.p));
+    HIPC(hipEventRecord(ctx->ph[2].b, st));
+    // classification into correction tiers
+    HIPC(hipEventRecord(ctx->ph[3].a, st));
+    LCHK(launch_classify(st, P, ctx->pe.p, ctx->pt.p, ctx->xt.p, T, tn, ctx->clq.p, ctx->circ.p, ctx->info.p,
+                         ctx->band.p, ctx->gc, ctx->tier.p, ctx->cls.p));
+    HIPC(hipEventRecord(ctx->ph[3].b, st));
+    // buckets per tier (x2/x4 grouped by element, padded to whole wavefronts)
+    HIPC(hipEventRecord(ctx->ph[4].a, st));
+    ALLOC(ctx->bcnt, (size_t)2 * E + 1);
+    ALLOC(ctx->bcur, (size_t)2 * E + 1);
+    HIPC(hipMemsetAsync(ctx->bcnt.p, 0, ((size_t)2 * E + 1) * sizeof(int), st));
+    LCHK(launch_bucket_count(st, P, ctx->tier.p, ctx->pe.p, ctx->bcnt.p, ctx->bcnt.p + E, ctx->bcnt.p + 2 * E));
+    std::vector<int> hc((size_t)2 * E + 1);
+    HIPC(hipMemcpyAsync(hc.data(), ctx->bcnt.p, hc.size() * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    std::vector<int> cur((size_t)2 * E + 1);
+    int nwaves[2] = {0, 0};
+    int64_t npair[2] = {0, 0};
+    std::vector<int> we[2];
+    for (int ti = 0; ti < 2; ++ti) {
+        int pos = 0;
+        for (int e = 0; e < E; ++e) {
+            int c = hc[(size_t)ti * E + e];
+            cur[(size_t)ti * E + e] = pos;
+            int w = (c + 63) / 64;
+            for (int k = 0; k < w; ++k) we[ti].push_back(e);
+            pos += w * 64;
+            npair[ti] += c;
+        }
+        nwaves[ti] = (int)we[ti].size();
+        ALLOC(ctx->list[ti], (size_t)nwaves[ti] * 64 + 1);
+        ALLOC(ctx->wave_elem[ti], (size_t)nwaves[ti] + 1);
+        HIPC(hipMemsetAsync(ctx->list[ti].p, 0xFF, ((size_t)nwaves[ti] * 64 + 1) * sizeof(int64_t), st));
+        if (nwaves[ti])
+            HIPC(hipMemcpyAsync(ctx->wave_elem[ti].p, we[ti].data(), we[ti].size() * sizeof(int),
+                                hipMemcpyHostToDevice, st));
+    }
+    const int nfull = hc[(size_t)2 * E];
+    cur[(size_t)2 * E] = 0;
+    ALLOC(ctx->listf, (size_t)nfull + 1);
+    HIPC(hipMemcpyAsync(ctx->bcur.p, cur.data(), cur.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    LCHK(launch_bucket_fill(st, P, ctx->tier.p, ctx->pe.p, ctx->bcur.p, ctx->bcur.p + E, ctx->bcur.p + 2 * E,
+                            ctx->list[0].p, ctx->list[1].p, ctx->listf.p));
+    HIPC(hipEventRecord(ctx->ph[4].b, st));
+    // upsampled-rule corrections
+    HIPC(hipEventRecord(ctx->ph[5].a, st));
+    for (int ti = 0; ti < 2; ++ti) {
+        if (!nwaves[ti]) continue;
+        int f = ti ? 4 : 2;
+        ALLOC(ctx->swf[ti], (size_t)ctx->Mtot[ti] * 3);
+        LCHK(launch_sigma_up(st, E, f, ctx->sh.p, ctx->Lup[ti].p, ctx->cpw[ti].p, ctx->sw.p, N, ctx->swf[ti].p,
+                             ctx->Mtot[ti]));
+        LCHK(launch_corr_up(st, f, nwaves[ti], ctx->wave_elem[ti].p, ctx->list[ti].p, ctx->pt.p, ctx->xt.p, T,
+                            ctx->cpy[ti].p, ctx->cpn[ti].p, ctx->swf[ti].p, ctx->Mtot[ti], ctx->corr.p));
+    }
+    HIPC(hipEventRecord(ctx->ph[5].b, st));
+    // special quadrature corrections
+    HIPC(hipEventRecord(ctx->ph[6].a, st));
+    ALLOC(ctx->work, (size_t)2 * nfull + 2);
+    LCHK(launch_corr_full(st, nfull, ctx->listf.p, ctx->pe.p, ctx->pt.p, ctx->xt.p, T, tn, ctx->clq.p, ctx->sh.p,
+                          ctx->info.p, ctx->band.p, ctx->cls.p, ctx->ny.p, ctx->nn.p, ctx->sw.p, N, ctx->roff.p,
+                          ctx->rth.p, ctx->rw.p, ctx->nb, ctx->lx.p, ctx->lw.p, ctx->nl, ctx->gc, ctx->corr.p,
+                          ctx->err_d.p, ctx->work.p));
+    HIPC(hipEventRecord(ctx->ph[6].b, st));
+    // reduction
+    HIPC(hipEventRecord(ctx->ph[7].a, st));
+    double *usl, *udl;
+    if ((rc = outputs_back(ctx, T, u_sl, u_dl, mem, &usl, &udl))) return rc;
+    if (T > 0) LCHK(launch_reduce(st, T, nchunk, ctx->part.p, ctx->off.p, ctx->tier.p, ctx->corr.p, usl, udl));
+    HIPC(hipEventRecord(ctx->ph[7].b, st));
+    ctx->last_T = T;
+    ctx->last_P = P;
+    ctx->last_n2 = npair[0];
+    ctx->last_n4 = npair[1];
+    ctx->last_nf = nfull;
+    ctx->ph_ok = true;
+    return finish(ctx, T, u_sl, u_dl, mem);
+}
+
+int csbq_stats(const csbq_ctx* ctx, char* buf, int64_t cap)
+{
+    if (!ctx || !buf || cap <= 0) return CSBQ_EINVAL;
+    std::string s = "{";
+    char tmp[256];
+    std::snprintf(tmp, sizeof tmp,
+                  "\"targets\": %lld, \"candidates\": %lld, \"pairs_x2\": %lld, \"pairs_x4\": %lld, "
+                  "\"pairs_full\": %lld, \"flags\": %d",
+                  (long long)ctx->last_T, (long long)ctx->last_P, (long long)ctx->last_n2, (long long)ctx->last_n4,
+                  (long long)ctx->last_nf, ctx->last_err_flags);
+    s += tmp;
+    if (ctx->ph_ok && ctx->last_nf > 0) {
+        std::vector<int> wk((size_t)2 * ctx->last_nf);
+        if (hipMemcpy(wk.data(), ctx->work.p, wk.size() * sizeof(int), hipMemcpyDeviceToHost) == hipSuccess) {
+            long long nq = 0, nsn = 0;
+            for (size_t i = 0; i < wk.size(); i += 2) {
+                nq += wk[i];
+                nsn += wk[i + 1];
+            }
+            std::snprintf(tmp, sizeof tmp, ", \"theta_nodes\": %lld, \"s_nodes\": %lld", nq, nsn);
+            s += tmp;
+        }
+    }
+    if (ctx->ph_ok) {
+        (void)hipEventSynchronize(ctx->ph[kNPhase - 1].b);
+        s += ", \"ms\": {";
+        for (int k = 0; k < kNPhase; ++k) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, ctx->ph[k].a, ctx->ph[k].b) != hipSuccess) {
+                (void)hipGetLastError();
+                ms = -1.f;
+            }
+            std::snprintf(tmp, sizeof tmp, "%s\"%s\": %.4f", k ? ", " : "", ctx->ph[k].name, ms);
+            s += tmp;
+        }
+        s += "}";
+    }
+    s += "}";
+    std::snprintf(buf, (size_t)cap, "%s", s.c_str());
+    return CSBQ_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,51 @@
+// csbq_common.hpp -- shared definitions of the gfx950 layer-potential library.
+//
+// Fixed discretisation orders of this build: NS Gauss-Legendre nodes per panel
+// in s and NT uniform angles (Section 3.1).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace csbq {
+
+constexpr int NS = 16;
+constexpr int NT = 32;
+constexpr int NPE = NS * NT;           // nodes per element
+constexpr int NMODE = NT / 2 + 1;      // Fourier modes 0..NT/2 of a real density
+constexpr int NSH = NMODE * 6;         // per GL row: (a_x a_y a_z b_x b_y b_z) per mode
+constexpr int CLQ = 17;                // centerline quantities per GL node
+constexpr int NCIRC = NS + 2;          // GL circles + the two panel-end circles
+constexpr int CIRQ = 9;                // per circle: X(3) t(3) eps smax s
+constexpr int MAXSUB = 96;             // s sub-panels of one special quadrature
+constexpr int MAXRULE = 256;           // nodes of one theta rule
+constexpr int MAXLOG = 64;             // nodes of the log rule
+
+// centerline quantity slots (clq[e][q][i], i = GL node)
+enum { Q_X = 0, Q_XP = 3, Q_XPP = 6, Q_E = 9, Q_EP = 10, Q_F = 11, Q_FP = 14 };
+
+// correction tiers of a (target, element) pair
+enum : int8_t { TIER_SKIP = 0, TIER_UP2 = 1, TIER_UP4 = 2, TIER_FULL = 3 };
+
+// sub-panel kinds of an s-rule
+enum : int { SUB_GL = 0, SUB_LOG_LO = 1, SUB_LOG_HI = 2 };  // log singularity at lo / at hi
+
+struct ElemInfo {
+    double a, c;       // panel interval in s
+    double cen[3];     // bounding-ball centre
+    double rad;        // bounding-ball radius
+    double eps_max;    // largest cross-section radius
+    double smax;       // largest surface speed |dy/ds| bound
+    int32_t sign;      // normal orientation
+    int32_t body;
+};
+
+// constants of the error estimates (calibrated against the CPU oracle)
+struct GateConsts {
+    double tol;        // per-element quadrature tolerance
+    double cs;         // Gauss-Legendre estimate prefactor
+    double ct;         // trapezoid estimate prefactor
+    double hmin_fac;   // dyadic refinement stops at hmin_fac * eps / speed
+    int extra_modes;   // modes added to the density band for J and the normal
+};
+
+}  // namespace csbq

@@ -1,0 +1,154 @@
+"""GPU path vs the CPU oracle (element by element on the same seeded inputs).
+
+Bar: every output within 1e-10 of the oracle relative to the largest oracle
+value of that output (u_S or u_D) and target class; geometry and the plain
+smooth sum within 1e-12 (1e-10 for the fat-pipe normals and weights, whose
+second centerline derivatives carry ~1e-11 rounding in both evaluators)."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+GATE = 1e-10
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+@pytest.fixture(scope="module")
+def ev():
+    import torch
+    import paper_2310_00889_amd as pk
+    torch.zeros(1, device="cuda")           # initialise the device through torch first
+    e = pk.Evaluator(quad_tol=1e-12)
+    yield e
+    e.close()
+
+
+def _check_classes(u, uo, cls, what):
+    for c in np.unique(cls):
+        m = cls == c
+        err = np.abs(u[m] - uo[m]).max() / np.abs(uo[m]).max()
+        print(f"{what} class {c}: {err:.2e}", flush=True)
+        assert err < GATE, (what, c, err)
+
+
+def test_native_library_is_loaded(ev):
+    import paper_2310_00889_amd as pk
+    with open("/proc/self/maps") as f:
+        maps = f.read()
+    assert os.path.realpath(pk.LIB_PATH) in maps
+
+
+def test_nodes_match_oracle(ev):
+    for sc, tol in ((synth.config1(4), 1e-13), (synth.small_pipe_scene(), 1e-10)):
+        ev.set_geometry(sc)
+        y, n, w = ev.nodes()
+        yo, no, wo = oracle.nodes(sc)
+        assert _rel(y, yo) < 1e-13
+        assert np.abs(n - no).max() < tol
+        assert _rel(w, wo) < tol
+
+
+def test_smooth_sum_matches_oracle(ev):
+    sc = synth.small_pipe_scene(n_panels=6, n_spheres=3)
+    ev.set_geometry(sc)
+    rng = np.random.default_rng(1)
+    tn = np.concatenate([rng.choice(sc.n_nodes, 300, replace=False), -np.ones(37, np.int64)])
+    x = rng.uniform(-2, 6, (len(tn), 3))
+    us, ud = ev.smooth_sum(sc.sigma, x, tn)
+    uso, udo = oracle.smooth_sum(sc, None, x, tn)
+    assert _rel(us, uso) < 1e-12 and _rel(ud, udo) < 1e-12
+
+
+def test_sphere_config1_off_surface(ev):
+    sc = synth.config1()
+    ev.set_geometry(sc)
+    us, ud = ev.eval(sc.sigma, sc.x, sc.tgt_node)
+    uso, udo = oracle.evaluate(sc)
+    _check_classes(us, uso, sc.tgt_class, "S")
+    _check_classes(ud, udo, sc.tgt_class, "D")
+
+
+def test_sphere_on_surface(ev):
+    sc = synth.config1(4)
+    ev.set_geometry(sc)
+    tn = np.arange(0, sc.n_nodes, 3)
+    us, ud = ev.eval(sc.sigma, None, tn)
+    uso, udo = oracle.evaluate(sc, None, None, tn)
+    assert _rel(us, uso) < GATE, _rel(us, uso)
+    assert _rel(ud, udo) < GATE, _rel(ud, udo)
+
+
+def test_small_pipe_on_and_off_surface(ev):
+    sc = synth.small_pipe_scene(n_panels=6, n_spheres=3)
+    ev.set_geometry(sc)
+    rng = np.random.default_rng(2)
+    tn = rng.choice(sc.n_nodes, 300, replace=False)
+    us, ud = ev.eval(sc.sigma, None, tn)
+    uso, udo = oracle.evaluate(sc, None, None, tn)
+    print("on-surface", _rel(us, uso), _rel(ud, udo), ev.stats(), flush=True)
+    assert _rel(us, uso) < GATE and _rel(ud, udo) < GATE
+    y, n, _ = oracle.nodes(sc)
+    k = rng.choice(sc.n_nodes, 300, replace=False)
+    d = 10.0 ** rng.uniform(-3, -0.3, 300) * np.where(rng.random(300) < 0.5, 1, -1)
+    xs = y[k] + d[:, None] * n[k]
+    us, ud = ev.eval(sc.sigma, xs, None)
+    uso, udo = oracle.evaluate(sc, None, xs, -np.ones(300, np.int64))
+    print("off-surface", _rel(us, uso), _rel(ud, udo), ev.stats(), flush=True)
+    assert _rel(us, uso) < GATE and _rel(ud, udo) < GATE
+
+
+def test_config2_full_size_sampled(ev):
+    """Full config-2 evaluation (153,600 on-surface targets) in the launch
+    configuration the benchmark times; sampled targets against the oracle."""
+    import torch
+    sc = synth.config2()
+    ev.set_geometry(sc)
+    sig = torch.from_numpy(sc.sigma).cuda()
+    tn = torch.from_numpy(sc.tgt_node).cuda()
+    us, ud = ev.eval(sig, None, tn)
+    torch.cuda.synchronize()
+    us, ud = us.cpu().numpy(), ud.cpu().numpy()
+    assert np.isfinite(us).all() and np.isfinite(ud).all()
+    rng = np.random.default_rng(3)
+    idx = np.concatenate([rng.choice(51200, 8, replace=False), 51200 + rng.choice(102400, 16, replace=False)])
+    uso, udo = oracle.evaluate(sc, None, None, sc.tgt_node[idx])
+    _check_classes(us[idx], uso, sc.tgt_class[idx], "S")
+    _check_classes(ud[idx], udo, sc.tgt_class[idx], "D")
+
+
+def test_determinism_and_device_host_agree(ev):
+    import torch
+    sc = synth.small_pipe_scene(n_panels=4, n_spheres=2)
+    ev.set_geometry(sc)
+    tn = np.arange(0, sc.n_nodes, 5)
+    a1, b1 = ev.eval(sc.sigma, None, tn)
+    a2, b2 = ev.eval(sc.sigma, None, tn)
+    assert np.array_equal(a1, a2) and np.array_equal(b1, b2)
+    ad, bd = ev.eval(torch.from_numpy(sc.sigma).cuda(), None, torch.from_numpy(tn).cuda())
+    torch.cuda.synchronize()
+    assert np.array_equal(ad.cpu().numpy(), a1) and np.array_equal(bd.cpu().numpy(), b1)
+
+
+def test_empty_and_invalid_inputs(ev):
+    import paper_2310_00889_amd as pk
+    sc = synth.small_pipe_scene(n_panels=2, n_spheres=1)
+    ev.set_geometry(sc)
+    us, ud = ev.eval(sc.sigma, np.zeros((0, 3)), None)
+    assert us.shape == (0, 3)
+    bad = sc.sigma.copy()
+    bad[5, 1] = np.nan
+    with pytest.raises(pk.CsbqError):
+        ev.eval(bad, np.ones((2, 3)), None)
+    with pytest.raises(pk.CsbqError):
+        ev.eval(sc.sigma, None, np.array([sc.n_nodes + 3]))
+    # the context stays usable after an error
+    us, ud = ev.eval(sc.sigma, None, np.array([0, 1]))
+    assert np.isfinite(us).all()
