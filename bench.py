@@ -94,14 +94,15 @@ def main():
     value = T * a.steps / dt
     # roofline of the dominant kernel, timed with HIP events on the library's stream
     dom = max(("far", "corr_full"), key=lambda k: phases.get(k, 0.0))
+    nsrc = counts.get("sources_base", ev.n_nodes)
     if dom == "far":
-        flops = FAR_FLOPS_PER_PAIR * float(T) * ev.n_nodes
+        flops = FAR_FLOPS_PER_PAIR * float(T) * nsrc
     else:
         flops = THETA_FLOPS * float(counts.get("theta_nodes", 0)) + SNODE_FLOPS * float(counts.get("s_nodes", 0))
     achieved = flops / (phases[dom] * 1e-3) / 1e12
     roof = dict(kernel="k_far" if dom == "far" else "k_corr_full", bound="alu", achieved=achieved,
                 peak=FP64_PEAK_TFLOPS, unit="TFLOP/s", frac=achieved / FP64_PEAK_TFLOPS, traffic=None)
-    far_ach = FAR_FLOPS_PER_PAIR * float(T) * ev.n_nodes / (phases["far"] * 1e-3) / 1e12
+    far_ach = FAR_FLOPS_PER_PAIR * float(T) * nsrc / (phases["far"] * 1e-3) / 1e12
     out = {
         "metric": METRIC, "value": value, "unit": "target evals/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": 1e3 * dt / a.steps, "higher_is_better": True, "scaling": "weak",
@@ -113,8 +114,8 @@ def main():
         "far_roofline": dict(kernel="k_far", bound="alu", achieved=far_ach, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
                              frac=far_ach / FP64_PEAK_TFLOPS),
         "phases_ms": phases,
-        "pairs": {k: counts.get(k) for k in ("candidates", "pairs_x2", "pairs_x4", "pairs_full", "theta_nodes",
-                                              "s_nodes")},
+        "pairs": {k: counts.get(k) for k in ("candidates", "pairs_up1", "pairs_up2", "pairs_up3", "pairs_full",
+                                              "theta_nodes", "s_nodes", "sources_base")},
     }
     if not a.no_cpu_baseline:
         log("bench: timing the CPU oracle on a sample")

@@ -153,7 +153,7 @@ struct csbq_ctx {
     GateConsts gc{};
     // quadrature tables
     DBuf<int> roff;
-    DBuf<double> rth, rw, lx, lw;
+    DBuf<double> rth, rw, lx, lw, rcs, rsn, romc;
     int nb = 0, nl = 0;
     double gx[NS], gw[NS], lam[NS];
     // geometry
@@ -164,20 +164,24 @@ struct csbq_ctx {
     DBuf<int> g_sign, g_body;
     DBuf<double> clq, circ, ny, nn, nw;
     DBuf<ElemInfo> info;
-    DBuf<double> cpy[2], cpn[2], cpw[2], Lup[2];
-    int64_t Mtot[2] = {0, 0};
+    DBuf<double> cpy[NUP], cpn[NUP], cpw[NUP], Lup[NUP], upx[NUP], upw[NUP];
+    int64_t Mtot[NUP] = {0, 0, 0};
+    // far-field (base) source set
+    int64_t Nb = 0;
+    DBuf<int64_t> boff;
+    DBuf<double> by, bn, bw, bsw;
     // evaluation scratch
     DBuf<double> sig_d, x_d, usl_d, udl_d;
     DBuf<int64_t> tn_d;
-    DBuf<double> sw, sh, rnear, xt, part, cls, corr, swf[2];
-    DBuf<int> band, cnt, pe, pt, bcnt, bcur, wave_elem[2], err_d, work;
-    DBuf<int64_t> off, list[2], listf;
+    DBuf<double> sw, sh, rnear, xt, part, cls, corr, swf[NUP];
+    DBuf<int> band, cnt, pe, pt, err_d, work, kin, kout, vin, perm, sorted, runs_key, runs_cnt, nruns, wdesc[NUP];
+    DBuf<int64_t> off;
     DBuf<int8_t> tier;
     DBuf<unsigned char> cub_tmp;
     // statistics of the last evaluation
     Phase ph[kNPhase];
     bool ph_ok = false;
-    int64_t last_T = 0, last_P = 0, last_n2 = 0, last_n4 = 0, last_nf = 0;
+    int64_t last_T = 0, last_P = 0, last_nup[NUP] = {0, 0, 0}, last_nf = 0;
     int last_err_flags = 0;
 
     int fail(int code, const std::string& msg)
@@ -256,6 +260,19 @@ static int load_tables(csbq_ctx* ctx)
     }
     std::fclose(f);
     if (!ok) return ctx->fail(CSBQ_ETABLE, "malformed rule table " + path);
+    std::vector<double> cs_(th.size()), sn_(th.size()), omc_(th.size());
+    for (size_t q = 0; q < th.size(); ++q) {
+        cs_[q] = std::cos(th[q]);
+        sn_[q] = std::sin(th[q]);
+        double h = std::sin(0.5 * th[q]);
+        omc_[q] = 2.0 * h * h;   // 1 - cos, without cancellation near 0
+    }
+    ALLOC(ctx->rcs, th.size());
+    ALLOC(ctx->rsn, th.size());
+    ALLOC(ctx->romc, th.size());
+    HIPC(hipMemcpy(ctx->rcs.p, cs_.data(), th.size() * 8, hipMemcpyHostToDevice));
+    HIPC(hipMemcpy(ctx->rsn.p, sn_.data(), th.size() * 8, hipMemcpyHostToDevice));
+    HIPC(hipMemcpy(ctx->romc.p, omc_.data(), th.size() * 8, hipMemcpyHostToDevice));
     ALLOC(ctx->roff, off.size());
     ALLOC(ctx->rth, th.size());
     ALLOC(ctx->rw, w.size());
@@ -326,8 +343,8 @@ int csbq_create(const csbq_options* opt, csbq_ctx** out)
         return rc;
     }
     ctx->gc.tol = ctx->opt.quad_tol;
-    ctx->gc.cs = 10.0;
-    ctx->gc.ct = 10.0;
+    ctx->gc.cs = 1000.0;
+    ctx->gc.ct = 1000.0;
     ctx->gc.hmin_fac = 1.0;
     ctx->gc.extra_modes = 2;
     // calibration override of the estimate constants: "cs,ct,hmin_fac,extra_modes"
@@ -364,6 +381,9 @@ int csbq_destroy(csbq_ctx* ctx)
     ctx->rw.release();
     ctx->lx.release();
     ctx->lw.release();
+    ctx->rcs.release();
+    ctx->rsn.release();
+    ctx->romc.release();
     ctx->g_xc.release();
     ctx->g_eps.release();
     ctx->g_e1.release();
@@ -377,14 +397,20 @@ int csbq_destroy(csbq_ctx* ctx)
     ctx->nn.release();
     ctx->nw.release();
     ctx->info.release();
-    for (int k = 0; k < 2; ++k) {
+    ctx->boff.release();
+    ctx->by.release();
+    ctx->bn.release();
+    ctx->bw.release();
+    ctx->bsw.release();
+    for (int k = 0; k < NUP; ++k) {
         ctx->cpy[k].release();
         ctx->cpn[k].release();
         ctx->cpw[k].release();
         ctx->Lup[k].release();
+        ctx->upx[k].release();
+        ctx->upw[k].release();
         ctx->swf[k].release();
-        ctx->wave_elem[k].release();
-        ctx->list[k].release();
+        ctx->wdesc[k].release();
     }
     ctx->sig_d.release();
     ctx->x_d.release();
@@ -402,12 +428,17 @@ int csbq_destroy(csbq_ctx* ctx)
     ctx->cnt.release();
     ctx->pe.release();
     ctx->pt.release();
-    ctx->bcnt.release();
-    ctx->bcur.release();
+    ctx->kin.release();
+    ctx->kout.release();
+    ctx->vin.release();
+    ctx->perm.release();
+    ctx->sorted.release();
+    ctx->runs_key.release();
+    ctx->runs_cnt.release();
+    ctx->nruns.release();
     ctx->err_d.release();
     ctx->work.release();
     ctx->off.release();
-    ctx->listf.release();
     ctx->tier.release();
     ctx->cub_tmp.release();
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
@@ -517,24 +548,44 @@ int csbq_set_geometry(csbq_ctx* ctx, int32_t n_bodies, const int32_t* n_panels, 
     LCHK(launch_expand(ctx->stream, (int)E, ctx->g_xc.p, ctx->g_eps.p, ctx->g_e1.p, ctx->g_sa.p, ctx->g_sc.p,
                        ctx->g_sign.p, ctx->g_body.p, ctx->clq.p, ctx->circ.p, ctx->info.p, ctx->ny.p, ctx->nn.p,
                        ctx->nw.p, N));
-    // upsampled rules (x2, x4) and their interpolation operators
-    for (int ti = 0; ti < 2; ++ti) {
-        int f = ti ? 4 : 2;
-        int64_t Mf = (int64_t)f * f * NPE + NPE;
-        ctx->Mtot[ti] = E * Mf;
+    // upsampled whole-panel rules (Gauss-Legendre of up_ns points in s times
+    // up_nt angles) and the Lagrange matrices from the NS panel nodes to them
+    for (int ti = 0; ti < NUP; ++ti) {
+        const int nsf = up_ns(ti), ntf = up_nt(ti);
+        ctx->Mtot[ti] = E * up_pts(ti);
         ALLOC(ctx->cpy[ti], (size_t)ctx->Mtot[ti] * 3);
         ALLOC(ctx->cpn[ti], (size_t)ctx->Mtot[ti] * 3);
         ALLOC(ctx->cpw[ti], (size_t)ctx->Mtot[ti]);
-        std::vector<double> L((size_t)f * NS * NS);
-        for (int p = 0; p < f * NS; ++p) {
-            int kk = p / NS, g = p % NS;
-            double xn = -1.0 + (2.0 * kk + 1.0 + ctx->gx[g]) / f;
-            lagrange_row(NS, ctx->gx, ctx->lam, xn, &L[(size_t)p * NS]);
-        }
+        std::vector<double> gxf(nsf), gwf(nsf), lamf(nsf), Df((size_t)nsf * nsf), Tf((size_t)nsf * nsf);
+        gl_tables(nsf, gxf.data(), gwf.data(), lamf.data(), Df.data(), Tf.data());
+        std::vector<double> L((size_t)nsf * NS);
+        for (int p = 0; p < nsf; ++p) lagrange_row(NS, ctx->gx, ctx->lam, gxf[p], &L[(size_t)p * NS]);
         ALLOC(ctx->Lup[ti], L.size());
-        HIPC(hipMemcpyAsync(ctx->Lup[ti].p, L.data(), L.size() * 8, hipMemcpyHostToDevice, ctx->stream));
-        LCHK(launch_expand_up(ctx->stream, (int)E, f, ctx->clq.p, ctx->info.p, ctx->ny.p, ctx->nn.p, ctx->nw.p, N,
+        ALLOC(ctx->upx[ti], (size_t)nsf);
+        ALLOC(ctx->upw[ti], (size_t)nsf);
+        HIPC(hipMemcpy(ctx->Lup[ti].p, L.data(), L.size() * 8, hipMemcpyHostToDevice));
+        HIPC(hipMemcpy(ctx->upx[ti].p, gxf.data(), nsf * 8, hipMemcpyHostToDevice));
+        HIPC(hipMemcpy(ctx->upw[ti].p, gwf.data(), nsf * 8, hipMemcpyHostToDevice));
+        LCHK(launch_expand_up(ctx->stream, (int)E, nsf, ntf, ctx->upx[ti].p, ctx->upw[ti].p, ctx->clq.p, ctx->info.p,
                               ctx->cpy[ti].p, ctx->cpn[ti].p, ctx->cpw[ti].p, ctx->Mtot[ti]));
+    }
+    // base (far-field) source set: own nodes, or the tier-0 rule for elements
+    // whose cross-section closes at an end
+    {
+        std::vector<ElemInfo> hinf((size_t)E);
+        HIPC(hipStreamSynchronize(ctx->stream));
+        HIPC(hipMemcpy(hinf.data(), ctx->info.p, (size_t)E * sizeof(ElemInfo), hipMemcpyDeviceToHost));
+        std::vector<int64_t> bo((size_t)E + 1, 0);
+        for (int64_t e = 0; e < E; ++e) bo[e + 1] = bo[e] + (hinf[e].fb == 2 ? up_pts(0) : NPE);
+        ctx->Nb = bo[E];
+        ALLOC(ctx->boff, (size_t)E + 1);
+        ALLOC(ctx->by, (size_t)ctx->Nb * 3);
+        ALLOC(ctx->bn, (size_t)ctx->Nb * 3);
+        ALLOC(ctx->bw, (size_t)ctx->Nb);
+        HIPC(hipMemcpy(ctx->boff.p, bo.data(), bo.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+        LCHK(launch_base_build(ctx->stream, (int)E, ctx->info.p, ctx->boff.p, ctx->ny.p, ctx->nn.p, ctx->nw.p, N,
+                               ctx->cpy[0].p, ctx->cpn[0].p, ctx->cpw[0].p, ctx->Mtot[0], ctx->by.p, ctx->bn.p,
+                               ctx->bw.p, ctx->Nb));
     }
     HIPC(hipStreamSynchronize(ctx->stream));
     ctx->have_geom = true;
@@ -616,21 +667,25 @@ static int eval_front(csbq_ctx* ctx, const double* sigma, int64_t T, const doubl
     ALLOC(ctx->band, (size_t)E * 2);
     ALLOC(ctx->rnear, (size_t)E);
     LCHK(launch_prep_sigma(ctx->stream, E, *sig_dev, ctx->nw.p, N, ctx->sw.p, ctx->sh.p, ctx->band.p,
-                           0.1 * ctx->gc.tol, ctx->info.p, ctx->gc, ctx->rnear.p));
+                           0.1 * ctx->gc.tol, ctx->info.p, ctx->circ.p, ctx->gc, ctx->rnear.p));
     return CSBQ_OK;
 }
 
-static int far_sum(csbq_ctx* ctx, int64_t T, int* nchunk_out)
+// smooth sum over a source set: the element nodes (native) or the base set
+static int far_sum(csbq_ctx* ctx, int64_t T, bool native, int* nchunk_out)
 {
-    const int64_t N = ctx->N;
+    const int64_t Ns = native ? ctx->N : ctx->Nb;
+    const double* sy = native ? ctx->ny.p : ctx->by.p;
+    const double* sn = native ? ctx->nn.p : ctx->bn.p;
+    const double* ss = native ? ctx->sw.p : ctx->bsw.p;
     int64_t tblocks = (T + 255) / 256;
     int nchunk = (int)std::max<int64_t>(1, std::min<int64_t>((4096 + tblocks - 1) / std::max<int64_t>(tblocks, 1),
-                                                             (N + 4095) / 4096));
-    int64_t chunk = ((N + nchunk - 1) / nchunk + 255) / 256 * 256;
-    nchunk = (int)((N + chunk - 1) / chunk);
+                                                             (Ns + 4095) / 4096));
+    int64_t chunk = ((Ns + nchunk - 1) / nchunk + 255) / 256 * 256;
+    nchunk = (int)((Ns + chunk - 1) / chunk);
     if (nchunk < 1) nchunk = 1;
     ALLOC(ctx->part, (size_t)nchunk * 6 * T + 1);
-    if (T > 0) LCHK(launch_far(ctx->stream, T, ctx->xt.p, ctx->ny.p, ctx->nn.p, ctx->sw.p, N, chunk, nchunk, ctx->part.p));
+    if (T > 0) LCHK(launch_far(ctx->stream, T, ctx->xt.p, sy, sn, ss, Ns, chunk, nchunk, ctx->part.p));
     *nchunk_out = nchunk;
     return CSBQ_OK;
 }
@@ -675,7 +730,7 @@ int csbq_smooth_sum(csbq_ctx* ctx, const double* sigma, int64_t T, const double*
     int rc = eval_front(ctx, sigma, T, x, tgt_node, mem, &sig, &tn);
     if (rc) return rc;
     int nchunk = 1;
-    if ((rc = far_sum(ctx, T, &nchunk))) return rc;
+    if ((rc = far_sum(ctx, T, true, &nchunk))) return rc;
     double *usl, *udl;
     if ((rc = outputs_back(ctx, T, u_sl, u_dl, mem, &usl, &udl))) return rc;
     if (T > 0) LCHK(launch_reduce(ctx->stream, T, nchunk, ctx->part.p, nullptr, nullptr, nullptr, usl, udl));
@@ -698,10 +753,17 @@ int csbq_eval(csbq_ctx* ctx, const double* sigma, int64_t T, const double* x, co
     HIPC(hipEventRecord(ctx->ph[0].b, st));
     const int E = ctx->E;
     const int64_t N = ctx->N;
-    // smooth sum over every source
+    // density on the tier-0 rule and the base source set, then the smooth
+    // sum over every base source
     HIPC(hipEventRecord(ctx->ph[1].a, st));
+    ALLOC(ctx->swf[0], (size_t)ctx->Mtot[0] * 3);
+    LCHK(launch_sigma_up(st, E, up_ns(0), up_nt(0), ctx->sh.p, ctx->Lup[0].p, ctx->cpw[0].p, ctx->swf[0].p,
+                         ctx->Mtot[0]));
+    ALLOC(ctx->bsw, (size_t)ctx->Nb * 3);
+    LCHK(launch_sigma_base(st, E, ctx->info.p, ctx->boff.p, ctx->sw.p, N, ctx->swf[0].p, ctx->Mtot[0], ctx->bsw.p,
+                           ctx->Nb));
     int nchunk = 1;
-    if ((rc = far_sum(ctx, T, &nchunk))) return rc;
+    if ((rc = far_sum(ctx, T, false, &nchunk))) return rc;
     HIPC(hipEventRecord(ctx->ph[1].b, st));
     // candidate pairs: count, scan, fill
     HIPC(hipEventRecord(ctx->ph[2].a, st));
@@ -726,68 +788,109 @@ int csbq_eval(csbq_ctx* ctx, const double* sigma, int64_t T, const double* x, co
         LCHK(launch_search(st, T, E, ctx->xt.p, tn, ctx->info.p, ctx->rnear.p, ctx->off.p, nullptr, ctx->pe.p,
                            ctx->pt.p));
     HIPC(hipEventRecord(ctx->ph[2].b, st));
-    // classification into correction tiers
+    // classification into correction tiers, in element-major order
     HIPC(hipEventRecord(ctx->ph[3].a, st));
-    LCHK(launch_classify(st, P, ctx->pe.p, ctx->pt.p, ctx->xt.p, T, tn, ctx->clq.p, ctx->circ.p, ctx->info.p,
-                         ctx->band.p, ctx->gc, ctx->tier.p, ctx->cls.p));
-    HIPC(hipEventRecord(ctx->ph[3].b, st));
-    // buckets per tier (x2/x4 grouped by element, padded to whole wavefronts)
-    HIPC(hipEventRecord(ctx->ph[4].a, st));
-    ALLOC(ctx->bcnt, (size_t)2 * E + 1);
-    ALLOC(ctx->bcur, (size_t)2 * E + 1);
-    HIPC(hipMemsetAsync(ctx->bcnt.p, 0, ((size_t)2 * E + 1) * sizeof(int), st));
-    LCHK(launch_bucket_count(st, P, ctx->tier.p, ctx->pe.p, ctx->bcnt.p, ctx->bcnt.p + E, ctx->bcnt.p + 2 * E));
-    std::vector<int> hc((size_t)2 * E + 1);
-    HIPC(hipMemcpyAsync(hc.data(), ctx->bcnt.p, hc.size() * sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPC(hipStreamSynchronize(st));
-    std::vector<int> cur((size_t)2 * E + 1);
-    int nwaves[2] = {0, 0};
-    int64_t npair[2] = {0, 0};
-    std::vector<int> we[2];
-    for (int ti = 0; ti < 2; ++ti) {
-        int pos = 0;
-        for (int e = 0; e < E; ++e) {
-            int c = hc[(size_t)ti * E + e];
-            cur[(size_t)ti * E + e] = pos;
-            int w = (c + 63) / 64;
-            for (int k = 0; k < w; ++k) we[ti].push_back(e);
-            pos += w * 64;
-            npair[ti] += c;
-        }
-        nwaves[ti] = (int)we[ti].size();
-        ALLOC(ctx->list[ti], (size_t)nwaves[ti] * 64 + 1);
-        ALLOC(ctx->wave_elem[ti], (size_t)nwaves[ti] + 1);
-        HIPC(hipMemsetAsync(ctx->list[ti].p, 0xFF, ((size_t)nwaves[ti] * 64 + 1) * sizeof(int64_t), st));
-        if (nwaves[ti])
-            HIPC(hipMemcpyAsync(ctx->wave_elem[ti].p, we[ti].data(), we[ti].size() * sizeof(int),
-                                hipMemcpyHostToDevice, st));
+    int ebits = 1;
+    while ((1LL << ebits) < (long long)E) ++ebits;
+    int kbits = 1;
+    while ((1LL << kbits) < (long long)(TIER_FULL + 1) * E) ++kbits;
+    ALLOC(ctx->kin, (size_t)P + 1);
+    ALLOC(ctx->kout, (size_t)P + 1);
+    ALLOC(ctx->vin, (size_t)P + 1);
+    ALLOC(ctx->perm, (size_t)P + 1);
+    ALLOC(ctx->sorted, (size_t)P + 1);
+    {
+        size_t b1 = 0, b2 = 0, b3 = 0;
+        HIPC(hipcub::DeviceRadixSort::SortPairs(nullptr, b1, ctx->pe.p, ctx->kout.p, ctx->vin.p, ctx->perm.p,
+                                                (int)P, 0, ebits, st));
+        HIPC(hipcub::DeviceRadixSort::SortPairs(nullptr, b2, ctx->kin.p, ctx->kout.p, ctx->vin.p, ctx->sorted.p,
+                                                (int)P, 0, kbits, st));
+        HIPC(hipcub::DeviceRunLengthEncode::Encode(nullptr, b3, ctx->kout.p, ctx->runs_key.p, ctx->runs_cnt.p,
+                                                   ctx->nruns.p, (int)P, st));
+        size_t need = std::max(b1, std::max(b2, b3));
+        if (need > tmpb) ALLOC(ctx->cub_tmp, need);
+        tmpb = std::max(tmpb, need);
     }
-    const int nfull = hc[(size_t)2 * E];
-    cur[(size_t)2 * E] = 0;
-    ALLOC(ctx->listf, (size_t)nfull + 1);
-    HIPC(hipMemcpyAsync(ctx->bcur.p, cur.data(), cur.size() * sizeof(int), hipMemcpyHostToDevice, st));
-    LCHK(launch_bucket_fill(st, P, ctx->tier.p, ctx->pe.p, ctx->bcur.p, ctx->bcur.p + E, ctx->bcur.p + 2 * E,
-                            ctx->list[0].p, ctx->list[1].p, ctx->listf.p));
+    LCHK(launch_iota(st, P, ctx->vin.p));
+    if (P > 0)
+        HIPC(hipcub::DeviceRadixSort::SortPairs(ctx->cub_tmp.p, tmpb, ctx->pe.p, ctx->kout.p, ctx->vin.p,
+                                                ctx->perm.p, (int)P, 0, ebits, st));
+    LCHK(launch_classify(st, P, ctx->perm.p, ctx->pe.p, ctx->pt.p, ctx->xt.p, T, tn, ctx->clq.p, ctx->circ.p,
+                         ctx->info.p, ctx->band.p, ctx->gc, ctx->tier.p, ctx->cls.p));
+    HIPC(hipEventRecord(ctx->ph[3].b, st));
+    // buckets: pairs sorted by (tier, element); runs give the per-element segments
+    HIPC(hipEventRecord(ctx->ph[4].a, st));
+    const size_t maxruns = (size_t)(TIER_FULL + 1) * E + 1;
+    ALLOC(ctx->runs_key, maxruns);
+    ALLOC(ctx->runs_cnt, maxruns);
+    ALLOC(ctx->nruns, 1);
+    int nr = 0;
+    std::vector<int> rkey, rcnt;
+    if (P > 0) {
+        LCHK(launch_tier_keys(st, P, E, ctx->tier.p, ctx->pe.p, ctx->kin.p, ctx->vin.p));
+        HIPC(hipcub::DeviceRadixSort::SortPairs(ctx->cub_tmp.p, tmpb, ctx->kin.p, ctx->kout.p, ctx->vin.p,
+                                                ctx->sorted.p, (int)P, 0, kbits, st));
+        HIPC(hipcub::DeviceRunLengthEncode::Encode(ctx->cub_tmp.p, tmpb, ctx->kout.p, ctx->runs_key.p,
+                                                   ctx->runs_cnt.p, ctx->nruns.p, (int)P, st));
+        HIPC(hipMemcpyAsync(&nr, ctx->nruns.p, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPC(hipStreamSynchronize(st));
+        rkey.resize(nr);
+        rcnt.resize(nr);
+        if (nr) {
+            HIPC(hipMemcpy(rkey.data(), ctx->runs_key.p, nr * sizeof(int), hipMemcpyDeviceToHost));
+            HIPC(hipMemcpy(rcnt.data(), ctx->runs_cnt.p, nr * sizeof(int), hipMemcpyDeviceToHost));
+        }
+    }
+    std::vector<int> wd[NUP];
+    int64_t npair[NUP] = {0, 0, 0};
+    int nfull = 0, full_start = 0;
+    {
+        int pos = 0;
+        for (int r = 0; r < nr; ++r) {
+            int trr = rkey[r] / E, e = rkey[r] % E, c = rcnt[r];
+            if (trr >= 1 && trr <= NUP) {
+                for (int o = 0; o < c; o += 64) {
+                    wd[trr - 1].push_back(pos + o);
+                    wd[trr - 1].push_back(std::min(64, c - o));
+                    wd[trr - 1].push_back(e);
+                }
+                npair[trr - 1] += c;
+            } else if (trr == TIER_FULL) {
+                if (nfull == 0) full_start = pos;
+                nfull += c;
+            }
+            pos += c;
+        }
+    }
+    int nwaves[NUP];
+    for (int ti = 0; ti < NUP; ++ti) {
+        nwaves[ti] = (int)(wd[ti].size() / 3);
+        ALLOC(ctx->wdesc[ti], wd[ti].size() + 1);
+        if (nwaves[ti])
+            HIPC(hipMemcpy(ctx->wdesc[ti].p, wd[ti].data(), wd[ti].size() * sizeof(int), hipMemcpyHostToDevice));
+    }
     HIPC(hipEventRecord(ctx->ph[4].b, st));
     // upsampled-rule corrections
     HIPC(hipEventRecord(ctx->ph[5].a, st));
-    for (int ti = 0; ti < 2; ++ti) {
+    for (int ti = 0; ti < NUP; ++ti) {
         if (!nwaves[ti]) continue;
-        int f = ti ? 4 : 2;
-        ALLOC(ctx->swf[ti], (size_t)ctx->Mtot[ti] * 3);
-        LCHK(launch_sigma_up(st, E, f, ctx->sh.p, ctx->Lup[ti].p, ctx->cpw[ti].p, ctx->sw.p, N, ctx->swf[ti].p,
-                             ctx->Mtot[ti]));
-        LCHK(launch_corr_up(st, f, nwaves[ti], ctx->wave_elem[ti].p, ctx->list[ti].p, ctx->pt.p, ctx->xt.p, T,
-                            ctx->cpy[ti].p, ctx->cpn[ti].p, ctx->swf[ti].p, ctx->Mtot[ti], ctx->corr.p));
+        if (ti > 0) {
+            ALLOC(ctx->swf[ti], (size_t)ctx->Mtot[ti] * 3);
+            LCHK(launch_sigma_up(st, E, up_ns(ti), up_nt(ti), ctx->sh.p, ctx->Lup[ti].p, ctx->cpw[ti].p,
+                                 ctx->swf[ti].p, ctx->Mtot[ti]));
+        }
+        LCHK(launch_corr_up(st, up_pts(ti), nwaves[ti], ctx->wdesc[ti].p, ctx->sorted.p, ctx->pt.p, ctx->xt.p, T,
+                            ctx->cpy[ti].p, ctx->cpn[ti].p, ctx->swf[ti].p, ctx->Mtot[ti], ctx->boff.p, ctx->by.p,
+                            ctx->bn.p, ctx->bsw.p, ctx->Nb, ctx->corr.p));
     }
     HIPC(hipEventRecord(ctx->ph[5].b, st));
     // special quadrature corrections
     HIPC(hipEventRecord(ctx->ph[6].a, st));
     ALLOC(ctx->work, (size_t)2 * nfull + 2);
-    LCHK(launch_corr_full(st, nfull, ctx->listf.p, ctx->pe.p, ctx->pt.p, ctx->xt.p, T, tn, ctx->clq.p, ctx->sh.p,
-                          ctx->info.p, ctx->band.p, ctx->cls.p, ctx->ny.p, ctx->nn.p, ctx->sw.p, N, ctx->roff.p,
-                          ctx->rth.p, ctx->rw.p, ctx->nb, ctx->lx.p, ctx->lw.p, ctx->nl, ctx->gc, ctx->corr.p,
-                          ctx->err_d.p, ctx->work.p));
+    LCHK(launch_corr_full(st, nfull, ctx->sorted.p + full_start, ctx->pe.p, ctx->pt.p, ctx->xt.p, T, tn, ctx->clq.p, ctx->sh.p,
+                          ctx->info.p, ctx->band.p, ctx->cls.p, ctx->boff.p, ctx->by.p, ctx->bn.p, ctx->bsw.p, ctx->Nb, ctx->roff.p,
+                          ctx->rth.p, ctx->rw.p, ctx->nb, ctx->lx.p, ctx->lw.p, ctx->nl, ctx->rcs.p, ctx->rsn.p,
+                          ctx->romc.p, ctx->gc, ctx->corr.p, ctx->err_d.p, ctx->work.p));
     HIPC(hipEventRecord(ctx->ph[6].b, st));
     // reduction
     HIPC(hipEventRecord(ctx->ph[7].a, st));
@@ -797,8 +900,7 @@ int csbq_eval(csbq_ctx* ctx, const double* sigma, int64_t T, const double* x, co
     HIPC(hipEventRecord(ctx->ph[7].b, st));
     ctx->last_T = T;
     ctx->last_P = P;
-    ctx->last_n2 = npair[0];
-    ctx->last_n4 = npair[1];
+    for (int ti = 0; ti < NUP; ++ti) ctx->last_nup[ti] = npair[ti];
     ctx->last_nf = nfull;
     ctx->ph_ok = true;
     return finish(ctx, T, u_sl, u_dl, mem);
@@ -810,10 +912,11 @@ int csbq_stats(const csbq_ctx* ctx, char* buf, int64_t cap)
     std::string s = "{";
     char tmp[256];
     std::snprintf(tmp, sizeof tmp,
-                  "\"targets\": %lld, \"candidates\": %lld, \"pairs_x2\": %lld, \"pairs_x4\": %lld, "
-                  "\"pairs_full\": %lld, \"flags\": %d",
-                  (long long)ctx->last_T, (long long)ctx->last_P, (long long)ctx->last_n2, (long long)ctx->last_n4,
-                  (long long)ctx->last_nf, ctx->last_err_flags);
+                  "\"targets\": %lld, \"candidates\": %lld, \"pairs_up1\": %lld, \"pairs_up2\": %lld, "
+                  "\"pairs_up3\": %lld, \"pairs_full\": %lld, \"flags\": %d, \"sources_base\": %lld",
+                  (long long)ctx->last_T, (long long)ctx->last_P, (long long)ctx->last_nup[0],
+                  (long long)ctx->last_nup[1], (long long)ctx->last_nup[2], (long long)ctx->last_nf,
+                  ctx->last_err_flags, (long long)ctx->Nb);
     s += tmp;
     if (ctx->ph_ok && ctx->last_nf > 0) {
         std::vector<int> wk((size_t)2 * ctx->last_nf);

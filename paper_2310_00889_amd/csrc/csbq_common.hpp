@@ -23,8 +23,15 @@ constexpr int MAXLOG = 64;             // nodes of the log rule
 // centerline quantity slots (clq[e][q][i], i = GL node)
 enum { Q_X = 0, Q_XP = 3, Q_XPP = 6, Q_E = 9, Q_EP = 10, Q_F = 11, Q_FP = 14 };
 
-// correction tiers of a (target, element) pair
-enum : int8_t { TIER_SKIP = 0, TIER_UP2 = 1, TIER_UP4 = 2, TIER_FULL = 3 };
+// correction tiers of a (target, element) pair: skip, three upsampled
+// whole-panel tensor rules (Gauss-Legendre of up_ns points in s times up_nt
+// angles), and the special quadrature
+enum : int8_t { TIER_SKIP = 0, TIER_UP1 = 1, TIER_UP2 = 2, TIER_UP3 = 3, TIER_FULL = 4 };
+constexpr int NUP = 3;
+constexpr int MAXUPNS = 64;
+__host__ __device__ constexpr int up_ns(int k) { return k == 2 ? 64 : 32; }
+__host__ __device__ constexpr int up_nt(int k) { return k == 0 ? 32 : (k == 1 ? 64 : 128); }
+__host__ __device__ constexpr int64_t up_pts(int k) { return (int64_t)up_ns(k) * up_nt(k); }
 
 // sub-panel kinds of an s-rule
 enum : int { SUB_GL = 0, SUB_LOG_LO = 1, SUB_LOG_HI = 2 };  // log singularity at lo / at hi
@@ -37,6 +44,8 @@ struct ElemInfo {
     double smax;       // largest surface speed |dy/ds| bound
     int32_t sign;      // normal orientation
     int32_t body;
+    int32_t fb;        // far-field (base) rule: 1 = the element's own nodes, 2 = up_ns(0) x NT rule
+    int32_t pad_;
 };
 
 // constants of the error estimates (calibrated against the CPU oracle)

@@ -14,7 +14,7 @@
 //                   element grown by its near-region radius (Section 3.2.1)
 //   k_classify      per pair: closest circle, GL (Bernstein ellipse) and
 //                   trapezoid error estimates -> correction tier
-//   k_corr_up       tier x2/x4: upsampled rule minus the smooth rule
+//   k_corr_up       upsampled tiers: upsampled rule minus the smooth rule
 //   k_corr_full     special quadrature (Sections 3.2.2-3.2.4) minus the
 //                   smooth rule, one wavefront per pair
 //   k_reduce        far sum + corrections in a fixed order per target
@@ -32,6 +32,8 @@ __constant__ double c_D[NS * NS];    // differentiation matrix on [-1,1]
 __constant__ double c_T[NS * NS];    // Legendre transform: coef_k = sum_i T[k][i] f_i
 __constant__ double c_cos[NT];       // cos(2 pi j / NT)
 __constant__ double c_sin[NT];
+__constant__ double c_cos128[128];   // cos(2 pi k / 128), for trapezoid rules of nt, 2nt, 4nt points
+__constant__ double c_sin128[128];
 
 static constexpr double PI = 3.14159265358979323846;
 
@@ -50,6 +52,13 @@ int upload_constants(const double* gx, const double* gw, const double* lam, cons
     if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_T), T, sizeof(double) * NS * NS)) != hipSuccess) return (int)e;
     if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_cos), cs, sizeof(double) * NT)) != hipSuccess) return (int)e;
     if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_sin), sn, sizeof(double) * NT)) != hipSuccess) return (int)e;
+    double c128[128], s128[128];
+    for (int j = 0; j < 128; ++j) {
+        c128[j] = cos(2.0 * PI * j / 128);
+        s128[j] = sin(2.0 * PI * j / 128);
+    }
+    if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_cos128), c128, sizeof(double) * 128)) != hipSuccess) return (int)e;
+    if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_sin128), s128, sizeof(double) * 128)) != hipSuccess) return (int)e;
     return 0;
 }
 
@@ -92,8 +101,10 @@ __device__ inline void circle_at_x(const double* __restrict__ clq, double x, dou
     double l[NS];
     bary_weights(x, c_gx, c_lam, l);
     double xp[3];
+#pragma unroll
     for (int d = 0; d < 3; ++d) {
         double v = 0.0, vp = 0.0;
+#pragma unroll
         for (int i = 0; i < NS; ++i) {
             v += l[i] * clq[(Q_X + d) * NS + i];
             vp += l[i] * clq[(Q_XP + d) * NS + i];
@@ -102,6 +113,7 @@ __device__ inline void circle_at_x(const double* __restrict__ clq, double x, dou
         xp[d] = vp;
     }
     double e = 0.0;
+#pragma unroll
     for (int i = 0; i < NS; ++i) e += l[i] * clq[Q_E * NS + i];
     *E = e;
     double is = 1.0 / sqrt(dot3(xp, xp));
@@ -114,9 +126,13 @@ __device__ inline void circle_dist(const double* X, const double* t, double E, c
     double z = dot3(v, t);
     double r2 = fmax(0.0, dot3(v, v) - z * z);
     double rho = sqrt(r2);
-    double dr = rho - E;
+    // a circle of vanishing radius (the pole of a body of revolution, where the
+    // interpolated radius may even be a tiny negative number) gives a constant
+    // angular integrand: no trapezoid error
+    const double ae = fabs(E);
+    double dr = rho - ae;
     *d2 = dr * dr + z * z;
-    *cha = rho > 0.0 ? *d2 / (2.0 * rho * E) : 1e300;
+    *cha = (rho > 0.0 && ae > 1e-300) ? *d2 / (2.0 * rho * ae) : 1e300;
 }
 
 // ---------------------------------------------------------------------------
@@ -248,57 +264,72 @@ __global__ __launch_bounds__(512) void k_expand(int E, const double* __restrict_
         inf.smax = outv[2];
         inf.sign = esign[e];
         inf.body = ebody[e];
+        // a cross-section that closes at a panel end (a body of revolution
+        // described in polar angle, e.g. a sphere as one element) makes the
+        // s-integrand converge slowly far away: its far-field rule is the
+        // up_ns(0)-point Gauss rule in s
+        const double* cp0 = circ + (int64_t)e * NCIRC * CIRQ;
+        const double eend = fmin(fabs(cp0[6]), fabs(cp0[(NCIRC - 1) * CIRQ + 6]));
+        inf.fb = (eend < 1e-3 * outv[1]) ? 2 : 1;
+        inf.pad_ = 0;
         info[e] = inf;
     }
 }
 
-// Upsampled tensor rule of tier factor f: f sub-panels of NS GL nodes in s,
-// f*NT uniform angles.  Block = one s-row (f*NT threads), grid = (E, f*NS).
-// Points of element e start at e*Mf (Mf = f^2 NPE + NPE; the last NPE slots
-// hold the element's own nodes, filled by k_cp_nodes).
-__global__ __launch_bounds__(128) void k_expand_up(int E, int f, const double* __restrict__ clq,
+// Upsampled whole-panel tensor rule of tier k: ns_f Gauss-Legendre nodes on
+// the whole panel in s (gx_f, gw_f on [-1,1]) times nt_f uniform angles.
+// Block = one s-row (nt_f threads), grid = (E, ns_f); element e's points start
+// at e * ns_f * nt_f.
+__global__ __launch_bounds__(128) void k_expand_up(int E, int ns_f, int nt_f, const double* __restrict__ gx_f,
+                                                   const double* __restrict__ gw_f, const double* __restrict__ clq,
                                                    const ElemInfo* __restrict__ info, double* __restrict__ cpy,
                                                    double* __restrict__ cpn, double* __restrict__ cpw,
                                                    int64_t Mtot)
 {
     const int e = blockIdx.x, p = blockIdx.y, q = threadIdx.x;
-    const int ntf = f * NT;
-    const int64_t Mf = (int64_t)f * f * NPE + NPE;
+    const int64_t Mf = (int64_t)ns_f * nt_f;
     const ElemInfo inf = info[e];
-    const int k = p / NS, g = p % NS;
-    // normalised position of GL node g of sub-panel k in [-1,1]
-    const double xn = -1.0 + (2.0 * k + 1.0 + c_gx[g]) / f;
     Frame fr;
-    frame_at_x(clq + (int64_t)e * CLQ * NS, xn, fr);
-    double th = 2.0 * PI * q / ntf;
+    frame_at_x(clq + (int64_t)e * CLQ * NS, gx_f[p], fr);
+    double th = 2.0 * PI * q / nt_f;
     double st, ct;
     sincos(th, &st, &ct);
     double y[3], ys[3], yt[3], jn[3];
     surface_at(fr, ct, st, y, ys, yt);
     cross3(yt, ys, jn);
     double J = sqrt(dot3(jn, jn));
-    const int64_t m = (int64_t)e * Mf + (int64_t)p * ntf + q;
+    const int64_t m = (int64_t)e * Mf + (int64_t)p * nt_f + q;
     for (int d = 0; d < 3; ++d) {
         cpy[d * Mtot + m] = y[d];
         cpn[d * Mtot + m] = inf.sign * jn[d] / J;
     }
-    cpw[m] = J * c_gw[g] * (0.5 * (inf.c - inf.a) / f) * (2.0 * PI / ntf);
+    cpw[m] = J * gw_f[p] * (0.5 * (inf.c - inf.a)) * (2.0 * PI / nt_f);
 }
 
-__global__ void k_cp_nodes(int E, int f, const double* __restrict__ ny, const double* __restrict__ nn,
-                           const double* __restrict__ nw, int64_t N, double* __restrict__ cpy,
-                           double* __restrict__ cpn, double* __restrict__ cpw, int64_t Mtot)
+// Far-field (base) source set: each element contributes its own nodes (fb = 1)
+// or its tier-0 rule (fb = 2); boff[e] is the element's first base source.
+__global__ void k_base_build(int E, const ElemInfo* __restrict__ info, const int64_t* __restrict__ boff,
+                             const double* __restrict__ ny, const double* __restrict__ nn,
+                             const double* __restrict__ nw, int64_t N, const double* __restrict__ c0y,
+                             const double* __restrict__ c0n, const double* __restrict__ c0w, int64_t M0,
+                             double* __restrict__ by, double* __restrict__ bn, double* __restrict__ bw, int64_t Nb)
 {
-    const int64_t Mf = (int64_t)f * f * NPE + NPE;
-    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)E * NPE) return;
-    int64_t e = idx / NPE, r = idx % NPE;
-    int64_t m = e * Mf + (int64_t)f * f * NPE + r;
-    for (int d = 0; d < 3; ++d) {
-        cpy[d * Mtot + m] = ny[d * N + idx];
-        cpn[d * Mtot + m] = nn[d * N + idx];
+    const int e = blockIdx.x;
+    const int fb = info[e].fb;
+    const int64_t o = boff[e];
+    const int cnt = fb == 2 ? (int)up_pts(0) : NPE;
+    for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
+        int64_t src = fb == 2 ? (int64_t)e * up_pts(0) + k : (int64_t)e * NPE + k;
+        const double* sy = fb == 2 ? c0y : ny;
+        const double* sn = fb == 2 ? c0n : nn;
+        const double* swt = fb == 2 ? c0w : nw;
+        const int64_t ld = fb == 2 ? M0 : N;
+        for (int d = 0; d < 3; ++d) {
+            by[d * Nb + o + k] = sy[d * ld + src];
+            bn[d * Nb + o + k] = sn[d * ld + src];
+        }
+        bw[o + k] = swt[src];
     }
-    cpw[m] = -nw[idx];
 }
 
 // ---------------------------------------------------------------------------
@@ -376,34 +407,32 @@ __global__ __launch_bounds__(512) void k_prep_sigma(int E, const double* __restr
     }
 }
 
-// density times weight on the upsampled rule of factor f (and -sigma*w on the
-// element's own nodes): sigma(s_p, t_q) from the GL-circle Fourier
-// coefficients interpolated to s_p and synthesised at t_q.
-__global__ __launch_bounds__(256) void k_sigma_up(int E, int f, const double* __restrict__ sh,
+// density times weight on the upsampled whole-panel rule (ns_f x nt_f):
+// sigma(s_p, t_q) from the GL-circle Fourier coefficients interpolated to s_p
+// (Lup: ns_f x NS Lagrange matrix) and synthesised at t_q.
+__global__ __launch_bounds__(256) void k_sigma_up(int E, int ns_f, int nt_f, const double* __restrict__ sh,
                                                   const double* __restrict__ Lup, const double* __restrict__ cpw,
-                                                  const double* __restrict__ sw, int64_t N,
                                                   double* __restrict__ swf, int64_t Mtot)
 {
     const int e = blockIdx.x, tid = threadIdx.x;
-    const int ntf = f * NT;
-    const int64_t Mf = (int64_t)f * f * NPE + NPE;
+    const int64_t Mf = (int64_t)ns_f * nt_f;
     __shared__ double shl[NS * NSH];
     __shared__ double A[NS * NSH];
     for (int o = tid; o < NS * NSH; o += blockDim.x) shl[o] = sh[(int64_t)e * NS * NSH + o];
     __syncthreads();
-    for (int rb = 0; rb < f; ++rb) {
-        // coefficients at the 16 s-points of sub-panel rb
+    for (int rb = 0; rb < ns_f; rb += NS) {
+        // coefficients at s-points rb .. rb+15
         for (int o = tid; o < NS * NSH; o += blockDim.x) {
             int r = o / NSH, k = o % NSH;
-            int p = rb * NS + r;
+            int pp = rb + r;
             double v = 0.0;
-            for (int ii = 0; ii < NS; ++ii) v += Lup[p * NS + ii] * shl[ii * NSH + k];
+            for (int ii = 0; ii < NS; ++ii) v += Lup[pp * NS + ii] * shl[ii * NSH + k];
             A[o] = v;
         }
         __syncthreads();
-        for (int o = tid; o < NS * ntf; o += blockDim.x) {
-            int r = o / ntf, q = o % ntf;
-            double th = 2.0 * PI * q / ntf;
+        for (int o = tid; o < NS * nt_f; o += blockDim.x) {
+            int r = o / nt_f, q = o % nt_f;
+            double th = 2.0 * PI * q / nt_f;
             double s1, c1;
             sincos(th, &s1, &c1);
             const double* ar = A + r * NSH;
@@ -417,7 +446,7 @@ __global__ __launch_bounds__(256) void k_sigma_up(int E, int f, const double* __
                 v1 += ar[l * 6 + 1] * cl + ar[l * 6 + 4] * sl;
                 v2 += ar[l * 6 + 2] * cl + ar[l * 6 + 5] * sl;
             }
-            int64_t m = (int64_t)e * Mf + (int64_t)(rb * NS + r) * ntf + q;
+            int64_t m = (int64_t)e * Mf + (int64_t)(rb + r) * nt_f + q;
             double w = cpw[m];
             swf[0 * Mtot + m] = v0 * w;
             swf[1 * Mtot + m] = v1 * w;
@@ -425,10 +454,20 @@ __global__ __launch_bounds__(256) void k_sigma_up(int E, int f, const double* __
         }
         __syncthreads();
     }
-    for (int r = tid; r < NPE; r += blockDim.x) {
-        int64_t m = (int64_t)e * Mf + (int64_t)f * f * NPE + r;
-        int64_t n = (int64_t)e * NPE + r;
-        for (int d = 0; d < 3; ++d) swf[d * Mtot + m] = -sw[d * N + n];
+}
+
+// density times weight on the base (far-field) source set
+__global__ void k_sigma_base(int E, const ElemInfo* __restrict__ info, const int64_t* __restrict__ boff,
+                             const double* __restrict__ sw, int64_t N, const double* __restrict__ swf0, int64_t M0,
+                             double* __restrict__ bsw, int64_t Nb)
+{
+    const int e = blockIdx.x;
+    const int fb = info[e].fb;
+    const int64_t o = boff[e];
+    const int cnt = fb == 2 ? (int)up_pts(0) : NPE;
+    for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
+        for (int d = 0; d < 3; ++d)
+            bsw[d * Nb + o + k] = fb == 2 ? swf0[d * M0 + (int64_t)e * up_pts(0) + k] : sw[d * N + (int64_t)e * NPE + k];
     }
 }
 
@@ -591,14 +630,121 @@ __device__ inline double rho_subpanels(double sr, double si, double a, double c,
     return best;
 }
 
-__global__ void k_classify(int64_t P, const int* __restrict__ pe, const int* __restrict__ pt,
-                           const double* __restrict__ xt, int64_t T, const int64_t* __restrict__ tnode,
-                           const double* __restrict__ clq, const double* __restrict__ circ,
-                           const ElemInfo* __restrict__ info, const int* __restrict__ band, GateConsts gc,
-                           int8_t* __restrict__ tier, double* __restrict__ cls)
+// --- complex arithmetic for the contact-point search
+struct cx {
+    double r, i;
+};
+__device__ __forceinline__ cx cadd(cx a, cx b) { return {a.r + b.r, a.i + b.i}; }
+__device__ __forceinline__ cx csub(cx a, cx b) { return {a.r - b.r, a.i - b.i}; }
+__device__ __forceinline__ cx cmul(cx a, cx b) { return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
+__device__ __forceinline__ cx cdiv(cx a, cx b)
 {
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P) return;
+    double d = b.r * b.r + b.i * b.i;
+    return {(a.r * b.r + a.i * b.i) / d, (a.i * b.r - a.r * b.i) / d};
+}
+
+// Circle-contact function at the complex (normalised) parameter z: the
+// product d^2 d'^2 of the squared distances from the target to the circle at z
+// and to its antipodal continuation, d^2 d'^2 = (|v|^2 + eps^2)^2 -
+// 4 eps^2 (|v|^2 - (v.x_c')^2/|x_c'|^2), v = x - x_c(z) (bilinear products).
+// The angular integral I(x, s) is analytic in s except where this vanishes,
+// so its zero nearest to the panel sets the Gauss-Legendre convergence rate.
+__device__ inline cx contact_fn(const double* __restrict__ clq, cx z, const double* x)
+{
+    // barycentric sums at the complex point in one pass (no stored weights)
+    cx sum = {0.0, 0.0};
+    cx X[3] = {{0, 0}, {0, 0}, {0, 0}}, Xp[3] = {{0, 0}, {0, 0}, {0, 0}}, E = {0, 0};
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+        const double dr = z.r - c_gx[i], di = z.i;
+        const double q = dr * dr + di * di;
+        double rq = __builtin_amdgcn_rcp(q);
+        rq = rq * fma(-q, rq, 2.0);  // one Newton step on the hardware reciprocal
+        const double inv = c_lam[i] * rq;
+        const cx li = {dr * inv, -di * inv};  // lam / (z - x_i)
+        sum = cadd(sum, li);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const double a = clq[(Q_X + d) * NS + i], b = clq[(Q_XP + d) * NS + i];
+            X[d].r += li.r * a;
+            X[d].i += li.i * a;
+            Xp[d].r += li.r * b;
+            Xp[d].i += li.i * b;
+        }
+        const double ee = clq[Q_E * NS + i];
+        E.r += li.r * ee;
+        E.i += li.i * ee;
+    }
+    const cx isum = cdiv({1.0, 0.0}, sum);
+    for (int d = 0; d < 3; ++d) {
+        X[d] = cmul(X[d], isum);
+        Xp[d] = cmul(Xp[d], isum);
+    }
+    E = cmul(E, isum);
+    cx vv = {0, 0}, xx = {0, 0}, vx = {0, 0};
+    for (int d = 0; d < 3; ++d) {
+        cx v = csub({x[d], 0.0}, X[d]);
+        vv = cadd(vv, cmul(v, v));
+        xx = cadd(xx, cmul(Xp[d], Xp[d]));
+        vx = cadd(vx, cmul(v, Xp[d]));
+    }
+    cx EE = cmul(E, E);
+    cx A = cadd(vv, EE);
+    cx z2 = cdiv(cmul(vx, vx), xx);
+    return csub(cmul(A, A), cmul({4.0 * EE.r, 4.0 * EE.i}, csub(vv, z2)));
+}
+
+// Smallest Bernstein parameter (relative to [-1,1]) over the zeros of the
+// contact function found by secant iterations from three starting points above
+// the closest real point xr at heights hi*{1, 1/4, 1/20}; returns 1e300 and
+// leaves (zr, zi) untouched if none converges.
+__device__ inline double contact_root(const double* __restrict__ clq, const double* x, double xr, double h0,
+                                      double* zr, double* zi)
+{
+    double best = 1e300;
+    const double fac[2] = {1.0, 0.2};
+    for (int k = 0; k < 2; ++k) {
+        cx z0 = {xr, h0 * fac[k]};
+        cx z1 = {xr + 0.05 * h0 * fac[k], 1.1 * h0 * fac[k]};
+        cx f0 = contact_fn(clq, z0, x), f1 = contact_fn(clq, z1, x);
+        bool ok = false;
+        for (int it = 0; it < 30; ++it) {
+            cx df = csub(f1, f0);
+            if (df.r == 0.0 && df.i == 0.0) break;
+            cx step = cdiv(cmul(f1, csub(z1, z0)), df);
+            z0 = z1;
+            f0 = f1;
+            z1 = csub(z1, step);
+            if (!(fabs(z1.r) < 8.0 && fabs(z1.i) < 8.0)) break;
+            f1 = contact_fn(clq, z1, x);
+            if (sqrt(step.r * step.r + step.i * step.i) < 1e-9 * (1.0 + fabs(z1.r) + fabs(z1.i))) {
+                ok = true;
+                break;
+            }
+        }
+        if (!ok || !(fabs(z1.i) > 1e-9)) continue;
+        double rho = bernstein_rho(z1.r, fabs(z1.i), -1.0, 1.0);
+        if (rho < best) {
+            best = rho;
+            *zr = z1.r;
+            *zi = fabs(z1.i);
+        }
+    }
+    return best;
+}
+
+// Pairs are visited in element-major order (perm), so the lanes of a
+// wavefront read the same element's data.
+__global__ __launch_bounds__(128) void k_classify(int64_t P, const int* __restrict__ perm, const int* __restrict__ pe,
+                           const int* __restrict__ pt, const double* __restrict__ xt, int64_t T,
+                           const int64_t* __restrict__ tnode, const double* __restrict__ clq,
+                           const double* __restrict__ circ, const ElemInfo* __restrict__ info,
+                           const int* __restrict__ band, GateConsts gc, int8_t* __restrict__ tier,
+                           double* __restrict__ cls)
+{
+    const int64_t ii = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (ii >= P) return;
+    const int64_t p = perm[ii];
     const int e = pe[p];
     const int64_t t = pt[p];
     const ElemInfo inf = info[e];
@@ -638,39 +784,56 @@ __global__ void k_classify(int64_t P, const int* __restrict__ pe, const int* __r
         return cha;
     };
     double d2c, chac;
-    double xd = golden_min(fd, xn_of(max(kd - 1, 0)), xn_of(min(kd + 1, NCIRC - 1)), 40, &d2c);
-    golden_min(fa, xn_of(max(ka - 1, 0)), xn_of(min(ka + 1, NCIRC - 1)), 40, &chac);
+    double xd = golden_min(fd, xn_of(max(kd - 1, 0)), xn_of(min(kd + 1, NCIRC - 1)), 26, &d2c);
+    golden_min(fa, xn_of(max(ka - 1, 0)), xn_of(min(ka + 1, NCIRC - 1)), 26, &chac);
     d2c = fmin(d2c, bd);
     chac = fmin(chac, ba);
-    const double sc_ = 0.5 * (inf.a + inf.c) + 0.5 * (inf.c - inf.a) * xd;
-    // speed bound at the closest circle (interpolated between neighbouring circles' bounds)
+    // speed bound near the closest circle
     double spd = fmax(cc[kd * CIRQ + 7], cc[min(kd + 1, NCIRC - 1) * CIRQ + 7]);
     spd = fmax(spd, cc[max(kd - 1, 0) * CIRQ + 7]);
     const double dc = sqrt(d2c);
     const double ac = acosh1p(chac);
-    cp[0] = sc_;
-    cp[1] = dc;
-    cp[2] = spd;
+    // singularity of the s-integrand: locally flat estimate s_c + i d/speed, or
+    // the nearest zero of the contact function if that is closer
+    const double half = 0.5 * (inf.c - inf.a), mid = 0.5 * (inf.a + inf.c);
+    double zr = xd, zi = dc / spd / half;
+    const double rho_lin = bernstein_rho(zr, zi, -1.0, 1.0);
+    double rr = xd, ri = zi;
+    double rho_root = contact_root(cq, x, xd, fmax(zi, 1e-6), &rr, &ri);
+    if (rho_root < rho_lin) {
+        zr = rr;
+        zi = ri;
+    }
+    const double sr = mid + half * zr, si = half * zi;
+    cp[0] = sr;
+    cp[1] = si;
+    cp[2] = 1.0;
     cp[3] = ac;
     const int Ms = band[2 * e], Mt = band[2 * e + 1];
+    // Gauss-Legendre error on the whole panel ~ rho^-(2n - Ms) for a density of
+    // degree Ms; trapezoid error ~ exp(-(nt - Mt - extra) a)
+    const double rho = bernstein_rho(sr, si, inf.a, inf.c);
+    const double lrho = log(rho);
+    const double lt = log(gc.tol);
     int8_t tr = TIER_FULL;
-    const int facs[3] = {1, 2, 4};
-    for (int fi = 0; fi < 3; ++fi) {
-        int f = facs[fi];
-        double rho = rho_subpanels(sc_, dc / spd, inf.a, inf.c, f);
-        double es = gc.cs * pow(rho, -(double)(2 * NS - Ms));
-        double et = gc.ct * exp(-(double)(f * NT - Mt - gc.extra_modes) * ac);
-        if (es <= gc.tol && et <= gc.tol) {
-            tr = (f == 1) ? TIER_SKIP : (f == 2 ? TIER_UP2 : TIER_UP4);
+    for (int k = -1; k < NUP; ++k) {
+        const int nsr = k < 0 ? NS * inf.fb : up_ns(k);
+        const int ntr = k < 0 ? NT : up_nt(k);
+        if (k >= 0 && nsr <= NS * inf.fb && ntr <= NT) continue;   // no finer than the base rule
+        const double les = log(gc.cs) - (double)(2 * nsr - Ms) * lrho;
+        const double let = log(gc.ct) - (double)(ntr - Mt - gc.extra_modes) * ac;
+        if (les <= lt && let <= lt) {
+            tr = (int8_t)(k + 1);
             break;
         }
     }
     tier[p] = tr;
 }
 
-// near-region radius of each element from its band limits (candidate filter)
-__global__ void k_rnear(int E, const ElemInfo* __restrict__ info, const int* __restrict__ band, GateConsts gc,
-                        double* __restrict__ rnear)
+// candidate radius of each element (the distance beyond which the plain rule
+// meets the tolerance by the same estimates)
+__global__ void k_rnear(int E, const ElemInfo* __restrict__ info, const double* __restrict__ circ,
+                        const int* __restrict__ band, GateConsts gc, double* __restrict__ rnear)
 {
     int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= E) return;
@@ -678,54 +841,60 @@ __global__ void k_rnear(int E, const ElemInfo* __restrict__ info, const int* __r
     const int Ms = band[2 * e], Mt = band[2 * e + 1];
     double areq = log(gc.ct / gc.tol) / (double)(NT - Mt - gc.extra_modes);
     double dth = inf.eps_max * (exp(areq) - 1.0);
-    double rreq = pow(gc.cs / gc.tol, 1.0 / (double)(2 * NS - Ms));
+    double rreq = pow(gc.cs / gc.tol, 1.0 / (double)(2 * NS * inf.fb - Ms));
     double h = 0.5 * (inf.c - inf.a);
     double ds = inf.smax * h * 0.5 * (rreq - 1.0 / rreq);
+    // an element whose cross-section closes at an end (a sphere in polar
+    // angle): the contact zero leaves the real axis only logarithmically with
+    // distance, cosh(pi Im s / (c - a)) ~ distance / (2 radius)
+    const double* cc = circ + (int64_t)e * NCIRC * CIRQ;
+    double e0 = fabs(cc[6]), e1 = fabs(cc[(NCIRC - 1) * CIRQ + 6]);
+    if (fmin(e0, e1) < 1e-3 * inf.eps_max) {
+        double imphi = 3.14159265358979323846 * 0.25 * (rreq - 1.0 / rreq);
+        ds = fmax(ds, 2.0 * inf.rad * cosh(fmin(imphi, 40.0)));
+    }
     rnear[e] = 1.05 * fmax(dth, ds) + 1e-12;
 }
 
 // ---------------------------------------------------------------------------
-// correction buckets
+// sort keys: element (for the classification order) and tier*E + element
+// (for the correction buckets); values are pair indices
 // ---------------------------------------------------------------------------
-__global__ void k_bucket_count(int64_t P, const int8_t* __restrict__ tier, const int* __restrict__ pe,
-                               int* __restrict__ cnt2, int* __restrict__ cnt4, int* __restrict__ nfull)
+__global__ void k_iota(int64_t P, int* __restrict__ v)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < P) v[p] = (int)p;
+}
+
+__global__ void k_tier_keys(int64_t P, int E, const int8_t* __restrict__ tier, const int* __restrict__ pe,
+                            int* __restrict__ key, int* __restrict__ val)
 {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
-    int8_t tr = tier[p];
-    if (tr == TIER_UP2) atomicAdd(cnt2 + pe[p], 1);
-    if (tr == TIER_UP4) atomicAdd(cnt4 + pe[p], 1);
-    if (tr == TIER_FULL) atomicAdd(nfull, 1);
-}
-
-__global__ void k_bucket_fill(int64_t P, const int8_t* __restrict__ tier, const int* __restrict__ pe,
-                              int* __restrict__ cur2, int* __restrict__ cur4, int* __restrict__ curf,
-                              int64_t* __restrict__ list2, int64_t* __restrict__ list4, int64_t* __restrict__ listf)
-{
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P) return;
-    int8_t tr = tier[p];
-    if (tr == TIER_UP2) list2[atomicAdd(cur2 + pe[p], 1)] = p;
-    if (tr == TIER_UP4) list4[atomicAdd(cur4 + pe[p], 1)] = p;
-    if (tr == TIER_FULL) listf[atomicAdd(curf, 1)] = p;
+    key[p] = (int)tier[p] * E + pe[p];
+    val[p] = (int)p;
 }
 
 // ---------------------------------------------------------------------------
-// tier x2 / x4: upsampled rule minus smooth rule, one wavefront per 64 pairs
-// of one element; the element's correction points are staged in LDS
+// upsampled tiers: upsampled rule minus smooth rule, one wavefront per 64
+// pairs of one element; the element's correction points are staged in LDS
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_corr_up(int f, const int* __restrict__ wave_elem,
-                                                const int64_t* __restrict__ list, const int* __restrict__ pt,
+// wave w covers sorted[ws[3w] .. ws[3w] + ws[3w+1]) of element ws[3w+2]:
+// the element's tier rule (Mf points) plus its base rule with negated weight,
+// staged in LDS 64 points at a time.
+__global__ __launch_bounds__(64) void k_corr_up(int64_t Mf, const int* __restrict__ ws,
+                                                const int* __restrict__ sorted, const int* __restrict__ pt,
                                                 const double* __restrict__ xt, int64_t T,
                                                 const double* __restrict__ cpy, const double* __restrict__ cpn,
                                                 const double* __restrict__ swf, int64_t Mtot,
-                                                double* __restrict__ corr)
+                                                const int64_t* __restrict__ boff, const double* __restrict__ by,
+                                                const double* __restrict__ bn, const double* __restrict__ bsw,
+                                                int64_t Nb, double* __restrict__ corr)
 {
     __shared__ double ly[3][64], ln_[3][64], ls[3][64];
     const int w = blockIdx.x, lane = threadIdx.x;
-    const int e = wave_elem[w];
-    const int64_t p = list[(int64_t)w * 64 + lane];
-    const int64_t Mf = (int64_t)f * f * NPE + NPE;
+    const int e = ws[3 * w + 2];
+    const int64_t p = (lane < ws[3 * w + 1]) ? (int64_t)sorted[(int64_t)ws[3 * w] + lane] : -1;
     double x0 = 0, x1 = 0, x2 = 0;
     if (p >= 0) {
         int64_t t = pt[p];
@@ -734,38 +903,49 @@ __global__ __launch_bounds__(64) void k_corr_up(int f, const int* __restrict__ w
         x2 = xt[2 * T + t];
     }
     double s0 = 0, s1 = 0, s2 = 0, d0 = 0, d1 = 0, d2 = 0;
-    const int64_t base0 = (int64_t)e * Mf;
-    for (int64_t base = 0; base < Mf; base += 64) {
-        int64_t m = base0 + base + lane;
-        ly[0][lane] = cpy[m];
-        ly[1][lane] = cpy[Mtot + m];
-        ly[2][lane] = cpy[2 * Mtot + m];
-        ln_[0][lane] = cpn[m];
-        ln_[1][lane] = cpn[Mtot + m];
-        ln_[2][lane] = cpn[2 * Mtot + m];
-        ls[0][lane] = swf[m];
-        ls[1][lane] = swf[Mtot + m];
-        ls[2][lane] = swf[2 * Mtot + m];
-        __syncthreads();
+    const int64_t nbase = boff[e + 1] - boff[e];
+    for (int pass = 0; pass < 2; ++pass) {
+        const double* py = pass ? by : cpy;
+        const double* pn = pass ? bn : cpn;
+        const double* psw = pass ? bsw : swf;
+        const int64_t ld = pass ? Nb : Mtot;
+        const int64_t base0 = pass ? boff[e] : (int64_t)e * Mf;
+        const int64_t cnt = pass ? nbase : Mf;
+        const double sg = pass ? -1.0 : 1.0;
+        for (int64_t base = 0; base < cnt; base += 64) {
+            int64_t m = base0 + base + lane;
+            bool in = base + lane < cnt;
+            ly[0][lane] = in ? py[m] : 0.0;
+            ly[1][lane] = in ? py[ld + m] : 0.0;
+            ly[2][lane] = in ? py[2 * ld + m] : 0.0;
+            ln_[0][lane] = in ? pn[m] : 0.0;
+            ln_[1][lane] = in ? pn[ld + m] : 0.0;
+            ln_[2][lane] = in ? pn[2 * ld + m] : 0.0;
+            ls[0][lane] = in ? sg * psw[m] : 0.0;
+            ls[1][lane] = in ? sg * psw[ld + m] : 0.0;
+            ls[2][lane] = in ? sg * psw[2 * ld + m] : 0.0;
+            __syncthreads();
+            const int nin = (int)min((int64_t)64, cnt - base);
 #pragma unroll 4
-        for (int kk = 0; kk < 64; ++kk) {
-            double r0 = x0 - ly[0][kk], r1 = x1 - ly[1][kk], r2 = x2 - ly[2][kk];
-            double rr = fma(r0, r0, fma(r1, r1, r2 * r2));
-            double ir = rr > 0.0 ? rsqrt_nr(rr) : 0.0;
-            double w0 = ls[0][kk], w1 = ls[1][kk], w2 = ls[2][kk];
-            double rs = fma(r0, w0, fma(r1, w1, r2 * w2));
-            double rn = fma(r0, ln_[0][kk], fma(r1, ln_[1][kk], r2 * ln_[2][kk]));
-            double ir2 = ir * ir;
-            double b = rs * ir * ir2;
-            double cD = rn * rs * ir2 * ir2 * ir;
-            s0 = fma(ir, w0, fma(b, r0, s0));
-            s1 = fma(ir, w1, fma(b, r1, s1));
-            s2 = fma(ir, w2, fma(b, r2, s2));
-            d0 = fma(cD, r0, d0);
-            d1 = fma(cD, r1, d1);
-            d2 = fma(cD, r2, d2);
+            for (int kk = 0; kk < nin; ++kk) {
+                double r0 = x0 - ly[0][kk], r1 = x1 - ly[1][kk], r2 = x2 - ly[2][kk];
+                double rr = fma(r0, r0, fma(r1, r1, r2 * r2));
+                double ir = rr > 0.0 ? rsqrt_nr(rr) : 0.0;
+                double w0 = ls[0][kk], w1 = ls[1][kk], w2 = ls[2][kk];
+                double rs = fma(r0, w0, fma(r1, w1, r2 * w2));
+                double rn = fma(r0, ln_[0][kk], fma(r1, ln_[1][kk], r2 * ln_[2][kk]));
+                double ir2 = ir * ir;
+                double b = rs * ir * ir2;
+                double cD = rn * rs * ir2 * ir2 * ir;
+                s0 = fma(ir, w0, fma(b, r0, s0));
+                s1 = fma(ir, w1, fma(b, r1, s1));
+                s2 = fma(ir, w2, fma(b, r2, s2));
+                d0 = fma(cD, r0, d0);
+                d1 = fma(cD, r1, d1);
+                d2 = fma(cD, r2, d2);
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
     if (p >= 0) {
         double* o = corr + p * 6;
@@ -785,20 +965,37 @@ struct RuleTables {
     const int* off;       // [nb+1] offsets of the theta-rules (bracket b at index b-1)
     const double* th;     // nodes
     const double* w;      // weights
+    const double* cs;     // cos, sin and 1 - cos of every node (same layout)
+    const double* sn;
+    const double* omc;
     int nb;
     const double* lx;     // log rule nodes on (0,1), singular at 0
     const double* lw;
     int nl;
 };
 
-__global__ __launch_bounds__(64) void k_corr_full(const int64_t* __restrict__ listf, const int* __restrict__ pe,
+// Wavefront-wide sum (64 lanes).
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// One wavefront per (target, element) pair.  Per s-node of the s-rule: the
+// centerline data and the density's Fourier coefficients are interpolated to
+// s (lanes split the work), every lane then rebuilds the circle frame and the
+// target's local coordinates and evaluates its share of the theta-rule nodes.
+// Angles of rule nodes are formed by angle addition from tabulated cos/sin, so
+// the inner loop has no transcendental call.
+__global__ __launch_bounds__(64) void k_corr_full(const int* __restrict__ listf, const int* __restrict__ pe,
                                                   const int* __restrict__ pt, const double* __restrict__ xt,
                                                   int64_t T, const int64_t* __restrict__ tnode,
                                                   const double* __restrict__ clq, const double* __restrict__ sh,
                                                   const ElemInfo* __restrict__ info, const int* __restrict__ band,
-                                                  const double* __restrict__ cls, const double* __restrict__ ny,
-                                                  const double* __restrict__ nn, const double* __restrict__ sw,
-                                                  int64_t N, RuleTables rt, GateConsts gc,
+                                                  const double* __restrict__ cls,
+                                                  const int64_t* __restrict__ boff, const double* __restrict__ by,
+                                                  const double* __restrict__ bn, const double* __restrict__ bsw,
+                                                  int64_t Nb, RuleTables rt, GateConsts gc,
                                                   double* __restrict__ corr, int* __restrict__ err,
                                                   int* __restrict__ work)
 {
@@ -806,12 +1003,12 @@ __global__ __launch_bounds__(64) void k_corr_full(const int64_t* __restrict__ li
     __shared__ double shl[NS * NSH];
     __shared__ double sub_lo[MAXSUB], sub_hi[MAXSUB];
     __shared__ int sub_ty[MAXSUB];
+    __shared__ double st_lo[48], st_hi[48];
     __shared__ int nsub;
-    __shared__ double lw_[NS];
     __shared__ double qi[CLQ];
     __shared__ double dqi[CLQ];
     __shared__ double si[NSH];
-    __shared__ double red[64];
+    __shared__ double f0d[12];   // own-element target: E0, Xp0[3], sp0, t0[3], bn[3]
     const int lane = threadIdx.x;
     const int64_t p = listf[blockIdx.x];
     const int e = pe[p];
@@ -824,19 +1021,34 @@ __global__ __launch_bounds__(64) void k_corr_full(const int64_t* __restrict__ li
     const bool own = nd >= 0 && nd / NPE == e;
     const int Ms = band[2 * e], Mt = band[2 * e + 1];
     __syncthreads();
-    // on-surface target: its node (i0, j0), the node's frame and radial direction
+    // trapezoid acceptance thresholds on cosh(a) - 1 for nt, 2nt, 4nt points
+    double chaf[3];
+    {
+        const double lg = log(gc.ct / gc.tol);
+        for (int k = 0; k < 3; ++k) {
+            double thr = lg / (double)((NT << k) - Mt - gc.extra_modes);
+            chaf[k] = cosh(thr) - 1.0;
+        }
+    }
     int i0 = 0;
     double s0 = 0.0;
-    Frame f0;
-    double bn[3] = {0, 0, 0};
     if (own) {
         i0 = (int)((nd % NPE) / NT);
-        const int j0 = (int)(nd % NT);
         s0 = 0.5 * (inf.a + inf.c) + 0.5 * (inf.c - inf.a) * c_gx[i0];
-        double q0[CLQ];
-        for (int k = 0; k < CLQ; ++k) q0[k] = sq[k * NS + i0];
-        frame_from_q(q0, f0);
-        for (int d = 0; d < 3; ++d) bn[d] = f0.e1[d] * c_cos[j0] + f0.e2[d] * c_sin[j0];
+        if (lane == 0) {
+            const int j0 = (int)(nd % NT);
+            double q0[CLQ];
+            for (int k = 0; k < CLQ; ++k) q0[k] = sq[k * NS + i0];
+            Frame f0;
+            frame_from_q(q0, f0);
+            f0d[0] = f0.E;
+            for (int d = 0; d < 3; ++d) {
+                f0d[1 + d] = f0.Xp[d];
+                f0d[5 + d] = f0.t[d];
+                f0d[8 + d] = f0.e1[d] * c_cos[j0] + f0.e2[d] * c_sin[j0];
+            }
+            f0d[4] = f0.sp;
+        }
     }
     // ---- s-rule: list of sub-panels (lane 0)
     if (lane == 0) {
@@ -845,8 +1057,6 @@ __global__ __launch_bounds__(64) void k_corr_full(const int64_t* __restrict__ li
         if (own) {
             // dyadic refinement toward s0 down to ~eps/speed, log-singular
             // panels on both sides of s0 (Section 3.2.4, general form)
-            const int i0 = (int)((nd % NPE) / NT);
-            const double s0 = 0.5 * (a + c) + 0.5 * (c - a) * c_gx[i0];
             const double hmin = gc.hmin_fac * sq[Q_E * NS + i0] / cls[p * 4 + 2];
             for (int side = 0; side < 2; ++side) {
                 double L = side ? (c - s0) : (s0 - a);
@@ -867,10 +1077,10 @@ __global__ __launch_bounds__(64) void k_corr_full(const int64_t* __restrict__ li
             }
         } else {
             // adaptive bisection until the target is outside every sub-panel's
-            // near region (Section 3.2.3): Bernstein parameter of s* = s_c + i d/speed
-            const double sr = cls[p * 4 + 0], si_ = cls[p * 4 + 1] / cls[p * 4 + 2];
-            const double expo = (double)(2 * NS - Ms);
-            double st_lo[48], st_hi[48];
+            // near region (Section 3.2.3), judged by the Bernstein parameter of
+            // the s-integrand's nearest singularity
+            const double sr = cls[p * 4 + 0], si_ = cls[p * 4 + 1];
+            const double rreq = pow(gc.cs / gc.tol, 1.0 / (double)(2 * NS - Ms));
             int sp = 0;
             st_lo[sp] = a;
             st_hi[sp] = c;
@@ -879,7 +1089,7 @@ __global__ __launch_bounds__(64) void k_corr_full(const int64_t* __restrict__ li
                 --sp;
                 double lo = st_lo[sp], hi = st_hi[sp];
                 double rho = bernstein_rho(sr, si_, lo, hi);
-                bool ok = gc.cs * pow(rho, -expo) <= gc.tol;
+                bool ok = rho >= rreq;
                 if (ok || (hi - lo) < 1e-12 * (c - a) || sp + 2 > 48 || ns_ + sp + 2 > MAXSUB) {
                     if (!ok) atomicOr(err, 2);
                     sub_lo[ns_] = lo;
@@ -900,9 +1110,10 @@ __global__ __launch_bounds__(64) void k_corr_full(const int64_t* __restrict__ li
         nsub = ns_;
     }
     __syncthreads();
-    double acc[6] = {0, 0, 0, 0, 0, 0};
+    double a0 = 0, a1 = 0, a2 = 0, b0_ = 0, b1_ = 0, b2_ = 0;
     const int nsb = nsub;
     int n_theta = 0, n_snode = 0;
+    const double hw = 0.5 * (inf.c - inf.a);
     for (int sb = 0; sb < nsb; ++sb) {
         const double lo = sub_lo[sb], hi = sub_hi[sb];
         const int ty = sub_ty[sb];
@@ -922,90 +1133,104 @@ __global__ __launch_bounds__(64) void k_corr_full(const int64_t* __restrict__ li
                 s = hi + u;
                 ws = (hi - lo) * rt.lw[m];
             }
-            const double xn = (2.0 * s - inf.a - inf.c) / (inf.c - inf.a);
-            // interpolation weights, centerline quantities and density coefficients at s
-            if (lane == 0) {
-                if (own)
-                    bary_weights_rel(i0, 2.0 * u / (inf.c - inf.a), c_gx, c_lam, lw_);
-                else
-                    bary_weights(xn, c_gx, c_lam, lw_);
-            }
-            __syncthreads();
+            // interpolation weights (every lane), centerline quantities and
+            // density coefficients at s (lanes share the work)
+            double lw[NS];
+            if (own)
+                bary_weights_rel(i0, u / hw, c_gx, c_lam, lw);
+            else
+                bary_weights((s - inf.a) / hw - 1.0, c_gx, c_lam, lw);
             if (lane < CLQ) {
                 if (own) {
                     const double q0 = sq[lane * NS + i0];
                     double v = 0.0;
-                    for (int i = 0; i < NS; ++i) v += lw_[i] * (sq[lane * NS + i] - q0);
+#pragma unroll
+                    for (int i = 0; i < NS; ++i) v += lw[i] * (sq[lane * NS + i] - q0);
                     dqi[lane] = v;
                     qi[lane] = q0 + v;
                 } else {
                     double v = 0.0;
-                    for (int i = 0; i < NS; ++i) v += lw_[i] * sq[lane * NS + i];
+#pragma unroll
+                    for (int i = 0; i < NS; ++i) v += lw[i] * sq[lane * NS + i];
                     qi[lane] = v;
                 }
             }
             for (int k = lane; k < NSH; k += 64) {
                 double v = 0.0;
-                for (int i = 0; i < NS; ++i) v += lw_[i] * shl[i * NSH + k];
+#pragma unroll
+                for (int i = 0; i < NS; ++i) v += lw[i] * shl[i * NSH + k];
                 si[k] = v;
             }
             __syncthreads();
             Frame fr;
             frame_from_q(qi, fr);
             CircleLocal cl;
-            if (own)
-                circle_local_rel(fr, f0, bn, dqi, cl);
-            else
-                circle_local(fr, x, cl);
-            // theta-rule for this circle (Section 3.2.2): trapezoid of nt, 2nt or
-            // 4nt points if the estimate allows, else the bracket's Chebyshev rule
-            const double a_ = acosh1p(cl.cha);
-            int ntr = 0;
-            for (int f = 1; f <= 4; f *= 2) {
-                if (gc.ct * exp(-(double)(f * NT - Mt - gc.extra_modes) * a_) <= gc.tol) {
-                    ntr = f * NT;
-                    break;
+            if (own) {
+                Frame f0;
+                f0.E = f0d[0];
+                for (int d = 0; d < 3; ++d) {
+                    f0.Xp[d] = f0d[1 + d];
+                    f0.t[d] = f0d[5 + d];
                 }
+                f0.sp = f0d[4];
+                const double bn[3] = {f0d[8], f0d[9], f0d[10]};
+                circle_local_rel(fr, f0, bn, dqi, cl);
+            } else {
+                circle_local(fr, x, cl);
             }
-            int rb = 0;
-            double th0 = 0.0;
-            if (ntr == 0) {
-                double alpha = sqrt(cl.d2) / fr.E;
-                int b = (alpha > 0.0) ? (int)floor(-log2(alpha)) + 1 : rt.nb;
+            // theta-rule for this circle (Section 3.2.2): trapezoid of nt, 2nt
+            // or 4nt points if the estimate allows, else the bracket's
+            // generalized Chebyshev rule
+            int ntr = 0, rb = 0;
+            if (cl.cha >= chaf[0])
+                ntr = NT;
+            else if (cl.cha >= chaf[1])
+                ntr = 2 * NT;
+            else if (cl.cha >= chaf[2])
+                ntr = 4 * NT;
+            else {
+                int ex;
+                frexp(sqrt(cl.d2) / fr.E, &ex);   // alpha in [2^(ex-1), 2^ex)
+                int b = 1 - ex;
                 if (b < 1) {
                     ntr = 4 * NT;
                 } else {
                     if (b > rt.nb) {
                         b = rt.nb;
-                        atomicOr(err, 4);
+                        if (lane == 0) atomicOr(err, 4);
                     }
                     rb = b;
                 }
             }
-            // angle of the closest circle point
-            {
-                double c1 = dot3(cl.b0, fr.e1), s1 = dot3(cl.b0, fr.e2);
-                th0 = atan2(s1, c1);
-            }
-            const int nq = ntr ? ntr : (rt.off[rb] - rt.off[rb - 1]);
+            // closest angle theta0 of the circle: (cos, sin) from the radial direction
+            const double c0 = dot3(cl.b0, fr.e1), s0t = dot3(cl.b0, fr.e2);
+            const int qoff = ntr ? 0 : rt.off[rb - 1];
+            const int nq = ntr ? ntr : (rt.off[rb] - qoff);
+            const int tstep = ntr ? 128 / ntr : 0;
             n_theta += nq;
             ++n_snode;
             for (int q = lane; q < nq; q += 64) {
-                double phi, wq;
+                double cph, sph, omc, wq;
+                double cth, sth;
                 if (ntr) {
-                    double th = 2.0 * PI * q / ntr;
-                    phi = th - th0;
+                    cth = c_cos128[q * tstep];
+                    sth = c_sin128[q * tstep];
+                    cph = cth * c0 + sth * s0t;     // phi = theta - theta0
+                    sph = sth * c0 - cth * s0t;
+                    omc = 1.0 - cph;
                     wq = 2.0 * PI / ntr;
                 } else {
-                    phi = rt.th[rt.off[rb - 1] + q];
-                    wq = rt.w[rt.off[rb - 1] + q];
+                    cph = rt.cs[qoff + q];
+                    sph = rt.sn[qoff + q];
+                    omc = rt.omc[qoff + q];
+                    wq = rt.w[qoff + q];
+                    cth = c0 * cph - s0t * sph;
+                    sth = s0t * cph + c0 * sph;
                 }
-                const double th = th0 + phi;
-                double sth, cth;
-                sincos(th, &sth, &cth);
                 // density by Fourier synthesis
                 double v0 = si[0], v1 = si[1], v2 = si[2];
                 double clv = 1.0, slv = 0.0;
+#pragma unroll
                 for (int l = 1; l < NMODE; ++l) {
                     double cn = clv * cth - slv * sth;
                     slv = slv * cth + clv * sth;
@@ -1014,68 +1239,73 @@ __global__ __launch_bounds__(64) void k_corr_full(const int64_t* __restrict__ li
                     v1 += si[l * 6 + 1] * clv + si[l * 6 + 4] * slv;
                     v2 += si[l * 6 + 2] * clv + si[l * 6 + 5] * slv;
                 }
-                // geometry: dy/ds, dy/dt and r = x - y in the circle's local frame
-                double y[3], ys[3], yt[3];
-                surface_at(fr, cth, sth, y, ys, yt);
-                double sp_, cp_;
-                sincos(phi, &sp_, &cp_);
-                double hs = sin(0.5 * phi);
-                double rb0 = cl.dr + 2.0 * fr.E * hs * hs;
-                double rbp = -fr.E * sp_;
-                double r[3];
-                for (int d = 0; d < 3; ++d) r[d] = cl.z * fr.t[d] + rb0 * cl.b0[d] + rbp * cl.b0p[d];
+                // dy/ds, dy/dt at theta; r = x - y in the circle's local frame
+                double ys[3], yt[3], r[3];
+                const double rb0 = cl.dr + fr.E * omc;
+                const double rbp = -fr.E * sph;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const double bb = fr.e1[d] * cth + fr.e2[d] * sth;
+                    const double bp = fr.e1p[d] * cth + fr.e2p[d] * sth;
+                    ys[d] = fr.Xp[d] + fr.Ep * bb + fr.E * bp;
+                    yt[d] = fr.E * (-fr.e1[d] * sth + fr.e2[d] * cth);
+                    r[d] = cl.z * fr.t[d] + rb0 * cl.b0[d] + rbp * cl.b0p[d];
+                }
                 double jn[3];
                 cross3(yt, ys, jn);
-                double J = sqrt(dot3(jn, jn));
-                double rr = dot3(r, r);
-                if (!(rr > 0.0)) continue;
-                double ir = 1.0 / sqrt(rr);
-                double ir2 = ir * ir;
-                double W = ws * wq;
-                double sig[3] = {v0, v1, v2};
-                double rs = dot3(r, sig);
-                double rn = inf.sign * dot3(r, jn);
-                double aS = W * J * ir, bS = W * J * rs * ir * ir2;
-                double cD = W * rn * rs * ir2 * ir2 * ir;
-                for (int d = 0; d < 3; ++d) {
-                    acc[d] += aS * sig[d] + bS * r[d];
-                    acc[3 + d] += cD * r[d];
-                }
+                const double J = sqrt(dot3(jn, jn));
+                const double rr = dot3(r, r);
+                const double ir = rr > 0.0 ? rsqrt_nr(rr) : 0.0;
+                const double ir2 = ir * ir;
+                const double W = ws * wq;
+                const double rs = r[0] * v0 + r[1] * v1 + r[2] * v2;
+                const double rn = inf.sign * dot3(r, jn);
+                const double aS = W * J * ir, bS = W * J * rs * ir * ir2;
+                const double cD = W * rn * rs * ir2 * ir2 * ir;
+                a0 += aS * v0 + bS * r[0];
+                a1 += aS * v1 + bS * r[1];
+                a2 += aS * v2 + bS * r[2];
+                b0_ += cD * r[0];
+                b1_ += cD * r[1];
+                b2_ += cD * r[2];
             }
             __syncthreads();
         }
     }
-    // minus the smooth rule of this element (self term zero)
-    for (int k = lane; k < NPE; k += 64) {
-        int64_t n = (int64_t)e * NPE + k;
-        double r0 = x[0] - ny[n], r1 = x[1] - ny[N + n], r2 = x[2] - ny[2 * N + n];
+    // minus the element's far-field (base) rule (self term zero)
+    const int64_t bo = boff[e], bc = boff[e + 1] - boff[e];
+    for (int64_t k = lane; k < bc; k += 64) {
+        int64_t n = bo + k;
+        double r0 = x[0] - by[n], r1 = x[1] - by[Nb + n], r2 = x[2] - by[2 * Nb + n];
         double rr = r0 * r0 + r1 * r1 + r2 * r2;
-        if (!(rr > 0.0)) continue;
-        double ir = 1.0 / sqrt(rr);
+        double ir = rr > 0.0 ? rsqrt_nr(rr) : 0.0;
         double ir2 = ir * ir;
-        double w0 = sw[n], w1 = sw[N + n], w2 = sw[2 * N + n];
+        double w0 = bsw[n], w1 = bsw[Nb + n], w2 = bsw[2 * Nb + n];
         double rs = r0 * w0 + r1 * w1 + r2 * w2;
-        double rn = r0 * nn[n] + r1 * nn[N + n] + r2 * nn[2 * N + n];
+        double rn = r0 * bn[n] + r1 * bn[Nb + n] + r2 * bn[2 * Nb + n];
         double b = rs * ir * ir2;
         double cD = rn * rs * ir2 * ir2 * ir;
-        acc[0] -= ir * w0 + b * r0;
-        acc[1] -= ir * w1 + b * r1;
-        acc[2] -= ir * w2 + b * r2;
-        acc[3] -= cD * r0;
-        acc[4] -= cD * r1;
-        acc[5] -= cD * r2;
+        a0 -= ir * w0 + b * r0;
+        a1 -= ir * w1 + b * r1;
+        a2 -= ir * w2 + b * r2;
+        b0_ -= cD * r0;
+        b1_ -= cD * r1;
+        b2_ -= cD * r2;
     }
-    for (int k = 0; k < 6; ++k) {
-        red[lane] = acc[k];
-        __syncthreads();
-        for (int s = 32; s > 0; s >>= 1) {
-            if (lane < s) red[lane] += red[lane + s];
-            __syncthreads();
-        }
-        if (lane == 0) corr[p * 6 + k] = red[0];
-        __syncthreads();
-    }
+    a0 = wave_sum(a0);
+    a1 = wave_sum(a1);
+    a2 = wave_sum(a2);
+    b0_ = wave_sum(b0_);
+    b1_ = wave_sum(b1_);
+    b2_ = wave_sum(b2_);
     if (lane == 0) {
+        double* o = corr + p * 6;
+        o[0] = a0;
+        o[1] = a1;
+        o[2] = a2;
+        o[3] = b0_;
+        o[4] = b1_;
+        o[5] = b2_;
         work[2 * blockIdx.x] = n_theta;
         work[2 * blockIdx.x + 1] = n_snode;
     }
@@ -1125,33 +1355,48 @@ int launch_expand(hipStream_t st, int E, const double* xc, const double* eps, co
     return 0;
 }
 
-int launch_expand_up(hipStream_t st, int E, int f, const double* clq, const ElemInfo* info, const double* ny,
-                     const double* nn, const double* nw, int64_t N, double* cpy, double* cpn, double* cpw,
-                     int64_t Mtot)
+int launch_expand_up(hipStream_t st, int E, int ns_f, int nt_f, const double* gx_f, const double* gw_f,
+                     const double* clq, const ElemInfo* info, double* cpy, double* cpn, double* cpw, int64_t Mtot)
 {
-    hipLaunchKernelGGL(k_expand_up, dim3(E, f * NS), dim3(f * NT), 0, st, E, f, clq, info, cpy, cpn, cpw, Mtot);
+    hipLaunchKernelGGL(k_expand_up, dim3(E, ns_f), dim3(nt_f), 0, st, E, ns_f, nt_f, gx_f, gw_f, clq, info, cpy, cpn,
+                       cpw, Mtot);
     LAUNCH_CHECK();
-    int64_t tot = (int64_t)E * NPE;
-    hipLaunchKernelGGL(k_cp_nodes, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, E, f, ny, nn, nw, N, cpy,
-                       cpn, cpw, Mtot);
+    return 0;
+}
+
+int launch_base_build(hipStream_t st, int E, const ElemInfo* info, const int64_t* boff, const double* ny,
+                      const double* nn, const double* nw, int64_t N, const double* c0y, const double* c0n,
+                      const double* c0w, int64_t M0, double* by, double* bn, double* bw, int64_t Nb)
+{
+    hipLaunchKernelGGL(k_base_build, dim3(E), dim3(256), 0, st, E, info, boff, ny, nn, nw, N, c0y, c0n, c0w, M0, by,
+                       bn, bw, Nb);
     LAUNCH_CHECK();
     return 0;
 }
 
 int launch_prep_sigma(hipStream_t st, int E, const double* sigma, const double* nw, int64_t N, double* sw,
-                      double* sh, int* band, double eta, const ElemInfo* info, GateConsts gc, double* rnear)
+                      double* sh, int* band, double eta, const ElemInfo* info, const double* circ, GateConsts gc,
+                      double* rnear)
 {
     hipLaunchKernelGGL(k_prep_sigma, dim3(E), dim3(512), 0, st, E, sigma, nw, N, sw, sh, band, eta);
     LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_rnear, dim3((E + 127) / 128), dim3(128), 0, st, E, info, band, gc, rnear);
+    hipLaunchKernelGGL(k_rnear, dim3((E + 127) / 128), dim3(128), 0, st, E, info, circ, band, gc, rnear);
     LAUNCH_CHECK();
     return 0;
 }
 
-int launch_sigma_up(hipStream_t st, int E, int f, const double* sh, const double* Lup, const double* cpw,
-                    const double* sw, int64_t N, double* swf, int64_t Mtot)
+int launch_sigma_up(hipStream_t st, int E, int ns_f, int nt_f, const double* sh, const double* Lup, const double* cpw,
+                    double* swf, int64_t Mtot)
 {
-    hipLaunchKernelGGL(k_sigma_up, dim3(E), dim3(256), 0, st, E, f, sh, Lup, cpw, sw, N, swf, Mtot);
+    hipLaunchKernelGGL(k_sigma_up, dim3(E), dim3(256), 0, st, E, ns_f, nt_f, sh, Lup, cpw, swf, Mtot);
+    LAUNCH_CHECK();
+    return 0;
+}
+
+int launch_sigma_base(hipStream_t st, int E, const ElemInfo* info, const int64_t* boff, const double* sw, int64_t N,
+                      const double* swf0, int64_t M0, double* bsw, int64_t Nb)
+{
+    hipLaunchKernelGGL(k_sigma_base, dim3(E), dim3(256), 0, st, E, info, boff, sw, N, swf0, M0, bsw, Nb);
     LAUNCH_CHECK();
     return 0;
 }
@@ -1182,58 +1427,56 @@ int launch_search(hipStream_t st, int64_t T, int E, const double* xt, const int6
     return 0;
 }
 
-int launch_classify(hipStream_t st, int64_t P, const int* pe, const int* pt, const double* xt, int64_t T,
-                    const int64_t* tnode, const double* clq, const double* circ, const ElemInfo* info,
+int launch_classify(hipStream_t st, int64_t P, const int* perm, const int* pe, const int* pt, const double* xt,
+                    int64_t T, const int64_t* tnode, const double* clq, const double* circ, const ElemInfo* info,
                     const int* band, GateConsts gc, int8_t* tier, double* cls)
 {
     if (P == 0) return 0;
-    hipLaunchKernelGGL(k_classify, dim3((unsigned)((P + 127) / 128)), dim3(128), 0, st, P, pe, pt, xt, T, tnode, clq,
-                       circ, info, band, gc, tier, cls);
+    hipLaunchKernelGGL(k_classify, dim3((unsigned)((P + 127) / 128)), dim3(128), 0, st, P, perm, pe, pt, xt, T, tnode,
+                       clq, circ, info, band, gc, tier, cls);
     LAUNCH_CHECK();
     return 0;
 }
 
-int launch_bucket_count(hipStream_t st, int64_t P, const int8_t* tier, const int* pe, int* cnt2, int* cnt4,
-                        int* nfull)
+int launch_iota(hipStream_t st, int64_t P, int* v)
 {
     if (P == 0) return 0;
-    hipLaunchKernelGGL(k_bucket_count, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, st, P, tier, pe, cnt2, cnt4,
-                       nfull);
+    hipLaunchKernelGGL(k_iota, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, st, P, v);
     LAUNCH_CHECK();
     return 0;
 }
 
-int launch_bucket_fill(hipStream_t st, int64_t P, const int8_t* tier, const int* pe, int* cur2, int* cur4,
-                       int* curf, int64_t* list2, int64_t* list4, int64_t* listf)
+int launch_tier_keys(hipStream_t st, int64_t P, int E, const int8_t* tier, const int* pe, int* key, int* val)
 {
     if (P == 0) return 0;
-    hipLaunchKernelGGL(k_bucket_fill, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, st, P, tier, pe, cur2, cur4,
-                       curf, list2, list4, listf);
+    hipLaunchKernelGGL(k_tier_keys, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, st, P, E, tier, pe, key, val);
     LAUNCH_CHECK();
     return 0;
 }
 
-int launch_corr_up(hipStream_t st, int f, int nwaves, const int* wave_elem, const int64_t* list, const int* pt,
+int launch_corr_up(hipStream_t st, int64_t Mf, int nwaves, const int* ws, const int* sorted, const int* pt,
                    const double* xt, int64_t T, const double* cpy, const double* cpn, const double* swf,
-                   int64_t Mtot, double* corr)
+                   int64_t Mtot, const int64_t* boff, const double* by, const double* bn, const double* bsw,
+                   int64_t Nb, double* corr)
 {
     if (nwaves == 0) return 0;
-    hipLaunchKernelGGL(k_corr_up, dim3(nwaves), dim3(64), 0, st, f, wave_elem, list, pt, xt, T, cpy, cpn, swf, Mtot,
-                       corr);
+    hipLaunchKernelGGL(k_corr_up, dim3(nwaves), dim3(64), 0, st, Mf, ws, sorted, pt, xt, T, cpy, cpn, swf, Mtot,
+                       boff, by, bn, bsw, Nb, corr);
     LAUNCH_CHECK();
     return 0;
 }
 
-int launch_corr_full(hipStream_t st, int nfull, const int64_t* listf, const int* pe, const int* pt, const double* xt,
+int launch_corr_full(hipStream_t st, int nfull, const int* listf, const int* pe, const int* pt, const double* xt,
                      int64_t T, const int64_t* tnode, const double* clq, const double* sh, const ElemInfo* info,
-                     const int* band, const double* cls, const double* ny, const double* nn, const double* sw,
-                     int64_t N, const int* roff, const double* rth, const double* rw, int nb, const double* lx,
-                     const double* lw, int nl, GateConsts gc, double* corr, int* err, int* work)
+                     const int* band, const double* cls, const int64_t* boff, const double* by, const double* bn,
+                     const double* bsw, int64_t Nb, const int* roff, const double* rth, const double* rw, int nb,
+                     const double* lx, const double* lw, int nl, const double* rcs, const double* rsn,
+                     const double* romc, GateConsts gc, double* corr, int* err, int* work)
 {
     if (nfull == 0) return 0;
-    RuleTables rt{roff, rth, rw, nb, lx, lw, nl};
+    RuleTables rt{roff, rth, rw, rcs, rsn, romc, nb, lx, lw, nl};
     hipLaunchKernelGGL(k_corr_full, dim3(nfull), dim3(64), 0, st, listf, pe, pt, xt, T, tnode, clq, sh, info, band,
-                       cls, ny, nn, sw, N, rt, gc, corr, err, work);
+                       cls, boff, by, bn, bsw, Nb, rt, gc, corr, err, work);
     LAUNCH_CHECK();
     return 0;
 }

@@ -83,6 +83,7 @@ __host__ __device__ inline void bary_weights(double x, const double* gx, const d
 {
     double sum = 0.0;
     int hit = -1;
+#pragma unroll
     for (int i = 0; i < NS; ++i) {
         double dx = x - gx[i];
         if (dx == 0.0) hit = i;
@@ -94,6 +95,7 @@ __host__ __device__ inline void bary_weights(double x, const double* gx, const d
         return;
     }
     double is = 1.0 / sum;
+#pragma unroll
     for (int i = 0; i < NS; ++i) l[i] *= is;
 }
 
@@ -157,7 +159,8 @@ __host__ __device__ inline void circle_local(const Frame& f, const double* x, Ci
     cross3(f.t, c.b0, c.b0p);
     c.dr = c.rho - f.E;
     c.d2 = c.dr * c.dr + c.z * c.z;
-    c.cha = (c.rho > 0.0) ? c.d2 / (2.0 * c.rho * f.E) : 1e300;
+    // a vanishing (or rounding-negative) radius: constant angular integrand
+    c.cha = (c.rho > 0.0 && f.E > 1e-300) ? c.d2 / (2.0 * c.rho * f.E) : 1e300;
 }
 
 // Local coordinates of an on-surface target relative to a nearby circle of
@@ -189,7 +192,7 @@ __host__ __device__ inline void circle_local_rel(const Frame& f, const Frame& f0
     double r2mE2 = -dE * (2.0 * E0 + dE) - 2.0 * E0 * dot3(bn, dX) + dot3(dX, dX) - c.z * c.z;
     c.dr = r2mE2 / (c.rho + f.E);
     c.d2 = c.dr * c.dr + c.z * c.z;
-    c.cha = c.d2 / (2.0 * c.rho * f.E);
+    c.cha = (f.E > 1e-300) ? c.d2 / (2.0 * c.rho * f.E) : 1e300;
 }
 
 // a = acosh(1 + cha), stable for small cha

@@ -64,7 +64,9 @@ def test_smooth_sum_matches_oracle(ev):
     x = rng.uniform(-2, 6, (len(tn), 3))
     us, ud = ev.smooth_sum(sc.sigma, x, tn)
     uso, udo = oracle.smooth_sum(sc, None, x, tn)
-    assert _rel(us, uso) < 1e-12 and _rel(ud, udo) < 1e-12
+    # on-surface targets sum 1/r over neighbours ~1e-3 away near a sphere's
+    # poles, where the two evaluators' node positions differ by ~1e-15
+    assert _rel(us, uso) < 1e-11 and _rel(ud, udo) < 1e-11
 
 
 def test_sphere_config1_off_surface(ev):
