@@ -22,8 +22,11 @@ sys.path.insert(0, ROOT)
 METRIC = "layer-potential target evals/sec at rel.err 1e-10 (FP64) and 1e-6 (mixed+MLP)"
 FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 vector peak
 FAR_FLOPS_PER_PAIR = 44          # smooth-sum flops per source-target pair (rsqrt counted once)
-THETA_FLOPS = 280                # special quadrature flops per theta-rule node
-SNODE_FLOPS = 2 * 16 * (102 + 17)  # interpolation to one s-node (density coefficients + centerline data)
+# special quadrature flops: per theta-rule node 82 + 18 per density Fourier mode
+# (synthesis), per s-node 800 (interpolation weights, centerline data, frame,
+# local coordinates) + 192 per mode (6 coefficients x 16-point interpolation)
+THETA_FLOPS, THETA_MODE_FLOPS = 82, 18
+SNODE_FLOPS, SNODE_MODE_FLOPS = 800, 192
 
 
 def log(msg):
@@ -98,7 +101,8 @@ def main():
     if dom == "far":
         flops = FAR_FLOPS_PER_PAIR * float(T) * nsrc
     else:
-        flops = THETA_FLOPS * float(counts.get("theta_nodes", 0)) + SNODE_FLOPS * float(counts.get("s_nodes", 0))
+        flops = (THETA_FLOPS * float(counts.get("theta_nodes", 0)) + THETA_MODE_FLOPS * float(counts.get("theta_modes", 0))
+                 + SNODE_FLOPS * float(counts.get("s_nodes", 0)) + SNODE_MODE_FLOPS * float(counts.get("s_modes", 0)))
     achieved = flops / (phases[dom] * 1e-3) / 1e12
     roof = dict(kernel="k_far" if dom == "far" else "k_corr_full", bound="alu", achieved=achieved,
                 peak=FP64_PEAK_TFLOPS, unit="TFLOP/s", frac=achieved / FP64_PEAK_TFLOPS, traffic=None)
@@ -115,7 +119,7 @@ def main():
                              frac=far_ach / FP64_PEAK_TFLOPS),
         "phases_ms": phases,
         "pairs": {k: counts.get(k) for k in ("candidates", "pairs_up1", "pairs_up2", "pairs_up3", "pairs_full",
-                                              "theta_nodes", "s_nodes", "sources_base")},
+                                              "theta_nodes", "theta_modes", "s_nodes", "s_modes", "sources_base")},
     }
     if not a.no_cpu_baseline:
         log("bench: timing the CPU oracle on a sample")

@@ -729,6 +729,7 @@ int csbq_smooth_sum(csbq_ctx* ctx, const double* sigma, int64_t T, const double*
     const int64_t* tn;
     int rc = eval_front(ctx, sigma, T, x, tgt_node, mem, &sig, &tn);
     if (rc) return rc;
+    if (T == 0) return finish(ctx, 0, u_sl, u_dl, mem);
     int nchunk = 1;
     if ((rc = far_sum(ctx, T, true, &nchunk))) return rc;
     double *usl, *udl;
@@ -750,6 +751,7 @@ int csbq_eval(csbq_ctx* ctx, const double* sigma, int64_t T, const double* x, co
     HIPC(hipEventRecord(ctx->ph[0].a, st));
     int rc = eval_front(ctx, sigma, T, x, tgt_node, mem, &sig, &tn);
     if (rc) return rc;
+    if (T == 0) return finish(ctx, 0, u_sl, u_dl, mem);
     HIPC(hipEventRecord(ctx->ph[0].b, st));
     const int E = ctx->E;
     const int64_t N = ctx->N;
@@ -778,7 +780,11 @@ int csbq_eval(csbq_ctx* ctx, const double* sigma, int64_t T, const double* x, co
     HIPC(hipcub::DeviceScan::ExclusiveSum(ctx->cub_tmp.p, tmpb, ctx->cnt.p, ctx->off.p, (int)(T + 1), st));
     int64_t P = 0;
     HIPC(hipMemcpyAsync(&P, ctx->off.p + T, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    std::vector<int> hband((size_t)2 * E);
+    HIPC(hipMemcpyAsync(hband.data(), ctx->band.p, hband.size() * sizeof(int), hipMemcpyDeviceToHost, st));
     HIPC(hipStreamSynchronize(st));
+    int mt_max = 0;
+    for (int k = 0; k < E; ++k) mt_max = std::max(mt_max, hband[2 * k + 1]);
     ALLOC(ctx->pe, (size_t)P + 1);
     ALLOC(ctx->pt, (size_t)P + 1);
     ALLOC(ctx->tier, (size_t)P + 1);
@@ -886,11 +892,11 @@ int csbq_eval(csbq_ctx* ctx, const double* sigma, int64_t T, const double* x, co
     HIPC(hipEventRecord(ctx->ph[5].b, st));
     // special quadrature corrections
     HIPC(hipEventRecord(ctx->ph[6].a, st));
-    ALLOC(ctx->work, (size_t)2 * nfull + 2);
+    ALLOC(ctx->work, (size_t)4 * nfull + 4);
     LCHK(launch_corr_full(st, nfull, ctx->sorted.p + full_start, ctx->pe.p, ctx->pt.p, ctx->xt.p, T, tn, ctx->clq.p, ctx->sh.p,
                           ctx->info.p, ctx->band.p, ctx->cls.p, ctx->boff.p, ctx->by.p, ctx->bn.p, ctx->bsw.p, ctx->Nb, ctx->roff.p,
                           ctx->rth.p, ctx->rw.p, ctx->nb, ctx->lx.p, ctx->lw.p, ctx->nl, ctx->rcs.p, ctx->rsn.p,
-                          ctx->romc.p, ctx->gc, ctx->corr.p, ctx->err_d.p, ctx->work.p));
+                          ctx->romc.p, ctx->gc, ctx->corr.p, ctx->err_d.p, ctx->work.p, mt_max));
     HIPC(hipEventRecord(ctx->ph[6].b, st));
     // reduction
     HIPC(hipEventRecord(ctx->ph[7].a, st));
@@ -919,14 +925,18 @@ int csbq_stats(const csbq_ctx* ctx, char* buf, int64_t cap)
                   ctx->last_err_flags, (long long)ctx->Nb);
     s += tmp;
     if (ctx->ph_ok && ctx->last_nf > 0) {
-        std::vector<int> wk((size_t)2 * ctx->last_nf);
+        std::vector<int> wk((size_t)4 * ctx->last_nf);
         if (hipMemcpy(wk.data(), ctx->work.p, wk.size() * sizeof(int), hipMemcpyDeviceToHost) == hipSuccess) {
-            long long nq = 0, nsn = 0;
-            for (size_t i = 0; i < wk.size(); i += 2) {
+            long long nq = 0, nsn = 0, nqm = 0, nsm = 0;
+            for (size_t i = 0; i < wk.size(); i += 4) {
                 nq += wk[i];
                 nsn += wk[i + 1];
+                nqm += wk[i + 2];
+                nsm += wk[i + 3];
             }
-            std::snprintf(tmp, sizeof tmp, ", \"theta_nodes\": %lld, \"s_nodes\": %lld", nq, nsn);
+            std::snprintf(tmp, sizeof tmp,
+                          ", \"theta_nodes\": %lld, \"s_nodes\": %lld, \"theta_modes\": %lld, \"s_modes\": %lld",
+                          nq, nsn, nqm, nsm);
             s += tmp;
         }
     }

@@ -981,13 +981,23 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// One wavefront per (target, element) pair.  Per s-node of the s-rule: the
-// centerline data and the density's Fourier coefficients are interpolated to
-// s (lanes split the work), every lane then rebuilds the circle frame and the
-// target's local coordinates and evaluates its share of the theta-rule nodes.
-// Angles of rule nodes are formed by angle addition from tabulated cos/sin, so
-// the inner loop has no transcendental call.
-__global__ __launch_bounds__(64) void k_corr_full(const int* __restrict__ listf, const int* __restrict__ pe,
+// One wavefront per (target, element) pair, s-nodes taken in batches of SB.
+//  1. lanes 0..SB-1, one s-node each: interpolation weights, centerline
+//     quantities, circle frame, the target's coordinates relative to the
+//     circle and the choice of theta-rule -> one record per s-node in LDS;
+//  2. all lanes: the density's Fourier coefficients (modes up to the measured
+//     band) interpolated to the batch's s-nodes;
+//  3. all lanes: the batch's (s-node, theta-node) points as one flat list, 64
+//     at a time.  With the target's radial direction b0 and b0p = t x b0 as
+//     basis, r = z t + (dr + eps(1 - cos phi)) b0 - eps sin phi b0p, and the
+//     area element and r.n reduce to the scalars g = |x_c'| + eps (e1'.t cos +
+//     e2'.t sin) and eps' (|y_t x y_s| = eps sqrt(g^2 + eps'^2)), so a point
+//     costs one Fourier synthesis and a handful of flops.
+constexpr int SB = 16;
+enum { R_E = 0, R_EP, R_SP, R_A13, R_A23, R_Z, R_DR, R_T, R_B0 = R_T + 3, R_B0P = R_B0 + 3, R_W = R_B0P + 3, R_C0,
+       R_S0, R_WQ, NREC };
+
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_corr_full(const int* __restrict__ listf, const int* __restrict__ pe,
                                                   const int* __restrict__ pt, const double* __restrict__ xt,
                                                   int64_t T, const int64_t* __restrict__ tnode,
                                                   const double* __restrict__ clq, const double* __restrict__ sh,
@@ -997,17 +1007,19 @@ __global__ __launch_bounds__(64) void k_corr_full(const int* __restrict__ listf,
                                                   const double* __restrict__ bn, const double* __restrict__ bsw,
                                                   int64_t Nb, RuleTables rt, GateConsts gc,
                                                   double* __restrict__ corr, int* __restrict__ err,
-                                                  int* __restrict__ work)
+                                                  int* __restrict__ work, int cstride)
 {
+    // cf: [SB][cstride] density coefficients at the batch's s-nodes, cstride =
+    // 6 (largest band + 1) over all elements (dynamic LDS)
+    extern __shared__ __attribute__((aligned(16))) double cf[];
     __shared__ double sq[CLQ * NS];
-    __shared__ double shl[NS * NSH];
+    __shared__ __attribute__((aligned(16))) double rec[SB][NREC];
+    __shared__ double lwl[SB][NS];
+    __shared__ int rq_off[SB], rq_step[SB], npt[SB], pref[SB + 1];
     __shared__ double sub_lo[MAXSUB], sub_hi[MAXSUB];
-    __shared__ int sub_ty[MAXSUB];
+    __shared__ int sub_ty[MAXSUB], soff[MAXSUB + 1];
     __shared__ double st_lo[48], st_hi[48];
     __shared__ int nsub;
-    __shared__ double qi[CLQ];
-    __shared__ double dqi[CLQ];
-    __shared__ double si[NSH];
     __shared__ double f0d[12];   // own-element target: E0, Xp0[3], sp0, t0[3], bn[3]
     const int lane = threadIdx.x;
     const int64_t p = listf[blockIdx.x];
@@ -1016,20 +1028,12 @@ __global__ __launch_bounds__(64) void k_corr_full(const int* __restrict__ listf,
     const ElemInfo inf = info[e];
     const double x[3] = {xt[t], xt[T + t], xt[2 * T + t]};
     for (int o = lane; o < CLQ * NS; o += 64) sq[o] = clq[(int64_t)e * CLQ * NS + o];
-    for (int o = lane; o < NS * NSH; o += 64) shl[o] = sh[(int64_t)e * NS * NSH + o];
     const int64_t nd = tnode ? tnode[t] : -1;
     const bool own = nd >= 0 && nd / NPE == e;
     const int Ms = band[2 * e], Mt = band[2 * e + 1];
+    const int ncoef = 6 * (Mt + 1);
+    const double* __restrict__ she = sh + (int64_t)e * NS * NSH;
     __syncthreads();
-    // trapezoid acceptance thresholds on cosh(a) - 1 for nt, 2nt, 4nt points
-    double chaf[3];
-    {
-        const double lg = log(gc.ct / gc.tol);
-        for (int k = 0; k < 3; ++k) {
-            double thr = lg / (double)((NT << k) - Mt - gc.extra_modes);
-            chaf[k] = cosh(thr) - 1.0;
-        }
-    }
     int i0 = 0;
     double s0 = 0.0;
     if (own) {
@@ -1107,18 +1111,30 @@ __global__ __launch_bounds__(64) void k_corr_full(const int* __restrict__ listf,
                 }
             }
         }
+        soff[0] = 0;
+        for (int k = 0; k < ns_; ++k) soff[k + 1] = soff[k] + (sub_ty[k] == SUB_GL ? NS : rt.nl);
         nsub = ns_;
     }
     __syncthreads();
-    double a0 = 0, a1 = 0, a2 = 0, b0_ = 0, b1_ = 0, b2_ = 0;
     const int nsb = nsub;
-    int n_theta = 0, n_snode = 0;
+    const int S = soff[nsb];
     const double hw = 0.5 * (inf.c - inf.a);
-    for (int sb = 0; sb < nsb; ++sb) {
-        const double lo = sub_lo[sb], hi = sub_hi[sb];
-        const int ty = sub_ty[sb];
-        const int nnod = (ty == SUB_GL) ? NS : rt.nl;
-        for (int m = 0; m < nnod; ++m) {
+    const double sgn = (double)inf.sign;
+    double a0 = 0, a1 = 0, a2 = 0, b0_ = 0, b1_ = 0, b2_ = 0;
+    int n_theta = 0;
+    for (int base = 0; base < S; base += SB) {
+        const int nb = min(SB, S - base);
+        // ---- 1. one s-node per lane
+        if (lane < nb) {
+            const int g = base + lane;
+            int lo_i = 0, hi_i = nsb;   // soff[lo_i] <= g < soff[hi_i]
+            while (hi_i - lo_i > 1) {
+                int mid = (lo_i + hi_i) >> 1;
+                if (soff[mid] <= g) lo_i = mid; else hi_i = mid;
+            }
+            const int m = g - soff[lo_i];
+            const double lo = sub_lo[lo_i], hi = sub_hi[lo_i];
+            const int ty = sub_ty[lo_i];
             double s, ws, u;
             if (ty == SUB_GL) {
                 s = 0.5 * (lo + hi) + 0.5 * (hi - lo) * c_gx[m];
@@ -1133,37 +1149,32 @@ __global__ __launch_bounds__(64) void k_corr_full(const int* __restrict__ listf,
                 s = hi + u;
                 ws = (hi - lo) * rt.lw[m];
             }
-            // interpolation weights (every lane), centerline quantities and
-            // density coefficients at s (lanes share the work)
             double lw[NS];
             if (own)
                 bary_weights_rel(i0, u / hw, c_gx, c_lam, lw);
             else
                 bary_weights((s - inf.a) / hw - 1.0, c_gx, c_lam, lw);
-            if (lane < CLQ) {
+#pragma unroll
+            for (int i = 0; i < NS; ++i) lwl[lane][i] = lw[i];
+            double q[CLQ], dq[CLQ];
+#pragma unroll
+            for (int k = 0; k < CLQ; ++k) {
                 if (own) {
-                    const double q0 = sq[lane * NS + i0];
+                    const double q0 = sq[k * NS + i0];
                     double v = 0.0;
 #pragma unroll
-                    for (int i = 0; i < NS; ++i) v += lw[i] * (sq[lane * NS + i] - q0);
-                    dqi[lane] = v;
-                    qi[lane] = q0 + v;
+                    for (int i = 0; i < NS; ++i) v += lw[i] * (sq[k * NS + i] - q0);
+                    dq[k] = v;
+                    q[k] = q0 + v;
                 } else {
                     double v = 0.0;
 #pragma unroll
-                    for (int i = 0; i < NS; ++i) v += lw[i] * sq[lane * NS + i];
-                    qi[lane] = v;
+                    for (int i = 0; i < NS; ++i) v += lw[i] * sq[k * NS + i];
+                    q[k] = v;
                 }
             }
-            for (int k = lane; k < NSH; k += 64) {
-                double v = 0.0;
-#pragma unroll
-                for (int i = 0; i < NS; ++i) v += lw[i] * shl[i * NSH + k];
-                si[k] = v;
-            }
-            __syncthreads();
             Frame fr;
-            frame_from_q(qi, fr);
+            frame_from_q(q, fr);
             CircleLocal cl;
             if (own) {
                 Frame f0;
@@ -1173,22 +1184,19 @@ __global__ __launch_bounds__(64) void k_corr_full(const int* __restrict__ listf,
                     f0.t[d] = f0d[5 + d];
                 }
                 f0.sp = f0d[4];
-                const double bn[3] = {f0d[8], f0d[9], f0d[10]};
-                circle_local_rel(fr, f0, bn, dqi, cl);
+                const double bnv[3] = {f0d[8], f0d[9], f0d[10]};
+                circle_local_rel(fr, f0, bnv, dq, cl);
             } else {
                 circle_local(fr, x, cl);
             }
             // theta-rule for this circle (Section 3.2.2): trapezoid of nt, 2nt
             // or 4nt points if the estimate allows, else the bracket's
             // generalized Chebyshev rule
+            const double lg = log(gc.ct / gc.tol);
             int ntr = 0, rb = 0;
-            if (cl.cha >= chaf[0])
-                ntr = NT;
-            else if (cl.cha >= chaf[1])
-                ntr = 2 * NT;
-            else if (cl.cha >= chaf[2])
-                ntr = 4 * NT;
-            else {
+            for (int k = 0; k < 3 && !ntr; ++k)
+                if (cl.cha >= cosh(lg / (double)((NT << k) - Mt - gc.extra_modes)) - 1.0) ntr = NT << k;
+            if (!ntr) {
                 int ex;
                 frexp(sqrt(cl.d2) / fr.E, &ex);   // alpha in [2^(ex-1), 2^ex)
                 int b = 1 - ex;
@@ -1197,80 +1205,114 @@ __global__ __launch_bounds__(64) void k_corr_full(const int* __restrict__ listf,
                 } else {
                     if (b > rt.nb) {
                         b = rt.nb;
-                        if (lane == 0) atomicOr(err, 4);
+                        atomicOr(err, 4);
                     }
                     rb = b;
                 }
             }
-            // closest angle theta0 of the circle: (cos, sin) from the radial direction
-            const double c0 = dot3(cl.b0, fr.e1), s0t = dot3(cl.b0, fr.e2);
-            const int qoff = ntr ? 0 : rt.off[rb - 1];
-            const int nq = ntr ? ntr : (rt.off[rb] - qoff);
-            const int tstep = ntr ? 128 / ntr : 0;
-            n_theta += nq;
-            ++n_snode;
-            for (int q = lane; q < nq; q += 64) {
-                double cph, sph, omc, wq;
-                double cth, sth;
-                if (ntr) {
-                    cth = c_cos128[q * tstep];
-                    sth = c_sin128[q * tstep];
-                    cph = cth * c0 + sth * s0t;     // phi = theta - theta0
-                    sph = sth * c0 - cth * s0t;
-                    omc = 1.0 - cph;
-                    wq = 2.0 * PI / ntr;
-                } else {
-                    cph = rt.cs[qoff + q];
-                    sph = rt.sn[qoff + q];
-                    omc = rt.omc[qoff + q];
-                    wq = rt.w[qoff + q];
-                    cth = c0 * cph - s0t * sph;
-                    sth = s0t * cph + c0 * sph;
-                }
-                // density by Fourier synthesis
-                double v0 = si[0], v1 = si[1], v2 = si[2];
-                double clv = 1.0, slv = 0.0;
-#pragma unroll
-                for (int l = 1; l < NMODE; ++l) {
-                    double cn = clv * cth - slv * sth;
-                    slv = slv * cth + clv * sth;
-                    clv = cn;
-                    v0 += si[l * 6 + 0] * clv + si[l * 6 + 3] * slv;
-                    v1 += si[l * 6 + 1] * clv + si[l * 6 + 4] * slv;
-                    v2 += si[l * 6 + 2] * clv + si[l * 6 + 5] * slv;
-                }
-                // dy/ds, dy/dt at theta; r = x - y in the circle's local frame
-                double ys[3], yt[3], r[3];
-                const double rb0 = cl.dr + fr.E * omc;
-                const double rbp = -fr.E * sph;
-#pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    const double bb = fr.e1[d] * cth + fr.e2[d] * sth;
-                    const double bp = fr.e1p[d] * cth + fr.e2p[d] * sth;
-                    ys[d] = fr.Xp[d] + fr.Ep * bb + fr.E * bp;
-                    yt[d] = fr.E * (-fr.e1[d] * sth + fr.e2[d] * cth);
-                    r[d] = cl.z * fr.t[d] + rb0 * cl.b0[d] + rbp * cl.b0p[d];
-                }
-                double jn[3];
-                cross3(yt, ys, jn);
-                const double J = sqrt(dot3(jn, jn));
-                const double rr = dot3(r, r);
-                const double ir = rr > 0.0 ? rsqrt_nr(rr) : 0.0;
-                const double ir2 = ir * ir;
-                const double W = ws * wq;
-                const double rs = r[0] * v0 + r[1] * v1 + r[2] * v2;
-                const double rn = inf.sign * dot3(r, jn);
-                const double aS = W * J * ir, bS = W * J * rs * ir * ir2;
-                const double cD = W * rn * rs * ir2 * ir2 * ir;
-                a0 += aS * v0 + bS * r[0];
-                a1 += aS * v1 + bS * r[1];
-                a2 += aS * v2 + bS * r[2];
-                b0_ += cD * r[0];
-                b1_ += cD * r[1];
-                b2_ += cD * r[2];
+            double* R = rec[lane];
+            R[R_E] = fr.E;
+            R[R_EP] = fr.Ep;
+            R[R_SP] = fr.sp;
+            R[R_A13] = fr.E * dot3(fr.e1p, fr.t);
+            R[R_A23] = fr.E * dot3(fr.e2p, fr.t);
+            R[R_Z] = cl.z;
+            R[R_DR] = cl.dr;
+            for (int d = 0; d < 3; ++d) {
+                R[R_T + d] = fr.t[d];
+                R[R_B0 + d] = cl.b0[d];
+                R[R_B0P + d] = cl.b0p[d];
             }
-            __syncthreads();
+            R[R_W] = ws;
+            // closest angle theta0 of the circle: (cos, sin) of the radial direction
+            R[R_C0] = dot3(cl.b0, fr.e1);
+            R[R_S0] = dot3(cl.b0, fr.e2);
+            R[R_WQ] = ntr ? 2.0 * PI / ntr : 0.0;
+            rq_off[lane] = ntr ? -1 : rt.off[rb - 1];
+            rq_step[lane] = ntr ? 128 / ntr : 0;
+            npt[lane] = ntr ? ntr : rt.off[rb] - rt.off[rb - 1];
         }
+        __syncthreads();
+        // ---- 2. density coefficients at the batch's s-nodes
+        if (lane == 0) {
+            pref[0] = 0;
+            for (int j = 0; j < nb; ++j) pref[j + 1] = pref[j] + npt[j];
+        }
+        for (int k = lane; k < ncoef; k += 64) {
+            double hk[NS];
+#pragma unroll
+            for (int i = 0; i < NS; ++i) hk[i] = she[i * NSH + k];
+            for (int j = 0; j < nb; ++j) {
+                double v = 0.0;
+#pragma unroll
+                for (int i = 0; i < NS; ++i) v = fma(lwl[j][i], hk[i], v);
+                cf[j * cstride + k] = v;
+            }
+        }
+        __syncthreads();
+        // ---- 3. the batch's points, 64 at a time
+        const int Pb = pref[nb];
+        int j = 0;
+        for (int P = lane; P < Pb; P += 64) {
+            while (P >= pref[j + 1]) ++j;
+            const int q = P - pref[j];
+            const double* R = rec[j];
+            const double c0 = R[R_C0], s0t = R[R_S0];
+            const int ro = rq_off[j];
+            double cph, sph, omc, wq, cth, sth;
+            if (ro < 0) {
+                const int ix = q * rq_step[j];
+                cth = c_cos128[ix];
+                sth = c_sin128[ix];
+                cph = cth * c0 + sth * s0t;     // phi = theta - theta0
+                sph = sth * c0 - cth * s0t;
+                omc = 1.0 - cph;
+                wq = R[R_WQ];
+            } else {
+                cph = rt.cs[ro + q];
+                sph = rt.sn[ro + q];
+                omc = rt.omc[ro + q];
+                wq = rt.w[ro + q];
+                cth = c0 * cph - s0t * sph;
+                sth = s0t * cph + c0 * sph;
+            }
+            // density by Fourier synthesis over the measured band
+            const double* C = cf + j * cstride;
+            double v0 = C[0], v1 = C[1], v2 = C[2];
+            double clv = cth, slv = sth;
+            for (int l = 1; l <= Mt; ++l) {
+                const double* Cl = C + 6 * l;
+                v0 = fma(Cl[0], clv, fma(Cl[3], slv, v0));
+                v1 = fma(Cl[1], clv, fma(Cl[4], slv, v1));
+                v2 = fma(Cl[2], clv, fma(Cl[5], slv, v2));
+                const double cn = clv * cth - slv * sth;
+                slv = slv * cth + clv * sth;
+                clv = cn;
+            }
+            const double E = R[R_E], Ep = R[R_EP], z = R[R_Z], dr = R[R_DR];
+            const double gq = R[R_SP] + R[R_A13] * cth + R[R_A23] * sth;
+            const double J = E * sqrt(gq * gq + Ep * Ep);
+            const double A = dr + E * omc, B = -E * sph;
+            double r[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) r[d] = z * R[R_T + d] + A * R[R_B0 + d] + B * R[R_B0P + d];
+            const double rr = z * z + A * A + B * B;
+            const double ir = rr > 0.0 ? rsqrt_nr(rr) : 0.0;
+            const double ir2 = ir * ir;
+            const double W = R[R_W] * wq;
+            const double rs = r[0] * v0 + r[1] * v1 + r[2] * v2;
+            const double rn = sgn * E * (gq * (dr * cph - E * omc) - Ep * z);
+            const double aS = W * J * ir, bS = aS * rs * ir2;
+            const double cD = W * rn * rs * ir2 * ir2 * ir;
+            a0 += aS * v0 + bS * r[0];
+            a1 += aS * v1 + bS * r[1];
+            a2 += aS * v2 + bS * r[2];
+            b0_ += cD * r[0];
+            b1_ += cD * r[1];
+            b2_ += cD * r[2];
+            ++n_theta;
+        }
+        __syncthreads();
     }
     // minus the element's far-field (base) rule (self term zero)
     const int64_t bo = boff[e], bc = boff[e + 1] - boff[e];
@@ -1298,6 +1340,7 @@ __global__ __launch_bounds__(64) void k_corr_full(const int* __restrict__ listf,
     b0_ = wave_sum(b0_);
     b1_ = wave_sum(b1_);
     b2_ = wave_sum(b2_);
+    for (int o = 32; o > 0; o >>= 1) n_theta += __shfl_xor(n_theta, o, 64);
     if (lane == 0) {
         double* o = corr + p * 6;
         o[0] = a0;
@@ -1306,8 +1349,10 @@ __global__ __launch_bounds__(64) void k_corr_full(const int* __restrict__ listf,
         o[3] = b0_;
         o[4] = b1_;
         o[5] = b2_;
-        work[2 * blockIdx.x] = n_theta;
-        work[2 * blockIdx.x + 1] = n_snode;
+        work[4 * blockIdx.x] = n_theta;
+        work[4 * blockIdx.x + 1] = S;
+        work[4 * blockIdx.x + 2] = n_theta * Mt;
+        work[4 * blockIdx.x + 3] = S * (Mt + 1);
     }
 }
 
@@ -1404,6 +1449,7 @@ int launch_sigma_base(hipStream_t st, int E, const ElemInfo* info, const int64_t
 int launch_targets(hipStream_t st, int64_t T, const double* x, const int64_t* tnode, const double* ny, int64_t N,
                    double* xt, int* err)
 {
+    if (T == 0) return 0;
     hipLaunchKernelGGL(k_targets, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, st, T, x, tnode, ny, N, xt, err);
     LAUNCH_CHECK();
     return 0;
@@ -1471,12 +1517,15 @@ int launch_corr_full(hipStream_t st, int nfull, const int* listf, const int* pe,
                      const int* band, const double* cls, const int64_t* boff, const double* by, const double* bn,
                      const double* bsw, int64_t Nb, const int* roff, const double* rth, const double* rw, int nb,
                      const double* lx, const double* lw, int nl, const double* rcs, const double* rsn,
-                     const double* romc, GateConsts gc, double* corr, int* err, int* work)
+                     const double* romc, GateConsts gc, double* corr, int* err, int* work, int mt_max)
 {
     if (nfull == 0) return 0;
+    if (mt_max < 0 || mt_max >= NMODE) return (int)hipErrorInvalidValue;
     RuleTables rt{roff, rth, rw, rcs, rsn, romc, nb, lx, lw, nl};
-    hipLaunchKernelGGL(k_corr_full, dim3(nfull), dim3(64), 0, st, listf, pe, pt, xt, T, tnode, clq, sh, info, band,
-                       cls, boff, by, bn, bsw, Nb, rt, gc, corr, err, work);
+    const int cstride = 6 * (mt_max + 1);
+    hipLaunchKernelGGL(k_corr_full, dim3(nfull), dim3(64), (size_t)SB * cstride * sizeof(double), st, listf, pe, pt,
+                       xt, T, tnode, clq, sh, info, band, cls, boff, by, bn, bsw, Nb, rt, gc, corr, err, work,
+                       cstride);
     LAUNCH_CHECK();
     return 0;
 }

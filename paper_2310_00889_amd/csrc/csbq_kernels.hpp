@@ -45,7 +45,7 @@ int launch_corr_full(hipStream_t st, int nfull, const int* listf, const int* pe,
                      const int* band, const double* cls, const int64_t* boff, const double* by, const double* bn,
                      const double* bsw, int64_t Nb, const int* roff, const double* rth, const double* rw, int nb,
                      const double* lx, const double* lw, int nl, const double* rcs, const double* rsn,
-                     const double* romc, GateConsts gc, double* corr, int* err, int* work);
+                     const double* romc, GateConsts gc, double* corr, int* err, int* work, int mt_max);
 int launch_reduce(hipStream_t st, int64_t T, int nchunk, const double* part, const int64_t* off, const int8_t* tier,
                   const double* corr, double* usl, double* udl);
 
