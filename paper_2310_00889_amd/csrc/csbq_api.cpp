@@ -168,6 +168,7 @@ struct csbq_ctx {
     int64_t Mtot[NUP] = {0, 0, 0};
     // far-field (base) source set
     int64_t Nb = 0;
+    double mix_near2 = 0.0;   // squared radius of the FP64 near part of the mixed-precision far sum
     DBuf<int64_t> boff;
     DBuf<double> by, bn, bw, bsw;
     // evaluation scratch
@@ -586,6 +587,14 @@ int csbq_set_geometry(csbq_ctx* ctx, int32_t n_bodies, const int32_t* n_panels, 
         LCHK(launch_base_build(ctx->stream, (int)E, ctx->info.p, ctx->boff.p, ctx->ny.p, ctx->nn.p, ctx->nw.p, N,
                                ctx->cpy[0].p, ctx->cpn[0].p, ctx->cpw[0].p, ctx->Mtot[0], ctx->by.p, ctx->bn.p,
                                ctx->bw.p, ctx->Nb));
+        // mixed precision: sources within sqrt(100 w_max) of a target are
+        // summed in FP64, so no FP32 term exceeds ~1e-2 of the density scale
+        std::vector<double> hbw((size_t)ctx->Nb);
+        HIPC(hipMemcpyAsync(hbw.data(), ctx->bw.p, hbw.size() * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+        HIPC(hipStreamSynchronize(ctx->stream));
+        double wmax = 0.0;
+        for (double w : hbw) wmax = std::max(wmax, std::fabs(w));
+        ctx->mix_near2 = 100.0 * wmax;
     }
     HIPC(hipStreamSynchronize(ctx->stream));
     ctx->have_geom = true;
@@ -678,14 +687,18 @@ static int far_sum(csbq_ctx* ctx, int64_t T, bool native, int* nchunk_out)
     const double* sy = native ? ctx->ny.p : ctx->by.p;
     const double* sn = native ? ctx->nn.p : ctx->bn.p;
     const double* ss = native ? ctx->sw.p : ctx->bsw.p;
-    int64_t tblocks = (T + 255) / 256;
+    int64_t tblocks = (T + 511) / 512;   // far kernel: 512 targets per block
     int nchunk = (int)std::max<int64_t>(1, std::min<int64_t>((4096 + tblocks - 1) / std::max<int64_t>(tblocks, 1),
                                                              (Ns + 4095) / 4096));
     int64_t chunk = ((Ns + nchunk - 1) / nchunk + 255) / 256 * 256;
     nchunk = (int)((Ns + chunk - 1) / chunk);
     if (nchunk < 1) nchunk = 1;
     ALLOC(ctx->part, (size_t)nchunk * 6 * T + 1);
-    if (T > 0) LCHK(launch_far(ctx->stream, T, ctx->xt.p, sy, sn, ss, Ns, chunk, nchunk, ctx->part.p));
+    // the smooth sum over the element nodes (a diagnostic) stays FP64; the
+    // evaluation's far field follows the context's precision
+    const bool mixed = !native && ctx->opt.precision == CSBQ_MIXED;
+    if (T > 0)
+        LCHK(launch_far(ctx->stream, T, ctx->xt.p, sy, sn, ss, Ns, chunk, nchunk, ctx->part.p, mixed, ctx->mix_near2));
     *nchunk_out = nchunk;
     return CSBQ_OK;
 }

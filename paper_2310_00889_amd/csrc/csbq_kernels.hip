@@ -495,68 +495,284 @@ __global__ void k_targets(int64_t T, const double* __restrict__ x, const int64_t
 // smooth Nystrom sum (Section 3.2.1): targets x sources, sources staged in LDS
 // ---------------------------------------------------------------------------
 constexpr int FAR_BLOCK = 256;
+constexpr int FAR_TPT = 2;      // targets per thread
+constexpr int FAR_REC = 10;     // LDS record of a source: y(3) n(3) sigma*w(3), padded to 16-byte pairs
 
+// Each thread owns FAR_TPT targets; a block streams its source chunk through
+// LDS in tiles of FAR_BLOCK sources (one record each, read as five 16-byte
+// broadcasts), so every LDS read serves FAR_TPT pairs.
 __global__ __launch_bounds__(FAR_BLOCK) void k_far(int64_t T, const double* __restrict__ xt,
                                                    const double* __restrict__ sy, const double* __restrict__ sn,
                                                    const double* __restrict__ ssw, int64_t N, int64_t chunk,
                                                    double* __restrict__ part)
 {
-    __shared__ double ly[3][FAR_BLOCK], ln_[3][FAR_BLOCK], ls[3][FAR_BLOCK];
+    __shared__ __attribute__((aligned(16))) double src[FAR_BLOCK * FAR_REC];
     const int tid = threadIdx.x;
-    const int64_t t = (int64_t)blockIdx.x * FAR_BLOCK + tid;
-    const bool ok = t < T;
-    double x0 = 0, x1 = 0, x2 = 0;
-    if (ok) {
-        x0 = xt[t];
-        x1 = xt[T + t];
-        x2 = xt[2 * T + t];
+    const int64_t tb = (int64_t)blockIdx.x * (FAR_BLOCK * FAR_TPT) + tid;
+    double x[FAR_TPT][3], us[FAR_TPT][3], ud[FAR_TPT][3];
+#pragma unroll
+    for (int u = 0; u < FAR_TPT; ++u) {
+        const int64_t t = tb + u * FAR_BLOCK;
+        const bool ok = t < T;
+        x[u][0] = ok ? xt[t] : 0.0;
+        x[u][1] = ok ? xt[T + t] : 0.0;
+        x[u][2] = ok ? xt[2 * T + t] : 0.0;
+        for (int d = 0; d < 3; ++d) us[u][d] = ud[u][d] = 0.0;
     }
-    double s0 = 0, s1 = 0, s2 = 0, d0 = 0, d1 = 0, d2 = 0;
     const int64_t c0 = (int64_t)blockIdx.y * chunk;
     const int64_t c1 = min(N, c0 + chunk);
     for (int64_t base = c0; base < c1; base += FAR_BLOCK) {
         const int64_t k = base + tid;
         if (k < c1) {
-            ly[0][tid] = sy[k];
-            ly[1][tid] = sy[N + k];
-            ly[2][tid] = sy[2 * N + k];
-            ln_[0][tid] = sn[k];
-            ln_[1][tid] = sn[N + k];
-            ln_[2][tid] = sn[2 * N + k];
-            ls[0][tid] = ssw[k];
-            ls[1][tid] = ssw[N + k];
-            ls[2][tid] = ssw[2 * N + k];
+            double* r = src + tid * FAR_REC;
+            r[0] = sy[k];
+            r[1] = sy[N + k];
+            r[2] = sy[2 * N + k];
+            r[3] = sn[k];
+            r[4] = sn[N + k];
+            r[5] = sn[2 * N + k];
+            r[6] = ssw[k];
+            r[7] = ssw[N + k];
+            r[8] = ssw[2 * N + k];
+            r[9] = 0.0;
         }
         __syncthreads();
         const int nin = (int)min((int64_t)FAR_BLOCK, c1 - base);
-#pragma unroll 4
+#pragma unroll 2
         for (int kk = 0; kk < nin; ++kk) {
-            double r0 = x0 - ly[0][kk], r1 = x1 - ly[1][kk], r2 = x2 - ly[2][kk];
-            double rr = fma(r0, r0, fma(r1, r1, r2 * r2));
-            double ir = rr > 0.0 ? rsqrt_nr(rr) : 0.0;
-            double w0 = ls[0][kk], w1 = ls[1][kk], w2 = ls[2][kk];
-            double rs = fma(r0, w0, fma(r1, w1, r2 * w2));
-            double rn = fma(r0, ln_[0][kk], fma(r1, ln_[1][kk], r2 * ln_[2][kk]));
-            double ir2 = ir * ir;
-            double b = rs * ir * ir2;
-            double cD = rn * rs * ir2 * ir2 * ir;
-            s0 = fma(ir, w0, fma(b, r0, s0));
-            s1 = fma(ir, w1, fma(b, r1, s1));
-            s2 = fma(ir, w2, fma(b, r2, s2));
-            d0 = fma(cD, r0, d0);
-            d1 = fma(cD, r1, d1);
-            d2 = fma(cD, r2, d2);
+            const double2* r2 = reinterpret_cast<const double2*>(src + kk * FAR_REC);
+            const double2 A = r2[0], B = r2[1], C = r2[2], D = r2[3], F = r2[4];
+            // A = (y0, y1), B = (y2, n0), C = (n1, n2), D = (w0, w1), F = (w2, -)
+#pragma unroll
+            for (int u = 0; u < FAR_TPT; ++u) {
+                const double r0 = x[u][0] - A.x, r1 = x[u][1] - A.y, r2_ = x[u][2] - B.x;
+                const double rr = fma(r0, r0, fma(r1, r1, r2_ * r2_));
+                // evaluated unconditionally (a coincident node gives inf/NaN
+                // that the select discards), so the loop has no branch
+                const double irn = rsqrt_nr(rr);
+                const double ir = rr > 0.0 ? irn : 0.0;
+                const double rs = fma(r0, D.x, fma(r1, D.y, r2_ * F.x));
+                const double rn = fma(r0, B.y, fma(r1, C.x, r2_ * C.y));
+                const double ir2 = ir * ir;
+                const double b = rs * (ir * ir2);      // (r.sw) / r^3
+                const double cD = (rn * b) * ir2;      // (r.n)(r.sw) / r^5
+                us[u][0] = fma(ir, D.x, fma(b, r0, us[u][0]));
+                us[u][1] = fma(ir, D.y, fma(b, r1, us[u][1]));
+                us[u][2] = fma(ir, F.x, fma(b, r2_, us[u][2]));
+                ud[u][0] = fma(cD, r0, ud[u][0]);
+                ud[u][1] = fma(cD, r1, ud[u][1]);
+                ud[u][2] = fma(cD, r2_, ud[u][2]);
+            }
         }
         __syncthreads();
     }
-    if (ok) {
-        double* p = part + (int64_t)blockIdx.y * 6 * T;
-        p[0 * T + t] = s0;
-        p[1 * T + t] = s1;
-        p[2 * T + t] = s2;
-        p[3 * T + t] = d0;
-        p[4 * T + t] = d1;
-        p[5 * T + t] = d2;
+    double* p = part + (int64_t)blockIdx.y * 6 * T;
+#pragma unroll
+    for (int u = 0; u < FAR_TPT; ++u) {
+        const int64_t t = tb + u * FAR_BLOCK;
+        if (t < T) {
+            p[0 * T + t] = us[u][0];
+            p[1 * T + t] = us[u][1];
+            p[2 * T + t] = us[u][2];
+            p[3 * T + t] = ud[u][0];
+            p[4 * T + t] = ud[u][1];
+            p[5 * T + t] = ud[u][2];
+        }
+    }
+}
+
+// Mixed-precision smooth sum.  r = x - y is formed in FP64 (so a pair keeps
+// its relative accuracy whatever the coordinates' magnitude) and the kernel
+// is evaluated in FP32, summed in FP32 over one tile of FAR_BLOCK sources and
+// then into FP64 accumulators.  Sources closer than sqrt(near2) to a target
+// are evaluated and summed in FP64 from the FP64 record: their terms are the
+// large ones that the near corrections later cancel against an FP64
+// subtraction of the same terms, so they must carry FP64 rounding only.
+// Whole tiles whose bounding box is farther than that from the block's
+// targets skip the per-pair test.
+struct __attribute__((aligned(16))) FarRecMx {
+    double y0, y1, y2;
+    float n0, n1, n2, w0, w1, w2;    // FP32 copy for the far part
+    double n[3], w[3];               // FP64 values for the near part
+};
+
+// bounding box of the block's points (lo/hi per coordinate; +-inf if none)
+__device__ inline void block_box(double* lo, double* hi, double* red /*[2][3][FAR_BLOCK / 64]*/)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int d = 0; d < 3; ++d) {
+        double a = lo[d], b = hi[d];
+        for (int o = 32; o > 0; o >>= 1) {
+            a = fmin(a, __shfl_xor(a, o, 64));
+            b = fmax(b, __shfl_xor(b, o, 64));
+        }
+        if (lane == 0) {
+            red[d * (FAR_BLOCK / 64) + wv] = a;
+            red[(3 + d) * (FAR_BLOCK / 64) + wv] = b;
+        }
+    }
+    __syncthreads();
+    for (int d = 0; d < 3; ++d) {
+        double a = red[d * (FAR_BLOCK / 64)], b = red[(3 + d) * (FAR_BLOCK / 64)];
+        for (int k = 1; k < FAR_BLOCK / 64; ++k) {
+            a = fmin(a, red[d * (FAR_BLOCK / 64) + k]);
+            b = fmax(b, red[(3 + d) * (FAR_BLOCK / 64) + k]);
+        }
+        lo[d] = a;
+        hi[d] = b;
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(FAR_BLOCK) void k_far_mx(int64_t T, const double* __restrict__ xt,
+                                                      const double* __restrict__ sy, const double* __restrict__ sn,
+                                                      const double* __restrict__ ssw, int64_t N, int64_t chunk,
+                                                      double near2, double* __restrict__ part)
+{
+    __shared__ FarRecMx src[FAR_BLOCK];
+    __shared__ double red[6 * (FAR_BLOCK / 64)];
+    const int tid = threadIdx.x;
+    const int64_t tb = (int64_t)blockIdx.x * (FAR_BLOCK * FAR_TPT) + tid;
+    const float near2f = (float)near2;
+    double x[FAR_TPT][3], us[FAR_TPT][3], ud[FAR_TPT][3];
+    double tlo[3] = {INFINITY, INFINITY, INFINITY}, thi[3] = {-INFINITY, -INFINITY, -INFINITY};
+#pragma unroll
+    for (int u = 0; u < FAR_TPT; ++u) {
+        const int64_t t = tb + u * FAR_BLOCK;
+        const bool ok = t < T;
+        x[u][0] = ok ? xt[t] : 0.0;
+        x[u][1] = ok ? xt[T + t] : 0.0;
+        x[u][2] = ok ? xt[2 * T + t] : 0.0;
+        for (int d = 0; d < 3; ++d) {
+            us[u][d] = ud[u][d] = 0.0;
+            if (ok) {
+                tlo[d] = fmin(tlo[d], x[u][d]);
+                thi[d] = fmax(thi[d], x[u][d]);
+            }
+        }
+    }
+    block_box(tlo, thi, red);
+    const int64_t c0 = (int64_t)blockIdx.y * chunk;
+    const int64_t c1 = min(N, c0 + chunk);
+    for (int64_t base = c0; base < c1; base += FAR_BLOCK) {
+        const int64_t k = base + tid;
+        double slo[3] = {INFINITY, INFINITY, INFINITY}, shi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        if (k < c1) {
+            FarRecMx r;
+            r.y0 = sy[k];
+            r.y1 = sy[N + k];
+            r.y2 = sy[2 * N + k];
+            for (int d = 0; d < 3; ++d) {
+                r.n[d] = sn[d * N + k];
+                r.w[d] = ssw[d * N + k];
+            }
+            r.n0 = (float)r.n[0];
+            r.n1 = (float)r.n[1];
+            r.n2 = (float)r.n[2];
+            r.w0 = (float)r.w[0];
+            r.w1 = (float)r.w[1];
+            r.w2 = (float)r.w[2];
+            src[tid] = r;
+            slo[0] = shi[0] = r.y0;
+            slo[1] = shi[1] = r.y1;
+            slo[2] = shi[2] = r.y2;
+        }
+        block_box(slo, shi, red);   // also the barrier after the tile is stored
+        double gap2 = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            const double g = fmax(0.0, fmax(tlo[d] - shi[d], slo[d] - thi[d]));
+            gap2 += g * g;
+        }
+        const bool near_tile = !(gap2 >= near2 && gap2 > 0.0);   // uniform over the block
+        const int nin = (int)min((int64_t)FAR_BLOCK, c1 - base);
+        float fs[FAR_TPT][3], fd[FAR_TPT][3];
+#pragma unroll
+        for (int u = 0; u < FAR_TPT; ++u)
+            for (int d = 0; d < 3; ++d) fs[u][d] = fd[u][d] = 0.0f;
+        if (!near_tile) {
+#pragma unroll 2
+            for (int kk = 0; kk < nin; ++kk) {
+                const FarRecMx& R = src[kk];
+                const double y0 = R.y0, y1 = R.y1, y2 = R.y2;
+                const float n0 = R.n0, n1 = R.n1, n2 = R.n2, w0 = R.w0, w1 = R.w1, w2 = R.w2;
+#pragma unroll
+                for (int u = 0; u < FAR_TPT; ++u) {
+                    const float r0 = (float)(x[u][0] - y0), r1 = (float)(x[u][1] - y1), r2 = (float)(x[u][2] - y2);
+                    const float rr = fmaf(r0, r0, fmaf(r1, r1, r2 * r2));
+                    const float ir = __builtin_amdgcn_rsqf(rr);   // rr > 0: the tile is away from every target
+                    const float rs = fmaf(r0, w0, fmaf(r1, w1, r2 * w2));
+                    const float rn = fmaf(r0, n0, fmaf(r1, n1, r2 * n2));
+                    const float ir2 = ir * ir;
+                    const float b = rs * (ir * ir2);
+                    const float cD = (rn * b) * ir2;
+                    fs[u][0] = fmaf(ir, w0, fmaf(b, r0, fs[u][0]));
+                    fs[u][1] = fmaf(ir, w1, fmaf(b, r1, fs[u][1]));
+                    fs[u][2] = fmaf(ir, w2, fmaf(b, r2, fs[u][2]));
+                    fd[u][0] = fmaf(cD, r0, fd[u][0]);
+                    fd[u][1] = fmaf(cD, r1, fd[u][1]);
+                    fd[u][2] = fmaf(cD, r2, fd[u][2]);
+                }
+            }
+        } else {
+            for (int kk = 0; kk < nin; ++kk) {
+                const FarRecMx& R = src[kk];
+#pragma unroll
+                for (int u = 0; u < FAR_TPT; ++u) {
+                    const double d0 = x[u][0] - R.y0, d1 = x[u][1] - R.y1, d2 = x[u][2] - R.y2;
+                    const float r0 = (float)d0, r1 = (float)d1, r2 = (float)d2;
+                    const float rr = fmaf(r0, r0, fmaf(r1, r1, r2 * r2));
+                    if (rr < near2f) {
+                        const double rr64 = fma(d0, d0, fma(d1, d1, d2 * d2));
+                        const double irn = rsqrt_nr(rr64);
+                        const double ir = rr64 > 0.0 ? irn : 0.0;
+                        const double rs = fma(d0, R.w[0], fma(d1, R.w[1], d2 * R.w[2]));
+                        const double rn = fma(d0, R.n[0], fma(d1, R.n[1], d2 * R.n[2]));
+                        const double ir2 = ir * ir;
+                        const double b = rs * (ir * ir2);
+                        const double cD = (rn * b) * ir2;
+                        us[u][0] = fma(ir, R.w[0], fma(b, d0, us[u][0]));
+                        us[u][1] = fma(ir, R.w[1], fma(b, d1, us[u][1]));
+                        us[u][2] = fma(ir, R.w[2], fma(b, d2, us[u][2]));
+                        ud[u][0] = fma(cD, d0, ud[u][0]);
+                        ud[u][1] = fma(cD, d1, ud[u][1]);
+                        ud[u][2] = fma(cD, d2, ud[u][2]);
+                    } else {
+                        const float ir = __builtin_amdgcn_rsqf(rr);
+                        const float rs = fmaf(r0, R.w0, fmaf(r1, R.w1, r2 * R.w2));
+                        const float rn = fmaf(r0, R.n0, fmaf(r1, R.n1, r2 * R.n2));
+                        const float ir2 = ir * ir;
+                        const float b = rs * (ir * ir2);
+                        const float cD = (rn * b) * ir2;
+                        fs[u][0] = fmaf(ir, R.w0, fmaf(b, r0, fs[u][0]));
+                        fs[u][1] = fmaf(ir, R.w1, fmaf(b, r1, fs[u][1]));
+                        fs[u][2] = fmaf(ir, R.w2, fmaf(b, r2, fs[u][2]));
+                        fd[u][0] = fmaf(cD, r0, fd[u][0]);
+                        fd[u][1] = fmaf(cD, r1, fd[u][1]);
+                        fd[u][2] = fmaf(cD, r2, fd[u][2]);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < FAR_TPT; ++u)
+            for (int d = 0; d < 3; ++d) {
+                us[u][d] += (double)fs[u][d];
+                ud[u][d] += (double)fd[u][d];
+            }
+        __syncthreads();
+    }
+    double* p = part + (int64_t)blockIdx.y * 6 * T;
+#pragma unroll
+    for (int u = 0; u < FAR_TPT; ++u) {
+        const int64_t t = tb + u * FAR_BLOCK;
+        if (t < T) {
+            p[0 * T + t] = us[u][0];
+            p[1 * T + t] = us[u][1];
+            p[2 * T + t] = us[u][2];
+            p[3 * T + t] = ud[u][0];
+            p[4 * T + t] = ud[u][1];
+            p[5 * T + t] = ud[u][2];
+        }
     }
 }
 
@@ -1456,10 +1672,14 @@ int launch_targets(hipStream_t st, int64_t T, const double* x, const int64_t* tn
 }
 
 int launch_far(hipStream_t st, int64_t T, const double* xt, const double* sy, const double* sn, const double* ssw,
-               int64_t N, int64_t chunk, int nchunk, double* part)
+               int64_t N, int64_t chunk, int nchunk, double* part, bool mixed, double near2)
 {
-    dim3 grid((unsigned)((T + FAR_BLOCK - 1) / FAR_BLOCK), (unsigned)nchunk);
-    hipLaunchKernelGGL(k_far, grid, dim3(FAR_BLOCK), 0, st, T, xt, sy, sn, ssw, N, chunk, part);
+    const int64_t per = (int64_t)FAR_BLOCK * FAR_TPT;
+    dim3 grid((unsigned)((T + per - 1) / per), (unsigned)nchunk);
+    if (mixed)
+        hipLaunchKernelGGL(k_far_mx, grid, dim3(FAR_BLOCK), 0, st, T, xt, sy, sn, ssw, N, chunk, near2, part);
+    else
+        hipLaunchKernelGGL(k_far, grid, dim3(FAR_BLOCK), 0, st, T, xt, sy, sn, ssw, N, chunk, part);
     LAUNCH_CHECK();
     return 0;
 }

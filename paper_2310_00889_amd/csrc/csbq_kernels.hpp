@@ -28,7 +28,7 @@ int launch_sigma_base(hipStream_t st, int E, const ElemInfo* info, const int64_t
 int launch_targets(hipStream_t st, int64_t T, const double* x, const int64_t* tnode, const double* ny, int64_t N,
                    double* xt, int* err);
 int launch_far(hipStream_t st, int64_t T, const double* xt, const double* sy, const double* sn, const double* ssw,
-               int64_t N, int64_t chunk, int nchunk, double* part);
+               int64_t N, int64_t chunk, int nchunk, double* part, bool mixed, double near2);
 int launch_search(hipStream_t st, int64_t T, int E, const double* xt, const int64_t* tnode, const ElemInfo* info,
                   const double* rnear, const int64_t* off, int* cnt, int* pe, int* pt);
 int launch_classify(hipStream_t st, int64_t P, const int* perm, const int* pe, const int* pt, const double* xt,

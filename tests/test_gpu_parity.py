@@ -161,3 +161,62 @@ def test_empty_and_invalid_inputs(ev):
     # the context stays usable after an error
     us, ud = ev.eval(sc.sigma, None, np.array([0, 1]))
     assert np.isfinite(us).all()
+
+
+MIXED_GATE = 1e-6
+
+
+@pytest.fixture(scope="module")
+def ev_mixed():
+    import torch
+    import paper_2310_00889_amd as pk
+    torch.zeros(1, device="cuda")
+    e = pk.Evaluator(quad_tol=1e-7, precision="mixed")
+    yield e
+    e.close()
+
+
+def test_mixed_small_pipe(ev_mixed):
+    """Mixed precision (FP32 far field, FP64 near corrections) at quad_tol 1e-7:
+    every output within 1e-6 of the FP64 oracle, on and off the surface."""
+    sc = synth.small_pipe_scene(n_panels=6, n_spheres=3)
+    ev_mixed.set_geometry(sc)
+    rng = np.random.default_rng(4)
+    tn = rng.choice(sc.n_nodes, 200, replace=False)
+    us, ud = ev_mixed.eval(sc.sigma, None, tn)
+    uso, udo = oracle.evaluate(sc, None, None, tn)
+    print("mixed on-surface", _rel(us, uso), _rel(ud, udo), flush=True)
+    assert _rel(us, uso) < MIXED_GATE and _rel(ud, udo) < MIXED_GATE
+    y, n, _ = oracle.nodes(sc)
+    k = rng.choice(sc.n_nodes, 200, replace=False)
+    d = 10.0 ** rng.uniform(-3, -0.3, 200) * np.where(rng.random(200) < 0.5, 1, -1)
+    xs = y[k] + d[:, None] * n[k]
+    us, ud = ev_mixed.eval(sc.sigma, xs, None)
+    uso, udo = oracle.evaluate(sc, None, xs, -np.ones(200, np.int64))
+    print("mixed off-surface", _rel(us, uso), _rel(ud, udo), flush=True)
+    assert _rel(us, uso) < MIXED_GATE and _rel(ud, udo) < MIXED_GATE
+
+
+def test_mixed_config3_full_size_sampled(ev_mixed):
+    """Config 3 (1000 spheres in the scaled pipe, 563,200 on-surface targets) in
+    mixed precision, full size; 12 sampled targets per class (wall, particle,
+    near-contact particle) against the oracle, 1e-6 per class."""
+    import torch
+    sc = synth.config3()
+    ev_mixed.set_geometry(sc)
+    sig = torch.from_numpy(sc.sigma).cuda()
+    tn = torch.from_numpy(sc.tgt_node).cuda()
+    us, ud = ev_mixed.eval(sig, None, tn)
+    torch.cuda.synchronize()
+    us, ud = us.cpu().numpy(), ud.cpu().numpy()
+    assert np.isfinite(us).all() and np.isfinite(ud).all()
+    print("config3 mixed stats", ev_mixed.stats(), flush=True)
+    rng = np.random.default_rng(6)
+    idx = np.concatenate([rng.choice(np.where(sc.tgt_class == c)[0], 12, replace=False) for c in (0, 1, 2)])
+    uso, udo = oracle.evaluate(sc, None, None, sc.tgt_node[idx])
+    for u, uo, what in ((us[idx], uso, "S"), (ud[idx], udo, "D")):
+        for c in (0, 1, 2):
+            m = sc.tgt_class[idx] == c
+            err = np.abs(u[m] - uo[m]).max() / np.abs(uo[m]).max()
+            print(f"mixed {what} class {c}: {err:.2e}", flush=True)
+            assert err < MIXED_GATE, (what, c, err)
