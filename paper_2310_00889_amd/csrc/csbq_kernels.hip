@@ -95,29 +95,52 @@ __device__ inline void frame_at_x(const double* __restrict__ clq, double x, Fram
     frame_from_q(q, f);
 }
 
-// position/tangent/radius only (for distance searches)
+// position/tangent/radius only (for the distance searches of the
+// classification, which only steer estimates): barycentric interpolation with
+// the weights formed on the fly from the hardware reciprocal refined by two
+// Newton steps (~1 ulp); a node hit (x equal to a GL node) takes the node's
+// values.  The node loop is only partly unrolled so that the element's data
+// is read in the loop rather than held in registers.
 __device__ inline void circle_at_x(const double* __restrict__ clq, double x, double* X, double* t, double* E)
 {
-    double l[NS];
-    bary_weights(x, c_gx, c_lam, l);
-    double xp[3];
+    double xp[3] = {0.0, 0.0, 0.0}, e = 0.0, sum = 0.0;
+    X[0] = X[1] = X[2] = 0.0;
+    int hit = -1;
+#pragma unroll 2
+    for (int i = 0; i < NS; ++i) {
+        const double dx = x - c_gx[i];
+        if (dx == 0.0) hit = i;
+        double r = __builtin_amdgcn_rcp(dx);
+        r = r * fma(-dx, r, 2.0);
+        r = r * fma(-dx, r, 2.0);
+        const double li = c_lam[i] * r;
+        sum += li;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        double v = 0.0, vp = 0.0;
-#pragma unroll
-        for (int i = 0; i < NS; ++i) {
-            v += l[i] * clq[(Q_X + d) * NS + i];
-            vp += l[i] * clq[(Q_XP + d) * NS + i];
+        for (int d = 0; d < 3; ++d) {
+            X[d] += li * clq[(Q_X + d) * NS + i];
+            xp[d] += li * clq[(Q_XP + d) * NS + i];
         }
-        X[d] = v;
-        xp[d] = vp;
+        e += li * clq[Q_E * NS + i];
     }
-    double e = 0.0;
-#pragma unroll
-    for (int i = 0; i < NS; ++i) e += l[i] * clq[Q_E * NS + i];
+    if (hit >= 0) {
+        for (int d = 0; d < 3; ++d) {
+            X[d] = clq[(Q_X + d) * NS + hit];
+            xp[d] = clq[(Q_XP + d) * NS + hit];
+        }
+        e = clq[Q_E * NS + hit];
+    } else {
+        double is = __builtin_amdgcn_rcp(sum);
+        is = is * fma(-sum, is, 2.0);
+        is = is * fma(-sum, is, 2.0);
+        for (int d = 0; d < 3; ++d) {
+            X[d] *= is;
+            xp[d] *= is;
+        }
+        e *= is;
+    }
     *E = e;
-    double is = 1.0 / sqrt(dot3(xp, xp));
-    for (int d = 0; d < 3; ++d) t[d] = xp[d] * is;
+    double it = rsqrt_nr(dot3(xp, xp));
+    for (int d = 0; d < 3; ++d) t[d] = xp[d] * it;
 }
 
 __device__ inline void circle_dist(const double* X, const double* t, double E, const double* x, double* d2, double* cha)
@@ -870,7 +893,9 @@ __device__ inline cx contact_fn(const double* __restrict__ clq, cx z, const doub
     // barycentric sums at the complex point in one pass (no stored weights)
     cx sum = {0.0, 0.0};
     cx X[3] = {{0, 0}, {0, 0}, {0, 0}}, Xp[3] = {{0, 0}, {0, 0}, {0, 0}}, E = {0, 0};
-#pragma unroll
+    // partly unrolled: a full unroll lets the compiler hoist all 112 element
+    // values out of the root iteration into registers
+#pragma unroll 2
     for (int i = 0; i < NS; ++i) {
         const double dr = z.r - c_gx[i], di = z.i;
         const double q = dr * dr + di * di;
@@ -1000,8 +1025,8 @@ __global__ __launch_bounds__(128) void k_classify(int64_t P, const int* __restri
         return cha;
     };
     double d2c, chac;
-    double xd = golden_min(fd, xn_of(max(kd - 1, 0)), xn_of(min(kd + 1, NCIRC - 1)), 26, &d2c);
-    golden_min(fa, xn_of(max(ka - 1, 0)), xn_of(min(ka + 1, NCIRC - 1)), 26, &chac);
+    double xd = golden_min(fd, xn_of(max(kd - 1, 0)), xn_of(min(kd + 1, NCIRC - 1)), 20, &d2c);
+    golden_min(fa, xn_of(max(ka - 1, 0)), xn_of(min(ka + 1, NCIRC - 1)), 20, &chac);
     d2c = fmin(d2c, bd);
     chac = fmin(chac, ba);
     // speed bound near the closest circle
