@@ -111,6 +111,19 @@ int csbq_set_geometry(csbq_ctx* ctx, int32_t n_bodies, const int32_t* n_panels, 
                       const double* s_break, const double* xc, const double* eps, const double* e1, int32_t ns,
                       int32_t nt, int mem);
 
+/* Several independent geometries in one context (a batch): body_group[b] in
+   0..G-1 names the geometry of body b (non-decreasing, every group present,
+   starting at 0; NULL = one geometry).  Bodies of different groups never
+   interact: each group's potential is the same sum as if it were alone (Eq.
+   e:nystrom-no-correction and its local corrections, per geometry).  Every
+   evaluation then runs as one pass over the whole batch: one smooth-sum
+   launch over all groups' blocks ordered by cost (sources x targets), one
+   near-pair search, one classification and one correction launch per tier.
+   Other arguments as csbq_set_geometry; body_group lives in `mem`. */
+int csbq_set_geometry_batch(csbq_ctx* ctx, int32_t n_bodies, const int32_t* body_group, const int32_t* n_panels,
+                            const int32_t* normal_sign, const double* s_break, const double* xc, const double* eps,
+                            const double* e1, int32_t ns, int32_t nt, int mem);
+
 /* Number of surface nodes of the current geometry. */
 int csbq_num_nodes(const csbq_ctx* ctx, int64_t* n_nodes);
 
@@ -136,6 +149,14 @@ int csbq_eval(csbq_ctx* ctx, const double* sigma, int64_t n_tgt, const double* x
    precision mode. */
 int csbq_smooth_sum(csbq_ctx* ctx, const double* sigma, int64_t n_tgt, const double* x, const int64_t* tgt_node,
                     double* u_sl, double* u_dl, int mem);
+
+/* csbq_eval over a batch (csbq_set_geometry_batch): tgt_group[n_tgt] names
+   the geometry of every free target (ignored for on-surface targets, whose
+   node fixes it; NULL = group 0 for free targets).  Targets must be ordered by
+   group (non-decreasing); an unordered list or a group out of range fails with
+   CSBQ_EINVAL.  tgt_group lives in `mem`. */
+int csbq_eval_batch(csbq_ctx* ctx, const double* sigma, int64_t n_tgt, const double* x, const int64_t* tgt_node,
+                    const int32_t* tgt_group, double* u_sl, double* u_dl, int mem);
 
 /* Statistics of the last csbq_eval as a JSON object (phase times in ms from
    HIP events, pair counts per correction tier).  Writes at most cap bytes

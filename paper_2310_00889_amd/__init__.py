@@ -54,9 +54,11 @@ def load_library():
     lib.csbq_last_error.argtypes = [vp]
     lib.csbq_last_error.restype = C.c_char_p
     lib.csbq_set_geometry.argtypes = [vp, C.c_int32, ip, ip, dp, dp, dp, dp, C.c_int32, C.c_int32, C.c_int]
+    lib.csbq_set_geometry_batch.argtypes = [vp, C.c_int32, ip, ip, ip, dp, dp, dp, dp, C.c_int32, C.c_int32, C.c_int]
     lib.csbq_num_nodes.argtypes = [vp, C.POINTER(C.c_int64)]
     lib.csbq_get_nodes.argtypes = [vp, dp, dp, dp, C.c_int]
     lib.csbq_eval.argtypes = [vp, dp, C.c_int64, dp, lp, dp, dp, C.c_int]
+    lib.csbq_eval_batch.argtypes = [vp, dp, C.c_int64, dp, lp, ip, dp, dp, C.c_int]
     lib.csbq_smooth_sum.argtypes = [vp, dp, C.c_int64, dp, lp, dp, dp, C.c_int]
     lib.csbq_stats.argtypes = [vp, C.c_char_p, C.c_int64]
     lib.csbq_synchronize.argtypes = [vp]
@@ -122,8 +124,11 @@ class Evaluator:
             raise CsbqError(f"{what} failed ({_STATUS.get(rc, rc)}): {msg}")
 
     def set_geometry(self, scene):
-        """Geometry from a scene (see ``synth.Scene``) or a dict of flat arrays."""
+        """Geometry from a scene (see ``synth.Scene``) or a dict of flat arrays.
+        A scene with ``body_group`` (see ``synth.merge_scenes``) is a batch of
+        independent geometries."""
         f = scene.flat() if hasattr(scene, "flat") else scene
+        bg = getattr(scene, "body_group", None) if hasattr(scene, "flat") else f.get("body_group")
         ns = getattr(scene, "ns", 16)
         nt = getattr(scene, "nt", 32)
         arrs = dict(n_panels=np.ascontiguousarray(f["n_panels"], np.int32),
@@ -132,10 +137,11 @@ class Evaluator:
                     xc=np.ascontiguousarray(f["xc"], np.float64),
                     eps=np.ascontiguousarray(f["eps"], np.float64),
                     e1=np.ascontiguousarray(f["e1"], np.float64))
-        rc = self._lib.csbq_set_geometry(self._h, int(f["n_bodies"]), _ptr(arrs["n_panels"]),
-                                         _ptr(arrs["normal_sign"]), _ptr(arrs["s_break"]), _ptr(arrs["xc"]),
-                                         _ptr(arrs["eps"]), _ptr(arrs["e1"]), ns, nt, CSBQ_HOST)
-        self._check(rc, "csbq_set_geometry")
+        bga = None if bg is None else np.ascontiguousarray(bg, np.int32)
+        rc = self._lib.csbq_set_geometry_batch(self._h, int(f["n_bodies"]), _ptr(bga), _ptr(arrs["n_panels"]),
+                                               _ptr(arrs["normal_sign"]), _ptr(arrs["s_break"]), _ptr(arrs["xc"]),
+                                               _ptr(arrs["eps"]), _ptr(arrs["e1"]), ns, nt, CSBQ_HOST)
+        self._check(rc, "csbq_set_geometry_batch")
         n = C.c_int64()
         self._check(self._lib.csbq_num_nodes(self._h, C.byref(n)), "csbq_num_nodes")
         self.n_nodes = n.value
@@ -147,7 +153,7 @@ class Evaluator:
         self._check(self._lib.csbq_get_nodes(self._h, _ptr(y), _ptr(nr), _ptr(w), CSBQ_HOST), "csbq_get_nodes")
         return y, nr, w
 
-    def _call(self, fn, name, sigma, x, tgt_node, out_sl, out_dl):
+    def _call(self, fn, name, sigma, x, tgt_node, out_sl, out_dl, tgt_group=None, batch=False):
         dev = _is_torch_cuda(sigma)
         if dev:
             import torch
@@ -156,10 +162,14 @@ class Evaluator:
                 out_sl = torch.empty((T, 3), dtype=torch.float64, device=sigma.device)
             if out_dl is None:
                 out_dl = torch.empty((T, 3), dtype=torch.float64, device=sigma.device)
-            for a in (sigma, x, tgt_node, out_sl, out_dl):
+            for a in (sigma, x, tgt_node, tgt_group, out_sl, out_dl):
                 if a is not None and not (_is_torch_cuda(a) and a.is_contiguous()):
                     raise CsbqError("device calls need contiguous CUDA tensors throughout")
-            rc = fn(self._h, _ptr(sigma), T, _ptr(x), _ptr(tgt_node), _ptr(out_sl), _ptr(out_dl), CSBQ_DEVICE)
+            if batch:
+                rc = fn(self._h, _ptr(sigma), T, _ptr(x), _ptr(tgt_node), _ptr(tgt_group), _ptr(out_sl),
+                        _ptr(out_dl), CSBQ_DEVICE)
+            else:
+                rc = fn(self._h, _ptr(sigma), T, _ptr(x), _ptr(tgt_node), _ptr(out_sl), _ptr(out_dl), CSBQ_DEVICE)
             self._check(rc, name)
             return out_sl, out_dl
         sigma = np.ascontiguousarray(sigma, np.float64)
@@ -167,15 +177,25 @@ class Evaluator:
             x = np.ascontiguousarray(x, np.float64).reshape(-1, 3)
         if tgt_node is not None:
             tgt_node = np.ascontiguousarray(tgt_node, np.int64)
+        if tgt_group is not None:
+            tgt_group = np.ascontiguousarray(tgt_group, np.int32)
         T = int(tgt_node.shape[0] if tgt_node is not None else x.shape[0])
         usl = np.zeros((T, 3))
         udl = np.zeros((T, 3))
-        rc = fn(self._h, _ptr(sigma), T, _ptr(x), _ptr(tgt_node), _ptr(usl), _ptr(udl), CSBQ_HOST)
+        if batch:
+            rc = fn(self._h, _ptr(sigma), T, _ptr(x), _ptr(tgt_node), _ptr(tgt_group), _ptr(usl), _ptr(udl),
+                    CSBQ_HOST)
+        else:
+            rc = fn(self._h, _ptr(sigma), T, _ptr(x), _ptr(tgt_node), _ptr(usl), _ptr(udl), CSBQ_HOST)
         self._check(rc, name)
         return usl, udl
 
-    def eval(self, sigma, x=None, tgt_node=None, out_sl=None, out_dl=None):
-        """(u_S, u_D) at the targets: the full evaluation."""
+    def eval(self, sigma, x=None, tgt_node=None, out_sl=None, out_dl=None, tgt_group=None):
+        """(u_S, u_D) at the targets: the full evaluation.  ``tgt_group`` names
+        the geometry of each free target of a batch (targets ordered by group)."""
+        if tgt_group is not None:
+            return self._call(self._lib.csbq_eval_batch, "csbq_eval_batch", sigma, x, tgt_node, out_sl, out_dl,
+                              tgt_group, batch=True)
         return self._call(self._lib.csbq_eval, "csbq_eval", sigma, x, tgt_node, out_sl, out_dl)
 
     def smooth_sum(self, sigma, x=None, tgt_node=None, out_sl=None, out_dl=None):

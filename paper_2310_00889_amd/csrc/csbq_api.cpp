@@ -43,6 +43,10 @@ struct DBuf {
         p = nullptr;
         n = 0;
     }
+    DBuf() = default;
+    DBuf(const DBuf&) = delete;
+    DBuf& operator=(const DBuf&) = delete;
+    ~DBuf() { release(); }
 };
 
 struct Phase {
@@ -161,7 +165,12 @@ struct csbq_ctx {
     int64_t N = 0;
     bool have_geom = false;
     DBuf<double> g_xc, g_eps, g_e1, g_sa, g_sc;
-    DBuf<int> g_sign, g_body;
+    DBuf<int> g_sign, g_body, g_group;
+    // batch of independent geometries: elements [h_gel[g], h_gel[g+1]) form group g
+    int G = 1;
+    std::vector<int> h_gel;
+    std::vector<int64_t> h_boff;
+    DBuf<int> gel;
     DBuf<double> clq, circ, ny, nn, nw;
     DBuf<ElemInfo> info;
     DBuf<double> cpy[NUP], cpn[NUP], cpw[NUP], Lup[NUP], upx[NUP], upw[NUP];
@@ -176,8 +185,15 @@ struct csbq_ctx {
     DBuf<int64_t> tn_d;
     DBuf<double> sw, sh, rnear, xt, part, cls, corr, swf[NUP];
     DBuf<int> band, cnt, pe, pt, err_d, work, kin, kout, vin, perm, sorted, runs_key, runs_cnt, nruns, wdesc[NUP];
-    DBuf<int64_t> off;
+    DBuf<int64_t> off, gstart;
+    DBuf<int> tgroup, tgrp_d, gnchunk;
+    DBuf<FarTile> tiles;
     DBuf<int8_t> tier;
+    // smooth-sum launch shape, chosen by timing (targets per thread, sources per chunk)
+    int far_tpt = 2;
+    int64_t far_chunk = 16384;
+    uint64_t tuned_key = 0;
+    float tune_ms[6] = {0, 0, 0, 0, 0, 0};
     DBuf<unsigned char> cub_tmp;
     // statistics of the last evaluation
     Phase ph[kNPhase];
@@ -481,6 +497,13 @@ int csbq_set_geometry(csbq_ctx* ctx, int32_t n_bodies, const int32_t* n_panels, 
                       const double* s_break, const double* xc, const double* eps, const double* e1, int32_t ns,
                       int32_t nt, int mem)
 {
+    return csbq_set_geometry_batch(ctx, n_bodies, nullptr, n_panels, normal_sign, s_break, xc, eps, e1, ns, nt, mem);
+}
+
+int csbq_set_geometry_batch(csbq_ctx* ctx, int32_t n_bodies, const int32_t* body_group, const int32_t* n_panels,
+                            const int32_t* normal_sign, const double* s_break, const double* xc, const double* eps,
+                            const double* e1, int32_t ns, int32_t nt, int mem)
+{
     if (!ctx) return CSBQ_EINVAL;
     ctx->err.clear();
     if (ns != NS || nt != NT) return ctx->fail(CSBQ_EINVAL, "this build supports ns=16, nt=32 only");
@@ -488,15 +511,23 @@ int csbq_set_geometry(csbq_ctx* ctx, int32_t n_bodies, const int32_t* n_panels, 
         return ctx->fail(CSBQ_EINVAL, "missing geometry arrays");
     if (mem != CSBQ_HOST && mem != CSBQ_DEVICE) return ctx->fail(CSBQ_EINVAL, "bad mem flag");
     HIPC(hipSetDevice(ctx->opt.device));
+    ctx->have_geom = false;
     // body tables are small: bring them to the host for validation
-    std::vector<int32_t> np(n_bodies), sg(n_bodies);
+    std::vector<int32_t> np(n_bodies), sg(n_bodies), bg(n_bodies, 0);
     if (mem == CSBQ_DEVICE) {
         HIPC(hipMemcpy(np.data(), n_panels, n_bodies * 4, hipMemcpyDeviceToHost));
         HIPC(hipMemcpy(sg.data(), normal_sign, n_bodies * 4, hipMemcpyDeviceToHost));
+        if (body_group) HIPC(hipMemcpy(bg.data(), body_group, n_bodies * 4, hipMemcpyDeviceToHost));
     } else {
         std::memcpy(np.data(), n_panels, n_bodies * 4);
         std::memcpy(sg.data(), normal_sign, n_bodies * 4);
+        if (body_group) std::memcpy(bg.data(), body_group, n_bodies * 4);
     }
+    if (bg[0] != 0) return ctx->fail(CSBQ_EINVAL, "body_group must start at 0");
+    for (int b = 1; b < n_bodies; ++b)
+        if (bg[b] != bg[b - 1] && bg[b] != bg[b - 1] + 1)
+            return ctx->fail(CSBQ_EINVAL, "body_group must be non-decreasing without gaps");
+    const int G = bg[n_bodies - 1] + 1;
     int64_t E = 0, nsb = 0;
     for (int b = 0; b < n_bodies; ++b) {
         if (np[b] < 1) return ctx->fail(CSBQ_EINVAL, "a body has no panel");
@@ -514,7 +545,7 @@ int csbq_set_geometry(csbq_ctx* ctx, int32_t n_bodies, const int32_t* n_panels, 
         std::memcpy(h_eps.data(), eps, h_eps.size() * 8);
     }
     std::vector<double> sa(E), sc(E);
-    std::vector<int> es(E), eb(E);
+    std::vector<int> es(E), eb(E), eg(E), gel(G + 1, 0);
     int64_t k = 0, o = 0;
     for (int b = 0; b < n_bodies; ++b) {
         for (int p = 0; p < np[b]; ++p, ++k) {
@@ -524,8 +555,10 @@ int csbq_set_geometry(csbq_ctx* ctx, int32_t n_bodies, const int32_t* n_panels, 
                 return ctx->fail(CSBQ_EINVAL, "panel end points must increase");
             es[k] = sg[b];
             eb[k] = b;
+            eg[k] = bg[b];
         }
         o += np[b] + 1;
+        gel[bg[b] + 1] = (int)k;
     }
     for (double v : h_eps)
         if (!(v > 0) || !std::isfinite(v)) return ctx->fail(CSBQ_EINVAL, "eps must be positive and finite");
@@ -540,6 +573,11 @@ int csbq_set_geometry(csbq_ctx* ctx, int32_t n_bodies, const int32_t* n_panels, 
     if ((rc = to_device(ctx, ctx->g_sc, sc.data(), (size_t)E, CSBQ_HOST))) return rc;
     if ((rc = to_device(ctx, ctx->g_sign, es.data(), (size_t)E, CSBQ_HOST))) return rc;
     if ((rc = to_device(ctx, ctx->g_body, eb.data(), (size_t)E, CSBQ_HOST))) return rc;
+    if ((rc = to_device(ctx, ctx->g_group, eg.data(), (size_t)E, CSBQ_HOST))) return rc;
+    if ((rc = to_device(ctx, ctx->gel, gel.data(), (size_t)G + 1, CSBQ_HOST))) return rc;
+    ctx->G = G;
+    ctx->h_gel = gel;
+    ctx->tuned_key = 0;
     ALLOC(ctx->clq, (size_t)E * CLQ * NS);
     ALLOC(ctx->circ, (size_t)E * NCIRC * CIRQ);
     ALLOC(ctx->info, (size_t)E);
@@ -547,7 +585,7 @@ int csbq_set_geometry(csbq_ctx* ctx, int32_t n_bodies, const int32_t* n_panels, 
     ALLOC(ctx->nn, (size_t)N * 3);
     ALLOC(ctx->nw, (size_t)N);
     LCHK(launch_expand(ctx->stream, (int)E, ctx->g_xc.p, ctx->g_eps.p, ctx->g_e1.p, ctx->g_sa.p, ctx->g_sc.p,
-                       ctx->g_sign.p, ctx->g_body.p, ctx->clq.p, ctx->circ.p, ctx->info.p, ctx->ny.p, ctx->nn.p,
+                       ctx->g_sign.p, ctx->g_body.p, ctx->g_group.p, ctx->clq.p, ctx->circ.p, ctx->info.p, ctx->ny.p, ctx->nn.p,
                        ctx->nw.p, N));
     // upsampled whole-panel rules (Gauss-Legendre of up_ns points in s times
     // up_nt angles) and the Lagrange matrices from the NS panel nodes to them
@@ -579,6 +617,7 @@ int csbq_set_geometry(csbq_ctx* ctx, int32_t n_bodies, const int32_t* n_panels, 
         std::vector<int64_t> bo((size_t)E + 1, 0);
         for (int64_t e = 0; e < E; ++e) bo[e + 1] = bo[e] + (hinf[e].fb == 2 ? up_pts(0) : NPE);
         ctx->Nb = bo[E];
+        ctx->h_boff = bo;
         ALLOC(ctx->boff, (size_t)E + 1);
         ALLOC(ctx->by, (size_t)ctx->Nb * 3);
         ALLOC(ctx->bn, (size_t)ctx->Nb * 3);
@@ -629,7 +668,7 @@ int csbq_get_nodes(csbq_ctx* ctx, double* y, double* normal, double* weight, int
 
 // common front part: inputs on the device, targets, density preparation
 static int eval_front(csbq_ctx* ctx, const double* sigma, int64_t T, const double* x, const int64_t* tgt_node,
-                      int mem, const double** sig_dev, const int64_t** tn_dev)
+                      const int32_t* tgt_group, int mem, const double** sig_dev, const int64_t** tn_dev)
 {
     if (!ctx->have_geom) return ctx->fail(CSBQ_ESTATE, "set_geometry must be called first");
     if (!sigma || T < 0) return ctx->fail(CSBQ_EINVAL, "missing density or negative target count");
@@ -662,6 +701,12 @@ static int eval_front(csbq_ctx* ctx, const double* sigma, int64_t T, const doubl
             if ((rc = to_device(ctx, ctx->tn_d, tgt_node, (size_t)T, CSBQ_HOST))) return rc;
             tgt_node = ctx->tn_d.p;
         }
+        if (tgt_group) {
+            for (int64_t t = 0; t < T; ++t)
+                if (tgt_group[t] < 0 || tgt_group[t] >= ctx->G) return ctx->fail(CSBQ_EINVAL, "tgt_group out of range");
+            if ((rc = to_device(ctx, ctx->tgrp_d, tgt_group, (size_t)T, CSBQ_HOST))) return rc;
+            tgt_group = ctx->tgrp_d.p;
+        }
     } else {
         *sig_dev = sigma;
     }
@@ -669,7 +714,10 @@ static int eval_front(csbq_ctx* ctx, const double* sigma, int64_t T, const doubl
     ALLOC(ctx->err_d, 1);
     HIPC(hipMemsetAsync(ctx->err_d.p, 0, sizeof(int), ctx->stream));
     ALLOC(ctx->xt, (size_t)T * 3 + 1);
-    LCHK(launch_targets(ctx->stream, T, x, tgt_node, ctx->ny.p, N, ctx->xt.p, ctx->err_d.p));
+    ALLOC(ctx->tgroup, (size_t)T + 1);
+    ALLOC(ctx->gstart, (size_t)ctx->G);
+    LCHK(launch_targets(ctx->stream, T, x, tgt_node, tgt_group, ctx->G, ctx->info.p, ctx->ny.p, N, ctx->xt.p,
+                        ctx->tgroup.p, ctx->gstart.p, ctx->err_d.p));
     const int E = ctx->E;
     ALLOC(ctx->sw, (size_t)N * 3);
     ALLOC(ctx->sh, (size_t)E * NS * NSH);
@@ -680,26 +728,145 @@ static int eval_front(csbq_ctx* ctx, const double* sigma, int64_t T, const doubl
     return CSBQ_OK;
 }
 
-// smooth sum over a source set: the element nodes (native) or the base set
-static int far_sum(csbq_ctx* ctx, int64_t T, bool native, int* nchunk_out)
+// Target range of every group, [tr[g], tr[g+1]), from the device's first-target
+// table (after a stream synchronisation); fails on unordered targets.
+static int group_ranges(csbq_ctx* ctx, int64_t T, int flags, std::vector<int64_t>& tr)
 {
+    if (flags & 8) return ctx->fail(CSBQ_EINVAL, "target group out of range");
+    if (flags & 16) return ctx->fail(CSBQ_EINVAL, "targets must be ordered by group");
+    const int G = ctx->G;
+    tr.assign((size_t)G + 1, 0);
+    tr[G] = T;
+    if (G == 1) return CSBQ_OK;
+    std::vector<int64_t> gs((size_t)G);
+    HIPC(hipMemcpy(gs.data(), ctx->gstart.p, (size_t)G * sizeof(int64_t), hipMemcpyDeviceToHost));
+    for (int g = G - 1; g >= 0; --g) tr[g] = gs[g] >= 0 ? gs[g] : tr[g + 1];
+    return CSBQ_OK;
+}
+
+// Smooth-sum blocks: per group, blocks of 256*tpt consecutive targets times
+// chunks of `chunk` sources, ordered by cost (largest first) so that one
+// launch drains a batch of unequal geometries evenly.
+static void far_tiles(const csbq_ctx* ctx, const std::vector<int64_t>& tr, bool native, int tpt, int64_t chunk,
+                      int g_only, int64_t t_cap, std::vector<FarTile>& tiles, std::vector<int>& gnc, int* maxchunk)
+{
+    const int G = ctx->G;
+    tiles.clear();
+    gnc.assign((size_t)G, 0);
+    *maxchunk = 0;
+    const int64_t tb = 256LL * tpt;
+    for (int g = 0; g < G; ++g) {
+        if (g_only >= 0 && g != g_only) continue;
+        const int64_t t0 = tr[g], tn = std::min(tr[g + 1] - tr[g], t_cap);
+        const int e0 = ctx->h_gel[g], e1 = ctx->h_gel[g + 1];
+        const int64_t s0 = native ? (int64_t)e0 * NPE : ctx->h_boff[e0];
+        const int64_t s1 = native ? (int64_t)e1 * NPE : ctx->h_boff[e1];
+        const int64_t S = s1 - s0;
+        const int nch = (int)((S + chunk - 1) / chunk);
+        gnc[g] = nch;
+        *maxchunk = std::max(*maxchunk, nch);
+        for (int64_t a = 0; a < tn; a += tb)
+            for (int c = 0; c < nch; ++c)
+                tiles.push_back(FarTile{t0 + a, s0 + c * chunk, (int32_t)std::min(tb, tn - a),
+                                        (int32_t)std::min(chunk, S - c * chunk), c, 0});
+    }
+    std::stable_sort(tiles.begin(), tiles.end(), [](const FarTile& a, const FarTile& b) {
+        return (int64_t)a.tn * a.sn > (int64_t)b.tn * b.sn;
+    });
+}
+
+// Launch shape of the smooth sum, chosen by timing: targets per thread 1/2/4
+// times 8192/32768 sources per chunk, each timed once on a sample of the
+// largest group (about 2e9 pairs at most); cached per (targets, sources,
+// precision).  Small sums keep the default shape.
+static int tune_far(csbq_ctx* ctx, int64_t T, const std::vector<int64_t>& tr, bool native, bool mixed)
+{
+    const uint64_t key = ((uint64_t)T * 1000003ULL) ^ ((uint64_t)(native ? ctx->N : ctx->Nb) << 20) ^
+                         ((uint64_t)ctx->G << 50) ^ (mixed ? 7ULL : 3ULL) ^ (native ? 11ULL : 0ULL);
+    if (ctx->tuned_key == key) return CSBQ_OK;
+    ctx->tuned_key = key;
+    int gbig = 0;
+    double pbig = -1, ptot = 0;
+    for (int g = 0; g < ctx->G; ++g) {
+        const int e0 = ctx->h_gel[g], e1 = ctx->h_gel[g + 1];
+        const double S = native ? (double)(e1 - e0) * NPE : (double)(ctx->h_boff[e1] - ctx->h_boff[e0]);
+        const double pr = S * (double)(tr[g + 1] - tr[g]);
+        ptot += pr;
+        if (pr > pbig) {
+            pbig = pr;
+            gbig = g;
+        }
+    }
+    ctx->far_tpt = 2;
+    ctx->far_chunk = 16384;
+    if (ptot < 2e8) return CSBQ_OK;
+    const int e0 = ctx->h_gel[gbig], e1 = ctx->h_gel[gbig + 1];
+    const int64_t S = native ? (int64_t)(e1 - e0) * NPE : ctx->h_boff[e1] - ctx->h_boff[e0];
+    const int64_t t_cap = std::max<int64_t>(4096, (int64_t)(2e9 / std::max<int64_t>(S, 1))) / 1024 * 1024;
+    const double* sy = native ? ctx->ny.p : ctx->by.p;
+    const double* sn = native ? ctx->nn.p : ctx->bn.p;
+    const double* ss = native ? ctx->sw.p : ctx->bsw.p;
+    const int64_t Ns = native ? ctx->N : ctx->Nb;
+    const int tpts[3] = {1, 2, 4};
+    const int64_t chunks[2] = {8192, 32768};
+    hipEvent_t a, b;
+    HIPC(hipEventCreate(&a));
+    HIPC(hipEventCreate(&b));
+    float best = 1e30f;
+    std::vector<FarTile> tl;
+    std::vector<int> gnc;
+    for (int pass = -1; pass < 6; ++pass) {
+        const int tpt = tpts[pass < 0 ? 1 : pass / 2];
+        const int64_t chunk = chunks[pass < 0 ? 0 : pass % 2];
+        int maxch = 0;
+        far_tiles(ctx, tr, native, tpt, chunk, gbig, t_cap, tl, gnc, &maxch);
+        ALLOC(ctx->tiles, tl.size() + 1);
+        HIPC(hipMemcpyAsync(ctx->tiles.p, tl.data(), tl.size() * sizeof(FarTile), hipMemcpyHostToDevice, ctx->stream));
+        ALLOC(ctx->part, (size_t)std::max(maxch, 1) * 6 * T + 1);
+        HIPC(hipEventRecord(a, ctx->stream));
+        LCHK(launch_far(ctx->stream, T, ctx->xt.p, sy, sn, ss, Ns, ctx->tiles.p, (int)tl.size(), ctx->part.p, mixed,
+                        ctx->mix_near2, tpt));
+        HIPC(hipEventRecord(b, ctx->stream));
+        HIPC(hipEventSynchronize(b));
+        float ms = 0.f;
+        HIPC(hipEventElapsedTime(&ms, a, b));
+        if (pass < 0) continue;   // warm-up of the code object
+        ctx->tune_ms[pass] = ms;
+        if (ms < best) {
+            best = ms;
+            ctx->far_tpt = tpt;
+            ctx->far_chunk = chunk;
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return CSBQ_OK;
+}
+
+// smooth sum over a source set: the element nodes (native) or the base set
+static int far_sum(csbq_ctx* ctx, int64_t T, bool native, const std::vector<int64_t>& tr)
+{
+    // the smooth sum over the element nodes (a diagnostic) stays FP64; the
+    // evaluation's far field follows the context's precision
+    const bool mixed = !native && ctx->opt.precision == CSBQ_MIXED;
+    int rc;
+    if ((rc = tune_far(ctx, T, tr, native, mixed))) return rc;
     const int64_t Ns = native ? ctx->N : ctx->Nb;
     const double* sy = native ? ctx->ny.p : ctx->by.p;
     const double* sn = native ? ctx->nn.p : ctx->bn.p;
     const double* ss = native ? ctx->sw.p : ctx->bsw.p;
-    int64_t tblocks = (T + 511) / 512;   // far kernel: 512 targets per block
-    int nchunk = (int)std::max<int64_t>(1, std::min<int64_t>((4096 + tblocks - 1) / std::max<int64_t>(tblocks, 1),
-                                                             (Ns + 4095) / 4096));
-    int64_t chunk = ((Ns + nchunk - 1) / nchunk + 255) / 256 * 256;
-    nchunk = (int)((Ns + chunk - 1) / chunk);
-    if (nchunk < 1) nchunk = 1;
-    ALLOC(ctx->part, (size_t)nchunk * 6 * T + 1);
-    // the smooth sum over the element nodes (a diagnostic) stays FP64; the
-    // evaluation's far field follows the context's precision
-    const bool mixed = !native && ctx->opt.precision == CSBQ_MIXED;
+    std::vector<FarTile> tl;
+    std::vector<int> gnc;
+    int maxch = 0;
+    far_tiles(ctx, tr, native, ctx->far_tpt, ctx->far_chunk, -1, INT64_MAX, tl, gnc, &maxch);
+    ALLOC(ctx->tiles, tl.size() + 1);
+    ALLOC(ctx->gnchunk, gnc.size());
+    HIPC(hipMemcpyAsync(ctx->tiles.p, tl.data(), tl.size() * sizeof(FarTile), hipMemcpyHostToDevice, ctx->stream));
+    HIPC(hipMemcpyAsync(ctx->gnchunk.p, gnc.data(), gnc.size() * sizeof(int), hipMemcpyHostToDevice, ctx->stream));
+    ALLOC(ctx->part, (size_t)std::max(maxch, 1) * 6 * T + 1);
     if (T > 0)
-        LCHK(launch_far(ctx->stream, T, ctx->xt.p, sy, sn, ss, Ns, chunk, nchunk, ctx->part.p, mixed, ctx->mix_near2));
-    *nchunk_out = nchunk;
+        LCHK(launch_far(ctx->stream, T, ctx->xt.p, sy, sn, ss, Ns, ctx->tiles.p, (int)tl.size(), ctx->part.p, mixed,
+                        ctx->mix_near2, ctx->far_tpt));
     return CSBQ_OK;
 }
 
@@ -740,19 +907,30 @@ int csbq_smooth_sum(csbq_ctx* ctx, const double* sigma, int64_t T, const double*
     HIPC(hipSetDevice(ctx->opt.device));
     const double* sig;
     const int64_t* tn;
-    int rc = eval_front(ctx, sigma, T, x, tgt_node, mem, &sig, &tn);
+    int rc = eval_front(ctx, sigma, T, x, tgt_node, nullptr, mem, &sig, &tn);
     if (rc) return rc;
     if (T == 0) return finish(ctx, 0, u_sl, u_dl, mem);
-    int nchunk = 1;
-    if ((rc = far_sum(ctx, T, true, &nchunk))) return rc;
+    int flags = 0;
+    HIPC(hipMemcpyAsync(&flags, ctx->err_d.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIPC(hipStreamSynchronize(ctx->stream));
+    std::vector<int64_t> tr;
+    if ((rc = group_ranges(ctx, T, flags, tr))) return rc;
+    if ((rc = far_sum(ctx, T, true, tr))) return rc;
     double *usl, *udl;
     if ((rc = outputs_back(ctx, T, u_sl, u_dl, mem, &usl, &udl))) return rc;
-    if (T > 0) LCHK(launch_reduce(ctx->stream, T, nchunk, ctx->part.p, nullptr, nullptr, nullptr, usl, udl));
+    LCHK(launch_reduce(ctx->stream, T, ctx->tgroup.p, ctx->gnchunk.p, ctx->part.p, nullptr, nullptr, nullptr, usl,
+                       udl));
     return finish(ctx, T, u_sl, u_dl, mem);
 }
 
 int csbq_eval(csbq_ctx* ctx, const double* sigma, int64_t T, const double* x, const int64_t* tgt_node, double* u_sl,
               double* u_dl, int mem)
+{
+    return csbq_eval_batch(ctx, sigma, T, x, tgt_node, nullptr, u_sl, u_dl, mem);
+}
+
+int csbq_eval_batch(csbq_ctx* ctx, const double* sigma, int64_t T, const double* x, const int64_t* tgt_node,
+                    const int32_t* tgt_group, double* u_sl, double* u_dl, int mem)
 {
     if (!ctx) return CSBQ_EINVAL;
     ctx->err.clear();
@@ -762,51 +940,53 @@ int csbq_eval(csbq_ctx* ctx, const double* sigma, int64_t T, const double* x, co
     const double* sig;
     const int64_t* tn;
     HIPC(hipEventRecord(ctx->ph[0].a, st));
-    int rc = eval_front(ctx, sigma, T, x, tgt_node, mem, &sig, &tn);
+    int rc = eval_front(ctx, sigma, T, x, tgt_node, tgt_group, mem, &sig, &tn);
     if (rc) return rc;
     if (T == 0) return finish(ctx, 0, u_sl, u_dl, mem);
     HIPC(hipEventRecord(ctx->ph[0].b, st));
     const int E = ctx->E;
     const int64_t N = ctx->N;
-    // density on the tier-0 rule and the base source set, then the smooth
-    // sum over every base source
-    HIPC(hipEventRecord(ctx->ph[1].a, st));
+    // density on the tier-0 rule and the base source set
     ALLOC(ctx->swf[0], (size_t)ctx->Mtot[0] * 3);
     LCHK(launch_sigma_up(st, E, up_ns(0), up_nt(0), ctx->sh.p, ctx->Lup[0].p, ctx->cpw[0].p, ctx->swf[0].p,
                          ctx->Mtot[0]));
     ALLOC(ctx->bsw, (size_t)ctx->Nb * 3);
     LCHK(launch_sigma_base(st, E, ctx->info.p, ctx->boff.p, ctx->sw.p, N, ctx->swf[0].p, ctx->Mtot[0], ctx->bsw.p,
                            ctx->Nb));
-    int nchunk = 1;
-    if ((rc = far_sum(ctx, T, false, &nchunk))) return rc;
-    HIPC(hipEventRecord(ctx->ph[1].b, st));
-    // candidate pairs: count, scan, fill
+    // candidate pairs: count, scan (the fill follows the synchronisation)
     HIPC(hipEventRecord(ctx->ph[2].a, st));
     ALLOC(ctx->cnt, (size_t)T + 1);
     ALLOC(ctx->off, (size_t)T + 1);
     HIPC(hipMemsetAsync(ctx->cnt.p, 0, ((size_t)T + 1) * sizeof(int), st));
-    if (T > 0)
-        LCHK(launch_search(st, T, E, ctx->xt.p, tn, ctx->info.p, ctx->rnear.p, nullptr, ctx->cnt.p, nullptr, nullptr));
+    LCHK(launch_search(st, T, ctx->tgroup.p, ctx->gel.p, ctx->xt.p, tn, ctx->info.p, ctx->rnear.p, nullptr,
+                       ctx->cnt.p, nullptr, nullptr));
     size_t tmpb = 0;
     HIPC(hipcub::DeviceScan::ExclusiveSum(nullptr, tmpb, ctx->cnt.p, ctx->off.p, (int)(T + 1), st));
     ALLOC(ctx->cub_tmp, tmpb);
     HIPC(hipcub::DeviceScan::ExclusiveSum(ctx->cub_tmp.p, tmpb, ctx->cnt.p, ctx->off.p, (int)(T + 1), st));
     int64_t P = 0;
+    int flags = 0;
     HIPC(hipMemcpyAsync(&P, ctx->off.p + T, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIPC(hipMemcpyAsync(&flags, ctx->err_d.p, sizeof(int), hipMemcpyDeviceToHost, st));
     std::vector<int> hband((size_t)2 * E);
     HIPC(hipMemcpyAsync(hband.data(), ctx->band.p, hband.size() * sizeof(int), hipMemcpyDeviceToHost, st));
     HIPC(hipStreamSynchronize(st));
     int mt_max = 0;
     for (int k = 0; k < E; ++k) mt_max = std::max(mt_max, hband[2 * k + 1]);
+    std::vector<int64_t> tr;
+    if ((rc = group_ranges(ctx, T, flags, tr))) return rc;
     ALLOC(ctx->pe, (size_t)P + 1);
     ALLOC(ctx->pt, (size_t)P + 1);
     ALLOC(ctx->tier, (size_t)P + 1);
     ALLOC(ctx->cls, (size_t)P * 4 + 1);
     ALLOC(ctx->corr, (size_t)P * 6 + 1);
-    if (T > 0)
-        LCHK(launch_search(st, T, E, ctx->xt.p, tn, ctx->info.p, ctx->rnear.p, ctx->off.p, nullptr, ctx->pe.p,
-                           ctx->pt.p));
+    LCHK(launch_search(st, T, ctx->tgroup.p, ctx->gel.p, ctx->xt.p, tn, ctx->info.p, ctx->rnear.p, ctx->off.p,
+                       nullptr, ctx->pe.p, ctx->pt.p));
     HIPC(hipEventRecord(ctx->ph[2].b, st));
+    // the smooth sum over every base source of the target's group
+    HIPC(hipEventRecord(ctx->ph[1].a, st));
+    if ((rc = far_sum(ctx, T, false, tr))) return rc;
+    HIPC(hipEventRecord(ctx->ph[1].b, st));
     // classification into correction tiers, in element-major order
     HIPC(hipEventRecord(ctx->ph[3].a, st));
     int ebits = 1;
@@ -868,9 +1048,9 @@ int csbq_eval(csbq_ctx* ctx, const double* sigma, int64_t T, const double* x, co
         for (int r = 0; r < nr; ++r) {
             int trr = rkey[r] / E, e = rkey[r] % E, c = rcnt[r];
             if (trr >= 1 && trr <= NUP) {
-                for (int o = 0; o < c; o += 64) {
+                for (int o = 0; o < c; o += UP_PAIRS) {
                     wd[trr - 1].push_back(pos + o);
-                    wd[trr - 1].push_back(std::min(64, c - o));
+                    wd[trr - 1].push_back(std::min(UP_PAIRS, c - o));
                     wd[trr - 1].push_back(e);
                 }
                 npair[trr - 1] += c;
@@ -915,7 +1095,8 @@ int csbq_eval(csbq_ctx* ctx, const double* sigma, int64_t T, const double* x, co
     HIPC(hipEventRecord(ctx->ph[7].a, st));
     double *usl, *udl;
     if ((rc = outputs_back(ctx, T, u_sl, u_dl, mem, &usl, &udl))) return rc;
-    if (T > 0) LCHK(launch_reduce(st, T, nchunk, ctx->part.p, ctx->off.p, ctx->tier.p, ctx->corr.p, usl, udl));
+    LCHK(launch_reduce(st, T, ctx->tgroup.p, ctx->gnchunk.p, ctx->part.p, ctx->off.p, ctx->tier.p, ctx->corr.p, usl,
+                       udl));
     HIPC(hipEventRecord(ctx->ph[7].b, st));
     ctx->last_T = T;
     ctx->last_P = P;

@@ -28,6 +28,8 @@ enum { Q_X = 0, Q_XP = 3, Q_XPP = 6, Q_E = 9, Q_EP = 10, Q_F = 11, Q_FP = 14 };
 // angles), and the special quadrature
 enum : int8_t { TIER_SKIP = 0, TIER_UP1 = 1, TIER_UP2 = 2, TIER_UP3 = 3, TIER_FULL = 4 };
 constexpr int NUP = 3;
+constexpr int UP_TPT = 2;              // pairs per lane of the upsampled-rule corrections
+constexpr int UP_PAIRS = 64 * UP_TPT;  // pairs per wavefront (one element)
 constexpr int MAXUPNS = 64;
 __host__ __device__ constexpr int up_ns(int k) { return k == 2 ? 64 : 32; }
 __host__ __device__ constexpr int up_nt(int k) { return k == 0 ? 32 : (k == 1 ? 64 : 128); }
@@ -45,6 +47,15 @@ struct ElemInfo {
     int32_t sign;      // normal orientation
     int32_t body;
     int32_t fb;        // far-field (base) rule: 1 = the element's own nodes, 2 = up_ns(0) x NT rule
+    int32_t group;     // geometry of a batch: elements of different groups do not interact
+};
+
+// one block of the smooth sum: up to 256 x (targets per thread) consecutive
+// targets of one group against a chunk of that group's sources
+struct FarTile {
+    int64_t t0, s0;    // first target, first source
+    int32_t tn, sn;    // counts
+    int32_t chunk;     // partial-sum slot
     int32_t pad_;
 };
 

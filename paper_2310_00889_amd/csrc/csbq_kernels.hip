@@ -164,7 +164,7 @@ __device__ inline void circle_dist(const double* X, const double* t, double E, c
 __global__ __launch_bounds__(512) void k_expand(int E, const double* __restrict__ xc, const double* __restrict__ eps,
                                                 const double* __restrict__ e1, const double* __restrict__ sa,
                                                 const double* __restrict__ sc, const int* __restrict__ esign,
-                                                const int* __restrict__ ebody, double* __restrict__ clq,
+                                                const int* __restrict__ ebody, const int* __restrict__ egroup, double* __restrict__ clq,
                                                 double* __restrict__ circ, ElemInfo* __restrict__ info,
                                                 double* __restrict__ ny, double* __restrict__ nn,
                                                 double* __restrict__ nw, int64_t N)
@@ -294,7 +294,7 @@ __global__ __launch_bounds__(512) void k_expand(int E, const double* __restrict_
         const double* cp0 = circ + (int64_t)e * NCIRC * CIRQ;
         const double eend = fmin(fabs(cp0[6]), fabs(cp0[(NCIRC - 1) * CIRQ + 6]));
         inf.fb = (eend < 1e-3 * outv[1]) ? 2 : 1;
-        inf.pad_ = 0;
+        inf.group = egroup[e];
         info[e] = inf;
     }
 }
@@ -497,9 +497,12 @@ __global__ void k_sigma_base(int E, const ElemInfo* __restrict__ info, const int
 // ---------------------------------------------------------------------------
 // targets
 // ---------------------------------------------------------------------------
+// Target coordinates (node position for an on-surface target) and group: the
+// node's element group, else the caller's group (0 without a list).
 __global__ void k_targets(int64_t T, const double* __restrict__ x, const int64_t* __restrict__ tnode,
+                          const int* __restrict__ tgrp_in, int G, const ElemInfo* __restrict__ info,
                           const double* __restrict__ ny, int64_t N, double* __restrict__ xt,
-                          int* __restrict__ err)
+                          int* __restrict__ tgroup, int* __restrict__ err)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= T) return;
@@ -512,38 +515,62 @@ __global__ void k_targets(int64_t T, const double* __restrict__ x, const int64_t
         double v = (nd >= 0) ? ny[d * N + nd] : (x ? x[t * 3 + d] : 0.0);
         xt[d * T + t] = v;
     }
+    int g = (nd >= 0) ? info[nd / NPE].group : (tgrp_in ? tgrp_in[t] : 0);
+    if (g < 0 || g >= G) {
+        atomicOr(err, 8);
+        g = 0;
+    }
+    tgroup[t] = g;
+}
+
+// first target of every group (gstart preset to -1); flags targets that are
+// not ordered by group
+__global__ void k_group_bounds(int64_t T, const int* __restrict__ tgroup, int64_t* __restrict__ gstart,
+                               int* __restrict__ err)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T) return;
+    const int g = tgroup[t];
+    if (t == 0 || tgroup[t - 1] != g) gstart[g] = t;
+    if (t > 0 && tgroup[t - 1] > g) atomicOr(err, 16);
+}
+
+__global__ void k_fill_i64(int64_t n, int64_t* __restrict__ v, int64_t val)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) v[i] = val;
 }
 
 // ---------------------------------------------------------------------------
 // smooth Nystrom sum (Section 3.2.1): targets x sources, sources staged in LDS
 // ---------------------------------------------------------------------------
-constexpr int FAR_BLOCK = 256;
-constexpr int FAR_TPT = 2;      // targets per thread
 constexpr int FAR_REC = 10;     // LDS record of a source: y(3) n(3) sigma*w(3), padded to 16-byte pairs
 
-// Each thread owns FAR_TPT targets; a block streams its source chunk through
-// LDS in tiles of FAR_BLOCK sources (one record each, read as five 16-byte
-// broadcasts), so every LDS read serves FAR_TPT pairs.
+// Each thread owns TPT targets; a block streams its source chunk through LDS
+// in tiles of FAR_BLOCK sources (one record each, read as five 16-byte
+// broadcasts), so every LDS read serves TPT pairs.
+template <int TPT>
 __global__ __launch_bounds__(FAR_BLOCK) void k_far(int64_t T, const double* __restrict__ xt,
                                                    const double* __restrict__ sy, const double* __restrict__ sn,
-                                                   const double* __restrict__ ssw, int64_t N, int64_t chunk,
-                                                   double* __restrict__ part)
+                                                   const double* __restrict__ ssw, int64_t N,
+                                                   const FarTile* __restrict__ tiles, double* __restrict__ part)
 {
     __shared__ __attribute__((aligned(16))) double src[FAR_BLOCK * FAR_REC];
     const int tid = threadIdx.x;
-    const int64_t tb = (int64_t)blockIdx.x * (FAR_BLOCK * FAR_TPT) + tid;
-    double x[FAR_TPT][3], us[FAR_TPT][3], ud[FAR_TPT][3];
+    const FarTile tl = tiles[blockIdx.x];
+    const int64_t tb = tl.t0 + tid, tend = tl.t0 + tl.tn;
+    double x[TPT][3], us[TPT][3], ud[TPT][3];
 #pragma unroll
-    for (int u = 0; u < FAR_TPT; ++u) {
+    for (int u = 0; u < TPT; ++u) {
         const int64_t t = tb + u * FAR_BLOCK;
-        const bool ok = t < T;
+        const bool ok = t < tend;
         x[u][0] = ok ? xt[t] : 0.0;
         x[u][1] = ok ? xt[T + t] : 0.0;
         x[u][2] = ok ? xt[2 * T + t] : 0.0;
         for (int d = 0; d < 3; ++d) us[u][d] = ud[u][d] = 0.0;
     }
-    const int64_t c0 = (int64_t)blockIdx.y * chunk;
-    const int64_t c1 = min(N, c0 + chunk);
+    const int64_t c0 = tl.s0;
+    const int64_t c1 = tl.s0 + tl.sn;
     for (int64_t base = c0; base < c1; base += FAR_BLOCK) {
         const int64_t k = base + tid;
         if (k < c1) {
@@ -567,7 +594,7 @@ __global__ __launch_bounds__(FAR_BLOCK) void k_far(int64_t T, const double* __re
             const double2 A = r2[0], B = r2[1], C = r2[2], D = r2[3], F = r2[4];
             // A = (y0, y1), B = (y2, n0), C = (n1, n2), D = (w0, w1), F = (w2, -)
 #pragma unroll
-            for (int u = 0; u < FAR_TPT; ++u) {
+            for (int u = 0; u < TPT; ++u) {
                 const double r0 = x[u][0] - A.x, r1 = x[u][1] - A.y, r2_ = x[u][2] - B.x;
                 const double rr = fma(r0, r0, fma(r1, r1, r2_ * r2_));
                 // evaluated unconditionally (a coincident node gives inf/NaN
@@ -589,11 +616,11 @@ __global__ __launch_bounds__(FAR_BLOCK) void k_far(int64_t T, const double* __re
         }
         __syncthreads();
     }
-    double* p = part + (int64_t)blockIdx.y * 6 * T;
+    double* p = part + (int64_t)tl.chunk * 6 * T;
 #pragma unroll
-    for (int u = 0; u < FAR_TPT; ++u) {
+    for (int u = 0; u < TPT; ++u) {
         const int64_t t = tb + u * FAR_BLOCK;
-        if (t < T) {
+        if (t < tend) {
             p[0 * T + t] = us[u][0];
             p[1 * T + t] = us[u][1];
             p[2 * T + t] = us[u][2];
@@ -647,22 +674,25 @@ __device__ inline void block_box(double* lo, double* hi, double* red /*[2][3][FA
     __syncthreads();
 }
 
+template <int TPT>
 __global__ __launch_bounds__(FAR_BLOCK) void k_far_mx(int64_t T, const double* __restrict__ xt,
                                                       const double* __restrict__ sy, const double* __restrict__ sn,
-                                                      const double* __restrict__ ssw, int64_t N, int64_t chunk,
-                                                      double near2, double* __restrict__ part)
+                                                      const double* __restrict__ ssw, int64_t N,
+                                                      const FarTile* __restrict__ tiles, double near2,
+                                                      double* __restrict__ part)
 {
     __shared__ FarRecMx src[FAR_BLOCK];
     __shared__ double red[6 * (FAR_BLOCK / 64)];
     const int tid = threadIdx.x;
-    const int64_t tb = (int64_t)blockIdx.x * (FAR_BLOCK * FAR_TPT) + tid;
+    const FarTile tl = tiles[blockIdx.x];
+    const int64_t tb = tl.t0 + tid, tend = tl.t0 + tl.tn;
     const float near2f = (float)near2;
-    double x[FAR_TPT][3], us[FAR_TPT][3], ud[FAR_TPT][3];
+    double x[TPT][3], us[TPT][3], ud[TPT][3];
     double tlo[3] = {INFINITY, INFINITY, INFINITY}, thi[3] = {-INFINITY, -INFINITY, -INFINITY};
 #pragma unroll
-    for (int u = 0; u < FAR_TPT; ++u) {
+    for (int u = 0; u < TPT; ++u) {
         const int64_t t = tb + u * FAR_BLOCK;
-        const bool ok = t < T;
+        const bool ok = t < tend;
         x[u][0] = ok ? xt[t] : 0.0;
         x[u][1] = ok ? xt[T + t] : 0.0;
         x[u][2] = ok ? xt[2 * T + t] : 0.0;
@@ -675,8 +705,8 @@ __global__ __launch_bounds__(FAR_BLOCK) void k_far_mx(int64_t T, const double* _
         }
     }
     block_box(tlo, thi, red);
-    const int64_t c0 = (int64_t)blockIdx.y * chunk;
-    const int64_t c1 = min(N, c0 + chunk);
+    const int64_t c0 = tl.s0;
+    const int64_t c1 = tl.s0 + tl.sn;
     for (int64_t base = c0; base < c1; base += FAR_BLOCK) {
         const int64_t k = base + tid;
         double slo[3] = {INFINITY, INFINITY, INFINITY}, shi[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -708,9 +738,9 @@ __global__ __launch_bounds__(FAR_BLOCK) void k_far_mx(int64_t T, const double* _
         }
         const bool near_tile = !(gap2 >= near2 && gap2 > 0.0);   // uniform over the block
         const int nin = (int)min((int64_t)FAR_BLOCK, c1 - base);
-        float fs[FAR_TPT][3], fd[FAR_TPT][3];
+        float fs[TPT][3], fd[TPT][3];
 #pragma unroll
-        for (int u = 0; u < FAR_TPT; ++u)
+        for (int u = 0; u < TPT; ++u)
             for (int d = 0; d < 3; ++d) fs[u][d] = fd[u][d] = 0.0f;
         if (!near_tile) {
 #pragma unroll 2
@@ -719,7 +749,7 @@ __global__ __launch_bounds__(FAR_BLOCK) void k_far_mx(int64_t T, const double* _
                 const double y0 = R.y0, y1 = R.y1, y2 = R.y2;
                 const float n0 = R.n0, n1 = R.n1, n2 = R.n2, w0 = R.w0, w1 = R.w1, w2 = R.w2;
 #pragma unroll
-                for (int u = 0; u < FAR_TPT; ++u) {
+                for (int u = 0; u < TPT; ++u) {
                     const float r0 = (float)(x[u][0] - y0), r1 = (float)(x[u][1] - y1), r2 = (float)(x[u][2] - y2);
                     const float rr = fmaf(r0, r0, fmaf(r1, r1, r2 * r2));
                     const float ir = __builtin_amdgcn_rsqf(rr);   // rr > 0: the tile is away from every target
@@ -740,7 +770,7 @@ __global__ __launch_bounds__(FAR_BLOCK) void k_far_mx(int64_t T, const double* _
             for (int kk = 0; kk < nin; ++kk) {
                 const FarRecMx& R = src[kk];
 #pragma unroll
-                for (int u = 0; u < FAR_TPT; ++u) {
+                for (int u = 0; u < TPT; ++u) {
                     const double d0 = x[u][0] - R.y0, d1 = x[u][1] - R.y1, d2 = x[u][2] - R.y2;
                     const float r0 = (float)d0, r1 = (float)d1, r2 = (float)d2;
                     const float rr = fmaf(r0, r0, fmaf(r1, r1, r2 * r2));
@@ -777,18 +807,18 @@ __global__ __launch_bounds__(FAR_BLOCK) void k_far_mx(int64_t T, const double* _
             }
         }
 #pragma unroll
-        for (int u = 0; u < FAR_TPT; ++u)
+        for (int u = 0; u < TPT; ++u)
             for (int d = 0; d < 3; ++d) {
                 us[u][d] += (double)fs[u][d];
                 ud[u][d] += (double)fd[u][d];
             }
         __syncthreads();
     }
-    double* p = part + (int64_t)blockIdx.y * 6 * T;
+    double* p = part + (int64_t)tl.chunk * 6 * T;
 #pragma unroll
-    for (int u = 0; u < FAR_TPT; ++u) {
+    for (int u = 0; u < TPT; ++u) {
         const int64_t t = tb + u * FAR_BLOCK;
-        if (t < T) {
+        if (t < tend) {
             p[0 * T + t] = us[u][0];
             p[1 * T + t] = us[u][1];
             p[2 * T + t] = us[u][2];
@@ -802,7 +832,8 @@ __global__ __launch_bounds__(FAR_BLOCK) void k_far_mx(int64_t T, const double* _
 // ---------------------------------------------------------------------------
 // near-pair search (candidates) and classification
 // ---------------------------------------------------------------------------
-__global__ void k_search(int64_t T, int E, const double* __restrict__ xt, const int64_t* __restrict__ tnode,
+__global__ void k_search(int64_t T, const int* __restrict__ tgroup, const int* __restrict__ gel,
+                         const double* __restrict__ xt, const int64_t* __restrict__ tnode,
                          const ElemInfo* __restrict__ info, const double* __restrict__ rnear,
                          const int64_t* __restrict__ off, int* __restrict__ cnt, int* __restrict__ pe,
                          int* __restrict__ pt)
@@ -813,7 +844,8 @@ __global__ void k_search(int64_t T, int E, const double* __restrict__ xt, const 
     int own = (tnode && tnode[t] >= 0) ? (int)(tnode[t] / NPE) : -1;
     int n = 0;
     int64_t o = off ? off[t] : 0;
-    for (int e = 0; e < E; ++e) {
+    const int g = tgroup[t];
+    for (int e = gel[g]; e < gel[g + 1]; ++e) {
         const ElemInfo& inf = info[e];
         double dx = x[0] - inf.cen[0], dy = x[1] - inf.cen[1], dz = x[2] - inf.cen[2];
         double R = inf.rad + rnear[e];
@@ -1132,20 +1164,26 @@ __global__ __launch_bounds__(64) void k_corr_up(int64_t Mf, const int* __restric
                                                 const double* __restrict__ bn, const double* __restrict__ bsw,
                                                 int64_t Nb, double* __restrict__ corr)
 {
-    __shared__ double ly[3][64], ln_[3][64], ls[3][64];
+    // one wavefront per run of up to UP_PAIRS pairs of one element, UP_TPT
+    // pairs per lane; rule points staged through LDS as 16-byte-pair records
+    __shared__ __attribute__((aligned(16))) double src[64 * FAR_REC];
     const int w = blockIdx.x, lane = threadIdx.x;
     const int e = ws[3 * w + 2];
-    const int64_t p = (lane < ws[3 * w + 1]) ? (int64_t)sorted[(int64_t)ws[3 * w] + lane] : -1;
-    double x0 = 0, x1 = 0, x2 = 0;
-    if (p >= 0) {
-        int64_t t = pt[p];
-        x0 = xt[t];
-        x1 = xt[T + t];
-        x2 = xt[2 * T + t];
+    int64_t p[UP_TPT];
+    double x[UP_TPT][3], us[UP_TPT][3], ud[UP_TPT][3];
+#pragma unroll
+    for (int u = 0; u < UP_TPT; ++u) {
+        const int k = lane + 64 * u;
+        p[u] = (k < ws[3 * w + 1]) ? (int64_t)sorted[(int64_t)ws[3 * w] + k] : -1;
+        const int64_t t = p[u] >= 0 ? pt[p[u]] : -1;
+        x[u][0] = t >= 0 ? xt[t] : 0.0;
+        x[u][1] = t >= 0 ? xt[T + t] : 0.0;
+        x[u][2] = t >= 0 ? xt[2 * T + t] : 0.0;
+        for (int d = 0; d < 3; ++d) us[u][d] = ud[u][d] = 0.0;
     }
-    double s0 = 0, s1 = 0, s2 = 0, d0 = 0, d1 = 0, d2 = 0;
     const int64_t nbase = boff[e + 1] - boff[e];
     for (int pass = 0; pass < 2; ++pass) {
+        // pass 0: the upsampled rule; pass 1: minus the element's far-field rule
         const double* py = pass ? by : cpy;
         const double* pn = pass ? bn : cpn;
         const double* psw = pass ? bsw : swf;
@@ -1154,48 +1192,59 @@ __global__ __launch_bounds__(64) void k_corr_up(int64_t Mf, const int* __restric
         const int64_t cnt = pass ? nbase : Mf;
         const double sg = pass ? -1.0 : 1.0;
         for (int64_t base = 0; base < cnt; base += 64) {
-            int64_t m = base0 + base + lane;
-            bool in = base + lane < cnt;
-            ly[0][lane] = in ? py[m] : 0.0;
-            ly[1][lane] = in ? py[ld + m] : 0.0;
-            ly[2][lane] = in ? py[2 * ld + m] : 0.0;
-            ln_[0][lane] = in ? pn[m] : 0.0;
-            ln_[1][lane] = in ? pn[ld + m] : 0.0;
-            ln_[2][lane] = in ? pn[2 * ld + m] : 0.0;
-            ls[0][lane] = in ? sg * psw[m] : 0.0;
-            ls[1][lane] = in ? sg * psw[ld + m] : 0.0;
-            ls[2][lane] = in ? sg * psw[2 * ld + m] : 0.0;
+            const int64_t m = base0 + base + lane;
+            if (base + lane < cnt) {
+                double* r = src + lane * FAR_REC;
+                r[0] = py[m];
+                r[1] = py[ld + m];
+                r[2] = py[2 * ld + m];
+                r[3] = pn[m];
+                r[4] = pn[ld + m];
+                r[5] = pn[2 * ld + m];
+                r[6] = sg * psw[m];
+                r[7] = sg * psw[ld + m];
+                r[8] = sg * psw[2 * ld + m];
+                r[9] = 0.0;
+            }
             __syncthreads();
             const int nin = (int)min((int64_t)64, cnt - base);
-#pragma unroll 4
+#pragma unroll 2
             for (int kk = 0; kk < nin; ++kk) {
-                double r0 = x0 - ly[0][kk], r1 = x1 - ly[1][kk], r2 = x2 - ly[2][kk];
-                double rr = fma(r0, r0, fma(r1, r1, r2 * r2));
-                double ir = rr > 0.0 ? rsqrt_nr(rr) : 0.0;
-                double w0 = ls[0][kk], w1 = ls[1][kk], w2 = ls[2][kk];
-                double rs = fma(r0, w0, fma(r1, w1, r2 * w2));
-                double rn = fma(r0, ln_[0][kk], fma(r1, ln_[1][kk], r2 * ln_[2][kk]));
-                double ir2 = ir * ir;
-                double b = rs * ir * ir2;
-                double cD = rn * rs * ir2 * ir2 * ir;
-                s0 = fma(ir, w0, fma(b, r0, s0));
-                s1 = fma(ir, w1, fma(b, r1, s1));
-                s2 = fma(ir, w2, fma(b, r2, s2));
-                d0 = fma(cD, r0, d0);
-                d1 = fma(cD, r1, d1);
-                d2 = fma(cD, r2, d2);
+                const double2* r2 = reinterpret_cast<const double2*>(src + kk * FAR_REC);
+                const double2 A = r2[0], B = r2[1], C = r2[2], D = r2[3], F = r2[4];
+#pragma unroll
+                for (int u = 0; u < UP_TPT; ++u) {
+                    const double r0 = x[u][0] - A.x, r1 = x[u][1] - A.y, r2_ = x[u][2] - B.x;
+                    const double rr = fma(r0, r0, fma(r1, r1, r2_ * r2_));
+                    const double irn = rsqrt_nr(rr);
+                    const double ir = rr > 0.0 ? irn : 0.0;
+                    const double rs = fma(r0, D.x, fma(r1, D.y, r2_ * F.x));
+                    const double rn = fma(r0, B.y, fma(r1, C.x, r2_ * C.y));
+                    const double ir2 = ir * ir;
+                    const double b = rs * (ir * ir2);
+                    const double cD = (rn * b) * ir2;
+                    us[u][0] = fma(ir, D.x, fma(b, r0, us[u][0]));
+                    us[u][1] = fma(ir, D.y, fma(b, r1, us[u][1]));
+                    us[u][2] = fma(ir, F.x, fma(b, r2_, us[u][2]));
+                    ud[u][0] = fma(cD, r0, ud[u][0]);
+                    ud[u][1] = fma(cD, r1, ud[u][1]);
+                    ud[u][2] = fma(cD, r2_, ud[u][2]);
+                }
             }
             __syncthreads();
         }
     }
-    if (p >= 0) {
-        double* o = corr + p * 6;
-        o[0] = s0;
-        o[1] = s1;
-        o[2] = s2;
-        o[3] = d0;
-        o[4] = d1;
-        o[5] = d2;
+#pragma unroll
+    for (int u = 0; u < UP_TPT; ++u) {
+        if (p[u] >= 0) {
+            double* o = corr + p[u] * 6;
+            o[0] = us[u][0];
+            o[1] = us[u][1];
+            o[2] = us[u][2];
+            o[3] = ud[u][0];
+            o[4] = ud[u][1];
+            o[5] = ud[u][2];
+        }
     }
 }
 
@@ -1600,13 +1649,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
 // ---------------------------------------------------------------------------
 // final reduction: far chunks in order, then the pair corrections in CSR order
 // ---------------------------------------------------------------------------
-__global__ void k_reduce(int64_t T, int nchunk, const double* __restrict__ part, const int64_t* __restrict__ off,
+__global__ void k_reduce(int64_t T, const int* __restrict__ tgroup, const int* __restrict__ gnchunk,
+                         const double* __restrict__ part, const int64_t* __restrict__ off,
                          const int8_t* __restrict__ tier, const double* __restrict__ corr,
                          double* __restrict__ usl, double* __restrict__ udl)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= T) return;
     double u[6] = {0, 0, 0, 0, 0, 0};
+    const int nchunk = gnchunk[tgroup[t]];
     for (int c = 0; c < nchunk; ++c)
         for (int k = 0; k < 6; ++k) u[k] += part[((int64_t)c * 6 + k) * T + t];
     if (off) {
@@ -1632,11 +1683,11 @@ __global__ void k_reduce(int64_t T, int nchunk, const double* __restrict__ part,
     } while (0)
 
 int launch_expand(hipStream_t st, int E, const double* xc, const double* eps, const double* e1, const double* sa,
-                  const double* sc, const int* esign, const int* ebody, double* clq, double* circ, ElemInfo* info,
-                  double* ny, double* nn, double* nw, int64_t N)
+                  const double* sc, const int* esign, const int* ebody, const int* egroup, double* clq, double* circ,
+                  ElemInfo* info, double* ny, double* nn, double* nw, int64_t N)
 {
-    hipLaunchKernelGGL(k_expand, dim3(E), dim3(512), 0, st, E, xc, eps, e1, sa, sc, esign, ebody, clq, circ, info,
-                       ny, nn, nw, N);
+    hipLaunchKernelGGL(k_expand, dim3(E), dim3(512), 0, st, E, xc, eps, e1, sa, sc, esign, ebody, egroup, clq, circ,
+                       info, ny, nn, nw, N);
     LAUNCH_CHECK();
     return 0;
 }
@@ -1687,33 +1738,50 @@ int launch_sigma_base(hipStream_t st, int E, const ElemInfo* info, const int64_t
     return 0;
 }
 
-int launch_targets(hipStream_t st, int64_t T, const double* x, const int64_t* tnode, const double* ny, int64_t N,
-                   double* xt, int* err)
+int launch_targets(hipStream_t st, int64_t T, const double* x, const int64_t* tnode, const int* tgrp_in, int G,
+                   const ElemInfo* info, const double* ny, int64_t N, double* xt, int* tgroup, int64_t* gstart,
+                   int* err)
 {
+    hipLaunchKernelGGL(k_fill_i64, dim3((unsigned)((G + 255) / 256)), dim3(256), 0, st, (int64_t)G, gstart,
+                       (int64_t)-1);
+    LAUNCH_CHECK();
     if (T == 0) return 0;
-    hipLaunchKernelGGL(k_targets, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, st, T, x, tnode, ny, N, xt, err);
+    const dim3 grid((unsigned)((T + 255) / 256));
+    hipLaunchKernelGGL(k_targets, grid, dim3(256), 0, st, T, x, tnode, tgrp_in, G, info, ny, N, xt, tgroup, err);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_group_bounds, grid, dim3(256), 0, st, T, tgroup, gstart, err);
     LAUNCH_CHECK();
     return 0;
 }
 
 int launch_far(hipStream_t st, int64_t T, const double* xt, const double* sy, const double* sn, const double* ssw,
-               int64_t N, int64_t chunk, int nchunk, double* part, bool mixed, double near2)
+               int64_t N, const FarTile* tiles, int ntiles, double* part, bool mixed, double near2, int tpt)
 {
-    const int64_t per = (int64_t)FAR_BLOCK * FAR_TPT;
-    dim3 grid((unsigned)((T + per - 1) / per), (unsigned)nchunk);
-    if (mixed)
-        hipLaunchKernelGGL(k_far_mx, grid, dim3(FAR_BLOCK), 0, st, T, xt, sy, sn, ssw, N, chunk, near2, part);
-    else
-        hipLaunchKernelGGL(k_far, grid, dim3(FAR_BLOCK), 0, st, T, xt, sy, sn, ssw, N, chunk, part);
+    if (ntiles == 0) return 0;
+    const dim3 grid((unsigned)ntiles), blk(FAR_BLOCK);
+#define CSBQ_FAR(K)                                                                                                 \
+    if (mixed)                                                                                                      \
+        hipLaunchKernelGGL(k_far_mx<K>, grid, blk, 0, st, T, xt, sy, sn, ssw, N, tiles, near2, part);              \
+    else                                                                                                            \
+        hipLaunchKernelGGL(k_far<K>, grid, blk, 0, st, T, xt, sy, sn, ssw, N, tiles, part);
+    switch (tpt) {
+    case 1: CSBQ_FAR(1) break;
+    case 2: CSBQ_FAR(2) break;
+    case 4: CSBQ_FAR(4) break;
+    default: return (int)hipErrorInvalidValue;
+    }
+#undef CSBQ_FAR
     LAUNCH_CHECK();
     return 0;
 }
 
-int launch_search(hipStream_t st, int64_t T, int E, const double* xt, const int64_t* tnode, const ElemInfo* info,
-                  const double* rnear, const int64_t* off, int* cnt, int* pe, int* pt)
+int launch_search(hipStream_t st, int64_t T, const int* tgroup, const int* gel, const double* xt,
+                  const int64_t* tnode, const ElemInfo* info, const double* rnear, const int64_t* off, int* cnt,
+                  int* pe, int* pt)
 {
-    hipLaunchKernelGGL(k_search, dim3((unsigned)((T + 127) / 128)), dim3(128), 0, st, T, E, xt, tnode, info, rnear,
-                       off, cnt, pe, pt);
+    if (T == 0) return 0;
+    hipLaunchKernelGGL(k_search, dim3((unsigned)((T + 127) / 128)), dim3(128), 0, st, T, tgroup, gel, xt, tnode,
+                       info, rnear, off, cnt, pe, pt);
     LAUNCH_CHECK();
     return 0;
 }
@@ -1775,11 +1843,12 @@ int launch_corr_full(hipStream_t st, int nfull, const int* listf, const int* pe,
     return 0;
 }
 
-int launch_reduce(hipStream_t st, int64_t T, int nchunk, const double* part, const int64_t* off, const int8_t* tier,
-                  const double* corr, double* usl, double* udl)
+int launch_reduce(hipStream_t st, int64_t T, const int* tgroup, const int* gnchunk, const double* part,
+                  const int64_t* off, const int8_t* tier, const double* corr, double* usl, double* udl)
 {
-    hipLaunchKernelGGL(k_reduce, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, st, T, nchunk, part, off, tier,
-                       corr, usl, udl);
+    if (T == 0) return 0;
+    hipLaunchKernelGGL(k_reduce, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, st, T, tgroup, gnchunk, part, off,
+                       tier, corr, usl, udl);
     LAUNCH_CHECK();
     return 0;
 }

@@ -11,8 +11,8 @@ namespace csbq {
 int upload_constants(const double* gx, const double* gw, const double* lam, const double* D, const double* T);
 
 int launch_expand(hipStream_t st, int E, const double* xc, const double* eps, const double* e1, const double* sa,
-                  const double* sc, const int* esign, const int* ebody, double* clq, double* circ, ElemInfo* info,
-                  double* ny, double* nn, double* nw, int64_t N);
+                  const double* sc, const int* esign, const int* ebody, const int* egroup, double* clq, double* circ,
+                  ElemInfo* info, double* ny, double* nn, double* nw, int64_t N);
 int launch_expand_up(hipStream_t st, int E, int ns_f, int nt_f, const double* gx_f, const double* gw_f,
                      const double* clq, const ElemInfo* info, double* cpy, double* cpn, double* cpw, int64_t Mtot);
 int launch_base_build(hipStream_t st, int E, const ElemInfo* info, const int64_t* boff, const double* ny,
@@ -25,12 +25,14 @@ int launch_sigma_up(hipStream_t st, int E, int ns_f, int nt_f, const double* sh,
                     double* swf, int64_t Mtot);
 int launch_sigma_base(hipStream_t st, int E, const ElemInfo* info, const int64_t* boff, const double* sw, int64_t N,
                       const double* swf0, int64_t M0, double* bsw, int64_t Nb);
-int launch_targets(hipStream_t st, int64_t T, const double* x, const int64_t* tnode, const double* ny, int64_t N,
-                   double* xt, int* err);
+int launch_targets(hipStream_t st, int64_t T, const double* x, const int64_t* tnode, const int* tgrp_in, int G,
+                   const ElemInfo* info, const double* ny, int64_t N, double* xt, int* tgroup, int64_t* gstart,
+                   int* err);
 int launch_far(hipStream_t st, int64_t T, const double* xt, const double* sy, const double* sn, const double* ssw,
-               int64_t N, int64_t chunk, int nchunk, double* part, bool mixed, double near2);
-int launch_search(hipStream_t st, int64_t T, int E, const double* xt, const int64_t* tnode, const ElemInfo* info,
-                  const double* rnear, const int64_t* off, int* cnt, int* pe, int* pt);
+               int64_t N, const FarTile* tiles, int ntiles, double* part, bool mixed, double near2, int tpt);
+int launch_search(hipStream_t st, int64_t T, const int* tgroup, const int* gel, const double* xt,
+                  const int64_t* tnode, const ElemInfo* info, const double* rnear, const int64_t* off, int* cnt,
+                  int* pe, int* pt);
 int launch_classify(hipStream_t st, int64_t P, const int* perm, const int* pe, const int* pt, const double* xt,
                     int64_t T, const int64_t* tnode, const double* clq, const double* circ, const ElemInfo* info,
                     const int* band, GateConsts gc, int8_t* tier, double* cls);
@@ -40,13 +42,14 @@ int launch_corr_up(hipStream_t st, int64_t Mf, int nwaves, const int* ws, const 
                    const double* xt, int64_t T, const double* cpy, const double* cpn, const double* swf,
                    int64_t Mtot, const int64_t* boff, const double* by, const double* bn, const double* bsw,
                    int64_t Nb, double* corr);
+constexpr int FAR_BLOCK = 256;         // threads of a smooth-sum block (TPT targets each)
 int launch_corr_full(hipStream_t st, int nfull, const int* listf, const int* pe, const int* pt, const double* xt,
                      int64_t T, const int64_t* tnode, const double* clq, const double* sh, const ElemInfo* info,
                      const int* band, const double* cls, const int64_t* boff, const double* by, const double* bn,
                      const double* bsw, int64_t Nb, const int* roff, const double* rth, const double* rw, int nb,
                      const double* lx, const double* lw, int nl, const double* rcs, const double* rsn,
                      const double* romc, GateConsts gc, double* corr, int* err, int* work, int mt_max);
-int launch_reduce(hipStream_t st, int64_t T, int nchunk, const double* part, const int64_t* off, const int8_t* tier,
-                  const double* corr, double* usl, double* udl);
+int launch_reduce(hipStream_t st, int64_t T, const int* tgroup, const int* gnchunk, const double* part,
+                  const int64_t* off, const int8_t* tier, const double* corr, double* usl, double* udl);
 
 }  // namespace csbq

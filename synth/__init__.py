@@ -402,3 +402,31 @@ def small_pipe_scene(seed=7000, n_panels=6, n_spheres=3, arc=0.6) -> Scene:
     sc.pipe_scale = 1.0
     sc.name = f"pipe{n_panels}-spheres{n_spheres}"
     return sc
+
+
+def merge_scenes(scenes) -> Scene:
+    """Several independent scenes as one batch: bodies concatenated in order,
+    ``body_group[b]`` = index of the scene body b comes from (bodies of
+    different groups do not interact), densities and targets concatenated
+    (node ids shifted to the merged numbering).  ``group_node_offsets`` and
+    ``group_target_offsets`` give each scene's slice of nodes and targets."""
+    bodies, groups, sig, xs, tns, cls = [], [], [], [], [], []
+    noff, toff = [0], [0]
+    for g, sc in enumerate(scenes):
+        bodies.extend(sc.bodies)
+        groups.extend([g] * len(sc.bodies))
+        sig.append(sc.sigma)
+        tn = sc.tgt_node if sc.tgt_node is not None else np.arange(sc.n_nodes, dtype=np.int64)  # default: all nodes
+        T = len(tn)
+        xs.append(sc.x if sc.x is not None else np.zeros((T, 3)))
+        tns.append(np.where(tn >= 0, tn + noff[-1], -1))
+        cls.append(sc.tgt_class if sc.tgt_class is not None else np.zeros(T, np.int64))
+        noff.append(noff[-1] + sc.n_nodes)
+        toff.append(toff[-1] + T)
+    out = Scene(bodies, scenes[0].ns, scenes[0].nt, np.ascontiguousarray(np.concatenate(sig)),
+                np.ascontiguousarray(np.concatenate(xs)), np.ascontiguousarray(np.concatenate(tns)).astype(np.int64),
+                np.concatenate(cls), scenes[0].class_names, "batch%d" % len(scenes))
+    out.body_group = np.asarray(groups, dtype=np.int32)
+    out.group_node_offsets = np.asarray(noff, dtype=np.int64)
+    out.group_target_offsets = np.asarray(toff, dtype=np.int64)
+    return out
