@@ -21,6 +21,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "layer-potential target evals/sec at rel.err 1e-10 (FP64) and 1e-6 (mixed+MLP)"
 FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 vector peak
+FP32_PEAK_TFLOPS = 157.3         # MI355X FP32 vector peak (the mixed-precision smooth sum)
 FAR_FLOPS_PER_PAIR = 44          # smooth-sum flops per source-target pair (rsqrt counted once)
 # special quadrature flops: per theta-rule node 82 + 18 per density Fourier mode
 # (synthesis), per s-node 800 (interpolation weights, centerline data, frame,
@@ -59,6 +60,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--gate", default=None, choices=["criterion", "mlp"],
+                    help="correction-tier gate (default: criterion for fp64, the trained network for mixed)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     a = ap.parse_args()
@@ -73,7 +76,12 @@ def main():
     log("bench: building workload")
     sc = synth.config2()
     quad_tol = 1e-12 if a.precision == "fp64" else 1e-7   # under the 1e-10 / 1e-6 parity gates
-    ev = pk.Evaluator(quad_tol=quad_tol, precision=a.precision)
+    gate = a.gate or ("criterion" if a.precision == "fp64" else "mlp")
+    ev = pk.Evaluator(quad_tol=quad_tol, precision=a.precision, gate=gate)
+    if gate == "mlp":
+        from paper_2310_00889_amd import gate as gmod
+        w, meta = gmod.load_weights()
+        ev.gate_load(w, float(meta["tau_esc"]))
     ev.set_geometry(sc)
     sig = torch.from_numpy(sc.sigma).cuda()
     tn = torch.from_numpy(sc.tgt_node).cuda()
@@ -105,8 +113,11 @@ def main():
         flops = (THETA_FLOPS * float(counts.get("theta_nodes", 0)) + THETA_MODE_FLOPS * float(counts.get("theta_modes", 0))
                  + SNODE_FLOPS * float(counts.get("s_nodes", 0)) + SNODE_MODE_FLOPS * float(counts.get("s_modes", 0)))
     achieved = flops / (phases[dom] * 1e-3) / 1e12
-    roof = dict(kernel="k_far" if dom == "far" else "k_corr_full", bound="alu", achieved=achieved,
-                peak=FP64_PEAK_TFLOPS, unit="TFLOP/s", frac=achieved / FP64_PEAK_TFLOPS, traffic=None)
+    far_kernel = "k_far" if a.precision == "fp64" else "k_far_mx"
+    far_peak = FP64_PEAK_TFLOPS if a.precision == "fp64" else FP32_PEAK_TFLOPS
+    peak = far_peak if dom == "far" else FP64_PEAK_TFLOPS
+    roof = dict(kernel=far_kernel if dom == "far" else "k_corr_full", bound="alu", achieved=achieved,
+                peak=peak, unit="TFLOP/s", frac=achieved / peak, traffic=None)
     far_ach = FAR_FLOPS_PER_PAIR * float(T) * nsrc / (phases["far"] * 1e-3) / 1e12
     out = {
         "metric": METRIC, "value": value, "unit": "target evals/s", "n_gpus": 1, "steps": a.steps,
@@ -114,10 +125,10 @@ def main():
         "vs_baseline": None, "dtype": "f64" if a.precision == "fp64" else "f32+f64", "data": "synthetic",
         "config": {"workload": "pipe100-spheres200: torus-arc pipe (R=5, r=1, arc pi, 100 panels) + 200 spheres "
                                "r=0.2, 16x32 nodes per element, 153,600 sources = on-surface targets",
-                   "quad_tol": quad_tol, "precision": a.precision, "targets": T, "sources": ev.n_nodes},
+                   "quad_tol": quad_tol, "precision": a.precision, "gate": gate, "targets": T, "sources": ev.n_nodes},
         "roofline": roof,
-        "far_roofline": dict(kernel="k_far", bound="alu", achieved=far_ach, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
-                             frac=far_ach / FP64_PEAK_TFLOPS),
+        "far_roofline": dict(kernel=far_kernel, bound="alu", achieved=far_ach,
+                             peak=far_peak, unit="TFLOP/s", frac=far_ach / far_peak),
         "phases_ms": phases,
         "pairs": {k: counts.get(k) for k in ("candidates", "pairs_up1", "pairs_up2", "pairs_up3", "pairs_full",
                                               "theta_nodes", "theta_modes", "s_nodes", "s_modes", "sources_base")},

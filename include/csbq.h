@@ -158,6 +158,53 @@ int csbq_smooth_sum(csbq_ctx* ctx, const double* sigma, int64_t n_tgt, const dou
 int csbq_eval_batch(csbq_ctx* ctx, const double* sigma, int64_t n_tgt, const double* x, const int64_t* tgt_node,
                     const int32_t* tgt_group, double* u_sl, double* u_dl, int mem);
 
+/* ---- Learned correction-tier gate (an extension beyond the paper; the
+   criterion of Section 3.2's error estimates stays the fallback and the
+   judge).  A perceptron with three hidden layers of 64 ReLU units maps
+   CSBQ_GATE_NF features of a (target, element) pair to CSBQ_GATE_NO ordinal
+   outputs, output k estimating P(tier > k) for the tiers skip / three
+   upsampled whole-panel rules / special quadrature.  With gate = MLP the
+   evaluation takes the network's tier for the pairs it is confident about
+   and sends the rest (P(tier above the prediction) > tau_esc, predicted
+   special quadrature, own-element targets) to the criterion.  Inference runs
+   on bf16 MFMA with FP32 accumulation; training is FP32.
+   Weights: CSBQ_GATE_NW floats, W1[16][64] b1[64] W2[64][64] b2[64]
+   W3[64][64] b3[64] W4[64][4] b4[4] (row-major, input index first). */
+#define CSBQ_GATE_NF 16
+#define CSBQ_GATE_NO 4
+#define CSBQ_GATE_NW 9668
+
+/* Install inference weights (host array) and the escalation threshold
+   tau_esc in (0, 1). */
+int csbq_gate_load(csbq_ctx* ctx, const float* weights, float tau_esc);
+
+/* Run the installed network on n feature rows (host [n][16]); outputs (host,
+   any may be NULL): tier [n] (0..4), esc [n] (1 = decided by the criterion),
+   logits [n][4]. */
+int csbq_gate_infer(csbq_ctx* ctx, const float* feat, int64_t n, int8_t* tier, uint8_t* esc, float* logits);
+
+/* Mean loss and gradient (host [CSBQ_GATE_NW]) of the weighted ordinal
+   cross-entropy  sum_k -(posw[k] y_k log s_k + (1 - y_k) log(1 - s_k)),
+   y_k = [label > k], over n samples, at the given weights (host arrays). */
+int csbq_gate_grad(csbq_ctx* ctx, const float* weights, const float* feat, const int8_t* label, int64_t n,
+                   const float* posw, float* grad, float* loss);
+
+/* Adam training (minibatches of `batch`, `epochs` passes, samples shuffled
+   with `seed`): weights (host) hold the initial values on entry and the
+   trained values on return; loss_out [epochs] (may be NULL) the mean loss of
+   every pass. */
+int csbq_gate_train(csbq_ctx* ctx, const float* feat, const int8_t* label, int64_t n, const float* posw, int epochs,
+                    int batch, float lr, uint64_t seed, float* weights, float* loss_out);
+
+/* Training data from one evaluation (criterion gate, host arrays): the
+   features of every candidate pair and its label, the cheapest tier whose
+   correction agrees with the special quadrature's to label_tol times the
+   largest |u| of that kernel over the targets (4 if none does); crit (may be
+   NULL) receives the criterion's tier.  At most cap pairs are returned (an
+   even stride through the pair list); *n_out receives the count. */
+int csbq_gate_dataset(csbq_ctx* ctx, const double* sigma, int64_t n_tgt, const double* x, const int64_t* tgt_node,
+                      double label_tol, int64_t cap, float* feat, int8_t* label, int8_t* crit, int64_t* n_out);
+
 /* Statistics of the last csbq_eval as a JSON object (phase times in ms from
    HIP events, pair counts per correction tier).  Writes at most cap bytes
    including the terminating zero. */

@@ -23,6 +23,8 @@ TABLE_DIR = os.path.join(HERE, "tables")
 
 CSBQ_HOST, CSBQ_DEVICE = 0, 1
 CSBQ_FP64, CSBQ_MIXED = 0, 1
+CSBQ_GATE_CRITERION, CSBQ_GATE_MLP = 0, 1
+GATE_NF, GATE_NO, GATE_NW = 16, 4, 9668
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ETABLE", -5: "ESTATE", -6: "ELIMIT"}
 
 
@@ -61,6 +63,12 @@ def load_library():
     lib.csbq_eval_batch.argtypes = [vp, dp, C.c_int64, dp, lp, ip, dp, dp, C.c_int]
     lib.csbq_smooth_sum.argtypes = [vp, dp, C.c_int64, dp, lp, dp, dp, C.c_int]
     lib.csbq_stats.argtypes = [vp, C.c_char_p, C.c_int64]
+    lib.csbq_gate_load.argtypes = [vp, dp, C.c_float]
+    lib.csbq_gate_infer.argtypes = [vp, dp, C.c_int64, dp, dp, dp]
+    lib.csbq_gate_grad.argtypes = [vp, dp, dp, dp, C.c_int64, dp, dp, dp]
+    lib.csbq_gate_train.argtypes = [vp, dp, dp, C.c_int64, dp, C.c_int, C.c_int, C.c_float, C.c_uint64, dp, dp]
+    lib.csbq_gate_dataset.argtypes = [vp, dp, C.c_int64, dp, lp, C.c_double, C.c_int64, dp, dp, dp,
+                                      C.POINTER(C.c_int64)]
     lib.csbq_synchronize.argtypes = [vp]
     _lib = lib
     return lib
@@ -81,12 +89,13 @@ def _ptr(a):
 class Evaluator:
     """One library context: geometry, quadrature tables, device buffers."""
 
-    def __init__(self, quad_tol=1e-12, precision="fp64", device=0, stream=None, table_dir=None):
+    def __init__(self, quad_tol=1e-12, precision="fp64", device=0, stream=None, table_dir=None, gate="criterion"):
         lib = load_library()
         opt = _Options()
         lib.csbq_default_options(C.byref(opt))
         opt.quad_tol = float(quad_tol)
         opt.precision = CSBQ_MIXED if precision == "mixed" else CSBQ_FP64
+        opt.gate = CSBQ_GATE_MLP if gate == "mlp" else CSBQ_GATE_CRITERION
         opt.device = int(device)
         if stream is None:
             try:
@@ -201,6 +210,60 @@ class Evaluator:
     def smooth_sum(self, sigma, x=None, tgt_node=None, out_sl=None, out_dl=None):
         """(u_S, u_D) of the plain smooth Nystrom sum (no corrections)."""
         return self._call(self._lib.csbq_smooth_sum, "csbq_smooth_sum", sigma, x, tgt_node, out_sl, out_dl)
+
+    # ---- learned gate
+    def gate_load(self, weights, tau_esc=0.05):
+        w = np.ascontiguousarray(weights, np.float32).reshape(GATE_NW)
+        self._check(self._lib.csbq_gate_load(self._h, _ptr(w), float(tau_esc)), "csbq_gate_load")
+
+    def gate_infer(self, feat):
+        f = np.ascontiguousarray(feat, np.float32).reshape(-1, GATE_NF)
+        n = f.shape[0]
+        tier = np.zeros(n, np.int8)
+        esc = np.zeros(n, np.uint8)
+        lg = np.zeros((n, GATE_NO), np.float32)
+        self._check(self._lib.csbq_gate_infer(self._h, _ptr(f), n, _ptr(tier), _ptr(esc), _ptr(lg)),
+                    "csbq_gate_infer")
+        return tier, esc, lg
+
+    def gate_grad(self, weights, feat, label, posw):
+        w = np.ascontiguousarray(weights, np.float32).reshape(GATE_NW)
+        f = np.ascontiguousarray(feat, np.float32).reshape(-1, GATE_NF)
+        lab = np.ascontiguousarray(label, np.int8)
+        pw = np.ascontiguousarray(posw, np.float32).reshape(GATE_NO)
+        g = np.zeros(GATE_NW, np.float32)
+        loss = np.zeros(1, np.float32)
+        self._check(self._lib.csbq_gate_grad(self._h, _ptr(w), _ptr(f), _ptr(lab), f.shape[0], _ptr(pw), _ptr(g),
+                                             _ptr(loss)), "csbq_gate_grad")
+        return g, float(loss[0])
+
+    def gate_train(self, feat, label, posw, weights, epochs=10, batch=4096, lr=1e-3, seed=0):
+        w = np.array(weights, np.float32).reshape(GATE_NW).copy()
+        f = np.ascontiguousarray(feat, np.float32).reshape(-1, GATE_NF)
+        lab = np.ascontiguousarray(label, np.int8)
+        pw = np.ascontiguousarray(posw, np.float32).reshape(GATE_NO)
+        losses = np.zeros(epochs, np.float32)
+        self._check(self._lib.csbq_gate_train(self._h, _ptr(f), _ptr(lab), f.shape[0], _ptr(pw), int(epochs),
+                                              int(batch), float(lr), int(seed), _ptr(w), _ptr(losses)),
+                    "csbq_gate_train")
+        return w, losses
+
+    def gate_dataset(self, sigma, x=None, tgt_node=None, label_tol=1e-8, cap=1 << 20):
+        sigma = np.ascontiguousarray(sigma, np.float64)
+        if x is not None:
+            x = np.ascontiguousarray(x, np.float64).reshape(-1, 3)
+        if tgt_node is not None:
+            tgt_node = np.ascontiguousarray(tgt_node, np.int64)
+        T = int(tgt_node.shape[0] if tgt_node is not None else x.shape[0])
+        feat = np.zeros((cap, GATE_NF), np.float32)
+        lab = np.zeros(cap, np.int8)
+        crit = np.zeros(cap, np.int8)
+        n = C.c_int64()
+        self._check(self._lib.csbq_gate_dataset(self._h, _ptr(sigma), T, _ptr(x), _ptr(tgt_node), float(label_tol),
+                                                int(cap), _ptr(feat), _ptr(lab), _ptr(crit), C.byref(n)),
+                    "csbq_gate_dataset")
+        k = n.value
+        return feat[:k].copy(), lab[:k].copy(), crit[:k].copy()
 
     def synchronize(self):
         self._check(self._lib.csbq_synchronize(self._h), "csbq_synchronize")

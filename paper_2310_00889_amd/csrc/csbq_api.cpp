@@ -15,7 +15,10 @@
 
 #include "../../include/csbq.h"
 #include "csbq_common.hpp"
+#include "csbq_gate.hpp"
 #include "csbq_kernels.hpp"
+#include <algorithm>
+#include <random>
 
 using namespace csbq;
 
@@ -194,6 +197,16 @@ struct csbq_ctx {
     int64_t far_chunk = 16384;
     uint64_t tuned_key = 0;
     float tune_ms[6] = {0, 0, 0, 0, 0, 0};
+    // learned gate: inference weights (bf16 MFMA fragments, FP32 biases) and
+    // per-pair scratch
+    bool gate_ready = false;
+    float gate_tau = 0.05f;
+    DBuf<uint16_t> gate_wfrag;
+    DBuf<float> gate_bias, gfeat;
+    DBuf<int8_t> gtier;
+    DBuf<uint8_t> gesc, gflag;
+    DBuf<int> gsel, gnsel;
+    int64_t last_esc = -1;
     DBuf<unsigned char> cub_tmp;
     // statistics of the last evaluation
     Phase ph[kNPhase];
@@ -316,6 +329,10 @@ int csbq_create(const csbq_options* opt, csbq_ctx** out)
     else
         csbq_default_options(&ctx->opt);
     if (!(ctx->opt.quad_tol > 0)) ctx->opt.quad_tol = 1e-12;
+    if (ctx->opt.gate != CSBQ_GATE_CRITERION && ctx->opt.gate != CSBQ_GATE_MLP) {
+        delete ctx;
+        return CSBQ_EINVAL;
+    }
     if (ctx->opt.precision != CSBQ_FP64 && ctx->opt.precision != CSBQ_MIXED) {
         delete ctx;
         return CSBQ_EINVAL;
@@ -1014,8 +1031,45 @@ int csbq_eval_batch(csbq_ctx* ctx, const double* sigma, int64_t T, const double*
     if (P > 0)
         HIPC(hipcub::DeviceRadixSort::SortPairs(ctx->cub_tmp.p, tmpb, ctx->pe.p, ctx->kout.p, ctx->vin.p,
                                                 ctx->perm.p, (int)P, 0, ebits, st));
-    LCHK(launch_classify(st, P, ctx->perm.p, ctx->pe.p, ctx->pt.p, ctx->xt.p, T, tn, ctx->clq.p, ctx->circ.p,
-                         ctx->info.p, ctx->band.p, ctx->gc, ctx->tier.p, ctx->cls.p));
+    if (ctx->opt.gate == CSBQ_GATE_MLP) {
+        // learned gate: every pair's tier from the network; the pairs it is
+        // not confident about (and every special-quadrature or own-element
+        // pair, whose s-rule needs the singularity estimate) go to the
+        // criterion
+        if (!ctx->gate_ready) return ctx->fail(CSBQ_ESTATE, "the learned gate has no weights (csbq_gate_load)");
+        ALLOC(ctx->gfeat, (size_t)P * GATE_NF + GATE_NF);
+        ALLOC(ctx->gtier, (size_t)P + 1);
+        ALLOC(ctx->gesc, (size_t)P + 1);
+        ALLOC(ctx->gflag, (size_t)P + 1);
+        ALLOC(ctx->gsel, (size_t)P + 1);
+        ALLOC(ctx->gnsel, 1);
+        LCHK(launch_gate_features(st, P, ctx->pe.p, ctx->pt.p, ctx->xt.p, T, tn, ctx->circ.p, ctx->info.p,
+                                  ctx->band.p, (float)std::log10(ctx->gc.tol), ctx->gfeat.p));
+        LCHK(launch_gate_mlp(st, P, ctx->gfeat.p, ctx->gate_wfrag.p, ctx->gate_bias.p, ctx->gate_tau, ctx->gtier.p,
+                             ctx->gesc.p, nullptr));
+        LCHK(launch_gate_select(st, P, ctx->perm.p, ctx->gesc.p, ctx->gtier.p, ctx->tier.p, ctx->gflag.p));
+        size_t sb = 0;
+        HIPC(hipcub::DeviceSelect::Flagged(nullptr, sb, ctx->perm.p, ctx->gflag.p, ctx->gsel.p, ctx->gnsel.p, (int)P,
+                                           st));
+        if (sb > tmpb) {
+            ALLOC(ctx->cub_tmp, sb);
+            tmpb = sb;
+        }
+        int nsel = 0;
+        if (P > 0) {
+            HIPC(hipcub::DeviceSelect::Flagged(ctx->cub_tmp.p, tmpb, ctx->perm.p, ctx->gflag.p, ctx->gsel.p,
+                                               ctx->gnsel.p, (int)P, st));
+            HIPC(hipMemcpyAsync(&nsel, ctx->gnsel.p, sizeof(int), hipMemcpyDeviceToHost, st));
+            HIPC(hipStreamSynchronize(st));
+        }
+        ctx->last_esc = nsel;
+        LCHK(launch_classify(st, nsel, ctx->gsel.p, ctx->pe.p, ctx->pt.p, ctx->xt.p, T, tn, ctx->clq.p,
+                             ctx->circ.p, ctx->info.p, ctx->band.p, ctx->gc, ctx->tier.p, ctx->cls.p));
+    } else {
+        ctx->last_esc = -1;
+        LCHK(launch_classify(st, P, ctx->perm.p, ctx->pe.p, ctx->pt.p, ctx->xt.p, T, tn, ctx->clq.p, ctx->circ.p,
+                             ctx->info.p, ctx->band.p, ctx->gc, ctx->tier.p, ctx->cls.p));
+    }
     HIPC(hipEventRecord(ctx->ph[3].b, st));
     // buckets: pairs sorted by (tier, element); runs give the per-element segments
     HIPC(hipEventRecord(ctx->ph[4].a, st));
@@ -1106,6 +1160,265 @@ int csbq_eval_batch(csbq_ctx* ctx, const double* sigma, int64_t T, const double*
     return finish(ctx, T, u_sl, u_dl, mem);
 }
 
+// ---------------------------------------------------------------------------
+// learned gate
+// ---------------------------------------------------------------------------
+static_assert(GATE_NF == CSBQ_GATE_NF && GATE_NO == CSBQ_GATE_NO && GATE_NW == CSBQ_GATE_NW, "gate shape");
+
+static uint16_t host_bf16(float f)
+{
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+int csbq_gate_load(csbq_ctx* ctx, const float* W, float tau_esc)
+{
+    if (!ctx) return CSBQ_EINVAL;
+    ctx->err.clear();
+    if (!W) return ctx->fail(CSBQ_EINVAL, "missing weights");
+    if (!(tau_esc > 0.f && tau_esc < 1.f)) return ctx->fail(CSBQ_EINVAL, "tau_esc must lie in (0, 1)");
+    for (int i = 0; i < GATE_NW; ++i)
+        if (!std::isfinite(W[i])) return ctx->fail(CSBQ_EINVAL, "weights have NaN/Inf");
+    HIPC(hipSetDevice(ctx->opt.device));
+    // B fragments of v_mfma_f32_16x16x16_bf16: lane l holds B[4 (l/16) + i][l % 16]
+    std::vector<uint16_t> fr((size_t)GATE_NFRAG * GATE_FRAG_ELEMS, 0);
+    int f = 0;
+    auto put = [&](const float* M, int ncol, int kb, int nb, int ncol_used) {
+        for (int l = 0; l < 64; ++l)
+            for (int i = 0; i < 4; ++i) {
+                const int k = kb * 16 + 4 * (l / 16) + i, c = nb * 16 + (l % 16);
+                const float v = c < ncol_used ? M[(size_t)k * ncol + c] : 0.f;
+                fr[((size_t)f * 64 + l) * 4 + i] = host_bf16(v);
+            }
+        ++f;
+    };
+    for (int nb = 0; nb < 4; ++nb) put(W + GW1, GATE_H, 0, nb, GATE_H);
+    for (int kb = 0; kb < 4; ++kb)
+        for (int nb = 0; nb < 4; ++nb) put(W + GW2, GATE_H, kb, nb, GATE_H);
+    for (int kb = 0; kb < 4; ++kb)
+        for (int nb = 0; nb < 4; ++nb) put(W + GW3, GATE_H, kb, nb, GATE_H);
+    for (int kb = 0; kb < 4; ++kb) put(W + GW4, GATE_NO, kb, 0, GATE_NO);
+    std::vector<float> b((size_t)GATE_NBIAS, 0.f);
+    for (int j = 0; j < GATE_H; ++j) {
+        b[j] = W[GB1 + j];
+        b[GATE_H + j] = W[GB2 + j];
+        b[2 * GATE_H + j] = W[GB3 + j];
+    }
+    for (int c = 0; c < GATE_NO; ++c) b[3 * GATE_H + c] = W[GB4 + c];
+    ALLOC(ctx->gate_wfrag, fr.size());
+    ALLOC(ctx->gate_bias, b.size());
+    HIPC(hipMemcpy(ctx->gate_wfrag.p, fr.data(), fr.size() * 2, hipMemcpyHostToDevice));
+    HIPC(hipMemcpy(ctx->gate_bias.p, b.data(), b.size() * 4, hipMemcpyHostToDevice));
+    ctx->gate_tau = tau_esc;
+    ctx->gate_ready = true;
+    return CSBQ_OK;
+}
+
+int csbq_gate_infer(csbq_ctx* ctx, const float* feat, int64_t n, int8_t* tier, uint8_t* esc, float* logits)
+{
+    if (!ctx) return CSBQ_EINVAL;
+    ctx->err.clear();
+    if (!ctx->gate_ready) return ctx->fail(CSBQ_ESTATE, "no gate weights loaded");
+    if (!feat || n < 0 || n > (int64_t)INT32_MAX) return ctx->fail(CSBQ_EINVAL, "bad features");
+    HIPC(hipSetDevice(ctx->opt.device));
+    hipStream_t st = ctx->stream;
+    int rc;
+    if ((rc = to_device(ctx, ctx->gfeat, feat, (size_t)n * GATE_NF, CSBQ_HOST))) return rc;
+    ALLOC(ctx->gtier, (size_t)n + 1);
+    ALLOC(ctx->gesc, (size_t)n + 1);
+    DBuf<float> lg;
+    ALLOC(lg, (size_t)n * GATE_NO + 1);
+    LCHK(launch_gate_mlp(st, n, ctx->gfeat.p, ctx->gate_wfrag.p, ctx->gate_bias.p, ctx->gate_tau, ctx->gtier.p,
+                         ctx->gesc.p, lg.p));
+    if (n > 0) {
+        if (tier) HIPC(hipMemcpyAsync(tier, ctx->gtier.p, (size_t)n, hipMemcpyDeviceToHost, st));
+        if (esc) HIPC(hipMemcpyAsync(esc, ctx->gesc.p, (size_t)n, hipMemcpyDeviceToHost, st));
+        if (logits) HIPC(hipMemcpyAsync(logits, lg.p, (size_t)n * GATE_NO * 4, hipMemcpyDeviceToHost, st));
+    }
+    HIPC(hipStreamSynchronize(st));
+    return CSBQ_OK;
+}
+
+// one forward/backward pass over samples perm[0..n) of (feat, label) on the
+// device buffers; grad (NW + 1 floats, the last the loss) averaged over n
+static int gate_grad_dev(csbq_ctx* ctx, int64_t off, int64_t n, const int64_t* perm, const float* feat,
+                         const int8_t* label, const float* W, const float* posw, DBuf<float>& partial,
+                         float* grad)
+{
+    const int spb = 64;
+    const int nblk = (int)((n + spb - 1) / spb);
+    ALLOC(partial, (size_t)std::max(nblk, 1) * (GATE_NW + 1));
+    LCHK(launch_gate_train_step(ctx->stream, nblk, spb, off, n, perm, feat, label, W, posw, partial.p));
+    LCHK(launch_gate_reduce(ctx->stream, nblk, partial.p, 1.f / (float)std::max<int64_t>(n, 1), grad));
+    return CSBQ_OK;
+}
+
+int csbq_gate_grad(csbq_ctx* ctx, const float* W, const float* feat, const int8_t* label, int64_t n,
+                   const float* posw, float* grad_out, float* loss_out)
+{
+    if (!ctx) return CSBQ_EINVAL;
+    ctx->err.clear();
+    if (!W || !feat || !label || !posw || !grad_out || n <= 0) return ctx->fail(CSBQ_EINVAL, "bad arguments");
+    HIPC(hipSetDevice(ctx->opt.device));
+    DBuf<float> dW, df, dpw, part, grad;
+    DBuf<int8_t> dl;
+    DBuf<int64_t> dp;
+    int rc;
+    if ((rc = to_device(ctx, dW, W, GATE_NW, CSBQ_HOST))) return rc;
+    if ((rc = to_device(ctx, df, feat, (size_t)n * GATE_NF, CSBQ_HOST))) return rc;
+    if ((rc = to_device(ctx, dl, label, (size_t)n, CSBQ_HOST))) return rc;
+    if ((rc = to_device(ctx, dpw, posw, GATE_NO, CSBQ_HOST))) return rc;
+    std::vector<int64_t> id((size_t)n);
+    for (int64_t i = 0; i < n; ++i) id[i] = i;
+    if ((rc = to_device(ctx, dp, id.data(), (size_t)n, CSBQ_HOST))) return rc;
+    ALLOC(grad, GATE_NW + 1);
+    if ((rc = gate_grad_dev(ctx, 0, n, dp.p, df.p, dl.p, dW.p, dpw.p, part, grad.p))) return rc;
+    std::vector<float> g(GATE_NW + 1);
+    HIPC(hipMemcpyAsync(g.data(), grad.p, g.size() * 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIPC(hipStreamSynchronize(ctx->stream));
+    std::memcpy(grad_out, g.data(), GATE_NW * 4);
+    if (loss_out) *loss_out = g[GATE_NW];
+    return CSBQ_OK;
+}
+
+int csbq_gate_train(csbq_ctx* ctx, const float* feat, const int8_t* label, int64_t n, const float* posw, int epochs,
+                    int batch, float lr, uint64_t seed, float* W, float* loss_out)
+{
+    if (!ctx) return CSBQ_EINVAL;
+    ctx->err.clear();
+    if (!W || !feat || !label || !posw || n <= 0 || epochs <= 0 || batch <= 0 || !(lr > 0))
+        return ctx->fail(CSBQ_EINVAL, "bad arguments");
+    HIPC(hipSetDevice(ctx->opt.device));
+    hipStream_t st = ctx->stream;
+    DBuf<float> dW, df, dpw, part, grad, m, v;
+    DBuf<int8_t> dl;
+    DBuf<int64_t> dp;
+    int rc;
+    if ((rc = to_device(ctx, dW, W, GATE_NW, CSBQ_HOST))) return rc;
+    if ((rc = to_device(ctx, df, feat, (size_t)n * GATE_NF, CSBQ_HOST))) return rc;
+    if ((rc = to_device(ctx, dl, label, (size_t)n, CSBQ_HOST))) return rc;
+    if ((rc = to_device(ctx, dpw, posw, GATE_NO, CSBQ_HOST))) return rc;
+    std::vector<float> zero(GATE_NW, 0.f);
+    if ((rc = to_device(ctx, m, zero.data(), GATE_NW, CSBQ_HOST))) return rc;
+    if ((rc = to_device(ctx, v, zero.data(), GATE_NW, CSBQ_HOST))) return rc;
+    ALLOC(grad, GATE_NW + 1);
+    ALLOC(dp, (size_t)n);
+    std::vector<int64_t> id((size_t)n);
+    for (int64_t i = 0; i < n; ++i) id[i] = i;
+    std::mt19937_64 rng(seed);
+    int step = 0;
+    std::vector<float> g(GATE_NW + 1);
+    for (int ep = 0; ep < epochs; ++ep) {
+        std::shuffle(id.begin(), id.end(), rng);
+        HIPC(hipMemcpyAsync(dp.p, id.data(), (size_t)n * 8, hipMemcpyHostToDevice, st));
+        double lsum = 0.0;
+        for (int64_t off = 0; off < n; off += batch) {
+            const int64_t nb = std::min<int64_t>(batch, n - off);
+            if ((rc = gate_grad_dev(ctx, off, nb, dp.p, df.p, dl.p, dW.p, dpw.p, part, grad.p))) return rc;
+            LCHK(launch_gate_adam(st, dW.p, grad.p, m.p, v.p, lr, 0.9f, 0.999f, 1e-8f, ++step));
+            HIPC(hipMemcpyAsync(g.data() + GATE_NW, grad.p + GATE_NW, 4, hipMemcpyDeviceToHost, st));
+            HIPC(hipStreamSynchronize(st));
+            lsum += (double)g[GATE_NW] * (double)nb;
+        }
+        if (loss_out) loss_out[ep] = (float)(lsum / (double)n);
+    }
+    HIPC(hipMemcpyAsync(W, dW.p, GATE_NW * 4, hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    return CSBQ_OK;
+}
+
+int csbq_gate_dataset(csbq_ctx* ctx, const double* sigma, int64_t T, const double* x, const int64_t* tgt_node,
+                      double label_tol, int64_t cap, float* feat_out, int8_t* label_out, int8_t* crit_out,
+                      int64_t* n_out)
+{
+    if (!ctx) return CSBQ_EINVAL;
+    ctx->err.clear();
+    if (!feat_out || !label_out || !n_out || cap <= 0 || !(label_tol > 0) || T <= 0)
+        return ctx->fail(CSBQ_EINVAL, "bad arguments");
+    if (ctx->opt.gate != CSBQ_GATE_CRITERION)
+        return ctx->fail(CSBQ_ESTATE, "labels are generated with the criterion gate");
+    // the evaluation leaves the candidate pairs, their classification
+    // (singularity estimates for the special quadrature) and the element-major
+    // order in the context
+    std::vector<double> us((size_t)T * 3), ud((size_t)T * 3);
+    int rc = csbq_eval(ctx, sigma, T, x, tgt_node, us.data(), ud.data(), CSBQ_HOST);
+    if (rc) return rc;
+    double ms = 0.0, md = 0.0;
+    for (double v : us) ms = std::max(ms, std::fabs(v));
+    for (double v : ud) md = std::max(md, std::fabs(v));
+    const double PI_ = 3.14159265358979323846;
+    const double thr_s = label_tol * ms * 8.0 * PI_, thr_d = label_tol * md * 4.0 * PI_ / 3.0;
+    hipStream_t st = ctx->stream;
+    const int64_t P = ctx->last_P;
+    const int E = ctx->E;
+    const int64_t* tn = tgt_node ? ctx->tn_d.p : nullptr;
+    // features of every pair
+    ALLOC(ctx->gfeat, (size_t)P * GATE_NF + GATE_NF);
+    LCHK(launch_gate_features(st, P, ctx->pe.p, ctx->pt.p, ctx->xt.p, T, tn, ctx->circ.p, ctx->info.p, ctx->band.p,
+                              (float)std::log10(ctx->gc.tol), ctx->gfeat.p));
+    // every pair through every tier: upsampled rules by element runs of the
+    // element-major order, special quadrature on all
+    std::vector<int> hperm((size_t)P), hpe((size_t)P);
+    HIPC(hipMemcpyAsync(hperm.data(), ctx->perm.p, (size_t)P * 4, hipMemcpyDeviceToHost, st));
+    HIPC(hipMemcpyAsync(hpe.data(), ctx->pe.p, (size_t)P * 4, hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    std::vector<int> wd;
+    for (int64_t i = 0; i < P;) {
+        const int e = hpe[hperm[i]];
+        int64_t j = i;
+        while (j < P && hpe[hperm[j]] == e) ++j;
+        for (int64_t o = i; o < j; o += UP_PAIRS) {
+            wd.push_back((int)o);
+            wd.push_back((int)std::min<int64_t>(UP_PAIRS, j - o));
+            wd.push_back(e);
+        }
+        i = j;
+    }
+    const int nw = (int)(wd.size() / 3);
+    DBuf<int> dwd;
+    if ((rc = to_device(ctx, dwd, wd.data(), wd.size(), CSBQ_HOST))) return rc;
+    DBuf<double> cup[NUP], cfull;
+    for (int ti = 0; ti < NUP; ++ti) {
+        ALLOC(cup[ti], (size_t)P * 6 + 1);
+        ALLOC(ctx->swf[ti], (size_t)ctx->Mtot[ti] * 3);
+        LCHK(launch_sigma_up(st, E, up_ns(ti), up_nt(ti), ctx->sh.p, ctx->Lup[ti].p, ctx->cpw[ti].p, ctx->swf[ti].p,
+                             ctx->Mtot[ti]));
+        LCHK(launch_corr_up(st, up_pts(ti), nw, dwd.p, ctx->perm.p, ctx->pt.p, ctx->xt.p, T, ctx->cpy[ti].p,
+                            ctx->cpn[ti].p, ctx->swf[ti].p, ctx->Mtot[ti], ctx->boff.p, ctx->by.p, ctx->bn.p,
+                            ctx->bsw.p, ctx->Nb, cup[ti].p));
+    }
+    ALLOC(cfull, (size_t)P * 6 + 1);
+    std::vector<int> hband((size_t)2 * E);
+    HIPC(hipMemcpy(hband.data(), ctx->band.p, hband.size() * 4, hipMemcpyDeviceToHost));
+    int mt_max = 0;
+    for (int k = 0; k < E; ++k) mt_max = std::max(mt_max, hband[2 * k + 1]);
+    ALLOC(ctx->work, (size_t)4 * P + 4);
+    LCHK(launch_corr_full(st, (int)P, ctx->perm.p, ctx->pe.p, ctx->pt.p, ctx->xt.p, T, tn, ctx->clq.p, ctx->sh.p,
+                          ctx->info.p, ctx->band.p, ctx->cls.p, ctx->boff.p, ctx->by.p, ctx->bn.p, ctx->bsw.p,
+                          ctx->Nb, ctx->roff.p, ctx->rth.p, ctx->rw.p, ctx->nb, ctx->lx.p, ctx->lw.p, ctx->nl,
+                          ctx->rcs.p, ctx->rsn.p, ctx->romc.p, ctx->gc, cfull.p, ctx->err_d.p, ctx->work.p, mt_max));
+    DBuf<int8_t> lab;
+    ALLOC(lab, (size_t)P + 1);
+    LCHK(launch_gate_labels(st, P, cup[0].p, cup[1].p, cup[2].p, cfull.p, thr_s, thr_d, lab.p));
+    ctx->ph_ok = false;   // the work counters now describe the label run
+    // a strided sample of at most cap pairs
+    const int64_t stride = (P + cap - 1) / cap;
+    const int64_t nsel = stride > 0 ? (P + stride - 1) / stride : 0;
+    if (nsel > 0) {
+        HIPC(hipMemcpy2DAsync(feat_out, GATE_NF * 4, ctx->gfeat.p, (size_t)stride * GATE_NF * 4, GATE_NF * 4,
+                              (size_t)nsel, hipMemcpyDeviceToHost, st));
+        HIPC(hipMemcpy2DAsync(label_out, 1, lab.p, (size_t)stride, 1, (size_t)nsel, hipMemcpyDeviceToHost, st));
+        if (crit_out)
+            HIPC(hipMemcpy2DAsync(crit_out, 1, ctx->tier.p, (size_t)stride, 1, (size_t)nsel, hipMemcpyDeviceToHost,
+                                  st));
+    }
+    HIPC(hipStreamSynchronize(st));
+    *n_out = nsel;
+    return CSBQ_OK;
+}
+
 int csbq_stats(const csbq_ctx* ctx, char* buf, int64_t cap)
 {
     if (!ctx || !buf || cap <= 0) return CSBQ_EINVAL;
@@ -1117,6 +1430,12 @@ int csbq_stats(const csbq_ctx* ctx, char* buf, int64_t cap)
                   (long long)ctx->last_T, (long long)ctx->last_P, (long long)ctx->last_nup[0],
                   (long long)ctx->last_nup[1], (long long)ctx->last_nup[2], (long long)ctx->last_nf,
                   ctx->last_err_flags, (long long)ctx->Nb);
+    s += tmp;
+    if (ctx->last_esc >= 0) {
+        std::snprintf(tmp, sizeof tmp, ", \"gate_escalated\": %lld", (long long)ctx->last_esc);
+        s += tmp;
+    }
+    std::snprintf(tmp, sizeof tmp, ", \"far_tpt\": %d, \"far_chunk\": %lld", ctx->far_tpt, (long long)ctx->far_chunk);
     s += tmp;
     if (ctx->ph_ok && ctx->last_nf > 0) {
         std::vector<int> wk((size_t)4 * ctx->last_nf);

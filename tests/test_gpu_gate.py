@@ -1,0 +1,229 @@
+"""Learned correction-tier gate: the bf16-MFMA forward pass and the FP32
+gradients against plain numpy references, training on a learnable synthetic
+task, the method-generated labels, and the mixed-precision evaluation with the
+trained gate against the oracle."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _bf16(a):
+    u = np.ascontiguousarray(a, np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000).astype(np.uint32)
+    return u.view(np.float32)
+
+
+def _unpack(w):
+    from paper_2310_00889_amd import gate
+    return {k: v.astype(np.float64) for k, v in gate.unpack(np.asarray(w, np.float32)).items()}
+
+
+def _forward_bf16(w, x):
+    """What the inference kernel computes: bf16 inputs, weights and hidden
+    activations, wide accumulation, FP32 biases."""
+    p = {k: _bf16(v).astype(np.float64) if k.startswith("W") else v for k, v in _unpack(w).items()}
+    h = _bf16(x).astype(np.float64)
+    for i in (1, 2, 3):
+        h = _bf16(np.maximum(h @ p[f"W{i}"] + p[f"b{i}"], 0.0)).astype(np.float64)
+    return h @ p["W4"] + p["b4"]
+
+
+def _loss_grad(w, x, lab, posw):
+    """Mean weighted ordinal cross-entropy and its gradient, float64."""
+    p = _unpack(w)
+    x = x.astype(np.float64)
+    n = x.shape[0]
+    a1 = x @ p["W1"] + p["b1"]
+    h1 = np.maximum(a1, 0)
+    a2 = h1 @ p["W2"] + p["b2"]
+    h2 = np.maximum(a2, 0)
+    a3 = h2 @ p["W3"] + p["b3"]
+    h3 = np.maximum(a3, 0)
+    z = h3 @ p["W4"] + p["b4"]
+    y = (lab[:, None] > np.arange(4)[None, :]).astype(np.float64)
+    sp = np.logaddexp(0, z)
+    loss = np.sum(posw * y * (sp - z) + (1 - y) * sp) / n
+    s = 1 / (1 + np.exp(-z))
+    dz = (-posw * y * (1 - s) + (1 - y) * s) / n
+    g = {"W4": h3.T @ dz, "b4": dz.sum(0)}
+    d3 = (dz @ p["W4"].T) * (a3 > 0)
+    g["W3"], g["b3"] = h2.T @ d3, d3.sum(0)
+    d2 = (d3 @ p["W3"].T) * (a2 > 0)
+    g["W2"], g["b2"] = h1.T @ d2, d2.sum(0)
+    d1 = (d2 @ p["W2"].T) * (a1 > 0)
+    g["W1"], g["b1"] = x.T @ d1, d1.sum(0)
+    from paper_2310_00889_amd import gate
+    return loss, np.concatenate([g[k].ravel() for k, _ in gate.SHAPES])
+
+
+@pytest.fixture(scope="module")
+def ev():
+    import torch
+    import paper_2310_00889_amd as pk
+    torch.zeros(1, device="cuda")
+    e = pk.Evaluator(quad_tol=1e-7, precision="mixed")
+    yield e
+    e.close()
+
+
+def _features(n, seed):
+    rng = np.random.default_rng(seed)
+    f = np.zeros((n, 16), np.float32)
+    f[:, :12] = rng.normal(0, 1, (n, 12))
+    return f
+
+
+def test_gate_forward_matches_numpy(ev):
+    from paper_2310_00889_amd import gate
+    w = gate.init_weights(seed=3)
+    w[gate.GATE_NW - 4:] = np.array([0.3, -0.2, 0.1, -0.4], np.float32)
+    x = _features(1000, 4)   # 1000 = 62 full tiles of 16 and a ragged one
+    ev.gate_load(w, 0.05)
+    tier, esc, lg = ev.gate_infer(x)
+    ref = _forward_bf16(w, x)
+    err = np.abs(lg - ref) / (1 + np.abs(ref))
+    print("forward max err", err.max(), flush=True)
+    assert err.max() < 2e-2
+    s = 1 / (1 + np.exp(-ref))
+    t_ref = np.zeros(len(x), int)
+    for k in range(4):
+        t_ref = np.where(s[:, k] > 0.5, k + 1, t_ref)
+    near = np.any(np.abs(s - 0.5) < 5e-3, axis=1)
+    assert np.array_equal(tier[~near], t_ref[~near])
+
+
+def test_gate_gradient_matches_numpy(ev):
+    from paper_2310_00889_amd import gate
+    w = gate.init_weights(seed=5)
+    x = _features(700, 6)
+    lab = np.random.default_rng(7).integers(0, 5, 700).astype(np.int8)
+    posw = np.array([4, 3, 2, 1], np.float32)
+    g, loss = ev.gate_grad(w, x, lab, posw)
+    lref, gref = _loss_grad(w, x, lab, posw)
+    rel = np.linalg.norm(g - gref) / np.linalg.norm(gref)
+    print("loss", loss, lref, "grad rel", rel, flush=True)
+    assert abs(loss - lref) < 1e-5 * max(1.0, abs(lref))
+    assert rel < 1e-4
+    # every parameter block carries gradient
+    off = 0
+    for name, shp in gate.SHAPES:
+        n = int(np.prod(shp))
+        assert np.abs(g[off:off + n]).max() > 0, name
+        off += n
+
+
+def test_gate_training_learns(ev):
+    from paper_2310_00889_amd import gate
+    x = _features(20000, 8)
+    lab = np.clip(np.floor(1.25 * (x[:, 0] + 2.0)), 0, 4).astype(np.int8)
+    w0 = gate.init_weights(seed=9)
+    w, losses = ev.gate_train(x, lab, np.ones(4, np.float32), w0, epochs=12, batch=1024, lr=3e-3, seed=1)
+    ev.gate_load(w, 0.05)
+    tier, _, _ = ev.gate_infer(x)
+    acc = np.mean(tier == lab)
+    print("losses", losses, "accuracy", acc, flush=True)
+    assert losses[-1] < 0.5 * losses[0]
+    assert acc > 0.85   # the labels jump at sharp thresholds of one feature
+
+
+def test_gate_dataset_labels(ev):
+    """Method-generated labels on a pipe section: the criterion's tier meets
+    the tolerance, so the cheapest adequate tier (the label) lies at or below
+    it for all but a sliver of pairs."""
+    sc = synth.small_pipe_scene(n_panels=6, n_spheres=3)
+    ev.set_geometry(sc)
+    tn = np.arange(sc.n_nodes, dtype=np.int64)
+    f, lab, crit = ev.gate_dataset(sc.sigma, None, tn, label_tol=1e-8, cap=1 << 20)
+    print("labels", np.bincount(lab, minlength=5), "criterion", np.bincount(crit, minlength=5), flush=True)
+    assert len(lab) > 1000
+    assert np.all((lab >= 0) & (lab <= 4)) and np.all((crit >= 0) & (crit <= 4))
+    assert np.mean(lab <= crit) > 0.99
+    # own-element pairs are special quadrature in both
+    own = f[:, 11] > 0.5
+    assert own.sum() == sc.n_nodes and np.all(crit[own] == 4)
+
+
+def _trained():
+    from paper_2310_00889_amd import gate
+    if not os.path.exists(gate.DEFAULT_WEIGHTS):
+        pytest.skip("no trained gate weights in the package")
+    return gate.load_weights()
+
+
+def test_mixed_mlp_gate_parity():
+    """Mixed precision with the trained gate: the pipe section on and off the
+    surface and sampled targets of the 1000-sphere scene per class, 1e-6."""
+    import torch
+    import paper_2310_00889_amd as pk
+    w, meta = _trained()
+    e = pk.Evaluator(quad_tol=1e-7, precision="mixed", gate="mlp")
+    e.gate_load(w, float(meta["tau_esc"]))
+    sc = synth.small_pipe_scene(n_panels=6, n_spheres=3)
+    e.set_geometry(sc)
+    rng = np.random.default_rng(21)
+    tn = rng.choice(sc.n_nodes, 200, replace=False)
+    us, ud = e.eval(sc.sigma, None, tn)
+    uso, udo = oracle.evaluate(sc, None, None, tn)
+    r = [np.abs(us - uso).max() / np.abs(uso).max(), np.abs(ud - udo).max() / np.abs(udo).max()]
+    print("mlp on-surface", r, e.stats().get("gate_escalated"), flush=True)
+    assert max(r) < 1e-6
+    sc3 = synth.config3()
+    e.set_geometry(sc3)
+    sig = torch.from_numpy(sc3.sigma).cuda()
+    tn3 = torch.from_numpy(sc3.tgt_node).cuda()
+    us, ud = e.eval(sig, None, tn3)
+    torch.cuda.synchronize()
+    us, ud = us.cpu().numpy(), ud.cpu().numpy()
+    st = e.stats()
+    print("config3 mlp stats", st, flush=True)
+    idx = np.concatenate([rng.choice(np.where(sc3.tgt_class == c)[0], 12, replace=False) for c in (0, 1, 2)])
+    uso, udo = oracle.evaluate(sc3, None, None, sc3.tgt_node[idx])
+    for u, uo, what in ((us[idx], uso, "S"), (ud[idx], udo, "D")):
+        for c in (0, 1, 2):
+            m = sc3.tgt_class[idx] == c
+            err = np.abs(u[m] - uo[m]).max() / np.abs(uo[m]).max()
+            print(f"mlp {what} class {c}: {err:.2e}", flush=True)
+            assert err < 1e-6, (what, c, err)
+    e.close()
+
+
+def test_config5_mlp_gate_speedup():
+    """2000 spheres in the pipe scaled by 10**(1/3) (1,075,200 on-surface
+    targets), mixed precision at quad_tol 1e-7: the trained gate spends less
+    time on the near field (classification + corrections) than the criterion,
+    at the same 1e-6 accuracy on sampled targets."""
+    import torch
+    import paper_2310_00889_amd as pk
+    w, meta = _trained()
+    sc = synth.config5()
+    sig = torch.from_numpy(sc.sigma).cuda()
+    tn = torch.from_numpy(sc.tgt_node).cuda()
+    nwall = sc.bodies[0].n_panels * sc.ns * sc.nt
+    rng = np.random.default_rng(31)
+    idx = np.concatenate([rng.choice(nwall, 4, replace=False), nwall + rng.choice(sc.n_nodes - nwall, 8, replace=False)])
+    uso, udo = oracle.evaluate(sc, None, None, sc.tgt_node[idx])
+    near = {}
+    for gate in ("criterion", "mlp"):
+        e = pk.Evaluator(quad_tol=1e-7, precision="mixed", gate=gate)
+        if gate == "mlp":
+            e.gate_load(w, float(meta["tau_esc"]))
+        e.set_geometry(sc)
+        for _ in range(2):      # the second evaluation is timed (the first tunes the smooth sum)
+            us, ud = e.eval(sig, None, tn)
+        torch.cuda.synchronize()
+        st = e.stats()
+        ms = st["ms"]
+        near[gate] = ms["classify"] + ms["corr_up"] + ms["corr_full"]
+        us, ud = us.cpu().numpy()[idx], ud.cpu().numpy()[idx]
+        es = np.abs(us - uso).max() / np.abs(uso).max()
+        ed = np.abs(ud - udo).max() / np.abs(udo).max()
+        print(f"config5 {gate}: near field {near[gate]:.1f} ms, errors S {es:.2e} D {ed:.2e}, stats {st}", flush=True)
+        assert es < 1e-6 and ed < 1e-6
+        e.close()
+    assert near["mlp"] < near["criterion"]
