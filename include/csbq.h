@@ -158,6 +158,24 @@ int csbq_smooth_sum(csbq_ctx* ctx, const double* sigma, int64_t n_tgt, const dou
 int csbq_eval_batch(csbq_ctx* ctx, const double* sigma, int64_t n_tgt, const double* x, const int64_t* tgt_node,
                     const int32_t* tgt_group, double* u_sl, double* u_dl, int mem);
 
+/* ---- Setup / apply split (the paper's precomputed corrections, Section
+   3.2.1 and Section 3.3, in density form).  csbq_plan evaluates like
+   csbq_eval_batch and freezes what depends on the geometry and targets only:
+   the candidate pairs, their tiers and special-quadrature rules, the
+   smooth-sum blocks; the per-density part (density coefficients, smooth sum,
+   corrections, reduction) is captured as a HIP graph.  csbq_apply replays it
+   for a new density on the same geometry and targets, without a search,
+   classification or host round trip inside, and returns once the outputs are
+   in place.  Rules were chosen for the planning density's band limits: a
+   density with a wider band (more Fourier or Legendre modes above the
+   tolerance on some element) makes csbq_apply fail with CSBQ_ESTATE (plan
+   again).  Any other evaluation call, set_geometry or destroy drops the plan.
+   Arrays as in csbq_eval_batch; sigma, u_sl and u_dl of csbq_apply live in
+   `mem`. */
+int csbq_plan(csbq_ctx* ctx, const double* sigma, int64_t n_tgt, const double* x, const int64_t* tgt_node,
+              const int32_t* tgt_group, double* u_sl, double* u_dl, int mem);
+int csbq_apply(csbq_ctx* ctx, const double* sigma, double* u_sl, double* u_dl, int mem);
+
 /* ---- Learned correction-tier gate (an extension beyond the paper; the
    criterion of Section 3.2's error estimates stays the fallback and the
    judge).  A perceptron with three hidden layers of 64 ReLU units maps

@@ -63,6 +63,8 @@ def load_library():
     lib.csbq_eval_batch.argtypes = [vp, dp, C.c_int64, dp, lp, ip, dp, dp, C.c_int]
     lib.csbq_smooth_sum.argtypes = [vp, dp, C.c_int64, dp, lp, dp, dp, C.c_int]
     lib.csbq_stats.argtypes = [vp, C.c_char_p, C.c_int64]
+    lib.csbq_plan.argtypes = [vp, dp, C.c_int64, dp, lp, ip, dp, dp, C.c_int]
+    lib.csbq_apply.argtypes = [vp, dp, dp, dp, C.c_int]
     lib.csbq_gate_load.argtypes = [vp, dp, C.c_float]
     lib.csbq_gate_infer.argtypes = [vp, dp, C.c_int64, dp, dp, dp]
     lib.csbq_gate_grad.argtypes = [vp, dp, dp, dp, C.c_int64, dp, dp, dp]
@@ -164,6 +166,7 @@ class Evaluator:
 
     def _call(self, fn, name, sigma, x, tgt_node, out_sl, out_dl, tgt_group=None, batch=False):
         dev = _is_torch_cuda(sigma)
+        self._plan_T = int(tgt_node.shape[0] if tgt_node is not None else x.shape[0])
         if dev:
             import torch
             T = int(tgt_node.shape[0] if tgt_node is not None else x.shape[0])
@@ -210,6 +213,31 @@ class Evaluator:
     def smooth_sum(self, sigma, x=None, tgt_node=None, out_sl=None, out_dl=None):
         """(u_S, u_D) of the plain smooth Nystrom sum (no corrections)."""
         return self._call(self._lib.csbq_smooth_sum, "csbq_smooth_sum", sigma, x, tgt_node, out_sl, out_dl)
+
+    # ---- setup / apply split
+    def plan(self, sigma, x=None, tgt_node=None, out_sl=None, out_dl=None, tgt_group=None):
+        """Evaluate and freeze the plan (pairs, tiers, rules, smooth-sum blocks)
+        for later apply() calls on the same targets."""
+        return self._call(self._lib.csbq_plan, "csbq_plan", sigma, x, tgt_node, out_sl, out_dl, tgt_group,
+                          batch=True)
+
+    def apply(self, sigma, out_sl=None, out_dl=None):
+        """(u_S, u_D) of a new density under the frozen plan (graph replay)."""
+        if _is_torch_cuda(sigma):
+            import torch
+            T = self._plan_T
+            if out_sl is None:
+                out_sl = torch.empty((T, 3), dtype=torch.float64, device=sigma.device)
+            if out_dl is None:
+                out_dl = torch.empty((T, 3), dtype=torch.float64, device=sigma.device)
+            self._check(self._lib.csbq_apply(self._h, _ptr(sigma), _ptr(out_sl), _ptr(out_dl), CSBQ_DEVICE),
+                        "csbq_apply")
+            return out_sl, out_dl
+        sigma = np.ascontiguousarray(sigma, np.float64)
+        usl = np.zeros((self._plan_T, 3))
+        udl = np.zeros((self._plan_T, 3))
+        self._check(self._lib.csbq_apply(self._h, _ptr(sigma), _ptr(usl), _ptr(udl), CSBQ_HOST), "csbq_apply")
+        return usl, udl
 
     # ---- learned gate
     def gate_load(self, weights, tau_esc=0.05):

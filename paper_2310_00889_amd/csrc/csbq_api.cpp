@@ -207,6 +207,22 @@ struct csbq_ctx {
     DBuf<uint8_t> gesc, gflag;
     DBuf<int> gsel, gnsel;
     int64_t last_esc = -1;
+    // frozen evaluation plan (pairs, tiers, rules, smooth-sum blocks of the
+    // last evaluation) and its apply sequence captured as a HIP graph
+    struct Plan {
+        bool valid = false;
+        int64_t T = 0;
+        int nwaves[NUP] = {0, 0, 0};
+        int nfull = 0, full_start = 0, mt_max = 0, ntiles = 0, tpt = 2;
+        bool mixed = false;
+        const int64_t* tn = nullptr;
+        hipStream_t gst = nullptr;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+    } plan;
+    DBuf<int> band_apply;
+    int last_ntiles = 0;
     DBuf<unsigned char> cub_tmp;
     // statistics of the last evaluation
     Phase ph[kNPhase];
@@ -220,6 +236,8 @@ struct csbq_ctx {
         return code;
     }
 };
+
+static void plan_drop(csbq_ctx* ctx);
 
 #define HIPC(call)                                                                             \
     do {                                                                                       \
@@ -475,6 +493,10 @@ int csbq_destroy(csbq_ctx* ctx)
     ctx->off.release();
     ctx->tier.release();
     ctx->cub_tmp.release();
+    plan_drop(ctx);
+    if (ctx->plan.e0) (void)hipEventDestroy(ctx->plan.e0);
+    if (ctx->plan.e1) (void)hipEventDestroy(ctx->plan.e1);
+    if (ctx->plan.gst) (void)hipStreamDestroy(ctx->plan.gst);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
     return CSBQ_OK;
@@ -528,6 +550,7 @@ int csbq_set_geometry_batch(csbq_ctx* ctx, int32_t n_bodies, const int32_t* body
         return ctx->fail(CSBQ_EINVAL, "missing geometry arrays");
     if (mem != CSBQ_HOST && mem != CSBQ_DEVICE) return ctx->fail(CSBQ_EINVAL, "bad mem flag");
     HIPC(hipSetDevice(ctx->opt.device));
+    plan_drop(ctx);
     ctx->have_geom = false;
     // body tables are small: bring them to the host for validation
     std::vector<int32_t> np(n_bodies), sg(n_bodies), bg(n_bodies, 0);
@@ -793,8 +816,9 @@ static void far_tiles(const csbq_ctx* ctx, const std::vector<int64_t>& tr, bool 
 }
 
 // Launch shape of the smooth sum, chosen by timing: targets per thread 1/2/4
-// times 8192/32768 sources per chunk, each timed once on a sample of the
-// largest group (about 2e9 pairs at most); cached per (targets, sources,
+// times 8192/32768 sources per chunk, each timed once on the largest group
+// (its first 4e10 / sources targets at most, so that a sample still fills
+// the device with thousands of blocks); cached per (targets, sources,
 // precision).  Small sums keep the default shape.
 static int tune_far(csbq_ctx* ctx, int64_t T, const std::vector<int64_t>& tr, bool native, bool mixed)
 {
@@ -819,7 +843,7 @@ static int tune_far(csbq_ctx* ctx, int64_t T, const std::vector<int64_t>& tr, bo
     if (ptot < 2e8) return CSBQ_OK;
     const int e0 = ctx->h_gel[gbig], e1 = ctx->h_gel[gbig + 1];
     const int64_t S = native ? (int64_t)(e1 - e0) * NPE : ctx->h_boff[e1] - ctx->h_boff[e0];
-    const int64_t t_cap = std::max<int64_t>(4096, (int64_t)(2e9 / std::max<int64_t>(S, 1))) / 1024 * 1024;
+    const int64_t t_cap = std::max<int64_t>(16384, (int64_t)(4e10 / std::max<int64_t>(S, 1))) / 1024 * 1024;
     const double* sy = native ? ctx->ny.p : ctx->by.p;
     const double* sn = native ? ctx->nn.p : ctx->bn.p;
     const double* ss = native ? ctx->sw.p : ctx->bsw.p;
@@ -884,7 +908,19 @@ static int far_sum(csbq_ctx* ctx, int64_t T, bool native, const std::vector<int6
     if (T > 0)
         LCHK(launch_far(ctx->stream, T, ctx->xt.p, sy, sn, ss, Ns, ctx->tiles.p, (int)tl.size(), ctx->part.p, mixed,
                         ctx->mix_near2, ctx->far_tpt));
+    ctx->last_ntiles = (int)tl.size();
     return CSBQ_OK;
+}
+
+// drop a frozen plan and its graph
+static void plan_drop(csbq_ctx* ctx)
+{
+    auto& pl = ctx->plan;
+    if (pl.exec) (void)hipGraphExecDestroy(pl.exec);
+    if (pl.graph) (void)hipGraphDestroy(pl.graph);
+    pl.exec = nullptr;
+    pl.graph = nullptr;
+    pl.valid = false;
 }
 
 static int outputs_back(csbq_ctx* ctx, int64_t T, double* u_sl, double* u_dl, int mem, double** usl_dev,
@@ -921,6 +957,7 @@ int csbq_smooth_sum(csbq_ctx* ctx, const double* sigma, int64_t T, const double*
 {
     if (!ctx) return CSBQ_EINVAL;
     ctx->err.clear();
+    plan_drop(ctx);
     HIPC(hipSetDevice(ctx->opt.device));
     const double* sig;
     const int64_t* tn;
@@ -951,6 +988,7 @@ int csbq_eval_batch(csbq_ctx* ctx, const double* sigma, int64_t T, const double*
 {
     if (!ctx) return CSBQ_EINVAL;
     ctx->err.clear();
+    plan_drop(ctx);
     HIPC(hipSetDevice(ctx->opt.device));
     hipStream_t st = ctx->stream;
     ctx->ph_ok = false;
@@ -1157,7 +1195,129 @@ int csbq_eval_batch(csbq_ctx* ctx, const double* sigma, int64_t T, const double*
     for (int ti = 0; ti < NUP; ++ti) ctx->last_nup[ti] = npair[ti];
     ctx->last_nf = nfull;
     ctx->ph_ok = true;
+    {
+        auto& pl = ctx->plan;
+        pl.T = T;
+        for (int ti = 0; ti < NUP; ++ti) pl.nwaves[ti] = nwaves[ti];
+        pl.nfull = nfull;
+        pl.full_start = full_start;
+        pl.mt_max = mt_max;
+        pl.ntiles = ctx->last_ntiles;
+        pl.tpt = ctx->far_tpt;
+        pl.mixed = ctx->opt.precision == CSBQ_MIXED;
+        pl.tn = tn;
+    }
     return finish(ctx, T, u_sl, u_dl, mem);
+}
+
+// The per-density part of an evaluation under a frozen plan: density
+// coefficients (band checked against the plan's), the smooth sum over the
+// plan's blocks, the corrections of the plan's tiers and rules, the
+// reduction into the context's output buffers.  No allocation, no host
+// synchronisation, no memset: the sequence is captured as a graph.
+static int enqueue_apply(csbq_ctx* ctx, hipStream_t st)
+{
+    const auto& pl = ctx->plan;
+    const int E = ctx->E;
+    const int64_t N = ctx->N, T = pl.T;
+    LCHK(launch_fill_i32(st, 1, ctx->err_d.p, 0));
+    LCHK(launch_prep_sigma(st, E, ctx->sig_d.p, ctx->nw.p, N, ctx->sw.p, ctx->sh.p, ctx->band_apply.p,
+                           0.1 * ctx->gc.tol, ctx->info.p, ctx->circ.p, ctx->gc, nullptr));
+    LCHK(launch_band_check(st, E, ctx->band_apply.p, ctx->band.p, ctx->err_d.p));
+    LCHK(launch_sigma_up(st, E, up_ns(0), up_nt(0), ctx->sh.p, ctx->Lup[0].p, ctx->cpw[0].p, ctx->swf[0].p,
+                         ctx->Mtot[0]));
+    LCHK(launch_sigma_base(st, E, ctx->info.p, ctx->boff.p, ctx->sw.p, N, ctx->swf[0].p, ctx->Mtot[0], ctx->bsw.p,
+                           ctx->Nb));
+    LCHK(launch_far(st, T, ctx->xt.p, ctx->by.p, ctx->bn.p, ctx->bsw.p, ctx->Nb, ctx->tiles.p, pl.ntiles, ctx->part.p,
+                    pl.mixed, ctx->mix_near2, pl.tpt));
+    for (int ti = 0; ti < NUP; ++ti) {
+        if (!pl.nwaves[ti]) continue;
+        if (ti > 0)
+            LCHK(launch_sigma_up(st, E, up_ns(ti), up_nt(ti), ctx->sh.p, ctx->Lup[ti].p, ctx->cpw[ti].p,
+                                 ctx->swf[ti].p, ctx->Mtot[ti]));
+        LCHK(launch_corr_up(st, up_pts(ti), pl.nwaves[ti], ctx->wdesc[ti].p, ctx->sorted.p, ctx->pt.p, ctx->xt.p, T,
+                            ctx->cpy[ti].p, ctx->cpn[ti].p, ctx->swf[ti].p, ctx->Mtot[ti], ctx->boff.p, ctx->by.p,
+                            ctx->bn.p, ctx->bsw.p, ctx->Nb, ctx->corr.p));
+    }
+    LCHK(launch_corr_full(st, pl.nfull, ctx->sorted.p + pl.full_start, ctx->pe.p, ctx->pt.p, ctx->xt.p, T, pl.tn,
+                          ctx->clq.p, ctx->sh.p, ctx->info.p, ctx->band.p, ctx->cls.p, ctx->boff.p, ctx->by.p,
+                          ctx->bn.p, ctx->bsw.p, ctx->Nb, ctx->roff.p, ctx->rth.p, ctx->rw.p, ctx->nb, ctx->lx.p,
+                          ctx->lw.p, ctx->nl, ctx->rcs.p, ctx->rsn.p, ctx->romc.p, ctx->gc, ctx->corr.p, ctx->err_d.p,
+                          ctx->work.p, pl.mt_max));
+    LCHK(launch_reduce(st, T, ctx->tgroup.p, ctx->gnchunk.p, ctx->part.p, ctx->off.p, ctx->tier.p, ctx->corr.p,
+                       ctx->usl_d.p, ctx->udl_d.p));
+    return CSBQ_OK;
+}
+
+int csbq_plan(csbq_ctx* ctx, const double* sigma, int64_t T, const double* x, const int64_t* tgt_node,
+              const int32_t* tgt_group, double* u_sl, double* u_dl, int mem)
+{
+    if (!ctx) return CSBQ_EINVAL;
+    if (T <= 0) return ctx->fail(CSBQ_EINVAL, "a plan needs targets");
+    int rc = csbq_eval_batch(ctx, sigma, T, x, tgt_node, tgt_group, u_sl, u_dl, mem);
+    if (rc) return rc;
+    auto& pl = ctx->plan;
+    hipStream_t st = ctx->stream;
+    // everything the graph reads must live in the context
+    ALLOC(ctx->sig_d, (size_t)ctx->N * 3);
+    if (mem == CSBQ_DEVICE && tgt_node) {
+        ALLOC(ctx->tn_d, (size_t)T);
+        HIPC(hipMemcpyAsync(ctx->tn_d.p, tgt_node, (size_t)T * 8, hipMemcpyDeviceToDevice, st));
+        pl.tn = ctx->tn_d.p;
+    }
+    ALLOC(ctx->usl_d, (size_t)T * 3 + 1);
+    ALLOC(ctx->udl_d, (size_t)T * 3 + 1);
+    ALLOC(ctx->band_apply, (size_t)ctx->E * 2);
+    HIPC(hipStreamSynchronize(st));
+    if (!pl.gst) HIPC(hipStreamCreateWithFlags(&pl.gst, hipStreamNonBlocking));
+    if (!pl.e0) HIPC(hipEventCreateWithFlags(&pl.e0, hipEventDisableTiming));
+    if (!pl.e1) HIPC(hipEventCreateWithFlags(&pl.e1, hipEventDisableTiming));
+    HIPC(hipStreamBeginCapture(pl.gst, hipStreamCaptureModeThreadLocal));
+    rc = enqueue_apply(ctx, pl.gst);
+    hipGraph_t g = nullptr;
+    hipError_t he = hipStreamEndCapture(pl.gst, &g);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (he != hipSuccess) return ctx->fail(CSBQ_EHIP, std::string("graph capture failed: ") + hipGetErrorString(he));
+    pl.graph = g;
+    HIPC(hipGraphInstantiate(&pl.exec, g, nullptr, nullptr, 0));
+    pl.valid = true;
+    return CSBQ_OK;
+}
+
+int csbq_apply(csbq_ctx* ctx, const double* sigma, double* u_sl, double* u_dl, int mem)
+{
+    if (!ctx) return CSBQ_EINVAL;
+    ctx->err.clear();
+    auto& pl = ctx->plan;
+    if (!pl.valid) return ctx->fail(CSBQ_ESTATE, "no evaluation plan (csbq_plan)");
+    if (!sigma) return ctx->fail(CSBQ_EINVAL, "missing density");
+    if (mem != CSBQ_HOST && mem != CSBQ_DEVICE) return ctx->fail(CSBQ_EINVAL, "bad mem flag");
+    HIPC(hipSetDevice(ctx->opt.device));
+    hipStream_t st = ctx->stream;
+    const int64_t N = ctx->N, T = pl.T;
+    if (mem == CSBQ_HOST)
+        for (int64_t i = 0; i < N * 3; ++i)
+            if (!std::isfinite(sigma[i])) return ctx->fail(CSBQ_EINVAL, "density has NaN/Inf");
+    HIPC(hipMemcpyAsync(ctx->sig_d.p, sigma, (size_t)N * 3 * 8,
+                        mem == CSBQ_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, st));
+    HIPC(hipEventRecord(pl.e0, st));
+    HIPC(hipStreamWaitEvent(pl.gst, pl.e0, 0));
+    HIPC(hipGraphLaunch(pl.exec, pl.gst));
+    HIPC(hipEventRecord(pl.e1, pl.gst));
+    HIPC(hipStreamWaitEvent(st, pl.e1, 0));
+    const hipMemcpyKind k = mem == CSBQ_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    if (u_sl) HIPC(hipMemcpyAsync(u_sl, ctx->usl_d.p, (size_t)T * 3 * 8, k, st));
+    if (u_dl) HIPC(hipMemcpyAsync(u_dl, ctx->udl_d.p, (size_t)T * 3 * 8, k, st));
+    int flags = 0;
+    HIPC(hipMemcpyAsync(&flags, ctx->err_d.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    ctx->last_err_flags = flags;
+    if (flags & 32)
+        return ctx->fail(CSBQ_ESTATE, "the density's band exceeds the one the plan was built for: plan again");
+    return CSBQ_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -1339,6 +1499,7 @@ int csbq_gate_dataset(csbq_ctx* ctx, const double* sigma, int64_t T, const doubl
         return ctx->fail(CSBQ_EINVAL, "bad arguments");
     if (ctx->opt.gate != CSBQ_GATE_CRITERION)
         return ctx->fail(CSBQ_ESTATE, "labels are generated with the criterion gate");
+    plan_drop(ctx);
     // the evaluation leaves the candidate pairs, their classification
     // (singularity estimates for the special quadrature) and the element-major
     // order in the context

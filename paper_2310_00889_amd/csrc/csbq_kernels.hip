@@ -1717,7 +1717,40 @@ int launch_prep_sigma(hipStream_t st, int E, const double* sigma, const double* 
 {
     hipLaunchKernelGGL(k_prep_sigma, dim3(E), dim3(512), 0, st, E, sigma, nw, N, sw, sh, band, eta);
     LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_rnear, dim3((E + 127) / 128), dim3(128), 0, st, E, info, circ, band, gc, rnear);
+    if (rnear) {
+        hipLaunchKernelGGL(k_rnear, dim3((E + 127) / 128), dim3(128), 0, st, E, info, circ, band, gc, rnear);
+        LAUNCH_CHECK();
+    }
+    return 0;
+}
+
+// a density whose band exceeds the one a frozen evaluation plan was built
+// for (flag 32): the plan's rules were chosen for the narrower band
+__global__ void k_band_check(int E, const int* __restrict__ band_new, const int* __restrict__ band_plan,
+                             int* __restrict__ err)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    if (band_new[2 * e] > band_plan[2 * e] || band_new[2 * e + 1] > band_plan[2 * e + 1]) atomicOr(err, 32);
+}
+
+__global__ void k_fill_i32(int64_t n, int* __restrict__ v, int val)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) v[i] = val;
+}
+
+int launch_band_check(hipStream_t st, int E, const int* band_new, const int* band_plan, int* err)
+{
+    hipLaunchKernelGGL(k_band_check, dim3((E + 127) / 128), dim3(128), 0, st, E, band_new, band_plan, err);
+    LAUNCH_CHECK();
+    return 0;
+}
+
+int launch_fill_i32(hipStream_t st, int64_t n, int* v, int val)
+{
+    if (n == 0) return 0;
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, v, val);
     LAUNCH_CHECK();
     return 0;
 }

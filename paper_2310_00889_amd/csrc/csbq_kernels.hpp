@@ -21,6 +21,8 @@ int launch_base_build(hipStream_t st, int E, const ElemInfo* info, const int64_t
 int launch_prep_sigma(hipStream_t st, int E, const double* sigma, const double* nw, int64_t N, double* sw,
                       double* sh, int* band, double eta, const ElemInfo* info, const double* circ, GateConsts gc,
                       double* rnear);
+int launch_band_check(hipStream_t st, int E, const int* band_new, const int* band_plan, int* err);
+int launch_fill_i32(hipStream_t st, int64_t n, int* v, int val);
 int launch_sigma_up(hipStream_t st, int E, int ns_f, int nt_f, const double* sh, const double* Lup, const double* cpw,
                     double* swf, int64_t Mtot);
 int launch_sigma_base(hipStream_t st, int E, const ElemInfo* info, const int64_t* boff, const double* sw, int64_t N,
