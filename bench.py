@@ -30,6 +30,20 @@ THETA_FLOPS, THETA_MODE_FLOPS = 82, 18
 SNODE_FLOPS, SNODE_MODE_FLOPS = 800, 192
 
 
+def measured_traffic(kernel, precision):
+    """HBM bytes per launch of `kernel` from the committed memory-counter
+    record, or None when there is none or the kernels have changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_pipe100_spheres200_{precision}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    with open(os.path.join(ROOT, "paper_2310_00889_amd", "csrc", "csbq_kernels.hip"), "rb") as f:
+        sha = hashlib.sha1(f.read()).hexdigest()
+    return rec["traffic_bytes"] if rec.get("kernels_sha1") == sha else None
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -64,6 +78,8 @@ def main():
                     help="correction-tier gate (default: criterion for fp64, the trained network for mixed)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--copy-check", action="store_true",
+                    help="first copy 1 GiB device to device (a known-size reference for memory counters)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not supported"}))
@@ -88,6 +104,12 @@ def main():
     T = int(tn.shape[0])
     usl = torch.empty((T, 3), dtype=torch.float64, device="cuda")
     udl = torch.empty((T, 3), dtype=torch.float64, device="cuda")
+    if a.copy_check:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     log(f"bench: {T} targets, {ev.n_nodes} sources; warmup {a.warmup}")
     for _ in range(a.warmup):
         ev.eval(sig, None, tn, usl, udl)
@@ -117,7 +139,8 @@ def main():
     far_peak = FP64_PEAK_TFLOPS if a.precision == "fp64" else FP32_PEAK_TFLOPS
     peak = far_peak if dom == "far" else FP64_PEAK_TFLOPS
     roof = dict(kernel=far_kernel if dom == "far" else "k_corr_full", bound="alu", achieved=achieved,
-                peak=peak, unit="TFLOP/s", frac=achieved / peak, traffic=None)
+                peak=peak, unit="TFLOP/s", frac=achieved / peak,
+                traffic=measured_traffic(far_kernel if dom == "far" else "k_corr_full", a.precision))
     far_ach = FAR_FLOPS_PER_PAIR * float(T) * nsrc / (phases["far"] * 1e-3) / 1e12
     out = {
         "metric": METRIC, "value": value, "unit": "target evals/s", "n_gpus": 1, "steps": a.steps,
