@@ -95,6 +95,56 @@ __device__ inline void frame_at_x(const double* __restrict__ clq, double x, Fram
     frame_from_q(q, f);
 }
 
+// 1/x from the hardware reciprocal refined by two Newton steps (~1 ulp)
+__device__ __forceinline__ double rcp_nr(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = r * fma(-x, r, 2.0);
+    return r * fma(-x, r, 2.0);
+}
+
+// barycentric weights (as bary_weights / bary_weights_rel) with refined
+// hardware reciprocals in place of divisions
+__device__ inline void bary_weights_rcp(double x, double* l)
+{
+    double sum = 0.0;
+    int hit = -1;
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+        const double dx = x - c_gx[i];
+        if (dx == 0.0) hit = i;
+        l[i] = c_lam[i] * rcp_nr(dx);
+        sum += l[i];
+    }
+    if (hit >= 0) {
+#pragma unroll
+        for (int i = 0; i < NS; ++i) l[i] = (i == hit) ? 1.0 : 0.0;
+        return;
+    }
+    const double is = rcp_nr(sum);
+#pragma unroll
+    for (int i = 0; i < NS; ++i) l[i] *= is;
+}
+
+__device__ inline void bary_weights_rel_rcp(int i0, double du, double* l)
+{
+    if (du == 0.0) {
+#pragma unroll
+        for (int i = 0; i < NS; ++i) l[i] = (i == i0) ? 1.0 : 0.0;
+        return;
+    }
+    double sum = 0.0;
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+        const double dx = (i == i0) ? du : (c_gx[i0] - c_gx[i]) + du;
+        l[i] = c_lam[i] * rcp_nr(dx);
+        sum += l[i];
+    }
+    const double is = rcp_nr(sum);
+#pragma unroll
+    for (int i = 0; i < NS; ++i) l[i] *= is;
+}
+
 // position/tangent/radius only (for the distance searches of the
 // classification, which only steer estimates): barycentric interpolation with
 // the weights formed on the fly from the hardware reciprocal refined by two
@@ -1283,7 +1333,9 @@ __device__ __forceinline__ double wave_sum(double v)
 //     area element and r.n reduce to the scalars g = |x_c'| + eps (e1'.t cos +
 //     e2'.t sin) and eps' (|y_t x y_s| = eps sqrt(g^2 + eps'^2)), so a point
 //     costs one Fourier synthesis and a handful of flops.
+typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int SB = 16;
+static_assert(SB == 16, "the coefficient interpolation uses 16-row MFMA tiles");
 enum { R_E = 0, R_EP, R_SP, R_A13, R_A23, R_Z, R_DR, R_T, R_B0 = R_T + 3, R_B0P = R_B0 + 3, R_W = R_B0P + 3, R_C0,
        R_S0, R_WQ, NREC };
 
@@ -1375,6 +1427,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
             // the s-integrand's nearest singularity
             const double sr = cls[p * 4 + 0], si_ = cls[p * 4 + 1];
             const double rreq = pow(gc.cs / gc.tol, 1.0 / (double)(2 * NS - Ms));
+            // rho(sub-panel) >= rreq  <=>  s* lies outside the Bernstein
+            // ellipse of parameter rreq (semi-axes A h, B h about the
+            // sub-panel's midpoint, h its half-length):
+            // (x B)^2 + (y A)^2 >= (A B h)^2, no root or division
+            const double EA = 0.5 * (rreq + 1.0 / rreq), EB = 0.5 * (rreq - 1.0 / rreq);
+            const double EA2 = EA * EA, EB2 = EB * EB, EAB2 = EA2 * EB2, y2A = si_ * si_ * EA2;
             int sp = 0;
             st_lo[sp] = a;
             st_hi[sp] = c;
@@ -1382,8 +1440,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
             while (sp > 0) {
                 --sp;
                 double lo = st_lo[sp], hi = st_hi[sp];
-                double rho = bernstein_rho(sr, si_, lo, hi);
-                bool ok = rho >= rreq;
+                const double xm = sr - 0.5 * (lo + hi), hh = 0.5 * (hi - lo);
+                bool ok = xm * xm * EB2 + y2A >= EAB2 * hh * hh;
                 if (ok || (hi - lo) < 1e-12 * (c - a) || sp + 2 > 48 || ns_ + sp + 2 > MAXSUB) {
                     if (!ok) atomicOr(err, 2);
                     sub_lo[ns_] = lo;
@@ -1441,9 +1499,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
             }
             double lw[NS];
             if (own)
-                bary_weights_rel(i0, u / hw, c_gx, c_lam, lw);
+                bary_weights_rel_rcp(i0, u / hw, lw);
             else
-                bary_weights((s - inf.a) / hw - 1.0, c_gx, c_lam, lw);
+                bary_weights_rcp((s - inf.a) / hw - 1.0, lw);
 #pragma unroll
             for (int i = 0; i < NS; ++i) lwl[lane][i] = lw[i];
             double q[CLQ], dq[CLQ];
@@ -1528,15 +1586,28 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
             pref[0] = 0;
             for (int j = 0; j < nb; ++j) pref[j + 1] = pref[j] + npt[j];
         }
-        for (int k = lane; k < ncoef; k += 64) {
-            double hk[NS];
+        // coefficients at the s-nodes = [nb x NS] interpolation weights times
+        // the [NS x ncoef] GL-row coefficients: FP64 MFMA 16x16x4 tiles
+        // (A: lane l holds W[l % 16][4 ks + l / 16]; B: C[4 ks + l / 16][l % 16];
+        // D: lane l holds rows l / 16 + 4 i, i < 4, of column l % 16)
+        {
+            const int r = lane & 15, qq = lane >> 4;
+            double wa[NS / 4];
 #pragma unroll
-            for (int i = 0; i < NS; ++i) hk[i] = she[i * NSH + k];
-            for (int j = 0; j < nb; ++j) {
-                double v = 0.0;
+            for (int ks = 0; ks < NS / 4; ++ks) wa[ks] = (r < nb) ? lwl[r][4 * ks + qq] : 0.0;
+            for (int cb = 0; cb * 16 < ncoef; ++cb) {
+                const int col = cb * 16 + r;
+                v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int i = 0; i < NS; ++i) v = fma(lwl[j][i], hk[i], v);
-                cf[j * cstride + k] = v;
+                for (int ks = 0; ks < NS / 4; ++ks) {
+                    const double bv = (col < ncoef) ? she[(4 * ks + qq) * NSH + col] : 0.0;
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(wa[ks], bv, acc, 0, 0, 0);
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int row = qq + 4 * i;
+                    if (row < nb && col < ncoef) cf[row * cstride + col] = acc[i];
+                }
             }
         }
         __syncthreads();
