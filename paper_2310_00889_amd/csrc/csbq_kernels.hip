@@ -1335,6 +1335,7 @@ __device__ __forceinline__ double wave_sum(double v)
 //     costs one Fourier synthesis and a handful of flops.
 typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int SB = 16;
+constexpr int PPL = 2;     // points per lane in the special-quadrature point loop
 static_assert(SB == 16, "the coefficient interpolation uses 16-row MFMA tiles");
 enum { R_E = 0, R_EP, R_SP, R_A13, R_A23, R_Z, R_DR, R_T, R_B0 = R_T + 3, R_B0P = R_B0 + 3, R_W = R_B0P + 3, R_C0,
        R_S0, R_WQ, NREC };
@@ -1584,7 +1585,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
         // ---- 2. density coefficients at the batch's s-nodes
         if (lane == 0) {
             pref[0] = 0;
-            for (int j = 0; j < nb; ++j) pref[j + 1] = pref[j] + npt[j];
+            for (int j = 0; j < nb; ++j) pref[j + 1] = pref[j] + (npt[j] + PPL - 1) / PPL * PPL;
         }
         // coefficients at the s-nodes = [nb x NS] interpolation weights times
         // the [NS x ncoef] GL-row coefficients: FP64 MFMA 16x16x4 tiles
@@ -1611,67 +1612,99 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
             }
         }
         __syncthreads();
-        // ---- 3. the batch's points, 64 at a time
+        // ---- 3. the batch's points: a lane takes PPL consecutive points of one
+        // s-node (counts padded to a multiple of PPL, padding points weighted
+        // zero), so every LDS read of the s-node's record and coefficients
+        // serves PPL points
         const int Pb = pref[nb];
         int j = 0;
-        for (int P = lane; P < Pb; P += 64) {
+        for (int P = lane * PPL; P < Pb; P += 64 * PPL) {
             while (P >= pref[j + 1]) ++j;
-            const int q = P - pref[j];
+            const int q0 = P - pref[j];
+            const int nqj = npt[j];
             const double* R = rec[j];
             const double c0 = R[R_C0], s0t = R[R_S0];
             const int ro = rq_off[j];
-            double cph, sph, omc, wq, cth, sth;
-            if (ro < 0) {
-                const int ix = q * rq_step[j];
-                cth = c_cos128[ix];
-                sth = c_sin128[ix];
-                cph = cth * c0 + sth * s0t;     // phi = theta - theta0
-                sph = sth * c0 - cth * s0t;
-                omc = 1.0 - cph;
-                wq = R[R_WQ];
-            } else {
-                cph = rt.cs[ro + q];
-                sph = rt.sn[ro + q];
-                omc = rt.omc[ro + q];
-                wq = rt.w[ro + q];
-                cth = c0 * cph - s0t * sph;
-                sth = s0t * cph + c0 * sph;
+            double cph[PPL], sph[PPL], omc[PPL], wq[PPL], cth[PPL], sth[PPL];
+#pragma unroll
+            for (int u = 0; u < PPL; ++u) {
+                const bool ok = q0 + u < nqj;
+                const int q = ok ? q0 + u : q0;
+                if (ro < 0) {
+                    const int ix = q * rq_step[j];
+                    cth[u] = c_cos128[ix];
+                    sth[u] = c_sin128[ix];
+                    cph[u] = cth[u] * c0 + sth[u] * s0t;     // phi = theta - theta0
+                    sph[u] = sth[u] * c0 - cth[u] * s0t;
+                    omc[u] = 1.0 - cph[u];
+                    wq[u] = R[R_WQ];
+                } else {
+                    cph[u] = rt.cs[ro + q];
+                    sph[u] = rt.sn[ro + q];
+                    omc[u] = rt.omc[ro + q];
+                    wq[u] = rt.w[ro + q];
+                    cth[u] = c0 * cph[u] - s0t * sph[u];
+                    sth[u] = s0t * cph[u] + c0 * sph[u];
+                }
+                if (!ok) wq[u] = 0.0;
+                n_theta += ok ? 1 : 0;
             }
             // density by Fourier synthesis over the measured band
             const double* C = cf + j * cstride;
-            double v0 = C[0], v1 = C[1], v2 = C[2];
-            double clv = cth, slv = sth;
+            double v[PPL][3], clv[PPL], slv[PPL];
+#pragma unroll
+            for (int u = 0; u < PPL; ++u) {
+                v[u][0] = C[0];
+                v[u][1] = C[1];
+                v[u][2] = C[2];
+                clv[u] = cth[u];
+                slv[u] = sth[u];
+            }
             for (int l = 1; l <= Mt; ++l) {
                 const double* Cl = C + 6 * l;
-                v0 = fma(Cl[0], clv, fma(Cl[3], slv, v0));
-                v1 = fma(Cl[1], clv, fma(Cl[4], slv, v1));
-                v2 = fma(Cl[2], clv, fma(Cl[5], slv, v2));
-                const double cn = clv * cth - slv * sth;
-                slv = slv * cth + clv * sth;
-                clv = cn;
+                const double k0 = Cl[0], k1 = Cl[1], k2 = Cl[2], k3 = Cl[3], k4 = Cl[4], k5 = Cl[5];
+#pragma unroll
+                for (int u = 0; u < PPL; ++u) {
+                    v[u][0] = fma(k0, clv[u], fma(k3, slv[u], v[u][0]));
+                    v[u][1] = fma(k1, clv[u], fma(k4, slv[u], v[u][1]));
+                    v[u][2] = fma(k2, clv[u], fma(k5, slv[u], v[u][2]));
+                    const double cn = clv[u] * cth[u] - slv[u] * sth[u];
+                    slv[u] = slv[u] * cth[u] + clv[u] * sth[u];
+                    clv[u] = cn;
+                }
             }
             const double E = R[R_E], Ep = R[R_EP], z = R[R_Z], dr = R[R_DR];
-            const double gq = R[R_SP] + R[R_A13] * cth + R[R_A23] * sth;
-            const double J = E * sqrt(gq * gq + Ep * Ep);
-            const double A = dr + E * omc, B = -E * sph;
-            double r[3];
+            const double sp_ = R[R_SP], a13 = R[R_A13], a23 = R[R_A23], Wsn = R[R_W];
+            double tv[3], b0v[3], b0pv[3];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) r[d] = z * R[R_T + d] + A * R[R_B0 + d] + B * R[R_B0P + d];
-            const double rr = z * z + A * A + B * B;
-            const double ir = rr > 0.0 ? rsqrt_nr(rr) : 0.0;
-            const double ir2 = ir * ir;
-            const double W = R[R_W] * wq;
-            const double rs = r[0] * v0 + r[1] * v1 + r[2] * v2;
-            const double rn = sgn * E * (gq * (dr * cph - E * omc) - Ep * z);
-            const double aS = W * J * ir, bS = aS * rs * ir2;
-            const double cD = W * rn * rs * ir2 * ir2 * ir;
-            a0 += aS * v0 + bS * r[0];
-            a1 += aS * v1 + bS * r[1];
-            a2 += aS * v2 + bS * r[2];
-            b0_ += cD * r[0];
-            b1_ += cD * r[1];
-            b2_ += cD * r[2];
-            ++n_theta;
+            for (int d = 0; d < 3; ++d) {
+                tv[d] = R[R_T + d];
+                b0v[d] = R[R_B0 + d];
+                b0pv[d] = R[R_B0P + d];
+            }
+#pragma unroll
+            for (int u = 0; u < PPL; ++u) {
+                const double gq = sp_ + a13 * cth[u] + a23 * sth[u];
+                const double J = E * sqrt(gq * gq + Ep * Ep);
+                const double A = dr + E * omc[u], B = -E * sph[u];
+                double r[3];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) r[d] = z * tv[d] + A * b0v[d] + B * b0pv[d];
+                const double rr = z * z + A * A + B * B;
+                const double ir = rr > 0.0 ? rsqrt_nr(rr) : 0.0;
+                const double ir2 = ir * ir;
+                const double W = Wsn * wq[u];
+                const double rs = r[0] * v[u][0] + r[1] * v[u][1] + r[2] * v[u][2];
+                const double rn = sgn * E * (gq * (dr * cph[u] - E * omc[u]) - Ep * z);
+                const double aS = W * J * ir, bS = aS * rs * ir2;
+                const double cD = W * rn * rs * ir2 * ir2 * ir;
+                a0 += aS * v[u][0] + bS * r[0];
+                a1 += aS * v[u][1] + bS * r[1];
+                a2 += aS * v[u][2] + bS * r[2];
+                b0_ += cD * r[0];
+                b1_ += cD * r[1];
+                b2_ += cD * r[2];
+            }
         }
         __syncthreads();
     }
