@@ -70,12 +70,24 @@ int upload_constants(const double* gx, const double* gw, const double* lam, cons
 __device__ __forceinline__ double rsqrt_nr(double x)
 {
     double y = __builtin_amdgcn_rsq(x);
-    double h = x * y;
-    double e = fma(-h, y, 1.0);
-    y = fma(0.5 * y, e, y);
-    h = x * y;
-    e = fma(-h, y, 1.0);
-    return fma(0.5 * y, e, y);
+    const double xh = 0.5 * x;
+    double e = fma(-xh, y * y, 0.5);   // y <- y (3/2 - x y^2 / 2)
+    y = fma(y, e, y);
+    e = fma(-xh, y * y, 0.5);
+    return fma(y, e, y);
+}
+
+// 1/sqrt(rr) of a squared distance, 0 for rr == 0 (a source at the target
+// itself).  The refined estimate of 0 is NaN (0 * inf in the Newton step);
+// clearing its high word leaves zero (the low word of the quiet NaN) or at
+// worst a denormal, so the coincident pair adds nothing.  rr is a sum of
+// squares of coordinate differences: its high word is zero only for rr = 0
+// or |r| below 1e-154.
+__device__ __forceinline__ double rsqrt_or_zero(double rr)
+{
+    const double y = rsqrt_nr(rr);
+    const int hi = (__double2hiint(rr) == 0) ? 0 : __double2hiint(y);
+    return __hiloint2double(hi, __double2loint(y));
 }
 
 // interpolate the CLQ centerline quantities of element data clq (layout
@@ -647,10 +659,7 @@ __global__ __launch_bounds__(FAR_BLOCK) void k_far(int64_t T, const double* __re
             for (int u = 0; u < TPT; ++u) {
                 const double r0 = x[u][0] - A.x, r1 = x[u][1] - A.y, r2_ = x[u][2] - B.x;
                 const double rr = fma(r0, r0, fma(r1, r1, r2_ * r2_));
-                // evaluated unconditionally (a coincident node gives inf/NaN
-                // that the select discards), so the loop has no branch
-                const double irn = rsqrt_nr(rr);
-                const double ir = rr > 0.0 ? irn : 0.0;
+                const double ir = rsqrt_or_zero(rr);   // branch-free self term
                 const double rs = fma(r0, D.x, fma(r1, D.y, r2_ * F.x));
                 const double rn = fma(r0, B.y, fma(r1, C.x, r2_ * C.y));
                 const double ir2 = ir * ir;
@@ -1266,8 +1275,7 @@ __global__ __launch_bounds__(64) void k_corr_up(int64_t Mf, const int* __restric
                 for (int u = 0; u < UP_TPT; ++u) {
                     const double r0 = x[u][0] - A.x, r1 = x[u][1] - A.y, r2_ = x[u][2] - B.x;
                     const double rr = fma(r0, r0, fma(r1, r1, r2_ * r2_));
-                    const double irn = rsqrt_nr(rr);
-                    const double ir = rr > 0.0 ? irn : 0.0;
+                    const double ir = rsqrt_or_zero(rr);
                     const double rs = fma(r0, D.x, fma(r1, D.y, r2_ * F.x));
                     const double rn = fma(r0, B.y, fma(r1, C.x, r2_ * C.y));
                     const double ir2 = ir * ir;
