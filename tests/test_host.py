@@ -1,0 +1,88 @@
+"""Host-side logic that runs without a GPU: batch assembly, the learned gate's
+weight files and constants, the measured-traffic record, and a clean failure
+when no device is present."""
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_merge_scenes_offsets_groups_and_targets():
+    a = synth.small_pipe_scene(n_panels=3, n_spheres=1)
+    b = synth.small_pipe_scene(seed=7100, n_panels=4, n_spheres=2)
+    m = synth.merge_scenes([a, b])
+    assert m.n_nodes == a.n_nodes + b.n_nodes
+    assert list(m.body_group) == [0] * len(a.bodies) + [1] * len(b.bodies)
+    assert list(m.group_node_offsets) == [0, a.n_nodes, a.n_nodes + b.n_nodes]
+    assert list(m.group_target_offsets) == [0, a.n_nodes, a.n_nodes + b.n_nodes]
+    # targets default to all nodes, renumbered into the merged node list
+    assert np.array_equal(m.tgt_node, np.arange(m.n_nodes))
+    assert np.array_equal(m.sigma[:a.n_nodes], a.sigma) and np.array_equal(m.sigma[a.n_nodes:], b.sigma)
+    f = m.flat()
+    assert f["n_bodies"] == len(a.bodies) + len(b.bodies)
+    assert f["xc"].shape[0] == (a.n_panels + b.n_panels) * synth.NS
+
+
+def test_gate_constants_match_header():
+    import paper_2310_00889_amd as pk
+    from paper_2310_00889_amd import gate
+    h = open(os.path.join(ROOT, "include", "csbq.h")).read()
+    consts = dict(re.findall(r"#define CSBQ_GATE_(\w+) (\d+)", h))
+    assert int(consts["NF"]) == pk.GATE_NF and int(consts["NO"]) == pk.GATE_NO and int(consts["NW"]) == pk.GATE_NW
+    n = sum(int(np.prod(s)) for _, s in gate.SHAPES)
+    assert n == pk.GATE_NW
+
+
+def test_gate_weights_roundtrip(tmp_path):
+    from paper_2310_00889_amd import gate
+    w = gate.init_weights(seed=4)
+    p = tmp_path / "w.npz"
+    gate.save_weights(p, w, tau_esc=0.05, note="test")
+    w2, meta = gate.load_weights(p)
+    assert np.array_equal(w, w2) and float(meta["tau_esc"]) == 0.05
+    parts = gate.unpack(w2)
+    assert parts["W2"].shape == (64, 64) and parts["b4"].shape == (4,)
+    # He initialisation: biases zero, weight scale sqrt(2 / fan_in)
+    assert np.all(parts["b1"] == 0) and abs(parts["W2"].std() - np.sqrt(2 / 64)) < 0.02
+    with pytest.raises(ValueError):
+        gate.save_weights(p, w[:-1])
+        gate.load_weights(p)
+
+
+def test_shipped_gate_weights():
+    from paper_2310_00889_amd import gate
+    if not os.path.exists(gate.DEFAULT_WEIGHTS):
+        pytest.skip("no trained weights shipped")
+    w, meta = gate.load_weights()
+    assert np.isfinite(w).all()
+    assert 0 < float(meta["tau_esc"]) < 1
+    assert float(meta["quad_tol"]) == 1e-7
+    conf = np.asarray(meta["confusion"])
+    assert conf.shape == (5, 5) and conf.sum() == int(meta["n_train"])
+
+
+def test_traffic_record_is_complete():
+    path = os.path.join(ROOT, "profiles", "traffic_k_corr_full_pipe100_spheres200_fp64.json")
+    rec = json.load(open(path))
+    for k in ("kernel", "fetch_kib", "write_kib", "fetch_factor", "write_factor", "traffic_bytes", "kernels_sha1",
+              "commands"):
+        assert k in rec, k
+    expect = rec["fetch_kib"] * 1024 / rec["fetch_factor"] + rec["write_kib"] * 1024 / rec["write_factor"]
+    assert abs(expect - rec["traffic_bytes"]) < 1e-6 * expect
+
+
+def test_create_without_device_fails_cleanly():
+    import torch
+    import paper_2310_00889_amd as pk
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    if not os.path.exists(pk.LIB_PATH):
+        pytest.skip("libcsbq.so not built")
+    with pytest.raises(pk.CsbqError):
+        pk.Evaluator(stream=0)
