@@ -920,37 +920,6 @@ __global__ void k_search(int64_t T, const int* __restrict__ tgroup, const int* _
     if (!off) cnt[t] = n;
 }
 
-// golden-section minimisation of a distance-like function of s over [lo, hi]
-template <typename F>
-__device__ inline double golden_min(F fn, double lo, double hi, int iters, double* fmin_out)
-{
-    const double gr = 0.6180339887498949;
-    double x1 = hi - gr * (hi - lo), x2 = lo + gr * (hi - lo);
-    double f1 = fn(x1), f2 = fn(x2);
-    for (int it = 0; it < iters; ++it) {
-        if (f1 < f2) {
-            hi = x2;
-            x2 = x1;
-            f2 = f1;
-            x1 = hi - gr * (hi - lo);
-            f1 = fn(x1);
-        } else {
-            lo = x1;
-            x1 = x2;
-            f1 = f2;
-            x2 = lo + gr * (hi - lo);
-            f2 = fn(x2);
-        }
-    }
-    double fl = fn(lo), fh = fn(hi);
-    double best = x1, fb = f1;
-    if (f2 < fb) { best = x2; fb = f2; }
-    if (fl < fb) { best = lo; fb = fl; }
-    if (fh < fb) { best = hi; fb = fh; }
-    *fmin_out = fb;
-    return best;
-}
-
 // worst Bernstein parameter of s* = sr + i si over f equal sub-panels of [a,c]
 __device__ inline double rho_subpanels(double sr, double si, double a, double c, int f)
 {
@@ -1049,6 +1018,8 @@ __device__ inline double contact_root(const double* __restrict__ clq, const doub
             z1 = csub(z1, step);
             if (!(fabs(z1.r) < 8.0 && fabs(z1.i) < 8.0)) break;
             f1 = contact_fn(clq, z1, x);
+            // a tight stop: a looser one (1e-7) also accepts iterates still
+            // wandering far from any zero, and the estimate turns pessimistic
             if (sqrt(step.r * step.r + step.i * step.i) < 1e-9 * (1.0 + fabs(z1.r) + fabs(z1.i))) {
                 ok = true;
                 break;
@@ -1103,23 +1074,76 @@ __global__ __launch_bounds__(128) void k_classify(int64_t P, const int* __restri
         if (cha < ba) { ba = cha; ka = k; }
     }
     auto xn_of = [&](int k) { return k == 0 ? -1.0 : (k == NCIRC - 1 ? 1.0 : c_gx[k - 1]); };
-    auto fd = [&](double xn) {
-        double X[3], tt[3], EE, d2, cha;
-        circle_at_x(cq, xn, X, tt, &EE);
-        circle_dist(X, tt, EE, x, &d2, &cha);
-        return d2;
-    };
-    auto fa = [&](double xn) {
-        double X[3], tt[3], EE, d2, cha;
-        circle_at_x(cq, xn, X, tt, &EE);
-        circle_dist(X, tt, EE, x, &d2, &cha);
-        return cha;
-    };
-    double d2c, chac;
-    double xd = golden_min(fd, xn_of(max(kd - 1, 0)), xn_of(min(kd + 1, NCIRC - 1)), 20, &d2c);
-    golden_min(fa, xn_of(max(ka - 1, 0)), xn_of(min(ka + 1, NCIRC - 1)), 20, &chac);
-    d2c = fmin(d2c, bd);
-    chac = fmin(chac, ba);
+    // closest circle (minimum of d^2 over the two GL gaps around the sampled
+    // minimum) and fastest trapezoid decay (minimum of cosh a - 1, likewise):
+    // for each, a 9-point grid over its bracket, then two parabolic steps
+    double d2c = bd, chac = ba, xd = xn_of(kd);
+    {
+        auto eval = [&](double xn, double* d2, double* cha) {
+            double X[3], tt[3], EE;
+            circle_at_x(cq, xn, X, tt, &EE);
+            circle_dist(X, tt, EE, x, d2, cha);
+        };
+        // vertex of the parabola through (x - dx, fl), (x, fc), (x + dx, fr)
+        auto vertex = [](double xc, double dx, double fl, double fc, double fr) {
+            const double den = fl - 2.0 * fc + fr;
+            if (!(den > 0.0) || fl >= 1e299 || fr >= 1e299) return xc;
+            return xc + 0.5 * dx * (fl - fr) / den;
+        };
+        for (int which = 0; which < 2; ++which) {
+            const int kc = which ? ka : kd;
+            const double lo = xn_of(max(kc - 1, 0)), hi = xn_of(min(kc + 1, NCIRC - 1));
+            constexpr int G = 9;
+            const double h = (hi - lo) / (G - 1);
+            // running minimum of the grid with its neighbours (no indexed arrays)
+            double m = 1e300, ml = 1e300, mr = 1e300, pv = 1e300, xm = lo;
+            int im = -1;
+            for (int i = 0; i < G; ++i) {
+                double vd, va;
+                const double xi = lo + i * h;
+                eval(xi, &vd, &va);
+                const double v = which ? va : vd;
+                if (im == i - 1) mr = v;
+                if (v < m) {
+                    m = v;
+                    ml = pv;
+                    mr = 1e300;
+                    im = i;
+                    xm = xi;
+                }
+                pv = v;
+            }
+            const double xv = fmin(hi, fmax(lo, vertex(xm, h, ml, m, mr)));
+            const double dx = 0.125 * h;
+            double g[3];
+            for (int k = 0; k < 3; ++k) {
+                double vd, va;
+                const double xk = fmin(hi, fmax(lo, xv + (k - 1) * dx));
+                eval(xk, &vd, &va);
+                g[k] = which ? va : vd;
+                if (g[k] < m) {
+                    m = g[k];
+                    xm = xk;
+                }
+            }
+            {
+                double vd, va;
+                const double xk = fmin(hi, fmax(lo, vertex(xv, dx, g[0], g[1], g[2])));
+                eval(xk, &vd, &va);
+                const double v = which ? va : vd;
+                if (v < m) {
+                    m = v;
+                    xm = xk;
+                }
+            }
+            if (which) {
+                chac = fmin(chac, m);
+            } else if (m < d2c) {
+                d2c = m;
+                xd = xm;
+            }
+        }
+    }
     // speed bound near the closest circle
     double spd = fmax(cc[kd * CIRQ + 7], cc[min(kd + 1, NCIRC - 1) * CIRQ + 7]);
     spd = fmax(spd, cc[max(kd - 1, 0) * CIRQ + 7]);
