@@ -1026,6 +1026,9 @@ int csbq_eval_batch(csbq_ctx* ctx, const double* sigma, int64_t T, const double*
     std::vector<int> hband((size_t)2 * E);
     HIPC(hipMemcpyAsync(hband.data(), ctx->band.p, hband.size() * sizeof(int), hipMemcpyDeviceToHost, st));
     HIPC(hipStreamSynchronize(st));
+    // pair lists are sorted and scanned with 32-bit counts
+    if (P < 0 || P >= (int64_t)INT32_MAX)
+        return ctx->fail(CSBQ_ELIMIT, "more than 2^31 candidate pairs: evaluate the targets in slices");
     int mt_max = 0;
     for (int k = 0; k < E; ++k) mt_max = std::max(mt_max, hband[2 * k + 1]);
     std::vector<int64_t> tr;
