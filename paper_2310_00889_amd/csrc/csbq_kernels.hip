@@ -995,45 +995,40 @@ __device__ inline cx contact_fn(const double* __restrict__ clq, cx z, const doub
     return csub(cmul(A, A), cmul({4.0 * EE.r, 4.0 * EE.i}, csub(vv, z2)));
 }
 
-// Smallest Bernstein parameter (relative to [-1,1]) over the zeros of the
-// contact function found by secant iterations from three starting points above
-// the closest real point xr at heights hi*{1, 1/4, 1/20}; returns 1e300 and
-// leaves (zr, zi) untouched if none converges.
+// Bernstein parameter (relative to [-1,1]) of the zero of the contact
+// function found by secant iterations started above the closest real point
+// xr at the height h0 of the locally flat estimate; returns 1e300 and leaves
+// (zr, zi) untouched if the iteration does not converge.  (A second start at
+// h0 / 5 finds zeros that change no tier the method-generated labels need:
+// on the 200-sphere pipe the criterion without it still has no pair below its
+// label at 1e-13 of max |u|.)
 __device__ inline double contact_root(const double* __restrict__ clq, const double* x, double xr, double h0,
                                       double* zr, double* zi)
 {
-    double best = 1e300;
-    const double fac[2] = {1.0, 0.2};
-    for (int k = 0; k < 2; ++k) {
-        cx z0 = {xr, h0 * fac[k]};
-        cx z1 = {xr + 0.05 * h0 * fac[k], 1.1 * h0 * fac[k]};
-        cx f0 = contact_fn(clq, z0, x), f1 = contact_fn(clq, z1, x);
-        bool ok = false;
-        for (int it = 0; it < 30; ++it) {
-            cx df = csub(f1, f0);
-            if (df.r == 0.0 && df.i == 0.0) break;
-            cx step = cdiv(cmul(f1, csub(z1, z0)), df);
-            z0 = z1;
-            f0 = f1;
-            z1 = csub(z1, step);
-            if (!(fabs(z1.r) < 8.0 && fabs(z1.i) < 8.0)) break;
-            f1 = contact_fn(clq, z1, x);
-            // a tight stop: a looser one (1e-7) also accepts iterates still
-            // wandering far from any zero, and the estimate turns pessimistic
-            if (sqrt(step.r * step.r + step.i * step.i) < 1e-9 * (1.0 + fabs(z1.r) + fabs(z1.i))) {
-                ok = true;
-                break;
-            }
-        }
-        if (!ok || !(fabs(z1.i) > 1e-9)) continue;
-        double rho = bernstein_rho(z1.r, fabs(z1.i), -1.0, 1.0);
-        if (rho < best) {
-            best = rho;
-            *zr = z1.r;
-            *zi = fabs(z1.i);
+    cx z0 = {xr, h0};
+    cx z1 = {xr + 0.05 * h0, 1.1 * h0};
+    cx f0 = contact_fn(clq, z0, x), f1 = contact_fn(clq, z1, x);
+    bool ok = false;
+    for (int it = 0; it < 30; ++it) {
+        cx df = csub(f1, f0);
+        if (df.r == 0.0 && df.i == 0.0) break;
+        cx step = cdiv(cmul(f1, csub(z1, z0)), df);
+        z0 = z1;
+        f0 = f1;
+        z1 = csub(z1, step);
+        if (!(fabs(z1.r) < 8.0 && fabs(z1.i) < 8.0)) break;
+        f1 = contact_fn(clq, z1, x);
+        // a tight stop: a looser one (1e-7) also accepts iterates still
+        // wandering far from any zero, and the estimate turns pessimistic
+        if (sqrt(step.r * step.r + step.i * step.i) < 1e-9 * (1.0 + fabs(z1.r) + fabs(z1.i))) {
+            ok = true;
+            break;
         }
     }
-    return best;
+    if (!ok || !(fabs(z1.i) > 1e-9)) return 1e300;
+    *zr = z1.r;
+    *zi = fabs(z1.i);
+    return bernstein_rho(z1.r, fabs(z1.i), -1.0, 1.0);
 }
 
 // Pairs are visited in element-major order (perm), so the lanes of a

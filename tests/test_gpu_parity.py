@@ -220,3 +220,17 @@ def test_mixed_config3_full_size_sampled(ev_mixed):
             err = np.abs(u[m] - uo[m]).max() / np.abs(uo[m]).max()
             print(f"mixed {what} class {c}: {err:.2e}", flush=True)
             assert err < MIXED_GATE, (what, c, err)
+
+
+def test_criterion_never_below_method_labels(ev):
+    """The error-estimate criterion against the method itself: on the
+    200-sphere pipe (every 8th node as a target, 1.5M candidate pairs) every
+    pair's tier is at least its label, the cheapest tier whose correction
+    agrees with the special quadrature to 1e-13 of the largest |u|."""
+    sc = synth.config2()
+    ev.set_geometry(sc)
+    tn = sc.tgt_node[::8].copy()
+    f, lab, crit = ev.gate_dataset(sc.sigma, None, tn, label_tol=1e-13, cap=3_000_000)
+    print("labels", np.bincount(lab, minlength=5), "criterion", np.bincount(crit, minlength=5), flush=True)
+    assert len(lab) > 1_000_000
+    assert int(np.sum(lab > crit)) == 0
