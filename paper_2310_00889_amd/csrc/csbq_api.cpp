@@ -223,6 +223,12 @@ struct csbq_ctx {
     } plan;
     DBuf<int> band_apply;
     int last_ntiles = 0;
+    // the smooth sum runs on a second stream beside the near field; host
+    // copies of its block list outlive the asynchronous uploads
+    hipStream_t side = nullptr;
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+    std::vector<FarTile> h_tiles;
+    std::vector<int> h_gnc;
     DBuf<unsigned char> cub_tmp;
     // statistics of the last evaluation
     Phase ph[kNPhase];
@@ -497,6 +503,9 @@ int csbq_destroy(csbq_ctx* ctx)
     if (ctx->plan.e0) (void)hipEventDestroy(ctx->plan.e0);
     if (ctx->plan.e1) (void)hipEventDestroy(ctx->plan.e1);
     if (ctx->plan.gst) (void)hipStreamDestroy(ctx->plan.gst);
+    if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
+    if (ctx->join_ev) (void)hipEventDestroy(ctx->join_ev);
+    if (ctx->side) (void)hipStreamDestroy(ctx->side);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
     return CSBQ_OK;
@@ -885,10 +894,11 @@ static int tune_far(csbq_ctx* ctx, int64_t T, const std::vector<int64_t>& tr, bo
 }
 
 // smooth sum over a source set: the element nodes (native) or the base set
-static int far_sum(csbq_ctx* ctx, int64_t T, bool native, const std::vector<int64_t>& tr)
+// The smooth sum over a source set, enqueued on `st` (tuned on the
+// context's stream first): the element nodes (native, a diagnostic, always
+// FP64) or the base set (the context's precision).
+static int far_sum(csbq_ctx* ctx, int64_t T, bool native, const std::vector<int64_t>& tr, hipStream_t st)
 {
-    // the smooth sum over the element nodes (a diagnostic) stays FP64; the
-    // evaluation's far field follows the context's precision
     const bool mixed = !native && ctx->opt.precision == CSBQ_MIXED;
     int rc;
     if ((rc = tune_far(ctx, T, tr, native, mixed))) return rc;
@@ -896,17 +906,17 @@ static int far_sum(csbq_ctx* ctx, int64_t T, bool native, const std::vector<int6
     const double* sy = native ? ctx->ny.p : ctx->by.p;
     const double* sn = native ? ctx->nn.p : ctx->bn.p;
     const double* ss = native ? ctx->sw.p : ctx->bsw.p;
-    std::vector<FarTile> tl;
-    std::vector<int> gnc;
     int maxch = 0;
-    far_tiles(ctx, tr, native, ctx->far_tpt, ctx->far_chunk, -1, INT64_MAX, tl, gnc, &maxch);
+    far_tiles(ctx, tr, native, ctx->far_tpt, ctx->far_chunk, -1, INT64_MAX, ctx->h_tiles, ctx->h_gnc, &maxch);
+    const auto& tl = ctx->h_tiles;
+    const auto& gnc = ctx->h_gnc;
     ALLOC(ctx->tiles, tl.size() + 1);
     ALLOC(ctx->gnchunk, gnc.size());
-    HIPC(hipMemcpyAsync(ctx->tiles.p, tl.data(), tl.size() * sizeof(FarTile), hipMemcpyHostToDevice, ctx->stream));
-    HIPC(hipMemcpyAsync(ctx->gnchunk.p, gnc.data(), gnc.size() * sizeof(int), hipMemcpyHostToDevice, ctx->stream));
     ALLOC(ctx->part, (size_t)std::max(maxch, 1) * 6 * T + 1);
+    HIPC(hipMemcpyAsync(ctx->tiles.p, tl.data(), tl.size() * sizeof(FarTile), hipMemcpyHostToDevice, st));
+    HIPC(hipMemcpyAsync(ctx->gnchunk.p, gnc.data(), gnc.size() * sizeof(int), hipMemcpyHostToDevice, st));
     if (T > 0)
-        LCHK(launch_far(ctx->stream, T, ctx->xt.p, sy, sn, ss, Ns, ctx->tiles.p, (int)tl.size(), ctx->part.p, mixed,
+        LCHK(launch_far(st, T, ctx->xt.p, sy, sn, ss, Ns, ctx->tiles.p, (int)tl.size(), ctx->part.p, mixed,
                         ctx->mix_near2, ctx->far_tpt));
     ctx->last_ntiles = (int)tl.size();
     return CSBQ_OK;
@@ -969,7 +979,7 @@ int csbq_smooth_sum(csbq_ctx* ctx, const double* sigma, int64_t T, const double*
     HIPC(hipStreamSynchronize(ctx->stream));
     std::vector<int64_t> tr;
     if ((rc = group_ranges(ctx, T, flags, tr))) return rc;
-    if ((rc = far_sum(ctx, T, true, tr))) return rc;
+    if ((rc = far_sum(ctx, T, true, tr, ctx->stream))) return rc;
     double *usl, *udl;
     if ((rc = outputs_back(ctx, T, u_sl, u_dl, mem, &usl, &udl))) return rc;
     LCHK(launch_reduce(ctx->stream, T, ctx->tgroup.p, ctx->gnchunk.p, ctx->part.p, nullptr, nullptr, nullptr, usl,
@@ -1041,10 +1051,21 @@ int csbq_eval_batch(csbq_ctx* ctx, const double* sigma, int64_t T, const double*
     LCHK(launch_search(st, T, ctx->tgroup.p, ctx->gel.p, ctx->xt.p, tn, ctx->info.p, ctx->rnear.p, ctx->off.p,
                        nullptr, ctx->pe.p, ctx->pt.p));
     HIPC(hipEventRecord(ctx->ph[2].b, st));
-    // the smooth sum over every base source of the target's group
-    HIPC(hipEventRecord(ctx->ph[1].a, st));
-    if ((rc = far_sum(ctx, T, false, tr))) return rc;
-    HIPC(hipEventRecord(ctx->ph[1].b, st));
+    // the smooth sum over every base source of the target's group, on the
+    // side stream so that it overlaps the near field; joined before the
+    // reduction
+    if (!ctx->side) {
+        HIPC(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+        HIPC(hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming));
+        HIPC(hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming));
+    }
+    if ((rc = tune_far(ctx, T, tr, false, ctx->opt.precision == CSBQ_MIXED))) return rc;
+    HIPC(hipEventRecord(ctx->fork_ev, st));
+    HIPC(hipStreamWaitEvent(ctx->side, ctx->fork_ev, 0));
+    HIPC(hipEventRecord(ctx->ph[1].a, ctx->side));
+    if ((rc = far_sum(ctx, T, false, tr, ctx->side))) return rc;
+    HIPC(hipEventRecord(ctx->ph[1].b, ctx->side));
+    HIPC(hipEventRecord(ctx->join_ev, ctx->side));
     // classification into correction tiers, in element-major order
     HIPC(hipEventRecord(ctx->ph[3].a, st));
     int ebits = 1;
@@ -1187,6 +1208,7 @@ int csbq_eval_batch(csbq_ctx* ctx, const double* sigma, int64_t T, const double*
                           ctx->romc.p, ctx->gc, ctx->corr.p, ctx->err_d.p, ctx->work.p, mt_max));
     HIPC(hipEventRecord(ctx->ph[6].b, st));
     // reduction
+    HIPC(hipStreamWaitEvent(st, ctx->join_ev, 0));
     HIPC(hipEventRecord(ctx->ph[7].a, st));
     double *usl, *udl;
     if ((rc = outputs_back(ctx, T, u_sl, u_dl, mem, &usl, &udl))) return rc;
