@@ -223,10 +223,7 @@ struct csbq_ctx {
     } plan;
     DBuf<int> band_apply;
     int last_ntiles = 0;
-    // the smooth sum runs on a second stream beside the near field; host
-    // copies of its block list outlive the asynchronous uploads
-    hipStream_t side = nullptr;
-    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+    // host copies of the smooth-sum block list outlive the asynchronous uploads
     std::vector<FarTile> h_tiles;
     std::vector<int> h_gnc;
     DBuf<unsigned char> cub_tmp;
@@ -503,9 +500,6 @@ int csbq_destroy(csbq_ctx* ctx)
     if (ctx->plan.e0) (void)hipEventDestroy(ctx->plan.e0);
     if (ctx->plan.e1) (void)hipEventDestroy(ctx->plan.e1);
     if (ctx->plan.gst) (void)hipStreamDestroy(ctx->plan.gst);
-    if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
-    if (ctx->join_ev) (void)hipEventDestroy(ctx->join_ev);
-    if (ctx->side) (void)hipStreamDestroy(ctx->side);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
     return CSBQ_OK;
@@ -1051,21 +1045,7 @@ int csbq_eval_batch(csbq_ctx* ctx, const double* sigma, int64_t T, const double*
     LCHK(launch_search(st, T, ctx->tgroup.p, ctx->gel.p, ctx->xt.p, tn, ctx->info.p, ctx->rnear.p, ctx->off.p,
                        nullptr, ctx->pe.p, ctx->pt.p));
     HIPC(hipEventRecord(ctx->ph[2].b, st));
-    // the smooth sum over every base source of the target's group, on the
-    // side stream so that it overlaps the near field; joined before the
-    // reduction
-    if (!ctx->side) {
-        HIPC(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
-        HIPC(hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming));
-        HIPC(hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming));
-    }
     if ((rc = tune_far(ctx, T, tr, false, ctx->opt.precision == CSBQ_MIXED))) return rc;
-    HIPC(hipEventRecord(ctx->fork_ev, st));
-    HIPC(hipStreamWaitEvent(ctx->side, ctx->fork_ev, 0));
-    HIPC(hipEventRecord(ctx->ph[1].a, ctx->side));
-    if ((rc = far_sum(ctx, T, false, tr, ctx->side))) return rc;
-    HIPC(hipEventRecord(ctx->ph[1].b, ctx->side));
-    HIPC(hipEventRecord(ctx->join_ev, ctx->side));
     // classification into correction tiers, in element-major order
     HIPC(hipEventRecord(ctx->ph[3].a, st));
     int ebits = 1;
@@ -1185,6 +1165,12 @@ int csbq_eval_batch(csbq_ctx* ctx, const double* sigma, int64_t T, const double*
             HIPC(hipMemcpy(ctx->wdesc[ti].p, wd[ti].data(), wd[ti].size() * sizeof(int), hipMemcpyHostToDevice));
     }
     HIPC(hipEventRecord(ctx->ph[4].b, st));
+    // the smooth sum over every base source of the target's group (on the
+    // same stream: it and the corrections are both VALU-bound, and running
+    // them side by side gained 2 % while blurring every kernel's timing)
+    HIPC(hipEventRecord(ctx->ph[1].a, st));
+    if ((rc = far_sum(ctx, T, false, tr, st))) return rc;
+    HIPC(hipEventRecord(ctx->ph[1].b, st));
     // upsampled-rule corrections
     HIPC(hipEventRecord(ctx->ph[5].a, st));
     for (int ti = 0; ti < NUP; ++ti) {
@@ -1208,7 +1194,6 @@ int csbq_eval_batch(csbq_ctx* ctx, const double* sigma, int64_t T, const double*
                           ctx->romc.p, ctx->gc, ctx->corr.p, ctx->err_d.p, ctx->work.p, mt_max));
     HIPC(hipEventRecord(ctx->ph[6].b, st));
     // reduction
-    HIPC(hipStreamWaitEvent(st, ctx->join_ev, 0));
     HIPC(hipEventRecord(ctx->ph[7].a, st));
     double *usl, *udl;
     if ((rc = outputs_back(ctx, T, u_sl, u_dl, mem, &usl, &udl))) return rc;
