@@ -77,17 +77,54 @@ __device__ __forceinline__ double rsqrt_nr(double x)
     return fma(y, e, y);
 }
 
-// 1/sqrt(rr) of a squared distance, 0 for rr == 0 (a source at the target
-// itself).  The refined estimate of 0 is NaN (0 * inf in the Newton step);
-// clearing its high word leaves zero (the low word of the quiet NaN) or at
-// worst a denormal, so the coincident pair adds nothing.  rr is a sum of
-// squares of coordinate differences: its high word is zero only for rr = 0
-// or |r| below 1e-154.
-__device__ __forceinline__ double rsqrt_or_zero(double rr)
+// 1/sqrt(x) for x > 0 from the hardware estimate y (relative error about
+// 5e-8) and one Newton step, y (3 - x y^2) / 2: the step leaves a relative
+// error of 1.5 e^2 + O(e^3) < 1e-14 for an estimate error e, always low.
+__device__ __forceinline__ double rsqrt_nr1(double x)
 {
-    const double y = rsqrt_nr(rr);
-    const int hi = (__double2hiint(rr) == 0) ? 0 : __double2hiint(y);
-    return __hiloint2double(hi, __double2loint(y));
+    const double y = __builtin_amdgcn_rsq(x);
+    return (0.5 * y) * fma(-x, y * y, 3.0);
+}
+
+// 2/sqrt(rr) of a squared distance, 0 for rr == 0 (a source at the target
+// itself): rsqrt_nr1 without its factor 1/2, which the callers take out of
+// their sums as an exact power of two.  The estimate of 0 is +inf; clearing
+// its high word leaves +0 before the Newton step, so the coincident pair adds
+// nothing.  rr is a sum of squares of coordinate differences: its high word
+// is zero only for rr = 0 or |r| below 1e-154.
+__device__ __forceinline__ double rsqrt2_or_zero(double rr)
+{
+    const double y0 = __builtin_amdgcn_rsq(rr);
+    const int hi = (__double2hiint(rr) == 0) ? 0 : __double2hiint(y0);
+    const double y = __hiloint2double(hi, __double2loint(y0));
+    return y * fma(-rr, y * y, 3.0);
+}
+
+// One source record (y, n, sigma*w as five 16-byte pairs A..F) against one
+// target x, accumulated in scaled form: with q = 2/r, sa += q (sigma w),
+// sb += q^3 (r.sigma w) r and sd += q^5 (r.n)(r.sigma w) r, i.e. 2, 8 and 32
+// times the single-layer's two parts and the double-layer term.
+__device__ __forceinline__ void pair_scaled(const double x[3], double2 A, double2 B, double2 C, double2 D, double2 F,
+                                            double sa[3], double sb[3], double sd[3])
+{
+    // A = (y0, y1), B = (y2, n0), C = (n1, n2), D = (w0, w1), F = (w2, -)
+    const double r0 = x[0] - A.x, r1 = x[1] - A.y, r2 = x[2] - B.x;
+    const double rr = fma(r0, r0, fma(r1, r1, r2 * r2));
+    const double q = rsqrt2_or_zero(rr);   // branch-free self term
+    const double rs = fma(r0, D.x, fma(r1, D.y, r2 * F.x));
+    const double rn = fma(r0, B.y, fma(r1, C.x, r2 * C.y));
+    const double q2 = q * q;
+    const double b = rs * (q * q2);
+    const double cD = (rn * b) * q2;
+    sa[0] = fma(q, D.x, sa[0]);
+    sa[1] = fma(q, D.y, sa[1]);
+    sa[2] = fma(q, F.x, sa[2]);
+    sb[0] = fma(b, r0, sb[0]);
+    sb[1] = fma(b, r1, sb[1]);
+    sb[2] = fma(b, r2, sb[2]);
+    sd[0] = fma(cD, r0, sd[0]);
+    sd[1] = fma(cD, r1, sd[1]);
+    sd[2] = fma(cD, r2, sd[2]);
 }
 
 // interpolate the CLQ centerline quantities of element data clq (layout
@@ -621,7 +658,7 @@ __global__ __launch_bounds__(FAR_BLOCK) void k_far(int64_t T, const double* __re
     const int tid = threadIdx.x;
     const FarTile tl = tiles[blockIdx.x];
     const int64_t tb = tl.t0 + tid, tend = tl.t0 + tl.tn;
-    double x[TPT][3], us[TPT][3], ud[TPT][3];
+    double x[TPT][3], sa[TPT][3], sb[TPT][3], sd[TPT][3];
 #pragma unroll
     for (int u = 0; u < TPT; ++u) {
         const int64_t t = tb + u * FAR_BLOCK;
@@ -629,7 +666,7 @@ __global__ __launch_bounds__(FAR_BLOCK) void k_far(int64_t T, const double* __re
         x[u][0] = ok ? xt[t] : 0.0;
         x[u][1] = ok ? xt[T + t] : 0.0;
         x[u][2] = ok ? xt[2 * T + t] : 0.0;
-        for (int d = 0; d < 3; ++d) us[u][d] = ud[u][d] = 0.0;
+        for (int d = 0; d < 3; ++d) sa[u][d] = sb[u][d] = sd[u][d] = 0.0;
     }
     const int64_t c0 = tl.s0;
     const int64_t c1 = tl.s0 + tl.sn;
@@ -654,24 +691,8 @@ __global__ __launch_bounds__(FAR_BLOCK) void k_far(int64_t T, const double* __re
         for (int kk = 0; kk < nin; ++kk) {
             const double2* r2 = reinterpret_cast<const double2*>(src + kk * FAR_REC);
             const double2 A = r2[0], B = r2[1], C = r2[2], D = r2[3], F = r2[4];
-            // A = (y0, y1), B = (y2, n0), C = (n1, n2), D = (w0, w1), F = (w2, -)
 #pragma unroll
-            for (int u = 0; u < TPT; ++u) {
-                const double r0 = x[u][0] - A.x, r1 = x[u][1] - A.y, r2_ = x[u][2] - B.x;
-                const double rr = fma(r0, r0, fma(r1, r1, r2_ * r2_));
-                const double ir = rsqrt_or_zero(rr);   // branch-free self term
-                const double rs = fma(r0, D.x, fma(r1, D.y, r2_ * F.x));
-                const double rn = fma(r0, B.y, fma(r1, C.x, r2_ * C.y));
-                const double ir2 = ir * ir;
-                const double b = rs * (ir * ir2);      // (r.sw) / r^3
-                const double cD = (rn * b) * ir2;      // (r.n)(r.sw) / r^5
-                us[u][0] = fma(ir, D.x, fma(b, r0, us[u][0]));
-                us[u][1] = fma(ir, D.y, fma(b, r1, us[u][1]));
-                us[u][2] = fma(ir, F.x, fma(b, r2_, us[u][2]));
-                ud[u][0] = fma(cD, r0, ud[u][0]);
-                ud[u][1] = fma(cD, r1, ud[u][1]);
-                ud[u][2] = fma(cD, r2_, ud[u][2]);
-            }
+            for (int u = 0; u < TPT; ++u) pair_scaled(x[u], A, B, C, D, F, sa[u], sb[u], sd[u]);
         }
         __syncthreads();
     }
@@ -680,12 +701,12 @@ __global__ __launch_bounds__(FAR_BLOCK) void k_far(int64_t T, const double* __re
     for (int u = 0; u < TPT; ++u) {
         const int64_t t = tb + u * FAR_BLOCK;
         if (t < tend) {
-            p[0 * T + t] = us[u][0];
-            p[1 * T + t] = us[u][1];
-            p[2 * T + t] = us[u][2];
-            p[3 * T + t] = ud[u][0];
-            p[4 * T + t] = ud[u][1];
-            p[5 * T + t] = ud[u][2];
+            p[0 * T + t] = fma(0.5, sa[u][0], 0.125 * sb[u][0]);
+            p[1 * T + t] = fma(0.5, sa[u][1], 0.125 * sb[u][1]);
+            p[2 * T + t] = fma(0.5, sa[u][2], 0.125 * sb[u][2]);
+            p[3 * T + t] = 0.03125 * sd[u][0];
+            p[4 * T + t] = 0.03125 * sd[u][1];
+            p[5 * T + t] = 0.03125 * sd[u][2];
         }
     }
 }
@@ -835,7 +856,7 @@ __global__ __launch_bounds__(FAR_BLOCK) void k_far_mx(int64_t T, const double* _
                     const float rr = fmaf(r0, r0, fmaf(r1, r1, r2 * r2));
                     if (rr < near2f) {
                         const double rr64 = fma(d0, d0, fma(d1, d1, d2 * d2));
-                        const double irn = rsqrt_nr(rr64);
+                        const double irn = rsqrt_nr1(rr64);
                         const double ir = rr64 > 0.0 ? irn : 0.0;
                         const double rs = fma(d0, R.w[0], fma(d1, R.w[1], d2 * R.w[2]));
                         const double rn = fma(d0, R.n[0], fma(d1, R.n[1], d2 * R.n[2]));
@@ -1248,7 +1269,7 @@ __global__ __launch_bounds__(64) void k_corr_up(int64_t Mf, const int* __restric
     const int w = blockIdx.x, lane = threadIdx.x;
     const int e = ws[3 * w + 2];
     int64_t p[UP_TPT];
-    double x[UP_TPT][3], us[UP_TPT][3], ud[UP_TPT][3];
+    double x[UP_TPT][3], sa[UP_TPT][3], sb[UP_TPT][3], sd[UP_TPT][3];
 #pragma unroll
     for (int u = 0; u < UP_TPT; ++u) {
         const int k = lane + 64 * u;
@@ -1257,7 +1278,7 @@ __global__ __launch_bounds__(64) void k_corr_up(int64_t Mf, const int* __restric
         x[u][0] = t >= 0 ? xt[t] : 0.0;
         x[u][1] = t >= 0 ? xt[T + t] : 0.0;
         x[u][2] = t >= 0 ? xt[2 * T + t] : 0.0;
-        for (int d = 0; d < 3; ++d) us[u][d] = ud[u][d] = 0.0;
+        for (int d = 0; d < 3; ++d) sa[u][d] = sb[u][d] = sd[u][d] = 0.0;
     }
     const int64_t nbase = boff[e + 1] - boff[e];
     for (int pass = 0; pass < 2; ++pass) {
@@ -1291,22 +1312,7 @@ __global__ __launch_bounds__(64) void k_corr_up(int64_t Mf, const int* __restric
                 const double2* r2 = reinterpret_cast<const double2*>(src + kk * FAR_REC);
                 const double2 A = r2[0], B = r2[1], C = r2[2], D = r2[3], F = r2[4];
 #pragma unroll
-                for (int u = 0; u < UP_TPT; ++u) {
-                    const double r0 = x[u][0] - A.x, r1 = x[u][1] - A.y, r2_ = x[u][2] - B.x;
-                    const double rr = fma(r0, r0, fma(r1, r1, r2_ * r2_));
-                    const double ir = rsqrt_or_zero(rr);
-                    const double rs = fma(r0, D.x, fma(r1, D.y, r2_ * F.x));
-                    const double rn = fma(r0, B.y, fma(r1, C.x, r2_ * C.y));
-                    const double ir2 = ir * ir;
-                    const double b = rs * (ir * ir2);
-                    const double cD = (rn * b) * ir2;
-                    us[u][0] = fma(ir, D.x, fma(b, r0, us[u][0]));
-                    us[u][1] = fma(ir, D.y, fma(b, r1, us[u][1]));
-                    us[u][2] = fma(ir, F.x, fma(b, r2_, us[u][2]));
-                    ud[u][0] = fma(cD, r0, ud[u][0]);
-                    ud[u][1] = fma(cD, r1, ud[u][1]);
-                    ud[u][2] = fma(cD, r2_, ud[u][2]);
-                }
+                for (int u = 0; u < UP_TPT; ++u) pair_scaled(x[u], A, B, C, D, F, sa[u], sb[u], sd[u]);
             }
             __syncthreads();
         }
@@ -1315,12 +1321,12 @@ __global__ __launch_bounds__(64) void k_corr_up(int64_t Mf, const int* __restric
     for (int u = 0; u < UP_TPT; ++u) {
         if (p[u] >= 0) {
             double* o = corr + p[u] * 6;
-            o[0] = us[u][0];
-            o[1] = us[u][1];
-            o[2] = us[u][2];
-            o[3] = ud[u][0];
-            o[4] = ud[u][1];
-            o[5] = ud[u][2];
+            o[0] = fma(0.5, sa[u][0], 0.125 * sb[u][0]);
+            o[1] = fma(0.5, sa[u][1], 0.125 * sb[u][1]);
+            o[2] = fma(0.5, sa[u][2], 0.125 * sb[u][2]);
+            o[3] = 0.03125 * sd[u][0];
+            o[4] = 0.03125 * sd[u][1];
+            o[5] = 0.03125 * sd[u][2];
         }
     }
 }
@@ -1712,13 +1718,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
 #pragma unroll
             for (int u = 0; u < PPL; ++u) {
                 const double gq = sp_ + a13 * cth[u] + a23 * sth[u];
-                const double J = E * sqrt(gq * gq + Ep * Ep);
+                // g^2 + eps'^2 > 0 on any admissible tube (eps * curvature < 1)
+                const double jq = fma(gq, gq, Ep * Ep);
+                const double J = E * (jq * rsqrt_nr1(jq));
                 const double A = dr + E * omc[u], B = -E * sph[u];
                 double r[3];
 #pragma unroll
                 for (int d = 0; d < 3; ++d) r[d] = z * tv[d] + A * b0v[d] + B * b0pv[d];
                 const double rr = z * z + A * A + B * B;
-                const double ir = rr > 0.0 ? rsqrt_nr(rr) : 0.0;
+                const double ir = rr > 0.0 ? rsqrt_nr1(rr) : 0.0;
                 const double ir2 = ir * ir;
                 const double W = Wsn * wq[u];
                 const double rs = r[0] * v[u][0] + r[1] * v[u][1] + r[2] * v[u][2];
@@ -1741,7 +1749,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
         int64_t n = bo + k;
         double r0 = x[0] - by[n], r1 = x[1] - by[Nb + n], r2 = x[2] - by[2 * Nb + n];
         double rr = r0 * r0 + r1 * r1 + r2 * r2;
-        double ir = rr > 0.0 ? rsqrt_nr(rr) : 0.0;
+        double ir = rr > 0.0 ? rsqrt_nr1(rr) : 0.0;
         double ir2 = ir * ir;
         double w0 = bsw[n], w1 = bsw[Nb + n], w2 = bsw[2 * Nb + n];
         double rs = r0 * w0 + r1 * w1 + r2 * w2;

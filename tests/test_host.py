@@ -67,14 +67,18 @@ def test_shipped_gate_weights():
     assert conf.shape == (5, 5) and conf.sum() == int(meta["n_train"])
 
 
-def test_traffic_record_is_complete():
-    path = os.path.join(ROOT, "profiles", "traffic_k_corr_full_pipe100_spheres200_fp64.json")
-    rec = json.load(open(path))
-    for k in ("kernel", "fetch_kib", "write_kib", "fetch_factor", "write_factor", "traffic_bytes", "kernels_sha1",
-              "commands"):
-        assert k in rec, k
-    expect = rec["fetch_kib"] * 1024 / rec["fetch_factor"] + rec["write_kib"] * 1024 / rec["write_factor"]
-    assert abs(expect - rec["traffic_bytes"]) < 1e-6 * expect
+def test_traffic_records_are_complete():
+    import glob
+    paths = sorted(glob.glob(os.path.join(ROOT, "profiles", "traffic_*_pipe100_spheres200_*.json")))
+    assert paths
+    for path in paths:
+        rec = json.load(open(path))
+        for k in ("kernel", "precision", "fetch_kib", "write_kib", "fetch_factor", "write_factor", "traffic_bytes",
+                  "kernels_sha1", "commands"):
+            assert k in rec, (path, k)
+        assert os.path.basename(path) == f"traffic_{rec['kernel']}_pipe100_spheres200_{rec['precision']}.json"
+        expect = rec["fetch_kib"] * 1024 / rec["fetch_factor"] + rec["write_kib"] * 1024 / rec["write_factor"]
+        assert abs(expect - rec["traffic_bytes"]) < 1e-6 * expect
 
 
 def test_create_without_device_fails_cleanly():
