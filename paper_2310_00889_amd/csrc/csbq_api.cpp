@@ -790,6 +790,44 @@ static int group_ranges(csbq_ctx* ctx, int64_t T, int flags, std::vector<int64_t
 // Smooth-sum blocks: per group, blocks of 256*tpt consecutive targets times
 // chunks of `chunk` sources, ordered by cost (largest first) so that one
 // launch drains a batch of unequal geometries evenly.
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2: block i runs on XCD i mod 8.  Within each run of equal-cost tiles
+// (the cost order is kept for load balance), tiles are re-placed so that the
+// blocks of one XCD take source chunks s0/chunk = XCD (mod 8), chunk by
+// chunk: an XCD then streams one or two chunks (a few hundred KB) at a time
+// from its L2 instead of every chunk of the sum from HBM.
+static void xcd_order(std::vector<FarTile>& tiles, int64_t chunk)
+{
+    constexpr int NX = 8;
+    std::vector<FarTile> q[NX];
+    size_t i0 = 0;
+    while (i0 < tiles.size()) {
+        const int64_t cost = (int64_t)tiles[i0].tn * tiles[i0].sn;
+        size_t i1 = i0;
+        while (i1 < tiles.size() && (int64_t)tiles[i1].tn * tiles[i1].sn == cost) ++i1;
+        for (auto& v : q) v.clear();
+        for (size_t i = i0; i < i1; ++i) q[(tiles[i].s0 / chunk) % NX].push_back(tiles[i]);
+        for (auto& v : q)
+            std::stable_sort(v.begin(), v.end(), [](const FarTile& a, const FarTile& b) {
+                return a.s0 != b.s0 ? a.s0 < b.s0 : a.t0 < b.t0;
+            });
+        size_t head[NX] = {};
+        for (size_t i = i0; i < i1; ++i) {
+            int x = (int)(i % NX);
+            if (head[x] == q[x].size()) {   // this XCD's share is used up: take from the fullest
+                size_t best = 0;
+                for (int y = 0; y < NX; ++y)
+                    if (q[y].size() - head[y] > best) {
+                        best = q[y].size() - head[y];
+                        x = y;
+                    }
+            }
+            tiles[i] = q[x][head[x]++];
+        }
+        i0 = i1;
+    }
+}
+
 static void far_tiles(const csbq_ctx* ctx, const std::vector<int64_t>& tr, bool native, int tpt, int64_t chunk,
                       int g_only, int64_t t_cap, std::vector<FarTile>& tiles, std::vector<int>& gnc, int* maxchunk)
 {
@@ -816,6 +854,7 @@ static void far_tiles(const csbq_ctx* ctx, const std::vector<int64_t>& tr, bool 
     std::stable_sort(tiles.begin(), tiles.end(), [](const FarTile& a, const FarTile& b) {
         return (int64_t)a.tn * a.sn > (int64_t)b.tn * b.sn;
     });
+    xcd_order(tiles, chunk);
 }
 
 // Launch shape of the smooth sum, chosen by timing: targets per thread 1/2/4
