@@ -1386,15 +1386,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
                                                   int* __restrict__ work, int cstride)
 {
     // cf: [SB][cstride] density coefficients at the batch's s-nodes, cstride =
-    // 6 (largest band + 1) over all elements (dynamic LDS)
+    // 6 (largest band + 1) over all elements (dynamic LDS, at least SB x NS
+    // doubles).  The same space holds the bisection stack while the s-rule
+    // is built and each batch's interpolation weights [SB][NS] from phase 1
+    // until phase 2 has read them, which keeps the block's LDS small enough
+    // for three waves per SIMD.
     extern __shared__ __attribute__((aligned(16))) double cf[];
-    __shared__ double sq[CLQ * NS];
+    double* const lwl = cf;
+    double* const st_lo = cf;
+    double* const st_hi = cf + 48;
     __shared__ __attribute__((aligned(16))) double rec[SB][NREC];
-    __shared__ double lwl[SB][NS];
     __shared__ int rq_off[SB], rq_step[SB], npt[SB], pref[SB + 1];
     __shared__ double sub_lo[MAXSUB], sub_hi[MAXSUB];
     __shared__ int sub_ty[MAXSUB], soff[MAXSUB + 1];
-    __shared__ double st_lo[48], st_hi[48];
     __shared__ int nsub;
     __shared__ double f0d[12];   // own-element target: E0, Xp0[3], sp0, t0[3], bn[3]
     const int lane = threadIdx.x;
@@ -1403,11 +1407,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
     const int64_t t = pt[p];
     const ElemInfo inf = info[e];
     const double x[3] = {xt[t], xt[T + t], xt[2 * T + t]};
-    for (int o = lane; o < CLQ * NS; o += 64) sq[o] = clq[(int64_t)e * CLQ * NS + o];
+    // the element's centerline data, read at wave-uniform addresses
+    const double* __restrict__ sq = clq + (int64_t)e * CLQ * NS;
     const int64_t nd = tnode ? tnode[t] : -1;
     const bool own = nd >= 0 && nd / NPE == e;
     const int Ms = band[2 * e], Mt = band[2 * e + 1];
     const int ncoef = 6 * (Mt + 1);
+    // thresholds on the circle's cosh(alpha) - 1 above which a trapezoid rule
+    // of nt, 2nt or 4nt points meets the tolerance (Section 3.2.2)
+    double trap_thr[3];
+    {
+        const double lg = log(gc.ct / gc.tol);
+        for (int k = 0; k < 3; ++k) trap_thr[k] = cosh(lg / (double)((NT << k) - Mt - gc.extra_modes)) - 1.0;
+    }
     const double* __restrict__ she = sh + (int64_t)e * NS * NSH;
     __syncthreads();
     int i0 = 0;
@@ -1537,7 +1549,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
             else
                 bary_weights_rcp((s - inf.a) / hw - 1.0, lw);
 #pragma unroll
-            for (int i = 0; i < NS; ++i) lwl[lane][i] = lw[i];
+            for (int i = 0; i < NS; ++i) lwl[lane * NS + i] = lw[i];
             double q[CLQ], dq[CLQ];
 #pragma unroll
             for (int k = 0; k < CLQ; ++k) {
@@ -1574,10 +1586,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
             // theta-rule for this circle (Section 3.2.2): trapezoid of nt, 2nt
             // or 4nt points if the estimate allows, else the bracket's
             // generalized Chebyshev rule
-            const double lg = log(gc.ct / gc.tol);
             int ntr = 0, rb = 0;
             for (int k = 0; k < 3 && !ntr; ++k)
-                if (cl.cha >= cosh(lg / (double)((NT << k) - Mt - gc.extra_modes)) - 1.0) ntr = NT << k;
+                if (cl.cha >= trap_thr[k]) ntr = NT << k;
             if (!ntr) {
                 int ex;
                 frexp(sqrt(cl.d2) / fr.E, &ex);   // alpha in [2^(ex-1), 2^ex)
@@ -1628,7 +1639,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
             const int r = lane & 15, qq = lane >> 4;
             double wa[NS / 4];
 #pragma unroll
-            for (int ks = 0; ks < NS / 4; ++ks) wa[ks] = (r < nb) ? lwl[r][4 * ks + qq] : 0.0;
+            for (int ks = 0; ks < NS / 4; ++ks) wa[ks] = (r < nb) ? lwl[r * NS + 4 * ks + qq] : 0.0;
+            __syncthreads();   // the weights are read before cf overwrites them
             for (int cb = 0; cb * 16 < ncoef; ++cb) {
                 const int col = cb * 16 + r;
                 v4d acc = {0.0, 0.0, 0.0, 0.0};
@@ -2008,7 +2020,8 @@ int launch_corr_full(hipStream_t st, int nfull, const int* listf, const int* pe,
     if (mt_max < 0 || mt_max >= NMODE) return (int)hipErrorInvalidValue;
     RuleTables rt{roff, rth, rw, rcs, rsn, romc, nb, lx, lw, nl};
     const int cstride = 6 * (mt_max + 1);
-    hipLaunchKernelGGL(k_corr_full, dim3(nfull), dim3(64), (size_t)SB * cstride * sizeof(double), st, listf, pe, pt,
+    const size_t lds = (size_t)SB * (cstride > NS ? cstride : NS) * sizeof(double);   // >= the weights and the stack
+    hipLaunchKernelGGL(k_corr_full, dim3(nfull), dim3(64), lds, st, listf, pe, pt,
                        xt, T, tnode, clq, sh, info, band, cls, boff, by, bn, bsw, Nb, rt, gc, corr, err, work,
                        cstride);
     LAUNCH_CHECK();
