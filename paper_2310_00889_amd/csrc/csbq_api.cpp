@@ -187,7 +187,7 @@ struct csbq_ctx {
     DBuf<double> sig_d, x_d, usl_d, udl_d;
     DBuf<int64_t> tn_d;
     DBuf<double> sw, sh, rnear, xt, part, cls, corr, swf[NUP];
-    DBuf<int> band, cnt, pe, pt, err_d, work, kin, kout, vin, perm, sorted, runs_key, runs_cnt, nruns, wdesc[NUP];
+    DBuf<int> band, cnt, pe, pt, err_d, work, kin, kout, vin, perm, sorted, runs_key, runs_cnt, nruns, wdesc;
     DBuf<int64_t> off, gstart;
     DBuf<int> tgroup, tgrp_d, gnchunk;
     DBuf<FarTile> tiles;
@@ -212,7 +212,8 @@ struct csbq_ctx {
     struct Plan {
         bool valid = false;
         int64_t T = 0;
-        int nwaves[NUP] = {0, 0, 0};
+        int nwaves[NUP] = {0, 0, 0};   // upsampled-rule wavefronts per tier
+        int nw_up = 0;                 // all of them, in the one launch
         int nfull = 0, full_start = 0, mt_max = 0, ntiles = 0, tpt = 2;
         bool mixed = false;
         const int64_t* tn = nullptr;
@@ -465,8 +466,8 @@ int csbq_destroy(csbq_ctx* ctx)
         ctx->upx[k].release();
         ctx->upw[k].release();
         ctx->swf[k].release();
-        ctx->wdesc[k].release();
     }
+    ctx->wdesc.release();
     ctx->sig_d.release();
     ctx->x_d.release();
     ctx->usl_d.release();
@@ -790,6 +791,20 @@ static int group_ranges(csbq_ctx* ctx, int64_t T, int flags, std::vector<int64_t
 // Smooth-sum blocks: per group, blocks of 256*tpt consecutive targets times
 // chunks of `chunk` sources, ordered by cost (largest first) so that one
 // launch drains a batch of unequal geometries evenly.
+// the context's upsampled rules of every tier, as the corrections kernel takes them
+static UpRules up_rules(const csbq_ctx* ctx)
+{
+    UpRules ur{};
+    for (int k = 0; k < NUP; ++k) {
+        ur.y[k] = ctx->cpy[k].p;
+        ur.n[k] = ctx->cpn[k].p;
+        ur.sw[k] = ctx->swf[k].p;
+        ur.Mf[k] = up_pts(k);
+        ur.Mtot[k] = ctx->Mtot[k];
+    }
+    return ur;
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own
 // L2: block i runs on XCD i mod 8.  Within each run of equal-cost tiles
 // (the cost order is kept for load balance), tiles are re-placed so that the
@@ -1187,6 +1202,7 @@ int csbq_eval_batch(csbq_ctx* ctx, const double* sigma, int64_t T, const double*
                     wd[trr - 1].push_back(pos + o);
                     wd[trr - 1].push_back(std::min(UP_PAIRS, c - o));
                     wd[trr - 1].push_back(e);
+                    wd[trr - 1].push_back(trr - 1);
                 }
                 npair[trr - 1] += c;
             } else if (trr == TIER_FULL) {
@@ -1196,13 +1212,17 @@ int csbq_eval_batch(csbq_ctx* ctx, const double* sigma, int64_t T, const double*
             pos += c;
         }
     }
+    // one launch for every upsampled tier, the largest rules' wavefronts
+    // first so that the short ones fill the device's tail
     int nwaves[NUP];
-    for (int ti = 0; ti < NUP; ++ti) {
-        nwaves[ti] = (int)(wd[ti].size() / 3);
-        ALLOC(ctx->wdesc[ti], wd[ti].size() + 1);
-        if (nwaves[ti])
-            HIPC(hipMemcpy(ctx->wdesc[ti].p, wd[ti].data(), wd[ti].size() * sizeof(int), hipMemcpyHostToDevice));
+    std::vector<int> wall;
+    for (int ti = NUP - 1; ti >= 0; --ti) {
+        nwaves[ti] = (int)(wd[ti].size() / 4);
+        wall.insert(wall.end(), wd[ti].begin(), wd[ti].end());
     }
+    const int nw_up = (int)(wall.size() / 4);
+    ALLOC(ctx->wdesc, wall.size() + 1);
+    if (nw_up) HIPC(hipMemcpy(ctx->wdesc.p, wall.data(), wall.size() * sizeof(int), hipMemcpyHostToDevice));
     HIPC(hipEventRecord(ctx->ph[4].b, st));
     // the smooth sum over every base source of the target's group (on the
     // same stream: it and the corrections are both VALU-bound, and running
@@ -1212,17 +1232,14 @@ int csbq_eval_batch(csbq_ctx* ctx, const double* sigma, int64_t T, const double*
     HIPC(hipEventRecord(ctx->ph[1].b, st));
     // upsampled-rule corrections
     HIPC(hipEventRecord(ctx->ph[5].a, st));
-    for (int ti = 0; ti < NUP; ++ti) {
+    for (int ti = 1; ti < NUP; ++ti) {
         if (!nwaves[ti]) continue;
-        if (ti > 0) {
-            ALLOC(ctx->swf[ti], (size_t)ctx->Mtot[ti] * 3);
-            LCHK(launch_sigma_up(st, E, up_ns(ti), up_nt(ti), ctx->sh.p, ctx->Lup[ti].p, ctx->cpw[ti].p,
-                                 ctx->swf[ti].p, ctx->Mtot[ti]));
-        }
-        LCHK(launch_corr_up(st, up_pts(ti), nwaves[ti], ctx->wdesc[ti].p, ctx->sorted.p, ctx->pt.p, ctx->xt.p, T,
-                            ctx->cpy[ti].p, ctx->cpn[ti].p, ctx->swf[ti].p, ctx->Mtot[ti], ctx->boff.p, ctx->by.p,
-                            ctx->bn.p, ctx->bsw.p, ctx->Nb, ctx->corr.p));
+        ALLOC(ctx->swf[ti], (size_t)ctx->Mtot[ti] * 3);
+        LCHK(launch_sigma_up(st, E, up_ns(ti), up_nt(ti), ctx->sh.p, ctx->Lup[ti].p, ctx->cpw[ti].p, ctx->swf[ti].p,
+                             ctx->Mtot[ti]));
     }
+    LCHK(launch_corr_up(st, up_rules(ctx), nw_up, ctx->wdesc.p, ctx->sorted.p, ctx->pt.p, ctx->xt.p, T, ctx->boff.p,
+                        ctx->by.p, ctx->bn.p, ctx->bsw.p, ctx->Nb, ctx->corr.p));
     HIPC(hipEventRecord(ctx->ph[5].b, st));
     // special quadrature corrections
     HIPC(hipEventRecord(ctx->ph[6].a, st));
@@ -1248,6 +1265,7 @@ int csbq_eval_batch(csbq_ctx* ctx, const double* sigma, int64_t T, const double*
         auto& pl = ctx->plan;
         pl.T = T;
         for (int ti = 0; ti < NUP; ++ti) pl.nwaves[ti] = nwaves[ti];
+        pl.nw_up = nw_up;
         pl.nfull = nfull;
         pl.full_start = full_start;
         pl.mt_max = mt_max;
@@ -1279,15 +1297,12 @@ static int enqueue_apply(csbq_ctx* ctx, hipStream_t st)
                            ctx->Nb));
     LCHK(launch_far(st, T, ctx->xt.p, ctx->by.p, ctx->bn.p, ctx->bsw.p, ctx->Nb, ctx->tiles.p, pl.ntiles, ctx->part.p,
                     pl.mixed, ctx->mix_near2, pl.tpt));
-    for (int ti = 0; ti < NUP; ++ti) {
-        if (!pl.nwaves[ti]) continue;
-        if (ti > 0)
+    for (int ti = 1; ti < NUP; ++ti)
+        if (pl.nwaves[ti])
             LCHK(launch_sigma_up(st, E, up_ns(ti), up_nt(ti), ctx->sh.p, ctx->Lup[ti].p, ctx->cpw[ti].p,
                                  ctx->swf[ti].p, ctx->Mtot[ti]));
-        LCHK(launch_corr_up(st, up_pts(ti), pl.nwaves[ti], ctx->wdesc[ti].p, ctx->sorted.p, ctx->pt.p, ctx->xt.p, T,
-                            ctx->cpy[ti].p, ctx->cpn[ti].p, ctx->swf[ti].p, ctx->Mtot[ti], ctx->boff.p, ctx->by.p,
-                            ctx->bn.p, ctx->bsw.p, ctx->Nb, ctx->corr.p));
-    }
+    LCHK(launch_corr_up(st, up_rules(ctx), pl.nw_up, ctx->wdesc.p, ctx->sorted.p, ctx->pt.p, ctx->xt.p, T,
+                        ctx->boff.p, ctx->by.p, ctx->bn.p, ctx->bsw.p, ctx->Nb, ctx->corr.p));
     LCHK(launch_corr_full(st, pl.nfull, ctx->sorted.p + pl.full_start, ctx->pe.p, ctx->pt.p, ctx->xt.p, T, pl.tn,
                           ctx->clq.p, ctx->sh.p, ctx->info.p, ctx->band.p, ctx->cls.p, ctx->boff.p, ctx->by.p,
                           ctx->bn.p, ctx->bsw.p, ctx->Nb, ctx->roff.p, ctx->rth.p, ctx->rw.p, ctx->nb, ctx->lx.p,
@@ -1574,30 +1589,30 @@ int csbq_gate_dataset(csbq_ctx* ctx, const double* sigma, int64_t T, const doubl
     HIPC(hipMemcpyAsync(hperm.data(), ctx->perm.p, (size_t)P * 4, hipMemcpyDeviceToHost, st));
     HIPC(hipMemcpyAsync(hpe.data(), ctx->pe.p, (size_t)P * 4, hipMemcpyDeviceToHost, st));
     HIPC(hipStreamSynchronize(st));
-    std::vector<int> wd;
-    for (int64_t i = 0; i < P;) {
-        const int e = hpe[hperm[i]];
-        int64_t j = i;
-        while (j < P && hpe[hperm[j]] == e) ++j;
-        for (int64_t o = i; o < j; o += UP_PAIRS) {
-            wd.push_back((int)o);
-            wd.push_back((int)std::min<int64_t>(UP_PAIRS, j - o));
-            wd.push_back(e);
-        }
-        i = j;
-    }
-    const int nw = (int)(wd.size() / 3);
-    DBuf<int> dwd;
-    if ((rc = to_device(ctx, dwd, wd.data(), wd.size(), CSBQ_HOST))) return rc;
+    DBuf<int> dwd[NUP];
     DBuf<double> cup[NUP], cfull;
     for (int ti = 0; ti < NUP; ++ti) {
+        std::vector<int> wd;
+        for (int64_t i = 0; i < P;) {
+            const int e = hpe[hperm[i]];
+            int64_t j = i;
+            while (j < P && hpe[hperm[j]] == e) ++j;
+            for (int64_t o = i; o < j; o += UP_PAIRS) {
+                wd.push_back((int)o);
+                wd.push_back((int)std::min<int64_t>(UP_PAIRS, j - o));
+                wd.push_back(e);
+                wd.push_back(ti);
+            }
+            i = j;
+        }
+        const int nw = (int)(wd.size() / 4);
+        if ((rc = to_device(ctx, dwd[ti], wd.data(), wd.size(), CSBQ_HOST))) return rc;
         ALLOC(cup[ti], (size_t)P * 6 + 1);
         ALLOC(ctx->swf[ti], (size_t)ctx->Mtot[ti] * 3);
         LCHK(launch_sigma_up(st, E, up_ns(ti), up_nt(ti), ctx->sh.p, ctx->Lup[ti].p, ctx->cpw[ti].p, ctx->swf[ti].p,
                              ctx->Mtot[ti]));
-        LCHK(launch_corr_up(st, up_pts(ti), nw, dwd.p, ctx->perm.p, ctx->pt.p, ctx->xt.p, T, ctx->cpy[ti].p,
-                            ctx->cpn[ti].p, ctx->swf[ti].p, ctx->Mtot[ti], ctx->boff.p, ctx->by.p, ctx->bn.p,
-                            ctx->bsw.p, ctx->Nb, cup[ti].p));
+        LCHK(launch_corr_up(st, up_rules(ctx), nw, dwd[ti].p, ctx->perm.p, ctx->pt.p, ctx->xt.p, T, ctx->boff.p,
+                            ctx->by.p, ctx->bn.p, ctx->bsw.p, ctx->Nb, cup[ti].p));
     }
     ALLOC(cfull, (size_t)P * 6 + 1);
     std::vector<int> hband((size_t)2 * E);

@@ -1251,14 +1251,14 @@ __global__ void k_tier_keys(int64_t P, int E, const int8_t* __restrict__ tier, c
 // upsampled tiers: upsampled rule minus smooth rule, one wavefront per 64
 // pairs of one element; the element's correction points are staged in LDS
 // ---------------------------------------------------------------------------
-// wave w covers sorted[ws[3w] .. ws[3w] + ws[3w+1]) of element ws[3w+2]:
-// the element's tier rule (Mf points) plus its base rule with negated weight,
-// staged in LDS 64 points at a time.
-__global__ __launch_bounds__(64) void k_corr_up(int64_t Mf, const int* __restrict__ ws,
+// wave w covers sorted[ws[4w] .. ws[4w] + ws[4w+1]) of element ws[4w+2]
+// with the rule of tier index ws[4w+3]: the element's tier rule (Mf points)
+// plus its base rule with negated weight, staged in LDS 64 points at a time.
+// One launch serves every tier, so the host can order the wavefronts by cost.
+static_assert(NUP == 3, "k_corr_up selects among three tiers' rules");
+__global__ __launch_bounds__(64) void k_corr_up(UpRules ur, const int* __restrict__ ws,
                                                 const int* __restrict__ sorted, const int* __restrict__ pt,
                                                 const double* __restrict__ xt, int64_t T,
-                                                const double* __restrict__ cpy, const double* __restrict__ cpn,
-                                                const double* __restrict__ swf, int64_t Mtot,
                                                 const int64_t* __restrict__ boff, const double* __restrict__ by,
                                                 const double* __restrict__ bn, const double* __restrict__ bsw,
                                                 int64_t Nb, double* __restrict__ corr)
@@ -1267,13 +1267,18 @@ __global__ __launch_bounds__(64) void k_corr_up(int64_t Mf, const int* __restric
     // pairs per lane; rule points staged through LDS as 16-byte-pair records
     __shared__ __attribute__((aligned(16))) double src[64 * FAR_REC];
     const int w = blockIdx.x, lane = threadIdx.x;
-    const int e = ws[3 * w + 2];
+    const int e = ws[4 * w + 2], ti = ws[4 * w + 3];
+    const double* __restrict__ cpy = ti == 0 ? ur.y[0] : (ti == 1 ? ur.y[1] : ur.y[2]);
+    const double* __restrict__ cpn = ti == 0 ? ur.n[0] : (ti == 1 ? ur.n[1] : ur.n[2]);
+    const double* __restrict__ swf = ti == 0 ? ur.sw[0] : (ti == 1 ? ur.sw[1] : ur.sw[2]);
+    const int64_t Mf = ti == 0 ? ur.Mf[0] : (ti == 1 ? ur.Mf[1] : ur.Mf[2]);
+    const int64_t Mtot = ti == 0 ? ur.Mtot[0] : (ti == 1 ? ur.Mtot[1] : ur.Mtot[2]);
     int64_t p[UP_TPT];
     double x[UP_TPT][3], sa[UP_TPT][3], sb[UP_TPT][3], sd[UP_TPT][3];
 #pragma unroll
     for (int u = 0; u < UP_TPT; ++u) {
         const int k = lane + 64 * u;
-        p[u] = (k < ws[3 * w + 1]) ? (int64_t)sorted[(int64_t)ws[3 * w] + k] : -1;
+        p[u] = (k < ws[4 * w + 1]) ? (int64_t)sorted[(int64_t)ws[4 * w] + k] : -1;
         const int64_t t = p[u] >= 0 ? pt[p[u]] : -1;
         x[u][0] = t >= 0 ? xt[t] : 0.0;
         x[u][1] = t >= 0 ? xt[T + t] : 0.0;
@@ -1997,14 +2002,13 @@ int launch_tier_keys(hipStream_t st, int64_t P, int E, const int8_t* tier, const
     return 0;
 }
 
-int launch_corr_up(hipStream_t st, int64_t Mf, int nwaves, const int* ws, const int* sorted, const int* pt,
-                   const double* xt, int64_t T, const double* cpy, const double* cpn, const double* swf,
-                   int64_t Mtot, const int64_t* boff, const double* by, const double* bn, const double* bsw,
-                   int64_t Nb, double* corr)
+int launch_corr_up(hipStream_t st, const UpRules& ur, int nwaves, const int* ws, const int* sorted, const int* pt,
+                   const double* xt, int64_t T, const int64_t* boff, const double* by, const double* bn,
+                   const double* bsw, int64_t Nb, double* corr)
 {
     if (nwaves == 0) return 0;
-    hipLaunchKernelGGL(k_corr_up, dim3(nwaves), dim3(64), 0, st, Mf, ws, sorted, pt, xt, T, cpy, cpn, swf, Mtot,
-                       boff, by, bn, bsw, Nb, corr);
+    hipLaunchKernelGGL(k_corr_up, dim3(nwaves), dim3(64), 0, st, ur, ws, sorted, pt, xt, T, boff, by, bn, bsw, Nb,
+                       corr);
     LAUNCH_CHECK();
     return 0;
 }

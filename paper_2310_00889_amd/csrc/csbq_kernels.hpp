@@ -40,10 +40,21 @@ int launch_classify(hipStream_t st, int64_t P, const int* perm, const int* pe, c
                     const int* band, GateConsts gc, int8_t* tier, double* cls);
 int launch_iota(hipStream_t st, int64_t P, int* v);
 int launch_tier_keys(hipStream_t st, int64_t P, int E, const int8_t* tier, const int* pe, int* key, int* val);
-int launch_corr_up(hipStream_t st, int64_t Mf, int nwaves, const int* ws, const int* sorted, const int* pt,
-                   const double* xt, int64_t T, const double* cpy, const double* cpn, const double* swf,
-                   int64_t Mtot, const int64_t* boff, const double* by, const double* bn, const double* bsw,
-                   int64_t Nb, double* corr);
+// points (y, n, sigma w) of the upsampled rules of every element, per tier:
+// element e's points of tier k are [e Mf[k], (e + 1) Mf[k]) of arrays with
+// leading dimension Mtot[k]
+struct UpRules {
+    const double* y[NUP];
+    const double* n[NUP];
+    const double* sw[NUP];
+    int64_t Mf[NUP];
+    int64_t Mtot[NUP];
+};
+// ws: 4 ints per wavefront (first sorted position, pair count <= UP_PAIRS,
+// element, tier index 0..NUP-1)
+int launch_corr_up(hipStream_t st, const UpRules& ur, int nwaves, const int* ws, const int* sorted, const int* pt,
+                   const double* xt, int64_t T, const int64_t* boff, const double* by, const double* bn,
+                   const double* bsw, int64_t Nb, double* corr);
 constexpr int FAR_BLOCK = 256;         // threads of a smooth-sum block (TPT targets each)
 int launch_corr_full(hipStream_t st, int nfull, const int* listf, const int* pe, const int* pt, const double* xt,
                      int64_t T, const int64_t* tnode, const double* clq, const double* sh, const ElemInfo* info,
