@@ -174,7 +174,7 @@ struct csbq_ctx {
     std::vector<int> h_gel;
     std::vector<int64_t> h_boff;
     DBuf<int> gel;
-    DBuf<double> clq, circ, ny, nn, nw;
+    DBuf<double> clq, circ, gridc, ny, nn, nw;
     DBuf<ElemInfo> info;
     DBuf<double> cpy[NUP], cpn[NUP], cpw[NUP], Lup[NUP], upx[NUP], upw[NUP];
     int64_t Mtot[NUP] = {0, 0, 0};
@@ -449,6 +449,7 @@ int csbq_destroy(csbq_ctx* ctx)
     ctx->g_body.release();
     ctx->clq.release();
     ctx->circ.release();
+    ctx->gridc.release();
     ctx->ny.release();
     ctx->nn.release();
     ctx->nw.release();
@@ -631,6 +632,8 @@ int csbq_set_geometry_batch(csbq_ctx* ctx, int32_t n_bodies, const int32_t* body
     LCHK(launch_expand(ctx->stream, (int)E, ctx->g_xc.p, ctx->g_eps.p, ctx->g_e1.p, ctx->g_sa.p, ctx->g_sc.p,
                        ctx->g_sign.p, ctx->g_body.p, ctx->g_group.p, ctx->clq.p, ctx->circ.p, ctx->info.p, ctx->ny.p, ctx->nn.p,
                        ctx->nw.p, N));
+    ALLOC(ctx->gridc, (size_t)E * NCIRC * CGRID * GRQ);
+    LCHK(launch_grid_circles(ctx->stream, (int)E, ctx->clq.p, ctx->gridc.p));
     // upsampled whole-panel rules (Gauss-Legendre of up_ns points in s times
     // up_nt angles) and the Lagrange matrices from the NS panel nodes to them
     for (int ti = 0; ti < NUP; ++ti) {
@@ -1160,11 +1163,11 @@ int csbq_eval_batch(csbq_ctx* ctx, const double* sigma, int64_t T, const double*
         }
         ctx->last_esc = nsel;
         LCHK(launch_classify(st, nsel, ctx->gsel.p, ctx->pe.p, ctx->pt.p, ctx->xt.p, T, tn, ctx->clq.p,
-                             ctx->circ.p, ctx->info.p, ctx->band.p, ctx->gc, ctx->tier.p, ctx->cls.p));
+                             ctx->circ.p, ctx->gridc.p, ctx->info.p, ctx->band.p, ctx->gc, ctx->tier.p, ctx->cls.p));
     } else {
         ctx->last_esc = -1;
         LCHK(launch_classify(st, P, ctx->perm.p, ctx->pe.p, ctx->pt.p, ctx->xt.p, T, tn, ctx->clq.p, ctx->circ.p,
-                             ctx->info.p, ctx->band.p, ctx->gc, ctx->tier.p, ctx->cls.p));
+                             ctx->gridc.p, ctx->info.p, ctx->band.p, ctx->gc, ctx->tier.p, ctx->cls.p));
     }
     HIPC(hipEventRecord(ctx->ph[3].b, st));
     // buckets: pairs sorted by (tier, element); runs give the per-element segments

@@ -16,6 +16,8 @@ constexpr int NSH = NMODE * 6;         // per GL row: (a_x a_y a_z b_x b_y b_z) 
 constexpr int CLQ = 17;                // centerline quantities per GL node
 constexpr int NCIRC = NS + 2;          // GL circles + the two panel-end circles
 constexpr int CIRQ = 9;                // per circle: X(3) t(3) eps smax s
+constexpr int CGRID = 9;               // grid circles per closest-circle bracket
+constexpr int GRQ = 8;                 // per grid circle: X(3) t(3) eps, padded
 constexpr int MAXSUB = 96;             // s sub-panels of one special quadrature
 constexpr int MAXRULE = 256;           // nodes of one theta rule
 constexpr int MAXLOG = 64;             // nodes of the log rule

@@ -1052,14 +1052,48 @@ __device__ inline double contact_root(const double* __restrict__ clq, const doub
     return bernstein_rho(z1.r, fabs(z1.i), -1.0, 1.0);
 }
 
+// normalised parameter of sampled circle k: the panel ends and the GL nodes
+__device__ __forceinline__ double circle_xn(int k)
+{
+    return k == 0 ? -1.0 : (k == NCIRC - 1 ? 1.0 : c_gx[k - 1]);
+}
+
+// the bracket around sampled circle kc (the GL gaps on both sides) and its
+// grid step
+__device__ __forceinline__ void circle_bracket(int kc, double* lo, double* hi, double* h)
+{
+    *lo = circle_xn(max(kc - 1, 0));
+    *hi = circle_xn(min(kc + 1, NCIRC - 1));
+    *h = (*hi - *lo) / (CGRID - 1);
+}
+
+// The bracket grids do not depend on the target: their circles are built
+// once per element, one thread per (bracket, grid point).
+__global__ __launch_bounds__(NCIRC * CGRID) void k_grid_circles(int E, const double* __restrict__ clq,
+                                                                 double* __restrict__ grid)
+{
+    const int e = blockIdx.x, k = threadIdx.x / CGRID, i = threadIdx.x % CGRID;
+    double lo, hi, h;
+    circle_bracket(k, &lo, &hi, &h);
+    double X[3], tt[3], EE;
+    circle_at_x(clq + (int64_t)e * CLQ * NS, lo + i * h, X, tt, &EE);
+    double* g = grid + (((int64_t)e * NCIRC + k) * CGRID + i) * GRQ;
+    for (int d = 0; d < 3; ++d) {
+        g[d] = X[d];
+        g[3 + d] = tt[d];
+    }
+    g[6] = EE;
+    g[7] = 0.0;
+}
+
 // Pairs are visited in element-major order (perm), so the lanes of a
 // wavefront read the same element's data.
 __global__ __launch_bounds__(128) void k_classify(int64_t P, const int* __restrict__ perm, const int* __restrict__ pe,
                            const int* __restrict__ pt, const double* __restrict__ xt, int64_t T,
                            const int64_t* __restrict__ tnode, const double* __restrict__ clq,
-                           const double* __restrict__ circ, const ElemInfo* __restrict__ info,
-                           const int* __restrict__ band, GateConsts gc, int8_t* __restrict__ tier,
-                           double* __restrict__ cls)
+                           const double* __restrict__ circ, const double* __restrict__ grid,
+                           const ElemInfo* __restrict__ info, const int* __restrict__ band, GateConsts gc,
+                           int8_t* __restrict__ tier, double* __restrict__ cls)
 {
     const int64_t ii = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (ii >= P) return;
@@ -1089,11 +1123,10 @@ __global__ __launch_bounds__(128) void k_classify(int64_t P, const int* __restri
         if (d2 < bd) { bd = d2; kd = k; }
         if (cha < ba) { ba = cha; ka = k; }
     }
-    auto xn_of = [&](int k) { return k == 0 ? -1.0 : (k == NCIRC - 1 ? 1.0 : c_gx[k - 1]); };
     // closest circle (minimum of d^2 over the two GL gaps around the sampled
     // minimum) and fastest trapezoid decay (minimum of cosh a - 1, likewise):
     // for each, a 9-point grid over its bracket, then two parabolic steps
-    double d2c = bd, chac = ba, xd = xn_of(kd);
+    double d2c = bd, chac = ba, xd = circle_xn(kd);
     {
         auto eval = [&](double xn, double* d2, double* cha) {
             double X[3], tt[3], EE;
@@ -1108,16 +1141,17 @@ __global__ __launch_bounds__(128) void k_classify(int64_t P, const int* __restri
         };
         for (int which = 0; which < 2; ++which) {
             const int kc = which ? ka : kd;
-            const double lo = xn_of(max(kc - 1, 0)), hi = xn_of(min(kc + 1, NCIRC - 1));
-            constexpr int G = 9;
-            const double h = (hi - lo) / (G - 1);
+            double lo, hi, h;
+            circle_bracket(kc, &lo, &hi, &h);
+            const double* gk = grid + ((int64_t)e * NCIRC + kc) * CGRID * GRQ;
             // running minimum of the grid with its neighbours (no indexed arrays)
             double m = 1e300, ml = 1e300, mr = 1e300, pv = 1e300, xm = lo;
             int im = -1;
-            for (int i = 0; i < G; ++i) {
+            for (int i = 0; i < CGRID; ++i) {
                 double vd, va;
                 const double xi = lo + i * h;
-                eval(xi, &vd, &va);
+                const double* gi = gk + i * GRQ;
+                circle_dist(gi, gi + 3, gi[6], x, &vd, &va);
                 const double v = which ? va : vd;
                 if (im == i - 1) mr = v;
                 if (v < m) {
@@ -1975,13 +2009,21 @@ int launch_search(hipStream_t st, int64_t T, const int* tgroup, const int* gel, 
     return 0;
 }
 
+int launch_grid_circles(hipStream_t st, int E, const double* clq, double* grid)
+{
+    if (E == 0) return 0;
+    hipLaunchKernelGGL(k_grid_circles, dim3(E), dim3(NCIRC * CGRID), 0, st, E, clq, grid);
+    LAUNCH_CHECK();
+    return 0;
+}
+
 int launch_classify(hipStream_t st, int64_t P, const int* perm, const int* pe, const int* pt, const double* xt,
-                    int64_t T, const int64_t* tnode, const double* clq, const double* circ, const ElemInfo* info,
-                    const int* band, GateConsts gc, int8_t* tier, double* cls)
+                    int64_t T, const int64_t* tnode, const double* clq, const double* circ, const double* grid,
+                    const ElemInfo* info, const int* band, GateConsts gc, int8_t* tier, double* cls)
 {
     if (P == 0) return 0;
     hipLaunchKernelGGL(k_classify, dim3((unsigned)((P + 127) / 128)), dim3(128), 0, st, P, perm, pe, pt, xt, T, tnode,
-                       clq, circ, info, band, gc, tier, cls);
+                       clq, circ, grid, info, band, gc, tier, cls);
     LAUNCH_CHECK();
     return 0;
 }
