@@ -312,6 +312,15 @@ static int load_tables(csbq_ctx* ctx)
     }
     std::fclose(f);
     if (!ok) return ctx->fail(CSBQ_ETABLE, "malformed rule table " + path);
+    // the special quadrature evaluates each theta-rule in mirror pairs
+    // (phi, -phi): every rule must be symmetric with equal mirrored weights
+    for (size_t b = 0; b + 1 < off.size(); ++b) {
+        const int o = off[b], m = off[b + 1] - off[b];
+        bool sym = m % 2 == 0;
+        for (int q = 0; sym && q < m / 2; ++q)
+            sym = th[o + q] == -th[o + m - 1 - q] && w[o + q] == w[o + m - 1 - q] && th[o + m - 1 - q] > 0.0;
+        if (!sym) return ctx->fail(CSBQ_ETABLE, "theta-rule " + std::to_string(b + 1) + " is not symmetric in " + path);
+    }
     std::vector<double> cs_(th.size()), sn_(th.size()), omc_(th.size());
     for (size_t q = 0; q < th.size(); ++q) {
         cs_[q] = std::cos(th[q]);

@@ -1399,15 +1399,14 @@ __device__ __forceinline__ double wave_sum(double v)
 //     circle and the choice of theta-rule -> one record per s-node in LDS;
 //  2. all lanes: the density's Fourier coefficients (modes up to the measured
 //     band) interpolated to the batch's s-nodes;
-//  3. all lanes: the batch's (s-node, theta-node) points as one flat list, 64
-//     at a time.  With the target's radial direction b0 and b0p = t x b0 as
+//  3. all lanes: the batch's (s-node, theta-node) points as one flat list of
+//     mirror pairs, 64 pairs at a time.  With the target's radial direction b0 and b0p = t x b0 as
 //     basis, r = z t + (dr + eps(1 - cos phi)) b0 - eps sin phi b0p, and the
 //     area element and r.n reduce to the scalars g = |x_c'| + eps (e1'.t cos +
 //     e2'.t sin) and eps' (|y_t x y_s| = eps sqrt(g^2 + eps'^2)), so a point
 //     costs one Fourier synthesis and a handful of flops.
 typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int SB = 16;
-constexpr int PPL = 2;     // points per lane in the special-quadrature point loop
 static_assert(SB == 16, "the coefficient interpolation uses 16-row MFMA tiles");
 enum { R_E = 0, R_EP, R_SP, R_A13, R_A23, R_Z, R_DR, R_T, R_B0 = R_T + 3, R_B0P = R_B0 + 3, R_W = R_B0P + 3, R_C0,
        R_S0, R_WQ, NREC };
@@ -1668,7 +1667,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
         // ---- 2. density coefficients at the batch's s-nodes
         if (lane == 0) {
             pref[0] = 0;
-            for (int j = 0; j < nb; ++j) pref[j + 1] = pref[j] + (npt[j] + PPL - 1) / PPL * PPL;
+            for (int j = 0; j < nb; ++j) pref[j + 1] = pref[j] + npt[j] / 2;   // point pairs
         }
         // coefficients at the s-nodes = [nb x NS] interpolation weights times
         // the [NS x ncoef] GL-row coefficients: FP64 MFMA 16x16x4 tiles
@@ -1696,69 +1695,118 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
             }
         }
         __syncthreads();
-        // ---- 3. the batch's points: a lane takes PPL consecutive points of one
-        // s-node (counts padded to a multiple of PPL, padding points weighted
-        // zero), so every LDS read of the s-node's record and coefficients
-        // serves PPL points
+        // s-nodes with a tabulated rule: coefficients turned to the closest
+        // angle theta0, (a, b)_l -> (a cos l theta0 + b sin l theta0,
+        // b cos l theta0 - a sin l theta0), so that the series is in phi
+        if (lane < 3 * nb) {
+            const int jj = lane / 3, d = lane - 3 * jj;
+            if (rq_off[jj] >= 0) {
+                const double c0 = rec[jj][R_C0], s0t = rec[jj][R_S0];
+                double* Cj = cf + jj * cstride;
+                double cl = c0, sl = s0t;
+                for (int l = 1; l <= Mt; ++l) {
+                    const double a = Cj[6 * l + d], b = Cj[6 * l + 3 + d];
+                    Cj[6 * l + d] = fma(a, cl, b * sl);
+                    Cj[6 * l + 3 + d] = fma(b, cl, -a * sl);
+                    const double cn = fma(cl, c0, -sl * s0t);
+                    sl = fma(sl, c0, cl * s0t);
+                    cl = cn;
+                }
+            }
+        }
+        __syncthreads();
+        // ---- 3. the batch's points in mirror pairs, one pair per lane and
+        // step: a trapezoid node theta with theta + pi, a tabulated rule's node
+        // theta0 + phi with theta0 - phi (the rules are symmetric, equal
+        // weights).  Both points share one Fourier recurrence in psi (theta,
+        // resp. phi): with the sums Ce, Co of the cosine terms of even and odd
+        // modes and Se, So of the sine terms, the pair's densities are
+        // T = Ce + Co + Se + So and, for the trapezoid, (Ce + Se) - (Co + So)
+        // (cos l(psi + pi) = (-1)^l cos l psi), for the rule (Ce + Co) -
+        // (Se + So) (sine terms odd in phi).
         const int Pb = pref[nb];
         int j = 0;
-        for (int P = lane * PPL; P < Pb; P += 64 * PPL) {
+        for (int P = lane; P < Pb; P += 64) {
             while (P >= pref[j + 1]) ++j;
-            const int q0 = P - pref[j];
-            const int nqj = npt[j];
+            const int k = P - pref[j];
             const double* R = rec[j];
             const double c0 = R[R_C0], s0t = R[R_S0];
             const int ro = rq_off[j];
-            double cph[PPL], sph[PPL], omc[PPL], wq[PPL], cth[PPL], sth[PPL];
-#pragma unroll
-            for (int u = 0; u < PPL; ++u) {
-                const bool ok = q0 + u < nqj;
-                const int q = ok ? q0 + u : q0;
-                if (ro < 0) {
-                    const int ix = q * rq_step[j];
-                    cth[u] = c_cos128[ix];
-                    sth[u] = c_sin128[ix];
-                    cph[u] = cth[u] * c0 + sth[u] * s0t;     // phi = theta - theta0
-                    sph[u] = sth[u] * c0 - cth[u] * s0t;
-                    omc[u] = 1.0 - cph[u];
-                    wq[u] = R[R_WQ];
-                } else {
-                    cph[u] = rt.cs[ro + q];
-                    sph[u] = rt.sn[ro + q];
-                    omc[u] = rt.omc[ro + q];
-                    wq[u] = rt.w[ro + q];
-                    cth[u] = c0 * cph[u] - s0t * sph[u];
-                    sth[u] = s0t * cph[u] + c0 * sph[u];
-                }
-                if (!ok) wq[u] = 0.0;
-                n_theta += ok ? 1 : 0;
+            const bool trap = ro < 0;
+            double ca, sa, wq, cth[2], sth[2], cph[2], sph[2], omc[2];
+            if (trap) {
+                const int ix = k * rq_step[j];
+                ca = c_cos128[ix];
+                sa = c_sin128[ix];
+                const double cp = fma(ca, c0, sa * s0t), sp = fma(sa, c0, -ca * s0t);   // phi = theta - theta0
+                cth[0] = ca;
+                sth[0] = sa;
+                cth[1] = -ca;
+                sth[1] = -sa;
+                cph[0] = cp;
+                sph[0] = sp;
+                cph[1] = -cp;
+                sph[1] = -sp;
+                omc[0] = 1.0 - cp;
+                omc[1] = 1.0 + cp;
+                wq = R[R_WQ];
+            } else {
+                const int q = ro + (npt[j] >> 1) + k;   // the positive half of the rule
+                ca = rt.cs[q];
+                sa = rt.sn[q];
+                const double om = rt.omc[q];
+                wq = rt.w[q];
+                cth[0] = fma(c0, ca, -s0t * sa);
+                sth[0] = fma(s0t, ca, c0 * sa);
+                cth[1] = fma(c0, ca, s0t * sa);
+                sth[1] = fma(s0t, ca, -c0 * sa);
+                cph[0] = cph[1] = ca;
+                sph[0] = sa;
+                sph[1] = -sa;
+                omc[0] = omc[1] = om;
             }
+            n_theta += 2;
             // density by Fourier synthesis over the measured band
             const double* C = cf + j * cstride;
-            double v[PPL][3], clv[PPL], slv[PPL];
-#pragma unroll
-            for (int u = 0; u < PPL; ++u) {
-                v[u][0] = C[0];
-                v[u][1] = C[1];
-                v[u][2] = C[2];
-                clv[u] = cth[u];
-                slv[u] = sth[u];
-            }
-            for (int l = 1; l <= Mt; ++l) {
+            double Ce[3] = {C[0], C[1], C[2]}, Co[3] = {0.0, 0.0, 0.0}, Se[3] = {0.0, 0.0, 0.0},
+                   So[3] = {0.0, 0.0, 0.0};
+            double cl = ca, sl = sa;
+            int l = 1;
+            for (; l + 1 <= Mt; l += 2) {
                 const double* Cl = C + 6 * l;
-                const double k0 = Cl[0], k1 = Cl[1], k2 = Cl[2], k3 = Cl[3], k4 = Cl[4], k5 = Cl[5];
 #pragma unroll
-                for (int u = 0; u < PPL; ++u) {
-                    v[u][0] = fma(k0, clv[u], fma(k3, slv[u], v[u][0]));
-                    v[u][1] = fma(k1, clv[u], fma(k4, slv[u], v[u][1]));
-                    v[u][2] = fma(k2, clv[u], fma(k5, slv[u], v[u][2]));
-                    const double cn = clv[u] * cth[u] - slv[u] * sth[u];
-                    slv[u] = slv[u] * cth[u] + clv[u] * sth[u];
-                    clv[u] = cn;
+                for (int d = 0; d < 3; ++d) {
+                    Co[d] = fma(Cl[d], cl, Co[d]);
+                    So[d] = fma(Cl[3 + d], sl, So[d]);
+                }
+                double cn = fma(cl, ca, -sl * sa);
+                sl = fma(sl, ca, cl * sa);
+                cl = cn;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    Ce[d] = fma(Cl[6 + d], cl, Ce[d]);
+                    Se[d] = fma(Cl[9 + d], sl, Se[d]);
+                }
+                cn = fma(cl, ca, -sl * sa);
+                sl = fma(sl, ca, cl * sa);
+                cl = cn;
+            }
+            if (l <= Mt) {
+                const double* Cl = C + 6 * l;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    Co[d] = fma(Cl[d], cl, Co[d]);
+                    So[d] = fma(Cl[3 + d], sl, So[d]);
                 }
             }
+            double v[2][3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                v[0][d] = (Ce[d] + Co[d]) + (Se[d] + So[d]);
+                v[1][d] = trap ? (Ce[d] + Se[d]) - (Co[d] + So[d]) : (Ce[d] + Co[d]) - (Se[d] + So[d]);
+            }
             const double E = R[R_E], Ep = R[R_EP], z = R[R_Z], dr = R[R_DR];
-            const double sp_ = R[R_SP], a13 = R[R_A13], a23 = R[R_A23], Wsn = R[R_W];
+            const double sp_ = R[R_SP], a13 = R[R_A13], a23 = R[R_A23], W = R[R_W] * wq;
             double tv[3], b0v[3], b0pv[3];
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
@@ -1767,7 +1815,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
                 b0pv[d] = R[R_B0P + d];
             }
 #pragma unroll
-            for (int u = 0; u < PPL; ++u) {
+            for (int u = 0; u < 2; ++u) {
                 const double gq = sp_ + a13 * cth[u] + a23 * sth[u];
                 // g^2 + eps'^2 > 0 on any admissible tube (eps * curvature < 1)
                 const double jq = fma(gq, gq, Ep * Ep);
@@ -1779,7 +1827,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
                 const double rr = z * z + A * A + B * B;
                 const double ir = rr > 0.0 ? rsqrt_nr1(rr) : 0.0;
                 const double ir2 = ir * ir;
-                const double W = Wsn * wq[u];
                 const double rs = r[0] * v[u][0] + r[1] * v[u][1] + r[2] * v[u][2];
                 const double rn = sgn * E * (gq * (dr * cph[u] - E * omc[u]) - Ep * z);
                 const double aS = W * J * ir, bS = aS * rs * ir2;

@@ -21,6 +21,16 @@ def test_table_header_and_sizes():
         assert np.allclose(th, -th[::-1]) and np.allclose(om, om[::-1])   # mirrored rule
 
 
+def test_theta_rules_are_mirror_symmetric():
+    """The special quadrature evaluates each theta-rule in pairs (phi, -phi)
+    sharing one weight, and the library refuses a table where that fails."""
+    for th, w in TAB["rules"]:
+        m = len(th)
+        assert m % 2 == 0
+        assert np.array_equal(th[: m // 2], -th[::-1][: m // 2]) and np.all(th[m // 2:] > 0)
+        assert np.array_equal(w[: m // 2], w[::-1][: m // 2])
+
+
 def test_log_rule_moments():
     x, w = TAB["log_rule"]
     assert x.min() > 1e-7 and x.max() < 1
