@@ -23,10 +23,11 @@ METRIC = "layer-potential target evals/sec at rel.err 1e-10 (FP64) and 1e-6 (mix
 FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 vector peak
 FP32_PEAK_TFLOPS = 157.3         # MI355X FP32 vector peak (the mixed-precision smooth sum)
 FAR_FLOPS_PER_PAIR = 44          # smooth-sum flops per source-target pair (rsqrt counted once)
-# special quadrature flops: per theta-rule node 82 + 18 per density Fourier mode
-# (synthesis), per s-node 800 (interpolation weights, centerline data, frame,
+# special quadrature flops: per theta-rule node 82 + 9 per density Fourier mode
+# (synthesis; a mirror pair of nodes shares one recurrence, 18 flops per pair
+# and mode), per s-node 800 (interpolation weights, centerline data, frame,
 # local coordinates) + 192 per mode (6 coefficients x 16-point interpolation)
-THETA_FLOPS, THETA_MODE_FLOPS = 82, 18
+THETA_FLOPS, THETA_MODE_FLOPS = 82, 9
 SNODE_FLOPS, SNODE_MODE_FLOPS = 800, 192
 
 
