@@ -645,16 +645,16 @@ __global__ void k_fill_i64(int64_t n, int64_t* __restrict__ v, int64_t val)
 // ---------------------------------------------------------------------------
 constexpr int FAR_REC = 10;     // LDS record of a source: y(3) n(3) sigma*w(3), padded to 16-byte pairs
 
-// Each thread owns TPT targets; a block streams its source chunk through LDS
-// in tiles of FAR_BLOCK sources (one record each, read as five 16-byte
-// broadcasts), so every LDS read serves TPT pairs.
+// Each thread owns TPT targets and walks its block's source chunk; a
+// source's record is read at wave-uniform addresses (scalar loads through the
+// scalar cache, shared by the block's four waves), so it costs no vector
+// memory, LDS or barrier and every load serves 64 TPT pairs.
 template <int TPT>
 __global__ __launch_bounds__(FAR_BLOCK) void k_far(int64_t T, const double* __restrict__ xt,
                                                    const double* __restrict__ sy, const double* __restrict__ sn,
                                                    const double* __restrict__ ssw, int64_t N,
                                                    const FarTile* __restrict__ tiles, double* __restrict__ part)
 {
-    __shared__ __attribute__((aligned(16))) double src[FAR_BLOCK * FAR_REC];
     const int tid = threadIdx.x;
     const FarTile tl = tiles[blockIdx.x];
     const int64_t tb = tl.t0 + tid, tend = tl.t0 + tl.tn;
@@ -670,31 +670,12 @@ __global__ __launch_bounds__(FAR_BLOCK) void k_far(int64_t T, const double* __re
     }
     const int64_t c0 = tl.s0;
     const int64_t c1 = tl.s0 + tl.sn;
-    for (int64_t base = c0; base < c1; base += FAR_BLOCK) {
-        const int64_t k = base + tid;
-        if (k < c1) {
-            double* r = src + tid * FAR_REC;
-            r[0] = sy[k];
-            r[1] = sy[N + k];
-            r[2] = sy[2 * N + k];
-            r[3] = sn[k];
-            r[4] = sn[N + k];
-            r[5] = sn[2 * N + k];
-            r[6] = ssw[k];
-            r[7] = ssw[N + k];
-            r[8] = ssw[2 * N + k];
-            r[9] = 0.0;
-        }
-        __syncthreads();
-        const int nin = (int)min((int64_t)FAR_BLOCK, c1 - base);
-#pragma unroll 2
-        for (int kk = 0; kk < nin; ++kk) {
-            const double2* r2 = reinterpret_cast<const double2*>(src + kk * FAR_REC);
-            const double2 A = r2[0], B = r2[1], C = r2[2], D = r2[3], F = r2[4];
+#pragma unroll 4
+    for (int64_t k = c0; k < c1; ++k) {
+        const double2 A = {sy[k], sy[N + k]}, B = {sy[2 * N + k], sn[k]}, C = {sn[N + k], sn[2 * N + k]},
+                      D = {ssw[k], ssw[N + k]}, F = {ssw[2 * N + k], 0.0};
 #pragma unroll
-            for (int u = 0; u < TPT; ++u) pair_scaled(x[u], A, B, C, D, F, sa[u], sb[u], sd[u]);
-        }
-        __syncthreads();
+        for (int u = 0; u < TPT; ++u) pair_scaled(x[u], A, B, C, D, F, sa[u], sb[u], sd[u]);
     }
     double* p = part + (int64_t)tl.chunk * 6 * T;
 #pragma unroll
