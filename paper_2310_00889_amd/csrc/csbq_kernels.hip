@@ -1391,6 +1391,8 @@ constexpr int SB = 16;
 static_assert(SB == 16, "the coefficient interpolation uses 16-row MFMA tiles");
 enum { R_E = 0, R_EP, R_SP, R_A13, R_A23, R_Z, R_DR, R_T, R_B0 = R_T + 3, R_B0P = R_B0 + 3, R_W = R_B0P + 3, R_C0,
        R_S0, R_WQ, NREC };
+constexpr int QVS = CLQ + 1;   // row stride of the interpolated centerline quantities
+static_assert(CLQ <= 32, "the centerline interpolation uses two 16-column MFMA tiles");
 
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_corr_full(const int* __restrict__ listf, const int* __restrict__ pe,
                                                   const int* __restrict__ pt, const double* __restrict__ xt,
@@ -1405,13 +1407,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
                                                   int* __restrict__ work, int cstride)
 {
     // cf: [SB][cstride] density coefficients at the batch's s-nodes, cstride =
-    // 6 (largest band + 1) over all elements (dynamic LDS, at least SB x NS
-    // doubles).  The same space holds the bisection stack while the s-rule
-    // is built and each batch's interpolation weights [SB][NS] from phase 1
-    // until phase 2 has read them, which keeps the block's LDS small enough
-    // for three waves per SIMD.
+    // 6 (largest band + 1) over all elements (dynamic LDS, at least
+    // SB x (NS + QVS) doubles).  The same space holds the bisection stack
+    // while the s-rule is built, and each batch's interpolation weights
+    // [SB][NS] and centerline quantities [SB][QVS] from phase 1 until phase 2
+    // has read them, which keeps the block's LDS small enough for three waves
+    // per SIMD.
     extern __shared__ __attribute__((aligned(16))) double cf[];
     double* const lwl = cf;
+    double* const qv = cf + SB * NS;   // phase 1b output [SB][QVS]
     double* const st_lo = cf;
     double* const st_hi = cf + 48;
     __shared__ __attribute__((aligned(16))) double rec[SB][NREC];
@@ -1537,7 +1541,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
     int n_theta = 0;
     for (int base = 0; base < S; base += SB) {
         const int nb = min(SB, S - base);
-        // ---- 1. one s-node per lane
+        // ---- 1a. one s-node per lane: node, weight, interpolation weights
+        double ws = 0.0;
         if (lane < nb) {
             const int g = base + lane;
             int lo_i = 0, hi_i = nsb;   // soff[lo_i] <= g < soff[hi_i]
@@ -1548,7 +1553,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
             const int m = g - soff[lo_i];
             const double lo = sub_lo[lo_i], hi = sub_hi[lo_i];
             const int ty = sub_ty[lo_i];
-            double s, ws, u;
+            double s, u;
             if (ty == SUB_GL) {
                 s = 0.5 * (lo + hi) + 0.5 * (hi - lo) * c_gx[m];
                 ws = 0.5 * (hi - lo) * c_gw[m];
@@ -1569,20 +1574,48 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
                 bary_weights_rcp((s - inf.a) / hw - 1.0, lw);
 #pragma unroll
             for (int i = 0; i < NS; ++i) lwl[lane * NS + i] = lw[i];
+        }
+        __syncthreads();
+        // ---- 1b. centerline quantities at the batch's s-nodes: [nb x NS]
+        // weights times the element's [NS x CLQ] samples (on the target's own
+        // element, differences from the samples at the target's GL node), as
+        // FP64 MFMA 16x16x4 tiles in the layout of phase 2
+        {
+            const int r = lane & 15, qq = lane >> 4;
+            double wa[NS / 4];
+#pragma unroll
+            for (int ks = 0; ks < NS / 4; ++ks) wa[ks] = (r < nb) ? lwl[r * NS + 4 * ks + qq] : 0.0;
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) {
+                const int col = cb * 16 + r;
+                v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int ks = 0; ks < NS / 4; ++ks) {
+                    double bv = 0.0;
+                    if (col < CLQ) {
+                        bv = sq[col * NS + 4 * ks + qq];
+                        if (own) bv -= sq[col * NS + i0];
+                    }
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(wa[ks], bv, acc, 0, 0, 0);
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int row = qq + 4 * i;
+                    if (row < nb && col < CLQ) qv[row * QVS + col] = acc[i];
+                }
+            }
+        }
+        __syncthreads();
+        // ---- 1c. one s-node per lane: frame, local coordinates, theta-rule
+        if (lane < nb) {
             double q[CLQ], dq[CLQ];
 #pragma unroll
             for (int k = 0; k < CLQ; ++k) {
+                const double v = qv[lane * QVS + k];
                 if (own) {
-                    const double q0 = sq[k * NS + i0];
-                    double v = 0.0;
-#pragma unroll
-                    for (int i = 0; i < NS; ++i) v += lw[i] * (sq[k * NS + i] - q0);
                     dq[k] = v;
-                    q[k] = q0 + v;
+                    q[k] = sq[k * NS + i0] + v;
                 } else {
-                    double v = 0.0;
-#pragma unroll
-                    for (int i = 0; i < NS; ++i) v += lw[i] * sq[k * NS + i];
                     q[k] = v;
                 }
             }
@@ -2094,7 +2127,8 @@ int launch_corr_full(hipStream_t st, int nfull, const int* listf, const int* pe,
     if (mt_max < 0 || mt_max >= NMODE) return (int)hipErrorInvalidValue;
     RuleTables rt{roff, rth, rw, rcs, rsn, romc, nb, lx, lw, nl};
     const int cstride = 6 * (mt_max + 1);
-    const size_t lds = (size_t)SB * (cstride > NS ? cstride : NS) * sizeof(double);   // >= the weights and the stack
+    // at least the phase-1 weights and centerline quantities (and the stack)
+    const size_t lds = (size_t)SB * (cstride > NS + QVS ? cstride : NS + QVS) * sizeof(double);
     hipLaunchKernelGGL(k_corr_full, dim3(nfull), dim3(64), lds, st, listf, pe, pt,
                        xt, T, tnode, clq, sh, info, band, cls, boff, by, bn, bsw, Nb, rt, gc, corr, err, work,
                        cstride);
