@@ -193,6 +193,32 @@ def test_mixed_mlp_gate_parity():
     e.close()
 
 
+def test_config2_mixed_mlp_full_size_sampled():
+    """The mixed + learned-gate evaluation exactly as the benchmark runs it
+    (200-sphere pipe, all 153,600 nodes as targets, quad_tol 1e-7): 12 wall
+    and 12 sphere targets against the oracle, 1e-6."""
+    import torch
+    import paper_2310_00889_amd as pk
+    w, meta = _trained()
+    e = pk.Evaluator(quad_tol=1e-7, precision="mixed", gate="mlp")
+    e.gate_load(w, float(meta["tau_esc"]))
+    sc = synth.config2()
+    e.set_geometry(sc)
+    us, ud = e.eval(torch.from_numpy(sc.sigma).cuda(), None, torch.from_numpy(sc.tgt_node).cuda())
+    torch.cuda.synchronize()
+    us, ud = us.cpu().numpy(), ud.cpu().numpy()
+    nwall = sc.bodies[0].n_panels * sc.ns * sc.nt
+    rng = np.random.default_rng(41)
+    idx = np.concatenate([rng.choice(nwall, 12, replace=False), nwall + rng.choice(sc.n_nodes - nwall, 12, replace=False)])
+    uso, udo = oracle.evaluate(sc, None, None, sc.tgt_node[idx])
+    for part, what in ((slice(0, 12), "wall"), (slice(12, 24), "spheres")):
+        es = np.abs(us[idx][part] - uso[part]).max() / np.abs(uso[part]).max()
+        ed = np.abs(ud[idx][part] - udo[part]).max() / np.abs(udo[part]).max()
+        print(f"config2 mixed+mlp {what}: S {es:.2e} D {ed:.2e}", flush=True)
+        assert es < 1e-6 and ed < 1e-6
+    e.close()
+
+
 def test_config5_mlp_gate_speedup():
     """2000 spheres in the pipe scaled by 10**(1/3) (1,075,200 on-surface
     targets), mixed precision at quad_tol 1e-7: the trained gate spends less

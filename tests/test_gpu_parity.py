@@ -95,6 +95,29 @@ def test_sphere_on_surface(ev):
     assert _rel(ud, udo) < GATE, _rel(ud, udo)
 
 
+def test_constant_density_on_unit_sphere_closed_forms(ev):
+    """Degenerate band (a constant density, Ms = Mt = 0) against closed forms
+    rather than the oracle: on the unit sphere S[c] = 2c/3 inside and on the
+    surface (the translating sphere), and D[c] = c inside, c/2 on the surface,
+    0 outside (the stresslet identity of the kernel as printed)."""
+    sc = synth.config1(400)
+    c = np.array([0.3, -1.1, 0.7])
+    sc.sigma = np.tile(c, (sc.n_nodes, 1))
+    ev.set_geometry(sc)
+    us, ud = ev.eval(sc.sigma, sc.x, None)
+    inside = sc.tgt_class == 0
+    scale = np.abs(c).max()
+    err_si = np.abs(us[inside] - 2 * c / 3).max() / scale
+    err_di = np.abs(ud[inside] - c).max() / scale
+    err_do = np.abs(ud[~inside]).max() / scale
+    tn = np.arange(0, sc.n_nodes, 5)
+    us_on, ud_on = ev.eval(sc.sigma, None, tn)
+    err_son = np.abs(us_on - 2 * c / 3).max() / scale
+    err_don = np.abs(ud_on - c / 2).max() / scale
+    print("constant density", err_si, err_di, err_do, err_son, err_don, ev.stats().get("pairs_full"), flush=True)
+    assert max(err_si, err_di, err_do, err_son, err_don) < GATE
+
+
 def test_small_pipe_on_and_off_surface(ev):
     sc = synth.small_pipe_scene(n_panels=6, n_spheres=3)
     ev.set_geometry(sc)
@@ -161,6 +184,22 @@ def test_empty_and_invalid_inputs(ev):
     # the context stays usable after an error
     us, ud = ev.eval(sc.sigma, None, np.array([0, 1]))
     assert np.isfinite(us).all()
+
+
+def test_asymmetric_theta_rule_table_is_refused(tmp_path):
+    """The special quadrature evaluates every theta-rule in mirror pairs, so a
+    table whose rule is not symmetric must be refused when a context loads it
+    (here one node of the first rule moved)."""
+    import struct
+    import paper_2310_00889_amd as pk
+    raw = bytearray(open(os.path.join(pk.TABLE_DIR, "rules.bin"), "rb").read())
+    m = struct.unpack_from("<i", raw, 28)[0]            # header: magic, version, NB, l0, tol
+    th0 = struct.unpack_from("<d", raw, 32)[0]
+    struct.pack_into("<d", raw, 32, th0 * (1 + 1e-9))
+    assert m > 0
+    (tmp_path / "rules.bin").write_bytes(bytes(raw))
+    with pytest.raises(pk.CsbqError, match="ETABLE"):
+        pk.Evaluator(table_dir=str(tmp_path))
 
 
 MIXED_GATE = 1e-6
