@@ -1250,8 +1250,8 @@ int csbq_eval_batch(csbq_ctx* ctx, const double* sigma, int64_t T, const double*
         LCHK(launch_sigma_up(st, E, up_ns(ti), up_nt(ti), ctx->sh.p, ctx->Lup[ti].p, ctx->cpw[ti].p, ctx->swf[ti].p,
                              ctx->Mtot[ti]));
     }
-    LCHK(launch_corr_up(st, up_rules(ctx), nw_up, ctx->wdesc.p, ctx->sorted.p, ctx->pt.p, ctx->xt.p, T, ctx->boff.p,
-                        ctx->by.p, ctx->bn.p, ctx->bsw.p, ctx->Nb, ctx->corr.p));
+    LCHK(launch_corr_up(st, up_rules(ctx), nw_up, ctx->wdesc.p, ctx->sorted.p, ctx->pt.p, ctx->xt.p, T, ctx->info.p,
+                        ctx->boff.p, ctx->by.p, ctx->bn.p, ctx->bsw.p, ctx->Nb, ctx->corr.p));
     HIPC(hipEventRecord(ctx->ph[5].b, st));
     // special quadrature corrections
     HIPC(hipEventRecord(ctx->ph[6].a, st));
@@ -1314,7 +1314,7 @@ static int enqueue_apply(csbq_ctx* ctx, hipStream_t st)
             LCHK(launch_sigma_up(st, E, up_ns(ti), up_nt(ti), ctx->sh.p, ctx->Lup[ti].p, ctx->cpw[ti].p,
                                  ctx->swf[ti].p, ctx->Mtot[ti]));
     LCHK(launch_corr_up(st, up_rules(ctx), pl.nw_up, ctx->wdesc.p, ctx->sorted.p, ctx->pt.p, ctx->xt.p, T,
-                        ctx->boff.p, ctx->by.p, ctx->bn.p, ctx->bsw.p, ctx->Nb, ctx->corr.p));
+                        ctx->info.p, ctx->boff.p, ctx->by.p, ctx->bn.p, ctx->bsw.p, ctx->Nb, ctx->corr.p));
     LCHK(launch_corr_full(st, pl.nfull, ctx->sorted.p + pl.full_start, ctx->pe.p, ctx->pt.p, ctx->xt.p, T, pl.tn,
                           ctx->clq.p, ctx->sh.p, ctx->info.p, ctx->band.p, ctx->cls.p, ctx->boff.p, ctx->by.p,
                           ctx->bn.p, ctx->bsw.p, ctx->Nb, ctx->roff.p, ctx->rth.p, ctx->rw.p, ctx->nb, ctx->lx.p,
@@ -1623,8 +1623,8 @@ int csbq_gate_dataset(csbq_ctx* ctx, const double* sigma, int64_t T, const doubl
         ALLOC(ctx->swf[ti], (size_t)ctx->Mtot[ti] * 3);
         LCHK(launch_sigma_up(st, E, up_ns(ti), up_nt(ti), ctx->sh.p, ctx->Lup[ti].p, ctx->cpw[ti].p, ctx->swf[ti].p,
                              ctx->Mtot[ti]));
-        LCHK(launch_corr_up(st, up_rules(ctx), nw, dwd[ti].p, ctx->perm.p, ctx->pt.p, ctx->xt.p, T, ctx->boff.p,
-                            ctx->by.p, ctx->bn.p, ctx->bsw.p, ctx->Nb, cup[ti].p));
+        LCHK(launch_corr_up(st, up_rules(ctx), nw, dwd[ti].p, ctx->perm.p, ctx->pt.p, ctx->xt.p, T, ctx->info.p,
+                            ctx->boff.p, ctx->by.p, ctx->bn.p, ctx->bsw.p, ctx->Nb, cup[ti].p));
     }
     ALLOC(cfull, (size_t)P * 6 + 1);
     std::vector<int> hband((size_t)2 * E);

@@ -1271,9 +1271,12 @@ __global__ void k_tier_keys(int64_t P, int E, const int8_t* __restrict__ tier, c
 // plus its base rule with negated weight, staged in LDS 64 points at a time.
 // One launch serves every tier, so the host can order the wavefronts by cost.
 static_assert(NUP == 3, "k_corr_up selects among three tiers' rules");
+static_assert(up_ns(1) == up_ns(0) && up_nt(1) == 2 * up_nt(0) && up_nt(0) == NT,
+              "the 32 x 64 rule contains the closed-end far-field rule at its even angles");
 __global__ __launch_bounds__(64) void k_corr_up(UpRules ur, const int* __restrict__ ws,
                                                 const int* __restrict__ sorted, const int* __restrict__ pt,
                                                 const double* __restrict__ xt, int64_t T,
+                                                const ElemInfo* __restrict__ info,
                                                 const int64_t* __restrict__ boff, const double* __restrict__ by,
                                                 const double* __restrict__ bn, const double* __restrict__ bsw,
                                                 int64_t Nb, double* __restrict__ corr)
@@ -1301,7 +1304,12 @@ __global__ __launch_bounds__(64) void k_corr_up(UpRules ur, const int* __restric
         for (int d = 0; d < 3; ++d) sa[u][d] = sb[u][d] = sd[u][d] = 0.0;
     }
     const int64_t nbase = boff[e + 1] - boff[e];
-    for (int pass = 0; pass < 2; ++pass) {
+    // An element whose far-field rule is the 32 x 32 tensor rule (closed
+    // ends) has those points among the 32 x 64 rule's, as its even angles,
+    // with twice the weight: the 32 x 64 correction is then the alternating
+    // sum over the 32 x 64 points alone (odd angles +, even angles -).
+    const bool alt = ti == 1 && info[e].fb == 2;
+    for (int pass = 0; pass < (alt ? 1 : 2); ++pass) {
         // pass 0: the upsampled rule; pass 1: minus the element's far-field rule
         const double* py = pass ? by : cpy;
         const double* pn = pass ? bn : cpn;
@@ -1309,9 +1317,9 @@ __global__ __launch_bounds__(64) void k_corr_up(UpRules ur, const int* __restric
         const int64_t ld = pass ? Nb : Mtot;
         const int64_t base0 = pass ? boff[e] : (int64_t)e * Mf;
         const int64_t cnt = pass ? nbase : Mf;
-        const double sg = pass ? -1.0 : 1.0;
         for (int64_t base = 0; base < cnt; base += 64) {
             const int64_t m = base0 + base + lane;
+            const double sg = pass ? -1.0 : (alt && !((base + lane) & 1) ? -1.0 : 1.0);
             if (base + lane < cnt) {
                 double* r = src + lane * FAR_REC;
                 r[0] = py[m];
@@ -2106,12 +2114,12 @@ int launch_tier_keys(hipStream_t st, int64_t P, int E, const int8_t* tier, const
 }
 
 int launch_corr_up(hipStream_t st, const UpRules& ur, int nwaves, const int* ws, const int* sorted, const int* pt,
-                   const double* xt, int64_t T, const int64_t* boff, const double* by, const double* bn,
-                   const double* bsw, int64_t Nb, double* corr)
+                   const double* xt, int64_t T, const ElemInfo* info, const int64_t* boff, const double* by,
+                   const double* bn, const double* bsw, int64_t Nb, double* corr)
 {
     if (nwaves == 0) return 0;
-    hipLaunchKernelGGL(k_corr_up, dim3(nwaves), dim3(64), 0, st, ur, ws, sorted, pt, xt, T, boff, by, bn, bsw, Nb,
-                       corr);
+    hipLaunchKernelGGL(k_corr_up, dim3(nwaves), dim3(64), 0, st, ur, ws, sorted, pt, xt, T, info, boff, by, bn, bsw,
+                       Nb, corr);
     LAUNCH_CHECK();
     return 0;
 }

@@ -57,8 +57,8 @@ struct UpRules {
 // ws: 4 ints per wavefront (first sorted position, pair count <= UP_PAIRS,
 // element, tier index 0..NUP-1)
 int launch_corr_up(hipStream_t st, const UpRules& ur, int nwaves, const int* ws, const int* sorted, const int* pt,
-                   const double* xt, int64_t T, const int64_t* boff, const double* by, const double* bn,
-                   const double* bsw, int64_t Nb, double* corr);
+                   const double* xt, int64_t T, const ElemInfo* info, const int64_t* boff, const double* by,
+                   const double* bn, const double* bsw, int64_t Nb, double* corr);
 constexpr int FAR_BLOCK = 256;         // threads of a smooth-sum block (TPT targets each)
 int launch_corr_full(hipStream_t st, int nfull, const int* listf, const int* pe, const int* pt, const double* xt,
                      int64_t T, const int64_t* tnode, const double* clq, const double* sh, const ElemInfo* info,
