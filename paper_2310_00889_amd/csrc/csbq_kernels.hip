@@ -1616,21 +1616,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
         __syncthreads();
         // ---- 1c. one s-node per lane: frame, local coordinates, theta-rule
         if (lane < nb) {
-            double q[CLQ], dq[CLQ];
-#pragma unroll
-            for (int k = 0; k < CLQ; ++k) {
-                const double v = qv[lane * QVS + k];
-                if (own) {
-                    dq[k] = v;
-                    q[k] = sq[k * NS + i0] + v;
-                } else {
-                    q[k] = v;
-                }
-            }
             Frame fr;
-            frame_from_q(q, fr);
             CircleLocal cl;
             if (own) {
+                double q[CLQ];
+                const double* dq = qv + lane * QVS;   // differences from the own node's samples
+#pragma unroll
+                for (int k = 0; k < CLQ; ++k) q[k] = sq[k * NS + i0] + dq[k];
+                frame_from_q(q, fr);
                 Frame f0;
                 f0.E = f0d[0];
                 for (int d = 0; d < 3; ++d) {
@@ -1641,6 +1634,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
                 const double bnv[3] = {f0d[8], f0d[9], f0d[10]};
                 circle_local_rel(fr, f0, bnv, dq, cl);
             } else {
+                double q[CLQ];
+#pragma unroll
+                for (int k = 0; k < CLQ; ++k) q[k] = qv[lane * QVS + k];
+                frame_from_q(q, fr);
                 circle_local(fr, x, cl);
             }
             // theta-rule for this circle (Section 3.2.2): trapezoid of nt, 2nt
