@@ -48,6 +48,14 @@ def load_library():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2310_00889_amd.build` "
                           "(there is no CPU fallback)")
+    # PyTorch carries its own HIP runtime.  Loading it first makes libcsbq's
+    # HIP dependency resolve to that same runtime (one runtime per process
+    # shares the device, streams and pointers with torch); loaded the other way
+    # round, the second runtime finds no device.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(LIB_PATH)
     vp, dp, ip, lp = C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p
     lib.csbq_default_options.argtypes = [C.POINTER(_Options)]

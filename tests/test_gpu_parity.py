@@ -46,6 +46,18 @@ def test_native_library_is_loaded(ev):
     assert os.path.realpath(pk.LIB_PATH) in maps
 
 
+def test_smoke_in_a_fresh_process():
+    """The smoke entry point in a process where nothing has imported torch
+    before the package loads its library (the HIP runtime must be torch's)."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", "import __graft_entry__ as g; g.smoke()"], cwd=root,
+                       capture_output=True, text=True, timeout=300)
+    print(r.stdout[-400:], r.stderr[-400:], flush=True)
+    assert r.returncode == 0
+
+
 def test_nodes_match_oracle(ev):
     for sc, tol in ((synth.config1(4), 1e-13), (synth.small_pipe_scene(), 1e-10)):
         ev.set_geometry(sc)
