@@ -177,8 +177,8 @@ int csbq_plan(csbq_ctx* ctx, const double* sigma, int64_t n_tgt, const double* x
 int csbq_apply(csbq_ctx* ctx, const double* sigma, double* u_sl, double* u_dl, int mem);
 
 /* ---- Learned correction-tier gate (an extension beyond the paper; the
-   criterion of Section 3.2's error estimates stays the fallback and the
-   judge).  A perceptron with three hidden layers of 64 ReLU units maps
+   criterion of Section 3.2's error estimates stays the fallback and decides
+   every pair the network is unsure of).  A perceptron with three hidden layers of 64 ReLU units maps
    CSBQ_GATE_NF features of a (target, element) pair to CSBQ_GATE_NO ordinal
    outputs, output k estimating P(tier > k) for the tiers skip / three
    upsampled whole-panel rules / special quadrature.  With gate = MLP the

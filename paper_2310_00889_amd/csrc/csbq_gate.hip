@@ -1,5 +1,5 @@
 // csbq_gate.hip -- learned correction-tier gate (not part of the paper's
-// method; its criterion, the error estimates of Section 3.2, stays the judge):
+// method; its criterion, the error estimates of Section 3.2, stays the fallback):
 //   k_gate_features    cheap per-pair features from the sampled circles
 //   k_gate_mlp         inference: bf16 MFMA (v_mfma_f32_16x16x16_bf16), FP32
 //                      accumulation, one 16-pair tile per wavefront step
