@@ -224,8 +224,8 @@ int csbq_gate_dataset(csbq_ctx* ctx, const double* sigma, int64_t n_tgt, const d
                       double label_tol, int64_t cap, float* feat, int8_t* label, int8_t* crit, int64_t* n_out);
 
 /* Statistics of the last csbq_eval as a JSON object (phase times in ms from
-   HIP events, pair counts per correction tier).  Writes at most cap bytes
-   including the terminating zero. */
+   HIP events, pair counts per correction tier, the theta-rule table in use).
+   Writes at most cap bytes including the terminating zero. */
 int csbq_stats(const csbq_ctx* ctx, char* buf, int64_t cap);
 
 /* Block until the context's stream has drained. */

@@ -154,7 +154,7 @@ std::string default_table_dir()
 struct csbq_ctx {
     csbq_options opt{};
     std::string err;
-    std::string table_dir;
+    std::string table_dir, table_path;
     hipStream_t stream = nullptr;
     bool own_stream = false;
     GateConsts gc{};
@@ -281,7 +281,8 @@ const char* csbq_last_error(const csbq_ctx* ctx) { return ctx ? ctx->err.c_str()
 
 static int load_tables(csbq_ctx* ctx)
 {
-    std::string path = ctx->table_dir + "/rules.bin";
+    const std::string path = ctx->table_dir + "/rules.bin";
+    ctx->table_path = path;
     FILE* f = std::fopen(path.c_str(), "rb");
     if (!f) return ctx->fail(CSBQ_ETABLE, "cannot open " + path);
     char magic[8];
@@ -1674,6 +1675,10 @@ int csbq_stats(const csbq_ctx* ctx, char* buf, int64_t cap)
     }
     std::snprintf(tmp, sizeof tmp, ", \"far_tpt\": %d, \"far_chunk\": %lld", ctx->far_tpt, (long long)ctx->far_chunk);
     s += tmp;
+    {
+        const size_t sl = ctx->table_path.find_last_of('/');
+        s += ", \"theta_rules\": \"" + ctx->table_path.substr(sl == std::string::npos ? 0 : sl + 1) + "\"";
+    }
     if (ctx->ph_ok && ctx->last_nf > 0) {
         std::vector<int> wk((size_t)4 * ctx->last_nf);
         if (hipMemcpy(wk.data(), ctx->work.p, wk.size() * sizeof(int), hipMemcpyDeviceToHost) == hipSuccess) {
