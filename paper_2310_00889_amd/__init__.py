@@ -161,6 +161,7 @@ class Evaluator:
                                                _ptr(arrs["normal_sign"]), _ptr(arrs["s_break"]), _ptr(arrs["xc"]),
                                                _ptr(arrs["eps"]), _ptr(arrs["e1"]), ns, nt, CSBQ_HOST)
         self._check(rc, "csbq_set_geometry_batch")
+        self._plan_T = None   # the library drops its plan with the geometry
         n = C.c_int64()
         self._check(self._lib.csbq_num_nodes(self._h, C.byref(n)), "csbq_num_nodes")
         self.n_nodes = n.value
@@ -172,9 +173,31 @@ class Evaluator:
         self._check(self._lib.csbq_get_nodes(self._h, _ptr(y), _ptr(nr), _ptr(w), CSBQ_HOST), "csbq_get_nodes")
         return y, nr, w
 
+    def _check_shapes(self, sigma, x, tgt_node, tgt_group, out_sl, out_dl):
+        """The C ABI takes bare pointers: every size and element type is checked
+        here, so that no call reads or writes past an array."""
+        def _dt(a):
+            return str(a.dtype).replace("torch.", "")
+
+        def need(a, what, n, dtype):
+            if a is None:
+                return
+            if int(np.prod(a.shape)) != n or _dt(a) != dtype:
+                raise CsbqError(f"{what}: expected {n} {dtype} values, got shape {tuple(a.shape)} of {_dt(a)}")
+
+        if tgt_node is None and x is None:
+            raise CsbqError("targets: give x, tgt_node or both")
+        T = int(tgt_node.shape[0] if tgt_node is not None else x.shape[0])
+        need(sigma, "sigma", 3 * self.n_nodes, "float64")
+        need(x, "x", 3 * T, "float64")
+        need(tgt_node, "tgt_node", T, "int64")
+        need(tgt_group, "tgt_group", T, "int32")
+        need(out_sl, "out_sl", 3 * T, "float64")
+        need(out_dl, "out_dl", 3 * T, "float64")
+        return T
+
     def _call(self, fn, name, sigma, x, tgt_node, out_sl, out_dl, tgt_group=None, batch=False):
         dev = _is_torch_cuda(sigma)
-        self._plan_T = int(tgt_node.shape[0] if tgt_node is not None else x.shape[0])
         if dev:
             import torch
             T = int(tgt_node.shape[0] if tgt_node is not None else x.shape[0])
@@ -185,6 +208,7 @@ class Evaluator:
             for a in (sigma, x, tgt_node, tgt_group, out_sl, out_dl):
                 if a is not None and not (_is_torch_cuda(a) and a.is_contiguous()):
                     raise CsbqError("device calls need contiguous CUDA tensors throughout")
+            self._last_T = self._check_shapes(sigma, x, tgt_node, tgt_group, out_sl, out_dl)
             if batch:
                 rc = fn(self._h, _ptr(sigma), T, _ptr(x), _ptr(tgt_node), _ptr(tgt_group), _ptr(out_sl),
                         _ptr(out_dl), CSBQ_DEVICE)
@@ -196,10 +220,11 @@ class Evaluator:
         if x is not None:
             x = np.ascontiguousarray(x, np.float64).reshape(-1, 3)
         if tgt_node is not None:
-            tgt_node = np.ascontiguousarray(tgt_node, np.int64)
+            tgt_node = np.ascontiguousarray(tgt_node, np.int64).reshape(-1)
         if tgt_group is not None:
-            tgt_group = np.ascontiguousarray(tgt_group, np.int32)
-        T = int(tgt_node.shape[0] if tgt_node is not None else x.shape[0])
+            tgt_group = np.ascontiguousarray(tgt_group, np.int32).reshape(-1)
+        T = self._check_shapes(sigma, x, tgt_node, tgt_group, None, None)
+        self._last_T = T
         usl = np.zeros((T, 3))
         udl = np.zeros((T, 3))
         if batch:
@@ -226,12 +251,22 @@ class Evaluator:
     def plan(self, sigma, x=None, tgt_node=None, out_sl=None, out_dl=None, tgt_group=None):
         """Evaluate and freeze the plan (pairs, tiers, rules, smooth-sum blocks)
         for later apply() calls on the same targets."""
-        return self._call(self._lib.csbq_plan, "csbq_plan", sigma, x, tgt_node, out_sl, out_dl, tgt_group,
-                          batch=True)
+        self._plan_T = None
+        out = self._call(self._lib.csbq_plan, "csbq_plan", sigma, x, tgt_node, out_sl, out_dl, tgt_group,
+                         batch=True)
+        self._plan_T = self._last_T   # apply() writes the plan's targets, whatever is evaluated in between
+        return out
 
     def apply(self, sigma, out_sl=None, out_dl=None):
         """(u_S, u_D) of a new density under the frozen plan (graph replay)."""
+        if getattr(self, "_plan_T", None) is None:
+            raise CsbqError("apply: no plan (call plan() first)")
+        plan_targets = np.zeros(self._plan_T, np.int64)   # stands for the plan's targets in the size checks
         if _is_torch_cuda(sigma):
+            for a in (sigma, out_sl, out_dl):
+                if a is not None and not (_is_torch_cuda(a) and a.is_contiguous()):
+                    raise CsbqError("device calls need contiguous CUDA tensors throughout")
+            self._check_shapes(sigma, None, plan_targets, None, out_sl, out_dl)
             import torch
             T = self._plan_T
             if out_sl is None:
@@ -242,6 +277,7 @@ class Evaluator:
                         "csbq_apply")
             return out_sl, out_dl
         sigma = np.ascontiguousarray(sigma, np.float64)
+        self._check_shapes(sigma, None, plan_targets, None, None, None)
         usl = np.zeros((self._plan_T, 3))
         udl = np.zeros((self._plan_T, 3))
         self._check(self._lib.csbq_apply(self._h, _ptr(sigma), _ptr(usl), _ptr(udl), CSBQ_HOST), "csbq_apply")

@@ -81,6 +81,28 @@ def test_traffic_records_are_complete():
         assert abs(expect - rec["traffic_bytes"]) < 1e-6 * expect
 
 
+def test_binding_checks_sizes_and_types_before_the_c_abi():
+    """The C ABI takes bare pointers, so the binding refuses any array whose
+    size or element type does not match the geometry and the targets."""
+    import paper_2310_00889_amd as pk
+    ev = pk.Evaluator.__new__(pk.Evaluator)   # no device needed for the checks
+    ev.n_nodes = 10
+    sig = np.zeros((10, 3))
+    tn = np.arange(4, dtype=np.int64)
+    assert ev._check_shapes(sig, None, tn, None, None, None) == 4
+    assert ev._check_shapes(sig, np.zeros((5, 3)), None, np.zeros(5, np.int32), np.zeros((5, 3)), None) == 5
+    bad = [(np.zeros((9, 3)), None, tn, None, None, None),                  # density of 9 nodes
+           (sig.astype(np.float32), None, tn, None, None, None),            # float32 density
+           (sig, np.zeros((5, 3)), tn, None, None, None),                   # x and tgt_node disagree on T
+           (sig, None, tn.astype(np.int32), None, None, None),              # int32 node ids
+           (sig, None, tn, np.zeros(4, np.int64), None, None),              # int64 groups
+           (sig, None, tn, None, np.zeros((3, 3)), None),                   # short output
+           (sig, None, None, None, None, None)]                             # no targets
+    for args in bad:
+        with pytest.raises(pk.CsbqError):
+            ev._check_shapes(*args)
+
+
 def test_create_without_device_fails_cleanly():
     import torch
     import paper_2310_00889_amd as pk
