@@ -301,7 +301,9 @@ class Evaluator:
     def gate_grad(self, weights, feat, label, posw):
         w = np.ascontiguousarray(weights, np.float32).reshape(GATE_NW)
         f = np.ascontiguousarray(feat, np.float32).reshape(-1, GATE_NF)
-        lab = np.ascontiguousarray(label, np.int8)
+        lab = np.ascontiguousarray(label, np.int8).reshape(-1)
+        if lab.shape[0] != f.shape[0]:
+            raise CsbqError(f"gate_grad: {f.shape[0]} feature rows but {lab.shape[0]} labels")
         pw = np.ascontiguousarray(posw, np.float32).reshape(GATE_NO)
         g = np.zeros(GATE_NW, np.float32)
         loss = np.zeros(1, np.float32)
@@ -312,7 +314,9 @@ class Evaluator:
     def gate_train(self, feat, label, posw, weights, epochs=10, batch=4096, lr=1e-3, seed=0):
         w = np.array(weights, np.float32).reshape(GATE_NW).copy()
         f = np.ascontiguousarray(feat, np.float32).reshape(-1, GATE_NF)
-        lab = np.ascontiguousarray(label, np.int8)
+        lab = np.ascontiguousarray(label, np.int8).reshape(-1)
+        if lab.shape[0] != f.shape[0]:
+            raise CsbqError(f"gate_train: {f.shape[0]} feature rows but {lab.shape[0]} labels")
         pw = np.ascontiguousarray(posw, np.float32).reshape(GATE_NO)
         losses = np.zeros(epochs, np.float32)
         self._check(self._lib.csbq_gate_train(self._h, _ptr(f), _ptr(lab), f.shape[0], _ptr(pw), int(epochs),
@@ -325,8 +329,8 @@ class Evaluator:
         if x is not None:
             x = np.ascontiguousarray(x, np.float64).reshape(-1, 3)
         if tgt_node is not None:
-            tgt_node = np.ascontiguousarray(tgt_node, np.int64)
-        T = int(tgt_node.shape[0] if tgt_node is not None else x.shape[0])
+            tgt_node = np.ascontiguousarray(tgt_node, np.int64).reshape(-1)
+        T = self._check_shapes(sigma, x, tgt_node, None, None, None)
         feat = np.zeros((cap, GATE_NF), np.float32)
         lab = np.zeros(cap, np.int8)
         crit = np.zeros(cap, np.int8)
