@@ -31,6 +31,14 @@ THETA_FLOPS, THETA_MODE_FLOPS = 82, 9
 SNODE_FLOPS, SNODE_MODE_FLOPS = 800, 192
 
 
+WORKLOADS = {
+    "pipe100-spheres200": "pipe100-spheres200: torus-arc pipe (R=5, r=1, arc pi, 100 panels) + 200 spheres r=0.2, "
+                          "16x32 nodes per element, 153,600 sources = on-surface targets",
+    "batch64-full": "batch64-full: 64 independent torus-arc pipes, panels U{20..200} + spheres U{10..500} "
+                    "r U(0.1,0.25), 16x32 nodes per element, 11,493,888 on-surface targets",
+}
+
+
 def measured_traffic(kernel, precision):
     """HBM bytes per launch of `kernel` from the committed memory-counter
     record, or None when there is none or the kernels have changed since."""
@@ -75,6 +83,9 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--workload", default="pipe100-spheres200", choices=["pipe100-spheres200", "batch64-full"],
+                    help="batch64-full: 64 independent pipe geometries, panels U{20..200}, spheres U{10..500} "
+                         "(11.5M targets; building it takes minutes of host time)")
     ap.add_argument("--gate", default=None, choices=["criterion", "mlp"],
                     help="correction-tier gate (default: criterion for fp64, the trained network for mixed)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -91,7 +102,13 @@ def main():
     import paper_2310_00889_amd as pk
 
     log("bench: building workload")
-    sc = synth.config2()
+    if a.workload == "batch64-full":
+        scenes = synth.config4(progress=lambda g, s: log(f"bench: geometry {g + 1}/64, {s.n_nodes} nodes"))
+        sc = synth.merge_scenes(scenes)
+        base_sc = scenes[0]   # the CPU baseline samples one geometry (the oracle knows no batches)
+    else:
+        sc = synth.config2()
+        base_sc = sc
     quad_tol = 1e-12 if a.precision == "fp64" else 1e-7   # under the 1e-10 / 1e-6 parity gates
     gate = a.gate or ("criterion" if a.precision == "fp64" else "mlp")
     ev = pk.Evaluator(quad_tol=quad_tol, precision=a.precision, gate=gate)
@@ -130,8 +147,9 @@ def main():
     # roofline of the dominant kernel, timed with HIP events on the library's stream
     dom = max(("far", "corr_full"), key=lambda k: phases.get(k, 0.0))
     nsrc = counts.get("sources_base", ev.n_nodes)
+    far_pairs = float(counts.get("far_pairs") or float(T) * nsrc)   # a batch pairs targets with their group only
     if dom == "far":
-        flops = FAR_FLOPS_PER_PAIR * float(T) * nsrc
+        flops = FAR_FLOPS_PER_PAIR * far_pairs
     else:
         flops = (THETA_FLOPS * float(counts.get("theta_nodes", 0)) + THETA_MODE_FLOPS * float(counts.get("theta_modes", 0))
                  + SNODE_FLOPS * float(counts.get("s_nodes", 0)) + SNODE_MODE_FLOPS * float(counts.get("s_modes", 0)))
@@ -141,25 +159,26 @@ def main():
     peak = far_peak if dom == "far" else FP64_PEAK_TFLOPS
     roof = dict(kernel=far_kernel if dom == "far" else "k_corr_full", bound="alu", achieved=achieved,
                 peak=peak, unit="TFLOP/s", frac=achieved / peak,
-                traffic=measured_traffic(far_kernel if dom == "far" else "k_corr_full", a.precision))
-    far_ach = FAR_FLOPS_PER_PAIR * float(T) * nsrc / (phases["far"] * 1e-3) / 1e12
+                traffic=measured_traffic(far_kernel if dom == "far" else "k_corr_full", a.precision)
+                if a.workload == "pipe100-spheres200" else None)   # the counters were taken on that workload
+    far_ach = FAR_FLOPS_PER_PAIR * far_pairs / (phases["far"] * 1e-3) / 1e12
     out = {
         "metric": METRIC, "value": value, "unit": "target evals/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": 1e3 * dt / a.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64" if a.precision == "fp64" else "f32+f64", "data": "synthetic",
-        "config": {"workload": "pipe100-spheres200: torus-arc pipe (R=5, r=1, arc pi, 100 panels) + 200 spheres "
-                               "r=0.2, 16x32 nodes per element, 153,600 sources = on-surface targets",
+        "config": {"workload": WORKLOADS[a.workload],
                    "quad_tol": quad_tol, "precision": a.precision, "gate": gate, "targets": T, "sources": ev.n_nodes},
         "roofline": roof,
         "far_roofline": dict(kernel=far_kernel, bound="alu", achieved=far_ach,
                              peak=far_peak, unit="TFLOP/s", frac=far_ach / far_peak),
         "phases_ms": phases,
-        "pairs": {k: counts.get(k) for k in ("candidates", "pairs_up1", "pairs_up2", "pairs_up3", "pairs_full",
-                                              "theta_nodes", "theta_modes", "s_nodes", "s_modes", "sources_base")},
+        "pairs": {k: counts.get(k) for k in ("far_pairs", "candidates", "pairs_up1", "pairs_up2", "pairs_up3",
+                                              "pairs_full", "theta_nodes", "theta_modes", "s_nodes", "s_modes",
+                                              "sources_base")},
     }
     if not a.no_cpu_baseline:
         log("bench: timing the CPU oracle on a sample")
-        out["cpu_baseline"] = cpu_baseline(sc, 240, a.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(base_sc, 240, a.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

@@ -224,6 +224,7 @@ struct csbq_ctx {
     } plan;
     DBuf<int> band_apply;
     int last_ntiles = 0;
+    int64_t last_far_pairs = 0;   // source-target pairs of the last smooth sum
     // host copies of the smooth-sum block list outlive the asynchronous uploads
     std::vector<FarTile> h_tiles;
     std::vector<int> h_gnc;
@@ -980,6 +981,8 @@ static int far_sum(csbq_ctx* ctx, int64_t T, bool native, const std::vector<int6
         LCHK(launch_far(st, T, ctx->xt.p, sy, sn, ss, Ns, ctx->tiles.p, (int)tl.size(), ctx->part.p, mixed,
                         ctx->mix_near2, ctx->far_tpt));
     ctx->last_ntiles = (int)tl.size();
+    ctx->last_far_pairs = 0;
+    for (const auto& t : tl) ctx->last_far_pairs += (int64_t)t.tn * t.sn;
     return CSBQ_OK;
 }
 
@@ -1673,7 +1676,8 @@ int csbq_stats(const csbq_ctx* ctx, char* buf, int64_t cap)
         std::snprintf(tmp, sizeof tmp, ", \"gate_escalated\": %lld", (long long)ctx->last_esc);
         s += tmp;
     }
-    std::snprintf(tmp, sizeof tmp, ", \"far_tpt\": %d, \"far_chunk\": %lld", ctx->far_tpt, (long long)ctx->far_chunk);
+    std::snprintf(tmp, sizeof tmp, ", \"far_tpt\": %d, \"far_chunk\": %lld, \"far_pairs\": %lld", ctx->far_tpt,
+                  (long long)ctx->far_chunk, (long long)ctx->last_far_pairs);
     s += tmp;
     {
         const size_t sl = ctx->table_path.find_last_of('/');

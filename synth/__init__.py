@@ -359,9 +359,11 @@ def config3(seed=3000, label=True) -> Scene:
     return sc
 
 
-def config4(seed=4000, n_geom=64, max_spheres=500, max_panels=200):
+def config4(seed=4000, n_geom=64, max_spheres=500, max_panels=200, progress=None):
     """List of independent scenes: panels U{20..200}, spheres U{10..500},
-    radii U(0.1,0.25), gaps 10**U(-3,-1); pipe scaled so RSA stays at <= 13.6 %."""
+    radii U(0.1,0.25), gaps 10**U(-3,-1); pipe scaled so RSA stays at <= 13.6 %.
+    progress(g, scene) is called after each geometry (the full size takes
+    minutes of host time)."""
     rng = np.random.default_rng(seed)
     scenes = []
     for g in range(n_geom):
@@ -375,6 +377,8 @@ def config4(seed=4000, n_geom=64, max_spheres=500, max_panels=200):
         sc = pipe_scene(seed + 17 * (g + 1), M, lam, n_panels=P, radii=radii, gaps=gaps)
         sc.name = f"batch{g}-P{P}-M{M}"
         scenes.append(sc)
+        if progress is not None:
+            progress(g, sc)
     return scenes
 
 
