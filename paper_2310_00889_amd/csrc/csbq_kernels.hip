@@ -641,9 +641,9 @@ __global__ void k_fill_i64(int64_t n, int64_t* __restrict__ v, int64_t val)
 }
 
 // ---------------------------------------------------------------------------
-// smooth Nystrom sum (Section 3.2.1): targets x sources, sources staged in LDS
+// smooth Nystrom sum (Section 3.2.1): targets x sources
 // ---------------------------------------------------------------------------
-constexpr int FAR_REC = 10;     // LDS record of a source: y(3) n(3) sigma*w(3), padded to 16-byte pairs
+constexpr int FAR_REC = 10;     // LDS record of a source (upsampled corrections): y(3) n(3) sigma*w(3), padded
 
 // Each thread owns TPT targets and walks its block's source chunk; a
 // source's record is read at wave-uniform addresses (scalar loads through the
@@ -1383,17 +1383,19 @@ __device__ __forceinline__ double wave_sum(double v)
 }
 
 // One wavefront per (target, element) pair, s-nodes taken in batches of SB.
-//  1. lanes 0..SB-1, one s-node each: interpolation weights, centerline
-//     quantities, circle frame, the target's coordinates relative to the
-//     circle and the choice of theta-rule -> one record per s-node in LDS;
+//  1. lanes 0..SB-1, one s-node each: node, weight, interpolation weights;
+//     all lanes: the centerline quantities at the s-nodes (an MFMA product);
+//     lanes 0..SB-1 again: circle frame, the target's coordinates relative to
+//     the circle and the choice of theta-rule -> one record per s-node in LDS;
 //  2. all lanes: the density's Fourier coefficients (modes up to the measured
-//     band) interpolated to the batch's s-nodes;
+//     band) interpolated to the batch's s-nodes (an MFMA product);
 //  3. all lanes: the batch's (s-node, theta-node) points as one flat list of
-//     mirror pairs, 64 pairs at a time.  With the target's radial direction b0 and b0p = t x b0 as
-//     basis, r = z t + (dr + eps(1 - cos phi)) b0 - eps sin phi b0p, and the
-//     area element and r.n reduce to the scalars g = |x_c'| + eps (e1'.t cos +
-//     e2'.t sin) and eps' (|y_t x y_s| = eps sqrt(g^2 + eps'^2)), so a point
-//     costs one Fourier synthesis and a handful of flops.
+//     mirror pairs, 64 pairs at a time.  With the target's radial direction
+//     b0 and b0p = t x b0 as basis, r = z t + (dr + eps(1 - cos phi)) b0 -
+//     eps sin phi b0p, and the area element and r.n reduce to the scalars
+//     g = |x_c'| + eps (e1'.t cos + e2'.t sin) and eps' (|y_t x y_s| =
+//     eps sqrt(g^2 + eps'^2)), so a point costs half a Fourier synthesis and
+//     a handful of flops.
 typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int SB = 16;
 static_assert(SB == 16, "the coefficient interpolation uses 16-row MFMA tiles");
