@@ -39,7 +39,8 @@ def _load():
         geo = [C.c_int, ip, ip, dp, dp, dp, dp, C.c_int, C.c_int]
         lib.oracle_nodes.argtypes = geo + [dp, dp, dp]
         lib.oracle_smooth_sum.argtypes = geo + [dp, C.c_int64, dp, lp, dp, dp, C.c_int]
-        lib.oracle_eval.argtypes = geo + [dp, C.c_int64, dp, lp, dp, dp, C.c_double, C.c_int, C.c_int]
+        lib.oracle_eval.argtypes = geo + [dp, C.c_int64, dp, lp, dp, dp, C.c_double, C.c_int, C.c_int, C.c_double,
+                                          C.c_int, lp]
         lib.oracle_surface_point.argtypes = geo + [dp, C.c_int, C.c_int, dp, dp, dp, dp, dp, dp]
         lib.oracle_gauss_legendre.argtypes = [C.c_int, dp, dp]
         lib.oracle_num_threads.restype = C.c_int
@@ -107,8 +108,15 @@ def smooth_sum(scene, sigma=None, x=None, tgt_node=None, threads=0):
     return usl, udl
 
 
-def evaluate(scene, sigma=None, x=None, tgt_node=None, rel_tol=1e-15, force_adaptive=False, threads=0):
-    """Single- and double-layer velocities (u_S, u_D), each (T, 3)."""
+def evaluate(scene, sigma=None, x=None, tgt_node=None, rel_tol=1e-15, force_adaptive=False, threads=0,
+             far_scale=0.0, far_ns_mult=0, return_deep=False):
+    """Single- and double-layer velocities (u_S, u_D), each (T, 3).
+
+    Test knobs that weaken the far route (so that pins can show they catch
+    it): far_scale scales the far test's distance, far_ns_mult replaces the
+    far rule's Gauss-Legendre points per panel node.  With return_deep the
+    number of adaptive cells accepted at the depth cap is returned as a third
+    value."""
     lib = _load()
     args, keep = _geo_args(scene)
     sig = np.ascontiguousarray(scene.sigma if sigma is None else sigma, dtype=np.float64)
@@ -117,10 +125,14 @@ def evaluate(scene, sigma=None, x=None, tgt_node=None, rel_tol=1e-15, force_adap
     x, tn = _targets(scene, x, tgt_node)
     usl = np.zeros((len(tn), 3))
     udl = np.zeros((len(tn), 3))
+    deep = np.zeros(1, np.int64)
     rc = lib.oracle_eval(*args, _p(sig), len(tn), _p(x), _p(tn, C.c_int64), _p(usl), _p(udl), float(rel_tol),
-                         int(bool(force_adaptive)), int(threads))
+                         int(bool(force_adaptive)), int(threads), float(far_scale), int(far_ns_mult),
+                         _p(deep, C.c_int64))
     if rc:
         raise ValueError(f"oracle_eval failed ({rc})")
+    if return_deep:
+        return usl, udl, int(deep[0])
     return usl, udl
 
 

@@ -29,8 +29,12 @@
  *  - dy/ds is taken by the complex-step derivative of the analytic map
  *    s -> y(s,t), which is exact to rounding;
  *  - a (target, element) pair whose distance exceeds the oracle's own
- *    conservative far test uses the plain tensor rule (GL x trapezoid),
- *    whose error there is below 1e-16;
+ *    conservative far test uses a plain tensor rule of 3 ns Gauss-Legendre
+ *    points in s times nt angles on the interpolated element, whose error
+ *    there is at rounding level;
+ *  - a pair whose target lies inside the element's bounding ball forms its
+ *    surface points and differences in long double (near a surface the
+ *    kernel depends on x - y to (unit round-off) |x| / distance);
  *  - every other pair is integrated by adaptive tensor Gauss-Legendre on
  *    parameter cells (20-point rule accepted when it agrees with a 13-point
  *    rule to an absolute tolerance), and the element that carries an
@@ -111,7 +115,24 @@ typedef struct {
     const double* sig;                 /* nodal density [ns*nt][3] */
     double ball_c[3], ball_r, eps_max, len, area, sigmax, sext; /* sext: surface extent along s */
     int64_t node0;                     /* global id of this element's node 0 */
+    /* far rule: FAR_NS_MULT * ns Gauss-Legendre points in s times nt angles on
+       the interpolated element (points, unit normals, weights, density) */
+    int nfar;
+    double *fy, *fn, *fw, *fsg;
 } oelem;
+
+/* The far rule's points in s per GL node of the panel rule.  The surface,
+   area element and density interpolants are polynomials of degree ns-1 in s;
+   the double-layer integrand multiplies several of them (J n, r twice, the
+   density), so even far from the element it is a polynomial of degree ~6 ns
+   times a smooth factor.  ns points (exact to degree 2 ns - 1) leave ~1e-12
+   of the result on a sphere as one element; 3 ns points (exact to degree
+   6 ns - 1) leave rounding only. */
+#define FAR_NS_MULT 3
+
+/* default far test: surface extents along s, radii */
+#define FAR_EXTENTS 40.0
+#define FAR_RADII 8.0
 
 typedef struct {
     int n1, n2;
@@ -164,6 +185,16 @@ typedef struct {
 } oaniso;
 
 static const double HSTEP = 1e-30;
+
+/* cells accepted only because the recursion reached OMAXDEPTH (their
+   13- and 20-point estimates still disagreed): reported by oracle_eval so
+   that a pin can require that none occurred */
+static int64_t g_deep_cells = 0;
+static void note_deep_cell(void)
+{
+#pragma omp atomic
+    g_deep_cells++;
+}
 
 #define RT double
 #define CT cplx
@@ -316,6 +347,38 @@ static void elem_setup(oelem* e, int ns, int nt, int sign, double a, double c, c
         if (fabs(sig[q]) > e->sigmax) e->sigmax = fabs(sig[q]);
 }
 
+/* far rule of an element: mult * ns Gauss-Legendre points in s times nt angles */
+static void elem_far_setup(oelem* e, int mult)
+{
+    const int ns = e->ns, nt = e->nt, nf = mult * ns;
+    const double a = e->a, c = e->c, hs = 0.5 * (c - a);
+    double* fx = (double*)malloc(sizeof(double) * nf);
+    double* fwg = (double*)malloc(sizeof(double) * nf);
+    oracle_gauss_legendre(nf, fx, fwg);
+    e->nfar = nf * nt;
+    e->fy = (double*)malloc(sizeof(double) * e->nfar * 3);
+    e->fn = (double*)malloc(sizeof(double) * e->nfar * 3);
+    e->fw = (double*)malloc(sizeof(double) * e->nfar);
+    e->fsg = (double*)malloc(sizeof(double) * e->nfar * 3);
+    for (int i = 0; i < nf; ++i) {
+        srow_d row;
+        srow_make_d(e, 0.5 * (a + c) + hs * fx[i], &row);
+        for (int j = 0; j < nt; ++j) {
+            double y[3], jn[3], J, sg[3];
+            point_eval_d(e, &row, 2.0 * OPI * j / nt, y, jn, &J, sg);
+            const int q = i * nt + j;
+            for (int d = 0; d < 3; ++d) {
+                e->fy[q * 3 + d] = y[d];
+                e->fn[q * 3 + d] = jn[d] / J;
+                e->fsg[q * 3 + d] = sg[d];
+            }
+            e->fw[q] = J * fwg[i] * hs * 2.0 * OPI / nt;
+        }
+    }
+    free(fx);
+    free(fwg);
+}
+
 static void elem_free(oelem* e)
 {
     free(e->dca);
@@ -323,6 +386,11 @@ static void elem_free(oelem* e)
     free(e->ny);
     free(e->nn);
     free(e->nw);
+    free(e->fy);
+    free(e->fn);
+    free(e->fw);
+    free(e->fsg);
+    e->fy = e->fn = e->fw = e->fsg = NULL;
 }
 
 /* ------------------------------------------------------------------ */
@@ -335,12 +403,26 @@ static void smooth_sum(const oelem* e, const double x[3], nacc* acc)
     nacc_add(acc, out);
 }
 
+/* plain tensor rule of FAR_NS_MULT * ns x nt points (far pairs only) */
+static void far_rule(const oelem* e, const double x[3], nacc* acc)
+{
+    double out[NQ] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int q = 0; q < e->nfar; ++q) kernel_add_d(x, e->fy + 3 * q, e->fn + 3 * q, e->fsg + 3 * q, e->fw[q], out);
+    nacc_add(acc, out);
+}
+
 static double elem_tol(const oelem* e, double rel)
 {
     double sc = (e->sigmax > 0 ? e->sigmax : 1.0) * e->area / (2.0 * e->ball_r);
     return rel * sc;
 }
 
+/* Adaptive integration of one element.  A target inside the element's
+   bounding ball may lie within a tiny distance d of the surface; the kernel
+   there depends on x - y to a relative accuracy of (unit round-off) |x| / d,
+   so such pairs form every surface point and difference in long double
+   (unit round-off 5.4e-20): at d = 1e-7 the rounding left in r.n is then
+   ~1e-13 of the result rather than ~1e-9. */
 static void elem_adaptive(const oelem* e, const double x[3], double rel, nacc* acc)
 {
     oaniso an;
@@ -354,10 +436,20 @@ static void elem_adaptive(const oelem* e, const double x[3], double rel, nacc* a
     int ns0 = (int)ceil(e->len / (2.0 * OPI * an.tx / nt0));
     if (ns0 < 1) ns0 = 1;
     if (ns0 > 64) ns0 = 64;
+    const double dc = sqrt(pow(x[0] - e->ball_c[0], 2) + pow(x[1] - e->ball_c[1], 2) + pow(x[2] - e->ball_c[2], 2));
+    const int inside = dc < e->ball_r;
+    const long double xl[3] = {x[0], x[1], x[2]};
     for (int i = 0; i < ns0; ++i)
-        for (int j = 0; j < nt0; ++j)
-            adapt_rect_d(e, x, e->a + (e->c - e->a) * i / ns0, e->a + (e->c - e->a) * (i + 1) / ns0,
-                       2.0 * OPI * j / nt0, 2.0 * OPI * (j + 1) / nt0, tol, 0, &an, acc);
+        for (int j = 0; j < nt0; ++j) {
+            if (inside)
+                adapt_rect_l(e, xl, e->a + (long double)(e->c - e->a) * i / ns0,
+                             e->a + (long double)(e->c - e->a) * (i + 1) / ns0,
+                             2.0L * 3.14159265358979323846264338327950288L * j / nt0,
+                             2.0L * 3.14159265358979323846264338327950288L * (j + 1) / nt0, tol, 0, &an, acc);
+            else
+                adapt_rect_d(e, x, e->a + (e->c - e->a) * i / ns0, e->a + (e->c - e->a) * (i + 1) / ns0,
+                             2.0 * OPI * j / nt0, 2.0 * OPI * (j + 1) / nt0, tol, 0, &an, acc);
+        }
 }
 
 /* element that carries the target as its node (i0, j0): the target and every
@@ -454,7 +546,9 @@ static void geom_free(ogeom* g)
     free(g->el);
 }
 
-static int far_test(const oelem* e, const double x[3])
+/* far_scale < 1 moves the threshold in (a test knob: a lax test must be caught
+   by the pins) */
+static int far_test(const oelem* e, const double x[3], double far_scale)
 {
     double d = sqrt(pow(x[0] - e->ball_c[0], 2) + pow(x[1] - e->ball_c[1], 2) + pow(x[2] - e->ball_c[2], 2)) -
                e->ball_r;
@@ -464,7 +558,7 @@ static int far_test(const oelem* e, const double x[3])
        parameterisation closes up (a sphere in polar angle) rho grows only
        logarithmically with distance, so the smooth rule is trusted only beyond
        40 surface extents along s */
-    double need = fmax(40.0 * e->sext, 8.0 * e->eps_max);
+    double need = far_scale * fmax(FAR_EXTENTS * e->sext, FAR_RADII * e->eps_max);
     return d >= need;
 }
 
@@ -532,15 +626,25 @@ int oracle_smooth_sum(int n_bodies, const int* n_panels, const int* normal_sign,
 
 /* The layer potentials themselves (the element integrals, evaluated to
    ~rel_tol of each element's scale).  force_adaptive != 0 disables the far
-   test (every pair integrated adaptively). */
+   test (every pair integrated adaptively).  Two test knobs weaken the far
+   route so that the pins can show they would catch it: far_scale > 0 scales
+   the far test's distance (default 1), far_ns_mult > 0 replaces the far
+   rule's FAR_NS_MULT.  *n_deep (may be NULL) receives the number of adaptive
+   cells accepted at the depth cap without their two estimates agreeing (zero
+   in a trustworthy result). */
 int oracle_eval(int n_bodies, const int* n_panels, const int* normal_sign, const double* s_break, const double* xc,
                 const double* eps, const double* e1, int ns, int nt, const double* sigma, int64_t n_tgt,
                 const double* x, const int64_t* tgt_node, double* u_sl, double* u_dl, double rel_tol,
-                int force_adaptive, int nthreads)
+                int force_adaptive, int nthreads, double far_scale, int far_ns_mult, int64_t* n_deep)
 {
     ogeom g;
     if (geom_build(&g, n_bodies, n_panels, normal_sign, s_break, xc, eps, e1, ns, nt, sigma)) return -1;
     if (!(rel_tol > 0)) rel_tol = 1e-15;
+    if (!(far_scale > 0)) far_scale = 1.0;
+    if (far_ns_mult <= 0) far_ns_mult = FAR_NS_MULT;
+    if (!force_adaptive)
+        for (int k = 0; k < g.n_elem; ++k) elem_far_setup(&g.el[k], far_ns_mult);
+    g_deep_cells = 0;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #endif
@@ -564,8 +668,8 @@ int oracle_eval(int n_bodies, const int* n_panels, const int* normal_sign, const
             const oelem* e = &g.el[k];
             if (k == own)
                 elem_singular(e, i0, j0, rel_tol, &acc);
-            else if (!force_adaptive && far_test(e, xt))
-                smooth_sum(e, xt, &acc);
+            else if (!force_adaptive && far_test(e, xt, far_scale))
+                far_rule(e, xt, &acc);
             else
                 elem_adaptive(e, xt, rel_tol, &acc);
         }
@@ -575,6 +679,7 @@ int oracle_eval(int n_bodies, const int* n_panels, const int* normal_sign, const
         }
     }
     geom_free(&g);
+    if (n_deep) *n_deep = g_deep_cells;
     return 0;
 }
 
