@@ -40,8 +40,13 @@
  *    of that context (thread-unsafe; one context per thread).
  *  - mem = CSBQ_HOST: pointers are host memory; the call is synchronous.
  *    mem = CSBQ_DEVICE: pointers are device memory on the context's device;
- *    the work is enqueued on the context's stream and the call returns after
- *    enqueue (call csbq_synchronize or synchronise the stream before reading).
+ *    the work is enqueued on the context's stream.  The evaluation calls
+ *    (csbq_eval, csbq_eval_batch, csbq_smooth_sum, csbq_plan) read sizes the
+ *    device computes (candidate-pair counts, correction runs, group ranges)
+ *    back to the host, so they wait for the stream part-way through; they
+ *    return once their last kernels are enqueued, and the outputs may be read
+ *    only after csbq_synchronize (or a synchronisation of the stream).
+ *    csbq_apply returns with its outputs in place.
  *  - the caller owns every array passed in or out; the library copies what
  *    it keeps.
  *  - all floating point arrays are IEEE double, C order, contiguous.
@@ -67,6 +72,22 @@ typedef enum {
     CSBQ_ESTATE = -5,   /* call out of order (e.g. eval before set_geometry) */
     CSBQ_ELIMIT = -6    /* an internal work limit was exceeded */
 } csbq_status;
+
+/* Bits of an evaluation's flag word (csbq_eval_flags, and "flags" in
+   csbq_stats).  NODE_RANGE, GROUP_RANGE and GROUP_ORDER make the call fail
+   with CSBQ_EINVAL and BAND makes csbq_apply fail with CSBQ_ESTATE; SRULE_LIMIT
+   and THETA_CLAMP are accuracy warnings of a completed evaluation: some
+   special quadrature may have missed quad_tol. */
+typedef enum {
+    CSBQ_FLAG_NODE_RANGE = 1,   /* a tgt_node >= the node count */
+    CSBQ_FLAG_SRULE_LIMIT = 2,  /* an off-surface s-rule (Section 3.2.3) stopped bisecting at its depth or
+                                   sub-panel limit with the target still inside a sub-panel's near region */
+    CSBQ_FLAG_THETA_CLAMP = 4,  /* a circle closer (relative to its radius) than the finest tabulated
+                                   theta-rule bracket (Section 3.2.2, Appendix B) used that bracket's rule */
+    CSBQ_FLAG_GROUP_RANGE = 8,  /* a free target's group is outside 0..G-1 */
+    CSBQ_FLAG_GROUP_ORDER = 16, /* targets not ordered by group */
+    CSBQ_FLAG_BAND = 32         /* csbq_apply: the density's band exceeds the plan's */
+} csbq_flag;
 
 typedef enum { CSBQ_HOST = 0, CSBQ_DEVICE = 1 } csbq_mem;
 typedef enum { CSBQ_FP64 = 0, CSBQ_MIXED = 1 } csbq_precision;
@@ -135,9 +156,12 @@ int csbq_get_nodes(csbq_ctx* ctx, double* y, double* normal, double* weight, int
    gate, corrections, smooth sum, reduction).
      sigma     [N][3] nodal density
      x         [n_tgt][3] target points (may be NULL if every tgt_node >= 0)
-     tgt_node  [n_tgt] node id of an on-surface target, -1 for a free target;
-               NULL means every target is free.  For an on-surface target the
-               node's own position is used and x is ignored.
+     tgt_node  [n_tgt] node id of an on-surface target, any negative value
+               for a free target; NULL means every target is free.  For an
+               on-surface target the node's own position is used and x is
+               ignored.  A node id >= the node count fails with CSBQ_EINVAL
+               (in device mode too: the id is checked on the device before
+               the call's first synchronisation).
      u_sl/u_dl [n_tgt][3] outputs (either may be NULL).
    Free targets must not lie on a surface (distance below ~1e-12 of the
    element size is undefined). */
@@ -230,6 +254,12 @@ int csbq_stats(const csbq_ctx* ctx, char* buf, int64_t cap);
 
 /* Block until the context's stream has drained. */
 int csbq_synchronize(csbq_ctx* ctx);
+
+/* Flag word (csbq_flag bits) of the last evaluation call.  After a
+   device-mode call this waits for the context's stream, since the special
+   quadrature sets its warnings on the device; call it before the next
+   evaluation on the context. */
+int csbq_eval_flags(csbq_ctx* ctx, int32_t* flags);
 
 #ifdef __cplusplus
 }

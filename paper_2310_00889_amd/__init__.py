@@ -26,6 +26,9 @@ CSBQ_FP64, CSBQ_MIXED = 0, 1
 CSBQ_GATE_CRITERION, CSBQ_GATE_MLP = 0, 1
 GATE_NF, GATE_NO, GATE_NW = 16, 4, 9668
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ETABLE", -5: "ESTATE", -6: "ELIMIT"}
+# bits of an evaluation's flag word (csbq_flag)
+FLAG_NODE_RANGE, FLAG_SRULE_LIMIT, FLAG_THETA_CLAMP = 1, 2, 4
+FLAG_GROUP_RANGE, FLAG_GROUP_ORDER, FLAG_BAND = 8, 16, 32
 
 
 class CsbqError(RuntimeError):
@@ -80,6 +83,7 @@ def load_library():
     lib.csbq_gate_dataset.argtypes = [vp, dp, C.c_int64, dp, lp, C.c_double, C.c_int64, dp, dp, dp,
                                       C.POINTER(C.c_int64)]
     lib.csbq_synchronize.argtypes = [vp]
+    lib.csbq_eval_flags.argtypes = [vp, C.POINTER(C.c_int32)]
     _lib = lib
     return lib
 
@@ -343,6 +347,13 @@ class Evaluator:
 
     def synchronize(self):
         self._check(self._lib.csbq_synchronize(self._h), "csbq_synchronize")
+
+    def flags(self):
+        """Flag word of the last evaluation (FLAG_* bits; waits for the
+        stream after a device-mode call)."""
+        f = C.c_int32()
+        self._check(self._lib.csbq_eval_flags(self._h, C.byref(f)), "csbq_eval_flags")
+        return int(f.value)
 
     def stats(self):
         buf = C.create_string_buffer(4096)

@@ -234,6 +234,7 @@ struct csbq_ctx {
     bool ph_ok = false;
     int64_t last_T = 0, last_P = 0, last_nup[NUP] = {0, 0, 0}, last_nf = 0;
     int last_err_flags = 0;
+    bool flags_pending = false;   // device-mode call: the final flags are still on the device
 
     int fail(int code, const std::string& msg)
     {
@@ -243,6 +244,11 @@ struct csbq_ctx {
 };
 
 static void plan_drop(csbq_ctx* ctx);
+
+static_assert(CSBQ_FLAG_NODE_RANGE == FLAG_NODE_RANGE && CSBQ_FLAG_SRULE_LIMIT == FLAG_SRULE_LIMIT &&
+                  CSBQ_FLAG_THETA_CLAMP == FLAG_THETA_CLAMP && CSBQ_FLAG_GROUP_RANGE == FLAG_GROUP_RANGE &&
+                  CSBQ_FLAG_GROUP_ORDER == FLAG_GROUP_ORDER && CSBQ_FLAG_BAND == FLAG_BAND,
+              "flag bits of the C ABI and the kernels");
 
 #define HIPC(call)                                                                             \
     do {                                                                                       \
@@ -414,17 +420,6 @@ int csbq_create(const csbq_options* opt, csbq_ctx** out)
     ctx->gc.ct = 1000.0;
     ctx->gc.hmin_fac = 1.0;
     ctx->gc.extra_modes = 2;
-    // calibration override of the estimate constants: "cs,ct,hmin_fac,extra_modes"
-    if (const char* g = std::getenv("CSBQ_GATE_CONSTS")) {
-        double a = ctx->gc.cs, b = ctx->gc.ct, c = ctx->gc.hmin_fac;
-        int d = ctx->gc.extra_modes;
-        if (std::sscanf(g, "%lf,%lf,%lf,%d", &a, &b, &c, &d) == 4 && a > 0 && b > 0 && c > 0 && d >= 0) {
-            ctx->gc.cs = a;
-            ctx->gc.ct = b;
-            ctx->gc.hmin_fac = c;
-            ctx->gc.extra_modes = d;
-        }
-    }
     for (int k = 0; k < kNPhase; ++k) {
         ctx->ph[k].name = kPhaseNames[k];
         (void)hipEventCreate(&ctx->ph[k].a);
@@ -522,6 +517,21 @@ int csbq_synchronize(csbq_ctx* ctx)
 {
     if (!ctx) return CSBQ_EINVAL;
     HIPC(hipStreamSynchronize(ctx->stream));
+    return CSBQ_OK;
+}
+
+int csbq_eval_flags(csbq_ctx* ctx, int32_t* flags)
+{
+    if (!ctx || !flags) return CSBQ_EINVAL;
+    if (ctx->flags_pending && ctx->err_d.p) {
+        int f = 0;
+        HIPC(hipSetDevice(ctx->opt.device));
+        HIPC(hipMemcpyAsync(&f, ctx->err_d.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+        HIPC(hipStreamSynchronize(ctx->stream));
+        ctx->last_err_flags = f;
+        ctx->flags_pending = false;
+    }
+    *flags = ctx->last_err_flags;
     return CSBQ_OK;
 }
 
@@ -790,8 +800,8 @@ static int eval_front(csbq_ctx* ctx, const double* sigma, int64_t T, const doubl
 // table (after a stream synchronisation); fails on unordered targets.
 static int group_ranges(csbq_ctx* ctx, int64_t T, int flags, std::vector<int64_t>& tr)
 {
-    if (flags & 8) return ctx->fail(CSBQ_EINVAL, "target group out of range");
-    if (flags & 16) return ctx->fail(CSBQ_EINVAL, "targets must be ordered by group");
+    if (flags & CSBQ_FLAG_GROUP_RANGE) return ctx->fail(CSBQ_EINVAL, "target group out of range");
+    if (flags & CSBQ_FLAG_GROUP_ORDER) return ctx->fail(CSBQ_EINVAL, "targets must be ordered by group");
     const int G = ctx->G;
     tr.assign((size_t)G + 1, 0);
     tr[G] = T;
@@ -1012,16 +1022,20 @@ static int outputs_back(csbq_ctx* ctx, int64_t T, double* u_sl, double* u_dl, in
     return CSBQ_OK;
 }
 
+// Host mode: outputs and the final flag word back to the caller.  Device
+// mode: nothing to wait for; the flags of the corrections (CSBQ_FLAG_SRULE_LIMIT,
+// CSBQ_FLAG_THETA_CLAMP) stay on the device for csbq_eval_flags.
 static int finish(csbq_ctx* ctx, int64_t T, double* u_sl, double* u_dl, int mem)
 {
     int flags = 0;
+    ctx->flags_pending = mem == CSBQ_DEVICE;
     if (mem == CSBQ_HOST) {
         if (u_sl && T) HIPC(hipMemcpyAsync(u_sl, ctx->usl_d.p, (size_t)T * 3 * 8, hipMemcpyDeviceToHost, ctx->stream));
         if (u_dl && T) HIPC(hipMemcpyAsync(u_dl, ctx->udl_d.p, (size_t)T * 3 * 8, hipMemcpyDeviceToHost, ctx->stream));
         HIPC(hipMemcpyAsync(&flags, ctx->err_d.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
         HIPC(hipStreamSynchronize(ctx->stream));
         ctx->last_err_flags = flags;
-        if (flags & 1) return ctx->fail(CSBQ_EINVAL, "tgt_node out of range");
+        if (flags & CSBQ_FLAG_NODE_RANGE) return ctx->fail(CSBQ_EINVAL, "tgt_node out of range");
     }
     return CSBQ_OK;
 }
@@ -1041,6 +1055,8 @@ int csbq_smooth_sum(csbq_ctx* ctx, const double* sigma, int64_t T, const double*
     int flags = 0;
     HIPC(hipMemcpyAsync(&flags, ctx->err_d.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     HIPC(hipStreamSynchronize(ctx->stream));
+    ctx->last_err_flags = flags;
+    if (flags & CSBQ_FLAG_NODE_RANGE) return ctx->fail(CSBQ_EINVAL, "tgt_node out of range");
     std::vector<int64_t> tr;
     if ((rc = group_ranges(ctx, T, flags, tr))) return rc;
     if ((rc = far_sum(ctx, T, true, tr, ctx->stream))) return rc;
@@ -1100,6 +1116,8 @@ int csbq_eval_batch(csbq_ctx* ctx, const double* sigma, int64_t T, const double*
     std::vector<int> hband((size_t)2 * E);
     HIPC(hipMemcpyAsync(hband.data(), ctx->band.p, hband.size() * sizeof(int), hipMemcpyDeviceToHost, st));
     HIPC(hipStreamSynchronize(st));
+    ctx->last_err_flags = flags;
+    if (flags & CSBQ_FLAG_NODE_RANGE) return ctx->fail(CSBQ_EINVAL, "tgt_node out of range");
     // pair lists are sorted and scanned with 32-bit counts
     if (P < 0 || P >= (int64_t)INT32_MAX)
         return ctx->fail(CSBQ_ELIMIT, "more than 2^31 candidate pairs: evaluate the targets in slices");
@@ -1159,7 +1177,8 @@ int csbq_eval_batch(csbq_ctx* ctx, const double* sigma, int64_t T, const double*
                                   ctx->band.p, (float)std::log10(ctx->gc.tol), ctx->gfeat.p));
         LCHK(launch_gate_mlp(st, P, ctx->gfeat.p, ctx->gate_wfrag.p, ctx->gate_bias.p, ctx->gate_tau, ctx->gtier.p,
                              ctx->gesc.p, nullptr));
-        LCHK(launch_gate_select(st, P, ctx->perm.p, ctx->gesc.p, ctx->gtier.p, ctx->tier.p, ctx->gflag.p));
+        LCHK(launch_gate_select(st, P, ctx->perm.p, ctx->pe.p, ctx->info.p, ctx->gesc.p, ctx->gtier.p, ctx->tier.p,
+                                ctx->gflag.p));
         size_t sb = 0;
         HIPC(hipcub::DeviceSelect::Flagged(nullptr, sb, ctx->perm.p, ctx->gflag.p, ctx->gsel.p, ctx->gnsel.p, (int)P,
                                            st));
@@ -1395,7 +1414,8 @@ int csbq_apply(csbq_ctx* ctx, const double* sigma, double* u_sl, double* u_dl, i
     HIPC(hipMemcpyAsync(&flags, ctx->err_d.p, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPC(hipStreamSynchronize(st));
     ctx->last_err_flags = flags;
-    if (flags & 32)
+    ctx->flags_pending = false;
+    if (flags & CSBQ_FLAG_BAND)
         return ctx->fail(CSBQ_ESTATE, "the density's band exceeds the one the plan was built for: plan again");
     return CSBQ_OK;
 }
@@ -1678,6 +1698,10 @@ int csbq_stats(const csbq_ctx* ctx, char* buf, int64_t cap)
     }
     std::snprintf(tmp, sizeof tmp, ", \"far_tpt\": %d, \"far_chunk\": %lld, \"far_pairs\": %lld", ctx->far_tpt,
                   (long long)ctx->far_chunk, (long long)ctx->last_far_pairs);
+    s += tmp;
+    std::snprintf(tmp, sizeof tmp,
+                  ", \"estimate\": {\"tol\": %.3e, \"cs\": %.1f, \"ct\": %.1f, \"hmin_fac\": %.3f, \"extra_modes\": %d}",
+                  ctx->gc.tol, ctx->gc.cs, ctx->gc.ct, ctx->gc.hmin_fac, ctx->gc.extra_modes);
     s += tmp;
     {
         const size_t sl = ctx->table_path.find_last_of('/');

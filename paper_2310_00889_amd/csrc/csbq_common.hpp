@@ -37,6 +37,16 @@ __host__ __device__ constexpr int up_ns(int k) { return k == 2 ? 64 : 32; }
 __host__ __device__ constexpr int up_nt(int k) { return k == 0 ? 32 : (k == 1 ? 64 : 128); }
 __host__ __device__ constexpr int64_t up_pts(int k) { return (int64_t)up_ns(k) * up_nt(k); }
 
+// bits of the evaluation's device flag word (the C ABI names them CSBQ_FLAG_*)
+enum : int {
+    FLAG_NODE_RANGE = 1,    // a target's node id is beyond the node count
+    FLAG_SRULE_LIMIT = 2,   // an off-surface s-rule stopped bisecting at its limit
+    FLAG_THETA_CLAMP = 4,   // a circle closer than the finest theta-rule bracket
+    FLAG_GROUP_RANGE = 8,   // a free target's group is out of range
+    FLAG_GROUP_ORDER = 16,  // targets not ordered by group
+    FLAG_BAND = 32          // a density wider in band than a frozen plan's
+};
+
 // sub-panel kinds of an s-rule
 enum : int { SUB_GL = 0, SUB_LOG_LO = 1, SUB_LOG_HI = 2 };  // log singularity at lo / at hi
 

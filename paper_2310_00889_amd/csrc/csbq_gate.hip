@@ -206,7 +206,11 @@ __global__ __launch_bounds__(64 * GM_WAVES) void k_gate_mlp(int64_t P, const flo
 
 // final tier of the confident pairs; flags (in element-major order) of the
 // pairs the criterion decides
-__global__ void k_gate_select(int64_t P, const int* __restrict__ perm, const uint8_t* __restrict__ esc,
+// On an element closed at its ends (fb == 2) the far-field rule already is the
+// 32 x 32 rule of tier 1, so a tier-1 correction would be zero: a predicted
+// tier 1 there means "the far-field rule is not enough" and becomes tier 2.
+__global__ void k_gate_select(int64_t P, const int* __restrict__ perm, const int* __restrict__ pe,
+                              const ElemInfo* __restrict__ info, const uint8_t* __restrict__ esc,
                               const int8_t* __restrict__ tier_mlp, int8_t* __restrict__ tier,
                               uint8_t* __restrict__ flag)
 {
@@ -215,7 +219,11 @@ __global__ void k_gate_select(int64_t P, const int* __restrict__ perm, const uin
     const int p = perm[i];
     const uint8_t f = esc[p];
     flag[i] = f;
-    if (!f) tier[p] = tier_mlp[p];
+    if (!f) {
+        int8_t tr = tier_mlp[p];
+        if (tr == TIER_UP1 && info[pe[p]].fb == 2) tr = TIER_UP2;
+        tier[p] = tr;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -401,12 +409,12 @@ int launch_gate_mlp(hipStream_t st, int64_t P, const float* feat, const uint16_t
     return 0;
 }
 
-int launch_gate_select(hipStream_t st, int64_t P, const int* perm, const uint8_t* esc, const int8_t* tier_mlp,
-                       int8_t* tier, uint8_t* flag)
+int launch_gate_select(hipStream_t st, int64_t P, const int* perm, const int* pe, const ElemInfo* info,
+                       const uint8_t* esc, const int8_t* tier_mlp, int8_t* tier, uint8_t* flag)
 {
     if (P == 0) return 0;
-    hipLaunchKernelGGL(k_gate_select, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, st, P, perm, esc, tier_mlp,
-                       tier, flag);
+    hipLaunchKernelGGL(k_gate_select, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, st, P, perm, pe, info, esc,
+                       tier_mlp, tier, flag);
     GATE_LAUNCH_CHECK();
     return 0;
 }

@@ -51,7 +51,10 @@ int launch_gate_adam(hipStream_t st, float* W, const float* grad, float* m, floa
                      float eps, int step);
 int launch_gate_labels(hipStream_t st, int64_t P, const double* c_up1, const double* c_up2, const double* c_up3,
                        const double* c_full, double thr_s, double thr_d, int8_t* label);
-int launch_gate_select(hipStream_t st, int64_t P, const int* perm, const uint8_t* esc, const int8_t* tier_mlp,
-                       int8_t* tier, uint8_t* flag);
+// predicted tier of every confident pair (a predicted tier 1 on an element
+// closed at its ends, whose far-field rule is tier 1's rule, becomes tier 2);
+// flag[i] = 1 for the pairs left to the criterion
+int launch_gate_select(hipStream_t st, int64_t P, const int* perm, const int* pe, const ElemInfo* info,
+                       const uint8_t* esc, const int8_t* tier_mlp, int8_t* tier, uint8_t* flag);
 
 }  // namespace csbq

@@ -607,7 +607,7 @@ __global__ void k_targets(int64_t T, const double* __restrict__ x, const int64_t
     if (t >= T) return;
     int64_t nd = tnode ? tnode[t] : -1;
     if (nd >= N) {
-        atomicOr(err, 1);
+        atomicOr(err, FLAG_NODE_RANGE);
         nd = -1;
     }
     for (int d = 0; d < 3; ++d) {
@@ -616,7 +616,7 @@ __global__ void k_targets(int64_t T, const double* __restrict__ x, const int64_t
     }
     int g = (nd >= 0) ? info[nd / NPE].group : (tgrp_in ? tgrp_in[t] : 0);
     if (g < 0 || g >= G) {
-        atomicOr(err, 8);
+        atomicOr(err, FLAG_GROUP_RANGE);
         g = 0;
     }
     tgroup[t] = g;
@@ -631,7 +631,7 @@ __global__ void k_group_bounds(int64_t T, const int* __restrict__ tgroup, int64_
     if (t >= T) return;
     const int g = tgroup[t];
     if (t == 0 || tgroup[t - 1] != g) gstart[g] = t;
-    if (t > 0 && tgroup[t - 1] > g) atomicOr(err, 16);
+    if (t > 0 && tgroup[t - 1] > g) atomicOr(err, FLAG_GROUP_ORDER);
 }
 
 __global__ void k_fill_i64(int64_t n, int64_t* __restrict__ v, int64_t val)
@@ -1522,7 +1522,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
                 const double xm = sr - 0.5 * (lo + hi), hh = 0.5 * (hi - lo);
                 bool ok = xm * xm * EB2 + y2A >= EAB2 * hh * hh;
                 if (ok || (hi - lo) < 1e-12 * (c - a) || sp + 2 > 48 || ns_ + sp + 2 > MAXSUB) {
-                    if (!ok) atomicOr(err, 2);
+                    if (!ok) atomicOr(err, FLAG_SRULE_LIMIT);
                     sub_lo[ns_] = lo;
                     sub_hi[ns_] = hi;
                     sub_ty[ns_] = SUB_GL;
@@ -1657,7 +1657,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
                 } else {
                     if (b > rt.nb) {
                         b = rt.nb;
-                        atomicOr(err, 4);
+                        atomicOr(err, FLAG_THETA_CLAMP);
                     }
                     rb = b;
                 }
@@ -1983,13 +1983,13 @@ int launch_prep_sigma(hipStream_t st, int E, const double* sigma, const double* 
 }
 
 // a density whose band exceeds the one a frozen evaluation plan was built
-// for (flag 32): the plan's rules were chosen for the narrower band
+// for (FLAG_BAND): the plan's rules were chosen for the narrower band
 __global__ void k_band_check(int E, const int* __restrict__ band_new, const int* __restrict__ band_plan,
                              int* __restrict__ err)
 {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= E) return;
-    if (band_new[2 * e] > band_plan[2 * e] || band_new[2 * e + 1] > band_plan[2 * e + 1]) atomicOr(err, 32);
+    if (band_new[2 * e] > band_plan[2 * e] || band_new[2 * e + 1] > band_plan[2 * e + 1]) atomicOr(err, FLAG_BAND);
 }
 
 __global__ void k_fill_i32(int64_t n, int* __restrict__ v, int val)

@@ -89,7 +89,9 @@ def test_gate_forward_matches_numpy(ev):
     ref = _forward_bf16(w, x)
     err = np.abs(lg - ref) / (1 + np.abs(ref))
     print("forward max err", err.max(), flush=True)
-    assert err.max() < 2e-2
+    # bf16 operands are emulated exactly; what remains is the order of the
+    # FP32 accumulation (~1e-7)
+    assert err.max() < 1e-5
     s = 1 / (1 + np.exp(-ref))
     t_ref = np.zeros(len(x), int)
     for k in range(4):
@@ -109,13 +111,42 @@ def test_gate_gradient_matches_numpy(ev):
     rel = np.linalg.norm(g - gref) / np.linalg.norm(gref)
     print("loss", loss, lref, "grad rel", rel, flush=True)
     assert abs(loss - lref) < 1e-5 * max(1.0, abs(lref))
-    assert rel < 1e-4
-    # every parameter block carries gradient
+    # element by element within every parameter block, relative to the
+    # block's largest gradient (FP32 sums of 700 samples against float64)
     off = 0
     for name, shp in gate.SHAPES:
         n = int(np.prod(shp))
-        assert np.abs(g[off:off + n]).max() > 0, name
+        gb, rb = g[off:off + n], gref[off:off + n]
+        assert np.abs(gb).max() > 0, name
+        eb = np.abs(gb - rb).max() / np.abs(rb).max()
+        print(f"grad {name}: max element error {eb:.1e} of the block's largest", flush=True)
+        assert eb < 1e-5, (name, eb)
         off += n
+
+
+def test_gate_adam_step_matches_numpy(ev):
+    """One Adam step (Kingma & Ba: m = (1 - b1) g, v = (1 - b2) g^2, bias
+    corrections 1 - b1, 1 - b2 at step 1) over one minibatch holding every
+    sample, against numpy from the float64 gradient."""
+    from paper_2310_00889_amd import gate
+    w0 = gate.init_weights(seed=11)
+    x = _features(512, 12)
+    lab = np.random.default_rng(13).integers(0, 5, 512).astype(np.int8)
+    posw = np.array([4, 3, 2, 1], np.float32)
+    lr, b1, b2, eps = 1e-3, 0.9, 0.999, 1e-8
+    w1, _ = ev.gate_train(x, lab, posw, w0, epochs=1, batch=512, lr=lr, seed=3)
+    _, g = _loss_grad(w0, x, lab, posw)
+    m_hat = (1 - b1) * g / (1 - b1)
+    v_hat = (1 - b2) * g * g / (1 - b2)
+    w_ref = w0.astype(np.float64) - lr * m_hat / (np.sqrt(v_hat) + eps)
+    # where |g| is far above eps the step is lr sign(g); where it is not, the
+    # FP32 gradient's own rounding (relative 1e-6 of the block) moves the step
+    big = np.abs(g) > 1e-4
+    err = np.abs(w1 - w_ref)
+    print("adam step: max error", err[big].max(), "elements with |g| > 1e-4:", big.sum(), flush=True)
+    assert big.sum() > 0.5 * len(g)
+    assert err[big].max() < 1e-6 * lr + 1e-7 * np.abs(w0[big]).max()
+    assert err.max() < 2 * lr
 
 
 def test_gate_training_learns(ev):
@@ -129,7 +160,7 @@ def test_gate_training_learns(ev):
     acc = np.mean(tier == lab)
     print("losses", losses, "accuracy", acc, flush=True)
     assert losses[-1] < 0.5 * losses[0]
-    assert acc > 0.85   # the labels jump at sharp thresholds of one feature
+    assert acc > 0.9   # the labels jump at sharp thresholds of one feature
 
 
 def test_gate_dataset_labels(ev):
@@ -253,3 +284,57 @@ def test_config5_mlp_gate_speedup():
         assert es < 1e-6 and ed < 1e-6
         e.close()
     assert near["mlp"] < near["criterion"]
+
+
+def test_predicted_tier1_on_sphere_becomes_tier2(ev):
+    """On a sphere (an element closed at its poles) the far-field rule is
+    already tier 1's 32 x 32 rule, so a confident network prediction of tier 1
+    must become the 32 x 64 correction.  Weights that predict tier 1 for every
+    pair with certainty: no pair ends in tier 1; own-element pairs go to the
+    criterion."""
+    import paper_2310_00889_amd as pk
+    from paper_2310_00889_amd import gate
+    w = np.zeros(gate.GATE_NW, np.float32)
+    w[gate.GATE_NW - 4:] = np.array([20.0, -20.0, -20.0, -20.0], np.float32)
+    e = pk.Evaluator(quad_tol=1e-7, precision="mixed", gate="mlp")
+    e.gate_load(w, 0.05)
+    b1 = synth.sphere_body([0.0, 0.0, 0.0], 0.2, [0, 0, 1], [1, 0, 0])
+    b2 = synth.sphere_body([0.0, 0.0, 0.45], 0.2, [0, 1, 0], [1, 0, 0])
+    sc = synth.Scene([b1, b2])
+    sc.sigma = np.random.default_rng(3).standard_normal((sc.n_nodes, 3))
+    e.set_geometry(sc)
+    tn = np.arange(0, sc.n_nodes, 7)
+    e.eval(sc.sigma, None, tn)
+    st = e.stats()
+    print("forced tier 1 on spheres:", st, flush=True)
+    assert st["pairs_up1"] == 0
+    assert st["pairs_up2"] > 0
+    assert st["gate_escalated"] >= len(tn)        # every own-element pair
+    e.close()
+
+
+def test_config5_held_out_miss_rate():
+    """The trained network on held-out pairs (the config-5 scene was never
+    trained on): the method-generated label of every candidate pair of every
+    64th node judges each confident prediction.  A miss is a pair the network
+    decides (not escalated to the criterion) at a tier below its label.  The
+    rate is asserted below 1e-3 (measured: see the printed line)."""
+    import paper_2310_00889_amd as pk
+    w, meta = _trained()
+    sc = synth.config5()
+    e = pk.Evaluator(quad_tol=1e-7, precision="mixed")
+    e.set_geometry(sc)
+    tn = sc.tgt_node[::64].copy()
+    f, lab, crit = e.gate_dataset(sc.sigma, None, tn, label_tol=1e-8, cap=4_000_000)
+    e.gate_load(w, float(meta["tau_esc"]))
+    tier, esc, _ = e.gate_infer(f)
+    closed = f[:, 4] > 0.5            # closed-end element: predicted tier 1 runs as tier 2
+    tier = np.where((tier == 1) & closed, 2, tier)
+    decided = (esc == 0) & (tier < 4) & (f[:, 11] < 0.5)   # own-element pairs always go to the criterion
+    miss = decided & (tier < lab)
+    rate = miss.sum() / len(lab)
+    print(f"config5 held out: {len(lab)} pairs, decided by the network {decided.mean():.3f}, "
+          f"misses {miss.sum()} ({rate:.2e}); labels {np.bincount(lab, minlength=5)}", flush=True)
+    assert len(lab) > 100_000
+    assert rate < 1e-3
+    e.close()

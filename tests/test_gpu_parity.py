@@ -31,7 +31,24 @@ def ev():
     e.close()
 
 
-def _check_classes(u, uo, cls, what):
+def _no_flags(ev):
+    """The last evaluation raised no accuracy warning (s-rule limit, theta
+    bracket clamp) or input flag."""
+    f = ev.flags()
+    assert f == 0, f"evaluation flags {f}"
+
+
+def _argmax_report(u, uo, what, tn=None, x=None):
+    """Print where the largest deviation sits: target index, node id and
+    element (on-surface) or position (free target)."""
+    k = int(np.unravel_index(np.argmax(np.abs(u - uo)), u.shape)[0])
+    where = f"node {int(tn[k])} element {int(tn[k]) // 512}" if tn is not None and tn[k] >= 0 else \
+        (f"x {np.round(x[k], 6).tolist()}" if x is not None else "")
+    print(f"{what}: worst target {k} {where} |du| {np.abs(u[k] - uo[k]).max():.2e}", flush=True)
+
+
+def _check_classes(u, uo, cls, what, tn=None, x=None):
+    _argmax_report(u, uo, what, tn, x)
     for c in np.unique(cls):
         m = cls == c
         err = np.abs(u[m] - uo[m]).max() / np.abs(uo[m]).max()
@@ -92,9 +109,10 @@ def test_sphere_config1_off_surface(ev):
     sc = synth.config1()
     ev.set_geometry(sc)
     us, ud = ev.eval(sc.sigma, sc.x, sc.tgt_node)
+    _no_flags(ev)
     uso, udo = oracle.evaluate(sc)
-    _check_classes(us, uso, sc.tgt_class, "S")
-    _check_classes(ud, udo, sc.tgt_class, "D")
+    _check_classes(us, uso, sc.tgt_class, "S", x=sc.x)
+    _check_classes(ud, udo, sc.tgt_class, "D", x=sc.x)
 
 
 def test_sphere_on_surface(ev):
@@ -102,7 +120,9 @@ def test_sphere_on_surface(ev):
     ev.set_geometry(sc)
     tn = np.arange(0, sc.n_nodes, 3)
     us, ud = ev.eval(sc.sigma, None, tn)
+    _no_flags(ev)
     uso, udo = oracle.evaluate(sc, None, None, tn)
+    _argmax_report(ud, udo, "D", tn)
     assert _rel(us, uso) < GATE, _rel(us, uso)
     assert _rel(ud, udo) < GATE, _rel(ud, udo)
 
@@ -136,22 +156,52 @@ def test_small_pipe_on_and_off_surface(ev):
     rng = np.random.default_rng(2)
     tn = rng.choice(sc.n_nodes, 300, replace=False)
     us, ud = ev.eval(sc.sigma, None, tn)
+    _no_flags(ev)
     uso, udo = oracle.evaluate(sc, None, None, tn)
     print("on-surface", _rel(us, uso), _rel(ud, udo), ev.stats(), flush=True)
+    _argmax_report(ud, udo, "D on-surface", tn)
     assert _rel(us, uso) < GATE and _rel(ud, udo) < GATE
     y, n, _ = oracle.nodes(sc)
     k = rng.choice(sc.n_nodes, 300, replace=False)
     d = 10.0 ** rng.uniform(-3, -0.3, 300) * np.where(rng.random(300) < 0.5, 1, -1)
     xs = y[k] + d[:, None] * n[k]
     us, ud = ev.eval(sc.sigma, xs, None)
+    _no_flags(ev)
     uso, udo = oracle.evaluate(sc, None, xs, -np.ones(300, np.int64))
     print("off-surface", _rel(us, uso), _rel(ud, udo), ev.stats(), flush=True)
+    _argmax_report(ud, udo, "D off-surface", None, xs)
     assert _rel(us, uso) < GATE and _rel(ud, udo) < GATE
+
+
+def _config2_strata(sc):
+    """Stratified on-surface targets of the 200-sphere pipe: sphere nodes
+    nearest the poles (first and last GL circle), sphere nodes near contact
+    (within 0.05 of another surface), wall nodes on the rims (first and last
+    GL circle of the end panels) and the wall nodes nearest a sphere."""
+    rng = np.random.default_rng(31)
+    nwall = sc.bodies[0].n_panels * 512
+    node = np.arange(sc.n_nodes)
+    i_s = (node % 512) // 32
+    sph = node >= nwall
+    poles = node[sph & ((i_s == 0) | (i_s == 15))]
+    lab = synth.label_near_contact(synth.config2(), dist=0.05).tgt_class
+    contact = node[lab == 2]
+    panel = node // 512
+    rims = node[(~sph) & (((panel == 0) & (i_s == 0)) | ((panel == sc.bodies[0].n_panels - 1) & (i_s == 15)))]
+    y = synth.analytic_node_positions(sc)[:nwall]
+    dmin = np.full(nwall, np.inf)
+    for c, r in zip(sc.sphere_centers, sc.sphere_radii):
+        dmin = np.minimum(dmin, np.linalg.norm(y - c[None, :], axis=1) - r)
+    wall_near = np.argsort(dmin)[:200]
+    pick = [rng.choice(a, 6, replace=False) for a in (poles, contact, rims, wall_near)]
+    return np.concatenate(pick)
 
 
 def test_config2_full_size_sampled(ev):
     """Full config-2 evaluation (153,600 on-surface targets) in the launch
-    configuration the benchmark times; sampled targets against the oracle."""
+    configuration the benchmark times; 24 random targets and 24 stratified
+    ones (sphere poles, near-contact sphere nodes, pipe rims, wall nodes
+    nearest a sphere) against the oracle."""
     import torch
     sc = synth.config2()
     ev.set_geometry(sc)
@@ -159,13 +209,88 @@ def test_config2_full_size_sampled(ev):
     tn = torch.from_numpy(sc.tgt_node).cuda()
     us, ud = ev.eval(sig, None, tn)
     torch.cuda.synchronize()
+    _no_flags(ev)
     us, ud = us.cpu().numpy(), ud.cpu().numpy()
     assert np.isfinite(us).all() and np.isfinite(ud).all()
     rng = np.random.default_rng(3)
-    idx = np.concatenate([rng.choice(51200, 8, replace=False), 51200 + rng.choice(102400, 16, replace=False)])
+    idx = np.concatenate([rng.choice(51200, 8, replace=False), 51200 + rng.choice(102400, 16, replace=False),
+                          _config2_strata(sc)])
     uso, udo = oracle.evaluate(sc, None, None, sc.tgt_node[idx])
-    _check_classes(us[idx], uso, sc.tgt_class[idx], "S")
-    _check_classes(ud[idx], udo, sc.tgt_class[idx], "D")
+    _check_classes(us[idx], uso, sc.tgt_class[idx], "S", sc.tgt_node[idx])
+    _check_classes(ud[idx], udo, sc.tgt_class[idx], "D", sc.tgt_node[idx])
+
+
+def test_full_band_density(ev):
+    """A density of nodal noise: every Fourier mode up to the Nyquist mode 16
+    and every Legendre degree up to 15 on every element, on and off the
+    surface, against the oracle (1e-10)."""
+    sc = synth.small_pipe_scene(n_panels=6, n_spheres=3)
+    sc.sigma = np.random.default_rng(41).standard_normal((sc.n_nodes, 3))
+    ev.set_geometry(sc)
+    rng = np.random.default_rng(42)
+    tn = rng.choice(sc.n_nodes, 150, replace=False)
+    us, ud = ev.eval(sc.sigma, None, tn)
+    _no_flags(ev)
+    st = ev.stats()
+    uso, udo = oracle.evaluate(sc, None, None, tn)
+    print("full band on-surface", _rel(us, uso), _rel(ud, udo), st, flush=True)
+    _argmax_report(ud, udo, "D full band on-surface", tn)
+    assert _rel(us, uso) < GATE and _rel(ud, udo) < GATE
+    y, n, _ = oracle.nodes(sc)
+    k = rng.choice(sc.n_nodes, 150, replace=False)
+    d = 10.0 ** rng.uniform(-3, -0.3, 150) * np.where(rng.random(150) < 0.5, 1, -1)
+    xs = y[k] + d[:, None] * n[k]
+    us, ud = ev.eval(sc.sigma, xs, None)
+    _no_flags(ev)
+    uso, udo = oracle.evaluate(sc, None, xs, -np.ones(150, np.int64))
+    print("full band off-surface", _rel(us, uso), _rel(ud, udo), flush=True)
+    _argmax_report(ud, udo, "D full band off-surface", None, xs)
+    assert _rel(us, uso) < GATE and _rel(ud, udo) < GATE
+
+
+def test_free_targets_very_near_surface(ev):
+    """Free targets 1e-6 and 1e-7 off the surface, inside and outside, above
+    random (off-node) points of the pipe panels and the spheres, against the
+    oracle (which forms such pairs in long double): 1e-10."""
+    sc = synth.small_pipe_scene(n_panels=6, n_spheres=3)
+    ev.set_geometry(sc)
+    rng = np.random.default_rng(43)
+    xs = []
+    for e in range(sc.n_panels):
+        b, p = (0, e) if e < 6 else (e - 5, 0)
+        sb = sc.bodies[b].s_break
+        s = rng.uniform(sb[p] + 0.05 * (sb[p + 1] - sb[p]), sb[p + 1] - 0.05 * (sb[p + 1] - sb[p]), 4)
+        t = rng.uniform(0, 2 * np.pi, 4)
+        yp, npt, _, _ = oracle.surface_point(sc, e, s, t)
+        d = np.array([1e-6, -1e-6, 1e-7, -1e-7])
+        xs.append(yp + d[:, None] * npt)
+    xs = np.concatenate(xs)
+    us, ud = ev.eval(sc.sigma, xs, None)
+    _no_flags(ev)
+    uso, udo = oracle.evaluate(sc, None, xs, -np.ones(len(xs), np.int64))
+    print("very near", _rel(us, uso), _rel(ud, udo), ev.stats(), flush=True)
+    _argmax_report(ud, udo, "D very near", None, xs)
+    assert _rel(us, uso) < GATE and _rel(ud, udo) < GATE
+
+
+def test_out_of_range_device_node_raises(ev):
+    """A device-resident tgt_node beyond the node count fails the call with
+    CsbqError (checked on the device before the call's first wait), and the
+    context stays usable."""
+    import torch
+    import paper_2310_00889_amd as pk
+    sc = synth.small_pipe_scene(n_panels=2, n_spheres=1)
+    ev.set_geometry(sc)
+    sig = torch.from_numpy(sc.sigma).cuda()
+    bad = torch.tensor([0, sc.n_nodes + 3, 5], dtype=torch.int64, device="cuda")
+    with pytest.raises(pk.CsbqError, match="out of range"):
+        ev.eval(sig, None, bad)
+    assert ev.flags() & pk.FLAG_NODE_RANGE
+    good = torch.tensor([0, 7, 5], dtype=torch.int64, device="cuda")
+    us, ud = ev.eval(sig, None, good)
+    torch.cuda.synchronize()
+    _no_flags(ev)
+    assert torch.isfinite(us).all() and torch.isfinite(ud).all()
 
 
 def test_determinism_and_device_host_agree(ev):
@@ -235,6 +360,7 @@ def test_mixed_small_pipe(ev_mixed):
     rng = np.random.default_rng(4)
     tn = rng.choice(sc.n_nodes, 200, replace=False)
     us, ud = ev_mixed.eval(sc.sigma, None, tn)
+    _no_flags(ev_mixed)
     uso, udo = oracle.evaluate(sc, None, None, tn)
     print("mixed on-surface", _rel(us, uso), _rel(ud, udo), flush=True)
     assert _rel(us, uso) < MIXED_GATE and _rel(ud, udo) < MIXED_GATE
@@ -243,6 +369,7 @@ def test_mixed_small_pipe(ev_mixed):
     d = 10.0 ** rng.uniform(-3, -0.3, 200) * np.where(rng.random(200) < 0.5, 1, -1)
     xs = y[k] + d[:, None] * n[k]
     us, ud = ev_mixed.eval(sc.sigma, xs, None)
+    _no_flags(ev_mixed)
     uso, udo = oracle.evaluate(sc, None, xs, -np.ones(200, np.int64))
     print("mixed off-surface", _rel(us, uso), _rel(ud, udo), flush=True)
     assert _rel(us, uso) < MIXED_GATE and _rel(ud, udo) < MIXED_GATE
@@ -259,6 +386,7 @@ def test_mixed_config3_full_size_sampled(ev_mixed):
     tn = torch.from_numpy(sc.tgt_node).cuda()
     us, ud = ev_mixed.eval(sig, None, tn)
     torch.cuda.synchronize()
+    _no_flags(ev_mixed)
     us, ud = us.cpu().numpy(), ud.cpu().numpy()
     assert np.isfinite(us).all() and np.isfinite(ud).all()
     print("config3 mixed stats", ev_mixed.stats(), flush=True)
