@@ -44,6 +44,8 @@ def _load():
         lib.oracle_surface_point.argtypes = geo + [dp, C.c_int, C.c_int, dp, dp, dp, dp, dp, dp]
         lib.oracle_gauss_legendre.argtypes = [C.c_int, dp, dp]
         lib.oracle_num_threads.restype = C.c_int
+        lib.oracle_set_kernel.argtypes = [C.c_int]
+        lib.oracle_set_kernel.restype = C.c_int
         _lib = lib
     return _lib
 
@@ -134,6 +136,37 @@ def evaluate(scene, sigma=None, x=None, tgt_node=None, rel_tol=1e-15, force_adap
     if return_deep:
         return usl, udl, int(deep[0])
     return usl, udl
+
+
+def evaluate_laplace(scene, sigma, x=None, tgt_node=None, rel_tol=1e-15, force_adaptive=False, threads=0,
+                     return_deep=False):
+    """Laplace single and double layers (Section 4.1) of a scalar density
+    sigma (n_nodes,): (u_S, u_D), each (T,), with u_S = int G sigma,
+    u_D = int dG/dn_y sigma, G = 1/(4 pi |x - y|)."""
+    lib = _load()
+    sig = np.zeros((scene.n_nodes, 3))
+    sig[:, 0] = np.asarray(sigma, dtype=np.float64).reshape(scene.n_nodes)
+    lib.oracle_set_kernel(1)
+    try:
+        r = evaluate(scene, sig, x, tgt_node, rel_tol, force_adaptive, threads, return_deep=return_deep)
+    finally:
+        lib.oracle_set_kernel(0)
+    if return_deep:
+        return r[0][:, 0].copy(), r[1][:, 0].copy(), r[2]
+    return r[0][:, 0].copy(), r[1][:, 0].copy()
+
+
+def smooth_sum_laplace(scene, sigma, x=None, tgt_node=None, threads=0):
+    """Plain tensor-rule Laplace sums (self term zero): (u_S, u_D), each (T,)."""
+    lib = _load()
+    sig = np.zeros((scene.n_nodes, 3))
+    sig[:, 0] = np.asarray(sigma, dtype=np.float64).reshape(scene.n_nodes)
+    lib.oracle_set_kernel(1)
+    try:
+        us, ud = smooth_sum(scene, sig, x, tgt_node, threads)
+    finally:
+        lib.oracle_set_kernel(0)
+    return us[:, 0].copy(), ud[:, 0].copy()
 
 
 def surface_point(scene, elem, s, t, sigma=None):

@@ -3,6 +3,9 @@
  * (stokeslet) and double-layer (stresslet) velocity potentials of
  * panel-discretised bodies.
  *
+ * The same routines evaluate the Laplace single and double layers of Section
+ * 4.1 on a scalar density (oracle_set_kernel).
+ *
  * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
  * CPU-baseline leg of the benchmark may load this library.  It shares no code,
  * header, table or constant with the GPU library; it is the independent
@@ -185,6 +188,23 @@ typedef struct {
 } oaniso;
 
 static const double HSTEP = 1e-30;
+
+/* kernel pair evaluated by every routine below: the Stokes single and double
+   layers (default), or the Laplace ones (Section 4.1: G = 1/(4 pi |r|) and its
+   normal derivative (r.n)/(4 pi |r|^3), r = x - y) acting on the scalar
+   density held in component 0 of sigma, with u_S and u_D returned in
+   component 0 of the outputs.  Set by oracle_set_kernel for the calls that
+   follow (one setting per process). */
+#define ORACLE_STOKES 0
+#define ORACLE_LAPLACE 1
+static int g_kernel = ORACLE_STOKES;
+
+int oracle_set_kernel(int kernel)
+{
+    if (kernel != ORACLE_STOKES && kernel != ORACLE_LAPLACE) return -1;
+    g_kernel = kernel;
+    return 0;
+}
 
 /* cells accepted only because the recursion reached OMAXDEPTH (their
    13- and 20-point estimates still disagreed): reported by oracle_eval so
