@@ -133,6 +133,38 @@ def run_mode(sc, sig, tn, precision, gate, quad_tol, steps, warmup, ref=None):
     return out
 
 
+def run_matrix(sc, sig, tn, quad_tol, steps, ref):
+    """Plan with the special-quadrature pairs' correction matrices (built once)
+    and time applies of the density: ms per apply, the build time, the
+    matrices' size and the apply kernel's bandwidth (it reads every matrix once)."""
+    import torch
+    import paper_2310_00889_amd as pk
+    ev = pk.Evaluator(quad_tol=quad_tol)
+    ev.set_geometry(sc)
+    T = int(tn.shape[0])
+    usl = torch.empty((T, 3), dtype=torch.float64, device="cuda")
+    udl = torch.empty((T, 3), dtype=torch.float64, device="cuda")
+    t0 = time.perf_counter()
+    ev.plan(sig, None, tn, usl, udl, matrix=True)
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
+    st = ev.stats()
+    ev.apply(sig, usl, udl)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ev.apply(sig, usl, udl)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    errs = {name: float((u - r).abs().max() / r.abs().max()) for name, u, r in (("S", usl, ref[0]), ("D", udl, ref[1]))}
+    mb = st["plan"]["matrix_bytes"]
+    out = dict(ms_per_apply=1e3 * dt, value=T / dt, unit="target evals/s", plan_s=plan_s,
+               build_ms=st["plan"]["build_ms"], matrix_bytes=mb, pairs_full=st.get("pairs_full"),
+               rel_err_vs_eval=errs)
+    ev.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -256,12 +288,19 @@ def main():
         # modes, each checked against the headline FP64 result (quad_tol
         # 1e-12, itself within 1e-10 of the oracle)
         ref = (usl.clone(), udl.clone())
+        usl_ref, udl_ref = ref
         ev.close()
         modes = {}
         for prec, gt in (("fp64", "criterion"), ("mixed", "criterion"), ("mixed", "mlp")):
             log(f"bench: mode {prec}+{gt} at quad_tol 1e-7")
             modes[f"{prec}+{gt}@1e-7"] = run_mode(sc, sig, tn, prec, gt, 1e-7, a.mode_steps, 2, ref)
         out["modes_at_1e-7"] = modes
+    if not a.no_modes and a.workload == "pipe100-spheres200" and a.precision == "fp64":
+        # the setup/evaluation split with stored correction matrices (the
+        # special-quadrature pairs' E): build time once, then timed applies of
+        # the same density, checked against the headline result
+        log("bench: matrix plan")
+        out["matrix_apply"] = run_matrix(sc, sig, tn, 1e-12, a.mode_steps, (usl_ref, udl_ref))
     if not a.no_cpu_baseline:
         log("bench: timing the CPU oracle on a sample")
         out["cpu_baseline"] = cpu_baseline(base_sc, 240, a.cpu_seconds)

@@ -92,6 +92,15 @@ typedef enum {
 typedef enum { CSBQ_HOST = 0, CSBQ_DEVICE = 1 } csbq_mem;
 typedef enum { CSBQ_FP64 = 0, CSBQ_MIXED = 1 } csbq_precision;
 typedef enum { CSBQ_GATE_CRITERION = 0, CSBQ_GATE_MLP = 1 } csbq_gate_mode;
+/* Kernel pair.  CSBQ_KERNEL_LAPLACE evaluates the Laplace single and double
+   layers of Section 4.1 instead of the Stokes ones, on a scalar density:
+     u_S(x) = int G(x - y) sigma(y) dS_y,  u_D(x) = int dG(x - y)/dn_y sigma(y) dS_y,
+     G(r) = 1 / (4 pi |r|),  dG/dn_y = (r.n) / (4 pi |r|^3),  r = x - y,
+   so that u_D of a constant 1 is -1 inside a closed surface, -1/2 on it and
+   0 outside.  Every density array then holds one value per node ([N]) and
+   every output one value per target ([n_tgt]) where the Stokes layers have
+   three; everything else (geometry, targets, tables, corrections) is shared. */
+typedef enum { CSBQ_KERNEL_STOKES = 0, CSBQ_KERNEL_LAPLACE = 1 } csbq_kernel;
 
 typedef struct {
     double quad_tol;       /* per-element quadrature tolerance (relative); <= 0 selects 1e-12 */
@@ -100,6 +109,7 @@ typedef struct {
     int32_t device;        /* HIP device ordinal */
     void* stream;          /* hipStream_t to enqueue on; NULL = a stream owned by the context */
     const char* table_dir; /* directory holding rules.bin; NULL = the package's tables/ */
+    int32_t kernel;        /* csbq_kernel: the Stokes layers, or the Laplace layers (FP64, criterion gate only) */
 } csbq_options;
 
 /* Fill *opt with defaults (quad_tol 1e-12, FP64, criterion gate, device 0,
@@ -198,7 +208,99 @@ int csbq_eval_batch(csbq_ctx* ctx, const double* sigma, int64_t n_tgt, const dou
    `mem`. */
 int csbq_plan(csbq_ctx* ctx, const double* sigma, int64_t n_tgt, const double* x, const int64_t* tgt_node,
               const int32_t* tgt_group, double* u_sl, double* u_dl, int mem);
+
+/* csbq_plan with options (flags, a bitwise or):
+   CSBQ_PLAN_FULL_BAND  tiers and rules for the widest band any density can
+                        have (every Legendre degree and Fourier mode), so that
+                        csbq_apply never refuses a density (the correction
+                        pairs then do not depend on the planning density, as
+                        the paper's E does not);
+   CSBQ_PLAN_MATRIX     the paper's setup/evaluation split for the special
+                        quadrature (Section 3.2.1, the sparse correction
+                        matrix of Eq. e:nystrom-correction; Section 3.4 costs):
+                        for every special-quadrature pair the 3 x 3 single- and
+                        double-layer blocks (12 symmetric components) against
+                        the element's density coefficients (16 GL rows x 32
+                        trigonometric basis functions), 48 KB per pair,
+                        built once; every csbq_apply then forms those
+                        corrections by one bandwidth-bound pass over the
+                        matrices instead of the special quadrature.  The
+                        upsampled-rule tiers stay in density form.  Stokes
+                        layers only (CSBQ_EINVAL otherwise); more than 160 GB
+                        of matrices fails with CSBQ_ELIMIT. */
+#define CSBQ_PLAN_MATRIX 1
+#define CSBQ_PLAN_FULL_BAND 2
+int csbq_plan_ex(csbq_ctx* ctx, const double* sigma, int64_t n_tgt, const double* x, const int64_t* tgt_node,
+                 const int32_t* tgt_group, int32_t flags, double* u_sl, double* u_dl, int mem);
 int csbq_apply(csbq_ctx* ctx, const double* sigma, double* u_sl, double* u_dl, int mem);
+
+/* ---- Boundary-integral solves (Section 4).  Both run on a single
+   geometry (csbq_set_geometry), with the density at every surface node.
+   Each freezes one evaluation plan over all surface nodes as on-surface
+   targets, with tiers and rules chosen for the widest band a density can
+   have (every Legendre degree and Fourier mode), and solves by restarted
+   GMRES (classical Gram-Schmidt applied twice, fixed-order reductions: a
+   solve is bitwise repeatable); every operator application replays the plan
+   (csbq_apply).  The plan stays valid afterwards for csbq_apply.
+
+   Double-layer orientation: the integral equations of Section 4 use the
+   double layer D_4 = -D, D the potential u_dl of csbq_eval (whose stresslet
+   gives c, c/2, 0 inside, on and outside a closed surface for a constant
+   density c); with D_4 the rigid motions lie in the null space of I/2 + D_4
+   (Proposition on the null space, Section 4.2).  The combined-field operator
+   is K = I/2 + D_4 + eta S (Section 4.1; the slender choice of the weight is
+   eta = 1 / (2 eps log(1/eps)), eps the cross-section radius). */
+typedef struct {
+    double eta;        /* weight of the single layer in K (> 0) */
+    double tol;        /* GMRES stops at ||b - A sigma|| <= tol ||b|| (the Arnoldi estimate) */
+    int32_t max_iter;  /* operator applications of the Krylov iterations, at most */
+    int32_t restart;   /* Krylov basis size before a restart */
+} csbq_solve_options;
+
+typedef struct {
+    int32_t iterations;   /* Krylov iterations taken */
+    double rel_residual;  /* ||b - A sigma|| / ||b||, recomputed with one more application */
+} csbq_solve_info;
+
+/* eta 1, tol 1e-10, max_iter 200, restart 60 */
+void csbq_default_solve_options(csbq_solve_options* opt);
+
+/* Exterior Stokes Dirichlet problem, slender combined-field form (Section
+   4.1): solves K sigma = u0 at the surface nodes.  The exterior velocity is
+   then u = D_4[sigma] + eta S[sigma] = eta u_sl - u_dl of csbq_eval.  With
+   the Laplace layers (CSBQ_KERNEL_LAPLACE) it is the Laplace problem of
+   Section 4.1, K = I/2 + D + eta S with the evaluator's D itself (whose
+   orientation is the one that equation uses), u0 and sigma of one value per
+   node, and u = u_dl + eta u_sl off the surface.
+     u0     [N][3] boundary velocity at the nodes (in `mem`)
+     sigma  [N][3] solution (in `mem`)
+     info   iterations and residual (host; may be NULL). */
+int csbq_solve_dirichlet(csbq_ctx* ctx, const csbq_solve_options* opt, const double* u0, double* sigma,
+                         csbq_solve_info* info, int mem);
+
+/* Stokes mobility problem, slender mobility combined-field form (Section
+   4.2): rigid bodies with given net force and torque and a slip velocity.
+   Per body b the completion density nu = a_b + beta_b x (y - c_b) (c_b the
+   surface centroid under the smooth weights) has sum w nu = F_b and
+   sum w (y - c_b) x nu = T_b (the torque about c_b; the printed equation
+   writes the cross product in the other order, which would flip the
+   torque's sign).  L is the orthogonal projector onto the rigid motions of
+   each body in the smooth-weight inner product.  Solves
+   (K (I - L) + L) sigma = u_slip - S nu; the rigid motion is -L sigma.
+     force, torque [n_bodies][3] (host)
+     u_slip  [N][3] slip velocity (in `mem`; NULL = none)
+     sigma   [N][3] out: the density (I - L) sigma of the representation
+             u = (D_4 + eta S)[(I - L) sigma] + S[nu] = eta u_sl - u_dl of
+             csbq_eval on this density, plus u_sl of csbq_eval on nu (in `mem`;
+             may be NULL)
+     nu      [N][3] out: the completion density (in `mem`; may be NULL)
+     rigid   [n_bodies][6] out: translational velocity V_b and angular
+             velocity Omega_b about c_b (host; may be NULL)
+     centers [n_bodies][3] out: c_b (host; may be NULL)
+   A body whose rigid-motion Gram matrix is singular fails with CSBQ_EINVAL. */
+int csbq_solve_mobility(csbq_ctx* ctx, const csbq_solve_options* opt, const double* force, const double* torque,
+                        const double* u_slip, double* sigma, double* nu, double* rigid, double* centers,
+                        csbq_solve_info* info, int mem);
 
 /* ---- Learned correction-tier gate (an extension beyond the paper; the
    criterion of Section 3.2's error estimates stays the fallback and decides

@@ -24,6 +24,7 @@ TABLE_DIR = os.path.join(HERE, "tables")
 CSBQ_HOST, CSBQ_DEVICE = 0, 1
 CSBQ_FP64, CSBQ_MIXED = 0, 1
 CSBQ_GATE_CRITERION, CSBQ_GATE_MLP = 0, 1
+CSBQ_KERNEL_STOKES, CSBQ_KERNEL_LAPLACE = 0, 1
 GATE_NF, GATE_NO, GATE_NW = 16, 4, 9668
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ETABLE", -5: "ESTATE", -6: "ELIMIT"}
 # bits of an evaluation's flag word (csbq_flag)
@@ -37,7 +38,24 @@ class CsbqError(RuntimeError):
 
 class _Options(C.Structure):
     _fields_ = [("quad_tol", C.c_double), ("precision", C.c_int32), ("gate", C.c_int32), ("device", C.c_int32),
-                ("stream", C.c_void_p), ("table_dir", C.c_char_p)]
+                ("stream", C.c_void_p), ("table_dir", C.c_char_p), ("kernel", C.c_int32)]
+
+
+class _SolveOptions(C.Structure):
+    _fields_ = [("eta", C.c_double), ("tol", C.c_double), ("max_iter", C.c_int32), ("restart", C.c_int32)]
+
+
+class _SolveInfo(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("rel_residual", C.c_double)]
+
+
+def slender_eta(eps):
+    """The slender combined-field weight 1 / (2 eps log(1/eps)) (Section 4.1);
+    positive for eps < 1."""
+    import math
+    if not 0 < eps < 1:
+        raise ValueError("the slender weight needs 0 < eps < 1")
+    return 1.0 / (2.0 * eps * math.log(1.0 / eps))
 
 
 _lib = None
@@ -75,6 +93,7 @@ def load_library():
     lib.csbq_smooth_sum.argtypes = [vp, dp, C.c_int64, dp, lp, dp, dp, C.c_int]
     lib.csbq_stats.argtypes = [vp, C.c_char_p, C.c_int64]
     lib.csbq_plan.argtypes = [vp, dp, C.c_int64, dp, lp, ip, dp, dp, C.c_int]
+    lib.csbq_plan_ex.argtypes = [vp, dp, C.c_int64, dp, lp, ip, C.c_int32, dp, dp, C.c_int]
     lib.csbq_apply.argtypes = [vp, dp, dp, dp, C.c_int]
     lib.csbq_gate_load.argtypes = [vp, dp, C.c_float]
     lib.csbq_gate_infer.argtypes = [vp, dp, C.c_int64, dp, dp, dp]
@@ -83,6 +102,10 @@ def load_library():
     lib.csbq_gate_dataset.argtypes = [vp, dp, C.c_int64, dp, lp, C.c_double, C.c_int64, dp, dp, dp,
                                       C.POINTER(C.c_int64)]
     lib.csbq_synchronize.argtypes = [vp]
+    lib.csbq_default_solve_options.argtypes = [C.POINTER(_SolveOptions)]
+    lib.csbq_solve_dirichlet.argtypes = [vp, C.POINTER(_SolveOptions), dp, dp, C.POINTER(_SolveInfo), C.c_int]
+    lib.csbq_solve_mobility.argtypes = [vp, C.POINTER(_SolveOptions), dp, dp, dp, dp, dp, dp, dp,
+                                        C.POINTER(_SolveInfo), C.c_int]
     lib.csbq_eval_flags.argtypes = [vp, C.POINTER(C.c_int32)]
     _lib = lib
     return lib
@@ -103,10 +126,19 @@ def _ptr(a):
 class Evaluator:
     """One library context: geometry, quadrature tables, device buffers."""
 
-    def __init__(self, quad_tol=1e-12, precision="fp64", device=0, stream=None, table_dir=None, gate="criterion"):
+    nc = 3   # density / output components per node / target (1 for the Laplace layers)
+
+    def __init__(self, quad_tol=1e-12, precision="fp64", device=0, stream=None, table_dir=None, gate="criterion",
+                 kernel="stokes"):
+        """kernel: "stokes" (densities and outputs of three components per
+        node / target) or "laplace" (one)."""
         lib = load_library()
         opt = _Options()
         lib.csbq_default_options(C.byref(opt))
+        if kernel not in ("stokes", "laplace"):
+            raise CsbqError(f"unknown kernel {kernel!r}")
+        opt.kernel = CSBQ_KERNEL_LAPLACE if kernel == "laplace" else CSBQ_KERNEL_STOKES
+        self.nc = 1 if kernel == "laplace" else 3
         opt.quad_tol = float(quad_tol)
         opt.precision = CSBQ_MIXED if precision == "mixed" else CSBQ_FP64
         opt.gate = CSBQ_GATE_MLP if gate == "mlp" else CSBQ_GATE_CRITERION
@@ -166,6 +198,7 @@ class Evaluator:
                                                _ptr(arrs["eps"]), _ptr(arrs["e1"]), ns, nt, CSBQ_HOST)
         self._check(rc, "csbq_set_geometry_batch")
         self._plan_T = None   # the library drops its plan with the geometry
+        self._n_bodies = int(f["n_bodies"])
         n = C.c_int64()
         self._check(self._lib.csbq_num_nodes(self._h, C.byref(n)), "csbq_num_nodes")
         self.n_nodes = n.value
@@ -192,13 +225,16 @@ class Evaluator:
         if tgt_node is None and x is None:
             raise CsbqError("targets: give x, tgt_node or both")
         T = int(tgt_node.shape[0] if tgt_node is not None else x.shape[0])
-        need(sigma, "sigma", 3 * self.n_nodes, "float64")
+        need(sigma, "sigma", self.nc * self.n_nodes, "float64")
         need(x, "x", 3 * T, "float64")
         need(tgt_node, "tgt_node", T, "int64")
         need(tgt_group, "tgt_group", T, "int32")
-        need(out_sl, "out_sl", 3 * T, "float64")
-        need(out_dl, "out_dl", 3 * T, "float64")
+        need(out_sl, "out_sl", self.nc * T, "float64")
+        need(out_dl, "out_dl", self.nc * T, "float64")
         return T
+
+    def _oshape(self, T):
+        return (T, 3) if self.nc == 3 else (T,)
 
     def _call(self, fn, name, sigma, x, tgt_node, out_sl, out_dl, tgt_group=None, batch=False):
         dev = _is_torch_cuda(sigma)
@@ -206,9 +242,9 @@ class Evaluator:
             import torch
             T = int(tgt_node.shape[0] if tgt_node is not None else x.shape[0])
             if out_sl is None:
-                out_sl = torch.empty((T, 3), dtype=torch.float64, device=sigma.device)
+                out_sl = torch.empty(self._oshape(T), dtype=torch.float64, device=sigma.device)
             if out_dl is None:
-                out_dl = torch.empty((T, 3), dtype=torch.float64, device=sigma.device)
+                out_dl = torch.empty(self._oshape(T), dtype=torch.float64, device=sigma.device)
             for a in (sigma, x, tgt_node, tgt_group, out_sl, out_dl):
                 if a is not None and not (_is_torch_cuda(a) and a.is_contiguous()):
                     raise CsbqError("device calls need contiguous CUDA tensors throughout")
@@ -229,8 +265,8 @@ class Evaluator:
             tgt_group = np.ascontiguousarray(tgt_group, np.int32).reshape(-1)
         T = self._check_shapes(sigma, x, tgt_node, tgt_group, None, None)
         self._last_T = T
-        usl = np.zeros((T, 3))
-        udl = np.zeros((T, 3))
+        usl = np.zeros(self._oshape(T))
+        udl = np.zeros(self._oshape(T))
         if batch:
             rc = fn(self._h, _ptr(sigma), T, _ptr(x), _ptr(tgt_node), _ptr(tgt_group), _ptr(usl), _ptr(udl),
                     CSBQ_HOST)
@@ -252,12 +288,16 @@ class Evaluator:
         return self._call(self._lib.csbq_smooth_sum, "csbq_smooth_sum", sigma, x, tgt_node, out_sl, out_dl)
 
     # ---- setup / apply split
-    def plan(self, sigma, x=None, tgt_node=None, out_sl=None, out_dl=None, tgt_group=None):
+    def plan(self, sigma, x=None, tgt_node=None, out_sl=None, out_dl=None, tgt_group=None, matrix=False,
+             full_band=False):
         """Evaluate and freeze the plan (pairs, tiers, rules, smooth-sum blocks)
-        for later apply() calls on the same targets."""
+        for later apply() calls on the same targets.  matrix: store the
+        special-quadrature pairs' correction matrices (CSBQ_PLAN_MATRIX);
+        full_band: rules for any density's band (CSBQ_PLAN_FULL_BAND)."""
         self._plan_T = None
-        out = self._call(self._lib.csbq_plan, "csbq_plan", sigma, x, tgt_node, out_sl, out_dl, tgt_group,
-                         batch=True)
+        flags = (1 if matrix else 0) | (2 if full_band else 0)
+        fn = lambda h, sg, T, xx, tn, tg, us, ud, mem: self._lib.csbq_plan_ex(h, sg, T, xx, tn, tg, flags, us, ud, mem)
+        out = self._call(fn, "csbq_plan_ex", sigma, x, tgt_node, out_sl, out_dl, tgt_group, batch=True)
         self._plan_T = self._last_T   # apply() writes the plan's targets, whatever is evaluated in between
         return out
 
@@ -274,18 +314,76 @@ class Evaluator:
             import torch
             T = self._plan_T
             if out_sl is None:
-                out_sl = torch.empty((T, 3), dtype=torch.float64, device=sigma.device)
+                out_sl = torch.empty(self._oshape(T), dtype=torch.float64, device=sigma.device)
             if out_dl is None:
-                out_dl = torch.empty((T, 3), dtype=torch.float64, device=sigma.device)
+                out_dl = torch.empty(self._oshape(T), dtype=torch.float64, device=sigma.device)
             self._check(self._lib.csbq_apply(self._h, _ptr(sigma), _ptr(out_sl), _ptr(out_dl), CSBQ_DEVICE),
                         "csbq_apply")
             return out_sl, out_dl
         sigma = np.ascontiguousarray(sigma, np.float64)
         self._check_shapes(sigma, None, plan_targets, None, None, None)
-        usl = np.zeros((self._plan_T, 3))
-        udl = np.zeros((self._plan_T, 3))
+        usl = np.zeros(self._oshape(self._plan_T))
+        udl = np.zeros(self._oshape(self._plan_T))
         self._check(self._lib.csbq_apply(self._h, _ptr(sigma), _ptr(usl), _ptr(udl), CSBQ_HOST), "csbq_apply")
         return usl, udl
+
+    # ---- boundary-integral solves (Section 4)
+    def _solve_opts(self, eta, tol, max_iter, restart):
+        o = _SolveOptions()
+        self._lib.csbq_default_solve_options(C.byref(o))
+        o.eta, o.tol, o.max_iter, o.restart = float(eta), float(tol), int(max_iter), int(restart)
+        return o
+
+    def solve_dirichlet(self, u0, eta, tol=1e-10, max_iter=200, restart=60):
+        """Density sigma of the slender combined-field Dirichlet problem
+        K sigma = u0 (K = I/2 + D_4 + eta S, D_4 = -u_dl's double layer) at
+        the surface nodes; returns (sigma, iterations, relative residual).
+        The exterior velocity is eta u_S - u_D of eval(sigma, ...)."""
+        o = self._solve_opts(eta, tol, max_iter, restart)
+        info = _SolveInfo()
+        if _is_torch_cuda(u0):
+            import torch
+            if not u0.is_contiguous() or u0.dtype != torch.float64 or u0.numel() != self.nc * self.n_nodes:
+                raise CsbqError(f"u0: expected {self.nc * self.n_nodes} contiguous float64 values")
+            sig = torch.empty_like(u0)
+            self._check(self._lib.csbq_solve_dirichlet(self._h, C.byref(o), _ptr(u0), _ptr(sig), C.byref(info),
+                                                       CSBQ_DEVICE), "csbq_solve_dirichlet")
+        else:
+            u = np.ascontiguousarray(u0, np.float64)
+            if u.size != self.nc * self.n_nodes:
+                raise CsbqError(f"u0: expected {self.nc * self.n_nodes} values, got {u.size}")
+            sig = np.zeros(self._oshape(self.n_nodes))
+            self._check(self._lib.csbq_solve_dirichlet(self._h, C.byref(o), _ptr(u), _ptr(sig), C.byref(info),
+                                                       CSBQ_HOST), "csbq_solve_dirichlet")
+        return sig, int(info.iterations), float(info.rel_residual)
+
+    def solve_mobility(self, force, torque, eta, u_slip=None, tol=1e-10, max_iter=200, restart=60):
+        """Rigid bodies under given forces and torques (n_bodies x 3 each) and
+        an optional slip velocity: the slender mobility combined-field
+        equation.  Returns a dict with the representation's density sigma
+        ((I - L) sigma), the completion density nu, the rigid motions (V, Omega)
+        per body about the centroids, the centroids, iterations and residual."""
+        B = int(np.asarray(force).reshape(-1, 3).shape[0])
+        f = np.ascontiguousarray(force, np.float64).reshape(-1, 3)
+        t = np.ascontiguousarray(torque, np.float64).reshape(-1, 3)
+        if f.shape != t.shape:
+            raise CsbqError("force and torque need one row per body")
+        o = self._solve_opts(eta, tol, max_iter, restart)
+        info = _SolveInfo()
+        rigid = np.zeros((B, 6))
+        cen = np.zeros((B, 3))
+        us = None if u_slip is None else np.ascontiguousarray(u_slip, np.float64)
+        if us is not None and us.size != 3 * self.n_nodes:
+            raise CsbqError(f"u_slip: expected {3 * self.n_nodes} values, got {us.size}")
+        if B != getattr(self, "_n_bodies", B):
+            raise CsbqError(f"force and torque: {B} rows for {self._n_bodies} bodies")
+        sig = np.zeros((self.n_nodes, 3))
+        nu = np.zeros((self.n_nodes, 3))
+        self._check(self._lib.csbq_solve_mobility(self._h, C.byref(o), _ptr(f), _ptr(t), _ptr(us), _ptr(sig), _ptr(nu),
+                                                  _ptr(rigid), _ptr(cen), C.byref(info), CSBQ_HOST),
+                    "csbq_solve_mobility")
+        return dict(sigma=sig, nu=nu, velocity=rigid[:, :3].copy(), omega=rigid[:, 3:].copy(), centers=cen,
+                    iterations=int(info.iterations), rel_residual=float(info.rel_residual))
 
     # ---- learned gate
     def gate_load(self, weights, tau_esc=0.05):

@@ -7,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = [os.path.join(HERE, "csrc", f) for f in ("csbq_kernels.hip", "csbq_gate.hip", "csbq_api.cpp")]
+SRC = [os.path.join(HERE, "csrc", f) for f in ("csbq_kernels.hip", "csbq_gate.hip", "csbq_solve.hip", "csbq_api.cpp", "csbq_solve.cpp")]
 LIB = os.path.join(HERE, "libcsbq.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

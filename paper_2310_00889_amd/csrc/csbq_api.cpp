@@ -13,10 +13,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/csbq.h"
-#include "csbq_common.hpp"
-#include "csbq_gate.hpp"
-#include "csbq_kernels.hpp"
+#include "csbq_ctx.hpp"
 #include <algorithm>
 #include <random>
 
@@ -24,41 +21,7 @@ using namespace csbq;
 
 namespace {
 
-// grow-only device buffer
-template <typename T>
-struct DBuf {
-    T* p = nullptr;
-    size_t n = 0;
-    hipError_t ensure(size_t m)
-    {
-        if (m <= n && p) return hipSuccess;
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        n = 0;
-        size_t bytes = (m ? m : 1) * sizeof(T);
-        hipError_t e = hipMalloc((void**)&p, bytes);
-        if (e == hipSuccess) n = m;
-        return e;
-    }
-    void release()
-    {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        n = 0;
-    }
-    DBuf() = default;
-    DBuf(const DBuf&) = delete;
-    DBuf& operator=(const DBuf&) = delete;
-    ~DBuf() { release(); }
-};
-
-struct Phase {
-    const char* name;
-    hipEvent_t a, b;
-};
-
 const char* kPhaseNames[] = {"prep", "far", "search", "classify", "bucket", "corr_up", "corr_full", "reduce"};
-constexpr int kNPhase = 8;
 
 // Gauss-Legendre nodes by Newton iteration on the Legendre recurrence, with
 // the closed-form barycentric weights (-1)^i sqrt((1-x_i^2) w_i) of the GL
@@ -151,97 +114,6 @@ std::string default_table_dir()
 
 }  // namespace
 
-struct csbq_ctx {
-    csbq_options opt{};
-    std::string err;
-    std::string table_dir, table_path;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    GateConsts gc{};
-    // quadrature tables
-    DBuf<int> roff;
-    DBuf<double> rth, rw, lx, lw, rcs, rsn, romc;
-    int nb = 0, nl = 0;
-    double gx[NS], gw[NS], lam[NS];
-    // geometry
-    int E = 0;
-    int64_t N = 0;
-    bool have_geom = false;
-    DBuf<double> g_xc, g_eps, g_e1, g_sa, g_sc;
-    DBuf<int> g_sign, g_body, g_group;
-    // batch of independent geometries: elements [h_gel[g], h_gel[g+1]) form group g
-    int G = 1;
-    std::vector<int> h_gel;
-    std::vector<int64_t> h_boff;
-    DBuf<int> gel;
-    DBuf<double> clq, circ, gridc, ny, nn, nw;
-    DBuf<ElemInfo> info;
-    DBuf<double> cpy[NUP], cpn[NUP], cpw[NUP], Lup[NUP], upx[NUP], upw[NUP];
-    int64_t Mtot[NUP] = {0, 0, 0};
-    // far-field (base) source set
-    int64_t Nb = 0;
-    double mix_near2 = 0.0;   // squared radius of the FP64 near part of the mixed-precision far sum
-    DBuf<int64_t> boff;
-    DBuf<double> by, bn, bw, bsw;
-    // evaluation scratch
-    DBuf<double> sig_d, x_d, usl_d, udl_d;
-    DBuf<int64_t> tn_d;
-    DBuf<double> sw, sh, rnear, xt, part, cls, corr, swf[NUP];
-    DBuf<int> band, cnt, pe, pt, err_d, work, kin, kout, vin, perm, sorted, runs_key, runs_cnt, nruns, wdesc;
-    DBuf<int64_t> off, gstart;
-    DBuf<int> tgroup, tgrp_d, gnchunk;
-    DBuf<FarTile> tiles;
-    DBuf<int8_t> tier;
-    // smooth-sum launch shape, chosen by timing (targets per thread, sources per chunk)
-    int far_tpt = 2;
-    int64_t far_chunk = 16384;
-    uint64_t tuned_key = 0;
-    float tune_ms[6] = {0, 0, 0, 0, 0, 0};
-    // learned gate: inference weights (bf16 MFMA fragments, FP32 biases) and
-    // per-pair scratch
-    bool gate_ready = false;
-    float gate_tau = 0.05f;
-    DBuf<uint16_t> gate_wfrag;
-    DBuf<float> gate_bias, gfeat;
-    DBuf<int8_t> gtier;
-    DBuf<uint8_t> gesc, gflag;
-    DBuf<int> gsel, gnsel;
-    int64_t last_esc = -1;
-    // frozen evaluation plan (pairs, tiers, rules, smooth-sum blocks of the
-    // last evaluation) and its apply sequence captured as a HIP graph
-    struct Plan {
-        bool valid = false;
-        int64_t T = 0;
-        int nwaves[NUP] = {0, 0, 0};   // upsampled-rule wavefronts per tier
-        int nw_up = 0;                 // all of them, in the one launch
-        int nfull = 0, full_start = 0, mt_max = 0, ntiles = 0, tpt = 2;
-        bool mixed = false;
-        const int64_t* tn = nullptr;
-        hipStream_t gst = nullptr;
-        hipGraph_t graph = nullptr;
-        hipGraphExec_t exec = nullptr;
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-    } plan;
-    DBuf<int> band_apply;
-    int last_ntiles = 0;
-    int64_t last_far_pairs = 0;   // source-target pairs of the last smooth sum
-    // host copies of the smooth-sum block list outlive the asynchronous uploads
-    std::vector<FarTile> h_tiles;
-    std::vector<int> h_gnc;
-    DBuf<unsigned char> cub_tmp;
-    // statistics of the last evaluation
-    Phase ph[kNPhase];
-    bool ph_ok = false;
-    int64_t last_T = 0, last_P = 0, last_nup[NUP] = {0, 0, 0}, last_nf = 0;
-    int last_err_flags = 0;
-    bool flags_pending = false;   // device-mode call: the final flags are still on the device
-
-    int fail(int code, const std::string& msg)
-    {
-        err = msg;
-        return code;
-    }
-};
 
 static void plan_drop(csbq_ctx* ctx);
 
@@ -250,25 +122,6 @@ static_assert(CSBQ_FLAG_NODE_RANGE == FLAG_NODE_RANGE && CSBQ_FLAG_SRULE_LIMIT =
                   CSBQ_FLAG_GROUP_ORDER == FLAG_GROUP_ORDER && CSBQ_FLAG_BAND == FLAG_BAND,
               "flag bits of the C ABI and the kernels");
 
-#define HIPC(call)                                                                             \
-    do {                                                                                       \
-        hipError_t e_ = (call);                                                                \
-        if (e_ != hipSuccess)                                                                  \
-            return ctx->fail(CSBQ_EHIP, std::string(#call " failed: ") + hipGetErrorString(e_)); \
-    } while (0)
-#define ALLOC(buf, n)                                                                 \
-    do {                                                                              \
-        if ((buf).ensure(n) != hipSuccess) {                                          \
-            (void)hipGetLastError();                                                  \
-            return ctx->fail(CSBQ_ENOMEM, "device allocation failed: " #buf);         \
-        }                                                                             \
-    } while (0)
-#define LCHK(call)                                                                                  \
-    do {                                                                                            \
-        int r_ = (call);                                                                            \
-        if (r_) return ctx->fail(CSBQ_EHIP, std::string(#call " failed: ") +                        \
-                                                hipGetErrorString((hipError_t)r_));                \
-    } while (0)
 
 extern "C" {
 
@@ -282,6 +135,7 @@ void csbq_default_options(csbq_options* opt)
     opt->device = 0;
     opt->stream = nullptr;
     opt->table_dir = nullptr;
+    opt->kernel = CSBQ_KERNEL_STOKES;
 }
 
 const char* csbq_last_error(const csbq_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
@@ -376,6 +230,15 @@ int csbq_create(const csbq_options* opt, csbq_ctx** out)
         delete ctx;
         return CSBQ_EINVAL;
     }
+    // the Laplace layers run in FP64 under the error-estimate criterion (the
+    // mixed-precision sum and the learned gate are built for the Stokes pair)
+    if ((ctx->opt.kernel != CSBQ_KERNEL_STOKES && ctx->opt.kernel != CSBQ_KERNEL_LAPLACE) ||
+        (ctx->opt.kernel == CSBQ_KERNEL_LAPLACE &&
+         (ctx->opt.precision != CSBQ_FP64 || ctx->opt.gate != CSBQ_GATE_CRITERION))) {
+        delete ctx;
+        return CSBQ_EINVAL;
+    }
+    ctx->ker = ctx->opt.kernel == CSBQ_KERNEL_LAPLACE ? KER_LAPLACE : KER_STOKES;
     ctx->table_dir = ctx->opt.table_dir ? std::string(ctx->opt.table_dir) : default_table_dir();
     ctx->opt.table_dir = nullptr;
     int ndev = 0;
@@ -523,10 +386,10 @@ int csbq_synchronize(csbq_ctx* ctx)
 int csbq_eval_flags(csbq_ctx* ctx, int32_t* flags)
 {
     if (!ctx || !flags) return CSBQ_EINVAL;
-    if (ctx->flags_pending && ctx->err_d.p) {
+    if (ctx->flags_pending && ctx->flags_src) {
         int f = 0;
         HIPC(hipSetDevice(ctx->opt.device));
-        HIPC(hipMemcpyAsync(&f, ctx->err_d.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+        HIPC(hipMemcpyAsync(&f, ctx->flags_src, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
         HIPC(hipStreamSynchronize(ctx->stream));
         ctx->last_err_flags = f;
         ctx->flags_pending = false;
@@ -643,6 +506,9 @@ int csbq_set_geometry_batch(csbq_ctx* ctx, int32_t n_bodies, const int32_t* body
     if ((rc = to_device(ctx, ctx->gel, gel.data(), (size_t)G + 1, CSBQ_HOST))) return rc;
     ctx->G = G;
     ctx->h_gel = gel;
+    ctx->n_bodies = n_bodies;
+    ctx->h_body_off.assign((size_t)n_bodies + 1, 0);
+    for (int b = 0; b < n_bodies; ++b) ctx->h_body_off[b + 1] = ctx->h_body_off[b] + (int64_t)np[b] * NPE;
     ctx->tuned_key = 0;
     ALLOC(ctx->clq, (size_t)E * CLQ * NS);
     ALLOC(ctx->circ, (size_t)E * NCIRC * CIRQ);
@@ -744,8 +610,9 @@ static int eval_front(csbq_ctx* ctx, const double* sigma, int64_t T, const doubl
     if (mem != CSBQ_HOST && mem != CSBQ_DEVICE) return ctx->fail(CSBQ_EINVAL, "bad mem flag");
     if (T > (int64_t)INT32_MAX) return ctx->fail(CSBQ_EINVAL, "too many targets");
     const int64_t N = ctx->N;
+    const int nc = ctx->nc();
     if (mem == CSBQ_HOST) {
-        for (int64_t i = 0; i < N * 3; ++i)
+        for (int64_t i = 0; i < N * nc; ++i)
             if (!std::isfinite(sigma[i])) return ctx->fail(CSBQ_EINVAL, "density has NaN/Inf");
         if (tgt_node)
             for (int64_t t = 0; t < T; ++t)
@@ -759,7 +626,14 @@ static int eval_front(csbq_ctx* ctx, const double* sigma, int64_t T, const doubl
             for (int64_t t = 0; t < T; ++t)
                 if (tgt_node[t] < 0) return ctx->fail(CSBQ_EINVAL, "free target without coordinates");
         int rc;
-        if ((rc = to_device(ctx, ctx->sig_d, sigma, (size_t)N * 3, CSBQ_HOST))) return rc;
+        if (nc == 3) {
+            if ((rc = to_device(ctx, ctx->sig_d, sigma, (size_t)N * 3, CSBQ_HOST))) return rc;
+        } else {
+            // the scalar (Laplace) density into the first of three components
+            if ((rc = to_device(ctx, ctx->sig1, sigma, (size_t)N, CSBQ_HOST))) return rc;
+            ALLOC(ctx->sig_d, (size_t)N * 3);
+            LCHK(launch_scalar_to_vec(ctx->stream, N, ctx->sig1.p, ctx->sig_d.p));
+        }
         *sig_dev = ctx->sig_d.p;
         if (x) {
             if ((rc = to_device(ctx, ctx->x_d, x, (size_t)T * 3, CSBQ_HOST))) return rc;
@@ -775,8 +649,12 @@ static int eval_front(csbq_ctx* ctx, const double* sigma, int64_t T, const doubl
             if ((rc = to_device(ctx, ctx->tgrp_d, tgt_group, (size_t)T, CSBQ_HOST))) return rc;
             tgt_group = ctx->tgrp_d.p;
         }
-    } else {
+    } else if (nc == 3) {
         *sig_dev = sigma;
+    } else {
+        ALLOC(ctx->sig_d, (size_t)N * 3);
+        LCHK(launch_scalar_to_vec(ctx->stream, N, sigma, ctx->sig_d.p));
+        *sig_dev = ctx->sig_d.p;
     }
     *tn_dev = tgt_node;
     ALLOC(ctx->err_d, 1);
@@ -791,8 +669,10 @@ static int eval_front(csbq_ctx* ctx, const double* sigma, int64_t T, const doubl
     ALLOC(ctx->sh, (size_t)E * NS * NSH);
     ALLOC(ctx->band, (size_t)E * 2);
     ALLOC(ctx->rnear, (size_t)E);
+    // (a negative threshold asks for the full band: see csbq_ctx::full_band)
     LCHK(launch_prep_sigma(ctx->stream, E, *sig_dev, ctx->nw.p, N, ctx->sw.p, ctx->sh.p, ctx->band.p,
-                           0.1 * ctx->gc.tol, ctx->info.p, ctx->circ.p, ctx->gc, ctx->rnear.p));
+                           ctx->full_band ? -1.0 : 0.1 * ctx->gc.tol, ctx->info.p, ctx->circ.p, ctx->gc,
+                           ctx->rnear.p));
     return CSBQ_OK;
 }
 
@@ -947,7 +827,7 @@ static int tune_far(csbq_ctx* ctx, int64_t T, const std::vector<int64_t>& tr, bo
         ALLOC(ctx->part, (size_t)std::max(maxch, 1) * 6 * T + 1);
         HIPC(hipEventRecord(a, ctx->stream));
         LCHK(launch_far(ctx->stream, T, ctx->xt.p, sy, sn, ss, Ns, ctx->tiles.p, (int)tl.size(), ctx->part.p, mixed,
-                        ctx->mix_near2, tpt));
+                        ctx->mix_near2, tpt, ctx->ker));
         HIPC(hipEventRecord(b, ctx->stream));
         HIPC(hipEventSynchronize(b));
         float ms = 0.f;
@@ -989,7 +869,7 @@ static int far_sum(csbq_ctx* ctx, int64_t T, bool native, const std::vector<int6
     HIPC(hipMemcpyAsync(ctx->gnchunk.p, gnc.data(), gnc.size() * sizeof(int), hipMemcpyHostToDevice, st));
     if (T > 0)
         LCHK(launch_far(st, T, ctx->xt.p, sy, sn, ss, Ns, ctx->tiles.p, (int)tl.size(), ctx->part.p, mixed,
-                        ctx->mix_near2, ctx->far_tpt));
+                        ctx->mix_near2, ctx->far_tpt, ctx->ker));
     ctx->last_ntiles = (int)tl.size();
     ctx->last_far_pairs = 0;
     for (const auto& t : tl) ctx->last_far_pairs += (int64_t)t.tn * t.sn;
@@ -1029,9 +909,11 @@ static int finish(csbq_ctx* ctx, int64_t T, double* u_sl, double* u_dl, int mem)
 {
     int flags = 0;
     ctx->flags_pending = mem == CSBQ_DEVICE;
+    ctx->flags_src = ctx->err_d.p;
     if (mem == CSBQ_HOST) {
-        if (u_sl && T) HIPC(hipMemcpyAsync(u_sl, ctx->usl_d.p, (size_t)T * 3 * 8, hipMemcpyDeviceToHost, ctx->stream));
-        if (u_dl && T) HIPC(hipMemcpyAsync(u_dl, ctx->udl_d.p, (size_t)T * 3 * 8, hipMemcpyDeviceToHost, ctx->stream));
+        const size_t ob = (size_t)T * ctx->nc() * 8;
+        if (u_sl && T) HIPC(hipMemcpyAsync(u_sl, ctx->usl_d.p, ob, hipMemcpyDeviceToHost, ctx->stream));
+        if (u_dl && T) HIPC(hipMemcpyAsync(u_dl, ctx->udl_d.p, ob, hipMemcpyDeviceToHost, ctx->stream));
         HIPC(hipMemcpyAsync(&flags, ctx->err_d.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
         HIPC(hipStreamSynchronize(ctx->stream));
         ctx->last_err_flags = flags;
@@ -1063,7 +945,7 @@ int csbq_smooth_sum(csbq_ctx* ctx, const double* sigma, int64_t T, const double*
     double *usl, *udl;
     if ((rc = outputs_back(ctx, T, u_sl, u_dl, mem, &usl, &udl))) return rc;
     LCHK(launch_reduce(ctx->stream, T, ctx->tgroup.p, ctx->gnchunk.p, ctx->part.p, nullptr, nullptr, nullptr, usl,
-                       udl));
+                       udl, ctx->ker));
     return finish(ctx, T, u_sl, u_dl, mem);
 }
 
@@ -1274,7 +1156,7 @@ int csbq_eval_batch(csbq_ctx* ctx, const double* sigma, int64_t T, const double*
                              ctx->Mtot[ti]));
     }
     LCHK(launch_corr_up(st, up_rules(ctx), nw_up, ctx->wdesc.p, ctx->sorted.p, ctx->pt.p, ctx->xt.p, T, ctx->info.p,
-                        ctx->boff.p, ctx->by.p, ctx->bn.p, ctx->bsw.p, ctx->Nb, ctx->corr.p));
+                        ctx->boff.p, ctx->by.p, ctx->bn.p, ctx->bsw.p, ctx->Nb, ctx->corr.p, ctx->ker));
     HIPC(hipEventRecord(ctx->ph[5].b, st));
     // special quadrature corrections
     HIPC(hipEventRecord(ctx->ph[6].a, st));
@@ -1282,14 +1164,14 @@ int csbq_eval_batch(csbq_ctx* ctx, const double* sigma, int64_t T, const double*
     LCHK(launch_corr_full(st, nfull, ctx->sorted.p + full_start, ctx->pe.p, ctx->pt.p, ctx->xt.p, T, tn, ctx->clq.p, ctx->sh.p,
                           ctx->info.p, ctx->band.p, ctx->cls.p, ctx->boff.p, ctx->by.p, ctx->bn.p, ctx->bsw.p, ctx->Nb, ctx->roff.p,
                           ctx->rth.p, ctx->rw.p, ctx->nb, ctx->lx.p, ctx->lw.p, ctx->nl, ctx->rcs.p, ctx->rsn.p,
-                          ctx->romc.p, ctx->gc, ctx->corr.p, ctx->err_d.p, ctx->work.p, mt_max));
+                          ctx->romc.p, ctx->gc, ctx->corr.p, ctx->err_d.p, ctx->work.p, mt_max, ctx->ker));
     HIPC(hipEventRecord(ctx->ph[6].b, st));
     // reduction
     HIPC(hipEventRecord(ctx->ph[7].a, st));
     double *usl, *udl;
     if ((rc = outputs_back(ctx, T, u_sl, u_dl, mem, &usl, &udl))) return rc;
     LCHK(launch_reduce(st, T, ctx->tgroup.p, ctx->gnchunk.p, ctx->part.p, ctx->off.p, ctx->tier.p, ctx->corr.p, usl,
-                       udl));
+                       udl, ctx->ker));
     HIPC(hipEventRecord(ctx->ph[7].b, st));
     ctx->last_T = T;
     ctx->last_P = P;
@@ -1323,6 +1205,7 @@ static int enqueue_apply(csbq_ctx* ctx, hipStream_t st)
     const int E = ctx->E;
     const int64_t N = ctx->N, T = pl.T;
     LCHK(launch_fill_i32(st, 1, ctx->err_d.p, 0));
+    if (ctx->nc() == 1) LCHK(launch_scalar_to_vec(st, N, ctx->sig1.p, ctx->sig_d.p));
     LCHK(launch_prep_sigma(st, E, ctx->sig_d.p, ctx->nw.p, N, ctx->sw.p, ctx->sh.p, ctx->band_apply.p,
                            0.1 * ctx->gc.tol, ctx->info.p, ctx->circ.p, ctx->gc, nullptr));
     LCHK(launch_band_check(st, E, ctx->band_apply.p, ctx->band.p, ctx->err_d.p));
@@ -1331,34 +1214,130 @@ static int enqueue_apply(csbq_ctx* ctx, hipStream_t st)
     LCHK(launch_sigma_base(st, E, ctx->info.p, ctx->boff.p, ctx->sw.p, N, ctx->swf[0].p, ctx->Mtot[0], ctx->bsw.p,
                            ctx->Nb));
     LCHK(launch_far(st, T, ctx->xt.p, ctx->by.p, ctx->bn.p, ctx->bsw.p, ctx->Nb, ctx->tiles.p, pl.ntiles, ctx->part.p,
-                    pl.mixed, ctx->mix_near2, pl.tpt));
+                    pl.mixed, ctx->mix_near2, pl.tpt, ctx->ker));
     for (int ti = 1; ti < NUP; ++ti)
         if (pl.nwaves[ti])
             LCHK(launch_sigma_up(st, E, up_ns(ti), up_nt(ti), ctx->sh.p, ctx->Lup[ti].p, ctx->cpw[ti].p,
                                  ctx->swf[ti].p, ctx->Mtot[ti]));
     LCHK(launch_corr_up(st, up_rules(ctx), pl.nw_up, ctx->wdesc.p, ctx->sorted.p, ctx->pt.p, ctx->xt.p, T,
-                        ctx->info.p, ctx->boff.p, ctx->by.p, ctx->bn.p, ctx->bsw.p, ctx->Nb, ctx->corr.p));
+                        ctx->info.p, ctx->boff.p, ctx->by.p, ctx->bn.p, ctx->bsw.p, ctx->Nb, ctx->corr.p, ctx->ker));
+    if (pl.matrix)
+        LCHK(launch_emat_apply(st, pl.nfull, ctx->sorted.p + pl.full_start, ctx->pe.p, ctx->emat.p, ctx->sh.p,
+                               ctx->corr.p));
+    else
     LCHK(launch_corr_full(st, pl.nfull, ctx->sorted.p + pl.full_start, ctx->pe.p, ctx->pt.p, ctx->xt.p, T, pl.tn,
                           ctx->clq.p, ctx->sh.p, ctx->info.p, ctx->band.p, ctx->cls.p, ctx->boff.p, ctx->by.p,
                           ctx->bn.p, ctx->bsw.p, ctx->Nb, ctx->roff.p, ctx->rth.p, ctx->rw.p, ctx->nb, ctx->lx.p,
                           ctx->lw.p, ctx->nl, ctx->rcs.p, ctx->rsn.p, ctx->romc.p, ctx->gc, ctx->corr.p, ctx->err_d.p,
-                          ctx->work.p, pl.mt_max));
+                          ctx->work.p, pl.mt_max, ctx->ker));
     LCHK(launch_reduce(st, T, ctx->tgroup.p, ctx->gnchunk.p, ctx->part.p, ctx->off.p, ctx->tier.p, ctx->corr.p,
-                       ctx->usl_d.p, ctx->udl_d.p));
+                       ctx->usl_d.p, ctx->udl_d.p, ctx->ker));
+    return CSBQ_OK;
+}
+
+// The correction matrices of the plan's special-quadrature pairs (Section
+// 3.2.1: the corrected rule's E for those pairs), in the density's
+// coefficient basis: rows counted per pair, then built in chunks of pairs
+// whose rows fit a bounded scratch, each chunk's rows assembled into the
+// pairs' matrices.
+static int build_matrix(csbq_ctx* ctx)
+{
+    auto& pl = ctx->plan;
+    hipStream_t st = ctx->stream;
+    const int nfull = pl.nfull;
+    pl.matrix = false;
+    if (ctx->ker != KER_STOKES) return ctx->fail(CSBQ_EINVAL, "the correction matrix is built for the Stokes layers");
+    const double bytes = (double)nfull * EMAT_DOUBLES * 8.0;
+    if (bytes > 160e9) return ctx->fail(CSBQ_ELIMIT, "correction matrices beyond 160 GB: plan fewer targets");
+    hipEvent_t a, b;
+    HIPC(hipEventCreate(&a));
+    HIPC(hipEventCreate(&b));
+    HIPC(hipEventRecord(a, st));
+    ALLOC(ctx->emat, (size_t)nfull * EMAT_DOUBLES + 1);
+    DBuf<int> cnt;
+    DBuf<int64_t> roff;
+    DBuf<double> V, L;
+    if (nfull > 0) {
+        const int* listf = ctx->sorted.p + pl.full_start;
+        ALLOC(cnt, (size_t)nfull);
+        ALLOC(ctx->work, (size_t)4 * nfull + 4);
+        MatrixRows mr{nullptr, nullptr, nullptr, cnt.p, ctx->Lup[0].p, ctx->bw.p};
+        auto corr_launch = [&](int n, const int* lf, int mode) {
+            return launch_corr_full(st, n, lf, ctx->pe.p, ctx->pt.p, ctx->xt.p, pl.T, pl.tn, ctx->clq.p, ctx->sh.p,
+                                    ctx->info.p, ctx->band.p, ctx->cls.p, ctx->boff.p, ctx->by.p, ctx->bn.p,
+                                    ctx->bsw.p, ctx->Nb, ctx->roff.p, ctx->rth.p, ctx->rw.p, ctx->nb, ctx->lx.p,
+                                    ctx->lw.p, ctx->nl, ctx->rcs.p, ctx->rsn.p, ctx->romc.p, ctx->gc, ctx->corr.p,
+                                    ctx->err_d.p, ctx->work.p, pl.mt_max, ctx->ker, mode, &mr);
+        };
+        LCHK(corr_launch(nfull, listf, MODE_COUNT));
+        std::vector<int> hc((size_t)nfull);
+        HIPC(hipMemcpyAsync(hc.data(), cnt.p, hc.size() * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPC(hipStreamSynchronize(st));
+        // chunks of pairs whose rows fit ~3 GB of scratch (3 KB + 128 B a row)
+        const int64_t budget = 3LL << 30, row_bytes = (int64_t)(12 * NT + NS) * 8;
+        const int64_t max_rows = budget / row_bytes;
+        int64_t rows_max_chunk = 0;
+        std::vector<std::pair<int, int>> chunks;
+        for (int p0 = 0; p0 < nfull;) {
+            int64_t rows = 0;
+            int p1 = p0;
+            while (p1 < nfull && (p1 == p0 || rows + hc[p1] <= max_rows)) rows += hc[p1++];
+            chunks.push_back({p0, p1});
+            rows_max_chunk = std::max(rows_max_chunk, rows);
+            p0 = p1;
+        }
+        ALLOC(V, (size_t)rows_max_chunk * 12 * NT);
+        ALLOC(L, (size_t)rows_max_chunk * NS);
+        int max_pairs = 0;
+        for (auto& c : chunks) max_pairs = std::max(max_pairs, c.second - c.first);
+        ALLOC(roff, (size_t)max_pairs + 1);
+        std::vector<int64_t> ho((size_t)max_pairs + 1);
+        for (auto& c : chunks) {
+            const int n = c.second - c.first;
+            ho[0] = 0;
+            for (int k = 0; k < n; ++k) ho[k + 1] = ho[k] + hc[c.first + k];
+            HIPC(hipMemcpyAsync(roff.p, ho.data(), ((size_t)n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
+            mr = MatrixRows{roff.p, V.p, L.p, nullptr, ctx->Lup[0].p, ctx->bw.p};
+            LCHK(corr_launch(n, listf + c.first, MODE_MATRIX));
+            LCHK(launch_emat(st, n, roff.p, V.p, L.p, c.first, ctx->emat.p));
+            HIPC(hipStreamSynchronize(st));   // ho is rewritten for the next chunk
+        }
+    }
+    HIPC(hipEventRecord(b, st));
+    HIPC(hipEventSynchronize(b));
+    HIPC(hipEventElapsedTime(&pl.build_ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    pl.matrix = true;
     return CSBQ_OK;
 }
 
 int csbq_plan(csbq_ctx* ctx, const double* sigma, int64_t T, const double* x, const int64_t* tgt_node,
               const int32_t* tgt_group, double* u_sl, double* u_dl, int mem)
 {
+    return csbq_plan_ex(ctx, sigma, T, x, tgt_node, tgt_group, 0, u_sl, u_dl, mem);
+}
+
+int csbq_plan_ex(csbq_ctx* ctx, const double* sigma, int64_t T, const double* x, const int64_t* tgt_node,
+                 const int32_t* tgt_group, int32_t flags, double* u_sl, double* u_dl, int mem)
+{
     if (!ctx) return CSBQ_EINVAL;
     if (T <= 0) return ctx->fail(CSBQ_EINVAL, "a plan needs targets");
+    if (flags & ~(CSBQ_PLAN_MATRIX | CSBQ_PLAN_FULL_BAND)) return ctx->fail(CSBQ_EINVAL, "unknown plan flags");
+    if ((flags & CSBQ_PLAN_MATRIX) && ctx->ker != KER_STOKES)
+        return ctx->fail(CSBQ_EINVAL, "the correction matrix is built for the Stokes layers");
+    const bool fb_prev = ctx->full_band;
+    ctx->full_band = fb_prev || (flags & CSBQ_PLAN_FULL_BAND);
     int rc = csbq_eval_batch(ctx, sigma, T, x, tgt_node, tgt_group, u_sl, u_dl, mem);
+    ctx->full_band = fb_prev;
     if (rc) return rc;
     auto& pl = ctx->plan;
     hipStream_t st = ctx->stream;
+    pl.matrix = false;
+    pl.build_ms = 0.f;
     // everything the graph reads must live in the context
     ALLOC(ctx->sig_d, (size_t)ctx->N * 3);
+    ALLOC(ctx->sig1, (size_t)ctx->N);
     if (mem == CSBQ_DEVICE && tgt_node) {
         ALLOC(ctx->tn_d, (size_t)T);
         HIPC(hipMemcpyAsync(ctx->tn_d.p, tgt_node, (size_t)T * 8, hipMemcpyDeviceToDevice, st));
@@ -1368,6 +1347,8 @@ int csbq_plan(csbq_ctx* ctx, const double* sigma, int64_t T, const double* x, co
     ALLOC(ctx->udl_d, (size_t)T * 3 + 1);
     ALLOC(ctx->band_apply, (size_t)ctx->E * 2);
     HIPC(hipStreamSynchronize(st));
+    if (flags & CSBQ_PLAN_MATRIX)
+        if ((rc = build_matrix(ctx))) return rc;
     if (!pl.gst) HIPC(hipStreamCreateWithFlags(&pl.gst, hipStreamNonBlocking));
     if (!pl.e0) HIPC(hipEventCreateWithFlags(&pl.e0, hipEventDisableTiming));
     if (!pl.e1) HIPC(hipEventCreateWithFlags(&pl.e1, hipEventDisableTiming));
@@ -1397,10 +1378,11 @@ int csbq_apply(csbq_ctx* ctx, const double* sigma, double* u_sl, double* u_dl, i
     HIPC(hipSetDevice(ctx->opt.device));
     hipStream_t st = ctx->stream;
     const int64_t N = ctx->N, T = pl.T;
+    const int nc = ctx->nc();
     if (mem == CSBQ_HOST)
-        for (int64_t i = 0; i < N * 3; ++i)
+        for (int64_t i = 0; i < N * nc; ++i)
             if (!std::isfinite(sigma[i])) return ctx->fail(CSBQ_EINVAL, "density has NaN/Inf");
-    HIPC(hipMemcpyAsync(ctx->sig_d.p, sigma, (size_t)N * 3 * 8,
+    HIPC(hipMemcpyAsync(nc == 3 ? ctx->sig_d.p : ctx->sig1.p, sigma, (size_t)N * nc * 8,
                         mem == CSBQ_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, st));
     HIPC(hipEventRecord(pl.e0, st));
     HIPC(hipStreamWaitEvent(pl.gst, pl.e0, 0));
@@ -1408,8 +1390,8 @@ int csbq_apply(csbq_ctx* ctx, const double* sigma, double* u_sl, double* u_dl, i
     HIPC(hipEventRecord(pl.e1, pl.gst));
     HIPC(hipStreamWaitEvent(st, pl.e1, 0));
     const hipMemcpyKind k = mem == CSBQ_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
-    if (u_sl) HIPC(hipMemcpyAsync(u_sl, ctx->usl_d.p, (size_t)T * 3 * 8, k, st));
-    if (u_dl) HIPC(hipMemcpyAsync(u_dl, ctx->udl_d.p, (size_t)T * 3 * 8, k, st));
+    if (u_sl) HIPC(hipMemcpyAsync(u_sl, ctx->usl_d.p, (size_t)T * nc * 8, k, st));
+    if (u_dl) HIPC(hipMemcpyAsync(u_dl, ctx->udl_d.p, (size_t)T * nc * 8, k, st));
     int flags = 0;
     HIPC(hipMemcpyAsync(&flags, ctx->err_d.p, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPC(hipStreamSynchronize(st));
@@ -1597,6 +1579,7 @@ int csbq_gate_dataset(csbq_ctx* ctx, const double* sigma, int64_t T, const doubl
     ctx->err.clear();
     if (!feat_out || !label_out || !n_out || cap <= 0 || !(label_tol > 0) || T <= 0)
         return ctx->fail(CSBQ_EINVAL, "bad arguments");
+    if (ctx->ker != KER_STOKES) return ctx->fail(CSBQ_EINVAL, "gate training data are for the Stokes layers");
     if (ctx->opt.gate != CSBQ_GATE_CRITERION)
         return ctx->fail(CSBQ_ESTATE, "labels are generated with the criterion gate");
     plan_drop(ctx);
@@ -1648,7 +1631,7 @@ int csbq_gate_dataset(csbq_ctx* ctx, const double* sigma, int64_t T, const doubl
         LCHK(launch_sigma_up(st, E, up_ns(ti), up_nt(ti), ctx->sh.p, ctx->Lup[ti].p, ctx->cpw[ti].p, ctx->swf[ti].p,
                              ctx->Mtot[ti]));
         LCHK(launch_corr_up(st, up_rules(ctx), nw, dwd[ti].p, ctx->perm.p, ctx->pt.p, ctx->xt.p, T, ctx->info.p,
-                            ctx->boff.p, ctx->by.p, ctx->bn.p, ctx->bsw.p, ctx->Nb, cup[ti].p));
+                            ctx->boff.p, ctx->by.p, ctx->bn.p, ctx->bsw.p, ctx->Nb, cup[ti].p, ctx->ker));
     }
     ALLOC(cfull, (size_t)P * 6 + 1);
     std::vector<int> hband((size_t)2 * E);
@@ -1659,7 +1642,7 @@ int csbq_gate_dataset(csbq_ctx* ctx, const double* sigma, int64_t T, const doubl
     LCHK(launch_corr_full(st, (int)P, ctx->perm.p, ctx->pe.p, ctx->pt.p, ctx->xt.p, T, tn, ctx->clq.p, ctx->sh.p,
                           ctx->info.p, ctx->band.p, ctx->cls.p, ctx->boff.p, ctx->by.p, ctx->bn.p, ctx->bsw.p,
                           ctx->Nb, ctx->roff.p, ctx->rth.p, ctx->rw.p, ctx->nb, ctx->lx.p, ctx->lw.p, ctx->nl,
-                          ctx->rcs.p, ctx->rsn.p, ctx->romc.p, ctx->gc, cfull.p, ctx->err_d.p, ctx->work.p, mt_max));
+                          ctx->rcs.p, ctx->rsn.p, ctx->romc.p, ctx->gc, cfull.p, ctx->err_d.p, ctx->work.p, mt_max, ctx->ker));
     DBuf<int8_t> lab;
     ALLOC(lab, (size_t)P + 1);
     LCHK(launch_gate_labels(st, P, cup[0].p, cup[1].p, cup[2].p, cfull.p, thr_s, thr_d, lab.p));
@@ -1706,6 +1689,13 @@ int csbq_stats(const csbq_ctx* ctx, char* buf, int64_t cap)
     {
         const size_t sl = ctx->table_path.find_last_of('/');
         s += ", \"theta_rules\": \"" + ctx->table_path.substr(sl == std::string::npos ? 0 : sl + 1) + "\"";
+    }
+    s += ctx->ker == KER_LAPLACE ? ", \"kernel\": \"laplace\"" : ", \"kernel\": \"stokes\"";
+    if (ctx->plan.valid) {
+        std::snprintf(tmp, sizeof tmp, ", \"plan\": {\"matrix\": %s, \"build_ms\": %.3f, \"matrix_bytes\": %lld}",
+                      ctx->plan.matrix ? "true" : "false", ctx->plan.build_ms,
+                      (long long)(ctx->plan.matrix ? (int64_t)ctx->plan.nfull * EMAT_DOUBLES * 8 : 0));
+        s += tmp;
     }
     if (ctx->ph_ok && ctx->last_nf > 0) {
         std::vector<int> wk((size_t)4 * ctx->last_nf);

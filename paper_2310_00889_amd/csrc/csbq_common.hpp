@@ -37,6 +37,10 @@ __host__ __device__ constexpr int up_ns(int k) { return k == 2 ? 64 : 32; }
 __host__ __device__ constexpr int up_nt(int k) { return k == 0 ? 32 : (k == 1 ? 64 : 128); }
 __host__ __device__ constexpr int64_t up_pts(int k) { return (int64_t)up_ns(k) * up_nt(k); }
 
+// kernel pair of an evaluation: the Stokes single and double layers (Section
+// 2) or the Laplace ones (Section 4.1)
+enum : int { KER_STOKES = 0, KER_LAPLACE = 1 };
+
 // bits of the evaluation's device flag word (the C ABI names them CSBQ_FLAG_*)
 enum : int {
     FLAG_NODE_RANGE = 1,    // a target's node id is beyond the node count

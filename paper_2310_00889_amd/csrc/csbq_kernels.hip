@@ -127,6 +127,49 @@ __device__ __forceinline__ void pair_scaled(const double x[3], double2 A, double
     sd[2] = fma(cD, r2, sd[2]);
 }
 
+// The Laplace pair (Section 4.1: G = 1/(4 pi |r|) and its normal derivative
+// (r.n)/(4 pi |r|^3)) on the scalar density held in the record's first
+// component: sa[0] += q (sigma w), sd[0] += q^3 (r.n)(sigma w), i.e. 2 and 8
+// times the single and double layers' terms (the 1/(4 pi) is applied last).
+__device__ __forceinline__ void pair_scaled_lap(const double x[3], double2 A, double2 B, double2 C, double2 D,
+                                                double sa[3], double sd[3])
+{
+    const double r0 = x[0] - A.x, r1 = x[1] - A.y, r2 = x[2] - B.x;
+    const double rr = fma(r0, r0, fma(r1, r1, r2 * r2));
+    const double q = rsqrt2_or_zero(rr);
+    const double rn = fma(r0, B.y, fma(r1, C.x, r2 * C.y));
+    const double qw = q * D.x;
+    sa[0] += qw;
+    sd[0] = fma(rn * qw, q * q, sd[0]);
+}
+
+template <int KER>
+__device__ __forceinline__ void pair_acc(const double x[3], double2 A, double2 B, double2 C, double2 D, double2 F,
+                                         double sa[3], double sb[3], double sd[3])
+{
+    if constexpr (KER == KER_LAPLACE)
+        pair_scaled_lap(x, A, B, C, D, sa, sd);
+    else
+        pair_scaled(x, A, B, C, D, F, sa, sb, sd);
+}
+
+// the six output slots (S: 0..2, D: 3..5) of the scaled sums; the Laplace
+// layers fill slots 0 and 3 only
+template <int KER>
+__device__ __forceinline__ void scaled_out(const double sa[3], const double sb[3], const double sd[3], double o[6])
+{
+    if constexpr (KER == KER_LAPLACE) {
+        o[0] = 0.5 * sa[0];
+        o[3] = 0.125 * sd[0];
+        o[1] = o[2] = o[4] = o[5] = 0.0;
+    } else {
+        for (int d = 0; d < 3; ++d) {
+            o[d] = fma(0.5, sa[d], 0.125 * sb[d]);
+            o[3 + d] = 0.03125 * sd[d];
+        }
+    }
+}
+
 // interpolate the CLQ centerline quantities of element data clq (layout
 // [CLQ][NS]) at normalised x, then build the frame
 __device__ inline void frame_at_x(const double* __restrict__ clq, double x, Frame& f)
@@ -177,17 +220,21 @@ __device__ inline void bary_weights_rcp(double x, double* l)
 
 __device__ inline void bary_weights_rel_rcp(int i0, double du, double* l)
 {
-    if (du == 0.0) {
-#pragma unroll
-        for (int i = 0; i < NS; ++i) l[i] = (i == i0) ? 1.0 : 0.0;
-        return;
-    }
+    // a node that falls on a GL node (x - x_i == 0 exactly, e.g. the nodes
+    // of a sub-panel that is the whole panel) takes that node's values
+    int hit = -1;
     double sum = 0.0;
 #pragma unroll
     for (int i = 0; i < NS; ++i) {
         const double dx = (i == i0) ? du : (c_gx[i0] - c_gx[i]) + du;
-        l[i] = c_lam[i] * rcp_nr(dx);
+        if (dx == 0.0) hit = i;
+        l[i] = c_lam[i] * rcp_nr(dx == 0.0 ? 1.0 : dx);
         sum += l[i];
+    }
+    if (hit >= 0) {
+#pragma unroll
+        for (int i = 0; i < NS; ++i) l[i] = (i == hit) ? 1.0 : 0.0;
+        return;
     }
     const double is = rcp_nr(sum);
 #pragma unroll
@@ -458,7 +505,8 @@ __global__ void k_base_build(int E, const ElemInfo* __restrict__ info, const int
 // density preparation
 // ---------------------------------------------------------------------------
 // sigma*w (SoA), Fourier coefficients on each GL circle sh[e][i][l][6], and the
-// band limits (highest Legendre degree Ms and Fourier mode Mt above eta).
+// band limits (highest Legendre degree Ms and Fourier mode Mt above eta times
+// the element's largest coefficient; eta < 0: the full band).
 __global__ __launch_bounds__(512) void k_prep_sigma(int E, const double* __restrict__ sigma,
                                                     const double* __restrict__ nw, int64_t N,
                                                     double* __restrict__ sw, double* __restrict__ sh,
@@ -524,6 +572,10 @@ __global__ __launch_bounds__(512) void k_prep_sigma(int E, const double* __restr
             if (amp[k] > eta * ms) Ms = k;
         for (int l = 0; l < NMODE; ++l)
             if (amp[NS + l] > eta * mt) Mt = l;
+        if (eta < 0.0) {   // the widest band any density can have
+            Ms = NS - 1;
+            Mt = NMODE - 1;
+        }
         band[2 * e] = Ms;
         band[2 * e + 1] = Mt;
     }
@@ -649,7 +701,7 @@ constexpr int FAR_REC = 10;     // LDS record of a source (upsampled corrections
 // source's record is read at wave-uniform addresses (scalar loads through the
 // scalar cache, shared by the block's four waves), so it costs no vector
 // memory, LDS or barrier and every load serves 64 TPT pairs.
-template <int TPT>
+template <int TPT, int KER>
 __global__ __launch_bounds__(FAR_BLOCK) void k_far(int64_t T, const double* __restrict__ xt,
                                                    const double* __restrict__ sy, const double* __restrict__ sn,
                                                    const double* __restrict__ ssw, int64_t N,
@@ -675,19 +727,17 @@ __global__ __launch_bounds__(FAR_BLOCK) void k_far(int64_t T, const double* __re
         const double2 A = {sy[k], sy[N + k]}, B = {sy[2 * N + k], sn[k]}, C = {sn[N + k], sn[2 * N + k]},
                       D = {ssw[k], ssw[N + k]}, F = {ssw[2 * N + k], 0.0};
 #pragma unroll
-        for (int u = 0; u < TPT; ++u) pair_scaled(x[u], A, B, C, D, F, sa[u], sb[u], sd[u]);
+        for (int u = 0; u < TPT; ++u) pair_acc<KER>(x[u], A, B, C, D, F, sa[u], sb[u], sd[u]);
     }
     double* p = part + (int64_t)tl.chunk * 6 * T;
 #pragma unroll
     for (int u = 0; u < TPT; ++u) {
         const int64_t t = tb + u * FAR_BLOCK;
         if (t < tend) {
-            p[0 * T + t] = fma(0.5, sa[u][0], 0.125 * sb[u][0]);
-            p[1 * T + t] = fma(0.5, sa[u][1], 0.125 * sb[u][1]);
-            p[2 * T + t] = fma(0.5, sa[u][2], 0.125 * sb[u][2]);
-            p[3 * T + t] = 0.03125 * sd[u][0];
-            p[4 * T + t] = 0.03125 * sd[u][1];
-            p[5 * T + t] = 0.03125 * sd[u][2];
+            double o[6];
+            scaled_out<KER>(sa[u], sb[u], sd[u], o);
+            for (int k = 0; k < 6; ++k)
+                if (KER != KER_LAPLACE || k == 0 || k == 3) p[k * T + t] = o[k];
         }
     }
 }
@@ -1273,6 +1323,7 @@ __global__ void k_tier_keys(int64_t P, int E, const int8_t* __restrict__ tier, c
 static_assert(NUP == 3, "k_corr_up selects among three tiers' rules");
 static_assert(up_ns(1) == up_ns(0) && up_nt(1) == 2 * up_nt(0) && up_nt(0) == NT,
               "the 32 x 64 rule contains the closed-end far-field rule at its even angles");
+template <int KER>
 __global__ __launch_bounds__(64) void k_corr_up(UpRules ur, const int* __restrict__ ws,
                                                 const int* __restrict__ sorted, const int* __restrict__ pt,
                                                 const double* __restrict__ xt, int64_t T,
@@ -1340,7 +1391,7 @@ __global__ __launch_bounds__(64) void k_corr_up(UpRules ur, const int* __restric
                 const double2* r2 = reinterpret_cast<const double2*>(src + kk * FAR_REC);
                 const double2 A = r2[0], B = r2[1], C = r2[2], D = r2[3], F = r2[4];
 #pragma unroll
-                for (int u = 0; u < UP_TPT; ++u) pair_scaled(x[u], A, B, C, D, F, sa[u], sb[u], sd[u]);
+                for (int u = 0; u < UP_TPT; ++u) pair_acc<KER>(x[u], A, B, C, D, F, sa[u], sb[u], sd[u]);
             }
             __syncthreads();
         }
@@ -1348,13 +1399,9 @@ __global__ __launch_bounds__(64) void k_corr_up(UpRules ur, const int* __restric
 #pragma unroll
     for (int u = 0; u < UP_TPT; ++u) {
         if (p[u] >= 0) {
-            double* o = corr + p[u] * 6;
-            o[0] = fma(0.5, sa[u][0], 0.125 * sb[u][0]);
-            o[1] = fma(0.5, sa[u][1], 0.125 * sb[u][1]);
-            o[2] = fma(0.5, sa[u][2], 0.125 * sb[u][2]);
-            o[3] = 0.03125 * sd[u][0];
-            o[4] = 0.03125 * sd[u][1];
-            o[5] = 0.03125 * sd[u][2];
+            double o[6];
+            scaled_out<KER>(sa[u], sb[u], sd[u], o);
+            for (int k = 0; k < 6; ++k) corr[p[u] * 6 + k] = o[k];
         }
     }
 }
@@ -1404,6 +1451,172 @@ enum { R_E = 0, R_EP, R_SP, R_A13, R_A23, R_Z, R_DR, R_T, R_B0 = R_T + 3, R_B0P 
 constexpr int QVS = CLQ + 1;   // row stride of the interpolated centerline quantities
 static_assert(CLQ <= 32, "the centerline interpolation uses two 16-column MFMA tiles");
 
+// Modes of the special-quadrature kernel (MODE_*, csbq_kernels.hpp): the
+// density route (corrections for the given density), the count of its rows
+// per pair, and the rows of the correction matrix in the density's
+// coefficient basis.
+struct MatrixOut {
+    const int64_t* roff;   // first row of each pair (by block), MODE_MATRIX
+    double* V;             // [rows][CORR_NC][NT]: kernel components times basis functions, summed over a node's angles
+    double* L;             // [rows][NS]: interpolation weights of the node from the GL rows
+    int* count;            // [pairs]: rows of each pair, MODE_COUNT
+    const double* lup0;    // [up_ns(0)][NS]: GL rows -> the closed-end far-field rule's rows
+    const double* bw;      // [Nb]: weights of the far-field rule's points
+};
+
+// Correction-matrix rows of one pair (one wavefront).  Row m of the pair is a
+// quadrature node s_m in s (an s-node of the special rule, or a row of the
+// element's far-field rule with negated weights); its entries are
+//   V[m][c][k] = sum over the node's angles q of w_q K_c(x, y(s_m, t_q)) b_k(t_q),
+// K_c the six symmetric components of the single layer (W J (I/|r| +
+// r r^T/|r|^3) up to the constant 1/(8 pi)) and of the double layer (W (r.n)
+// r r^T/|r|^5, up to -3/(4 pi)), b_k the density's trigonometric basis (cos
+// k t for k = 0..16, then sin k t for k = 1..15, at absolute angles t).  With
+// L[m][i] the interpolation weights of s_m from the GL rows, the correction of
+// the density with coefficients sigma^_{i,k} is sum_{m,i,k,c} L[m][i]
+// V[m][c][k] sigma^_{i,k}.  The sums over angles run as FP64 MFMA 16x16x4
+// products: four angles at a time, lane l holding component (l mod 16) of
+// angle l / 16 and basis function (l mod 16) there.
+constexpr int CORR_NC = 12;   // symmetric components: S (xx xy xz yy yz zz), D (same)
+__device__ __forceinline__ void sym_pair(int c, int& a, int& b)
+{
+    const int cc = c % 6;
+    a = cc < 3 ? 0 : (cc < 5 ? 1 : 2);
+    b = cc < 3 ? cc : (cc < 5 ? cc - 2 : 2);
+}
+
+// component `row` (0..11, else 0) of the Stokes kernel pair at r, scaled by the
+// single-layer factor aS = W J / |r| and the double-layer factor cD = W (r.n) / |r|^5
+__device__ __forceinline__ double sym_component(int row, const double r[3], double aS, double ir2, double cD)
+{
+    if (row >= CORR_NC) return 0.0;
+    int a, b;
+    sym_pair(row, a, b);
+    const double rab = r[a] * r[b];
+    return row < 6 ? aS * ((a == b ? 1.0 : 0.0) + ir2 * rab) : cD * rab;
+}
+
+// basis functions of lane column k (0..15) at angle t: cos k t (first block),
+// sin k t (second; cos 16 t in column 0)
+__device__ __forceinline__ void basis_pair(int k, double t, double& b0, double& b1)
+{
+    double sn, cs;
+    sincos((double)(k ? k : NT / 2) * t, &sn, &cs);
+    b0 = k ? cs : 1.0;
+    b1 = k ? sn : cs;
+}
+
+__device__ __forceinline__ void matrix_row_store(const MatrixOut& mo, int64_t row, int lane, v4d acc0, v4d acc1)
+{
+    const int g4 = lane >> 4, k = lane & 15;
+    double* Vr = mo.V + row * (CORR_NC * NT);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {   // rows g4 + 4i < 12 of the MFMA tile
+        const int c = g4 + 4 * i;
+        Vr[c * NT + k] = acc0[i];
+        Vr[c * NT + NT / 2 + k] = acc1[i];
+    }
+}
+
+template <int KER>
+__device__ void matrix_rows_special(int nb, int base, int lane, const double (*rec)[NREC], const int* rq_off,
+                                    const int* rq_step, const int* npt, const double* lwl, const RuleTables& rt,
+                                    double sgn, const MatrixOut& mo)
+{
+    static_assert(KER == KER_STOKES, "the correction matrix is built for the Stokes pair");
+    const int g4 = lane >> 4, col = lane & 15;
+    for (int j = 0; j < nb; ++j) {
+        const double* R = rec[j];
+        const int ro = rq_off[j];
+        const bool trap = ro < 0;
+        const int np_ = npt[j];
+        const double c0 = R[R_C0], s0t = R[R_S0];
+        const double th0 = atan2(s0t, c0);
+        const double E = R[R_E], Ep = R[R_EP], z = R[R_Z], dr = R[R_DR];
+        const double sp_ = R[R_SP], a13 = R[R_A13], a23 = R[R_A23];
+        v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+        for (int q0 = 0; q0 < np_; q0 += 4) {
+            const int q = q0 + g4;
+            double av = 0.0, bv0 = 0.0, bv1 = 0.0;
+            if (q < np_) {
+                double cth, sth, cph, sph, omc, wq, th;
+                if (trap) {
+                    const int ix = q * rq_step[j];
+                    cth = c_cos128[ix];
+                    sth = c_sin128[ix];
+                    th = 2.0 * PI * q / np_;
+                    cph = fma(cth, c0, sth * s0t);
+                    sph = fma(sth, c0, -cth * s0t);
+                    omc = 1.0 - cph;
+                    wq = R[R_WQ];
+                } else {
+                    const int qq = ro + q;
+                    cph = rt.cs[qq];
+                    sph = rt.sn[qq];
+                    omc = rt.omc[qq];
+                    wq = rt.w[qq];
+                    th = th0 + rt.th[qq];
+                    cth = fma(c0, cph, -s0t * sph);
+                    sth = fma(s0t, cph, c0 * sph);
+                }
+                const double W = R[R_W] * wq;
+                const double gq = sp_ + a13 * cth + a23 * sth;
+                const double jq = fma(gq, gq, Ep * Ep);
+                const double J = E * (jq * rsqrt_nr1(jq));
+                const double A = dr + E * omc, B = -E * sph;
+                double r[3];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) r[d] = z * R[R_T + d] + A * R[R_B0 + d] + B * R[R_B0P + d];
+                const double rr = z * z + A * A + B * B;
+                const double ir = rr > 0.0 ? rsqrt_nr1(rr) : 0.0;
+                const double ir2 = ir * ir;
+                const double rn = sgn * E * (gq * (dr * cph - E * omc) - Ep * z);
+                av = sym_component(col, r, W * J * ir, ir2, W * rn * ir2 * ir2 * ir);
+                basis_pair(col, th, bv0, bv1);
+            }
+            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv0, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv1, acc1, 0, 0, 0);
+        }
+        const int64_t row = mo.roff[blockIdx.x] + base + j;
+        matrix_row_store(mo, row, lane, acc0, acc1);
+        if (lane < NS) mo.L[row * NS + lane] = lwl[j * NS + lane];
+    }
+}
+
+// rows of the element's far-field rule (nbrows rows of NT angles at bo..),
+// with negated weights: the rule the smooth sum applied, which the correction
+// replaces (a source at the target itself contributes nothing)
+template <int KER>
+__device__ void matrix_rows_base(int nbrows, int S, int lane, const double x[3], int64_t bo,
+                                 const double* __restrict__ by, const double* __restrict__ bn, int64_t Nb,
+                                 const MatrixOut& mo, bool closed)
+{
+    static_assert(KER == KER_STOKES, "the correction matrix is built for the Stokes pair");
+    const int g4 = lane >> 4, col = lane & 15;
+    for (int rr_ = 0; rr_ < nbrows; ++rr_) {
+        v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+        for (int q0 = 0; q0 < NT; q0 += 4) {
+            const int q = q0 + g4;
+            const int64_t n = bo + (int64_t)rr_ * NT + q;
+            const double r[3] = {x[0] - by[n], x[1] - by[Nb + n], x[2] - by[2 * Nb + n]};
+            const double rr = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+            const double ir = rr > 0.0 ? rsqrt_nr1(rr) : 0.0;
+            const double ir2 = ir * ir;
+            const double w = -mo.bw[n];
+            const double rn = r[0] * bn[n] + r[1] * bn[Nb + n] + r[2] * bn[2 * Nb + n];
+            const double av = sym_component(col, r, w * ir, ir2, w * rn * ir2 * ir2 * ir);
+            double bv0, bv1;
+            basis_pair(col, 2.0 * PI * q / NT, bv0, bv1);
+            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv0, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv1, acc1, 0, 0, 0);
+        }
+        const int64_t row = mo.roff[blockIdx.x] + S + rr_;
+        matrix_row_store(mo, row, lane, acc0, acc1);
+        if (lane < NS) mo.L[row * NS + lane] = closed ? mo.lup0[rr_ * NS + lane] : (lane == rr_ ? 1.0 : 0.0);
+    }
+}
+
+template <int KER, int MODE>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_corr_full(const int* __restrict__ listf, const int* __restrict__ pe,
                                                   const int* __restrict__ pt, const double* __restrict__ xt,
                                                   int64_t T, const int64_t* __restrict__ tnode,
@@ -1414,7 +1627,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
                                                   const double* __restrict__ bn, const double* __restrict__ bsw,
                                                   int64_t Nb, RuleTables rt, GateConsts gc,
                                                   double* __restrict__ corr, int* __restrict__ err,
-                                                  int* __restrict__ work, int cstride)
+                                                  int* __restrict__ work, int cstride, MatrixOut mo)
 {
     // cf: [SB][cstride] density coefficients at the batch's s-nodes, cstride =
     // 6 (largest band + 1) over all elements (dynamic LDS, at least
@@ -1433,7 +1646,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
     __shared__ double sub_lo[MAXSUB], sub_hi[MAXSUB];
     __shared__ int sub_ty[MAXSUB], soff[MAXSUB + 1];
     __shared__ int nsub;
-    __shared__ double f0d[12];   // own-element target: E0, Xp0[3], sp0, t0[3], bn[3]
+    // reference GL node i0 (the target's own node, else the node nearest the
+    // singularity): E0, Xp0[3], sp0, t0[3], then bn[3] (own) or the target's
+    // offset xr[3] = x - x_c(s_i0), and z_ref = xr.t0, k_ref = |xr|^2 - E0^2
+    __shared__ double f0d[16];
     const int lane = threadIdx.x;
     const int64_t p = listf[blockIdx.x];
     const int e = pe[p];
@@ -1455,13 +1671,32 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
     }
     const double* __restrict__ she = sh + (int64_t)e * NS * NSH;
     __syncthreads();
+    // Every s-node and circle is placed relative to a reference GL node i0 of
+    // the element: its parameter as an offset from s_i0 and its centerline
+    // data as differences from the samples there.  Near the target these
+    // offsets are small and keep their relative accuracy, whereas absolute
+    // parameters (rounded to ~1e-16 of s) would move quadrature nodes by a
+    // relative 1e-16 / (distance in s): 2e-9 of the double layer at 1e-7 from
+    // the surface.
     int i0 = 0;
     double s0 = 0.0;
-    if (own) {
-        i0 = (int)((nd % NPE) / NT);
+    {
+        if (own) {
+            i0 = (int)((nd % NPE) / NT);
+        } else {
+            // the GL node nearest the singularity's real part
+            const double xr = (cls[p * 4 + 0] - inf.a) / (0.5 * (inf.c - inf.a)) - 1.0;
+            double best = 1e300;
+            for (int i = 0; i < NS; ++i) {
+                const double dd = fabs(c_gx[i] - xr);
+                if (dd < best) {
+                    best = dd;
+                    i0 = i;
+                }
+            }
+        }
         s0 = 0.5 * (inf.a + inf.c) + 0.5 * (inf.c - inf.a) * c_gx[i0];
         if (lane == 0) {
-            const int j0 = (int)(nd % NT);
             double q0[CLQ];
             for (int k = 0; k < CLQ; ++k) q0[k] = sq[k * NS + i0];
             Frame f0;
@@ -1470,9 +1705,21 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
             for (int d = 0; d < 3; ++d) {
                 f0d[1 + d] = f0.Xp[d];
                 f0d[5 + d] = f0.t[d];
-                f0d[8 + d] = f0.e1[d] * c_cos[j0] + f0.e2[d] * c_sin[j0];
             }
             f0d[4] = f0.sp;
+            if (own) {
+                const int j0 = (int)(nd % NT);
+                for (int d = 0; d < 3; ++d) f0d[8 + d] = f0.e1[d] * c_cos[j0] + f0.e2[d] * c_sin[j0];
+            } else {
+                double xr[3], xx = 0.0;
+                for (int d = 0; d < 3; ++d) {
+                    xr[d] = x[d] - q0[Q_X + d];
+                    f0d[8 + d] = xr[d];
+                    xx += xr[d] * xr[d];
+                }
+                f0d[11] = dot3(xr, f0.t);
+                f0d[12] = xx - f0.E * f0.E;
+            }
         }
     }
     // ---- s-rule: list of sub-panels (lane 0)
@@ -1481,8 +1728,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
         const double a = inf.a, c = inf.c;
         if (own) {
             // dyadic refinement toward s0 down to ~eps/speed, log-singular
-            // panels on both sides of s0 (Section 3.2.4, general form)
-            const double hmin = gc.hmin_fac * sq[Q_E * NS + i0] / cls[p * 4 + 2];
+            // panels on both sides of s0 (Section 3.2.4, general form).  The
+            // panel size is also cut by the density's Fourier band: the
+            // modal Green's function of mode l turns from its log form to
+            // decay at ~eps/l from the circle, so at band Mt the log rule
+            // (p log u + q, degree < 16) must cover eps/(Mt/4) at most (a
+            // density of every mode up to 16 left 1e-6 with eps/speed
+            // panels, 2e-11 with a quarter of that)
+            const double hmin = gc.hmin_fac * sq[Q_E * NS + i0] / cls[p * 4 + 2] * (Mt > 4 ? 4.0 / Mt : 1.0);
             for (int side = 0; side < 2; ++side) {
                 double L = side ? (c - s0) : (s0 - a);
                 int lev = 0;
@@ -1545,6 +1798,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
     __syncthreads();
     const int nsb = nsub;
     const int S = soff[nsb];
+    const int nbrows = inf.fb == 2 ? up_ns(0) : NS;   // rows of the element's far-field rule
+    if constexpr (MODE == MODE_COUNT) {
+        if (lane == 0) mo.count[blockIdx.x] = S + nbrows;
+        return;
+    }
     const double hw = 0.5 * (inf.c - inf.a);
     const double sgn = (double)inf.sign;
     double a0 = 0, a1 = 0, a2 = 0, b0_ = 0, b1_ = 0, b2_ = 0;
@@ -1567,7 +1825,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
             if (ty == SUB_GL) {
                 s = 0.5 * (lo + hi) + 0.5 * (hi - lo) * c_gx[m];
                 ws = 0.5 * (hi - lo) * c_gw[m];
-                u = s - s0;
+                // offset from s_i0 formed from differences (lo - s0 is exact
+                // for nearby sub-panels), not from the rounded absolute s
+                u = own ? s - s0 : (lo - s0) + 0.5 * (hi - lo) * (1.0 + c_gx[m]);
             } else if (ty == SUB_LOG_LO) {
                 u = (hi - lo) * rt.lx[m];
                 s = lo + u;
@@ -1578,10 +1838,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
                 ws = (hi - lo) * rt.lw[m];
             }
             double lw[NS];
-            if (own)
-                bary_weights_rel_rcp(i0, u / hw, lw);
-            else
-                bary_weights_rcp((s - inf.a) / hw - 1.0, lw);
+            bary_weights_rel_rcp(i0, u / hw, lw);
 #pragma unroll
             for (int i = 0; i < NS; ++i) lwl[lane * NS + i] = lw[i];
         }
@@ -1602,10 +1859,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
 #pragma unroll
                 for (int ks = 0; ks < NS / 4; ++ks) {
                     double bv = 0.0;
-                    if (col < CLQ) {
-                        bv = sq[col * NS + 4 * ks + qq];
-                        if (own) bv -= sq[col * NS + i0];
-                    }
+                    if (col < CLQ) bv = sq[col * NS + 4 * ks + qq] - sq[col * NS + i0];
                     acc = __builtin_amdgcn_mfma_f64_16x16x4f64(wa[ks], bv, acc, 0, 0, 0);
                 }
 #pragma unroll
@@ -1620,9 +1874,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
         if (lane < nb) {
             Frame fr;
             CircleLocal cl;
-            if (own) {
+            {
                 double q[CLQ];
-                const double* dq = qv + lane * QVS;   // differences from the own node's samples
+                const double* dq = qv + lane * QVS;   // differences from the reference node's samples
 #pragma unroll
                 for (int k = 0; k < CLQ; ++k) q[k] = sq[k * NS + i0] + dq[k];
                 frame_from_q(q, fr);
@@ -1633,14 +1887,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
                     f0.t[d] = f0d[5 + d];
                 }
                 f0.sp = f0d[4];
-                const double bnv[3] = {f0d[8], f0d[9], f0d[10]};
-                circle_local_rel(fr, f0, bnv, dq, cl);
-            } else {
-                double q[CLQ];
-#pragma unroll
-                for (int k = 0; k < CLQ; ++k) q[k] = qv[lane * QVS + k];
-                frame_from_q(q, fr);
-                circle_local(fr, x, cl);
+                const double v3[3] = {f0d[8], f0d[9], f0d[10]};
+                if (own)
+                    circle_local_rel(fr, f0, v3, dq, cl);
+                else
+                    circle_local_off(fr, f0, v3, f0d[11], f0d[12], dq, cl);
             }
             // theta-rule for this circle (Section 3.2.2): trapezoid of nt, 2nt
             // or 4nt points if the estimate allows, else the bracket's
@@ -1685,6 +1936,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
             npt[lane] = ntr ? ntr : rt.off[rb] - rt.off[rb - 1];
         }
         __syncthreads();
+        if constexpr (MODE == MODE_MATRIX) {
+            matrix_rows_special<KER>(nb, base, lane, rec, rq_off, rq_step, npt, lwl, rt, sgn, mo);
+            __syncthreads();
+            continue;
+        }
         // ---- 2. density coefficients at the batch's s-nodes
         if (lane == 0) {
             pref[0] = 0;
@@ -1787,7 +2043,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
                 omc[0] = omc[1] = om;
             }
             n_theta += 2;
-            // density by Fourier synthesis over the measured band
+            // density by Fourier synthesis over the measured band (the
+            // Laplace layers' scalar density is component 0)
+            constexpr int NC = KER == KER_LAPLACE ? 1 : 3;
             const double* C = cf + j * cstride;
             double Ce[3] = {C[0], C[1], C[2]}, Co[3] = {0.0, 0.0, 0.0}, Se[3] = {0.0, 0.0, 0.0},
                    So[3] = {0.0, 0.0, 0.0};
@@ -1796,7 +2054,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
             for (; l + 1 <= Mt; l += 2) {
                 const double* Cl = C + 6 * l;
 #pragma unroll
-                for (int d = 0; d < 3; ++d) {
+                for (int d = 0; d < NC; ++d) {
                     Co[d] = fma(Cl[d], cl, Co[d]);
                     So[d] = fma(Cl[3 + d], sl, So[d]);
                 }
@@ -1804,7 +2062,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
                 sl = fma(sl, ca, cl * sa);
                 cl = cn;
 #pragma unroll
-                for (int d = 0; d < 3; ++d) {
+                for (int d = 0; d < NC; ++d) {
                     Ce[d] = fma(Cl[6 + d], cl, Ce[d]);
                     Se[d] = fma(Cl[9 + d], sl, Se[d]);
                 }
@@ -1815,14 +2073,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
             if (l <= Mt) {
                 const double* Cl = C + 6 * l;
 #pragma unroll
-                for (int d = 0; d < 3; ++d) {
+                for (int d = 0; d < NC; ++d) {
                     Co[d] = fma(Cl[d], cl, Co[d]);
                     So[d] = fma(Cl[3 + d], sl, So[d]);
                 }
             }
             double v[2][3];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
+            for (int d = 0; d < NC; ++d) {
                 v[0][d] = (Ce[d] + Co[d]) + (Se[d] + So[d]);
                 v[1][d] = trap ? (Ce[d] + Se[d]) - (Co[d] + So[d]) : (Ce[d] + Co[d]) - (Se[d] + So[d]);
             }
@@ -1848,22 +2106,32 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
                 const double rr = z * z + A * A + B * B;
                 const double ir = rr > 0.0 ? rsqrt_nr1(rr) : 0.0;
                 const double ir2 = ir * ir;
-                const double rs = r[0] * v[u][0] + r[1] * v[u][1] + r[2] * v[u][2];
                 const double rn = sgn * E * (gq * (dr * cph[u] - E * omc[u]) - Ep * z);
-                const double aS = W * J * ir, bS = aS * rs * ir2;
-                const double cD = W * rn * rs * ir2 * ir2 * ir;
-                a0 += aS * v[u][0] + bS * r[0];
-                a1 += aS * v[u][1] + bS * r[1];
-                a2 += aS * v[u][2] + bS * r[2];
-                b0_ += cD * r[0];
-                b1_ += cD * r[1];
-                b2_ += cD * r[2];
+                const double aS = W * J * ir;
+                if constexpr (KER == KER_LAPLACE) {
+                    a0 = fma(aS, v[u][0], a0);
+                    b0_ = fma(W * rn * ir * ir2, v[u][0], b0_);
+                } else {
+                    const double rs = r[0] * v[u][0] + r[1] * v[u][1] + r[2] * v[u][2];
+                    const double bS = aS * rs * ir2;
+                    const double cD = W * rn * rs * ir2 * ir2 * ir;
+                    a0 += aS * v[u][0] + bS * r[0];
+                    a1 += aS * v[u][1] + bS * r[1];
+                    a2 += aS * v[u][2] + bS * r[2];
+                    b0_ += cD * r[0];
+                    b1_ += cD * r[1];
+                    b2_ += cD * r[2];
+                }
             }
         }
         __syncthreads();
     }
-    // minus the element's far-field (base) rule (self term zero)
     const int64_t bo = boff[e], bc = boff[e + 1] - boff[e];
+    if constexpr (MODE == MODE_MATRIX) {
+        matrix_rows_base<KER>(nbrows, S, lane, x, bo, by, bn, Nb, mo, inf.fb == 2);
+        return;
+    }
+    // minus the element's far-field (base) rule (self term zero)
     for (int64_t k = lane; k < bc; k += 64) {
         int64_t n = bo + k;
         double r0 = x[0] - by[n], r1 = x[1] - by[Nb + n], r2 = x[2] - by[2 * Nb + n];
@@ -1871,16 +2139,21 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
         double ir = rr > 0.0 ? rsqrt_nr1(rr) : 0.0;
         double ir2 = ir * ir;
         double w0 = bsw[n], w1 = bsw[Nb + n], w2 = bsw[2 * Nb + n];
-        double rs = r0 * w0 + r1 * w1 + r2 * w2;
         double rn = r0 * bn[n] + r1 * bn[Nb + n] + r2 * bn[2 * Nb + n];
-        double b = rs * ir * ir2;
-        double cD = rn * rs * ir2 * ir2 * ir;
-        a0 -= ir * w0 + b * r0;
-        a1 -= ir * w1 + b * r1;
-        a2 -= ir * w2 + b * r2;
-        b0_ -= cD * r0;
-        b1_ -= cD * r1;
-        b2_ -= cD * r2;
+        if constexpr (KER == KER_LAPLACE) {
+            a0 -= ir * w0;
+            b0_ -= rn * w0 * ir * ir2;
+        } else {
+            double rs = r0 * w0 + r1 * w1 + r2 * w2;
+            double b = rs * ir * ir2;
+            double cD = rn * rs * ir2 * ir2 * ir;
+            a0 -= ir * w0 + b * r0;
+            a1 -= ir * w1 + b * r1;
+            a2 -= ir * w2 + b * r2;
+            b0_ -= cD * r0;
+            b1_ -= cD * r1;
+            b2_ -= cD * r2;
+        }
     }
     a0 = wave_sum(a0);
     a1 = wave_sum(a1);
@@ -1905,30 +2178,129 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
 }
 
 // ---------------------------------------------------------------------------
+// correction matrix: assembly from the rows, and its application
+// ---------------------------------------------------------------------------
+// E[p][c][i][k] = sum over the pair's rows m of L[m][i] V[m][c][k]: a
+// [NS x rows] . [rows x CORR_NC NT] product per pair as FP64 MFMA 16x16x4
+// tiles (four wavefronts per pair, six 16-column tiles each).
+constexpr int EMAT = CORR_NC * NS * NT;   // doubles of one pair's matrix
+__global__ __launch_bounds__(256) void k_emat(int npairs, const int64_t* __restrict__ roff,
+                                              const double* __restrict__ V, const double* __restrict__ L,
+                                              int64_t p0, double* __restrict__ Em)
+{
+    const int p = blockIdx.x;
+    if (p >= npairs) return;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r = lane & 15, qq = lane >> 4;
+    const int64_t m0 = roff[p], m1 = roff[p + 1];
+    constexpr int TPW = CORR_NC * NT / 16 / 4;   // column tiles per wavefront
+    v4d acc[TPW];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int64_t m = m0; m < m1; m += 4) {
+        const int64_t mm = m + qq;
+        const bool ok = mm < m1;
+        const double a = ok ? L[mm * NS + r] : 0.0;   // A = L^T: lane holds L[m + l/16][l mod 16]
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) {
+            const int colt = (wv * TPW + t) * 16 + r;
+            const double b = ok ? V[mm * (CORR_NC * NT) + colt] : 0.0;
+            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+        }
+    }
+    double* E = Em + (p0 + p) * (int64_t)EMAT;
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+        const int colt = (wv * TPW + t) * 16 + r;   // column (c, k) = c * NT + k
+        const int c = colt / NT, k = colt % NT;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int i = qq + 4 * j;
+            E[(c * NS + i) * NT + k] = acc[t][j];
+        }
+    }
+}
+
+// corrections of the pairs from their matrices and the density's GL-circle
+// Fourier coefficients (sh: a_l at 6 l + d, b_l at 6 l + 3 + d): one wavefront
+// per pair, eight (row, basis function) slots per lane; the matrix is read
+// once, coalesced (bandwidth bound)
+__global__ __launch_bounds__(64) void k_emat_apply(int npairs, const int* __restrict__ listf,
+                                                   const int* __restrict__ pe, const double* __restrict__ Em,
+                                                   const double* __restrict__ sh, double* __restrict__ corr)
+{
+    const int w = blockIdx.x, lane = threadIdx.x;
+    if (w >= npairs) return;
+    const int64_t p = listf[w];
+    const double* E = Em + (int64_t)w * EMAT;
+    const double* she = sh + (int64_t)pe[p] * NS * NSH;
+    double o[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll 2
+    for (int sl = lane; sl < NS * NT; sl += 64) {
+        const int i = sl / NT, k = sl % NT;
+        const int off = k < NT / 2 ? 6 * k : (k == NT / 2 ? 6 * (NT / 2) : 6 * (k - NT / 2) + 3);
+        const double s0 = she[i * NSH + off], s1 = she[i * NSH + off + 1], s2 = she[i * NSH + off + 2];
+        double e[CORR_NC];
+#pragma unroll
+        for (int c = 0; c < CORR_NC; ++c) e[c] = E[c * (NS * NT) + sl];
+        // symmetric S (xx xy xz yy yz zz) and D blocks times (s0 s1 s2)
+        o[0] += e[0] * s0 + e[1] * s1 + e[2] * s2;
+        o[1] += e[1] * s0 + e[3] * s1 + e[4] * s2;
+        o[2] += e[2] * s0 + e[4] * s1 + e[5] * s2;
+        o[3] += e[6] * s0 + e[7] * s1 + e[8] * s2;
+        o[4] += e[7] * s0 + e[9] * s1 + e[10] * s2;
+        o[5] += e[8] * s0 + e[10] * s1 + e[11] * s2;
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) o[q] = wave_sum(o[q]);
+    if (lane == 0)
+        for (int q = 0; q < 6; ++q) corr[p * 6 + q] = o[q];
+}
+
+// ---------------------------------------------------------------------------
 // final reduction: far chunks in order, then the pair corrections in CSR order
 // ---------------------------------------------------------------------------
+// Stokes: u_S = u[0..2] / (8 pi), u_D = -3 u[3..5] / (4 pi) (three components
+// per target); Laplace: u_S = u[0] / (4 pi), u_D = u[3] / (4 pi) (one each).
 __global__ void k_reduce(int64_t T, const int* __restrict__ tgroup, const int* __restrict__ gnchunk,
                          const double* __restrict__ part, const int64_t* __restrict__ off,
                          const int8_t* __restrict__ tier, const double* __restrict__ corr,
-                         double* __restrict__ usl, double* __restrict__ udl)
+                         double* __restrict__ usl, double* __restrict__ udl, int ker)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= T) return;
     double u[6] = {0, 0, 0, 0, 0, 0};
     const int nchunk = gnchunk[tgroup[t]];
+    const int kstep = ker == KER_LAPLACE ? 3 : 1;   // Laplace: slots 0 and 3 only
     for (int c = 0; c < nchunk; ++c)
-        for (int k = 0; k < 6; ++k) u[k] += part[((int64_t)c * 6 + k) * T + t];
+        for (int k = 0; k < 6; k += kstep) u[k] += part[((int64_t)c * 6 + k) * T + t];
     if (off) {
         for (int64_t p = off[t]; p < off[t + 1]; ++p) {
             if (tier[p] == TIER_SKIP) continue;
-            for (int k = 0; k < 6; ++k) u[k] += corr[p * 6 + k];
+            for (int k = 0; k < 6; k += kstep) u[k] += corr[p * 6 + k];
         }
+    }
+    if (ker == KER_LAPLACE) {
+        const double cL = 1.0 / (4.0 * PI);
+        if (usl) usl[t] = cL * u[0];
+        if (udl) udl[t] = cL * u[3];
+        return;
     }
     const double cS = 1.0 / (8.0 * PI), cD = -3.0 / (4.0 * PI);
     for (int d = 0; d < 3; ++d) {
         if (usl) usl[t * 3 + d] = cS * u[d];
         if (udl) udl[t * 3 + d] = cD * u[3 + d];
     }
+}
+
+// scalar density (Laplace) into the first component of a 3-component array
+__global__ void k_scalar_to_vec(int64_t N, const double* __restrict__ s, double* __restrict__ v)
+{
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    v[3 * n] = s[n];
+    v[3 * n + 1] = 0.0;
+    v[3 * n + 2] = 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -2046,15 +2418,18 @@ int launch_targets(hipStream_t st, int64_t T, const double* x, const int64_t* tn
 }
 
 int launch_far(hipStream_t st, int64_t T, const double* xt, const double* sy, const double* sn, const double* ssw,
-               int64_t N, const FarTile* tiles, int ntiles, double* part, bool mixed, double near2, int tpt)
+               int64_t N, const FarTile* tiles, int ntiles, double* part, bool mixed, double near2, int tpt, int ker)
 {
     if (ntiles == 0) return 0;
+    if (mixed && ker != KER_STOKES) return (int)hipErrorInvalidValue;
     const dim3 grid((unsigned)ntiles), blk(FAR_BLOCK);
 #define CSBQ_FAR(K)                                                                                                 \
     if (mixed)                                                                                                      \
         hipLaunchKernelGGL(k_far_mx<K>, grid, blk, 0, st, T, xt, sy, sn, ssw, N, tiles, near2, part);              \
+    else if (ker == KER_LAPLACE)                                                                                    \
+        hipLaunchKernelGGL((k_far<K, KER_LAPLACE>), grid, blk, 0, st, T, xt, sy, sn, ssw, N, tiles, part);          \
     else                                                                                                            \
-        hipLaunchKernelGGL(k_far<K>, grid, blk, 0, st, T, xt, sy, sn, ssw, N, tiles, part);
+        hipLaunchKernelGGL((k_far<K, KER_STOKES>), grid, blk, 0, st, T, xt, sy, sn, ssw, N, tiles, part);
     switch (tpt) {
     case 1: CSBQ_FAR(1) break;
     case 2: CSBQ_FAR(2) break;
@@ -2114,11 +2489,15 @@ int launch_tier_keys(hipStream_t st, int64_t P, int E, const int8_t* tier, const
 
 int launch_corr_up(hipStream_t st, const UpRules& ur, int nwaves, const int* ws, const int* sorted, const int* pt,
                    const double* xt, int64_t T, const ElemInfo* info, const int64_t* boff, const double* by,
-                   const double* bn, const double* bsw, int64_t Nb, double* corr)
+                   const double* bn, const double* bsw, int64_t Nb, double* corr, int ker)
 {
     if (nwaves == 0) return 0;
-    hipLaunchKernelGGL(k_corr_up, dim3(nwaves), dim3(64), 0, st, ur, ws, sorted, pt, xt, T, info, boff, by, bn, bsw,
-                       Nb, corr);
+    if (ker == KER_LAPLACE)
+        hipLaunchKernelGGL(k_corr_up<KER_LAPLACE>, dim3(nwaves), dim3(64), 0, st, ur, ws, sorted, pt, xt, T, info, boff,
+                           by, bn, bsw, Nb, corr);
+    else
+        hipLaunchKernelGGL(k_corr_up<KER_STOKES>, dim3(nwaves), dim3(64), 0, st, ur, ws, sorted, pt, xt, T, info, boff,
+                           by, bn, bsw, Nb, corr);
     LAUNCH_CHECK();
     return 0;
 }
@@ -2128,29 +2507,73 @@ int launch_corr_full(hipStream_t st, int nfull, const int* listf, const int* pe,
                      const int* band, const double* cls, const int64_t* boff, const double* by, const double* bn,
                      const double* bsw, int64_t Nb, const int* roff, const double* rth, const double* rw, int nb,
                      const double* lx, const double* lw, int nl, const double* rcs, const double* rsn,
-                     const double* romc, GateConsts gc, double* corr, int* err, int* work, int mt_max)
+                     const double* romc, GateConsts gc, double* corr, int* err, int* work, int mt_max, int ker,
+                     int mode, const MatrixRows* mr)
 {
     if (nfull == 0) return 0;
     if (mt_max < 0 || mt_max >= NMODE) return (int)hipErrorInvalidValue;
+    if (mode != MODE_DENSITY && (ker != KER_STOKES || !mr)) return (int)hipErrorInvalidValue;
     RuleTables rt{roff, rth, rw, rcs, rsn, romc, nb, lx, lw, nl};
     const int cstride = 6 * (mt_max + 1);
     // at least the phase-1 weights and centerline quantities (and the stack)
     const size_t lds = (size_t)SB * (cstride > NS + QVS ? cstride : NS + QVS) * sizeof(double);
-    hipLaunchKernelGGL(k_corr_full, dim3(nfull), dim3(64), lds, st, listf, pe, pt,
-                       xt, T, tnode, clq, sh, info, band, cls, boff, by, bn, bsw, Nb, rt, gc, corr, err, work,
-                       cstride);
+    MatrixOut mo{};
+    if (mr) mo = MatrixOut{mr->roff, mr->V, mr->L, mr->count, mr->lup0, mr->bw};
+    if (ker == KER_LAPLACE)
+        hipLaunchKernelGGL((k_corr_full<KER_LAPLACE, MODE_DENSITY>), dim3(nfull), dim3(64), lds, st, listf, pe, pt, xt,
+                           T, tnode, clq, sh, info, band, cls, boff, by, bn, bsw, Nb, rt, gc, corr, err, work, cstride,
+                           mo);
+    else if (mode == MODE_COUNT)
+        hipLaunchKernelGGL((k_corr_full<KER_STOKES, MODE_COUNT>), dim3(nfull), dim3(64), lds, st, listf, pe, pt, xt,
+                           T, tnode, clq, sh, info, band, cls, boff, by, bn, bsw, Nb, rt, gc, corr, err, work, cstride,
+                           mo);
+    else if (mode == MODE_MATRIX)
+        hipLaunchKernelGGL((k_corr_full<KER_STOKES, MODE_MATRIX>), dim3(nfull), dim3(64), lds, st, listf, pe, pt, xt,
+                           T, tnode, clq, sh, info, band, cls, boff, by, bn, bsw, Nb, rt, gc, corr, err, work, cstride,
+                           mo);
+    else
+        hipLaunchKernelGGL((k_corr_full<KER_STOKES, MODE_DENSITY>), dim3(nfull), dim3(64), lds, st, listf, pe, pt, xt,
+                           T, tnode, clq, sh, info, band, cls, boff, by, bn, bsw, Nb, rt, gc, corr, err, work, cstride,
+                           mo);
     LAUNCH_CHECK();
     return 0;
 }
 
 int launch_reduce(hipStream_t st, int64_t T, const int* tgroup, const int* gnchunk, const double* part,
-                  const int64_t* off, const int8_t* tier, const double* corr, double* usl, double* udl)
+                  const int64_t* off, const int8_t* tier, const double* corr, double* usl, double* udl, int ker)
 {
     if (T == 0) return 0;
     hipLaunchKernelGGL(k_reduce, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, st, T, tgroup, gnchunk, part, off,
-                       tier, corr, usl, udl);
+                       tier, corr, usl, udl, ker);
     LAUNCH_CHECK();
     return 0;
 }
+
+int launch_emat(hipStream_t st, int npairs, const int64_t* roff, const double* V, const double* L, int64_t p0,
+                double* Em)
+{
+    if (npairs == 0) return 0;
+    hipLaunchKernelGGL(k_emat, dim3(npairs), dim3(256), 0, st, npairs, roff, V, L, p0, Em);
+    LAUNCH_CHECK();
+    return 0;
+}
+
+int launch_emat_apply(hipStream_t st, int npairs, const int* listf, const int* pe, const double* Em, const double* sh,
+                      double* corr)
+{
+    if (npairs == 0) return 0;
+    hipLaunchKernelGGL(k_emat_apply, dim3(npairs), dim3(64), 0, st, npairs, listf, pe, Em, sh, corr);
+    LAUNCH_CHECK();
+    return 0;
+}
+
+int launch_scalar_to_vec(hipStream_t st, int64_t N, const double* s, double* v)
+{
+    if (N == 0) return 0;
+    hipLaunchKernelGGL(k_scalar_to_vec, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, N, s, v);
+    LAUNCH_CHECK();
+    return 0;
+}
+
 
 }  // namespace csbq

@@ -31,7 +31,7 @@ int launch_targets(hipStream_t st, int64_t T, const double* x, const int64_t* tn
                    const ElemInfo* info, const double* ny, int64_t N, double* xt, int* tgroup, int64_t* gstart,
                    int* err);
 int launch_far(hipStream_t st, int64_t T, const double* xt, const double* sy, const double* sn, const double* ssw,
-               int64_t N, const FarTile* tiles, int ntiles, double* part, bool mixed, double near2, int tpt);
+               int64_t N, const FarTile* tiles, int ntiles, double* part, bool mixed, double near2, int tpt, int ker);
 int launch_search(hipStream_t st, int64_t T, const int* tgroup, const int* gel, const double* xt,
                   const int64_t* tnode, const ElemInfo* info, const double* rnear, const int64_t* off, int* cnt,
                   int* pe, int* pt);
@@ -58,15 +58,41 @@ struct UpRules {
 // element, tier index 0..NUP-1)
 int launch_corr_up(hipStream_t st, const UpRules& ur, int nwaves, const int* ws, const int* sorted, const int* pt,
                    const double* xt, int64_t T, const ElemInfo* info, const int64_t* boff, const double* by,
-                   const double* bn, const double* bsw, int64_t Nb, double* corr);
+                   const double* bn, const double* bsw, int64_t Nb, double* corr, int ker);
 constexpr int FAR_BLOCK = 256;         // threads of a smooth-sum block (TPT targets each)
+
+// Correction-matrix form of the special quadrature (Section 3.2.1, the
+// corrected rule's E): launch_corr_full in MODE_COUNT writes the rows of
+// every pair (its s-nodes plus the far-field rule's rows) to count[]; in
+// MODE_MATRIX the rows themselves (V: [rows][12][NT] kernel components times
+// trigonometric basis functions summed over each row's angles; L: [rows][NS]
+// interpolation weights), the pairs' rows starting at roff[]; launch_emat
+// assembles E[p][12][NS][NT] = L^T V per pair; launch_emat_apply forms the
+// pairs' corrections from E and the density's Fourier coefficients.
+enum { MODE_DENSITY = 0, MODE_COUNT = 1, MODE_MATRIX = 2 };
+constexpr int64_t EMAT_DOUBLES = 12 * NS * NT;
+struct MatrixRows {
+    const int64_t* roff;
+    double* V;
+    double* L;
+    int* count;
+    const double* lup0;
+    const double* bw;
+};
+int launch_emat(hipStream_t st, int npairs, const int64_t* roff, const double* V, const double* L, int64_t p0,
+                double* Em);
+int launch_emat_apply(hipStream_t st, int npairs, const int* listf, const int* pe, const double* Em, const double* sh,
+                      double* corr);
 int launch_corr_full(hipStream_t st, int nfull, const int* listf, const int* pe, const int* pt, const double* xt,
                      int64_t T, const int64_t* tnode, const double* clq, const double* sh, const ElemInfo* info,
                      const int* band, const double* cls, const int64_t* boff, const double* by, const double* bn,
                      const double* bsw, int64_t Nb, const int* roff, const double* rth, const double* rw, int nb,
                      const double* lx, const double* lw, int nl, const double* rcs, const double* rsn,
-                     const double* romc, GateConsts gc, double* corr, int* err, int* work, int mt_max);
+                     const double* romc, GateConsts gc, double* corr, int* err, int* work, int mt_max, int ker,
+                     int mode = MODE_DENSITY, const MatrixRows* mr = nullptr);
 int launch_reduce(hipStream_t st, int64_t T, const int* tgroup, const int* gnchunk, const double* part,
-                  const int64_t* off, const int8_t* tier, const double* corr, double* usl, double* udl);
+                  const int64_t* off, const int8_t* tier, const double* corr, double* usl, double* udl, int ker);
+// scalar density into component 0 of a [N][3] array (the Laplace layers)
+int launch_scalar_to_vec(hipStream_t st, int64_t N, const double* s, double* v);
 
 }  // namespace csbq

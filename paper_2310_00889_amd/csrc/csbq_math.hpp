@@ -195,6 +195,44 @@ __host__ __device__ inline void circle_local_rel(const Frame& f, const Frame& f0
     c.cha = (f.E > 1e-300) ? c.d2 / (2.0 * c.rho * f.E) : 1e300;
 }
 
+// Local coordinates of a free target relative to a circle of an element, in
+// the same difference form: xr = x - x_c(s0) is the target's offset from the
+// centerline at a reference node s0 of frame f0, z_ref = xr.t0 and
+// k_ref = |xr|^2 - eps0^2 (both formed once per pair, so their rounding is the
+// same for every circle), dq = q(s) - q(s0).  Then
+//   z = z_ref + xr.(t - t0) - dX.t,
+//   rho^2 - eps^2 = k_ref - 2 xr.dX + |dX|^2 - z^2 - deps (2 eps0 + deps),
+// and the distance to the circle keeps its relative accuracy however close the
+// target is (an on-surface target is xr = eps0 bn, z_ref = k_ref = 0).
+__host__ __device__ inline void circle_local_off(const Frame& f, const Frame& f0, const double* xr, double z_ref,
+                                                 double k_ref, const double* dq, CircleLocal& c)
+{
+    const double* dX = dq + Q_X;
+    const double* dXp = dq + Q_XP;
+    const double dE = dq[Q_E];
+    const double E0 = f0.E;
+    double v[3];
+    for (int d = 0; d < 3; ++d) v[d] = xr[d] - dX[d];
+    double sm[3] = {f.Xp[0] + f0.Xp[0], f.Xp[1] + f0.Xp[1], f.Xp[2] + f0.Xp[2]};
+    double dsp = dot3(dXp, sm) / (f.sp + f0.sp);
+    double dt[3];
+    for (int d = 0; d < 3; ++d) dt[d] = (dXp[d] - f0.t[d] * dsp) / f.sp;
+    c.z = z_ref + dot3(xr, dt) - dot3(dX, f.t);
+    double w[3] = {v[0] - c.z * f.t[0], v[1] - c.z * f.t[1], v[2] - c.z * f.t[2]};
+    c.rho = sqrt(dot3(w, w));
+    if (c.rho > 0.0) {
+        double ir = 1.0 / c.rho;
+        for (int d = 0; d < 3; ++d) c.b0[d] = w[d] * ir;
+    } else {
+        for (int d = 0; d < 3; ++d) c.b0[d] = f.e1[d];
+    }
+    cross3(f.t, c.b0, c.b0p);
+    double r2mE2 = k_ref - dE * (2.0 * E0 + dE) - 2.0 * dot3(xr, dX) + dot3(dX, dX) - c.z * c.z;
+    c.dr = r2mE2 / (c.rho + f.E);
+    c.d2 = c.dr * c.dr + c.z * c.z;
+    c.cha = (c.rho > 0.0 && f.E > 1e-300) ? c.d2 / (2.0 * c.rho * f.E) : 1e300;
+}
+
 // a = acosh(1 + cha), stable for small cha
 __host__ __device__ inline double acosh1p(double cha)
 {
