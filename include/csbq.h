@@ -184,6 +184,28 @@ int csbq_eval(csbq_ctx* ctx, const double* sigma, int64_t n_tgt, const double* x
 int csbq_smooth_sum(csbq_ctx* ctx, const double* sigma, int64_t n_tgt, const double* x, const int64_t* tgt_node,
                     double* u_sl, double* u_dl, int mem);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc):
+   csbq_smooth_sum with the same arguments and results (within rounding: the
+   sum is split into a fixed number of source chunks), all pointers in device
+   memory, and no allocation.  Every buffer beyond the caller's inputs and
+   outputs lives in one static device array of the library (about 58 MiB per
+   GPU, loaded with the library's code object and held until the process
+   ends), whose address csbq_create looks up once per device.  Limits: a
+   single geometry (csbq_set_geometry, not a batch of groups), at most
+   CSBQ_NOALLOC_MAX_TARGETS targets and CSBQ_NOALLOC_MAX_NODES surface nodes;
+   beyond them the call fails with CSBQ_ELIMIT.  The call only enqueues work
+   on the context's stream (no host wait, no memset); a tgt_node beyond the
+   node count sets CSBQ_FLAG_NODE_RANGE, read with csbq_eval_flags, and makes
+   that target's outputs meaningless.  Calls on one GPU share the array,
+   whose contents persist between calls: calls that overlap in time on one
+   GPU (other streams, other threads or contexts) race and must be ordered by
+   the caller. */
+#define CSBQ_NOALLOC_MAX_TARGETS 262144
+#define CSBQ_NOALLOC_MAX_NODES 262144
+int csbq_smooth_sum_noalloc(csbq_ctx* ctx, const double* sigma, int64_t n_tgt, const double* x,
+                            const int64_t* tgt_node, double* u_sl, double* u_dl);
+
 /* csbq_eval over a batch (csbq_set_geometry_batch): tgt_group[n_tgt] names
    the geometry of every free target (ignored for on-surface targets, whose
    node fixes it; NULL = group 0 for free targets).  Targets must be ordered by

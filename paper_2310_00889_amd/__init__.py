@@ -91,6 +91,7 @@ def load_library():
     lib.csbq_eval.argtypes = [vp, dp, C.c_int64, dp, lp, dp, dp, C.c_int]
     lib.csbq_eval_batch.argtypes = [vp, dp, C.c_int64, dp, lp, ip, dp, dp, C.c_int]
     lib.csbq_smooth_sum.argtypes = [vp, dp, C.c_int64, dp, lp, dp, dp, C.c_int]
+    lib.csbq_smooth_sum_noalloc.argtypes = [vp, dp, C.c_int64, dp, lp, dp, dp]
     lib.csbq_stats.argtypes = [vp, C.c_char_p, C.c_int64]
     lib.csbq_plan.argtypes = [vp, dp, C.c_int64, dp, lp, ip, dp, dp, C.c_int]
     lib.csbq_plan_ex.argtypes = [vp, dp, C.c_int64, dp, lp, ip, C.c_int32, dp, dp, C.c_int]
@@ -286,6 +287,24 @@ class Evaluator:
     def smooth_sum(self, sigma, x=None, tgt_node=None, out_sl=None, out_dl=None):
         """(u_S, u_D) of the plain smooth Nystrom sum (no corrections)."""
         return self._call(self._lib.csbq_smooth_sum, "csbq_smooth_sum", sigma, x, tgt_node, out_sl, out_dl)
+
+    def smooth_sum_noalloc(self, sigma, x=None, tgt_node=None, out_sl=None, out_dl=None):
+        """The smooth sum through the allocation-free entry point: device
+        tensors only (outputs are allocated here, by torch, when not given);
+        the call only enqueues work (flags via flags())."""
+        import torch
+        T = int(tgt_node.shape[0] if tgt_node is not None else x.shape[0])
+        if out_sl is None:
+            out_sl = torch.empty(self._oshape(T), dtype=torch.float64, device=sigma.device)
+        if out_dl is None:
+            out_dl = torch.empty(self._oshape(T), dtype=torch.float64, device=sigma.device)
+        for a in (sigma, x, tgt_node, out_sl, out_dl):
+            if a is not None and not (_is_torch_cuda(a) and a.is_contiguous()):
+                raise CsbqError("smooth_sum_noalloc takes contiguous CUDA tensors only")
+        self._check_shapes(sigma, x, tgt_node, None, out_sl, out_dl)
+        self._check(self._lib.csbq_smooth_sum_noalloc(self._h, _ptr(sigma), T, _ptr(x), _ptr(tgt_node), _ptr(out_sl),
+                                                      _ptr(out_dl)), "csbq_smooth_sum_noalloc")
+        return out_sl, out_dl
 
     # ---- setup / apply split
     def plan(self, sigma, x=None, tgt_node=None, out_sl=None, out_dl=None, tgt_group=None, matrix=False,

@@ -117,6 +117,8 @@ std::string default_table_dir()
 
 static void plan_drop(csbq_ctx* ctx);
 
+static_assert(CSBQ_NOALLOC_MAX_TARGETS == NOALLOC_MAX_TARGETS && CSBQ_NOALLOC_MAX_NODES == NOALLOC_MAX_NODES,
+              "limits of the allocation-free smooth sum");
 static_assert(CSBQ_FLAG_NODE_RANGE == FLAG_NODE_RANGE && CSBQ_FLAG_SRULE_LIMIT == FLAG_SRULE_LIMIT &&
                   CSBQ_FLAG_THETA_CLAMP == FLAG_THETA_CLAMP && CSBQ_FLAG_GROUP_RANGE == FLAG_GROUP_RANGE &&
                   CSBQ_FLAG_GROUP_ORDER == FLAG_GROUP_ORDER && CSBQ_FLAG_BAND == FLAG_BAND,
@@ -283,6 +285,16 @@ int csbq_create(const csbq_options* opt, csbq_ctx** out)
     ctx->gc.ct = 1000.0;
     ctx->gc.hmin_fac = 1.0;
     ctx->gc.extra_modes = 2;
+    {
+        void* sp = nullptr;
+        if (int se = scratch_address(ctx->opt.device, &sp)) {
+            std::fprintf(stderr, "csbq_create: scratch address lookup failed (%s)\n",
+                         hipGetErrorString((hipError_t)se));
+            csbq_destroy(ctx);
+            return CSBQ_EHIP;
+        }
+        ctx->scratch = (unsigned char*)sp;
+    }
     for (int k = 0; k < kNPhase; ++k) {
         ctx->ph[k].name = kPhaseNames[k];
         (void)hipEventCreate(&ctx->ph[k].a);
@@ -947,6 +959,63 @@ int csbq_smooth_sum(csbq_ctx* ctx, const double* sigma, int64_t T, const double*
     LCHK(launch_reduce(ctx->stream, T, ctx->tgroup.p, ctx->gnchunk.p, ctx->part.p, nullptr, nullptr, nullptr, usl,
                        udl, ctx->ker));
     return finish(ctx, T, u_sl, u_dl, mem);
+}
+
+// csbq_smooth_sum without any allocation: every buffer beyond the caller's
+// inputs and outputs lives in the device's static scratch array.  One fixed
+// launch shape (two targets per thread, as many source chunks as the
+// partial-sum space holds, at least 8192 sources each); no host wait, no
+// memset (a fill kernel clears the flag word).  Calls on one device share the
+// array, so overlapping calls race.
+int csbq_smooth_sum_noalloc(csbq_ctx* ctx, const double* sigma, int64_t T, const double* x, const int64_t* tgt_node,
+                            double* u_sl, double* u_dl)
+{
+    if (!ctx) return CSBQ_EINVAL;
+    ctx->err.clear();
+    if (!ctx->have_geom) return ctx->fail(CSBQ_ESTATE, "set_geometry must be called first");
+    if (ctx->G != 1) return ctx->fail(CSBQ_EINVAL, "the allocation-free smooth sum takes a single geometry");
+    if (!sigma || T < 0) return ctx->fail(CSBQ_EINVAL, "missing density or negative target count");
+    if (!x && !tgt_node && T > 0) return ctx->fail(CSBQ_EINVAL, "targets need x or tgt_node");
+    if (T > NOALLOC_MAX_TARGETS)
+        return ctx->fail(CSBQ_ELIMIT, "allocation-free smooth sum: more than 262144 targets");
+    if (ctx->N > NOALLOC_MAX_NODES)
+        return ctx->fail(CSBQ_ELIMIT, "allocation-free smooth sum: more than 262144 surface nodes");
+    if (!ctx->scratch) return ctx->fail(CSBQ_ESTATE, "no scratch array on this device");
+    HIPC(hipSetDevice(ctx->opt.device));
+    hipStream_t st = ctx->stream;
+    unsigned char* sp = ctx->scratch;
+    double* xt = (double*)(sp + NA_XT);
+    double* sw = (double*)(sp + NA_SW);
+    double* sh = (double*)(sp + NA_SH);
+    double* part = (double*)(sp + NA_PART);
+    int* tgroup = (int*)(sp + NA_TGROUP);
+    int* band = (int*)(sp + NA_BAND);
+    FarTile* tiles = (FarTile*)(sp + NA_TILES);
+    int64_t* gstart = (int64_t*)(sp + NA_GSTART);
+    int* gnchunk = (int*)(sp + NA_GNCHUNK);
+    int* errf = (int*)(sp + NA_ERR);
+    const int64_t N = ctx->N;
+    const int tb = 256 * 2;   // targets per block (two per thread)
+    const int64_t tblocks = std::max<int64_t>((T + tb - 1) / tb, 1);
+    int64_t nch = std::min<int64_t>((N + 8191) / 8192, NOALLOC_PART_DOUBLES / std::max<int64_t>(6 * T, 1));
+    nch = std::max<int64_t>(1, std::min<int64_t>(nch, NOALLOC_MAX_TILES / tblocks));
+    const int64_t chunk = (N + nch - 1) / nch;
+    const int ntiles = T > 0 ? (int)(tblocks * nch) : 0;
+    LCHK(launch_noalloc_setup(st, ntiles, (int)nch, T, N, tb, chunk, tiles, gnchunk, errf));
+    ctx->flags_src = errf;
+    ctx->flags_pending = true;
+    if (T == 0) return CSBQ_OK;
+    LCHK(launch_targets(st, T, x, tgt_node, nullptr, 1, ctx->info.p, ctx->ny.p, N, xt, tgroup, gstart, errf));
+    if (ctx->nc() == 1) {   // the scalar (Laplace) density into three components
+        double* s3 = (double*)(sp + NA_SIG);
+        LCHK(launch_scalar_to_vec(st, N, sigma, s3));
+        sigma = s3;
+    }
+    LCHK(launch_prep_sigma(st, ctx->E, sigma, ctx->nw.p, N, sw, sh, band, 0.1 * ctx->gc.tol, ctx->info.p,
+                           ctx->circ.p, ctx->gc, nullptr));
+    LCHK(launch_far(st, T, xt, ctx->ny.p, ctx->nn.p, sw, N, tiles, ntiles, part, false, 0.0, 2, ctx->ker));
+    LCHK(launch_reduce(st, T, tgroup, gnchunk, part, nullptr, nullptr, nullptr, u_sl, u_dl, ctx->ker));
+    return CSBQ_OK;
 }
 
 int csbq_eval(csbq_ctx* ctx, const double* sigma, int64_t T, const double* x, const int64_t* tgt_node, double* u_sl,

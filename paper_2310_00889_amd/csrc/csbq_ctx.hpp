@@ -154,6 +154,7 @@ struct csbq_ctx {
     std::vector<int64_t> h_body_off;   // surface-node offsets of the bodies [n_bodies + 1]
     DBuf<int64_t> s_boff, s_tn;
     DBuf<double> s_geo, s_ginv, s_coef, s_V, s_w, s_h, s_part, s_b, s_x, s_tau, s_usl, s_udl, s_nu, s_lsig;
+    unsigned char* scratch = nullptr;   // this device's static scratch (allocation-free smooth sum)
 
     int fail(int code, const std::string& msg)
     {

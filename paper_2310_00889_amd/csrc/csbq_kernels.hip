@@ -20,6 +20,8 @@
 //   k_reduce        far sum + corrections in a fixed order per target
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "csbq_kernels.hpp"
 #include "csbq_math.hpp"
 
@@ -2575,5 +2577,67 @@ int launch_scalar_to_vec(hipStream_t st, int64_t N, const double* s, double* v)
     return 0;
 }
 
+
+// ---------------------------------------------------------------------------
+// allocation-free smooth sum: scratch in a static device array
+// ---------------------------------------------------------------------------
+// One copy per device, zero-initialised when the code object loads and held
+// until the process ends.  Host code never passes this name to a kernel: the
+// device address comes from scratch_address().
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[NOALLOC_MAX_DEVICES];
+
+int scratch_address(int device, void** out)
+{
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) return (int)hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return (int)e;
+        if (cur != device) return (int)hipErrorInvalidDevice;   // the caller makes `device` current
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return (int)e;
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return 0;
+}
+
+// Block list of a single-geometry smooth sum (target block a = i / nch, source
+// chunk c = i % nch, so consecutive blocks -- one per XCD -- take consecutive
+// chunks), the group's chunk count and a cleared flag word.
+__global__ void k_noalloc_setup(int ntiles, int nch, int64_t T, int64_t N, int tb, int64_t chunk,
+                                FarTile* __restrict__ tiles, int* __restrict__ gnchunk, int* __restrict__ err)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
+        gnchunk[0] = nch;
+        err[0] = 0;
+    }
+    if (i >= ntiles) return;
+    const int a = i / nch, c = i - a * nch;
+    const int64_t t0 = (int64_t)a * tb, s0 = (int64_t)c * chunk;
+    FarTile f;
+    f.t0 = t0;
+    f.s0 = s0;
+    f.tn = (int32_t)min((int64_t)tb, T - t0);
+    f.sn = (int32_t)min(chunk, N - s0);
+    f.chunk = c;
+    f.pad_ = 0;
+    tiles[i] = f;
+}
+
+int launch_noalloc_setup(hipStream_t st, int ntiles, int nch, int64_t T, int64_t N, int tb, int64_t chunk,
+                         FarTile* tiles, int* gnchunk, int* err)
+{
+    hipLaunchKernelGGL(k_noalloc_setup, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0, st, ntiles, nch, T, N,
+                       tb, chunk, tiles, gnchunk, err);
+    LAUNCH_CHECK();
+    return 0;
+}
 
 }  // namespace csbq

@@ -61,6 +61,34 @@ int launch_corr_up(hipStream_t st, const UpRules& ur, int nwaves, const int* ws,
                    const double* bn, const double* bsw, int64_t Nb, double* corr, int ker);
 constexpr int FAR_BLOCK = 256;         // threads of a smooth-sum block (TPT targets each)
 
+// Allocation-free smooth sum: limits of the one static scratch array per
+// device (targets and nodes per call, partial-sum doubles) and its size.
+constexpr int64_t NOALLOC_MAX_TARGETS = 262144;
+constexpr int64_t NOALLOC_MAX_NODES = 262144;
+constexpr int64_t NOALLOC_MAX_ELEMS = NOALLOC_MAX_NODES / NPE;
+constexpr int64_t NOALLOC_PART_DOUBLES = 4LL << 20;       // 32 MiB of per-chunk partial sums
+constexpr int64_t NOALLOC_MAX_TILES = 16384;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+__host__ __device__ constexpr int64_t noalloc_align(int64_t b) { return (b + 255) / 256 * 256; }
+// byte offsets of the scratch's buffers
+constexpr int64_t NA_XT = 0;                                                                   // double [3][T]
+constexpr int64_t NA_SW = NA_XT + noalloc_align(8 * 3 * NOALLOC_MAX_TARGETS);                  // double [3][N]
+constexpr int64_t NA_SH = NA_SW + noalloc_align(8 * 3 * NOALLOC_MAX_NODES);                    // double [E][NS][NSH]
+constexpr int64_t NA_PART = NA_SH + noalloc_align(8 * NOALLOC_MAX_ELEMS * NS * NSH);           // double [nch][6][T]
+constexpr int64_t NA_TGROUP = NA_PART + noalloc_align(8 * NOALLOC_PART_DOUBLES);               // int [T]
+constexpr int64_t NA_BAND = NA_TGROUP + noalloc_align(4 * NOALLOC_MAX_TARGETS);                // int [E][2]
+constexpr int64_t NA_TILES = NA_BAND + noalloc_align(4 * 2 * NOALLOC_MAX_ELEMS);               // FarTile [ntiles]
+constexpr int64_t NA_GSTART = NA_TILES + noalloc_align((int64_t)sizeof(FarTile) * NOALLOC_MAX_TILES);  // int64 [1]
+constexpr int64_t NA_GNCHUNK = NA_GSTART + 256;                                                // int [1]
+constexpr int64_t NA_ERR = NA_GNCHUNK + 256;                                                   // int [1]
+constexpr int64_t NA_SIG = NA_ERR + 256;                                                       // double [N][3] (Laplace)
+constexpr int64_t NOALLOC_SCRATCH_BYTES = NA_SIG + noalloc_align(8 * 3 * NOALLOC_MAX_NODES);
+
+// Device address of this device's scratch array (the device must be
+// current); looked up once per device with hipGetSymbolAddress.
+int scratch_address(int device, void** out);
+int launch_noalloc_setup(hipStream_t st, int ntiles, int nch, int64_t T, int64_t N, int tb, int64_t chunk,
+                         FarTile* tiles, int* gnchunk, int* err);
 // Correction-matrix form of the special quadrature (Section 3.2.1, the
 // corrected rule's E): launch_corr_full in MODE_COUNT writes the rows of
 // every pair (its s-nodes plus the far-field rule's rows) to count[]; in
