@@ -285,6 +285,7 @@ int csbq_create(const csbq_options* opt, csbq_ctx** out)
     ctx->gc.ct = 1000.0;
     ctx->gc.hmin_fac = 1.0;
     ctx->gc.extra_modes = 2;
+    ctx->closed_fb = 2;
     {
         void* sp = nullptr;
         if (int se = scratch_address(ctx->opt.device, &sp)) {
@@ -530,7 +531,7 @@ int csbq_set_geometry_batch(csbq_ctx* ctx, int32_t n_bodies, const int32_t* body
     ALLOC(ctx->nw, (size_t)N);
     LCHK(launch_expand(ctx->stream, (int)E, ctx->g_xc.p, ctx->g_eps.p, ctx->g_e1.p, ctx->g_sa.p, ctx->g_sc.p,
                        ctx->g_sign.p, ctx->g_body.p, ctx->g_group.p, ctx->clq.p, ctx->circ.p, ctx->info.p, ctx->ny.p, ctx->nn.p,
-                       ctx->nw.p, N));
+                       ctx->nw.p, N, ctx->closed_fb));
     ALLOC(ctx->gridc, (size_t)E * NCIRC * CGRID * GRQ);
     LCHK(launch_grid_circles(ctx->stream, (int)E, ctx->clq.p, ctx->gridc.p));
     // upsampled whole-panel rules (Gauss-Legendre of up_ns points in s times

@@ -63,6 +63,7 @@ struct csbq_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     GateConsts gc{};
+    int closed_fb = 2;   // far-field rule of elements closed at an end: 2 = up_ns(0) x NT, 1 = their own nodes
     // quadrature tables
     DBuf<int> roff;
     DBuf<double> rth, rw, lx, lw, rcs, rsn, romc;

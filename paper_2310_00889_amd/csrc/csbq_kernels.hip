@@ -315,7 +315,7 @@ __global__ __launch_bounds__(512) void k_expand(int E, const double* __restrict_
                                                 const int* __restrict__ ebody, const int* __restrict__ egroup, double* __restrict__ clq,
                                                 double* __restrict__ circ, ElemInfo* __restrict__ info,
                                                 double* __restrict__ ny, double* __restrict__ nn,
-                                                double* __restrict__ nw, int64_t N)
+                                                double* __restrict__ nw, int64_t N, int closed_fb)
 {
     const int e = blockIdx.x;
     const int tid = threadIdx.x;
@@ -438,10 +438,12 @@ __global__ __launch_bounds__(512) void k_expand(int E, const double* __restrict_
         // a cross-section that closes at a panel end (a body of revolution
         // described in polar angle, e.g. a sphere as one element) makes the
         // s-integrand converge slowly far away: its far-field rule is the
-        // up_ns(0)-point Gauss rule in s
+        // up_ns(0)-point Gauss rule in s (closed_fb = 2), or its own nodes
+        // with the upsampled rule as a correction wherever the estimates ask
+        // for it (closed_fb = 1)
         const double* cp0 = circ + (int64_t)e * NCIRC * CIRQ;
         const double eend = fmin(fabs(cp0[6]), fabs(cp0[(NCIRC - 1) * CIRQ + 6]));
-        inf.fb = (eend < 1e-3 * outv[1]) ? 2 : 1;
+        inf.fb = (eend < 1e-3 * outv[1]) ? closed_fb : 1;
         inf.group = egroup[e];
         info[e] = inf;
     }
@@ -2316,10 +2318,11 @@ __global__ void k_scalar_to_vec(int64_t N, const double* __restrict__ s, double*
 
 int launch_expand(hipStream_t st, int E, const double* xc, const double* eps, const double* e1, const double* sa,
                   const double* sc, const int* esign, const int* ebody, const int* egroup, double* clq, double* circ,
-                  ElemInfo* info, double* ny, double* nn, double* nw, int64_t N)
+                  ElemInfo* info, double* ny, double* nn, double* nw, int64_t N, int closed_fb)
 {
+    if (closed_fb != 1 && closed_fb != 2) return (int)hipErrorInvalidValue;
     hipLaunchKernelGGL(k_expand, dim3(E), dim3(512), 0, st, E, xc, eps, e1, sa, sc, esign, ebody, egroup, clq, circ,
-                       info, ny, nn, nw, N);
+                       info, ny, nn, nw, N, closed_fb);
     LAUNCH_CHECK();
     return 0;
 }

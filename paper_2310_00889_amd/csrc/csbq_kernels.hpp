@@ -12,7 +12,7 @@ int upload_constants(const double* gx, const double* gw, const double* lam, cons
 
 int launch_expand(hipStream_t st, int E, const double* xc, const double* eps, const double* e1, const double* sa,
                   const double* sc, const int* esign, const int* ebody, const int* egroup, double* clq, double* circ,
-                  ElemInfo* info, double* ny, double* nn, double* nw, int64_t N);
+                  ElemInfo* info, double* ny, double* nn, double* nw, int64_t N, int closed_fb);
 int launch_expand_up(hipStream_t st, int E, int ns_f, int nt_f, const double* gx_f, const double* gw_f,
                      const double* clq, const ElemInfo* info, double* cpy, double* cpn, double* cpw, int64_t Mtot);
 int launch_base_build(hipStream_t st, int E, const ElemInfo* info, const int64_t* boff, const double* ny,

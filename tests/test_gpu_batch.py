@@ -110,3 +110,100 @@ def test_batch_64_geometries_sampled(evs):
         worst[1] = max(worst[1], np.abs(ud[t] - do).max() / scale_d)
     print("batch64 worst vs oracle", worst, flush=True)
     assert worst[0] < GATE and worst[1] < GATE
+
+
+def test_batch_plan_apply_per_geometry(evs):
+    """The setup/apply split on a batch: plan on 16 uneven geometries (all
+    nodes), then apply a second density; each geometry's part against the
+    oracle (sampled) and against the batch's own eager evaluation of that
+    density (rounding only)."""
+    import torch
+    ev, ev1 = evs
+    scs = synth.config4(seed=4100, n_geom=16, max_spheres=20, max_panels=24)
+    b = synth.merge_scenes(scs)
+    ev.set_geometry(b)
+    sig = torch.from_numpy(b.sigma).cuda()
+    tn = torch.from_numpy(b.tgt_node).cuda()
+    ev.plan(sig, None, tn)
+    sig2 = 0.5 * b.sigma + np.roll(b.sigma, 1, axis=1)   # the planning density's band limits
+    us, ud = ev.apply(torch.from_numpy(sig2).cuda())
+    torch.cuda.synchronize()
+    us, ud = us.cpu().numpy(), ud.cpu().numpy()
+    ev1.set_geometry(b)
+    ue, de = ev1.eval(sig2, None, b.tgt_node)
+    assert _rel(us, ue) < 1e-12 and _rel(ud, de) < 1e-12
+    rng = np.random.default_rng(14)
+    for g, sc in enumerate(scs):
+        off = int(b.group_target_offsets[g])
+        k = rng.choice(sc.n_nodes, 3, replace=False)
+        s2 = sig2[off: off + sc.n_nodes]   # targets are every node, in geometry order
+        uo, do = oracle.evaluate(sc, s2, None, k.astype(np.int64))
+        es, ed = _rel(us[off + k], uo), _rel(ud[off + k], do)
+        assert es < GATE and ed < GATE, (g, es, ed)
+
+
+def test_batch_mixed_precision_sampled(evs):
+    """A batch in mixed precision (FP32 smooth sum with the FP64 near part,
+    quad_tol 1e-7) against the oracle, 3 sampled targets per geometry: 1e-6."""
+    import torch
+    import paper_2310_00889_amd as pk
+    scs = synth.config4(seed=4200, n_geom=16, max_spheres=20, max_panels=24)
+    b = synth.merge_scenes(scs)
+    ev = pk.Evaluator(quad_tol=1e-7, precision="mixed")
+    try:
+        ev.set_geometry(b)
+        us, ud = ev.eval(torch.from_numpy(b.sigma).cuda(), None, torch.from_numpy(b.tgt_node).cuda())
+        torch.cuda.synchronize()
+        us, ud = us.cpu().numpy(), ud.cpu().numpy()
+    finally:
+        ev.close()
+    rng = np.random.default_rng(15)
+    worst = [0.0, 0.0]
+    for g, sc in enumerate(scs):
+        off = int(b.group_target_offsets[g])
+        k = rng.choice(sc.n_nodes, 3, replace=False)
+        uo, do = oracle.evaluate(sc, None, None, k.astype(np.int64))
+        worst[0] = max(worst[0], _rel(us[off + k], uo))
+        worst[1] = max(worst[1], _rel(ud[off + k], do))
+    print("mixed batch worst vs oracle", worst, flush=True)
+    assert worst[0] < 1e-6 and worst[1] < 1e-6
+
+
+def test_config4_full_range_geometry_sampled(evs):
+    """One geometry at the top of config 4's ranges (200 pipe panels, 500
+    spheres, radii U(0.1, 0.25), gaps 10^U(-3,-1)), in a batch with a small
+    one: 24 sampled targets (stratified: wall, spheres, nearest-contact
+    sphere nodes) against the oracle, 1e-10."""
+    import torch
+    ev, _ = evs
+    rng = np.random.default_rng(4300)
+    M = 500
+    radii = rng.uniform(0.1, 0.25, M)
+    gaps = 10.0 ** rng.uniform(-3, -1, M)
+    vs = np.sum(4 / 3 * np.pi * radii ** 3)
+    lam = max(1.0, (vs / (0.136 * np.pi * 5.0 * np.pi)) ** (1 / 3))
+    big = synth.pipe_scene(4301, M, lam, n_panels=200, radii=radii, gaps=gaps)
+    small = synth.small_pipe_scene(seed=7300, n_panels=3, n_spheres=1)
+    b = synth.merge_scenes([big, small])
+    ev.set_geometry(b)
+    us, ud = ev.eval(torch.from_numpy(b.sigma).cuda(), None, torch.from_numpy(b.tgt_node).cuda())
+    torch.cuda.synchronize()
+    assert ev.flags() == 0
+    us, ud = us.cpu().numpy()[: big.n_nodes], ud.cpu().numpy()[: big.n_nodes]
+    nwall = 200 * 512
+    y, _, _ = oracle.nodes(big)
+    sph = np.arange(nwall, big.n_nodes)
+    # sphere nodes nearest another sphere's surface
+    cen, rad = big.sphere_centers, big.sphere_radii
+    owner = (sph - nwall) // 512
+    dmin = np.full(len(sph), np.inf)
+    for j in range(len(cen)):
+        dj = np.linalg.norm(y[sph] - cen[j], axis=1) - rad[j]
+        dj[owner == j] = np.inf
+        dmin = np.minimum(dmin, dj)
+    pick = np.concatenate([rng.choice(nwall, 8, replace=False), rng.choice(sph, 8, replace=False),
+                           sph[np.argsort(dmin)[:8]]]).astype(np.int64)
+    uo, do = oracle.evaluate(big, None, None, pick)
+    es, ed = _rel(us[pick], uo), _rel(ud[pick], do)
+    print("config-4 full-range geometry vs oracle", es, ed, flush=True)
+    assert es < GATE and ed < GATE
