@@ -44,6 +44,7 @@ def _load():
         lib.oracle_surface_point.argtypes = geo + [dp, C.c_int, C.c_int, dp, dp, dp, dp, dp, dp]
         lib.oracle_gauss_legendre.argtypes = [C.c_int, dp, dp]
         lib.oracle_num_threads.restype = C.c_int
+        lib.oracle_smooth_sum_magnitude.argtypes = geo + [dp, C.c_int64, dp, lp, dp, C.c_int]
         lib.oracle_set_kernel.argtypes = [C.c_int]
         lib.oracle_set_kernel.restype = C.c_int
         _lib = lib
@@ -136,6 +137,20 @@ def evaluate(scene, sigma=None, x=None, tgt_node=None, rel_tol=1e-15, force_adap
     if return_deep:
         return usl, udl, int(deep[0])
     return usl, udl
+
+
+def smooth_sum_magnitude(scene, sigma=None, x=None, tgt_node=None, threads=0):
+    """Per target, the sums of |term| of the plain tensor rule's single- and
+    double-layer terms (T, 2): the scale of the smooth sum's rounding."""
+    lib = _load()
+    args, keep = _geo_args(scene)
+    sig = np.ascontiguousarray(scene.sigma if sigma is None else sigma, dtype=np.float64)
+    x, tn = _targets(scene, x, tgt_node)
+    mag = np.zeros((len(tn), 2))
+    rc = lib.oracle_smooth_sum_magnitude(*args, _p(sig), len(tn), _p(x), _p(tn, C.c_int64), _p(mag), threads)
+    if rc:
+        raise ValueError(f"oracle_smooth_sum_magnitude failed ({rc})")
+    return mag
 
 
 def evaluate_laplace(scene, sigma, x=None, tgt_node=None, rel_tol=1e-15, force_adaptive=False, threads=0,

@@ -644,6 +644,54 @@ int oracle_smooth_sum(int n_bodies, const int* n_panels, const int* normal_sign,
     return 0;
 }
 
+/* Sums of the magnitudes of the plain tensor rule's terms at every target:
+   mag[2t] = sum |S term| (both parts, every component), mag[2t+1] = sum |D
+   term|, with the same normalisation as the sums (1/(8 pi), 3/(4 pi)): the
+   scale against which the rounding of the smooth sum is judged. */
+int oracle_smooth_sum_magnitude(int n_bodies, const int* n_panels, const int* normal_sign, const double* s_break,
+                                const double* xc, const double* eps, const double* e1, int ns, int nt,
+                                const double* sigma, int64_t n_tgt, const double* x, const int64_t* tgt_node,
+                                double* mag, int nthreads)
+{
+    ogeom g;
+    if (geom_build(&g, n_bodies, n_panels, normal_sign, s_break, xc, eps, e1, ns, nt, sigma)) return -1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t t = 0; t < n_tgt; ++t) {
+        double xt[3];
+        if (tgt_node && tgt_node[t] >= 0) {
+            int64_t nd = tgt_node[t];
+            const oelem* e = &g.el[nd / (ns * nt)];
+            memcpy(xt, e->ny + 3 * (nd - e->node0), sizeof xt);
+        } else
+            memcpy(xt, x + 3 * t, sizeof xt);
+        double ms = 0.0, md = 0.0;
+        for (int k = 0; k < g.n_elem; ++k) {
+            const oelem* e = &g.el[k];
+            for (int q = 0; q < e->ns * e->nt; ++q) {
+                const double* y = e->ny + 3 * q;
+                const double* nn = e->nn + 3 * q;
+                const double* sg = e->sig + 3 * q;
+                double r[3] = {xt[0] - y[0], xt[1] - y[1], xt[2] - y[2]};
+                double rr = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+                if (rr == 0) continue;
+                double ir = 1 / sqrt(rr), w = e->nw[q];
+                double ar = fabs(r[0]) + fabs(r[1]) + fabs(r[2]);
+                double as = fabs(sg[0]) + fabs(sg[1]) + fabs(sg[2]);
+                double rn = fabs(r[0] * nn[0] + r[1] * nn[1] + r[2] * nn[2]);
+                ms += fabs(w) / (8 * OPI) * (ir * as + as * ar * ar * ir * ir * ir);
+                md += 3 / (4 * OPI) * fabs(w) * rn * as * ar * ar * ir * ir * ir * ir * ir;
+            }
+        }
+        mag[2 * t] = ms;
+        mag[2 * t + 1] = md;
+    }
+    geom_free(&g);
+    return 0;
+}
+
 /* The layer potentials themselves (the element integrals, evaluated to
    ~rel_tol of each element's scale).  force_adaptive != 0 disables the far
    test (every pair integrated adaptively).  Two test knobs weaken the far

@@ -124,8 +124,8 @@ def test_batch_plan_apply_per_geometry(evs):
     ev.set_geometry(b)
     sig = torch.from_numpy(b.sigma).cuda()
     tn = torch.from_numpy(b.tgt_node).cuda()
-    ev.plan(sig, None, tn)
-    sig2 = 0.5 * b.sigma + np.roll(b.sigma, 1, axis=1)   # the planning density's band limits
+    ev.plan(sig, None, tn, full_band=True)   # rules for any density's band
+    sig2 = 0.5 * b.sigma + np.roll(b.sigma, 1, axis=1)
     us, ud = ev.apply(torch.from_numpy(sig2).cuda())
     torch.cuda.synchronize()
     us, ud = us.cpu().numpy(), ud.cpu().numpy()
