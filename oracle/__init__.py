@@ -140,13 +140,16 @@ def evaluate(scene, sigma=None, x=None, tgt_node=None, rel_tol=1e-15, force_adap
 
 
 def smooth_sum_magnitude(scene, sigma=None, x=None, tgt_node=None, threads=0):
-    """Per target, the sums of |term| of the plain tensor rule's single- and
-    double-layer terms (T, 2): the scale of the smooth sum's rounding."""
+    """Per target (T, 5): the sums of |term| of the plain tensor rule's
+    single- and double-layer terms (the scale of the sums' rounding), the
+    first-order change of the S and D sums per unit displacement of the
+    target and of every node, and of the D sum per unit change of every
+    normal (bounds, not estimates)."""
     lib = _load()
     args, keep = _geo_args(scene)
     sig = np.ascontiguousarray(scene.sigma if sigma is None else sigma, dtype=np.float64)
     x, tn = _targets(scene, x, tgt_node)
-    mag = np.zeros((len(tn), 2))
+    mag = np.zeros((len(tn), 5))
     rc = lib.oracle_smooth_sum_magnitude(*args, _p(sig), len(tn), _p(x), _p(tn, C.c_int64), _p(mag), threads)
     if rc:
         raise ValueError(f"oracle_smooth_sum_magnitude failed ({rc})")

@@ -644,10 +644,19 @@ int oracle_smooth_sum(int n_bodies, const int* n_panels, const int* normal_sign,
     return 0;
 }
 
-/* Sums of the magnitudes of the plain tensor rule's terms at every target:
-   mag[2t] = sum |S term| (both parts, every component), mag[2t+1] = sum |D
-   term|, with the same normalisation as the sums (1/(8 pi), 3/(4 pi)): the
-   scale against which the rounding of the smooth sum is judged. */
+/* Scales of the plain tensor rule's sums at every target, five per target
+   (mag[5t + k]), with the same normalisation as the sums (1/(8 pi),
+   3/(4 pi)) and |sigma| taken as its 1-norm:
+     k = 0, 1: sum of |S term| and of |D term| (both parts, every component),
+       the scale of the sums' rounding;
+     k = 2, 3: first-order bounds of how much the S and the D sum change per
+       unit displacement of the target and of every node (|dr| <= 1, r =
+       x - y): |d(sigma/r + (r.sigma) r/r^3)| <= 6 |sigma| |dr| / r^2 and
+       |d((r.n)(r.sigma) r/r^5)| <= (|sigma|/r^3 + 7 |r.n| |sigma|/r^4) |dr|;
+     k = 4: the same for the D sum per unit change of every normal,
+       |(dn.r)(r.sigma) r/r^5| <= |sigma| |dn| / r^2.
+   Together they bound the difference between two evaluations of the sum on
+   node sets that differ by small amounts. */
 int oracle_smooth_sum_magnitude(int n_bodies, const int* n_panels, const int* normal_sign, const double* s_break,
                                 const double* xc, const double* eps, const double* e1, int ns, int nt,
                                 const double* sigma, int64_t n_tgt, const double* x, const int64_t* tgt_node,
@@ -667,7 +676,7 @@ int oracle_smooth_sum_magnitude(int n_bodies, const int* n_panels, const int* no
             memcpy(xt, e->ny + 3 * (nd - e->node0), sizeof xt);
         } else
             memcpy(xt, x + 3 * t, sizeof xt);
-        double ms = 0.0, md = 0.0;
+        double ms = 0.0, md = 0.0, gs = 0.0, gd = 0.0, gn = 0.0;
         for (int k = 0; k < g.n_elem; ++k) {
             const oelem* e = &g.el[k];
             for (int q = 0; q < e->ns * e->nt; ++q) {
@@ -683,10 +692,16 @@ int oracle_smooth_sum_magnitude(int n_bodies, const int* n_panels, const int* no
                 double rn = fabs(r[0] * nn[0] + r[1] * nn[1] + r[2] * nn[2]);
                 ms += fabs(w) / (8 * OPI) * (ir * as + as * ar * ar * ir * ir * ir);
                 md += 3 / (4 * OPI) * fabs(w) * rn * as * ar * ar * ir * ir * ir * ir * ir;
+                gs += fabs(w) / (8 * OPI) * 6 * as * ir * ir;
+                gd += 3 / (4 * OPI) * fabs(w) * as * (ir * ir * ir + 7 * rn * ir * ir * ir * ir);
+                gn += 3 / (4 * OPI) * fabs(w) * as * ir * ir;
             }
         }
-        mag[2 * t] = ms;
-        mag[2 * t + 1] = md;
+        mag[5 * t] = ms;
+        mag[5 * t + 1] = md;
+        mag[5 * t + 2] = gs;
+        mag[5 * t + 3] = gd;
+        mag[5 * t + 4] = gn;
     }
     geom_free(&g);
     return 0;

@@ -455,3 +455,36 @@ def test_double_layer_jump_resolved_at_1e_7():
     _, din = _ev(sc, sig, v * (1 - 1e-7))
     _, dout = _ev(sc, sig, v * (1 + 1e-7))
     assert np.abs((din - dout) - c).max() < 1e-12
+
+
+def test_smooth_sum_scales_bound_the_sum_and_its_change():
+    """The smooth sum's scales (the sums of |term| and the first-order change
+    per unit displacement) are bounds: they dominate the sums themselves, and
+    moving a target by delta changes the sums by at most delta times the
+    change bound, while the bound is not loose by orders of magnitude (a
+    dropped 1/r^3 term or a wrong power would break one side)."""
+    sc = synth.small_pipe_scene(n_panels=4, n_spheres=2)
+    y, n, _ = oracle.nodes(sc)
+    rng = np.random.default_rng(5)
+    k = rng.choice(sc.n_nodes, 40, replace=False)
+    d = 10.0 ** rng.uniform(-3, -1, 40)[:, None]
+    x = y[k] + d * n[k] * np.where(rng.random(40) < 0.5, 1, -1)[:, None]
+    free = -np.ones(40, np.int64)
+    us, ud = oracle.smooth_sum(sc, None, x, free)
+    mag = oracle.smooth_sum_magnitude(sc, None, x, free)
+    assert np.all(np.abs(us).max(1) <= mag[:, 0]) and np.all(np.abs(ud).max(1) <= mag[:, 1])
+    delta = 1e-9
+    e = rng.standard_normal((40, 3))
+    e /= np.linalg.norm(e, axis=1)[:, None]
+    us2, ud2 = oracle.smooth_sum(sc, None, x + delta * e, free)
+    ch_s = np.abs(us2 - us).max(1)
+    ch_d = np.abs(ud2 - ud).max(1)
+    rnd = 1e-15
+    assert np.all(ch_s <= 1.001 * delta * mag[:, 2] + rnd * mag[:, 0])
+    assert np.all(ch_d <= 1.001 * delta * mag[:, 3] + rnd * mag[:, 1])
+    assert (ch_s / (delta * mag[:, 2])).max() > 1e-2
+    assert (ch_d / (delta * mag[:, 3])).max() > 1e-2
+    # on-surface targets exclude only their own node: the scales are finite
+    tn = rng.choice(sc.n_nodes, 20, replace=False)
+    m2 = oracle.smooth_sum_magnitude(sc, None, None, tn)
+    assert np.all(np.isfinite(m2)) and np.all(m2 > 0)
