@@ -165,6 +165,48 @@ def run_matrix(sc, sig, tn, quad_tol, steps, ref):
     return out
 
 
+def run_slender(steps, n_panels=64, eps=1e-3):
+    """Every node of a slender torus (R = 1, cross-section radius eps,
+    n_panels elements; aspect 2 pi / (n_panels eps) per element) as an
+    on-surface target, FP64 at quad_tol 1e-12, with the whole-element singular
+    s-rules and with the general rule (dyadic panels and the log rule): ms per
+    evaluation, the special quadrature's share and s-node count, and the
+    largest difference between the two."""
+    import numpy as np
+    import torch
+    import paper_2310_00889_amd as pk
+    import synth
+    sc = synth.Scene([synth.torus_body(n_panels, 1.0, eps)])
+    rng = np.random.default_rng(17)
+    sig = torch.from_numpy(rng.standard_normal((sc.n_nodes, 3))).cuda()
+    tn = torch.arange(sc.n_nodes, dtype=torch.int64, device="cuda")
+    T = sc.n_nodes
+    out = dict(workload=f"torus R=1, eps={eps:g}, {n_panels} elements (aspect {2 * np.pi / (n_panels * eps):.0f}), "
+                        f"{T} on-surface targets, FP64, quad_tol 1e-12")
+    res = {}
+    for srule in ("whole", "general"):
+        ev = pk.Evaluator(quad_tol=1e-12, srule=srule)
+        ev.set_geometry(sc)
+        usl = torch.empty((T, 3), dtype=torch.float64, device="cuda")
+        udl = torch.empty((T, 3), dtype=torch.float64, device="cuda")
+        ev.eval(sig, None, tn, usl, udl)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ev.eval(sig, None, tn, usl, udl)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        st = ev.stats()
+        res[srule] = (usl.clone(), udl.clone())
+        out[srule] = dict(ms_per_eval=1e3 * dt, value=T / dt, special_quadrature_ms=st["ms"]["corr_full"],
+                          s_nodes=st.get("s_nodes"), pairs_whole_rule=st.get("pairs_whole_rule"),
+                          pairs_full=st.get("pairs_full"), flags=ev.flags())
+        ev.close()
+    out["rel_diff"] = {name: float((res["whole"][k] - res["general"][k]).abs().max() / res["general"][k].abs().max())
+                       for k, name in ((0, "S"), (1, "D"))}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -301,6 +343,11 @@ def main():
         # the same density, checked against the headline result
         log("bench: matrix plan")
         out["matrix_apply"] = run_matrix(sc, sig, tn, 1e-12, a.mode_steps, (usl_ref, udl_ref))
+    if not a.no_modes and a.workload == "pipe100-spheres200" and a.precision == "fp64":
+        # slender elements: whole-element singular s-rules against the
+        # general rule on a slender torus's on-surface targets
+        log("bench: slender torus, whole-element and general s-rules")
+        out["slender_torus"] = run_slender(a.mode_steps)
     if not a.no_cpu_baseline:
         log("bench: timing the CPU oracle on a sample")
         out["cpu_baseline"] = cpu_baseline(base_sc, 240, a.cpu_seconds)

@@ -102,23 +102,45 @@ typedef enum { CSBQ_GATE_CRITERION = 0, CSBQ_GATE_MLP = 1 } csbq_gate_mode;
    three; everything else (geometry, targets, tables, corrections) is shared. */
 typedef enum { CSBQ_KERNEL_STOKES = 0, CSBQ_KERNEL_LAPLACE = 1 } csbq_kernel;
 
+/* s-rule of an on-surface target's own element (Section 3.2.4).
+   GENERAL: Gauss-Legendre panels refined dyadically toward the target plus
+   the log-singular rule (p log + q) on its two sides.  The whole-element
+   singular rules (the section's second part) are one generalised Chebyshev
+   rule over the whole element per target GL index, built offline per
+   Appendix B (tables/srules.bin): per aspect bracket [2^b, 2^(b+1)), b =
+   2..30, from straight cylinders of constant radius, with the aspect at the
+   target A = 2 hw |x_c'(s0)| / eps(s0) (hw the panel's half-length in s);
+   and one set for a sphere given as one element in its polar-angle
+   parametrisation (x_c = c + a cos(pi t) axis, eps = a sin(pi t), t the
+   panel's normalised parameter, constant e1).
+   AUTO (default): the whole-element rules where the element is one of the
+   shapes they were built from (a straight cylinder of constant radius, speed
+   and e1 whose aspect has a bracket; such a sphere), the general rule
+   elsewhere.  WHOLE: also the cylinder rules on every other open element
+   whose aspect has a bracket (the paper's use; curved and tapered elements
+   are outside the rules' family, so their accuracy is not quad_tol's). */
+typedef enum { CSBQ_SRULE_AUTO = 0, CSBQ_SRULE_WHOLE = 1, CSBQ_SRULE_GENERAL = 2 } csbq_srule;
+
 typedef struct {
     double quad_tol;       /* per-element quadrature tolerance (relative); <= 0 selects 1e-12 */
     int32_t precision;     /* csbq_precision: FP64, or mixed (FP32 far field, FP64 near corrections) */
     int32_t gate;          /* csbq_gate_mode: the error-estimate criterion, or the learned gate */
     int32_t device;        /* HIP device ordinal */
     void* stream;          /* hipStream_t to enqueue on; NULL = a stream owned by the context */
-    const char* table_dir; /* directory holding rules.bin; NULL = the package's tables/ */
+    const char* table_dir; /* directory holding rules.bin (and srules.bin); NULL = the package's tables/ */
     int32_t kernel;        /* csbq_kernel: the Stokes layers, or the Laplace layers (FP64, criterion gate only) */
+    int32_t srule;         /* csbq_srule: the own element's s-rule for on-surface targets */
 } csbq_options;
 
 /* Fill *opt with defaults (quad_tol 1e-12, FP64, criterion gate, device 0,
-   own stream, packaged tables). */
+   own stream, packaged tables, Stokes layers, CSBQ_SRULE_AUTO). */
 void csbq_default_options(csbq_options* opt);
 
 /* Create a context: selects the device, creates/adopts the stream and loads
-   the quadrature tables (theta-rules of Section 3.2.2 and the log rule of
-   Section 3.2.4, generated offline per Appendix B).  *out receives the handle. */
+   the quadrature tables (theta-rules of Section 3.2.2, the log rule of
+   Section 3.2.4 and, unless CSBQ_SRULE_GENERAL, its whole-element singular
+   rules; generated offline per Appendix B).  *out receives the handle;
+   CSBQ_ETABLE if a table is missing or malformed. */
 int csbq_create(const csbq_options* opt, csbq_ctx** out);
 
 /* Release every resource of the context (the adopted stream is not destroyed). */

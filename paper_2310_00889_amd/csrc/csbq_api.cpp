@@ -138,6 +138,7 @@ void csbq_default_options(csbq_options* opt)
     opt->stream = nullptr;
     opt->table_dir = nullptr;
     opt->kernel = CSBQ_KERNEL_STOKES;
+    opt->srule = CSBQ_SRULE_AUTO;
 }
 
 const char* csbq_last_error(const csbq_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
@@ -213,6 +214,116 @@ static int load_tables(csbq_ctx* ctx)
     return CSBQ_OK;
 }
 
+// Whole-element singular s-rules (Section 3.2.4, second part), written by
+// tables/gen_srules.py: per cylinder aspect bracket and target GL index, then
+// (optionally) per target GL index of the sphere element, node offsets from
+// the GL node in the element variable v in [-1, 1] and their weights.
+static int load_srules(csbq_ctx* ctx)
+{
+    const std::string path = ctx->table_dir + "/srules.bin";
+    FILE* f = std::fopen(path.c_str(), "rb");
+    if (!f) return ctx->fail(CSBQ_ETABLE, "cannot open " + path);
+    char magic[8];
+    int32_t ver, ns, b_lo, nb, nsph, l0, npoly;
+    double tol;
+    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "CSBQSRL2", 8) == 0 &&
+              std::fread(&ver, 4, 1, f) == 1 && std::fread(&ns, 4, 1, f) == 1 && std::fread(&b_lo, 4, 1, f) == 1 &&
+              std::fread(&nb, 4, 1, f) == 1 && std::fread(&nsph, 4, 1, f) == 1 && std::fread(&l0, 4, 1, f) == 1 &&
+              std::fread(&npoly, 4, 1, f) == 1 && std::fread(&tol, 8, 1, f) == 1 && ns == NS && nb >= 0 &&
+              nb <= 64 && (nb == 0 || (b_lo >= 2 && b_lo + nb <= 31)) && (nsph == 0 || nsph == 1) && l0 >= 0 &&
+              l0 <= NT;
+    std::vector<int> off(1, 0);
+    std::vector<double> d, w;
+    for (int k = 0; ok && k < (nb + nsph) * NS; ++k) {
+        int32_t m;
+        ok = std::fread(&m, 4, 1, f) == 1 && m > 0 && m <= MAXWHOLE;
+        if (!ok) break;
+        const size_t o = d.size();
+        d.resize(o + m);
+        w.resize(o + m);
+        ok = std::fread(d.data() + o, 8, m, f) == (size_t)m && std::fread(w.data() + o, 8, m, f) == (size_t)m;
+        // nodes inside the element, off the target, ascending
+        const double xi = ctx->gx[k % NS];
+        for (int j = 0; ok && j < m; ++j)
+            ok = std::isfinite(d[o + j]) && std::isfinite(w[o + j]) && d[o + j] != 0.0 && xi + d[o + j] > -1.0 &&
+                 xi + d[o + j] < 1.0 && (j == 0 || d[o + j] > d[o + j - 1]);
+        off.push_back((int)d.size());
+    }
+    std::fclose(f);
+    if (!ok) return ctx->fail(CSBQ_ETABLE, "malformed whole-element rule table " + path);
+    ALLOC(ctx->woff, off.size());
+    ALLOC(ctx->wd, d.size() + 1);
+    ALLOC(ctx->ww, w.size() + 1);
+    HIPC(hipMemcpy(ctx->woff.p, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice));
+    if (!d.empty()) {
+        HIPC(hipMemcpy(ctx->wd.p, d.data(), d.size() * 8, hipMemcpyHostToDevice));
+        HIPC(hipMemcpy(ctx->ww.p, w.data(), w.size() * 8, hipMemcpyHostToDevice));
+    }
+    ctx->wb_lo = b_lo;
+    ctx->wnb = nb;
+    ctx->wl0 = l0;
+    ctx->wsph = nsph ? nb : -1;
+    return CSBQ_OK;
+}
+
+static RuleArgs rule_args(const csbq_ctx* ctx)
+{
+    const bool on = ctx->opt.srule != CSBQ_SRULE_GENERAL;
+    return RuleArgs{ctx->roff.p, ctx->rth.p, ctx->rw.p, ctx->nb, ctx->lx.p, ctx->lw.p, ctx->nl, ctx->rcs.p,
+                    ctx->rsn.p, ctx->romc.p, ctx->woff.p, ctx->wd.p, ctx->ww.p, ctx->wb_lo, on ? ctx->wnb : 0,
+                    ctx->wl0, on ? ctx->wsph : -1, ctx->opt.srule == CSBQ_SRULE_WHOLE ? 1 : 0};
+}
+
+// Shape of an element for the whole-element singular s-rules, from its GL
+// samples (xc [NS][3], eps [NS], e1 [NS][3] at the nodes gx of [-1, 1]):
+// SHAPE_CYLINDER if x_c is linear in v (constant speed along a straight
+// line) with constant eps and e1; SHAPE_SPHERE if x_c = c + a cos(pi t) q,
+// eps = a sin(pi t), t = (v + 1)/2, |q| = 1, with constant e1; both to 1e-12
+// of the element's size.  SHAPE_OTHER otherwise.
+static int element_shape(const double* xc, const double* eps, const double* e1, const double* gx)
+{
+    auto n3 = [](const double* v) { return std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]); };
+    const double tol = 1e-12;
+    const double e1n = n3(e1);
+    for (int i = 1; i < NS; ++i)
+        for (int d = 0; d < 3; ++d)
+            if (!(std::fabs(e1[3 * i + d] - e1[d]) <= tol * e1n)) return SHAPE_OTHER;
+    // straight cylinder: x_c(v) = m + v h
+    {
+        double h[3], m[3];
+        for (int d = 0; d < 3; ++d) {
+            h[d] = (xc[3 * (NS - 1) + d] - xc[d]) / (gx[NS - 1] - gx[0]);
+            m[d] = xc[d] - gx[0] * h[d];
+        }
+        const double size = n3(h) + eps[0];
+        bool ok = n3(h) > 0.0;
+        for (int i = 0; ok && i < NS; ++i) {
+            ok = std::fabs(eps[i] - eps[0]) <= tol * size;
+            for (int d = 0; ok && d < 3; ++d) ok = std::fabs(xc[3 * i + d] - (m[d] + gx[i] * h[d])) <= tol * size;
+        }
+        if (ok) return SHAPE_CYLINDER;
+    }
+    // sphere: x_c = c + a cos(pi t) q, eps = a sin(pi t)
+    {
+        const double PI_ = 3.14159265358979323846;
+        const double c0 = std::cos(PI_ * 0.5 * (gx[0] + 1.0)), c1 = std::cos(PI_ * 0.5 * (gx[NS - 1] + 1.0));
+        double aq[3], c[3];
+        for (int d = 0; d < 3; ++d) {
+            aq[d] = (xc[d] - xc[3 * (NS - 1) + d]) / (c0 - c1);
+            c[d] = xc[d] - c0 * aq[d];
+        }
+        const double a = n3(aq);
+        bool ok = a > 0.0;
+        for (int i = 0; ok && i < NS; ++i) {
+            const double t = PI_ * 0.5 * (gx[i] + 1.0);
+            ok = std::fabs(eps[i] - a * std::sin(t)) <= tol * a;
+            for (int d = 0; ok && d < 3; ++d) ok = std::fabs(xc[3 * i + d] - (c[d] + std::cos(t) * aq[d])) <= tol * a;
+        }
+        if (ok) return SHAPE_SPHERE;
+    }
+    return SHAPE_OTHER;
+}
+
 int csbq_create(const csbq_options* opt, csbq_ctx** out)
 {
     if (!out) return CSBQ_EINVAL;
@@ -237,6 +348,11 @@ int csbq_create(const csbq_options* opt, csbq_ctx** out)
     if ((ctx->opt.kernel != CSBQ_KERNEL_STOKES && ctx->opt.kernel != CSBQ_KERNEL_LAPLACE) ||
         (ctx->opt.kernel == CSBQ_KERNEL_LAPLACE &&
          (ctx->opt.precision != CSBQ_FP64 || ctx->opt.gate != CSBQ_GATE_CRITERION))) {
+        delete ctx;
+        return CSBQ_EINVAL;
+    }
+    if (ctx->opt.srule != CSBQ_SRULE_AUTO && ctx->opt.srule != CSBQ_SRULE_WHOLE &&
+        ctx->opt.srule != CSBQ_SRULE_GENERAL) {
         delete ctx;
         return CSBQ_EINVAL;
     }
@@ -275,6 +391,7 @@ int csbq_create(const csbq_options* opt, csbq_ctx** out)
         return CSBQ_EHIP;
     }
     int rc = load_tables(ctx);
+    if (!rc && ctx->opt.srule != CSBQ_SRULE_GENERAL) rc = load_srules(ctx);
     if (rc) {
         std::fprintf(stderr, "csbq: %s\n", ctx->err.c_str());
         csbq_destroy(ctx);
@@ -322,6 +439,9 @@ int csbq_destroy(csbq_ctx* ctx)
     ctx->rcs.release();
     ctx->rsn.release();
     ctx->romc.release();
+    ctx->woff.release();
+    ctx->wd.release();
+    ctx->ww.release();
     ctx->g_xc.release();
     ctx->g_eps.release();
     ctx->g_e1.release();
@@ -478,13 +598,17 @@ int csbq_set_geometry_batch(csbq_ctx* ctx, int32_t n_bodies, const int32_t* body
         nsb += np[b] + 1;
     }
     if (E > (1 << 26)) return ctx->fail(CSBQ_EINVAL, "too many panels");
-    std::vector<double> sb(nsb), h_eps((size_t)E * NS);
+    std::vector<double> sb(nsb), h_eps((size_t)E * NS), h_xc((size_t)E * NS * 3), h_e1((size_t)E * NS * 3);
     if (mem == CSBQ_DEVICE) {
         HIPC(hipMemcpy(sb.data(), s_break, nsb * 8, hipMemcpyDeviceToHost));
         HIPC(hipMemcpy(h_eps.data(), eps, h_eps.size() * 8, hipMemcpyDeviceToHost));
+        HIPC(hipMemcpy(h_xc.data(), xc, h_xc.size() * 8, hipMemcpyDeviceToHost));
+        HIPC(hipMemcpy(h_e1.data(), e1, h_e1.size() * 8, hipMemcpyDeviceToHost));
     } else {
         std::memcpy(sb.data(), s_break, nsb * 8);
         std::memcpy(h_eps.data(), eps, h_eps.size() * 8);
+        std::memcpy(h_xc.data(), xc, h_xc.size() * 8);
+        std::memcpy(h_e1.data(), e1, h_e1.size() * 8);
     }
     std::vector<double> sa(E), sc(E);
     std::vector<int> es(E), eb(E), eg(E), gel(G + 1, 0);
@@ -561,6 +685,16 @@ int csbq_set_geometry_batch(csbq_ctx* ctx, int32_t n_bodies, const int32_t* body
         std::vector<ElemInfo> hinf((size_t)E);
         HIPC(hipStreamSynchronize(ctx->stream));
         HIPC(hipMemcpy(hinf.data(), ctx->info.p, (size_t)E * sizeof(ElemInfo), hipMemcpyDeviceToHost));
+        // shapes with tabulated whole-element singular s-rules
+        int64_t nshape[3] = {0, 0, 0};
+        for (int64_t e = 0; e < E; ++e) {
+            hinf[e].shape = element_shape(&h_xc[(size_t)e * NS * 3], &h_eps[(size_t)e * NS], &h_e1[(size_t)e * NS * 3],
+                                          ctx->gx);
+            ++nshape[hinf[e].shape];
+        }
+        HIPC(hipMemcpy(ctx->info.p, hinf.data(), (size_t)E * sizeof(ElemInfo), hipMemcpyHostToDevice));
+        ctx->n_cyl = nshape[SHAPE_CYLINDER];
+        ctx->n_sph = nshape[SHAPE_SPHERE];
         std::vector<int64_t> bo((size_t)E + 1, 0);
         for (int64_t e = 0; e < E; ++e) bo[e + 1] = bo[e] + (hinf[e].fb == 2 ? up_pts(0) : NPE);
         ctx->Nb = bo[E];
@@ -1230,11 +1364,10 @@ int csbq_eval_batch(csbq_ctx* ctx, const double* sigma, int64_t T, const double*
     HIPC(hipEventRecord(ctx->ph[5].b, st));
     // special quadrature corrections
     HIPC(hipEventRecord(ctx->ph[6].a, st));
-    ALLOC(ctx->work, (size_t)4 * nfull + 4);
+    ALLOC(ctx->work, (size_t)WORK_STRIDE * nfull + WORK_STRIDE);
     LCHK(launch_corr_full(st, nfull, ctx->sorted.p + full_start, ctx->pe.p, ctx->pt.p, ctx->xt.p, T, tn, ctx->clq.p, ctx->sh.p,
-                          ctx->info.p, ctx->band.p, ctx->cls.p, ctx->boff.p, ctx->by.p, ctx->bn.p, ctx->bsw.p, ctx->Nb, ctx->roff.p,
-                          ctx->rth.p, ctx->rw.p, ctx->nb, ctx->lx.p, ctx->lw.p, ctx->nl, ctx->rcs.p, ctx->rsn.p,
-                          ctx->romc.p, ctx->gc, ctx->corr.p, ctx->err_d.p, ctx->work.p, mt_max, ctx->ker));
+                          ctx->info.p, ctx->band.p, ctx->cls.p, ctx->boff.p, ctx->by.p, ctx->bn.p, ctx->bsw.p, ctx->Nb,
+                          rule_args(ctx), ctx->gc, ctx->corr.p, ctx->err_d.p, ctx->work.p, mt_max, ctx->ker));
     HIPC(hipEventRecord(ctx->ph[6].b, st));
     // reduction
     HIPC(hipEventRecord(ctx->ph[7].a, st));
@@ -1297,8 +1430,7 @@ static int enqueue_apply(csbq_ctx* ctx, hipStream_t st)
     else
     LCHK(launch_corr_full(st, pl.nfull, ctx->sorted.p + pl.full_start, ctx->pe.p, ctx->pt.p, ctx->xt.p, T, pl.tn,
                           ctx->clq.p, ctx->sh.p, ctx->info.p, ctx->band.p, ctx->cls.p, ctx->boff.p, ctx->by.p,
-                          ctx->bn.p, ctx->bsw.p, ctx->Nb, ctx->roff.p, ctx->rth.p, ctx->rw.p, ctx->nb, ctx->lx.p,
-                          ctx->lw.p, ctx->nl, ctx->rcs.p, ctx->rsn.p, ctx->romc.p, ctx->gc, ctx->corr.p, ctx->err_d.p,
+                          ctx->bn.p, ctx->bsw.p, ctx->Nb, rule_args(ctx), ctx->gc, ctx->corr.p, ctx->err_d.p,
                           ctx->work.p, pl.mt_max, ctx->ker));
     LCHK(launch_reduce(st, T, ctx->tgroup.p, ctx->gnchunk.p, ctx->part.p, ctx->off.p, ctx->tier.p, ctx->corr.p,
                        ctx->usl_d.p, ctx->udl_d.p, ctx->ker));
@@ -1330,13 +1462,12 @@ static int build_matrix(csbq_ctx* ctx)
     if (nfull > 0) {
         const int* listf = ctx->sorted.p + pl.full_start;
         ALLOC(cnt, (size_t)nfull);
-        ALLOC(ctx->work, (size_t)4 * nfull + 4);
+        ALLOC(ctx->work, (size_t)WORK_STRIDE * nfull + WORK_STRIDE);
         MatrixRows mr{nullptr, nullptr, nullptr, cnt.p, ctx->Lup[0].p, ctx->bw.p};
         auto corr_launch = [&](int n, const int* lf, int mode) {
             return launch_corr_full(st, n, lf, ctx->pe.p, ctx->pt.p, ctx->xt.p, pl.T, pl.tn, ctx->clq.p, ctx->sh.p,
                                     ctx->info.p, ctx->band.p, ctx->cls.p, ctx->boff.p, ctx->by.p, ctx->bn.p,
-                                    ctx->bsw.p, ctx->Nb, ctx->roff.p, ctx->rth.p, ctx->rw.p, ctx->nb, ctx->lx.p,
-                                    ctx->lw.p, ctx->nl, ctx->rcs.p, ctx->rsn.p, ctx->romc.p, ctx->gc, ctx->corr.p,
+                                    ctx->bsw.p, ctx->Nb, rule_args(ctx), ctx->gc, ctx->corr.p,
                                     ctx->err_d.p, ctx->work.p, pl.mt_max, ctx->ker, mode, &mr);
         };
         LCHK(corr_launch(nfull, listf, MODE_COUNT));
@@ -1708,11 +1839,10 @@ int csbq_gate_dataset(csbq_ctx* ctx, const double* sigma, int64_t T, const doubl
     HIPC(hipMemcpy(hband.data(), ctx->band.p, hband.size() * 4, hipMemcpyDeviceToHost));
     int mt_max = 0;
     for (int k = 0; k < E; ++k) mt_max = std::max(mt_max, hband[2 * k + 1]);
-    ALLOC(ctx->work, (size_t)4 * P + 4);
+    ALLOC(ctx->work, (size_t)WORK_STRIDE * P + WORK_STRIDE);
     LCHK(launch_corr_full(st, (int)P, ctx->perm.p, ctx->pe.p, ctx->pt.p, ctx->xt.p, T, tn, ctx->clq.p, ctx->sh.p,
                           ctx->info.p, ctx->band.p, ctx->cls.p, ctx->boff.p, ctx->by.p, ctx->bn.p, ctx->bsw.p,
-                          ctx->Nb, ctx->roff.p, ctx->rth.p, ctx->rw.p, ctx->nb, ctx->lx.p, ctx->lw.p, ctx->nl,
-                          ctx->rcs.p, ctx->rsn.p, ctx->romc.p, ctx->gc, cfull.p, ctx->err_d.p, ctx->work.p, mt_max, ctx->ker));
+                          ctx->Nb, rule_args(ctx), ctx->gc, cfull.p, ctx->err_d.p, ctx->work.p, mt_max, ctx->ker));
     DBuf<int8_t> lab;
     ALLOC(lab, (size_t)P + 1);
     LCHK(launch_gate_labels(st, P, cup[0].p, cup[1].p, cup[2].p, cfull.p, thr_s, thr_d, lab.p));
@@ -1761,6 +1891,13 @@ int csbq_stats(const csbq_ctx* ctx, char* buf, int64_t cap)
         s += ", \"theta_rules\": \"" + ctx->table_path.substr(sl == std::string::npos ? 0 : sl + 1) + "\"";
     }
     s += ctx->ker == KER_LAPLACE ? ", \"kernel\": \"laplace\"" : ", \"kernel\": \"stokes\"";
+    s += ctx->opt.srule == CSBQ_SRULE_AUTO ? ", \"srule\": \"auto\""
+         : ctx->opt.srule == CSBQ_SRULE_WHOLE ? ", \"srule\": \"whole\"" : ", \"srule\": \"general\"";
+    if (ctx->have_geom) {
+        std::snprintf(tmp, sizeof tmp, ", \"elements_cylinder\": %lld, \"elements_sphere\": %lld",
+                      (long long)ctx->n_cyl, (long long)ctx->n_sph);
+        s += tmp;
+    }
     if (ctx->plan.valid) {
         std::snprintf(tmp, sizeof tmp, ", \"plan\": {\"matrix\": %s, \"build_ms\": %.3f, \"matrix_bytes\": %lld}",
                       ctx->plan.matrix ? "true" : "false", ctx->plan.build_ms,
@@ -1768,18 +1905,20 @@ int csbq_stats(const csbq_ctx* ctx, char* buf, int64_t cap)
         s += tmp;
     }
     if (ctx->ph_ok && ctx->last_nf > 0) {
-        std::vector<int> wk((size_t)4 * ctx->last_nf);
+        std::vector<int> wk((size_t)WORK_STRIDE * ctx->last_nf);
         if (hipMemcpy(wk.data(), ctx->work.p, wk.size() * sizeof(int), hipMemcpyDeviceToHost) == hipSuccess) {
-            long long nq = 0, nsn = 0, nqm = 0, nsm = 0;
-            for (size_t i = 0; i < wk.size(); i += 4) {
+            long long nq = 0, nsn = 0, nqm = 0, nsm = 0, nwh = 0;
+            for (size_t i = 0; i < wk.size(); i += WORK_STRIDE) {
                 nq += wk[i];
                 nsn += wk[i + 1];
                 nqm += wk[i + 2];
                 nsm += wk[i + 3];
+                nwh += wk[i + 4];
             }
             std::snprintf(tmp, sizeof tmp,
-                          ", \"theta_nodes\": %lld, \"s_nodes\": %lld, \"theta_modes\": %lld, \"s_modes\": %lld",
-                          nq, nsn, nqm, nsm);
+                          ", \"theta_nodes\": %lld, \"s_nodes\": %lld, \"theta_modes\": %lld, \"s_modes\": %lld"
+                          ", \"pairs_whole_rule\": %lld",
+                          nq, nsn, nqm, nsm, nwh);
             s += tmp;
         }
     }

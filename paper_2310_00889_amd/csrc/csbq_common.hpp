@@ -21,6 +21,9 @@ constexpr int GRQ = 8;                 // per grid circle: X(3) t(3) eps, padded
 constexpr int MAXSUB = 96;             // s sub-panels of one special quadrature
 constexpr int MAXRULE = 256;           // nodes of one theta rule
 constexpr int MAXLOG = 64;             // nodes of the log rule
+constexpr int MAXWHOLE = 160;          // nodes of one whole-element singular s-rule
+constexpr int WORK_STRIDE = 5;         // per special-quadrature pair: theta nodes, s-nodes, their mode
+                                       // counts, whole-element rule used (work counters)
 
 // centerline quantity slots (clq[e][q][i], i = GL node)
 enum { Q_X = 0, Q_XP = 3, Q_XPP = 6, Q_E = 9, Q_EP = 10, Q_F = 11, Q_FP = 14 };
@@ -52,7 +55,9 @@ enum : int {
 };
 
 // sub-panel kinds of an s-rule
-enum : int { SUB_GL = 0, SUB_LOG_LO = 1, SUB_LOG_HI = 2 };  // log singularity at lo / at hi
+// (log singularity at lo / at hi; SUB_WHOLE: one tabulated rule over the
+// whole element for an on-surface target, Section 3.2.4)
+enum : int { SUB_GL = 0, SUB_LOG_LO = 1, SUB_LOG_HI = 2, SUB_WHOLE = 3 };
 
 struct ElemInfo {
     double a, c;       // panel interval in s
@@ -64,7 +69,15 @@ struct ElemInfo {
     int32_t body;
     int32_t fb;        // far-field (base) rule: 1 = the element's own nodes, 2 = up_ns(0) x NT rule
     int32_t group;     // geometry of a batch: elements of different groups do not interact
+    int32_t closed;    // the cross-section closes at a panel end
+    int32_t shape;     // SHAPE_*: a shape a whole-element singular s-rule was built from
 };
+
+// element shapes with tabulated whole-element singular s-rules (Section
+// 3.2.4): a straight cylinder of constant radius at constant speed with a
+// constant e1, and a sphere as one element in its polar-angle
+// parametrisation with a constant e1
+enum : int { SHAPE_OTHER = 0, SHAPE_CYLINDER = 1, SHAPE_SPHERE = 2 };
 
 // one block of the smooth sum: up to 256 x (targets per thread) consecutive
 // targets of one group against a chunk of that group's sources

@@ -68,6 +68,13 @@ struct csbq_ctx {
     DBuf<int> roff;
     DBuf<double> rth, rw, lx, lw, rcs, rsn, romc;
     int nb = 0, nl = 0;
+    // whole-element singular s-rules (csbq_srule WHOLE): offsets per (aspect
+    // bracket, target GL index), node offsets and weights; wnb = 0 when the
+    // context uses the general rule
+    DBuf<int> woff;
+    DBuf<double> wd, ww;
+    int wb_lo = 0, wnb = 0, wl0 = 0, wsph = -1;
+    int64_t n_cyl = 0, n_sph = 0;   // elements of the geometry with those shapes
     double gx[NS], gw[NS], lam[NS];
     // geometry
     int E = 0;

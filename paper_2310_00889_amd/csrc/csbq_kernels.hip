@@ -443,8 +443,10 @@ __global__ __launch_bounds__(512) void k_expand(int E, const double* __restrict_
         // for it (closed_fb = 1)
         const double* cp0 = circ + (int64_t)e * NCIRC * CIRQ;
         const double eend = fmin(fabs(cp0[6]), fabs(cp0[(NCIRC - 1) * CIRQ + 6]));
-        inf.fb = (eend < 1e-3 * outv[1]) ? closed_fb : 1;
+        inf.closed = eend < 1e-3 * outv[1];
+        inf.fb = inf.closed ? closed_fb : 1;
         inf.group = egroup[e];
+        inf.shape = SHAPE_OTHER;   // set by the host's shape test
         info[e] = inf;
     }
 }
@@ -1424,6 +1426,17 @@ struct RuleTables {
     const double* lx;     // log rule nodes on (0,1), singular at 0
     const double* lw;
     int nl;
+    // whole-element singular s-rules (Section 3.2.4): set k, target GL index
+    // i has nodes wd[woff[k NS + i] ..) as offsets from the i-th GL node in
+    // the element variable v in [-1, 1], with weights ww for the integral
+    // over v.  Sets 0..wnb-1: cylinders of aspect [2^(wb_lo + k),
+    // 2^(wb_lo + k + 1)); set wsph (if >= 0): the sphere.  wany: the cylinder
+    // rules also on open elements of other shapes.  wnb = 0 and wsph < 0
+    // disable them.
+    const int* woff;
+    const double* wd;
+    const double* ww;
+    int wb_lo, wnb, wl0, wsph, wany;
 };
 
 // Wavefront-wide sum (64 lanes).
@@ -1649,7 +1662,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
     __shared__ int rq_off[SB], rq_step[SB], npt[SB], pref[SB + 1];
     __shared__ double sub_lo[MAXSUB], sub_hi[MAXSUB];
     __shared__ int sub_ty[MAXSUB], soff[MAXSUB + 1];
-    __shared__ int nsub;
+    __shared__ int nsub, wrule;
     // reference GL node i0 (the target's own node, else the node nearest the
     // singularity): E0, Xp0[3], sp0, t0[3], then bn[3] (own) or the target's
     // offset xr[3] = x - x_c(s_i0), and z_ref = xr.t0, k_ref = |xr|^2 - E0^2
@@ -1730,7 +1743,31 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
     if (lane == 0) {
         int ns_ = 0;
         const double a = inf.a, c = inf.c;
-        if (own) {
+        // whole-element singular rule (Section 3.2.4, second part) for an
+        // on-surface target on an open element whose aspect at the target,
+        // A = (element length at the target's speed) / radius = 2 hw |x_c'| / eps,
+        // falls in a tabulated bracket; closed cross-sections (the rules'
+        // cylinders have none) and bands beyond the rules' modes keep the
+        // general form below
+        int wr = -1;
+        if (own && Mt <= rt.wl0) {
+            if (inf.shape == SHAPE_SPHERE && rt.wsph >= 0) {
+                wr = rt.wsph * NS + i0;
+            } else if (rt.wnb > 0 && !inf.closed && (inf.shape == SHAPE_CYLINDER || rt.wany)) {
+                const double A = (c - a) * f0d[4] / f0d[0];
+                int ex;
+                frexp(A, &ex);   // A in [2^(ex-1), 2^ex)
+                const int b = ex - 1 - rt.wb_lo;
+                if (b >= 0 && b < rt.wnb) wr = b * NS + i0;
+            }
+        }
+        wrule = wr;
+        if (wr >= 0) {
+            sub_lo[0] = a;
+            sub_hi[0] = c;
+            sub_ty[0] = SUB_WHOLE;
+            ns_ = 1;
+        } else if (own) {
             // dyadic refinement toward s0 down to ~eps/speed, log-singular
             // panels on both sides of s0 (Section 3.2.4, general form).  The
             // panel size is also cut by the density's Fourier band: the
@@ -1796,7 +1833,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
             }
         }
         soff[0] = 0;
-        for (int k = 0; k < ns_; ++k) soff[k + 1] = soff[k] + (sub_ty[k] == SUB_GL ? NS : rt.nl);
+        for (int k = 0; k < ns_; ++k)
+            soff[k + 1] = soff[k] + (sub_ty[k] == SUB_GL ? NS
+                                    : sub_ty[k] == SUB_WHOLE ? rt.woff[wr + 1] - rt.woff[wr] : rt.nl);
         nsub = ns_;
     }
     __syncthreads();
@@ -1832,6 +1871,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
                 // offset from s_i0 formed from differences (lo - s0 is exact
                 // for nearby sub-panels), not from the rounded absolute s
                 u = own ? s - s0 : (lo - s0) + 0.5 * (hi - lo) * (1.0 + c_gx[m]);
+            } else if (ty == SUB_WHOLE) {
+                // tabulated node offsets from the target's GL node: u is
+                // formed without the absolute parameter
+                const int o = rt.woff[wrule] + m;
+                u = hw * rt.wd[o];
+                s = s0 + u;
+                ws = hw * rt.ww[o];
             } else if (ty == SUB_LOG_LO) {
                 u = (hi - lo) * rt.lx[m];
                 s = lo + u;
@@ -2174,10 +2220,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
         o[3] = b0_;
         o[4] = b1_;
         o[5] = b2_;
-        work[4 * blockIdx.x] = n_theta;
-        work[4 * blockIdx.x + 1] = S;
-        work[4 * blockIdx.x + 2] = n_theta * Mt;
-        work[4 * blockIdx.x + 3] = S * (Mt + 1);
+        int* wk = work + (int64_t)WORK_STRIDE * blockIdx.x;
+        wk[0] = n_theta;
+        wk[1] = S;
+        wk[2] = n_theta * Mt;
+        wk[3] = S * (Mt + 1);
+        wk[4] = wrule >= 0;
     }
 }
 
@@ -2510,15 +2558,16 @@ int launch_corr_up(hipStream_t st, const UpRules& ur, int nwaves, const int* ws,
 int launch_corr_full(hipStream_t st, int nfull, const int* listf, const int* pe, const int* pt, const double* xt,
                      int64_t T, const int64_t* tnode, const double* clq, const double* sh, const ElemInfo* info,
                      const int* band, const double* cls, const int64_t* boff, const double* by, const double* bn,
-                     const double* bsw, int64_t Nb, const int* roff, const double* rth, const double* rw, int nb,
-                     const double* lx, const double* lw, int nl, const double* rcs, const double* rsn,
-                     const double* romc, GateConsts gc, double* corr, int* err, int* work, int mt_max, int ker,
-                     int mode, const MatrixRows* mr)
+                     const double* bsw, int64_t Nb, const RuleArgs& ra, GateConsts gc, double* corr, int* err,
+                     int* work, int mt_max, int ker, int mode, const MatrixRows* mr)
 {
     if (nfull == 0) return 0;
     if (mt_max < 0 || mt_max >= NMODE) return (int)hipErrorInvalidValue;
     if (mode != MODE_DENSITY && (ker != KER_STOKES || !mr)) return (int)hipErrorInvalidValue;
-    RuleTables rt{roff, rth, rw, rcs, rsn, romc, nb, lx, lw, nl};
+    if (ra.wnb < 0 || ((ra.wnb > 0 || ra.wsph >= 0) && (!ra.woff || !ra.wd || !ra.ww)))
+        return (int)hipErrorInvalidValue;
+    RuleTables rt{ra.roff, ra.rth, ra.rw, ra.rcs, ra.rsn, ra.romc, ra.nb, ra.lx, ra.lw, ra.nl,
+                  ra.woff, ra.wd, ra.ww, ra.wb_lo, ra.wnb, ra.wl0, ra.wsph, ra.wany};
     const int cstride = 6 * (mt_max + 1);
     // at least the phase-1 weights and centerline quantities (and the stack)
     const size_t lds = (size_t)SB * (cstride > NS + QVS ? cstride : NS + QVS) * sizeof(double);

@@ -111,13 +111,33 @@ int launch_emat(hipStream_t st, int npairs, const int64_t* roff, const double* V
                 double* Em);
 int launch_emat_apply(hipStream_t st, int npairs, const int* listf, const int* pe, const double* Em, const double* sh,
                       double* corr);
+// the special quadrature's rule tables in device memory: theta-rules per
+// distance bracket (offsets, nodes, weights, and cos, sin, 1 - cos of every
+// node), the log rule, and the whole-element singular s-rules per (set,
+// target GL index): wnb cylinder aspect brackets from 2^wb_lo, the sphere
+// set wsph (-1: none), wany = 1 to apply the cylinder rules to every open
+// element (wnb = 0 and wsph = -1: not used)
+struct RuleArgs {
+    const int* roff;
+    const double* rth;
+    const double* rw;
+    int nb;
+    const double* lx;
+    const double* lw;
+    int nl;
+    const double* rcs;
+    const double* rsn;
+    const double* romc;
+    const int* woff;
+    const double* wd;
+    const double* ww;
+    int wb_lo, wnb, wl0, wsph, wany;
+};
 int launch_corr_full(hipStream_t st, int nfull, const int* listf, const int* pe, const int* pt, const double* xt,
                      int64_t T, const int64_t* tnode, const double* clq, const double* sh, const ElemInfo* info,
                      const int* band, const double* cls, const int64_t* boff, const double* by, const double* bn,
-                     const double* bsw, int64_t Nb, const int* roff, const double* rth, const double* rw, int nb,
-                     const double* lx, const double* lw, int nl, const double* rcs, const double* rsn,
-                     const double* romc, GateConsts gc, double* corr, int* err, int* work, int mt_max, int ker,
-                     int mode = MODE_DENSITY, const MatrixRows* mr = nullptr);
+                     const double* bsw, int64_t Nb, const RuleArgs& ra, GateConsts gc, double* corr, int* err,
+                     int* work, int mt_max, int ker, int mode = MODE_DENSITY, const MatrixRows* mr = nullptr);
 int launch_reduce(hipStream_t st, int64_t T, const int* tgroup, const int* gnchunk, const double* part,
                   const int64_t* off, const int8_t* tier, const double* corr, double* usl, double* udl, int ker);
 // scalar density into component 0 of a [N][3] array (the Laplace layers)

@@ -145,6 +145,33 @@ def torus_body(n_panels=8, R=1.0, radius=0.25, ns=NS) -> Body:
     return b
 
 
+def straight_tube_body(n_panels=4, length=2.0, radius=1e-2, ns=NS) -> Body:
+    """Open straight tube along z: x_c(s) = (0, 0, length s), constant radius,
+    e1 = x (every panel a straight cylinder of constant radius)."""
+    sb = np.linspace(0.0, 1.0, n_panels + 1)
+    s = panel_gl_points(sb, ns)
+    xc = np.stack([np.zeros_like(s), np.zeros_like(s), length * s], axis=-1)
+    eps = np.full_like(s, radius)
+    e1 = np.zeros_like(xc)
+    e1[..., 0] = 1.0
+    return Body(sb, xc, eps, e1, 1, "tube")
+
+
+def wavy_ring_body(n_panels=8, R=1.0, radius=1e-2, taper=0.3, ns=NS) -> Body:
+    """Closed slender loop that is neither planar nor of constant radius:
+    x_c(s) = (R + 0.1 R cos 3u) (cos u, sin u, 0) + 0.15 R sin 2u z, u = 2 pi s,
+    eps = radius (1 + taper cos 4u), e1 = z (re-orthonormalised by the
+    evaluators against the tangent)."""
+    sb = np.linspace(0.0, 1.0, n_panels + 1)
+    u = 2 * math.pi * panel_gl_points(sb, ns)
+    rr = R * (1.0 + 0.1 * np.cos(3 * u))
+    xc = np.stack([rr * np.cos(u), rr * np.sin(u), 0.15 * R * np.sin(2 * u)], axis=-1)
+    eps = radius * (1.0 + taper * np.cos(4 * u))
+    e1 = np.zeros_like(xc)
+    e1[..., 2] = 1.0
+    return Body(sb, xc, eps, e1, 1, "ring")
+
+
 # --------------------------------------------------------------------------
 # densities
 # --------------------------------------------------------------------------

@@ -38,3 +38,23 @@ def test_default_options_without_device():
     opt = pk._Options()
     lib.csbq_default_options(C.byref(opt))
     assert opt.quad_tol == 1e-12 and opt.precision == 0 and opt.device == 0
+    assert opt.kernel == pk.CSBQ_KERNEL_STOKES and opt.srule == pk.CSBQ_SRULE_AUTO
+
+
+def test_options_struct_matches_header():
+    """The binding's options struct has the header's fields in the header's
+    order (a missing or reordered field would shift every later one)."""
+    import paper_2310_00889_amd as pk
+    src = open(os.path.join(ROOT, "include", "csbq.h")).read()
+    body = re.search(r"typedef struct \{([^}]*)\} csbq_options;", src, flags=re.S).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    names = re.findall(r"(\w+)\s*;", body)
+    assert names == [f[0] for f in pk._Options._fields_]
+
+
+def test_unknown_srule_refused_before_the_library():
+    import paper_2310_00889_amd as pk
+    if not os.path.exists(pk.LIB_PATH):
+        pytest.skip("libcsbq.so not built")
+    with pytest.raises(pk.CsbqError):
+        pk.Evaluator(srule="dyadic-only")
