@@ -113,12 +113,14 @@ typedef enum { CSBQ_KERNEL_STOKES = 0, CSBQ_KERNEL_LAPLACE = 1 } csbq_kernel;
    and one set for a sphere given as one element in its polar-angle
    parametrisation (x_c = c + a cos(pi t) axis, eps = a sin(pi t), t the
    panel's normalised parameter, constant e1).
-   AUTO (default): the whole-element rules where the element is one of the
-   shapes they were built from (a straight cylinder of constant radius, speed
-   and e1 whose aspect has a bracket; such a sphere), the general rule
-   elsewhere.  WHOLE: also the cylinder rules on every other open element
-   whose aspect has a bracket (the paper's use; curved and tapered elements
-   are outside the rules' family, so their accuracy is not quad_tol's). */
+   AUTO (default): the sphere rules on such spheres; the cylinder rules on
+   open elements whose aspect has a bracket and that are close enough to the
+   rules' family to keep their accuracy (constant speed |x_c'| to 1e-9, bend
+   = largest curvature x element length <= 0.06, radius varying by <= 10 %,
+   e1 turning by <= 0.25 rad over the element); the general rule elsewhere.
+   WHOLE: the cylinder rules on every open element whose aspect has a
+   bracket (the paper's use; more bent or unevenly parametrised elements lie
+   outside the rules' family, so their accuracy is not quad_tol's). */
 typedef enum { CSBQ_SRULE_AUTO = 0, CSBQ_SRULE_WHOLE = 1, CSBQ_SRULE_GENERAL = 2 } csbq_srule;
 
 typedef struct {
@@ -139,8 +141,11 @@ void csbq_default_options(csbq_options* opt);
 /* Create a context: selects the device, creates/adopts the stream and loads
    the quadrature tables (theta-rules of Section 3.2.2, the log rule of
    Section 3.2.4 and, unless CSBQ_SRULE_GENERAL, its whole-element singular
-   rules; generated offline per Appendix B).  *out receives the handle;
-   CSBQ_ETABLE if a table is missing or malformed. */
+   rules; generated offline per Appendix B): rules.bin and srules.bin (built
+   to 1e-13 and 1e-12), or with quad_tol >= 1e-8 rules_t8.bin and
+   srules_t8.bin (built to 1e-8, fewer nodes) where the table directory holds
+   them.  *out receives the handle; CSBQ_ETABLE if a table is missing or
+   malformed. */
 int csbq_create(const csbq_options* opt, csbq_ctx** out);
 
 /* Release every resource of the context (the adopted stream is not destroyed). */
@@ -394,7 +399,8 @@ int csbq_gate_dataset(csbq_ctx* ctx, const double* sigma, int64_t n_tgt, const d
                       double label_tol, int64_t cap, float* feat, int8_t* label, int8_t* crit, int64_t* n_out);
 
 /* Statistics of the last csbq_eval as a JSON object (phase times in ms from
-   HIP events, pair counts per correction tier, the theta-rule table in use).
+   HIP events, pair counts per correction tier, s- and theta-node counts, the
+   rule tables in use).  Blocks until the context's stream has drained.
    Writes at most cap bytes including the terminating zero. */
 int csbq_stats(const csbq_ctx* ctx, char* buf, int64_t cap);
 

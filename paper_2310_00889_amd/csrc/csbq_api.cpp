@@ -143,9 +143,26 @@ void csbq_default_options(csbq_options* opt)
 
 const char* csbq_last_error(const csbq_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
+static bool file_exists(const std::string& path)
+{
+    FILE* f = std::fopen(path.c_str(), "rb");
+    if (f) std::fclose(f);
+    return f != nullptr;
+}
+
+// Rule tables of a context: with quad_tol >= 1e-8 the ones built to 1e-8
+// (rules_t8.bin, srules_t8.bin: fewer nodes) where the table directory holds
+// them, else those built to 1e-13 / 1e-12 (rules.bin, srules.bin).
+static std::string table_name(const csbq_ctx* ctx, const char* base)
+{
+    const std::string loose = std::string(base) + "_t8.bin";
+    if (ctx->opt.quad_tol >= 1e-8 && file_exists(ctx->table_dir + "/" + loose)) return loose;
+    return std::string(base) + ".bin";
+}
+
 static int load_tables(csbq_ctx* ctx)
 {
-    const std::string path = ctx->table_dir + "/rules.bin";
+    const std::string path = ctx->table_dir + "/" + table_name(ctx, "rules");
     ctx->table_path = path;
     FILE* f = std::fopen(path.c_str(), "rb");
     if (!f) return ctx->fail(CSBQ_ETABLE, "cannot open " + path);
@@ -220,7 +237,8 @@ static int load_tables(csbq_ctx* ctx)
 // the GL node in the element variable v in [-1, 1] and their weights.
 static int load_srules(csbq_ctx* ctx)
 {
-    const std::string path = ctx->table_dir + "/srules.bin";
+    const std::string path = ctx->table_dir + "/" + table_name(ctx, "srules");
+    ctx->srule_path = path;
     FILE* f = std::fopen(path.c_str(), "rb");
     if (!f) return ctx->fail(CSBQ_ETABLE, "cannot open " + path);
     char magic[8];
@@ -275,36 +293,34 @@ static RuleArgs rule_args(const csbq_ctx* ctx)
 }
 
 // Shape of an element for the whole-element singular s-rules, from its GL
-// samples (xc [NS][3], eps [NS], e1 [NS][3] at the nodes gx of [-1, 1]):
-// SHAPE_CYLINDER if x_c is linear in v (constant speed along a straight
-// line) with constant eps and e1; SHAPE_SPHERE if x_c = c + a cos(pi t) q,
-// eps = a sin(pi t), t = (v + 1)/2, |q| = 1, with constant e1; both to 1e-12
-// of the element's size.  SHAPE_OTHER otherwise.
-static int element_shape(const double* xc, const double* eps, const double* e1, const double* gx)
+// samples (xc [NS][3], eps [NS], e1 [NS][3] at the nodes gx of [-1, 1], D the
+// differentiation matrix there):
+//  * SHAPE_SPHERE: x_c = c + a cos(pi t) q, eps = a sin(pi t), t = (v + 1)/2,
+//    |q| = 1, with constant e1, to 1e-12 of the element's size (the sphere
+//    rules' family exactly);
+//  * SHAPE_CYLINDER: constant speed |x_c'| (to 1e-9), bend (largest curvature
+//    times the element's length) at most 0.06, radius varying by at most
+//    10 % and e1 turning by at most 0.25 rad over the element, none of which
+//    moved the cylinder rules by more than ~1e-13 in measurements (the rules
+//    are exact on straight cylinders of constant radius; at bend 0.13 they
+//    missed by 1.5e-12, at 0.79 by 7e-9; a 0.1 % speed variation cost 1e-10);
+//  * SHAPE_OTHER otherwise.
+static int element_shape(const double* xc, const double* eps, const double* e1, const double* gx, const double* D)
 {
-    auto n3 = [](const double* v) { return std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]); };
-    const double tol = 1e-12;
-    const double e1n = n3(e1);
-    for (int i = 1; i < NS; ++i)
-        for (int d = 0; d < 3; ++d)
-            if (!(std::fabs(e1[3 * i + d] - e1[d]) <= tol * e1n)) return SHAPE_OTHER;
-    // straight cylinder: x_c(v) = m + v h
+    auto dot3 = [](const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; };
+    auto n3 = [&](const double* v) { return std::sqrt(dot3(v, v)); };
+    auto cross3 = [](const double* a, const double* b, double* c) {
+        c[0] = a[1] * b[2] - a[2] * b[1];
+        c[1] = a[2] * b[0] - a[0] * b[2];
+        c[2] = a[0] * b[1] - a[1] * b[0];
+    };
+    // sphere: x_c = c + a cos(pi t) q, eps = a sin(pi t), constant e1
     {
-        double h[3], m[3];
-        for (int d = 0; d < 3; ++d) {
-            h[d] = (xc[3 * (NS - 1) + d] - xc[d]) / (gx[NS - 1] - gx[0]);
-            m[d] = xc[d] - gx[0] * h[d];
-        }
-        const double size = n3(h) + eps[0];
-        bool ok = n3(h) > 0.0;
-        for (int i = 0; ok && i < NS; ++i) {
-            ok = std::fabs(eps[i] - eps[0]) <= tol * size;
-            for (int d = 0; ok && d < 3; ++d) ok = std::fabs(xc[3 * i + d] - (m[d] + gx[i] * h[d])) <= tol * size;
-        }
-        if (ok) return SHAPE_CYLINDER;
-    }
-    // sphere: x_c = c + a cos(pi t) q, eps = a sin(pi t)
-    {
+        const double tol = 1e-12;
+        const double e1n = n3(e1);
+        bool ok = e1n > 0.0;
+        for (int i = 1; ok && i < NS; ++i)
+            for (int d = 0; ok && d < 3; ++d) ok = std::fabs(e1[3 * i + d] - e1[d]) <= tol * e1n;
         const double PI_ = 3.14159265358979323846;
         const double c0 = std::cos(PI_ * 0.5 * (gx[0] + 1.0)), c1 = std::cos(PI_ * 0.5 * (gx[NS - 1] + 1.0));
         double aq[3], c[3];
@@ -313,7 +329,7 @@ static int element_shape(const double* xc, const double* eps, const double* e1, 
             c[d] = xc[d] - c0 * aq[d];
         }
         const double a = n3(aq);
-        bool ok = a > 0.0;
+        ok = ok && a > 0.0;
         for (int i = 0; ok && i < NS; ++i) {
             const double t = PI_ * 0.5 * (gx[i] + 1.0);
             ok = std::fabs(eps[i] - a * std::sin(t)) <= tol * a;
@@ -321,7 +337,53 @@ static int element_shape(const double* xc, const double* eps, const double* e1, 
         }
         if (ok) return SHAPE_SPHERE;
     }
-    return SHAPE_OTHER;
+    // cylinder rules: constant speed, small bend, taper and e1 turn
+    double xp[NS][3], xpp[NS][3];
+    for (int i = 0; i < NS; ++i)
+        for (int d = 0; d < 3; ++d) {
+            double s1 = 0.0;
+            for (int j = 0; j < NS; ++j) s1 += D[i * NS + j] * xc[3 * j + d];
+            xp[i][d] = s1;
+        }
+    for (int i = 0; i < NS; ++i)
+        for (int d = 0; d < 3; ++d) {
+            double s2 = 0.0;
+            for (int j = 0; j < NS; ++j) s2 += D[i * NS + j] * xp[j][d];
+            xpp[i][d] = s2;
+        }
+    double spmin = 1e300, spmax = 0.0, spsum = 0.0, kmax = 0.0, emin = 1e300, emax = 0.0;
+    for (int i = 0; i < NS; ++i) {
+        const double sp = n3(xp[i]);
+        double cr[3];
+        cross3(xp[i], xpp[i], cr);
+        spmin = std::fmin(spmin, sp);
+        spmax = std::fmax(spmax, sp);
+        spsum += sp;
+        kmax = std::fmax(kmax, n3(cr) / (sp * sp * sp));
+        emin = std::fmin(emin, eps[i]);
+        emax = std::fmax(emax, eps[i]);
+    }
+    const double spm = spsum / NS;
+    if (!(spmin > 0.0) || !(emin > 0.0)) return SHAPE_OTHER;
+    if (spmax - spmin > 1e-9 * spm) return SHAPE_OTHER;
+    if (kmax * 2.0 * spm > 0.06) return SHAPE_OTHER;
+    if (emax > 1.1 * emin) return SHAPE_OTHER;
+    // e1 at both ends, each without its tangential part: the angle between them
+    double u0[3], u1[3];
+    {
+        const double* a = e1;
+        const double* b = e1 + 3 * (NS - 1);
+        const double* t0 = xp[0];
+        const double* t1 = xp[NS - 1];
+        const double at = dot3(a, t0) / dot3(t0, t0), bt = dot3(b, t1) / dot3(t1, t1);
+        for (int d = 0; d < 3; ++d) {
+            u0[d] = a[d] - at * t0[d];
+            u1[d] = b[d] - bt * t1[d];
+        }
+    }
+    const double cu = dot3(u0, u1) / (n3(u0) * n3(u1));
+    if (!(cu >= std::cos(0.25))) return SHAPE_OTHER;
+    return SHAPE_CYLINDER;
 }
 
 int csbq_create(const csbq_options* opt, csbq_ctx** out)
@@ -384,6 +446,7 @@ int csbq_create(const csbq_options* opt, csbq_ctx** out)
     }
     double D[NS * NS], T[NS * NS];
     gl_tables(NS, ctx->gx, ctx->gw, ctx->lam, D, T);
+    std::memcpy(ctx->Dgl, D, sizeof D);
     if (int uc = upload_constants(ctx->gx, ctx->gw, ctx->lam, D, T)) {
         std::fprintf(stderr, "csbq_create: constant upload failed (%d: %s)\n", uc,
                      hipGetErrorString(hipGetLastError()));
@@ -689,7 +752,7 @@ int csbq_set_geometry_batch(csbq_ctx* ctx, int32_t n_bodies, const int32_t* body
         int64_t nshape[3] = {0, 0, 0};
         for (int64_t e = 0; e < E; ++e) {
             hinf[e].shape = element_shape(&h_xc[(size_t)e * NS * 3], &h_eps[(size_t)e * NS], &h_e1[(size_t)e * NS * 3],
-                                          ctx->gx);
+                                          ctx->gx, ctx->Dgl);
             ++nshape[hinf[e].shape];
         }
         HIPC(hipMemcpy(ctx->info.p, hinf.data(), (size_t)E * sizeof(ElemInfo), hipMemcpyHostToDevice));
@@ -1866,6 +1929,10 @@ int csbq_gate_dataset(csbq_ctx* ctx, const double* sigma, int64_t T, const doubl
 int csbq_stats(const csbq_ctx* ctx, char* buf, int64_t cap)
 {
     if (!ctx || !buf || cap <= 0) return CSBQ_EINVAL;
+    // the work counters and phase events belong to work enqueued on the
+    // context's stream, which need not be ordered with the copies below
+    (void)hipSetDevice(ctx->opt.device);
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) (void)hipGetLastError();
     std::string s = "{";
     char tmp[256];
     std::snprintf(tmp, sizeof tmp,
@@ -1891,6 +1958,10 @@ int csbq_stats(const csbq_ctx* ctx, char* buf, int64_t cap)
         s += ", \"theta_rules\": \"" + ctx->table_path.substr(sl == std::string::npos ? 0 : sl + 1) + "\"";
     }
     s += ctx->ker == KER_LAPLACE ? ", \"kernel\": \"laplace\"" : ", \"kernel\": \"stokes\"";
+    if (!ctx->srule_path.empty()) {
+        const size_t sl = ctx->srule_path.find_last_of('/');
+        s += ", \"srule_table\": \"" + ctx->srule_path.substr(sl == std::string::npos ? 0 : sl + 1) + "\"";
+    }
     s += ctx->opt.srule == CSBQ_SRULE_AUTO ? ", \"srule\": \"auto\""
          : ctx->opt.srule == CSBQ_SRULE_WHOLE ? ", \"srule\": \"whole\"" : ", \"srule\": \"general\"";
     if (ctx->have_geom) {

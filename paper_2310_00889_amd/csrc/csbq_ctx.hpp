@@ -59,7 +59,7 @@ struct csbq_ctx {
     int nc() const { return ker == KER_LAPLACE ? 1 : 3; }   // density / output components
     DBuf<double> sig1;      // a scalar density before its expansion into three components
     std::string err;
-    std::string table_dir, table_path;
+    std::string table_dir, table_path, srule_path;
     hipStream_t stream = nullptr;
     bool own_stream = false;
     GateConsts gc{};
@@ -76,6 +76,7 @@ struct csbq_ctx {
     int wb_lo = 0, wnb = 0, wl0 = 0, wsph = -1;
     int64_t n_cyl = 0, n_sph = 0;   // elements of the geometry with those shapes
     double gx[NS], gw[NS], lam[NS];
+    double Dgl[NS * NS];   // differentiation matrix at the GL nodes of [-1, 1]
     // geometry
     int E = 0;
     int64_t N = 0;

@@ -1755,10 +1755,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
                 wr = rt.wsph * NS + i0;
             } else if (rt.wnb > 0 && !inf.closed && (inf.shape == SHAPE_CYLINDER || rt.wany)) {
                 const double A = (c - a) * f0d[4] / f0d[0];
-                int ex;
-                frexp(A, &ex);   // A in [2^(ex-1), 2^ex)
-                const int b = ex - 1 - rt.wb_lo;
-                if (b >= 0 && b < rt.wnb) wr = b * NS + i0;
+                if (A > 0.0 && A < 1e300) {
+                    int ex;
+                    frexp(A, &ex);   // A in [2^(ex-1), 2^ex)
+                    const int b = ex - 1 - rt.wb_lo;
+                    if (b >= 0 && b < rt.wnb) wr = b * NS + i0;
+                }
             }
         }
         wrule = wr;

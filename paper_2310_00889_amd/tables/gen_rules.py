@@ -244,9 +244,11 @@ def read_tables(path):
 
 def _one(args):
     b, l0, tol, check = args
-    t0 = time.time()
-    th, om = build_theta_rule(b, l0, tol)
-    err = check_theta_rule(b, th, om, l0) if check else float("nan")
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(1):   # one BLAS thread per worker process
+        t0 = time.time()
+        th, om = build_theta_rule(b, l0, tol)
+        err = check_theta_rule(b, th, om, l0) if check else float("nan")
     return b, th, om, err, time.time() - t0
 
 

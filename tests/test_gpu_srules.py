@@ -144,3 +144,64 @@ def test_laplace_takes_the_same_rules():
         ev.close()
     print(f"laplace tube eps 1e-2: S {_rel(us, uso):.2e} D {_rel(ud, udo):.2e}", flush=True)
     assert _rel(us, uso) < GATE and _rel(ud, udo) < GATE
+
+
+def test_tables_follow_the_tolerance():
+    """Contexts with quad_tol >= 1e-8 load the rule tables built to 1e-8 (fewer
+    nodes); at quad_tol 1e-8, the tightest they serve, an FP64 evaluation of a
+    pipe section with spheres (on- and off-surface targets, full-band density)
+    stays within 1e-7 of the oracle."""
+    import paper_2310_00889_amd as pk
+    sc = synth.small_pipe_scene(n_panels=6, n_spheres=3)
+    rng = np.random.default_rng(8)
+    sig = rng.standard_normal((sc.n_nodes, 3))
+    tn = rng.choice(sc.n_nodes, 150, replace=False).astype(np.int64)
+    y, n, _ = oracle.nodes(sc)
+    k = rng.choice(sc.n_nodes, 150, replace=False)
+    x = y[k] + 10.0 ** rng.uniform(-3, -1, 150)[:, None] * n[k] * np.where(rng.random(150) < 0.5, 1, -1)[:, None]
+    names = {}
+    for tol in (1e-12, 1e-8, 1e-7):
+        ev = pk.Evaluator(quad_tol=tol)
+        try:
+            ev.set_geometry(sc)
+            if tol == 1e-8:
+                us, ud = ev.eval(sig, None, tn)
+                assert ev.flags() == 0
+                uso, udo = oracle.evaluate(sc, sig, None, tn)
+                xs, xd = ev.eval(sig, x, None)
+                xso, xdo = oracle.evaluate(sc, sig, x, -np.ones(150, np.int64))
+                errs = (_rel(us, uso), _rel(ud, udo), _rel(xs, xso), _rel(xd, xdo))
+                print("quad_tol 1e-8 with the 1e-8 tables: on S %.1e D %.1e, off S %.1e D %.1e" % errs, flush=True)
+                assert max(errs) < 1e-7
+            st = ev.stats()
+            names[tol] = (st["theta_rules"], st["srule_table"])
+        finally:
+            ev.close()
+    assert names[1e-12] == ("rules.bin", "srules.bin")
+    assert names[1e-8] == names[1e-7] == ("rules_t8.bin", "srules_t8.bin")
+
+
+def test_finely_discretised_torus_admitted(evs):
+    """AUTO admits the cylinder rules on elements bent by at most 0.06 over
+    their length at constant speed: a torus of 128 elements per turn (bend
+    0.049) takes them on every on-surface target, within the parity bar of
+    the oracle and 1e-12 of the general rule; with 64 elements (bend 0.098)
+    none is admitted."""
+    sc64 = synth.Scene([synth.torus_body(64, 1.0, 1e-3)])
+    evs["auto"].set_geometry(sc64)
+    assert evs["auto"].stats()["elements_cylinder"] == 0
+    sc = synth.Scene([synth.torus_body(128, 1.0, 1e-3)])
+    rng = np.random.default_rng(128)
+    sig = rng.standard_normal((sc.n_nodes, 3))
+    tn = _targets(sc, rng, 12)
+    uso, udo = oracle.evaluate(sc, sig, None, tn)
+    us, ud, st = _run(evs["auto"], sc, sig, tn)
+    assert st["elements_cylinder"] == 128 and st["pairs_whole_rule"] == 12
+    allt = np.arange(sc.n_nodes, dtype=np.int64)
+    ua, va, sa = _run(evs["auto"], sc, sig, allt)
+    ug, vg, sg = _run(evs["general"], sc, sig, allt)
+    print(f"torus 128 elements eps 1e-3: auto vs oracle S {_rel(us, uso):.2e} D {_rel(ud, udo):.2e}; auto vs general "
+          f"on all {sc.n_nodes} nodes S {_rel(ua, ug):.2e} D {_rel(va, vg):.2e}; s-nodes {sa['s_nodes']} vs "
+          f"{sg['s_nodes']}", flush=True)
+    assert _rel(us, uso) < GATE and _rel(ud, udo) < GATE
+    assert _rel(ua, ug) < 1e-12 and _rel(va, vg) < 1e-12

@@ -13,7 +13,9 @@ import gen_rules  # noqa: E402
 
 TDIR = os.path.join(ROOT, "paper_2310_00889_amd", "tables")
 TAB = gen_rules.read_tables(os.path.join(TDIR, "rules.bin"))
-TABLES = {"rules.bin": TAB}
+# the tables built to 1e-13 (rules.bin) and to 1e-8 (rules_t8.bin, loaded by
+# contexts with quad_tol >= 1e-8)
+TABLES = {"rules.bin": TAB, "rules_t8.bin": gen_rules.read_tables(os.path.join(TDIR, "rules_t8.bin"))}
 
 
 @pytest.mark.parametrize("name", sorted(TABLES))
