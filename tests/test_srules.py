@@ -23,15 +23,25 @@ sys.path.insert(0, os.path.join(ROOT, "paper_2310_00889_amd", "tables"))
 import gen_srules  # noqa: E402
 
 pytestmark = pytest.mark.filterwarnings("ignore::scipy.integrate.IntegrationWarning")
-TAB = gen_srules.read_srules(os.path.join(ROOT, "paper_2310_00889_amd", "tables", "srules.bin"))
+TDIR = os.path.join(ROOT, "paper_2310_00889_amd", "tables")
+# the rules built to 1e-12 (srules.bin) and to 1e-8 (srules_t8.bin, loaded by
+# contexts with quad_tol >= 1e-8); each is held to its own bar
+TABLES = {name: gen_srules.read_srules(os.path.join(TDIR, name)) for name in ("srules.bin", "srules_t8.bin")}
+TAB = TABLES["srules.bin"]
+
+
+def _bar(tab):
+    return max(1e-12, 10 * tab["tol"])
 XG = leggauss(16)[0]
 
 
-def test_header_and_node_sets():
-    assert TAB["ns"] == 16 and TAB["b_lo"] == 2 and TAB["b_lo"] + TAB["nb"] - 1 == 30
-    assert TAB["l0"] >= 16 and TAB["np"] >= 16
-    assert TAB["sphere"] is not None and len(TAB["sphere"]) == 16
-    for (b, i), (d, w) in list(TAB["rules"].items()) + [((1, i), r) for i, r in TAB["sphere"].items()]:
+@pytest.mark.parametrize("name", sorted(TABLES))
+def test_header_and_node_sets(name):
+    tab = TABLES[name]
+    assert tab["ns"] == 16 and tab["b_lo"] == 2 and tab["b_lo"] + tab["nb"] - 1 == 30
+    assert tab["l0"] >= 16 and tab["np"] >= 16
+    assert tab["sphere"] is not None and len(tab["sphere"]) == 16
+    for (b, i), (d, w) in list(tab["rules"].items()) + [((1, i), r) for i, r in tab["sphere"].items()]:
         assert 32 <= len(d) <= 160
         x = XG[i] + d
         assert np.all(np.diff(d) > 0) and np.all(d != 0) and np.all((x > -1) & (x < 1))
@@ -77,12 +87,15 @@ def _element_integral(A, xi, l, p):
 CASES = [(2, 7, 0.37), (5, 0, 0.81), (9, 15, 0.05), (13, 4, 0.5), (20, 11, 0.93), (30, 8, 0.21)]
 
 
-@pytest.mark.parametrize("b,i,frac", CASES)
-def test_rule_integrates_modal_greens_function(b, i, frac):
+@pytest.mark.parametrize("name,b,i,frac", [(n,) + c for n in sorted(TABLES) for c in CASES])
+def test_rule_integrates_modal_greens_function(name, b, i, frac):
     """Error relative to the mode-0 integral of |P_p| / R (the family's
-    scale): at most 1e-12 for modes 0, 3 and 16, polynomials P_0 and P_1, at
-    an aspect inside the bracket that the generator did not sample."""
-    d, w = TAB["rules"][(b, i)]
+    scale): at most 1e-12 (the 1e-8 table: 1e-7) for modes 0, 3 and 16,
+    polynomials P_0 and P_1, at an aspect inside the bracket that the
+    generator did not sample."""
+    tab = TABLES[name]
+    bar = _bar(tab)
+    d, w = tab["rules"][(b, i)]
     A = 2.0 ** b * (1.0 + frac)
     xi = XG[i]
     scale = _element_integral(A, xi, 0, 0)
@@ -91,7 +104,7 @@ def test_rule_integrates_modal_greens_function(b, i, frac):
         for p in (0, 1):
             got = np.sum(w * g * ((xi + d) if p else 1.0))
             ref = _element_integral(A, xi, l, p)
-            assert abs(got - ref) < 1e-12 * scale, (b, i, l, p, got, ref, scale)
+            assert abs(got - ref) < bar * scale, (b, i, l, p, got, ref, scale)
 
 
 def _sphere_geometry(v):
@@ -140,18 +153,21 @@ def _sphere_angle_integral(v, i, kind):
                 quad(f, c, math.pi, epsabs=0, epsrel=2e-14, limit=200)[0])
 
 
-@pytest.mark.parametrize("i", [0, 3, 7, 12, 15])
-def test_sphere_rule_closed_forms(i):
+@pytest.mark.parametrize("name,i", [(n, i) for n in sorted(TABLES) for i in (0, 3, 7, 12, 15)])
+def test_sphere_rule_closed_forms(name, i):
     """On the unit sphere, for the target at the i-th GL node: the single
     layer of 1 is 4 pi, that of cos(polar angle) is (4 pi / 3) cos(polar
     angle at the target), the double layer of 1 has magnitude 2 pi.  The
-    interpolated sphere departs from the sphere by ~1e-11, hence the 1e-9."""
-    d, w = TAB["sphere"][i]
+    interpolated sphere departs from the sphere by ~1e-11, hence the 1e-9
+    (the 1e-8 table: 1e-7)."""
+    tab = TABLES[name]
+    bar = max(1e-9, _bar(tab))
+    d, w = tab["sphere"][i]
     v = XG[i] + d
     gS = np.array([_sphere_angle_integral(x, i, "S") for x in v])
     gD = np.array([_sphere_angle_integral(x, i, "D") for x in v])
-    assert abs(np.sum(w * gS) - 4 * np.pi) < 1e-9 * 4 * np.pi
+    assert abs(np.sum(w * gS) - 4 * np.pi) < bar * 4 * np.pi
     t0 = 0.5 * np.pi * (XG[i] + 1.0)
     ct = np.cos(0.5 * np.pi * (v + 1.0))
-    assert abs(np.sum(w * gS * ct) - 4 * np.pi / 3 * math.cos(t0)) < 1e-9 * 4 * np.pi
-    assert abs(abs(np.sum(w * gD)) - 2 * np.pi) < 1e-9 * 2 * np.pi
+    assert abs(np.sum(w * gS * ct) - 4 * np.pi / 3 * math.cos(t0)) < bar * 4 * np.pi
+    assert abs(abs(np.sum(w * gD)) - 2 * np.pi) < bar * 2 * np.pi
