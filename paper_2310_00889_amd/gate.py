@@ -14,7 +14,8 @@ import numpy as np
 from . import GATE_NF, GATE_NO, GATE_NW, TABLE_DIR
 
 H = 64
-DEFAULT_WEIGHTS = os.path.join(TABLE_DIR, "gate_mlp.npz")
+DEFAULT_WEIGHTS = os.path.join(TABLE_DIR, "gate_mlp.npz")            # mixed precision, quad_tol 1e-7
+FP64_WEIGHTS = os.path.join(TABLE_DIR, "gate_mlp_fp64.npz")          # FP64, quad_tol 1e-12
 SHAPES = (("W1", (GATE_NF, H)), ("b1", (H,)), ("W2", (H, H)), ("b2", (H,)), ("W3", (H, H)), ("b3", (H,)),
           ("W4", (H, GATE_NO)), ("b4", (GATE_NO,)))
 

@@ -5,13 +5,16 @@ Training data are made by the method itself on the GPU: random batches of
 pipe-with-spheres geometries of uneven size (panels U{20..60}, spheres
 U{10..120}, radii U(0.1, 0.25), gaps 10**U(-3,-1); seeds disjoint from every
 evaluation workload), evaluated with the criterion gate in mixed precision at
-quad_tol 1e-7.  For every candidate pair the library computes the correction
-with each tier and labels the pair with the cheapest tier that agrees with the
-special quadrature to 1e-8 of the largest |u| (csbq_gate_dataset).  The
-network is trained with Adam on the weighted ordinal cross-entropy (misses,
-i.e. a predicted tier below the label, weighted 4x).
+quad_tol 1e-7 (or in FP64 at the tolerance given).  For every candidate pair
+the library computes the correction with each tier and labels the pair with
+the cheapest tier that agrees with the special quadrature to label_tol of the
+largest |u| (csbq_gate_dataset).  The network is trained with Adam on the
+weighted ordinal cross-entropy (misses, i.e. a predicted tier below the
+label, weighted 4x).
 
     python paper_2310_00889_amd/tables/train_gate.py --out paper_2310_00889_amd/tables/gate_mlp.npz
+    python paper_2310_00889_amd/tables/train_gate.py --precision fp64 --quad-tol 1e-12 --label-tol 1e-13 \
+        --out paper_2310_00889_amd/tables/gate_mlp_fp64.npz
 """
 from __future__ import annotations
 
@@ -40,6 +43,7 @@ def main():
     ap.add_argument("--epochs", type=int, default=24)
     ap.add_argument("--quad-tol", type=float, default=1e-7)
     ap.add_argument("--label-tol", type=float, default=1e-8)
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     a = ap.parse_args()
     import torch
     import synth
@@ -47,7 +51,7 @@ def main():
     from paper_2310_00889_amd import gate
 
     torch.zeros(1, device="cuda")
-    ev = pk.Evaluator(quad_tol=a.quad_tol, precision="mixed")
+    ev = pk.Evaluator(quad_tol=a.quad_tol, precision=a.precision)
     feats, labs, crits = [], [], []
     for b in range(a.batches):
         t0 = time.time()
@@ -78,6 +82,7 @@ def main():
     log(f"below label: {miss:.4f} of pairs; below label and not escalated: {miss_kept:.5f}; "
         f"escalated {float(np.mean(esc)):.3f}")
     gate.save_weights(a.out, w, losses=losses, posw=posw, quad_tol=a.quad_tol, label_tol=a.label_tol,
+                      precision=a.precision,
                       n_train=len(L), label_counts=np.bincount(L, minlength=5),
                       criterion_counts=np.bincount(Cr, minlength=5), confusion=conf, miss=miss,
                       miss_kept=miss_kept, tau_esc=0.05)

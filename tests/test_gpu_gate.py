@@ -338,3 +338,57 @@ def test_config5_held_out_miss_rate():
     assert len(lab) > 100_000
     assert rate < 1e-3
     e.close()
+
+
+def test_fp64_gate_at_1e12_parity():
+    """FP64 at quad_tol 1e-12 with the network trained for it (labels at
+    1e-13): the pipe section on and off the surface against the oracle
+    (1e-10), and the benchmark's workload (all 153,600 nodes of the
+    200-sphere pipe) against the criterion gate on every target (1e-10 of
+    the largest value) plus 24 sampled targets against the oracle."""
+    import torch
+    import paper_2310_00889_amd as pk
+    from paper_2310_00889_amd import gate
+    if not os.path.exists(gate.FP64_WEIGHTS):
+        pytest.skip("no FP64 gate weights in the package")
+    w, meta = gate.load_weights(gate.FP64_WEIGHTS)
+    e = pk.Evaluator(quad_tol=1e-12, gate="mlp")
+    e.gate_load(w, float(meta["tau_esc"]))
+    sc = synth.small_pipe_scene(n_panels=6, n_spheres=3)
+    e.set_geometry(sc)
+    rng = np.random.default_rng(23)
+    tn = rng.choice(sc.n_nodes, 200, replace=False)
+    us, ud = e.eval(sc.sigma, None, tn)
+    uso, udo = oracle.evaluate(sc, None, None, tn)
+    y, n, _ = oracle.nodes(sc)
+    k = rng.choice(sc.n_nodes, 200, replace=False)
+    x = y[k] + 10.0 ** rng.uniform(-3, -0.5, 200)[:, None] * n[k] * np.where(rng.random(200) < 0.5, 1, -1)[:, None]
+    xs, xd = e.eval(sc.sigma, x, None)
+    xso, xdo = oracle.evaluate(sc, None, x, -np.ones(200, np.int64))
+    r = [np.abs(a - b).max() / np.abs(b).max() for a, b in ((us, uso), (ud, udo), (xs, xso), (xd, xdo))]
+    print("fp64 mlp pipe section on S %.1e D %.1e, off S %.1e D %.1e" % tuple(r), e.stats().get("gate_escalated"),
+          flush=True)
+    assert max(r) < 1e-10
+    sc2 = synth.config2()
+    sig = torch.from_numpy(sc2.sigma).cuda()
+    tn2 = torch.from_numpy(sc2.tgt_node).cuda()
+    e.set_geometry(sc2)
+    us, ud = e.eval(sig, None, tn2)
+    torch.cuda.synchronize()
+    us, ud = us.cpu().numpy(), ud.cpu().numpy()
+    e.close()
+    c = pk.Evaluator(quad_tol=1e-12)
+    c.set_geometry(sc2)
+    uc, vc = c.eval(sig, None, tn2)
+    torch.cuda.synchronize()
+    uc, vc = uc.cpu().numpy(), vc.cpu().numpy()
+    c.close()
+    es, ed = np.abs(us - uc).max() / np.abs(uc).max(), np.abs(ud - vc).max() / np.abs(vc).max()
+    nwall = sc2.bodies[0].n_panels * sc2.ns * sc2.nt
+    idx = np.concatenate([rng.choice(nwall, 12, replace=False),
+                          nwall + rng.choice(sc2.n_nodes - nwall, 12, replace=False)])
+    uso, udo = oracle.evaluate(sc2, None, None, sc2.tgt_node[idx])
+    eo = max(np.abs(us[idx] - uso).max() / np.abs(uso).max(), np.abs(ud[idx] - udo).max() / np.abs(udo).max())
+    print(f"config2 fp64 mlp vs criterion, all targets: S {es:.2e} D {ed:.2e}; 24 targets vs oracle {eo:.2e}",
+          flush=True)
+    assert es < 1e-10 and ed < 1e-10 and eo < 1e-10
