@@ -220,6 +220,32 @@ __device__ inline void bary_weights_rcp(double x, double* l)
     for (int i = 0; i < NS; ++i) l[i] *= is;
 }
 
+// As bary_weights_rel_rcp with the node offsets and barycentric weights read
+// from a per-wavefront table (LDS): tab[2 i] = x_i0 - x_i (exactly 0 at i0, so
+// that x - x_i0 = du there), tab[2 i + 1] = lam_i.  Read inside a loop with
+// barriers, the table is not kept in registers across the loop (the
+// constants, and the 16 masks of a test against i0, would be).
+__device__ inline void bary_weights_rel_tab(const double* tab, double du, double* l)
+{
+    int hit = -1;
+    double sum = 0.0;
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+        const double dx = tab[2 * i] + du;
+        if (dx == 0.0) hit = i;
+        l[i] = tab[2 * i + 1] * rcp_nr(dx == 0.0 ? 1.0 : dx);
+        sum += l[i];
+    }
+    if (hit >= 0) {
+#pragma unroll
+        for (int i = 0; i < NS; ++i) l[i] = (i == hit) ? 1.0 : 0.0;
+        return;
+    }
+    const double is = rcp_nr(sum);
+#pragma unroll
+    for (int i = 0; i < NS; ++i) l[i] *= is;
+}
+
 __device__ inline void bary_weights_rel_rcp(int i0, double du, double* l)
 {
     // a node that falls on a GL node (x - x_i == 0 exactly, e.g. the nodes
@@ -1667,6 +1693,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
     // singularity): E0, Xp0[3], sp0, t0[3], then bn[3] (own) or the target's
     // offset xr[3] = x - x_c(s_i0), and z_ref = xr.t0, k_ref = |xr|^2 - E0^2
     __shared__ double f0d[16];
+    // the barycentric table of the reference node: x_i0 - x_i and lam_i
+    __shared__ double bwt[2 * NS];
+    // the pair's scalars, read where they are used inside the s-node loop
+    // rather than held in registers across it: s0, hw, the normal's sign, the
+    // three trapezoid thresholds, the target x[3]
+    __shared__ double pq[9];
+    enum { PQ_S0 = 0, PQ_HW, PQ_SGN, PQ_TRAP, PQ_X = PQ_TRAP + 3 };
     const int lane = threadIdx.x;
     const int64_t p = listf[blockIdx.x];
     const int e = pe[p];
@@ -1681,10 +1714,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
     const int ncoef = 6 * (Mt + 1);
     // thresholds on the circle's cosh(alpha) - 1 above which a trapezoid rule
     // of nt, 2nt or 4nt points meets the tolerance (Section 3.2.2)
-    double trap_thr[3];
-    {
+    if (lane == 0) {
         const double lg = log(gc.ct / gc.tol);
-        for (int k = 0; k < 3; ++k) trap_thr[k] = cosh(lg / (double)((NT << k) - Mt - gc.extra_modes)) - 1.0;
+        for (int k = 0; k < 3; ++k) pq[PQ_TRAP + k] = cosh(lg / (double)((NT << k) - Mt - gc.extra_modes)) - 1.0;
+        pq[PQ_HW] = 0.5 * (inf.c - inf.a);
+        pq[PQ_SGN] = (double)inf.sign;
+        for (int d = 0; d < 3; ++d) pq[PQ_X + d] = x[d];
     }
     const double* __restrict__ she = sh + (int64_t)e * NS * NSH;
     __syncthreads();
@@ -1713,6 +1748,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
             }
         }
         s0 = 0.5 * (inf.a + inf.c) + 0.5 * (inf.c - inf.a) * c_gx[i0];
+        if (lane == 0) pq[PQ_S0] = s0;
+        if (lane < NS) {
+            bwt[2 * lane] = lane == i0 ? 0.0 : c_gx[i0] - c_gx[lane];
+            bwt[2 * lane + 1] = c_lam[lane];
+        }
         if (lane == 0) {
             double q0[CLQ];
             for (int k = 0; k < CLQ; ++k) q0[k] = sq[k * NS + i0];
@@ -1848,8 +1888,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
         if (lane == 0) mo.count[blockIdx.x] = S + nbrows;
         return;
     }
-    const double hw = 0.5 * (inf.c - inf.a);
-    const double sgn = (double)inf.sign;
     double a0 = 0, a1 = 0, a2 = 0, b0_ = 0, b1_ = 0, b2_ = 0;
     int n_theta = 0;
     for (int base = 0; base < S; base += SB) {
@@ -1872,14 +1910,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
                 ws = 0.5 * (hi - lo) * c_gw[m];
                 // offset from s_i0 formed from differences (lo - s0 is exact
                 // for nearby sub-panels), not from the rounded absolute s
-                u = own ? s - s0 : (lo - s0) + 0.5 * (hi - lo) * (1.0 + c_gx[m]);
+                u = own ? s - pq[PQ_S0] : (lo - pq[PQ_S0]) + 0.5 * (hi - lo) * (1.0 + c_gx[m]);
             } else if (ty == SUB_WHOLE) {
                 // tabulated node offsets from the target's GL node: u is
                 // formed without the absolute parameter
                 const int o = rt.woff[wrule] + m;
-                u = hw * rt.wd[o];
-                s = s0 + u;
-                ws = hw * rt.ww[o];
+                u = pq[PQ_HW] * rt.wd[o];
+                s = pq[PQ_S0] + u;
+                ws = pq[PQ_HW] * rt.ww[o];
             } else if (ty == SUB_LOG_LO) {
                 u = (hi - lo) * rt.lx[m];
                 s = lo + u;
@@ -1890,7 +1928,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
                 ws = (hi - lo) * rt.lw[m];
             }
             double lw[NS];
-            bary_weights_rel_rcp(i0, u / hw, lw);
+            bary_weights_rel_tab(bwt, u / pq[PQ_HW], lw);
 #pragma unroll
             for (int i = 0; i < NS; ++i) lwl[lane * NS + i] = lw[i];
         }
@@ -1950,7 +1988,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
             // generalized Chebyshev rule
             int ntr = 0, rb = 0;
             for (int k = 0; k < 3 && !ntr; ++k)
-                if (cl.cha >= trap_thr[k]) ntr = NT << k;
+                if (cl.cha >= pq[PQ_TRAP + k]) ntr = NT << k;
             if (!ntr) {
                 int ex;
                 frexp(sqrt(cl.d2) / fr.E, &ex);   // alpha in [2^(ex-1), 2^ex)
@@ -1989,7 +2027,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
         }
         __syncthreads();
         if constexpr (MODE == MODE_MATRIX) {
-            matrix_rows_special<KER>(nb, base, lane, rec, rq_off, rq_step, npt, lwl, rt, sgn, mo);
+            matrix_rows_special<KER>(nb, base, lane, rec, rq_off, rq_step, npt, lwl, rt, pq[PQ_SGN], mo);
             __syncthreads();
             continue;
         }
@@ -2158,7 +2196,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
                 const double rr = z * z + A * A + B * B;
                 const double ir = rr > 0.0 ? rsqrt_nr1(rr) : 0.0;
                 const double ir2 = ir * ir;
-                const double rn = sgn * E * (gq * (dr * cph[u] - E * omc[u]) - Ep * z);
+                const double rn = pq[PQ_SGN] * E * (gq * (dr * cph[u] - E * omc[u]) - Ep * z);
                 const double aS = W * J * ir;
                 if constexpr (KER == KER_LAPLACE) {
                     a0 = fma(aS, v[u][0], a0);
@@ -2179,14 +2217,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
         __syncthreads();
     }
     const int64_t bo = boff[e], bc = boff[e + 1] - boff[e];
+    const double xe[3] = {pq[PQ_X], pq[PQ_X + 1], pq[PQ_X + 2]};   // the target, kept in LDS through the loop
     if constexpr (MODE == MODE_MATRIX) {
-        matrix_rows_base<KER>(nbrows, S, lane, x, bo, by, bn, Nb, mo, inf.fb == 2);
+        matrix_rows_base<KER>(nbrows, S, lane, xe, bo, by, bn, Nb, mo, inf.fb == 2);
         return;
     }
     // minus the element's far-field (base) rule (self term zero)
     for (int64_t k = lane; k < bc; k += 64) {
         int64_t n = bo + k;
-        double r0 = x[0] - by[n], r1 = x[1] - by[Nb + n], r2 = x[2] - by[2 * Nb + n];
+        double r0 = xe[0] - by[n], r1 = xe[1] - by[Nb + n], r2 = xe[2] - by[2 * Nb + n];
         double rr = r0 * r0 + r1 * r1 + r2 * r2;
         double ir = rr > 0.0 ? rsqrt_nr1(rr) : 0.0;
         double ir2 = ir * ir;
