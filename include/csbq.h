@@ -50,7 +50,7 @@
  *  - the caller owns every array passed in or out; the library copies what
  *    it keeps.
  *  - all floating point arrays are IEEE double, C order, contiguous.
- *  - this build supports ns = 16 and nt = 32 exactly (CSBQ_EINVAL otherwise).
+ *  - the library supports ns = 16 and nt = 32 exactly (CSBQ_EINVAL otherwise).
  */
 #ifndef CSBQ_H
 #define CSBQ_H

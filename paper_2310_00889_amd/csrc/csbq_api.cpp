@@ -630,7 +630,7 @@ int csbq_set_geometry_batch(csbq_ctx* ctx, int32_t n_bodies, const int32_t* body
 {
     if (!ctx) return CSBQ_EINVAL;
     ctx->err.clear();
-    if (ns != NS || nt != NT) return ctx->fail(CSBQ_EINVAL, "this build supports ns=16, nt=32 only");
+    if (ns != NS || nt != NT) return ctx->fail(CSBQ_EINVAL, "the library supports ns=16, nt=32 only");
     if (n_bodies < 1 || !n_panels || !normal_sign || !s_break || !xc || !eps || !e1)
         return ctx->fail(CSBQ_EINVAL, "missing geometry arrays");
     if (mem != CSBQ_HOST && mem != CSBQ_DEVICE) return ctx->fail(CSBQ_EINVAL, "bad mem flag");

@@ -1,6 +1,6 @@
 // csbq_common.hpp -- shared definitions of the gfx950 layer-potential library.
 //
-// Fixed discretisation orders of this build: NS Gauss-Legendre nodes per panel
+// Fixed discretisation orders of the library: NS Gauss-Legendre nodes per panel
 // in s and NT uniform angles (Section 3.1).
 #pragma once
 #include <hip/hip_runtime.h>
