@@ -205,3 +205,30 @@ def test_finely_discretised_torus_admitted(evs):
           f"{sg['s_nodes']}", flush=True)
     assert _rel(us, uso) < GATE and _rel(ud, udo) < GATE
     assert _rel(ua, ug) < 1e-12 and _rel(va, vg) < 1e-12
+
+
+def test_element_shape_tests(evs):
+    """The host's shape tests behind AUTO, from the elements' GL samples: a
+    sphere is recognised in its polar-angle parametrisation with a constant
+    e1 but not with e1 turning; a straight tube is a cylinder unless its
+    parametrisation speed varies; a torus is admitted at 128 elements per
+    turn (bend 0.049) but not at 96 (0.065)."""
+    ev = evs["auto"]
+
+    def shapes(bodies):
+        ev.set_geometry(synth.Scene(bodies))
+        st = ev.stats()
+        return st["elements_sphere"], st["elements_cylinder"]
+
+    assert shapes([synth.sphere_body([0, 0, 0], 0.3, [0, 0, 1], [1, 0, 0])]) == (1, 0)
+    twisted = synth.sphere_body([0, 0, 0], 0.3, [0, 0, 1], [1, 0, 0])
+    s = synth.panel_gl_points(twisted.s_break, 16)[0]
+    twisted.e1 = np.stack([np.cos(0.3 * s), np.sin(0.3 * s), 0 * s], -1)[None]
+    assert shapes([twisted]) == (0, 0)
+    assert shapes([synth.straight_tube_body(4, 2.0, 1e-2)]) == (0, 4)
+    uneven = synth.straight_tube_body(4, 2.0, 1e-2)
+    s = synth.panel_gl_points(uneven.s_break, 16)
+    uneven.xc[..., 2] = 2.0 * (s + 0.01 * np.sin(2 * np.pi * s))
+    assert shapes([uneven]) == (0, 0)
+    assert shapes([synth.torus_body(128, 1.0, 1e-3)]) == (0, 128)
+    assert shapes([synth.torus_body(96, 1.0, 1e-3)]) == (0, 0)
