@@ -123,6 +123,17 @@ typedef enum { CSBQ_KERNEL_STOKES = 0, CSBQ_KERNEL_LAPLACE = 1 } csbq_kernel;
    outside the rules' family, so their accuracy is not quad_tol's). */
 typedef enum { CSBQ_SRULE_AUTO = 0, CSBQ_SRULE_WHOLE = 1, CSBQ_SRULE_GENERAL = 2 } csbq_srule;
 
+/* Far-field rule of an element closed at an end (a sphere as one element in
+   its polar angle; Section 3.2.1's smooth rule).  Its own N_s x N_theta
+   nodes converge slowly in s far from it, so near it the smooth sum uses a
+   32 x 32 rule (the first upsampled rule) that the local corrections then
+   subtract.  AUTO (default): a smooth-sum block whose targets all lie beyond
+   the distance at which the criterion's estimates let the own nodes meet
+   quad_tol (for the density's measured band) sums the element's own nodes
+   instead; every candidate pair lies inside that distance, so the
+   corrections are unchanged.  BASE: the 32 x 32 rule for every target. */
+typedef enum { CSBQ_FAR_AUTO = 0, CSBQ_FAR_BASE = 1 } csbq_far_rule;
+
 typedef struct {
     double quad_tol;       /* per-element quadrature tolerance (relative); <= 0 selects 1e-12 */
     int32_t precision;     /* csbq_precision: FP64, or mixed (FP32 far field, FP64 near corrections) */
@@ -132,10 +143,11 @@ typedef struct {
     const char* table_dir; /* directory holding rules.bin (and srules.bin); NULL = the package's tables/ */
     int32_t kernel;        /* csbq_kernel: the Stokes layers, or the Laplace layers (FP64, criterion gate only) */
     int32_t srule;         /* csbq_srule: the own element's s-rule for on-surface targets */
+    int32_t far_rule;      /* csbq_far_rule: far-field rule of elements closed at an end */
 } csbq_options;
 
 /* Fill *opt with defaults (quad_tol 1e-12, FP64, criterion gate, device 0,
-   own stream, packaged tables, Stokes layers, CSBQ_SRULE_AUTO). */
+   own stream, packaged tables, Stokes layers, CSBQ_SRULE_AUTO, CSBQ_FAR_AUTO). */
 void csbq_default_options(csbq_options* opt);
 
 /* Create a context: selects the device, creates/adopts the stream and loads

@@ -26,6 +26,7 @@ CSBQ_FP64, CSBQ_MIXED = 0, 1
 CSBQ_GATE_CRITERION, CSBQ_GATE_MLP = 0, 1
 CSBQ_KERNEL_STOKES, CSBQ_KERNEL_LAPLACE = 0, 1
 CSBQ_SRULE_AUTO, CSBQ_SRULE_WHOLE, CSBQ_SRULE_GENERAL = 0, 1, 2
+CSBQ_FAR_AUTO, CSBQ_FAR_BASE = 0, 1
 GATE_NF, GATE_NO, GATE_NW = 16, 4, 9668
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ETABLE", -5: "ESTATE", -6: "ELIMIT"}
 # bits of an evaluation's flag word (csbq_flag)
@@ -39,7 +40,8 @@ class CsbqError(RuntimeError):
 
 class _Options(C.Structure):
     _fields_ = [("quad_tol", C.c_double), ("precision", C.c_int32), ("gate", C.c_int32), ("device", C.c_int32),
-                ("stream", C.c_void_p), ("table_dir", C.c_char_p), ("kernel", C.c_int32), ("srule", C.c_int32)]
+                ("stream", C.c_void_p), ("table_dir", C.c_char_p), ("kernel", C.c_int32), ("srule", C.c_int32),
+                ("far_rule", C.c_int32)]
 
 
 class _SolveOptions(C.Structure):
@@ -131,7 +133,7 @@ class Evaluator:
     nc = 3   # density / output components per node / target (1 for the Laplace layers)
 
     def __init__(self, quad_tol=1e-12, precision="fp64", device=0, stream=None, table_dir=None, gate="criterion",
-                 kernel="stokes", srule="auto"):
+                 kernel="stokes", srule="auto", far_rule="auto"):
         """kernel: "stokes" (densities and outputs of three components per
         node / target) or "laplace" (one).  srule: the own element's s-rule
         for on-surface targets: "auto" (the whole-element singular rules on
@@ -139,7 +141,10 @@ class Evaluator:
         spheres as one element; the general rule elsewhere), "whole" (also
         the cylinder rules on every other open element with a tabulated
         aspect) or "general" (dyadic panels and the log-singular rule
-        everywhere)."""
+        everywhere).  far_rule: the far-field rule of elements closed at an
+        end (spheres): "auto" (their own nodes for targets beyond the
+        distance where those meet quad_tol, the 32 x 32 rule nearer) or
+        "base" (the 32 x 32 rule for every target)."""
         lib = load_library()
         opt = _Options()
         lib.csbq_default_options(C.byref(opt))
@@ -149,6 +154,10 @@ class Evaluator:
         if srule not in srules:
             raise CsbqError(f"unknown s-rule {srule!r}")
         opt.srule = srules[srule]
+        far_rules = {"auto": CSBQ_FAR_AUTO, "base": CSBQ_FAR_BASE}
+        if far_rule not in far_rules:
+            raise CsbqError(f"unknown far-field rule {far_rule!r}")
+        opt.far_rule = far_rules[far_rule]
         opt.kernel = CSBQ_KERNEL_LAPLACE if kernel == "laplace" else CSBQ_KERNEL_STOKES
         self.nc = 1 if kernel == "laplace" else 3
         opt.quad_tol = float(quad_tol)

@@ -139,6 +139,7 @@ void csbq_default_options(csbq_options* opt)
     opt->table_dir = nullptr;
     opt->kernel = CSBQ_KERNEL_STOKES;
     opt->srule = CSBQ_SRULE_AUTO;
+    opt->far_rule = CSBQ_FAR_AUTO;
 }
 
 const char* csbq_last_error(const csbq_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
@@ -418,6 +419,11 @@ int csbq_create(const csbq_options* opt, csbq_ctx** out)
         delete ctx;
         return CSBQ_EINVAL;
     }
+    if (ctx->opt.far_rule != CSBQ_FAR_AUTO && ctx->opt.far_rule != CSBQ_FAR_BASE) {
+        delete ctx;
+        return CSBQ_EINVAL;
+    }
+    ctx->far_split = ctx->opt.far_rule == CSBQ_FAR_AUTO;
     ctx->ker = ctx->opt.kernel == CSBQ_KERNEL_LAPLACE ? KER_LAPLACE : KER_STOKES;
     ctx->table_dir = ctx->opt.table_dir ? std::string(ctx->opt.table_dir) : default_table_dir();
     ctx->opt.table_dir = nullptr;
@@ -758,21 +764,33 @@ int csbq_set_geometry_batch(csbq_ctx* ctx, int32_t n_bodies, const int32_t* body
         HIPC(hipMemcpy(ctx->info.p, hinf.data(), (size_t)E * sizeof(ElemInfo), hipMemcpyHostToDevice));
         ctx->n_cyl = nshape[SHAPE_CYLINDER];
         ctx->n_sph = nshape[SHAPE_SPHERE];
-        std::vector<int64_t> bo((size_t)E + 1, 0);
+        // boff[0..E]: the base rules; boff[E + 1 + e]: the own nodes of an
+        // element with the tier-0 rule as its base rule, appended after them
+        std::vector<int64_t> bo((size_t)2 * E + 1, -1);
+        bo[0] = 0;
         for (int64_t e = 0; e < E; ++e) bo[e + 1] = bo[e] + (hinf[e].fb == 2 ? up_pts(0) : NPE);
-        ctx->Nb = bo[E];
-        ctx->h_boff = bo;
-        ALLOC(ctx->boff, (size_t)E + 1);
+        ctx->Nb_rules = bo[E];
+        int64_t nb = bo[E];
+        for (int64_t e = 0; e < E; ++e)
+            if (hinf[e].fb == 2) {
+                bo[E + 1 + e] = nb;
+                nb += NPE;
+            }
+        ctx->Nb = nb;
+        ctx->h_boff.assign(bo.begin(), bo.begin() + E + 1);
+        ALLOC(ctx->boff, bo.size());
         ALLOC(ctx->by, (size_t)ctx->Nb * 3);
         ALLOC(ctx->bn, (size_t)ctx->Nb * 3);
         ALLOC(ctx->bw, (size_t)ctx->Nb);
         HIPC(hipMemcpy(ctx->boff.p, bo.data(), bo.size() * sizeof(int64_t), hipMemcpyHostToDevice));
-        LCHK(launch_base_build(ctx->stream, (int)E, ctx->info.p, ctx->boff.p, ctx->ny.p, ctx->nn.p, ctx->nw.p, N,
-                               ctx->cpy[0].p, ctx->cpn[0].p, ctx->cpw[0].p, ctx->Mtot[0], ctx->by.p, ctx->bn.p,
-                               ctx->bw.p, ctx->Nb));
+        LCHK(launch_base_build(ctx->stream, (int)E, ctx->info.p, ctx->boff.p, ctx->boff.p + E + 1, ctx->ny.p,
+                               ctx->nn.p, ctx->nw.p, N, ctx->cpy[0].p, ctx->cpn[0].p, ctx->cpw[0].p, ctx->Mtot[0],
+                               ctx->by.p, ctx->bn.p, ctx->bw.p, ctx->Nb));
         // mixed precision: sources within sqrt(100 w_max) of a target are
         // summed in FP64, so no FP32 term exceeds ~1e-2 of the density scale
-        std::vector<double> hbw((size_t)ctx->Nb);
+        // (w_max over the base rules: the own nodes of closed elements are
+        // summed only far from them)
+        std::vector<double> hbw((size_t)ctx->Nb_rules);
         HIPC(hipMemcpyAsync(hbw.data(), ctx->bw.p, hbw.size() * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
         HIPC(hipStreamSynchronize(ctx->stream));
         double wmax = 0.0;
@@ -878,7 +896,7 @@ static int eval_front(csbq_ctx* ctx, const double* sigma, int64_t T, const doubl
     ALLOC(ctx->sw, (size_t)N * 3);
     ALLOC(ctx->sh, (size_t)E * NS * NSH);
     ALLOC(ctx->band, (size_t)E * 2);
-    ALLOC(ctx->rnear, (size_t)E);
+    ALLOC(ctx->rnear, (size_t)E * 2);
     // (a negative threshold asks for the full band: see csbq_ctx::full_band)
     LCHK(launch_prep_sigma(ctx->stream, E, *sig_dev, ctx->nw.p, N, ctx->sw.p, ctx->sh.p, ctx->band.p,
                            ctx->full_band ? -1.0 : 0.1 * ctx->gc.tol, ctx->info.p, ctx->circ.p, ctx->gc,
@@ -965,25 +983,53 @@ static void far_tiles(const csbq_ctx* ctx, const std::vector<int64_t>& tr, bool 
     gnc.assign((size_t)G, 0);
     *maxchunk = 0;
     const int64_t tb = 256LL * tpt;
+    struct Chunk {
+        int64_t s0, sn;
+        int e0, e1;
+    };
+    std::vector<Chunk> ch;
     for (int g = 0; g < G; ++g) {
         if (g_only >= 0 && g != g_only) continue;
         const int64_t t0 = tr[g], tn = std::min(tr[g + 1] - tr[g], t_cap);
         const int e0 = ctx->h_gel[g], e1 = ctx->h_gel[g + 1];
-        const int64_t s0 = native ? (int64_t)e0 * NPE : ctx->h_boff[e0];
-        const int64_t s1 = native ? (int64_t)e1 * NPE : ctx->h_boff[e1];
-        const int64_t S = s1 - s0;
-        const int nch = (int)((S + chunk - 1) / chunk);
+        ch.clear();
+        if (native) {   // plain source ranges of the element nodes
+            const int64_t s0 = (int64_t)e0 * NPE, S = (int64_t)(e1 - e0) * NPE;
+            for (int64_t a = 0; a < S; a += chunk) ch.push_back(Chunk{s0 + a, std::min(chunk, S - a), 0, 0});
+        } else {        // whole elements, up to `chunk` base sources each (at least one element)
+            int ea = e0;
+            while (ea < e1) {
+                int eb = ea + 1;
+                while (eb < e1 && ctx->h_boff[eb + 1] - ctx->h_boff[ea] <= chunk) ++eb;
+                ch.push_back(Chunk{ctx->h_boff[ea], ctx->h_boff[eb] - ctx->h_boff[ea], ea, eb});
+                ea = eb;
+            }
+        }
+        const int nch = (int)ch.size();
         gnc[g] = nch;
         *maxchunk = std::max(*maxchunk, nch);
         for (int64_t a = 0; a < tn; a += tb)
             for (int c = 0; c < nch; ++c)
-                tiles.push_back(FarTile{t0 + a, s0 + c * chunk, (int32_t)std::min(tb, tn - a),
-                                        (int32_t)std::min(chunk, S - c * chunk), c, 0});
+                tiles.push_back(FarTile{t0 + a, ch[c].s0, (int32_t)std::min(tb, tn - a), (int32_t)ch[c].sn, c,
+                                        ch[c].e0, ch[c].e1, 0});
     }
     std::stable_sort(tiles.begin(), tiles.end(), [](const FarTile& a, const FarTile& b) {
         return (int64_t)a.tn * a.sn > (int64_t)b.tn * b.sn;
     });
     xcd_order(tiles, chunk);
+}
+
+// the element chunks' choice of source set (closed elements' own nodes
+// beyond rc), with the per-block pair counts written to `pairs`
+static FarSplit far_split(const csbq_ctx* ctx, int64_t* pairs)
+{
+    FarSplit f{};
+    f.boff = ctx->boff.p;
+    f.ooff = ctx->boff.p + ctx->E + 1;
+    f.rc = ctx->far_split ? ctx->rnear.p + ctx->E : nullptr;
+    f.info = ctx->info.p;
+    f.pairs = pairs;
+    return f;
 }
 
 // Launch shape of the smooth sum, chosen by timing: targets per thread 1/2/4
@@ -1037,7 +1083,7 @@ static int tune_far(csbq_ctx* ctx, int64_t T, const std::vector<int64_t>& tr, bo
         ALLOC(ctx->part, (size_t)std::max(maxch, 1) * 6 * T + 1);
         HIPC(hipEventRecord(a, ctx->stream));
         LCHK(launch_far(ctx->stream, T, ctx->xt.p, sy, sn, ss, Ns, ctx->tiles.p, (int)tl.size(), ctx->part.p, mixed,
-                        ctx->mix_near2, tpt, ctx->ker));
+                        ctx->mix_near2, tpt, ctx->ker, native ? FarSplit{} : far_split(ctx, nullptr)));
         HIPC(hipEventRecord(b, ctx->stream));
         HIPC(hipEventSynchronize(b));
         float ms = 0.f;
@@ -1077,9 +1123,11 @@ static int far_sum(csbq_ctx* ctx, int64_t T, bool native, const std::vector<int6
     ALLOC(ctx->part, (size_t)std::max(maxch, 1) * 6 * T + 1);
     HIPC(hipMemcpyAsync(ctx->tiles.p, tl.data(), tl.size() * sizeof(FarTile), hipMemcpyHostToDevice, st));
     HIPC(hipMemcpyAsync(ctx->gnchunk.p, gnc.data(), gnc.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    ALLOC(ctx->fpairs, tl.size() + 1);
     if (T > 0)
         LCHK(launch_far(st, T, ctx->xt.p, sy, sn, ss, Ns, ctx->tiles.p, (int)tl.size(), ctx->part.p, mixed,
-                        ctx->mix_near2, ctx->far_tpt, ctx->ker));
+                        ctx->mix_near2, ctx->far_tpt, ctx->ker, native ? FarSplit{} : far_split(ctx, ctx->fpairs.p)));
+    ctx->fpairs_ok = !native && T > 0;
     ctx->last_ntiles = (int)tl.size();
     ctx->last_far_pairs = 0;
     for (const auto& t : tl) ctx->last_far_pairs += (int64_t)t.tn * t.sn;
@@ -1211,7 +1259,8 @@ int csbq_smooth_sum_noalloc(csbq_ctx* ctx, const double* sigma, int64_t T, const
     }
     LCHK(launch_prep_sigma(st, ctx->E, sigma, ctx->nw.p, N, sw, sh, band, 0.1 * ctx->gc.tol, ctx->info.p,
                            ctx->circ.p, ctx->gc, nullptr));
-    LCHK(launch_far(st, T, xt, ctx->ny.p, ctx->nn.p, sw, N, tiles, ntiles, part, false, 0.0, 2, ctx->ker));
+    LCHK(launch_far(st, T, xt, ctx->ny.p, ctx->nn.p, sw, N, tiles, ntiles, part, false, 0.0, 2, ctx->ker,
+                    FarSplit{}));
     LCHK(launch_reduce(st, T, tgroup, gnchunk, part, nullptr, nullptr, nullptr, u_sl, u_dl, ctx->ker));
     return CSBQ_OK;
 }
@@ -1245,8 +1294,8 @@ int csbq_eval_batch(csbq_ctx* ctx, const double* sigma, int64_t T, const double*
     LCHK(launch_sigma_up(st, E, up_ns(0), up_nt(0), ctx->sh.p, ctx->Lup[0].p, ctx->cpw[0].p, ctx->swf[0].p,
                          ctx->Mtot[0]));
     ALLOC(ctx->bsw, (size_t)ctx->Nb * 3);
-    LCHK(launch_sigma_base(st, E, ctx->info.p, ctx->boff.p, ctx->sw.p, N, ctx->swf[0].p, ctx->Mtot[0], ctx->bsw.p,
-                           ctx->Nb));
+    LCHK(launch_sigma_base(st, E, ctx->info.p, ctx->boff.p, ctx->boff.p + E + 1, ctx->sw.p, N, ctx->swf[0].p,
+                           ctx->Mtot[0], ctx->bsw.p, ctx->Nb));
     // candidate pairs: count, scan (the fill follows the synchronisation)
     HIPC(hipEventRecord(ctx->ph[2].a, st));
     ALLOC(ctx->cnt, (size_t)T + 1);
@@ -1477,10 +1526,10 @@ static int enqueue_apply(csbq_ctx* ctx, hipStream_t st)
     LCHK(launch_band_check(st, E, ctx->band_apply.p, ctx->band.p, ctx->err_d.p));
     LCHK(launch_sigma_up(st, E, up_ns(0), up_nt(0), ctx->sh.p, ctx->Lup[0].p, ctx->cpw[0].p, ctx->swf[0].p,
                          ctx->Mtot[0]));
-    LCHK(launch_sigma_base(st, E, ctx->info.p, ctx->boff.p, ctx->sw.p, N, ctx->swf[0].p, ctx->Mtot[0], ctx->bsw.p,
-                           ctx->Nb));
+    LCHK(launch_sigma_base(st, E, ctx->info.p, ctx->boff.p, ctx->boff.p + E + 1, ctx->sw.p, N, ctx->swf[0].p,
+                           ctx->Mtot[0], ctx->bsw.p, ctx->Nb));
     LCHK(launch_far(st, T, ctx->xt.p, ctx->by.p, ctx->bn.p, ctx->bsw.p, ctx->Nb, ctx->tiles.p, pl.ntiles, ctx->part.p,
-                    pl.mixed, ctx->mix_near2, pl.tpt, ctx->ker));
+                    pl.mixed, ctx->mix_near2, pl.tpt, ctx->ker, far_split(ctx, ctx->fpairs.p)));
     for (int ti = 1; ti < NUP; ++ti)
         if (pl.nwaves[ti])
             LCHK(launch_sigma_up(st, E, up_ns(ti), up_nt(ti), ctx->sh.p, ctx->Lup[ti].p, ctx->cpw[ti].p,
@@ -1940,14 +1989,29 @@ int csbq_stats(const csbq_ctx* ctx, char* buf, int64_t cap)
                   "\"pairs_up3\": %lld, \"pairs_full\": %lld, \"flags\": %d, \"sources_base\": %lld",
                   (long long)ctx->last_T, (long long)ctx->last_P, (long long)ctx->last_nup[0],
                   (long long)ctx->last_nup[1], (long long)ctx->last_nup[2], (long long)ctx->last_nf,
-                  ctx->last_err_flags, (long long)ctx->Nb);
+                  ctx->last_err_flags, (long long)ctx->Nb_rules);
     s += tmp;
     if (ctx->last_esc >= 0) {
         std::snprintf(tmp, sizeof tmp, ", \"gate_escalated\": %lld", (long long)ctx->last_esc);
         s += tmp;
     }
-    std::snprintf(tmp, sizeof tmp, ", \"far_tpt\": %d, \"far_chunk\": %lld, \"far_pairs\": %lld", ctx->far_tpt,
-                  (long long)ctx->far_chunk, (long long)ctx->last_far_pairs);
+    // pairs the last smooth sum summed (closed elements' own nodes where
+    // chosen), and what its base rules alone would have summed
+    int64_t far_pairs = ctx->last_far_pairs;
+    if (ctx->fpairs_ok && ctx->last_ntiles > 0) {
+        std::vector<int64_t> fp((size_t)ctx->last_ntiles);
+        if (hipMemcpy(fp.data(), ctx->fpairs.p, fp.size() * sizeof(int64_t), hipMemcpyDeviceToHost) == hipSuccess) {
+            far_pairs = 0;
+            for (int64_t v : fp) far_pairs += v;
+        } else {
+            (void)hipGetLastError();
+        }
+    }
+    std::snprintf(tmp, sizeof tmp,
+                  ", \"far_tpt\": %d, \"far_chunk\": %lld, \"far_pairs\": %lld, \"far_pairs_base\": %lld, "
+                  "\"far_split\": %d",
+                  ctx->far_tpt, (long long)ctx->far_chunk, (long long)far_pairs, (long long)ctx->last_far_pairs,
+                  ctx->far_split ? 1 : 0);
     s += tmp;
     std::snprintf(tmp, sizeof tmp,
                   ", \"estimate\": {\"tol\": %.3e, \"cs\": %.1f, \"ct\": %.1f, \"hmin_fac\": %.3f, \"extra_modes\": %d}",

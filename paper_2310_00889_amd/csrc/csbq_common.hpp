@@ -80,12 +80,29 @@ struct ElemInfo {
 enum : int { SHAPE_OTHER = 0, SHAPE_CYLINDER = 1, SHAPE_SPHERE = 2 };
 
 // one block of the smooth sum: up to 256 x (targets per thread) consecutive
-// targets of one group against a chunk of that group's sources
+// targets of one group against a chunk of that group's sources.  A chunk is
+// either a plain source range [s0, s0 + sn) or, when e1 > e0, the far-field
+// rules of the whole elements [e0, e1) (sn then counts their base sources)
 struct FarTile {
     int64_t t0, s0;    // first target, first source
     int32_t tn, sn;    // counts
     int32_t chunk;     // partial-sum slot
+    int32_t e0, e1;    // element range (element chunks only)
     int32_t pad_;
+};
+
+// Element chunks of the smooth sum: an element closed at an end (far-field
+// rule up_ns(0) x NT) is summed with its own N_s x N_theta nodes instead for
+// a block whose targets all lie at least rc[e] from the element's centre,
+// the distance beyond which the same error estimates that choose the
+// candidates let the own nodes meet the tolerance.  The own nodes of such
+// elements follow the base rules in the base source arrays.
+struct FarSplit {
+    const int64_t* boff;    // element e's base rule: sources [boff[e], boff[e + 1])
+    const int64_t* ooff;    // its own nodes: sources [ooff[e], ooff[e] + NPE) (closed elements)
+    const double* rc;       // rc[e] (+inf: never), or null: base rules only
+    const ElemInfo* info;   // element centres
+    int64_t* pairs;         // per block: source-target pairs summed (or null)
 };
 
 // constants of the error estimates (calibrated against the CPU oracle)

@@ -93,7 +93,8 @@ struct csbq_ctx {
     DBuf<double> cpy[NUP], cpn[NUP], cpw[NUP], Lup[NUP], upx[NUP], upw[NUP];
     int64_t Mtot[NUP] = {0, 0, 0};
     // far-field (base) source set
-    int64_t Nb = 0;
+    int64_t Nb = 0;         // base sources: the base rules, then the own nodes of closed elements
+    int64_t Nb_rules = 0;   // the base rules alone
     double mix_near2 = 0.0;   // squared radius of the FP64 near part of the mixed-precision far sum
     DBuf<int64_t> boff;
     DBuf<double> by, bn, bw, bsw;
@@ -143,7 +144,10 @@ struct csbq_ctx {
     // CSBQ_PLAN_MATRIX): EMAT_DOUBLES per pair, in the plan's pair order
     DBuf<double> emat;
     int last_ntiles = 0;
-    int64_t last_far_pairs = 0;   // source-target pairs of the last smooth sum
+    int64_t last_far_pairs = 0;   // source-target pairs of the last smooth sum's base rules
+    DBuf<int64_t> fpairs;         // per block of the last smooth sum: pairs summed (own nodes where chosen)
+    bool fpairs_ok = false;
+    bool far_split = true;        // closed elements' own nodes as their far-field rule where they suffice
     // host copies of the smooth-sum block list outlive the asynchronous uploads
     std::vector<FarTile> h_tiles;
     std::vector<int> h_gnc;

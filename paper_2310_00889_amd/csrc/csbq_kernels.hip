@@ -509,11 +509,14 @@ __global__ __launch_bounds__(128) void k_expand_up(int E, int ns_f, int nt_f, co
 
 // Far-field (base) source set: each element contributes its own nodes (fb = 1)
 // or its tier-0 rule (fb = 2); boff[e] is the element's first base source.
+// An fb = 2 element's own nodes follow at ooff[e] (the smooth sum's choice
+// for targets far from it).
 __global__ void k_base_build(int E, const ElemInfo* __restrict__ info, const int64_t* __restrict__ boff,
-                             const double* __restrict__ ny, const double* __restrict__ nn,
-                             const double* __restrict__ nw, int64_t N, const double* __restrict__ c0y,
-                             const double* __restrict__ c0n, const double* __restrict__ c0w, int64_t M0,
-                             double* __restrict__ by, double* __restrict__ bn, double* __restrict__ bw, int64_t Nb)
+                             const int64_t* __restrict__ ooff, const double* __restrict__ ny,
+                             const double* __restrict__ nn, const double* __restrict__ nw, int64_t N,
+                             const double* __restrict__ c0y, const double* __restrict__ c0n,
+                             const double* __restrict__ c0w, int64_t M0, double* __restrict__ by,
+                             double* __restrict__ bn, double* __restrict__ bw, int64_t Nb)
 {
     const int e = blockIdx.x;
     const int fb = info[e].fb;
@@ -531,6 +534,15 @@ __global__ void k_base_build(int E, const ElemInfo* __restrict__ info, const int
         }
         bw[o + k] = swt[src];
     }
+    if (fb == 2)
+        for (int k = threadIdx.x; k < NPE; k += blockDim.x) {
+            const int64_t src = (int64_t)e * NPE + k, dst = ooff[e] + k;
+            for (int d = 0; d < 3; ++d) {
+                by[d * Nb + dst] = ny[d * N + src];
+                bn[d * Nb + dst] = nn[d * N + src];
+            }
+            bw[dst] = nw[src];
+        }
 }
 
 // ---------------------------------------------------------------------------
@@ -664,8 +676,8 @@ __global__ __launch_bounds__(256) void k_sigma_up(int E, int ns_f, int nt_f, con
 
 // density times weight on the base (far-field) source set
 __global__ void k_sigma_base(int E, const ElemInfo* __restrict__ info, const int64_t* __restrict__ boff,
-                             const double* __restrict__ sw, int64_t N, const double* __restrict__ swf0, int64_t M0,
-                             double* __restrict__ bsw, int64_t Nb)
+                             const int64_t* __restrict__ ooff, const double* __restrict__ sw, int64_t N,
+                             const double* __restrict__ swf0, int64_t M0, double* __restrict__ bsw, int64_t Nb)
 {
     const int e = blockIdx.x;
     const int fb = info[e].fb;
@@ -675,6 +687,9 @@ __global__ void k_sigma_base(int E, const ElemInfo* __restrict__ info, const int
         for (int d = 0; d < 3; ++d)
             bsw[d * Nb + o + k] = fb == 2 ? swf0[d * M0 + (int64_t)e * up_pts(0) + k] : sw[d * N + (int64_t)e * NPE + k];
     }
+    if (fb == 2)
+        for (int k = threadIdx.x; k < NPE; k += blockDim.x)
+            for (int d = 0; d < 3; ++d) bsw[d * Nb + ooff[e] + k] = sw[d * N + (int64_t)e * NPE + k];
 }
 
 // ---------------------------------------------------------------------------
@@ -729,66 +744,6 @@ __global__ void k_fill_i64(int64_t n, int64_t* __restrict__ v, int64_t val)
 // ---------------------------------------------------------------------------
 constexpr int FAR_REC = 10;     // LDS record of a source (upsampled corrections): y(3) n(3) sigma*w(3), padded
 
-// Each thread owns TPT targets and walks its block's source chunk; a
-// source's record is read at wave-uniform addresses (scalar loads through the
-// scalar cache, shared by the block's four waves), so it costs no vector
-// memory, LDS or barrier and every load serves 64 TPT pairs.
-template <int TPT, int KER>
-__global__ __launch_bounds__(FAR_BLOCK) void k_far(int64_t T, const double* __restrict__ xt,
-                                                   const double* __restrict__ sy, const double* __restrict__ sn,
-                                                   const double* __restrict__ ssw, int64_t N,
-                                                   const FarTile* __restrict__ tiles, double* __restrict__ part)
-{
-    const int tid = threadIdx.x;
-    const FarTile tl = tiles[blockIdx.x];
-    const int64_t tb = tl.t0 + tid, tend = tl.t0 + tl.tn;
-    double x[TPT][3], sa[TPT][3], sb[TPT][3], sd[TPT][3];
-#pragma unroll
-    for (int u = 0; u < TPT; ++u) {
-        const int64_t t = tb + u * FAR_BLOCK;
-        const bool ok = t < tend;
-        x[u][0] = ok ? xt[t] : 0.0;
-        x[u][1] = ok ? xt[T + t] : 0.0;
-        x[u][2] = ok ? xt[2 * T + t] : 0.0;
-        for (int d = 0; d < 3; ++d) sa[u][d] = sb[u][d] = sd[u][d] = 0.0;
-    }
-    const int64_t c0 = tl.s0;
-    const int64_t c1 = tl.s0 + tl.sn;
-#pragma unroll 4
-    for (int64_t k = c0; k < c1; ++k) {
-        const double2 A = {sy[k], sy[N + k]}, B = {sy[2 * N + k], sn[k]}, C = {sn[N + k], sn[2 * N + k]},
-                      D = {ssw[k], ssw[N + k]}, F = {ssw[2 * N + k], 0.0};
-#pragma unroll
-        for (int u = 0; u < TPT; ++u) pair_acc<KER>(x[u], A, B, C, D, F, sa[u], sb[u], sd[u]);
-    }
-    double* p = part + (int64_t)tl.chunk * 6 * T;
-#pragma unroll
-    for (int u = 0; u < TPT; ++u) {
-        const int64_t t = tb + u * FAR_BLOCK;
-        if (t < tend) {
-            double o[6];
-            scaled_out<KER>(sa[u], sb[u], sd[u], o);
-            for (int k = 0; k < 6; ++k)
-                if (KER != KER_LAPLACE || k == 0 || k == 3) p[k * T + t] = o[k];
-        }
-    }
-}
-
-// Mixed-precision smooth sum.  r = x - y is formed in FP64 (so a pair keeps
-// its relative accuracy whatever the coordinates' magnitude) and the kernel
-// is evaluated in FP32, summed in FP32 over one tile of FAR_BLOCK sources and
-// then into FP64 accumulators.  Sources closer than sqrt(near2) to a target
-// are evaluated and summed in FP64 from the FP64 record: their terms are the
-// large ones that the near corrections later cancel against an FP64
-// subtraction of the same terms, so they must carry FP64 rounding only.
-// Whole tiles whose bounding box is farther than that from the block's
-// targets skip the per-pair test.
-struct __attribute__((aligned(16))) FarRecMx {
-    double y0, y1, y2;
-    float n0, n1, n2, w0, w1, w2;    // FP32 copy for the far part
-    double n[3], w[3];               // FP64 values for the near part
-};
-
 // bounding box of the block's points (lo/hi per coordinate; +-inf if none)
 __device__ inline void block_box(double* lo, double* hi, double* red /*[2][3][FAR_BLOCK / 64]*/)
 {
@@ -817,12 +772,166 @@ __device__ inline void block_box(double* lo, double* hi, double* red /*[2][3][FA
     __syncthreads();
 }
 
+// Which of the elements e0 .. e0 + n - 1 (n <= 64) of an element chunk are
+// summed with their own nodes: those whose rc[e] the block's target box
+// [lo, hi] keeps clear of their centre.  Lane l tests element e0 + l; the
+// ballot gives every lane (and the scalar unit) the same mask.
+__device__ __forceinline__ uint64_t far_own_mask(const FarSplit& spl, int e0, int n, const double* lo,
+                                                 const double* hi)
+{
+    const int l = threadIdx.x & 63;
+    bool own = false;
+    if (l < n) {
+        const int e = e0 + l;
+        const double rc = spl.rc[e];
+        if (rc < INFINITY) {
+            const ElemInfo& inf = spl.info[e];
+            double g2 = 0.0;
+            for (int d = 0; d < 3; ++d) {
+                const double g = fmax(0.0, fmax(lo[d] - inf.cen[d], inf.cen[d] - hi[d]));
+                g2 += g * g;
+            }
+            own = g2 >= rc * rc;
+        }
+    }
+    return (uint64_t)__ballot(own);
+}
+
+// the sources of segment q of a block: element tl.e0 + q's own nodes or base
+// rule (element chunks), else the chunk's plain range
+__device__ __forceinline__ void far_segment(const FarTile& tl, const FarSplit& spl, int q, uint64_t own, int64_t& a,
+                                            int64_t& b)
+{
+    if (tl.e1 > tl.e0) {
+        const int e = tl.e0 + q;
+        if ((own >> (q & 63)) & 1) {
+            a = spl.ooff[e];
+            b = a + NPE;
+        } else {
+            a = spl.boff[e];
+            b = spl.boff[e + 1];
+        }
+    } else {
+        a = tl.s0;
+        b = tl.s0 + tl.sn;
+    }
+}
+
+// bounding box of a block's targets, stored in box[0..5] (lo, hi) in LDS
+template <int TPT>
+__device__ __forceinline__ void target_box(const double x[TPT][3], int64_t tb, int64_t tend, double* box,
+                                           double* red)
+{
+    double lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = INFINITY;
+        hi[d] = -INFINITY;
+    }
+#pragma unroll
+    for (int u = 0; u < TPT; ++u)
+        if (tb + u * FAR_BLOCK < tend)
+            for (int d = 0; d < 3; ++d) {
+                lo[d] = fmin(lo[d], x[u][d]);
+                hi[d] = fmax(hi[d], x[u][d]);
+            }
+    block_box(lo, hi, red);
+    if (threadIdx.x == 0)
+        for (int d = 0; d < 3; ++d) {
+            box[d] = lo[d];
+            box[3 + d] = hi[d];
+        }
+    __syncthreads();
+}
+
+// Each thread owns TPT targets and walks its block's source chunk; a
+// source's record is read at wave-uniform addresses (scalar loads through the
+// scalar cache, shared by the block's four waves), so it costs no vector
+// memory, LDS or barrier and every load serves 64 TPT pairs.
+template <int TPT, int KER>
+__device__ __forceinline__ void far_range(const double x[TPT][3], const double* __restrict__ sy,
+                                          const double* __restrict__ sn, const double* __restrict__ ssw, int64_t N,
+                                          int64_t c0, int64_t c1, double sa[TPT][3], double sb[TPT][3],
+                                          double sd[TPT][3])
+{
+#pragma unroll 4
+    for (int64_t k = c0; k < c1; ++k) {
+        const double2 A = {sy[k], sy[N + k]}, B = {sy[2 * N + k], sn[k]}, C = {sn[N + k], sn[2 * N + k]},
+                      D = {ssw[k], ssw[N + k]}, F = {ssw[2 * N + k], 0.0};
+#pragma unroll
+        for (int u = 0; u < TPT; ++u) pair_acc<KER>(x[u], A, B, C, D, F, sa[u], sb[u], sd[u]);
+    }
+}
+
+template <int TPT, int KER>
+__global__ __launch_bounds__(FAR_BLOCK) void k_far(int64_t T, const double* __restrict__ xt,
+                                                   const double* __restrict__ sy, const double* __restrict__ sn,
+                                                   const double* __restrict__ ssw, int64_t N,
+                                                   const FarTile* __restrict__ tiles, double* __restrict__ part,
+                                                   FarSplit spl)
+{
+    __shared__ double red[6 * (FAR_BLOCK / 64)];
+    __shared__ double box[6];
+    const int tid = threadIdx.x;
+    const FarTile tl = tiles[blockIdx.x];
+    const int64_t tb = tl.t0 + tid, tend = tl.t0 + tl.tn;
+    double x[TPT][3], sa[TPT][3], sb[TPT][3], sd[TPT][3];
+#pragma unroll
+    for (int u = 0; u < TPT; ++u) {
+        const int64_t t = tb + u * FAR_BLOCK;
+        const bool ok = t < tend;
+        x[u][0] = ok ? xt[t] : 0.0;
+        x[u][1] = ok ? xt[T + t] : 0.0;
+        x[u][2] = ok ? xt[2 * T + t] : 0.0;
+        for (int d = 0; d < 3; ++d) sa[u][d] = sb[u][d] = sd[u][d] = 0.0;
+    }
+    // a plain source range, or the far-field rules of whole elements
+    const bool split = tl.e1 > tl.e0 && spl.rc;
+    if (split) target_box<TPT>(x, tb, tend, box, red);
+    const int nseg = tl.e1 > tl.e0 ? tl.e1 - tl.e0 : 1;
+    uint64_t own = 0;
+    int64_t npts = 0;
+    for (int q = 0; q < nseg; ++q) {
+        if (split && (q & 63) == 0) own = far_own_mask(spl, tl.e0 + q, min(64, nseg - q), box, box + 3);
+        int64_t a, b;
+        far_segment(tl, spl, q, own, a, b);
+        far_range<TPT, KER>(x, sy, sn, ssw, N, a, b, sa, sb, sd);
+        npts += b - a;
+    }
+    if (spl.pairs && tid == 0) spl.pairs[blockIdx.x] = npts * tl.tn;
+    double* p = part + (int64_t)tl.chunk * 6 * T;
+#pragma unroll
+    for (int u = 0; u < TPT; ++u) {
+        const int64_t t = tb + u * FAR_BLOCK;
+        if (t < tend) {
+            double o[6];
+            scaled_out<KER>(sa[u], sb[u], sd[u], o);
+            for (int k = 0; k < 6; ++k)
+                if (KER != KER_LAPLACE || k == 0 || k == 3) p[k * T + t] = o[k];
+        }
+    }
+}
+
+// Mixed-precision smooth sum.  r = x - y is formed in FP64 (so a pair keeps
+// its relative accuracy whatever the coordinates' magnitude) and the kernel
+// is evaluated in FP32, summed in FP32 over one tile of FAR_BLOCK sources and
+// then into FP64 accumulators.  Sources closer than sqrt(near2) to a target
+// are evaluated and summed in FP64 from the FP64 record: their terms are the
+// large ones that the near corrections later cancel against an FP64
+// subtraction of the same terms, so they must carry FP64 rounding only.
+// Whole tiles whose bounding box is farther than that from the block's
+// targets skip the per-pair test.
+struct __attribute__((aligned(16))) FarRecMx {
+    double y0, y1, y2;
+    float n0, n1, n2, w0, w1, w2;    // FP32 copy for the far part
+    double n[3], w[3];               // FP64 values for the near part
+};
+
 template <int TPT>
 __global__ __launch_bounds__(FAR_BLOCK) void k_far_mx(int64_t T, const double* __restrict__ xt,
                                                       const double* __restrict__ sy, const double* __restrict__ sn,
                                                       const double* __restrict__ ssw, int64_t N,
                                                       const FarTile* __restrict__ tiles, double near2,
-                                                      double* __restrict__ part)
+                                                      double* __restrict__ part, FarSplit spl)
 {
     __shared__ FarRecMx src[FAR_BLOCK];
     __shared__ double red[6 * (FAR_BLOCK / 64)];
@@ -848,115 +957,128 @@ __global__ __launch_bounds__(FAR_BLOCK) void k_far_mx(int64_t T, const double* _
         }
     }
     block_box(tlo, thi, red);
-    const int64_t c0 = tl.s0;
-    const int64_t c1 = tl.s0 + tl.sn;
-    for (int64_t base = c0; base < c1; base += FAR_BLOCK) {
-        const int64_t k = base + tid;
-        double slo[3] = {INFINITY, INFINITY, INFINITY}, shi[3] = {-INFINITY, -INFINITY, -INFINITY};
-        if (k < c1) {
-            FarRecMx r;
-            r.y0 = sy[k];
-            r.y1 = sy[N + k];
-            r.y2 = sy[2 * N + k];
-            for (int d = 0; d < 3; ++d) {
-                r.n[d] = sn[d * N + k];
-                r.w[d] = ssw[d * N + k];
-            }
-            r.n0 = (float)r.n[0];
-            r.n1 = (float)r.n[1];
-            r.n2 = (float)r.n[2];
-            r.w0 = (float)r.w[0];
-            r.w1 = (float)r.w[1];
-            r.w2 = (float)r.w[2];
-            src[tid] = r;
-            slo[0] = shi[0] = r.y0;
-            slo[1] = shi[1] = r.y1;
-            slo[2] = shi[2] = r.y2;
-        }
-        block_box(slo, shi, red);   // also the barrier after the tile is stored
-        double gap2 = 0.0;
-        for (int d = 0; d < 3; ++d) {
-            const double g = fmax(0.0, fmax(tlo[d] - shi[d], slo[d] - thi[d]));
-            gap2 += g * g;
-        }
-        const bool near_tile = !(gap2 >= near2 && gap2 > 0.0);   // uniform over the block
-        const int nin = (int)min((int64_t)FAR_BLOCK, c1 - base);
-        float fs[TPT][3], fd[TPT][3];
-#pragma unroll
-        for (int u = 0; u < TPT; ++u)
-            for (int d = 0; d < 3; ++d) fs[u][d] = fd[u][d] = 0.0f;
-        if (!near_tile) {
-#pragma unroll 2
-            for (int kk = 0; kk < nin; ++kk) {
-                const FarRecMx& R = src[kk];
-                const double y0 = R.y0, y1 = R.y1, y2 = R.y2;
-                const float n0 = R.n0, n1 = R.n1, n2 = R.n2, w0 = R.w0, w1 = R.w1, w2 = R.w2;
-#pragma unroll
-                for (int u = 0; u < TPT; ++u) {
-                    const float r0 = (float)(x[u][0] - y0), r1 = (float)(x[u][1] - y1), r2 = (float)(x[u][2] - y2);
-                    const float rr = fmaf(r0, r0, fmaf(r1, r1, r2 * r2));
-                    const float ir = __builtin_amdgcn_rsqf(rr);   // rr > 0: the tile is away from every target
-                    const float rs = fmaf(r0, w0, fmaf(r1, w1, r2 * w2));
-                    const float rn = fmaf(r0, n0, fmaf(r1, n1, r2 * n2));
-                    const float ir2 = ir * ir;
-                    const float b = rs * (ir * ir2);
-                    const float cD = (rn * b) * ir2;
-                    fs[u][0] = fmaf(ir, w0, fmaf(b, r0, fs[u][0]));
-                    fs[u][1] = fmaf(ir, w1, fmaf(b, r1, fs[u][1]));
-                    fs[u][2] = fmaf(ir, w2, fmaf(b, r2, fs[u][2]));
-                    fd[u][0] = fmaf(cD, r0, fd[u][0]);
-                    fd[u][1] = fmaf(cD, r1, fd[u][1]);
-                    fd[u][2] = fmaf(cD, r2, fd[u][2]);
+    // one source range [c0, c1)
+    auto sum_range = [&](int64_t c0, int64_t c1) {
+        for (int64_t base = c0; base < c1; base += FAR_BLOCK) {
+            const int64_t k = base + tid;
+            double slo[3] = {INFINITY, INFINITY, INFINITY}, shi[3] = {-INFINITY, -INFINITY, -INFINITY};
+            if (k < c1) {
+                FarRecMx r;
+                r.y0 = sy[k];
+                r.y1 = sy[N + k];
+                r.y2 = sy[2 * N + k];
+                for (int d = 0; d < 3; ++d) {
+                    r.n[d] = sn[d * N + k];
+                    r.w[d] = ssw[d * N + k];
                 }
+                r.n0 = (float)r.n[0];
+                r.n1 = (float)r.n[1];
+                r.n2 = (float)r.n[2];
+                r.w0 = (float)r.w[0];
+                r.w1 = (float)r.w[1];
+                r.w2 = (float)r.w[2];
+                src[tid] = r;
+                slo[0] = shi[0] = r.y0;
+                slo[1] = shi[1] = r.y1;
+                slo[2] = shi[2] = r.y2;
             }
-        } else {
-            for (int kk = 0; kk < nin; ++kk) {
-                const FarRecMx& R = src[kk];
+            block_box(slo, shi, red);   // also the barrier after the tile is stored
+            double gap2 = 0.0;
+            for (int d = 0; d < 3; ++d) {
+                const double g = fmax(0.0, fmax(tlo[d] - shi[d], slo[d] - thi[d]));
+                gap2 += g * g;
+            }
+            const bool near_tile = !(gap2 >= near2 && gap2 > 0.0);   // uniform over the block
+            const int nin = (int)min((int64_t)FAR_BLOCK, c1 - base);
+            float fs[TPT][3], fd[TPT][3];
 #pragma unroll
-                for (int u = 0; u < TPT; ++u) {
-                    const double d0 = x[u][0] - R.y0, d1 = x[u][1] - R.y1, d2 = x[u][2] - R.y2;
-                    const float r0 = (float)d0, r1 = (float)d1, r2 = (float)d2;
-                    const float rr = fmaf(r0, r0, fmaf(r1, r1, r2 * r2));
-                    if (rr < near2f) {
-                        const double rr64 = fma(d0, d0, fma(d1, d1, d2 * d2));
-                        const double irn = rsqrt_nr1(rr64);
-                        const double ir = rr64 > 0.0 ? irn : 0.0;
-                        const double rs = fma(d0, R.w[0], fma(d1, R.w[1], d2 * R.w[2]));
-                        const double rn = fma(d0, R.n[0], fma(d1, R.n[1], d2 * R.n[2]));
-                        const double ir2 = ir * ir;
-                        const double b = rs * (ir * ir2);
-                        const double cD = (rn * b) * ir2;
-                        us[u][0] = fma(ir, R.w[0], fma(b, d0, us[u][0]));
-                        us[u][1] = fma(ir, R.w[1], fma(b, d1, us[u][1]));
-                        us[u][2] = fma(ir, R.w[2], fma(b, d2, us[u][2]));
-                        ud[u][0] = fma(cD, d0, ud[u][0]);
-                        ud[u][1] = fma(cD, d1, ud[u][1]);
-                        ud[u][2] = fma(cD, d2, ud[u][2]);
-                    } else {
-                        const float ir = __builtin_amdgcn_rsqf(rr);
-                        const float rs = fmaf(r0, R.w0, fmaf(r1, R.w1, r2 * R.w2));
-                        const float rn = fmaf(r0, R.n0, fmaf(r1, R.n1, r2 * R.n2));
+            for (int u = 0; u < TPT; ++u)
+                for (int d = 0; d < 3; ++d) fs[u][d] = fd[u][d] = 0.0f;
+            if (!near_tile) {
+#pragma unroll 2
+                for (int kk = 0; kk < nin; ++kk) {
+                    const FarRecMx& R = src[kk];
+                    const double y0 = R.y0, y1 = R.y1, y2 = R.y2;
+                    const float n0 = R.n0, n1 = R.n1, n2 = R.n2, w0 = R.w0, w1 = R.w1, w2 = R.w2;
+#pragma unroll
+                    for (int u = 0; u < TPT; ++u) {
+                        const float r0 = (float)(x[u][0] - y0), r1 = (float)(x[u][1] - y1), r2 = (float)(x[u][2] - y2);
+                        const float rr = fmaf(r0, r0, fmaf(r1, r1, r2 * r2));
+                        const float ir = __builtin_amdgcn_rsqf(rr);   // rr > 0: the tile is away from every target
+                        const float rs = fmaf(r0, w0, fmaf(r1, w1, r2 * w2));
+                        const float rn = fmaf(r0, n0, fmaf(r1, n1, r2 * n2));
                         const float ir2 = ir * ir;
                         const float b = rs * (ir * ir2);
                         const float cD = (rn * b) * ir2;
-                        fs[u][0] = fmaf(ir, R.w0, fmaf(b, r0, fs[u][0]));
-                        fs[u][1] = fmaf(ir, R.w1, fmaf(b, r1, fs[u][1]));
-                        fs[u][2] = fmaf(ir, R.w2, fmaf(b, r2, fs[u][2]));
+                        fs[u][0] = fmaf(ir, w0, fmaf(b, r0, fs[u][0]));
+                        fs[u][1] = fmaf(ir, w1, fmaf(b, r1, fs[u][1]));
+                        fs[u][2] = fmaf(ir, w2, fmaf(b, r2, fs[u][2]));
                         fd[u][0] = fmaf(cD, r0, fd[u][0]);
                         fd[u][1] = fmaf(cD, r1, fd[u][1]);
                         fd[u][2] = fmaf(cD, r2, fd[u][2]);
                     }
                 }
-            }
-        }
+            } else {
+                for (int kk = 0; kk < nin; ++kk) {
+                    const FarRecMx& R = src[kk];
 #pragma unroll
-        for (int u = 0; u < TPT; ++u)
-            for (int d = 0; d < 3; ++d) {
-                us[u][d] += (double)fs[u][d];
-                ud[u][d] += (double)fd[u][d];
+                    for (int u = 0; u < TPT; ++u) {
+                        const double d0 = x[u][0] - R.y0, d1 = x[u][1] - R.y1, d2 = x[u][2] - R.y2;
+                        const float r0 = (float)d0, r1 = (float)d1, r2 = (float)d2;
+                        const float rr = fmaf(r0, r0, fmaf(r1, r1, r2 * r2));
+                        if (rr < near2f) {
+                            const double rr64 = fma(d0, d0, fma(d1, d1, d2 * d2));
+                            const double irn = rsqrt_nr1(rr64);
+                            const double ir = rr64 > 0.0 ? irn : 0.0;
+                            const double rs = fma(d0, R.w[0], fma(d1, R.w[1], d2 * R.w[2]));
+                            const double rn = fma(d0, R.n[0], fma(d1, R.n[1], d2 * R.n[2]));
+                            const double ir2 = ir * ir;
+                            const double b = rs * (ir * ir2);
+                            const double cD = (rn * b) * ir2;
+                            us[u][0] = fma(ir, R.w[0], fma(b, d0, us[u][0]));
+                            us[u][1] = fma(ir, R.w[1], fma(b, d1, us[u][1]));
+                            us[u][2] = fma(ir, R.w[2], fma(b, d2, us[u][2]));
+                            ud[u][0] = fma(cD, d0, ud[u][0]);
+                            ud[u][1] = fma(cD, d1, ud[u][1]);
+                            ud[u][2] = fma(cD, d2, ud[u][2]);
+                        } else {
+                            const float ir = __builtin_amdgcn_rsqf(rr);
+                            const float rs = fmaf(r0, R.w0, fmaf(r1, R.w1, r2 * R.w2));
+                            const float rn = fmaf(r0, R.n0, fmaf(r1, R.n1, r2 * R.n2));
+                            const float ir2 = ir * ir;
+                            const float b = rs * (ir * ir2);
+                            const float cD = (rn * b) * ir2;
+                            fs[u][0] = fmaf(ir, R.w0, fmaf(b, r0, fs[u][0]));
+                            fs[u][1] = fmaf(ir, R.w1, fmaf(b, r1, fs[u][1]));
+                            fs[u][2] = fmaf(ir, R.w2, fmaf(b, r2, fs[u][2]));
+                            fd[u][0] = fmaf(cD, r0, fd[u][0]);
+                            fd[u][1] = fmaf(cD, r1, fd[u][1]);
+                            fd[u][2] = fmaf(cD, r2, fd[u][2]);
+                        }
+                    }
+                }
             }
-        __syncthreads();
+#pragma unroll
+            for (int u = 0; u < TPT; ++u)
+                for (int d = 0; d < 3; ++d) {
+                    us[u][d] += (double)fs[u][d];
+                    ud[u][d] += (double)fd[u][d];
+                }
+            __syncthreads();
+        }
+    };
+    const bool split = tl.e1 > tl.e0 && spl.rc;
+    const int nseg = tl.e1 > tl.e0 ? tl.e1 - tl.e0 : 1;
+    uint64_t own = 0;
+    int64_t npts = 0;
+    for (int q = 0; q < nseg; ++q) {
+        if (split && (q & 63) == 0) own = far_own_mask(spl, tl.e0 + q, min(64, nseg - q), tlo, thi);
+        int64_t a, b;
+        far_segment(tl, spl, q, own, a, b);
+        sum_range(a, b);
+        npts += b - a;
     }
+    if (spl.pairs && tid == 0) spl.pairs[blockIdx.x] = npts * tl.tn;
     double* p = part + (int64_t)tl.chunk * 6 * T;
 #pragma unroll
     for (int u = 0; u < TPT; ++u) {
@@ -1323,6 +1445,18 @@ __global__ void k_rnear(int E, const ElemInfo* __restrict__ info, const double* 
         ds = fmax(ds, 2.0 * inf.rad * cosh(fmin(imphi, 40.0)));
     }
     rnear[e] = 1.05 * fmax(dth, ds) + 1e-12;
+    // the distance from the centre beyond which an element closed at an end
+    // may use its own nodes (the N_s-point Gauss rule in s) as its far-field
+    // rule, by the same estimates; at least the candidate radius, since the
+    // own rule is the coarser one
+    double rc = INFINITY;
+    if (inf.closed && inf.fb == 2) {
+        const double rq = pow(gc.cs / gc.tol, 1.0 / (double)(2 * NS - Ms));
+        double ds1 = inf.smax * h * 0.5 * (rq - 1.0 / rq);
+        ds1 = fmax(ds1, 2.0 * inf.rad * cosh(fmin(3.14159265358979323846 * 0.25 * (rq - 1.0 / rq), 40.0)));
+        rc = inf.rad + fmax(1.05 * fmax(dth, ds1) + 1e-12, rnear[e]);
+    }
+    rnear[E + e] = rc;
 }
 
 // ---------------------------------------------------------------------------
@@ -2425,12 +2559,12 @@ int launch_expand_up(hipStream_t st, int E, int ns_f, int nt_f, const double* gx
     return 0;
 }
 
-int launch_base_build(hipStream_t st, int E, const ElemInfo* info, const int64_t* boff, const double* ny,
-                      const double* nn, const double* nw, int64_t N, const double* c0y, const double* c0n,
-                      const double* c0w, int64_t M0, double* by, double* bn, double* bw, int64_t Nb)
+int launch_base_build(hipStream_t st, int E, const ElemInfo* info, const int64_t* boff, const int64_t* ooff,
+                      const double* ny, const double* nn, const double* nw, int64_t N, const double* c0y,
+                      const double* c0n, const double* c0w, int64_t M0, double* by, double* bn, double* bw, int64_t Nb)
 {
-    hipLaunchKernelGGL(k_base_build, dim3(E), dim3(256), 0, st, E, info, boff, ny, nn, nw, N, c0y, c0n, c0w, M0, by,
-                       bn, bw, Nb);
+    hipLaunchKernelGGL(k_base_build, dim3(E), dim3(256), 0, st, E, info, boff, ooff, ny, nn, nw, N, c0y, c0n, c0w, M0,
+                       by, bn, bw, Nb);
     LAUNCH_CHECK();
     return 0;
 }
@@ -2487,10 +2621,10 @@ int launch_sigma_up(hipStream_t st, int E, int ns_f, int nt_f, const double* sh,
     return 0;
 }
 
-int launch_sigma_base(hipStream_t st, int E, const ElemInfo* info, const int64_t* boff, const double* sw, int64_t N,
-                      const double* swf0, int64_t M0, double* bsw, int64_t Nb)
+int launch_sigma_base(hipStream_t st, int E, const ElemInfo* info, const int64_t* boff, const int64_t* ooff,
+                      const double* sw, int64_t N, const double* swf0, int64_t M0, double* bsw, int64_t Nb)
 {
-    hipLaunchKernelGGL(k_sigma_base, dim3(E), dim3(256), 0, st, E, info, boff, sw, N, swf0, M0, bsw, Nb);
+    hipLaunchKernelGGL(k_sigma_base, dim3(E), dim3(256), 0, st, E, info, boff, ooff, sw, N, swf0, M0, bsw, Nb);
     LAUNCH_CHECK();
     return 0;
 }
@@ -2512,18 +2646,19 @@ int launch_targets(hipStream_t st, int64_t T, const double* x, const int64_t* tn
 }
 
 int launch_far(hipStream_t st, int64_t T, const double* xt, const double* sy, const double* sn, const double* ssw,
-               int64_t N, const FarTile* tiles, int ntiles, double* part, bool mixed, double near2, int tpt, int ker)
+               int64_t N, const FarTile* tiles, int ntiles, double* part, bool mixed, double near2, int tpt, int ker,
+               const FarSplit& spl)
 {
     if (ntiles == 0) return 0;
     if (mixed && ker != KER_STOKES) return (int)hipErrorInvalidValue;
     const dim3 grid((unsigned)ntiles), blk(FAR_BLOCK);
 #define CSBQ_FAR(K)                                                                                                 \
     if (mixed)                                                                                                      \
-        hipLaunchKernelGGL(k_far_mx<K>, grid, blk, 0, st, T, xt, sy, sn, ssw, N, tiles, near2, part);              \
+        hipLaunchKernelGGL(k_far_mx<K>, grid, blk, 0, st, T, xt, sy, sn, ssw, N, tiles, near2, part, spl);         \
     else if (ker == KER_LAPLACE)                                                                                    \
-        hipLaunchKernelGGL((k_far<K, KER_LAPLACE>), grid, blk, 0, st, T, xt, sy, sn, ssw, N, tiles, part);          \
+        hipLaunchKernelGGL((k_far<K, KER_LAPLACE>), grid, blk, 0, st, T, xt, sy, sn, ssw, N, tiles, part, spl);     \
     else                                                                                                            \
-        hipLaunchKernelGGL((k_far<K, KER_STOKES>), grid, blk, 0, st, T, xt, sy, sn, ssw, N, tiles, part);
+        hipLaunchKernelGGL((k_far<K, KER_STOKES>), grid, blk, 0, st, T, xt, sy, sn, ssw, N, tiles, part, spl);
     switch (tpt) {
     case 1: CSBQ_FAR(1) break;
     case 2: CSBQ_FAR(2) break;
@@ -2720,6 +2855,7 @@ __global__ void k_noalloc_setup(int ntiles, int nch, int64_t T, int64_t N, int t
     f.tn = (int32_t)min((int64_t)tb, T - t0);
     f.sn = (int32_t)min(chunk, N - s0);
     f.chunk = c;
+    f.e0 = f.e1 = 0;   // a plain source range
     f.pad_ = 0;
     tiles[i] = f;
 }
