@@ -124,14 +124,16 @@ typedef enum { CSBQ_KERNEL_STOKES = 0, CSBQ_KERNEL_LAPLACE = 1 } csbq_kernel;
 typedef enum { CSBQ_SRULE_AUTO = 0, CSBQ_SRULE_WHOLE = 1, CSBQ_SRULE_GENERAL = 2 } csbq_srule;
 
 /* Far-field rule of an element closed at an end (a sphere as one element in
-   its polar angle; Section 3.2.1's smooth rule).  Its own N_s x N_theta
-   nodes converge slowly in s far from it, so near it the smooth sum uses a
-   32 x 32 rule (the first upsampled rule) that the local corrections then
-   subtract.  AUTO (default): a smooth-sum block whose targets all lie beyond
-   the distance at which the criterion's estimates let the own nodes meet
-   quad_tol (for the density's measured band) sums the element's own nodes
-   instead; every candidate pair lies inside that distance, so the
-   corrections are unchanged.  BASE: the 32 x 32 rule for every target. */
+   its polar angle; Section 3.2.1's smooth rule).  Gauss-Legendre rules in
+   the polar angle converge slowly near such an element, so near it the
+   smooth sum uses a 32 x 32 rule (the first upsampled rule) that the local
+   corrections then subtract.  AUTO (default): a smooth-sum block of targets
+   sums the coarsest of the element's 24 x 32, 20 x 32 and own 16 x 32 rules
+   whose distance from the element's centre, at which the criterion's
+   estimates let it meet quad_tol for the density's measured band, all its
+   targets lie beyond; else the 32 x 32 rule.  Every candidate pair lies
+   inside those distances, so the corrections are unchanged.  BASE: the
+   32 x 32 rule for every target. */
 typedef enum { CSBQ_FAR_AUTO = 0, CSBQ_FAR_BASE = 1 } csbq_far_rule;
 
 typedef struct {

@@ -142,8 +142,9 @@ class Evaluator:
         the cylinder rules on every other open element with a tabulated
         aspect) or "general" (dyadic panels and the log-singular rule
         everywhere).  far_rule: the far-field rule of elements closed at an
-        end (spheres): "auto" (their own nodes for targets beyond the
-        distance where those meet quad_tol, the 32 x 32 rule nearer) or
+        end (spheres): "auto" (for each block of targets the coarsest of
+        their 24 x 32, 20 x 32 and own 16 x 32 rules that meets quad_tol
+        there by the criterion's estimates, the 32 x 32 rule nearer) or
         "base" (the 32 x 32 rule for every target)."""
         lib = load_library()
         opt = _Options()

@@ -233,6 +233,33 @@ static int load_tables(csbq_ctx* ctx)
 }
 
 // Whole-element singular s-rules (Section 3.2.4, second part), written by
+// the coarser far-field rules as the base-set kernels take them
+static FarRules far_rules(const csbq_ctx* ctx)
+{
+    FarRules fr{};
+    for (int k = 0; k < NFAR - 1; ++k) {
+        fr.y[k] = ctx->cfy[k].p;
+        fr.n[k] = ctx->cfn[k].p;
+        fr.w[k] = ctx->cfw[k].p;
+        fr.sw[k] = ctx->swfar[k].p;
+        fr.M[k] = ctx->Mfar[k];
+    }
+    return fr;
+}
+
+// density times weight on the coarser far-field rules (from the Fourier
+// coefficients on the GL circles, as on the upsampled rules); the buffers
+// are sized by the geometry, so an evaluation plan's replay allocates nothing
+static int sigma_far(csbq_ctx* ctx, hipStream_t st)
+{
+    for (int k = 0; k < NFAR - 1; ++k) {
+        int r = launch_sigma_up(st, ctx->E, far_ns(k), NT, ctx->sh.p, ctx->Lfar[k].p, ctx->cfw[k].p, ctx->swfar[k].p,
+                                ctx->Mfar[k]);
+        if (r) return r;
+    }
+    return 0;
+}
+
 // tables/gen_srules.py: per cylinder aspect bracket and target GL index, then
 // (optionally) per target GL index of the sphere element, node offsets from
 // the GL node in the element variable v in [-1, 1] and their weights.
@@ -748,6 +775,28 @@ int csbq_set_geometry_batch(csbq_ctx* ctx, int32_t n_bodies, const int32_t* body
         LCHK(launch_expand_up(ctx->stream, (int)E, nsf, ntf, ctx->upx[ti].p, ctx->upw[ti].p, ctx->clq.p, ctx->info.p,
                               ctx->cpy[ti].p, ctx->cpn[ti].p, ctx->cpw[ti].p, ctx->Mtot[ti]));
     }
+    // coarser far-field rules (far_ns(k) x NT) the smooth sum may take for
+    // an element closed at an end far from its targets
+    for (int k = 0; k < NFAR - 1; ++k) {
+        const int nsf = far_ns(k);
+        ctx->Mfar[k] = E * nsf * NT;
+        ALLOC(ctx->cfy[k], (size_t)ctx->Mfar[k] * 3);
+        ALLOC(ctx->cfn[k], (size_t)ctx->Mfar[k] * 3);
+        ALLOC(ctx->cfw[k], (size_t)ctx->Mfar[k]);
+        std::vector<double> gxf(nsf), gwf(nsf), lamf(nsf), Df((size_t)nsf * nsf), Tf((size_t)nsf * nsf);
+        gl_tables(nsf, gxf.data(), gwf.data(), lamf.data(), Df.data(), Tf.data());
+        std::vector<double> L((size_t)nsf * NS);
+        for (int p = 0; p < nsf; ++p) lagrange_row(NS, ctx->gx, ctx->lam, gxf[p], &L[(size_t)p * NS]);
+        ALLOC(ctx->Lfar[k], L.size());
+        ALLOC(ctx->farx[k], (size_t)nsf);
+        ALLOC(ctx->farw[k], (size_t)nsf);
+        HIPC(hipMemcpy(ctx->Lfar[k].p, L.data(), L.size() * 8, hipMemcpyHostToDevice));
+        HIPC(hipMemcpy(ctx->farx[k].p, gxf.data(), nsf * 8, hipMemcpyHostToDevice));
+        HIPC(hipMemcpy(ctx->farw[k].p, gwf.data(), nsf * 8, hipMemcpyHostToDevice));
+        ALLOC(ctx->swfar[k], (size_t)ctx->Mfar[k] * 3);
+        LCHK(launch_expand_up(ctx->stream, (int)E, nsf, NT, ctx->farx[k].p, ctx->farw[k].p, ctx->clq.p, ctx->info.p,
+                              ctx->cfy[k].p, ctx->cfn[k].p, ctx->cfw[k].p, ctx->Mfar[k]));
+    }
     // base (far-field) source set: own nodes, or the tier-0 rule for elements
     // whose cross-section closes at an end
     {
@@ -764,8 +813,9 @@ int csbq_set_geometry_batch(csbq_ctx* ctx, int32_t n_bodies, const int32_t* body
         HIPC(hipMemcpy(ctx->info.p, hinf.data(), (size_t)E * sizeof(ElemInfo), hipMemcpyHostToDevice));
         ctx->n_cyl = nshape[SHAPE_CYLINDER];
         ctx->n_sph = nshape[SHAPE_SPHERE];
-        // boff[0..E]: the base rules; boff[E + 1 + e]: the own nodes of an
-        // element with the tier-0 rule as its base rule, appended after them
+        // boff[0..E]: the base rules; boff[E + 1 + e]: the coarser far-field
+        // rules of an element with the tier-0 rule as its base rule, appended
+        // after them
         std::vector<int64_t> bo((size_t)2 * E + 1, -1);
         bo[0] = 0;
         for (int64_t e = 0; e < E; ++e) bo[e + 1] = bo[e] + (hinf[e].fb == 2 ? up_pts(0) : NPE);
@@ -774,7 +824,7 @@ int csbq_set_geometry_batch(csbq_ctx* ctx, int32_t n_bodies, const int32_t* body
         for (int64_t e = 0; e < E; ++e)
             if (hinf[e].fb == 2) {
                 bo[E + 1 + e] = nb;
-                nb += NPE;
+                nb += FAR_EXT;
             }
         ctx->Nb = nb;
         ctx->h_boff.assign(bo.begin(), bo.begin() + E + 1);
@@ -785,10 +835,10 @@ int csbq_set_geometry_batch(csbq_ctx* ctx, int32_t n_bodies, const int32_t* body
         HIPC(hipMemcpy(ctx->boff.p, bo.data(), bo.size() * sizeof(int64_t), hipMemcpyHostToDevice));
         LCHK(launch_base_build(ctx->stream, (int)E, ctx->info.p, ctx->boff.p, ctx->boff.p + E + 1, ctx->ny.p,
                                ctx->nn.p, ctx->nw.p, N, ctx->cpy[0].p, ctx->cpn[0].p, ctx->cpw[0].p, ctx->Mtot[0],
-                               ctx->by.p, ctx->bn.p, ctx->bw.p, ctx->Nb));
+                               far_rules(ctx), ctx->by.p, ctx->bn.p, ctx->bw.p, ctx->Nb));
         // mixed precision: sources within sqrt(100 w_max) of a target are
         // summed in FP64, so no FP32 term exceeds ~1e-2 of the density scale
-        // (w_max over the base rules: the own nodes of closed elements are
+        // (w_max over the base rules: the coarser rules of closed elements are
         // summed only far from them)
         std::vector<double> hbw((size_t)ctx->Nb_rules);
         HIPC(hipMemcpyAsync(hbw.data(), ctx->bw.p, hbw.size() * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
@@ -896,7 +946,7 @@ static int eval_front(csbq_ctx* ctx, const double* sigma, int64_t T, const doubl
     ALLOC(ctx->sw, (size_t)N * 3);
     ALLOC(ctx->sh, (size_t)E * NS * NSH);
     ALLOC(ctx->band, (size_t)E * 2);
-    ALLOC(ctx->rnear, (size_t)E * 2);
+    ALLOC(ctx->rnear, (size_t)E * (1 + NFAR));
     // (a negative threshold asks for the full band: see csbq_ctx::full_band)
     LCHK(launch_prep_sigma(ctx->stream, E, *sig_dev, ctx->nw.p, N, ctx->sw.p, ctx->sh.p, ctx->band.p,
                            ctx->full_band ? -1.0 : 0.1 * ctx->gc.tol, ctx->info.p, ctx->circ.p, ctx->gc,
@@ -1019,16 +1069,17 @@ static void far_tiles(const csbq_ctx* ctx, const std::vector<int64_t>& tr, bool 
     xcd_order(tiles, chunk);
 }
 
-// the element chunks' choice of source set (closed elements' own nodes
+// the element chunks' choice of source set (closed elements' coarser rules
 // beyond rc), with the per-block pair counts written to `pairs`
 static FarSplit far_split(const csbq_ctx* ctx, int64_t* pairs)
 {
     FarSplit f{};
     f.boff = ctx->boff.p;
-    f.ooff = ctx->boff.p + ctx->E + 1;
+    f.xoff = ctx->boff.p + ctx->E + 1;
     f.rc = ctx->far_split ? ctx->rnear.p + ctx->E : nullptr;
     f.info = ctx->info.p;
     f.pairs = pairs;
+    f.E = ctx->E;
     return f;
 }
 
@@ -1294,8 +1345,9 @@ int csbq_eval_batch(csbq_ctx* ctx, const double* sigma, int64_t T, const double*
     LCHK(launch_sigma_up(st, E, up_ns(0), up_nt(0), ctx->sh.p, ctx->Lup[0].p, ctx->cpw[0].p, ctx->swf[0].p,
                          ctx->Mtot[0]));
     ALLOC(ctx->bsw, (size_t)ctx->Nb * 3);
+    LCHK(sigma_far(ctx, st));
     LCHK(launch_sigma_base(st, E, ctx->info.p, ctx->boff.p, ctx->boff.p + E + 1, ctx->sw.p, N, ctx->swf[0].p,
-                           ctx->Mtot[0], ctx->bsw.p, ctx->Nb));
+                           ctx->Mtot[0], far_rules(ctx), ctx->bsw.p, ctx->Nb));
     // candidate pairs: count, scan (the fill follows the synchronisation)
     HIPC(hipEventRecord(ctx->ph[2].a, st));
     ALLOC(ctx->cnt, (size_t)T + 1);
@@ -1526,8 +1578,9 @@ static int enqueue_apply(csbq_ctx* ctx, hipStream_t st)
     LCHK(launch_band_check(st, E, ctx->band_apply.p, ctx->band.p, ctx->err_d.p));
     LCHK(launch_sigma_up(st, E, up_ns(0), up_nt(0), ctx->sh.p, ctx->Lup[0].p, ctx->cpw[0].p, ctx->swf[0].p,
                          ctx->Mtot[0]));
+    LCHK(sigma_far(ctx, st));
     LCHK(launch_sigma_base(st, E, ctx->info.p, ctx->boff.p, ctx->boff.p + E + 1, ctx->sw.p, N, ctx->swf[0].p,
-                           ctx->Mtot[0], ctx->bsw.p, ctx->Nb));
+                           ctx->Mtot[0], far_rules(ctx), ctx->bsw.p, ctx->Nb));
     LCHK(launch_far(st, T, ctx->xt.p, ctx->by.p, ctx->bn.p, ctx->bsw.p, ctx->Nb, ctx->tiles.p, pl.ntiles, ctx->part.p,
                     pl.mixed, ctx->mix_near2, pl.tpt, ctx->ker, far_split(ctx, ctx->fpairs.p)));
     for (int ti = 1; ti < NUP; ++ti)
@@ -1995,7 +2048,7 @@ int csbq_stats(const csbq_ctx* ctx, char* buf, int64_t cap)
         std::snprintf(tmp, sizeof tmp, ", \"gate_escalated\": %lld", (long long)ctx->last_esc);
         s += tmp;
     }
-    // pairs the last smooth sum summed (closed elements' own nodes where
+    // pairs the last smooth sum summed (closed elements' coarser rules where
     // chosen), and what its base rules alone would have summed
     int64_t far_pairs = ctx->last_far_pairs;
     if (ctx->fpairs_ok && ctx->last_ntiles > 0) {

@@ -40,6 +40,16 @@ __host__ __device__ constexpr int up_ns(int k) { return k == 2 ? 64 : 32; }
 __host__ __device__ constexpr int up_nt(int k) { return k == 0 ? 32 : (k == 1 ? 64 : 128); }
 __host__ __device__ constexpr int64_t up_pts(int k) { return (int64_t)up_ns(k) * up_nt(k); }
 
+// coarser far-field rules of an element closed at an end, finest first:
+// Gauss-Legendre of far_ns(k) points in s times NT angles, the last one its
+// own nodes; they follow the base rules in the base source set, FAR_EXT
+// points per such element (far_off(k): the rule's first point)
+constexpr int NFAR = 3;
+__host__ __device__ constexpr int far_ns(int k) { return k == 0 ? 24 : (k == 1 ? 20 : NS); }
+__host__ __device__ constexpr int64_t far_off(int k) { return k == 0 ? 0 : far_off(k - 1) + (int64_t)far_ns(k - 1) * NT; }
+constexpr int64_t FAR_EXT = far_off(NFAR - 1) + (int64_t)far_ns(NFAR - 1) * NT;
+static_assert(far_ns(NFAR - 1) == NS, "the coarsest far-field rule is the element's own nodes");
+
 // kernel pair of an evaluation: the Stokes single and double layers (Section
 // 2) or the Laplace ones (Section 4.1)
 enum : int { KER_STOKES = 0, KER_LAPLACE = 1 };
@@ -91,20 +101,19 @@ struct FarTile {
     int32_t pad_;
 };
 
-// Element chunks of the smooth sum: an element closed at an end (far-field
-// rule up_ns(0) x NT) is summed with its own N_s x N_theta nodes instead for
-// a block whose targets all lie at least rc[e] from the element's centre,
-// the distance beyond which the same error estimates that choose the
-// candidates let the own nodes meet the tolerance.  The own nodes of such
-// elements follow the base rules in the base source arrays.
+// Element chunks of the smooth sum: an element closed at an end (base rule
+// up_ns(0) x NT) is summed with the coarsest of its far_ns(k) x NT rules
+// whose radius rc_k[e] from the element's centre the block's targets all
+// lie beyond: the distance at which the same error estimates that choose the
+// candidates let that rule meet the tolerance.
 struct FarSplit {
     const int64_t* boff;    // element e's base rule: sources [boff[e], boff[e + 1])
-    const int64_t* ooff;    // its own nodes: sources [ooff[e], ooff[e] + NPE) (closed elements)
-    const double* rc;       // rc[e] (+inf: never), or null: base rules only
+    const int64_t* xoff;    // its coarser rules: sources xoff[e] + far_off(k) .. (closed elements)
+    const double* rc;       // rc_k[e] = rc[k E + e] (+inf: never), or null: base rules only
     const ElemInfo* info;   // element centres
     int64_t* pairs;         // per block: source-target pairs summed (or null)
+    int E;
 };
-
 // constants of the error estimates (calibrated against the CPU oracle)
 struct GateConsts {
     double tol;        // per-element quadrature tolerance

@@ -92,8 +92,14 @@ struct csbq_ctx {
     DBuf<ElemInfo> info;
     DBuf<double> cpy[NUP], cpn[NUP], cpw[NUP], Lup[NUP], upx[NUP], upw[NUP];
     int64_t Mtot[NUP] = {0, 0, 0};
+    // coarser far-field rules of elements closed at an end (every element's,
+    // far_ns(k) x NT points; the own nodes aside), their Lagrange matrices
+    // and density times weight
+    DBuf<double> cfy[NFAR - 1], cfn[NFAR - 1], cfw[NFAR - 1], Lfar[NFAR - 1], farx[NFAR - 1], farw[NFAR - 1],
+        swfar[NFAR - 1];
+    int64_t Mfar[NFAR - 1] = {};
     // far-field (base) source set
-    int64_t Nb = 0;         // base sources: the base rules, then the own nodes of closed elements
+    int64_t Nb = 0;         // base sources: the base rules, then the coarser rules of closed elements
     int64_t Nb_rules = 0;   // the base rules alone
     double mix_near2 = 0.0;   // squared radius of the FP64 near part of the mixed-precision far sum
     DBuf<int64_t> boff;
@@ -145,9 +151,9 @@ struct csbq_ctx {
     DBuf<double> emat;
     int last_ntiles = 0;
     int64_t last_far_pairs = 0;   // source-target pairs of the last smooth sum's base rules
-    DBuf<int64_t> fpairs;         // per block of the last smooth sum: pairs summed (own nodes where chosen)
+    DBuf<int64_t> fpairs;         // per block of the last smooth sum: pairs summed (coarser rules where chosen)
     bool fpairs_ok = false;
-    bool far_split = true;        // closed elements' own nodes as their far-field rule where they suffice
+    bool far_split = true;        // closed elements' coarser far-field rules where they suffice
     // host copies of the smooth-sum block list outlive the asynchronous uploads
     std::vector<FarTile> h_tiles;
     std::vector<int> h_gnc;

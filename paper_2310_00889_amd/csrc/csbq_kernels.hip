@@ -509,13 +509,14 @@ __global__ __launch_bounds__(128) void k_expand_up(int E, int ns_f, int nt_f, co
 
 // Far-field (base) source set: each element contributes its own nodes (fb = 1)
 // or its tier-0 rule (fb = 2); boff[e] is the element's first base source.
-// An fb = 2 element's own nodes follow at ooff[e] (the smooth sum's choice
-// for targets far from it).
+// An fb = 2 element's coarser far-field rules follow at xoff[e] (the smooth
+// sum's choice for targets far from it): the far_ns(k) x NT rules of fr,
+// then its own nodes.
 __global__ void k_base_build(int E, const ElemInfo* __restrict__ info, const int64_t* __restrict__ boff,
-                             const int64_t* __restrict__ ooff, const double* __restrict__ ny,
+                             const int64_t* __restrict__ xoff, const double* __restrict__ ny,
                              const double* __restrict__ nn, const double* __restrict__ nw, int64_t N,
                              const double* __restrict__ c0y, const double* __restrict__ c0n,
-                             const double* __restrict__ c0w, int64_t M0, double* __restrict__ by,
+                             const double* __restrict__ c0w, int64_t M0, FarRules fr, double* __restrict__ by,
                              double* __restrict__ bn, double* __restrict__ bw, int64_t Nb)
 {
     const int e = blockIdx.x;
@@ -534,15 +535,23 @@ __global__ void k_base_build(int E, const ElemInfo* __restrict__ info, const int
         }
         bw[o + k] = swt[src];
     }
-    if (fb == 2)
-        for (int k = threadIdx.x; k < NPE; k += blockDim.x) {
-            const int64_t src = (int64_t)e * NPE + k, dst = ooff[e] + k;
+    if (fb != 2) return;
+    for (int r = 0; r < NFAR; ++r) {
+        const int npt = far_ns(r) * NT;
+        const bool own = r == NFAR - 1;
+        const double* sy = own ? ny : fr.y[r];
+        const double* sn = own ? nn : fr.n[r];
+        const double* swt = own ? nw : fr.w[r];
+        const int64_t ld = own ? N : fr.M[r];
+        for (int k = threadIdx.x; k < npt; k += blockDim.x) {
+            const int64_t src = (int64_t)e * npt + k, dst = xoff[e] + far_off(r) + k;
             for (int d = 0; d < 3; ++d) {
-                by[d * Nb + dst] = ny[d * N + src];
-                bn[d * Nb + dst] = nn[d * N + src];
+                by[d * Nb + dst] = sy[d * ld + src];
+                bn[d * Nb + dst] = sn[d * ld + src];
             }
-            bw[dst] = nw[src];
+            bw[dst] = swt[src];
         }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -639,8 +648,9 @@ __global__ __launch_bounds__(256) void k_sigma_up(int E, int ns_f, int nt_f, con
     for (int o = tid; o < NS * NSH; o += blockDim.x) shl[o] = sh[(int64_t)e * NS * NSH + o];
     __syncthreads();
     for (int rb = 0; rb < ns_f; rb += NS) {
-        // coefficients at s-points rb .. rb+15
-        for (int o = tid; o < NS * NSH; o += blockDim.x) {
+        // coefficients at s-points rb .. min(rb + 16, ns_f) - 1
+        const int nr = min(NS, ns_f - rb);
+        for (int o = tid; o < nr * NSH; o += blockDim.x) {
             int r = o / NSH, k = o % NSH;
             int pp = rb + r;
             double v = 0.0;
@@ -648,7 +658,7 @@ __global__ __launch_bounds__(256) void k_sigma_up(int E, int ns_f, int nt_f, con
             A[o] = v;
         }
         __syncthreads();
-        for (int o = tid; o < NS * nt_f; o += blockDim.x) {
+        for (int o = tid; o < nr * nt_f; o += blockDim.x) {
             int r = o / nt_f, q = o % nt_f;
             double th = 2.0 * PI * q / nt_f;
             double s1, c1;
@@ -676,8 +686,9 @@ __global__ __launch_bounds__(256) void k_sigma_up(int E, int ns_f, int nt_f, con
 
 // density times weight on the base (far-field) source set
 __global__ void k_sigma_base(int E, const ElemInfo* __restrict__ info, const int64_t* __restrict__ boff,
-                             const int64_t* __restrict__ ooff, const double* __restrict__ sw, int64_t N,
-                             const double* __restrict__ swf0, int64_t M0, double* __restrict__ bsw, int64_t Nb)
+                             const int64_t* __restrict__ xoff, const double* __restrict__ sw, int64_t N,
+                             const double* __restrict__ swf0, int64_t M0, FarRules fr, double* __restrict__ bsw,
+                             int64_t Nb)
 {
     const int e = blockIdx.x;
     const int fb = info[e].fb;
@@ -687,9 +698,16 @@ __global__ void k_sigma_base(int E, const ElemInfo* __restrict__ info, const int
         for (int d = 0; d < 3; ++d)
             bsw[d * Nb + o + k] = fb == 2 ? swf0[d * M0 + (int64_t)e * up_pts(0) + k] : sw[d * N + (int64_t)e * NPE + k];
     }
-    if (fb == 2)
-        for (int k = threadIdx.x; k < NPE; k += blockDim.x)
-            for (int d = 0; d < 3; ++d) bsw[d * Nb + ooff[e] + k] = sw[d * N + (int64_t)e * NPE + k];
+    if (fb != 2) return;
+    for (int r = 0; r < NFAR; ++r) {
+        const int npt = far_ns(r) * NT;
+        const bool own = r == NFAR - 1;
+        const double* ssw = own ? sw : fr.sw[r];
+        const int64_t ld = own ? N : fr.M[r];
+        for (int k = threadIdx.x; k < npt; k += blockDim.x)
+            for (int d = 0; d < 3; ++d)
+                bsw[d * Nb + xoff[e] + far_off(r) + k] = ssw[d * ld + (int64_t)e * npt + k];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -772,49 +790,48 @@ __device__ inline void block_box(double* lo, double* hi, double* red /*[2][3][FA
     __syncthreads();
 }
 
-// Which of the elements e0 .. e0 + n - 1 (n <= 64) of an element chunk are
-// summed with their own nodes: those whose rc[e] the block's target box
-// [lo, hi] keeps clear of their centre.  Lane l tests element e0 + l; the
-// ballot gives every lane (and the scalar unit) the same mask.
-__device__ __forceinline__ uint64_t far_own_mask(const FarSplit& spl, int e0, int n, const double* lo,
-                                                 const double* hi)
+// Source ranges [seg[2 q], seg[2 q + 1]) of segments q0 .. q0 + nq - 1
+// (nq <= 64) of a block, written to LDS by the first nq threads: for an
+// element chunk, element tl.e0 + q's coarsest far-field rule k whose radius
+// rc_k[e] from the element's centre the block's target box [lo, hi] keeps
+// clear of, else its base rule; for a plain chunk, its source range.
+__device__ __forceinline__ void far_segments(const FarTile& tl, const FarSplit& spl, int q0, int nq, const double* lo,
+                                             const double* hi, int64_t* seg)
 {
-    const int l = threadIdx.x & 63;
-    bool own = false;
-    if (l < n) {
-        const int e = e0 + l;
-        const double rc = spl.rc[e];
-        if (rc < INFINITY) {
+    const int l = threadIdx.x;
+    if (l >= nq) return;
+    int64_t a = tl.s0, b = tl.s0 + tl.sn;
+    if (tl.e1 > tl.e0) {
+        const int e = tl.e0 + q0 + l;
+        a = spl.boff[e];
+        b = spl.boff[e + 1];
+        if (spl.rc) {
             const ElemInfo& inf = spl.info[e];
             double g2 = 0.0;
             for (int d = 0; d < 3; ++d) {
                 const double g = fmax(0.0, fmax(lo[d] - inf.cen[d], inf.cen[d] - hi[d]));
                 g2 += g * g;
             }
-            own = g2 >= rc * rc;
+            for (int k = NFAR - 1; k >= 0; --k) {
+                const double rc = spl.rc[(int64_t)k * spl.E + e];
+                if (rc < INFINITY && g2 >= rc * rc) {
+                    a = spl.xoff[e] + far_off(k);
+                    b = a + (int64_t)far_ns(k) * NT;
+                    break;
+                }
+            }
         }
     }
-    return (uint64_t)__ballot(own);
+    seg[2 * l] = a;
+    seg[2 * l + 1] = b;
 }
 
-// the sources of segment q of a block: element tl.e0 + q's own nodes or base
-// rule (element chunks), else the chunk's plain range
-__device__ __forceinline__ void far_segment(const FarTile& tl, const FarSplit& spl, int q, uint64_t own, int64_t& a,
-                                            int64_t& b)
+// a value every lane holds alike, made provably uniform (scalar registers)
+__device__ __forceinline__ int64_t uniform64(int64_t v)
 {
-    if (tl.e1 > tl.e0) {
-        const int e = tl.e0 + q;
-        if ((own >> (q & 63)) & 1) {
-            a = spl.ooff[e];
-            b = a + NPE;
-        } else {
-            a = spl.boff[e];
-            b = spl.boff[e + 1];
-        }
-    } else {
-        a = tl.s0;
-        b = tl.s0 + tl.sn;
-    }
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
 // bounding box of a block's targets, stored in box[0..5] (lo, hi) in LDS
@@ -871,6 +888,7 @@ __global__ __launch_bounds__(FAR_BLOCK) void k_far(int64_t T, const double* __re
 {
     __shared__ double red[6 * (FAR_BLOCK / 64)];
     __shared__ double box[6];
+    __shared__ int64_t seg[2 * 64];
     const int tid = threadIdx.x;
     const FarTile tl = tiles[blockIdx.x];
     const int64_t tb = tl.t0 + tid, tend = tl.t0 + tl.tn;
@@ -884,18 +902,21 @@ __global__ __launch_bounds__(FAR_BLOCK) void k_far(int64_t T, const double* __re
         x[u][2] = ok ? xt[2 * T + t] : 0.0;
         for (int d = 0; d < 3; ++d) sa[u][d] = sb[u][d] = sd[u][d] = 0.0;
     }
-    // a plain source range, or the far-field rules of whole elements
-    const bool split = tl.e1 > tl.e0 && spl.rc;
-    if (split) target_box<TPT>(x, tb, tend, box, red);
+    // a plain source range, or the far-field rules of whole elements, in
+    // batches of up to 64 segments whose ranges are staged in LDS
+    if (tl.e1 > tl.e0 && spl.rc) target_box<TPT>(x, tb, tend, box, red);
     const int nseg = tl.e1 > tl.e0 ? tl.e1 - tl.e0 : 1;
-    uint64_t own = 0;
     int64_t npts = 0;
-    for (int q = 0; q < nseg; ++q) {
-        if (split && (q & 63) == 0) own = far_own_mask(spl, tl.e0 + q, min(64, nseg - q), box, box + 3);
-        int64_t a, b;
-        far_segment(tl, spl, q, own, a, b);
-        far_range<TPT, KER>(x, sy, sn, ssw, N, a, b, sa, sb, sd);
-        npts += b - a;
+    for (int q0 = 0; q0 < nseg; q0 += 64) {
+        const int nq = min(64, nseg - q0);
+        far_segments(tl, spl, q0, nq, box, box + 3, seg);
+        __syncthreads();
+        for (int q = 0; q < nq; ++q) {
+            const int64_t a = uniform64(seg[2 * q]), b = uniform64(seg[2 * q + 1]);
+            far_range<TPT, KER>(x, sy, sn, ssw, N, a, b, sa, sb, sd);
+            npts += b - a;
+        }
+        __syncthreads();
     }
     if (spl.pairs && tid == 0) spl.pairs[blockIdx.x] = npts * tl.tn;
     double* p = part + (int64_t)tl.chunk * 6 * T;
@@ -935,6 +956,7 @@ __global__ __launch_bounds__(FAR_BLOCK) void k_far_mx(int64_t T, const double* _
 {
     __shared__ FarRecMx src[FAR_BLOCK];
     __shared__ double red[6 * (FAR_BLOCK / 64)];
+    __shared__ int64_t seg[2 * 64];
     const int tid = threadIdx.x;
     const FarTile tl = tiles[blockIdx.x];
     const int64_t tb = tl.t0 + tid, tend = tl.t0 + tl.tn;
@@ -1067,16 +1089,18 @@ __global__ __launch_bounds__(FAR_BLOCK) void k_far_mx(int64_t T, const double* _
             __syncthreads();
         }
     };
-    const bool split = tl.e1 > tl.e0 && spl.rc;
     const int nseg = tl.e1 > tl.e0 ? tl.e1 - tl.e0 : 1;
-    uint64_t own = 0;
     int64_t npts = 0;
-    for (int q = 0; q < nseg; ++q) {
-        if (split && (q & 63) == 0) own = far_own_mask(spl, tl.e0 + q, min(64, nseg - q), tlo, thi);
-        int64_t a, b;
-        far_segment(tl, spl, q, own, a, b);
-        sum_range(a, b);
-        npts += b - a;
+    for (int q0 = 0; q0 < nseg; q0 += 64) {
+        const int nq = min(64, nseg - q0);
+        far_segments(tl, spl, q0, nq, tlo, thi, seg);
+        __syncthreads();
+        for (int q = 0; q < nq; ++q) {
+            const int64_t a = uniform64(seg[2 * q]), b = uniform64(seg[2 * q + 1]);
+            sum_range(a, b);
+            npts += b - a;
+        }
+        __syncthreads();
     }
     if (spl.pairs && tid == 0) spl.pairs[blockIdx.x] = npts * tl.tn;
     double* p = part + (int64_t)tl.chunk * 6 * T;
@@ -1445,18 +1469,20 @@ __global__ void k_rnear(int E, const ElemInfo* __restrict__ info, const double* 
         ds = fmax(ds, 2.0 * inf.rad * cosh(fmin(imphi, 40.0)));
     }
     rnear[e] = 1.05 * fmax(dth, ds) + 1e-12;
-    // the distance from the centre beyond which an element closed at an end
-    // may use its own nodes (the N_s-point Gauss rule in s) as its far-field
-    // rule, by the same estimates; at least the candidate radius, since the
-    // own rule is the coarser one
-    double rc = INFINITY;
-    if (inf.closed && inf.fb == 2) {
-        const double rq = pow(gc.cs / gc.tol, 1.0 / (double)(2 * NS - Ms));
-        double ds1 = inf.smax * h * 0.5 * (rq - 1.0 / rq);
-        ds1 = fmax(ds1, 2.0 * inf.rad * cosh(fmin(3.14159265358979323846 * 0.25 * (rq - 1.0 / rq), 40.0)));
-        rc = inf.rad + fmax(1.05 * fmax(dth, ds1) + 1e-12, rnear[e]);
+    // the distances from the centre beyond which an element closed at an end
+    // may use its coarser far-field rules (far_ns(k) Gauss points in s) in
+    // the smooth sum, by the same estimates; at least the candidate radius
+    // (the base rule is the finest)
+    for (int k = 0; k < NFAR; ++k) {
+        double rc = INFINITY;
+        if (inf.closed && inf.fb == 2) {
+            const double rq = pow(gc.cs / gc.tol, 1.0 / (double)(2 * far_ns(k) - Ms));
+            double dsk = inf.smax * h * 0.5 * (rq - 1.0 / rq);
+            dsk = fmax(dsk, 2.0 * inf.rad * cosh(fmin(3.14159265358979323846 * 0.25 * (rq - 1.0 / rq), 40.0)));
+            rc = inf.rad + fmax(1.05 * fmax(dth, dsk) + 1e-12, rnear[e]);
+        }
+        rnear[(int64_t)(1 + k) * E + e] = rc;
     }
-    rnear[E + e] = rc;
 }
 
 // ---------------------------------------------------------------------------
@@ -2559,12 +2585,13 @@ int launch_expand_up(hipStream_t st, int E, int ns_f, int nt_f, const double* gx
     return 0;
 }
 
-int launch_base_build(hipStream_t st, int E, const ElemInfo* info, const int64_t* boff, const int64_t* ooff,
+int launch_base_build(hipStream_t st, int E, const ElemInfo* info, const int64_t* boff, const int64_t* xoff,
                       const double* ny, const double* nn, const double* nw, int64_t N, const double* c0y,
-                      const double* c0n, const double* c0w, int64_t M0, double* by, double* bn, double* bw, int64_t Nb)
+                      const double* c0n, const double* c0w, int64_t M0, const FarRules& fr, double* by, double* bn,
+                      double* bw, int64_t Nb)
 {
-    hipLaunchKernelGGL(k_base_build, dim3(E), dim3(256), 0, st, E, info, boff, ooff, ny, nn, nw, N, c0y, c0n, c0w, M0,
-                       by, bn, bw, Nb);
+    hipLaunchKernelGGL(k_base_build, dim3(E), dim3(256), 0, st, E, info, boff, xoff, ny, nn, nw, N, c0y, c0n, c0w, M0,
+                       fr, by, bn, bw, Nb);
     LAUNCH_CHECK();
     return 0;
 }
@@ -2621,10 +2648,11 @@ int launch_sigma_up(hipStream_t st, int E, int ns_f, int nt_f, const double* sh,
     return 0;
 }
 
-int launch_sigma_base(hipStream_t st, int E, const ElemInfo* info, const int64_t* boff, const int64_t* ooff,
-                      const double* sw, int64_t N, const double* swf0, int64_t M0, double* bsw, int64_t Nb)
+int launch_sigma_base(hipStream_t st, int E, const ElemInfo* info, const int64_t* boff, const int64_t* xoff,
+                      const double* sw, int64_t N, const double* swf0, int64_t M0, const FarRules& fr, double* bsw,
+                      int64_t Nb)
 {
-    hipLaunchKernelGGL(k_sigma_base, dim3(E), dim3(256), 0, st, E, info, boff, ooff, sw, N, swf0, M0, bsw, Nb);
+    hipLaunchKernelGGL(k_sigma_base, dim3(E), dim3(256), 0, st, E, info, boff, xoff, sw, N, swf0, M0, fr, bsw, Nb);
     LAUNCH_CHECK();
     return 0;
 }

@@ -15,14 +15,26 @@ int launch_expand(hipStream_t st, int E, const double* xc, const double* eps, co
                   ElemInfo* info, double* ny, double* nn, double* nw, int64_t N, int closed_fb);
 int launch_expand_up(hipStream_t st, int E, int ns_f, int nt_f, const double* gx_f, const double* gw_f,
                      const double* clq, const ElemInfo* info, double* cpy, double* cpn, double* cpw, int64_t Mtot);
-// base (far-field) source set; ooff[e]: where an fb = 2 element's own nodes
-// follow the base rules (elements closed at an end)
-int launch_base_build(hipStream_t st, int E, const ElemInfo* info, const int64_t* boff, const int64_t* ooff,
+// The coarser far-field rules of every element (far_ns(k) x NT points, SoA
+// with leading dimension M[k] = E far_ns(k) NT; their own nodes aside): the
+// points, normals and weights, and sigma * w after the density preparation.
+struct FarRules {
+    const double* y[NFAR - 1];
+    const double* n[NFAR - 1];
+    const double* w[NFAR - 1];
+    const double* sw[NFAR - 1];
+    int64_t M[NFAR - 1];
+};
+// base (far-field) source set; xoff[e]: where an fb = 2 element's coarser
+// far-field rules follow the base rules (elements closed at an end)
+int launch_base_build(hipStream_t st, int E, const ElemInfo* info, const int64_t* boff, const int64_t* xoff,
                       const double* ny, const double* nn, const double* nw, int64_t N, const double* c0y,
-                      const double* c0n, const double* c0w, int64_t M0, double* by, double* bn, double* bw, int64_t Nb);
-// rnear (if not null, 2E doubles): the candidate radius of each element in
-// [0, E), and in [E, 2E) the distance from its centre beyond which an element
-// closed at an end may use its own nodes as its far-field rule (+inf: never)
+                      const double* c0n, const double* c0w, int64_t M0, const FarRules& fr, double* by, double* bn,
+                      double* bw, int64_t Nb);
+// rnear (if not null, (1 + NFAR) E doubles): the candidate radius of each
+// element in [0, E), and in [(1 + k) E, (2 + k) E) the distance from its
+// centre beyond which an element closed at an end may use its far-field
+// rule k in the smooth sum (+inf: never)
 int launch_prep_sigma(hipStream_t st, int E, const double* sigma, const double* nw, int64_t N, double* sw,
                       double* sh, int* band, double eta, const ElemInfo* info, const double* circ, GateConsts gc,
                       double* rnear);
@@ -30,8 +42,9 @@ int launch_band_check(hipStream_t st, int E, const int* band_new, const int* ban
 int launch_fill_i32(hipStream_t st, int64_t n, int* v, int val);
 int launch_sigma_up(hipStream_t st, int E, int ns_f, int nt_f, const double* sh, const double* Lup, const double* cpw,
                     double* swf, int64_t Mtot);
-int launch_sigma_base(hipStream_t st, int E, const ElemInfo* info, const int64_t* boff, const int64_t* ooff,
-                      const double* sw, int64_t N, const double* swf0, int64_t M0, double* bsw, int64_t Nb);
+int launch_sigma_base(hipStream_t st, int E, const ElemInfo* info, const int64_t* boff, const int64_t* xoff,
+                      const double* sw, int64_t N, const double* swf0, int64_t M0, const FarRules& fr, double* bsw,
+                      int64_t Nb);
 int launch_targets(hipStream_t st, int64_t T, const double* x, const int64_t* tnode, const int* tgrp_in, int G,
                    const ElemInfo* info, const double* ny, int64_t N, double* xt, int* tgroup, int64_t* gstart,
                    int* err);

@@ -1,9 +1,10 @@
-"""Far-field rule of elements closed at an end (spheres as one element): the
-smooth sum takes a sphere's own 16 x 32 nodes instead of its 32 x 32 rule for
-blocks of targets beyond the distance at which the criterion's estimates let
-the own nodes meet quad_tol (Section 3.2.1's smooth rule, with the error
-estimates of Section 3.3).  Checked against the oracle and against the same
-evaluation with the 32 x 32 rule everywhere (far_rule="base")."""
+"""Far-field rules of elements closed at an end (spheres as one element): the
+smooth sum takes, for a block of targets, the coarsest of a sphere's
+Gauss-Legendre rules in s (32, 24, 20 points, or its own 16, times 32
+angles) whose distance, by the criterion's estimates, lets it meet quad_tol
+beyond it (Section 3.2.1's smooth rule, with the error estimates of Section
+3.3).  Checked against the oracle and against the same evaluation with the
+32 x 32 rule everywhere (far_rule="base")."""
 import numpy as np
 import pytest
 
@@ -21,8 +22,8 @@ def _rel(a, b):
 
 def _lattice_scene(seed=11, n=3, spacing=2.5, radius=0.3):
     """n^3 spheres on a cubic lattice, randomly oriented, each carrying a
-    constant density vector (Legendre and Fourier bands 0: the own nodes
-    suffice from about ten radii at quad_tol 1e-12)."""
+    constant density vector (Legendre and Fourier bands 0: at quad_tol 1e-12
+    the 24-, 20- and 16-point rules suffice from about 5, 6 and 10 radii)."""
     rng = np.random.default_rng(seed)
     bodies, sig = [], []
     for i in range(n):
@@ -60,8 +61,8 @@ def test_far_rule_option_reported(evs):
     assert ev.stats()["far_split"] == 1 and base.stats()["far_split"] == 0
 
 
-def test_own_nodes_on_separated_spheres_fp64(evs):
-    """27 spheres, constant densities, quad_tol 1e-12: the own nodes replace
+def test_coarser_rules_on_separated_spheres_fp64(evs):
+    """27 spheres, constant densities, quad_tol 1e-12: coarser rules replace
     the 32 x 32 rule for far blocks (fewer pairs summed), every output stays
     within 1e-10 of the oracle on and off the surfaces (off them the double
     layer vanishes), and within 1e-11 of the evaluation with the 32 x 32 rule
@@ -79,7 +80,7 @@ def test_own_nodes_on_separated_spheres_fp64(evs):
     assert st["far_pairs_base"] == sb["far_pairs"] == sb["far_pairs_base"]
     assert st["far_pairs"] < 0.9 * st["far_pairs_base"]
     assert ev.flags() == 0
-    print("own nodes vs 32 x 32 rule:", _rel(us, ub), _rel(ud, db), flush=True)
+    print("coarser rules vs 32 x 32 rule:", _rel(us, ub), _rel(ud, db), flush=True)
     assert _rel(us, ub) < 1e-11 and _rel(ud, db) < 1e-11
     rng = np.random.default_rng(3)
     k = rng.choice(sc.n_nodes, 80, replace=False)
@@ -102,11 +103,11 @@ def test_own_nodes_on_separated_spheres_fp64(evs):
     assert _rel(uf, ufo) < GATE and np.abs(df - dfo).max() < GATE * smax and np.abs(df).max() < GATE * smax
 
 
-def test_own_nodes_under_a_plan(evs):
-    """A frozen plan replays the own-node choice of its evaluation: apply()
+def test_coarser_rules_under_a_plan(evs):
+    """A frozen plan replays the rule choice of its evaluation: apply()
     with a density of the same band equals a fresh evaluation bit for bit
     (8 spheres 5 apart: small enough that both contexts keep the default
-    smooth-sum shape, far enough apart for the own nodes)."""
+    smooth-sum shape, far enough apart for the coarser rules)."""
     ev, _ = evs
     import paper_2310_00889_amd as pk
     sc = _lattice_scene(seed=12, n=2, spacing=5.0)
@@ -126,9 +127,9 @@ def test_own_nodes_under_a_plan(evs):
     assert np.array_equal(us, ur) and np.array_equal(ud, dr)
 
 
-def test_own_nodes_config3_fp64_at_1e7():
+def test_coarser_rules_config3_fp64_at_1e7():
     """The 1000-sphere pipe (563,200 on-surface targets) in FP64 at quad_tol
-    1e-7: the own nodes take over most sphere pairs of the smooth sum; the
+    1e-7: coarser rules take over most sphere pairs of the smooth sum; the
     result stays within 1e-6 of the evaluation with the 32 x 32 rule and, on
     12 sampled targets per class, of the oracle."""
     import torch
@@ -152,7 +153,7 @@ def test_own_nodes_config3_fp64_at_1e7():
     us, ud, st = out["auto"]
     ub, db, _ = out["base"]
     assert st["far_pairs"] < 0.8 * st["far_pairs_base"]
-    print("own nodes vs 32 x 32 rule:", _rel(us, ub), _rel(ud, db), flush=True)
+    print("coarser rules vs 32 x 32 rule:", _rel(us, ub), _rel(ud, db), flush=True)
     assert _rel(us, ub) < 1e-6 and _rel(ud, db) < 1e-6
     rng = np.random.default_rng(8)
     idx = np.concatenate([rng.choice(np.where(sc.tgt_class == c)[0], 12, replace=False) for c in (0, 1, 2)])
