@@ -237,7 +237,7 @@ static int load_tables(csbq_ctx* ctx)
 static FarRules far_rules(const csbq_ctx* ctx)
 {
     FarRules fr{};
-    for (int k = 0; k < NFAR - 1; ++k) {
+    for (int k = 0; k < NFL; ++k) {
         fr.y[k] = ctx->cfy[k].p;
         fr.n[k] = ctx->cfn[k].p;
         fr.w[k] = ctx->cfw[k].p;
@@ -252,9 +252,10 @@ static FarRules far_rules(const csbq_ctx* ctx)
 // are sized by the geometry, so an evaluation plan's replay allocates nothing
 static int sigma_far(csbq_ctx* ctx, hipStream_t st)
 {
-    for (int k = 0; k < NFAR - 1; ++k) {
-        int r = launch_sigma_up(st, ctx->E, far_ns(k), NT, ctx->sh.p, ctx->Lfar[k].p, ctx->cfw[k].p, ctx->swfar[k].p,
-                                ctx->Mfar[k]);
+    for (int k = 0; k < NFL; ++k) {
+        if (k == FAR_OWN) continue;
+        int r = launch_sigma_up(st, ctx->E, far_ns(k / NFT), far_nt(k % NFT), ctx->sh.p, ctx->Lfar[k / NFT].p,
+                                ctx->cfw[k].p, ctx->swfar[k].p, ctx->Mfar[k]);
         if (r) return r;
     }
     return 0;
@@ -775,27 +776,31 @@ int csbq_set_geometry_batch(csbq_ctx* ctx, int32_t n_bodies, const int32_t* body
         LCHK(launch_expand_up(ctx->stream, (int)E, nsf, ntf, ctx->upx[ti].p, ctx->upw[ti].p, ctx->clq.p, ctx->info.p,
                               ctx->cpy[ti].p, ctx->cpn[ti].p, ctx->cpw[ti].p, ctx->Mtot[ti]));
     }
-    // coarser far-field rules (far_ns(k) x NT) the smooth sum may take for
-    // an element closed at an end far from its targets
-    for (int k = 0; k < NFAR - 1; ++k) {
-        const int nsf = far_ns(k);
-        ctx->Mfar[k] = E * nsf * NT;
-        ALLOC(ctx->cfy[k], (size_t)ctx->Mfar[k] * 3);
-        ALLOC(ctx->cfn[k], (size_t)ctx->Mfar[k] * 3);
-        ALLOC(ctx->cfw[k], (size_t)ctx->Mfar[k]);
+    // coarser far-field rules (far_ns(i) x far_nt(j)) the smooth sum may take
+    // for an element closed at an end far from its targets
+    for (int i = 0; i < NFS; ++i) {
+        const int nsf = far_ns(i);
         std::vector<double> gxf(nsf), gwf(nsf), lamf(nsf), Df((size_t)nsf * nsf), Tf((size_t)nsf * nsf);
         gl_tables(nsf, gxf.data(), gwf.data(), lamf.data(), Df.data(), Tf.data());
         std::vector<double> L((size_t)nsf * NS);
         for (int p = 0; p < nsf; ++p) lagrange_row(NS, ctx->gx, ctx->lam, gxf[p], &L[(size_t)p * NS]);
-        ALLOC(ctx->Lfar[k], L.size());
-        ALLOC(ctx->farx[k], (size_t)nsf);
-        ALLOC(ctx->farw[k], (size_t)nsf);
-        HIPC(hipMemcpy(ctx->Lfar[k].p, L.data(), L.size() * 8, hipMemcpyHostToDevice));
-        HIPC(hipMemcpy(ctx->farx[k].p, gxf.data(), nsf * 8, hipMemcpyHostToDevice));
-        HIPC(hipMemcpy(ctx->farw[k].p, gwf.data(), nsf * 8, hipMemcpyHostToDevice));
-        ALLOC(ctx->swfar[k], (size_t)ctx->Mfar[k] * 3);
-        LCHK(launch_expand_up(ctx->stream, (int)E, nsf, NT, ctx->farx[k].p, ctx->farw[k].p, ctx->clq.p, ctx->info.p,
-                              ctx->cfy[k].p, ctx->cfn[k].p, ctx->cfw[k].p, ctx->Mfar[k]));
+        ALLOC(ctx->Lfar[i], L.size());
+        ALLOC(ctx->farx[i], (size_t)nsf);
+        ALLOC(ctx->farw[i], (size_t)nsf);
+        HIPC(hipMemcpy(ctx->Lfar[i].p, L.data(), L.size() * 8, hipMemcpyHostToDevice));
+        HIPC(hipMemcpy(ctx->farx[i].p, gxf.data(), nsf * 8, hipMemcpyHostToDevice));
+        HIPC(hipMemcpy(ctx->farw[i].p, gwf.data(), nsf * 8, hipMemcpyHostToDevice));
+        for (int j = 0; j < NFT; ++j) {
+            const int k = i * NFT + j;
+            if (k == FAR_OWN) continue;
+            ctx->Mfar[k] = E * far_pts(k);
+            ALLOC(ctx->cfy[k], (size_t)ctx->Mfar[k] * 3);
+            ALLOC(ctx->cfn[k], (size_t)ctx->Mfar[k] * 3);
+            ALLOC(ctx->cfw[k], (size_t)ctx->Mfar[k]);
+            ALLOC(ctx->swfar[k], (size_t)ctx->Mfar[k] * 3);
+            LCHK(launch_expand_up(ctx->stream, (int)E, nsf, far_nt(j), ctx->farx[i].p, ctx->farw[i].p, ctx->clq.p,
+                                  ctx->info.p, ctx->cfy[k].p, ctx->cfn[k].p, ctx->cfw[k].p, ctx->Mfar[k]));
+        }
     }
     // base (far-field) source set: own nodes, or the tier-0 rule for elements
     // whose cross-section closes at an end
@@ -946,7 +951,7 @@ static int eval_front(csbq_ctx* ctx, const double* sigma, int64_t T, const doubl
     ALLOC(ctx->sw, (size_t)N * 3);
     ALLOC(ctx->sh, (size_t)E * NS * NSH);
     ALLOC(ctx->band, (size_t)E * 2);
-    ALLOC(ctx->rnear, (size_t)E * (1 + NFAR));
+    ALLOC(ctx->rnear, (size_t)E * (NFS + NFT));
     // (a negative threshold asks for the full band: see csbq_ctx::full_band)
     LCHK(launch_prep_sigma(ctx->stream, E, *sig_dev, ctx->nw.p, N, ctx->sw.p, ctx->sh.p, ctx->band.p,
                            ctx->full_band ? -1.0 : 0.1 * ctx->gc.tol, ctx->info.p, ctx->circ.p, ctx->gc,

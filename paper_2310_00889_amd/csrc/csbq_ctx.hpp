@@ -93,11 +93,10 @@ struct csbq_ctx {
     DBuf<double> cpy[NUP], cpn[NUP], cpw[NUP], Lup[NUP], upx[NUP], upw[NUP];
     int64_t Mtot[NUP] = {0, 0, 0};
     // coarser far-field rules of elements closed at an end (every element's,
-    // far_ns(k) x NT points; the own nodes aside), their Lagrange matrices
-    // and density times weight
-    DBuf<double> cfy[NFAR - 1], cfn[NFAR - 1], cfw[NFAR - 1], Lfar[NFAR - 1], farx[NFAR - 1], farw[NFAR - 1],
-        swfar[NFAR - 1];
-    int64_t Mfar[NFAR - 1] = {};
+    // far_pts(k) points; the own nodes aside) and density times weight on
+    // them; Lagrange matrices and Gauss tables per number of points in s
+    DBuf<double> cfy[NFL], cfn[NFL], cfw[NFL], swfar[NFL], Lfar[NFS], farx[NFS], farw[NFS];
+    int64_t Mfar[NFL] = {};
     // far-field (base) source set
     int64_t Nb = 0;         // base sources: the base rules, then the coarser rules of closed elements
     int64_t Nb_rules = 0;   // the base rules alone

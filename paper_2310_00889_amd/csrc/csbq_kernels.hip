@@ -510,8 +510,8 @@ __global__ __launch_bounds__(128) void k_expand_up(int E, int ns_f, int nt_f, co
 // Far-field (base) source set: each element contributes its own nodes (fb = 1)
 // or its tier-0 rule (fb = 2); boff[e] is the element's first base source.
 // An fb = 2 element's coarser far-field rules follow at xoff[e] (the smooth
-// sum's choice for targets far from it): the far_ns(k) x NT rules of fr,
-// then its own nodes.
+// sum's choice for targets far from it): the rules of fr in order, its own
+// nodes in the place of rule FAR_OWN.
 __global__ void k_base_build(int E, const ElemInfo* __restrict__ info, const int64_t* __restrict__ boff,
                              const int64_t* __restrict__ xoff, const double* __restrict__ ny,
                              const double* __restrict__ nn, const double* __restrict__ nw, int64_t N,
@@ -536,9 +536,9 @@ __global__ void k_base_build(int E, const ElemInfo* __restrict__ info, const int
         bw[o + k] = swt[src];
     }
     if (fb != 2) return;
-    for (int r = 0; r < NFAR; ++r) {
-        const int npt = far_ns(r) * NT;
-        const bool own = r == NFAR - 1;
+    for (int r = 0; r < NFL; ++r) {
+        const int npt = (int)far_pts(r);
+        const bool own = r == FAR_OWN;
         const double* sy = own ? ny : fr.y[r];
         const double* sn = own ? nn : fr.n[r];
         const double* swt = own ? nw : fr.w[r];
@@ -699,9 +699,9 @@ __global__ void k_sigma_base(int E, const ElemInfo* __restrict__ info, const int
             bsw[d * Nb + o + k] = fb == 2 ? swf0[d * M0 + (int64_t)e * up_pts(0) + k] : sw[d * N + (int64_t)e * NPE + k];
     }
     if (fb != 2) return;
-    for (int r = 0; r < NFAR; ++r) {
-        const int npt = far_ns(r) * NT;
-        const bool own = r == NFAR - 1;
+    for (int r = 0; r < NFL; ++r) {
+        const int npt = (int)far_pts(r);
+        const bool own = r == FAR_OWN;
         const double* ssw = own ? sw : fr.sw[r];
         const int64_t ld = own ? N : fr.M[r];
         for (int k = threadIdx.x; k < npt; k += blockDim.x)
@@ -792,9 +792,10 @@ __device__ inline void block_box(double* lo, double* hi, double* red /*[2][3][FA
 
 // Source ranges [seg[2 q], seg[2 q + 1]) of segments q0 .. q0 + nq - 1
 // (nq <= 64) of a block, written to LDS by the first nq threads: for an
-// element chunk, element tl.e0 + q's coarsest far-field rule k whose radius
-// rc_k[e] from the element's centre the block's target box [lo, hi] keeps
-// clear of, else its base rule; for a plain chunk, its source range.
+// element chunk, element tl.e0 + q's coarsest far-field rule whose radii
+// from the element's centre (for its points in s and its angles) the block's
+// target box [lo, hi] keeps clear of, else its base rule; for a plain chunk,
+// its source range.
 __device__ __forceinline__ void far_segments(const FarTile& tl, const FarSplit& spl, int q0, int nq, const double* lo,
                                              const double* hi, int64_t* seg)
 {
@@ -805,20 +806,28 @@ __device__ __forceinline__ void far_segments(const FarTile& tl, const FarSplit& 
         const int e = tl.e0 + q0 + l;
         a = spl.boff[e];
         b = spl.boff[e + 1];
-        if (spl.rc) {
+        if (spl.rc && spl.rc[e] < INFINITY) {
             const ElemInfo& inf = spl.info[e];
             double g2 = 0.0;
             for (int d = 0; d < 3; ++d) {
                 const double g = fmax(0.0, fmax(lo[d] - inf.cen[d], inf.cen[d] - hi[d]));
                 g2 += g * g;
             }
-            for (int k = NFAR - 1; k >= 0; --k) {
-                const double rc = spl.rc[(int64_t)k * spl.E + e];
-                if (rc < INFINITY && g2 >= rc * rc) {
-                    a = spl.xoff[e] + far_off(k);
-                    b = a + (int64_t)far_ns(k) * NT;
-                    break;
-                }
+            // the radii grow as the rules coarsen: the coarsest admissible
+            // number of points in s, then of angles
+            int i = -1, j = 0;
+            for (int ii = 0; ii < NFS; ++ii) {
+                const double r = spl.rc[(int64_t)ii * spl.E + e];
+                if (g2 >= r * r) i = ii;
+            }
+            for (int jj = 1; jj < NFT; ++jj) {
+                const double r = spl.rc[(int64_t)(NFS + jj - 1) * spl.E + e];
+                if (g2 >= r * r) j = jj;
+            }
+            if (i >= 0) {
+                const int k = i * NFT + j;
+                a = spl.xoff[e] + far_off(k);
+                b = a + far_pts(k);
             }
         }
     }
@@ -1470,18 +1479,28 @@ __global__ void k_rnear(int E, const ElemInfo* __restrict__ info, const double* 
     }
     rnear[e] = 1.05 * fmax(dth, ds) + 1e-12;
     // the distances from the centre beyond which an element closed at an end
-    // may use its coarser far-field rules (far_ns(k) Gauss points in s) in
-    // the smooth sum, by the same estimates; at least the candidate radius
-    // (the base rule is the finest)
-    for (int k = 0; k < NFAR; ++k) {
+    // may use far_ns(i) Gauss points in s, and far_nt(j) angles, in the
+    // smooth sum, by the same estimates; at least the candidate radius (the
+    // base rule is the finest)
+    const bool ladder = inf.closed && inf.fb == 2;
+    for (int i = 0; i < NFS; ++i) {
         double rc = INFINITY;
-        if (inf.closed && inf.fb == 2) {
-            const double rq = pow(gc.cs / gc.tol, 1.0 / (double)(2 * far_ns(k) - Ms));
-            double dsk = inf.smax * h * 0.5 * (rq - 1.0 / rq);
-            dsk = fmax(dsk, 2.0 * inf.rad * cosh(fmin(3.14159265358979323846 * 0.25 * (rq - 1.0 / rq), 40.0)));
-            rc = inf.rad + fmax(1.05 * fmax(dth, dsk) + 1e-12, rnear[e]);
+        if (ladder) {
+            const double rq = pow(gc.cs / gc.tol, 1.0 / (double)(2 * far_ns(i) - Ms));
+            double dsi = inf.smax * h * 0.5 * (rq - 1.0 / rq);
+            dsi = fmax(dsi, 2.0 * inf.rad * cosh(fmin(3.14159265358979323846 * 0.25 * (rq - 1.0 / rq), 40.0)));
+            rc = inf.rad + fmax(1.05 * dsi + 1e-12, rnear[e]);
         }
-        rnear[(int64_t)(1 + k) * E + e] = rc;
+        rnear[(int64_t)(1 + i) * E + e] = rc;
+    }
+    for (int j = 1; j < NFT; ++j) {
+        double rc = INFINITY;
+        const int ex = far_nt(j) - Mt - gc.extra_modes;
+        if (ladder && ex > 0) {
+            const double dtj = inf.eps_max * (exp(log(gc.ct / gc.tol) / (double)ex) - 1.0);
+            rc = inf.rad + fmax(1.05 * dtj + 1e-12, rnear[e]);
+        }
+        rnear[(int64_t)(NFS + j) * E + e] = rc;
     }
 }
 

@@ -15,15 +15,16 @@ int launch_expand(hipStream_t st, int E, const double* xc, const double* eps, co
                   ElemInfo* info, double* ny, double* nn, double* nw, int64_t N, int closed_fb);
 int launch_expand_up(hipStream_t st, int E, int ns_f, int nt_f, const double* gx_f, const double* gw_f,
                      const double* clq, const ElemInfo* info, double* cpy, double* cpn, double* cpw, int64_t Mtot);
-// The coarser far-field rules of every element (far_ns(k) x NT points, SoA
-// with leading dimension M[k] = E far_ns(k) NT; their own nodes aside): the
-// points, normals and weights, and sigma * w after the density preparation.
+// The coarser far-field rules of every element (rule k: far_pts(k) points
+// per element, SoA with leading dimension M[k] = E far_pts(k); the entry
+// FAR_OWN unused, the own nodes standing in): the points, normals and
+// weights, and sigma * w after the density preparation.
 struct FarRules {
-    const double* y[NFAR - 1];
-    const double* n[NFAR - 1];
-    const double* w[NFAR - 1];
-    const double* sw[NFAR - 1];
-    int64_t M[NFAR - 1];
+    const double* y[NFL];
+    const double* n[NFL];
+    const double* w[NFL];
+    const double* sw[NFL];
+    int64_t M[NFL];
 };
 // base (far-field) source set; xoff[e]: where an fb = 2 element's coarser
 // far-field rules follow the base rules (elements closed at an end)
@@ -31,10 +32,10 @@ int launch_base_build(hipStream_t st, int E, const ElemInfo* info, const int64_t
                       const double* ny, const double* nn, const double* nw, int64_t N, const double* c0y,
                       const double* c0n, const double* c0w, int64_t M0, const FarRules& fr, double* by, double* bn,
                       double* bw, int64_t Nb);
-// rnear (if not null, (1 + NFAR) E doubles): the candidate radius of each
-// element in [0, E), and in [(1 + k) E, (2 + k) E) the distance from its
-// centre beyond which an element closed at an end may use its far-field
-// rule k in the smooth sum (+inf: never)
+// rnear (if not null, (NFS + NFT) E doubles): the candidate radius of each
+// element in [0, E), then the distances from its centre beyond which an
+// element closed at an end may use far_ns(i) Gauss points in s (i < NFS)
+// and far_nt(j) angles (0 < j < NFT) in the smooth sum (+inf: never)
 int launch_prep_sigma(hipStream_t st, int E, const double* sigma, const double* nw, int64_t N, double* sw,
                       double* sh, int* band, double eta, const ElemInfo* info, const double* circ, GateConsts gc,
                       double* rnear);

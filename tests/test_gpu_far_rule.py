@@ -1,10 +1,10 @@
 """Far-field rules of elements closed at an end (spheres as one element): the
-smooth sum takes, for a block of targets, the coarsest of a sphere's
-Gauss-Legendre rules in s (32, 24, 20 points, or its own 16, times 32
-angles) whose distance, by the criterion's estimates, lets it meet quad_tol
-beyond it (Section 3.2.1's smooth rule, with the error estimates of Section
-3.3).  Checked against the oracle and against the same evaluation with the
-32 x 32 rule everywhere (far_rule="base")."""
+smooth sum takes, for a block of targets, the coarsest of a sphere's tensor
+rules (24, 20 or its own 16 Gauss-Legendre points in s times 32, 24 or 16
+angles; else 32 x 32) whose distances, by the criterion's estimates, let it
+meet quad_tol beyond them (Section 3.2.1's smooth rule, with the error
+estimates of Section 3.3).  Checked against the oracle and against the same
+evaluation with the 32 x 32 rule everywhere (far_rule="base")."""
 import numpy as np
 import pytest
 
@@ -23,7 +23,8 @@ def _rel(a, b):
 def _lattice_scene(seed=11, n=3, spacing=2.5, radius=0.3):
     """n^3 spheres on a cubic lattice, randomly oriented, each carrying a
     constant density vector (Legendre and Fourier bands 0: at quad_tol 1e-12
-    the 24-, 20- and 16-point rules suffice from about 5, 6 and 10 radii)."""
+    the 24-, 20- and 16-point rules in s suffice from about 5, 6 and 10
+    radii, 16 angles from about 5)."""
     rng = np.random.default_rng(seed)
     bodies, sig = [], []
     for i in range(n):
