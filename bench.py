@@ -296,9 +296,9 @@ def main():
                 if a.workload == "pipe100-spheres200" else None)   # the counters were taken on that workload
     far_ach = FAR_FLOPS_PER_PAIR * far_pairs / (phases["far"] * 1e-3) / 1e12
     # the smooth sum's algorithmic rate: 48 flops per pair of surface nodes of
-    # one geometry (the implementation sums more pairs: near a body closed at
-    # its poles a block of targets sums its 32 x 32, 24 x 32 or 20 x 32
-    # far-field rule instead of its 16 x 32 nodes)
+    # one geometry (the implementation sums other pairs: a block of targets
+    # sums a body closed at its poles with its 32 x 32 far-field rule near it,
+    # farther away with a coarser tensor rule, down to 16 x 16)
     node_pairs = float(T) * float(ev.n_nodes) if a.workload == "pipe100-spheres200" else None
     if node_pairs is not None and dom == "far":
         alg = ALG_FLOPS_PER_PAIR * node_pairs / (phases["far"] * 1e-3) / 1e12
@@ -306,7 +306,7 @@ def main():
                         frac=alg / far_peak, traffic=roof["traffic"],
                         flops=f"{ALG_FLOPS_PER_PAIR} per pair of surface nodes x {T} targets x {ev.n_nodes} nodes")
         roof_impl = dict(roof, flops=f"{FAR_FLOPS_PER_PAIR} per summed pair x {int(far_pairs)} pairs "
-                                     "(spheres: 32 x 32, 24 x 32, 20 x 32 or 16 x 32 rule by distance)")
+                                     "(spheres: 32 x 32 near, coarser tensor rules by distance)")
         roof = roof_alg
     else:
         roof_impl = None
