@@ -232,35 +232,23 @@ static int load_tables(csbq_ctx* ctx)
     return CSBQ_OK;
 }
 
-// Whole-element singular s-rules (Section 3.2.4, second part), written by
-// the coarser far-field rules as the base-set kernels take them
-static FarRules far_rules(const csbq_ctx* ctx)
-{
-    FarRules fr{};
-    for (int k = 0; k < NFL; ++k) {
-        fr.y[k] = ctx->cfy[k].p;
-        fr.n[k] = ctx->cfn[k].p;
-        fr.w[k] = ctx->cfw[k].p;
-        fr.sw[k] = ctx->swfar[k].p;
-        fr.M[k] = ctx->Mfar[k];
-    }
-    return fr;
-}
-
 // density times weight on the coarser far-field rules (from the Fourier
-// coefficients on the GL circles, as on the upsampled rules); the buffers
-// are sized by the geometry, so an evaluation plan's replay allocates nothing
+// coefficients on the GL circles, as on the upsampled rules), straight into
+// the base source set; nothing is allocated, so an evaluation plan's replay
+// can run it
 static int sigma_far(csbq_ctx* ctx, hipStream_t st)
 {
     for (int k = 0; k < NFL; ++k) {
-        if (k == FAR_OWN) continue;
-        int r = launch_sigma_up(st, ctx->E, far_ns(k / NFT), far_nt(k % NFT), ctx->sh.p, ctx->Lfar[k / NFT].p,
-                                ctx->cfw[k].p, ctx->swfar[k].p, ctx->Mfar[k]);
+        if (!ctx->far_used[k]) continue;
+        const int i = k / NFT;
+        int r = launch_sigma_up(st, ctx->E, far_ns(i), far_nt(k % NFT), ctx->sh.p, ctx->Lfar[i].p, ctx->bw.p,
+                                ctx->bsw.p, ctx->Nb, ctx->loff.p + (int64_t)k * ctx->E);
         if (r) return r;
     }
     return 0;
 }
 
+// Whole-element singular s-rules (Section 3.2.4, second part), written by
 // tables/gen_srules.py: per cylinder aspect bracket and target GL index, then
 // (optionally) per target GL index of the sphere element, node offsets from
 // the GL node in the element variable v in [-1, 1] and their weights.
@@ -776,8 +764,7 @@ int csbq_set_geometry_batch(csbq_ctx* ctx, int32_t n_bodies, const int32_t* body
         LCHK(launch_expand_up(ctx->stream, (int)E, nsf, ntf, ctx->upx[ti].p, ctx->upw[ti].p, ctx->clq.p, ctx->info.p,
                               ctx->cpy[ti].p, ctx->cpn[ti].p, ctx->cpw[ti].p, ctx->Mtot[ti]));
     }
-    // coarser far-field rules (far_ns(i) x far_nt(j)) the smooth sum may take
-    // for an element closed at an end far from its targets
+    // Gauss tables and Lagrange matrices of the coarser far-field rules
     for (int i = 0; i < NFS; ++i) {
         const int nsf = far_ns(i);
         std::vector<double> gxf(nsf), gwf(nsf), lamf(nsf), Df((size_t)nsf * nsf), Tf((size_t)nsf * nsf);
@@ -790,17 +777,6 @@ int csbq_set_geometry_batch(csbq_ctx* ctx, int32_t n_bodies, const int32_t* body
         HIPC(hipMemcpy(ctx->Lfar[i].p, L.data(), L.size() * 8, hipMemcpyHostToDevice));
         HIPC(hipMemcpy(ctx->farx[i].p, gxf.data(), nsf * 8, hipMemcpyHostToDevice));
         HIPC(hipMemcpy(ctx->farw[i].p, gwf.data(), nsf * 8, hipMemcpyHostToDevice));
-        for (int j = 0; j < NFT; ++j) {
-            const int k = i * NFT + j;
-            if (k == FAR_OWN) continue;
-            ctx->Mfar[k] = E * far_pts(k);
-            ALLOC(ctx->cfy[k], (size_t)ctx->Mfar[k] * 3);
-            ALLOC(ctx->cfn[k], (size_t)ctx->Mfar[k] * 3);
-            ALLOC(ctx->cfw[k], (size_t)ctx->Mfar[k]);
-            ALLOC(ctx->swfar[k], (size_t)ctx->Mfar[k] * 3);
-            LCHK(launch_expand_up(ctx->stream, (int)E, nsf, far_nt(j), ctx->farx[i].p, ctx->farw[i].p, ctx->clq.p,
-                                  ctx->info.p, ctx->cfy[k].p, ctx->cfn[k].p, ctx->cfw[k].p, ctx->Mfar[k]));
-        }
     }
     // base (far-field) source set: own nodes, or the tier-0 rule for elements
     // whose cross-section closes at an end
@@ -818,33 +794,46 @@ int csbq_set_geometry_batch(csbq_ctx* ctx, int32_t n_bodies, const int32_t* body
         HIPC(hipMemcpy(ctx->info.p, hinf.data(), (size_t)E * sizeof(ElemInfo), hipMemcpyHostToDevice));
         ctx->n_cyl = nshape[SHAPE_CYLINDER];
         ctx->n_sph = nshape[SHAPE_SPHERE];
-        // boff[0..E]: the base rules; boff[E + 1 + e]: the coarser far-field
-        // rules of an element with the tier-0 rule as its base rule, appended
-        // after them
-        std::vector<int64_t> bo((size_t)2 * E + 1, -1);
-        bo[0] = 0;
+        // the base rules, then each element's coarser far-field rules (rule k
+        // of element e at loff[k E + e], -1 where the element has none)
+        std::vector<int64_t> bo((size_t)E + 1, 0);
         for (int64_t e = 0; e < E; ++e) bo[e + 1] = bo[e] + (hinf[e].fb == 2 ? up_pts(0) : NPE);
         ctx->Nb_rules = bo[E];
+        std::vector<int64_t> lo((size_t)NFL * E, -1);
         int64_t nb = bo[E];
-        for (int64_t e = 0; e < E; ++e)
-            if (hinf[e].fb == 2) {
-                bo[E + 1 + e] = nb;
-                nb += FAR_EXT;
-            }
+        for (int k = 0; k < NFL; ++k) ctx->far_used[k] = false;
+        for (int64_t e = 0; e < E; ++e) {
+            const int i0 = far_i0(hinf[e].fb == 2);
+            for (int i = i0; i < i0 + FAR_NI; ++i)
+                for (int j = 0; j < NFT; ++j) {
+                    const int k = i * NFT + j;
+                    if (hinf[e].fb != 2 && k == FAR_OPEN_BASE) continue;   // the base rule itself
+                    lo[(size_t)k * E + e] = nb;
+                    nb += far_pts(k);
+                    ctx->far_used[k] = true;
+                }
+        }
         ctx->Nb = nb;
-        ctx->h_boff.assign(bo.begin(), bo.begin() + E + 1);
+        ctx->h_boff = bo;
         ALLOC(ctx->boff, bo.size());
+        ALLOC(ctx->loff, lo.size());
         ALLOC(ctx->by, (size_t)ctx->Nb * 3);
         ALLOC(ctx->bn, (size_t)ctx->Nb * 3);
         ALLOC(ctx->bw, (size_t)ctx->Nb);
         HIPC(hipMemcpy(ctx->boff.p, bo.data(), bo.size() * sizeof(int64_t), hipMemcpyHostToDevice));
-        LCHK(launch_base_build(ctx->stream, (int)E, ctx->info.p, ctx->boff.p, ctx->boff.p + E + 1, ctx->ny.p,
-                               ctx->nn.p, ctx->nw.p, N, ctx->cpy[0].p, ctx->cpn[0].p, ctx->cpw[0].p, ctx->Mtot[0],
-                               far_rules(ctx), ctx->by.p, ctx->bn.p, ctx->bw.p, ctx->Nb));
+        HIPC(hipMemcpy(ctx->loff.p, lo.data(), lo.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+        LCHK(launch_base_build(ctx->stream, (int)E, ctx->info.p, ctx->boff.p, ctx->ny.p, ctx->nn.p, ctx->nw.p, N,
+                               ctx->cpy[0].p, ctx->cpn[0].p, ctx->cpw[0].p, ctx->Mtot[0], ctx->by.p, ctx->bn.p,
+                               ctx->bw.p, ctx->Nb));
+        for (int k = 0; k < NFL; ++k)
+            if (ctx->far_used[k])
+                LCHK(launch_expand_up(ctx->stream, (int)E, far_ns(k / NFT), far_nt(k % NFT), ctx->farx[k / NFT].p,
+                                      ctx->farw[k / NFT].p, ctx->clq.p, ctx->info.p, ctx->by.p, ctx->bn.p, ctx->bw.p,
+                                      ctx->Nb, ctx->loff.p + (int64_t)k * E));
         // mixed precision: sources within sqrt(100 w_max) of a target are
         // summed in FP64, so no FP32 term exceeds ~1e-2 of the density scale
-        // (w_max over the base rules: the coarser rules of closed elements are
-        // summed only far from them)
+        // (w_max over the base rules: the coarser rules are summed only far
+        // from their elements)
         std::vector<double> hbw((size_t)ctx->Nb_rules);
         HIPC(hipMemcpyAsync(hbw.data(), ctx->bw.p, hbw.size() * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
         HIPC(hipStreamSynchronize(ctx->stream));
@@ -1080,7 +1069,7 @@ static FarSplit far_split(const csbq_ctx* ctx, int64_t* pairs)
 {
     FarSplit f{};
     f.boff = ctx->boff.p;
-    f.xoff = ctx->boff.p + ctx->E + 1;
+    f.loff = ctx->loff.p;
     f.rc = ctx->far_split ? ctx->rnear.p + ctx->E : nullptr;
     f.info = ctx->info.p;
     f.pairs = pairs;
@@ -1350,9 +1339,9 @@ int csbq_eval_batch(csbq_ctx* ctx, const double* sigma, int64_t T, const double*
     LCHK(launch_sigma_up(st, E, up_ns(0), up_nt(0), ctx->sh.p, ctx->Lup[0].p, ctx->cpw[0].p, ctx->swf[0].p,
                          ctx->Mtot[0]));
     ALLOC(ctx->bsw, (size_t)ctx->Nb * 3);
+    LCHK(launch_sigma_base(st, E, ctx->info.p, ctx->boff.p, ctx->sw.p, N, ctx->swf[0].p, ctx->Mtot[0], ctx->bsw.p,
+                           ctx->Nb));
     LCHK(sigma_far(ctx, st));
-    LCHK(launch_sigma_base(st, E, ctx->info.p, ctx->boff.p, ctx->boff.p + E + 1, ctx->sw.p, N, ctx->swf[0].p,
-                           ctx->Mtot[0], far_rules(ctx), ctx->bsw.p, ctx->Nb));
     // candidate pairs: count, scan (the fill follows the synchronisation)
     HIPC(hipEventRecord(ctx->ph[2].a, st));
     ALLOC(ctx->cnt, (size_t)T + 1);
@@ -1583,9 +1572,9 @@ static int enqueue_apply(csbq_ctx* ctx, hipStream_t st)
     LCHK(launch_band_check(st, E, ctx->band_apply.p, ctx->band.p, ctx->err_d.p));
     LCHK(launch_sigma_up(st, E, up_ns(0), up_nt(0), ctx->sh.p, ctx->Lup[0].p, ctx->cpw[0].p, ctx->swf[0].p,
                          ctx->Mtot[0]));
+    LCHK(launch_sigma_base(st, E, ctx->info.p, ctx->boff.p, ctx->sw.p, N, ctx->swf[0].p, ctx->Mtot[0], ctx->bsw.p,
+                           ctx->Nb));
     LCHK(sigma_far(ctx, st));
-    LCHK(launch_sigma_base(st, E, ctx->info.p, ctx->boff.p, ctx->boff.p + E + 1, ctx->sw.p, N, ctx->swf[0].p,
-                           ctx->Mtot[0], far_rules(ctx), ctx->bsw.p, ctx->Nb));
     LCHK(launch_far(st, T, ctx->xt.p, ctx->by.p, ctx->bn.p, ctx->bsw.p, ctx->Nb, ctx->tiles.p, pl.ntiles, ctx->part.p,
                     pl.mixed, ctx->mix_near2, pl.tpt, ctx->ker, far_split(ctx, ctx->fpairs.p)));
     for (int ti = 1; ti < NUP; ++ti)

@@ -40,20 +40,20 @@ __host__ __device__ constexpr int up_ns(int k) { return k == 2 ? 64 : 32; }
 __host__ __device__ constexpr int up_nt(int k) { return k == 0 ? 32 : (k == 1 ? 64 : 128); }
 __host__ __device__ constexpr int64_t up_pts(int k) { return (int64_t)up_ns(k) * up_nt(k); }
 
-// coarser far-field rules of an element closed at an end: Gauss-Legendre of
-// far_ns(i) points in s times far_nt(j) angles, i < NFS, j < NFT, finest
-// first in each direction; rule k = i NFT + j of the NFL rules, the rule
-// FAR_OWN (N_s x N_theta) being the element's own nodes.  They follow the base
-// rules in the base source set, FAR_EXT points per such element (far_off(k):
-// rule k's first point).
-constexpr int NFS = 3, NFT = 3, NFL = NFS * NFT;
-__host__ __device__ constexpr int far_ns(int i) { return i == 0 ? 24 : (i == 1 ? 20 : NS); }
+// Far-field rules of the smooth sum coarser than an element's base rule:
+// Gauss-Legendre of far_ns(i) points in s (i < NFS) times far_nt(j) angles
+// (j < NFT), rule k = i NFT + j.  An element closed at an end (base rule
+// up_ns(0) x NT) may take i in [0, 3): 24, 20 or 16 points; any other element
+// (base rule: its own N_s x N_theta nodes) i in [2, 5): 16, 12 or 8 points,
+// its base being the rule FAR_OPEN_BASE.  The rules follow the base rules in
+// the base source set.
+constexpr int NFS = 5, NFT = 3, NFL = NFS * NFT, FAR_NI = 3;
+__host__ __device__ constexpr int far_ns(int i) { return i == 0 ? 24 : i == 1 ? 20 : i == 2 ? NS : i == 3 ? 12 : 8; }
 __host__ __device__ constexpr int far_nt(int j) { return j == 0 ? NT : (j == 1 ? 24 : 16); }
 __host__ __device__ constexpr int64_t far_pts(int k) { return (int64_t)far_ns(k / NFT) * far_nt(k % NFT); }
-__host__ __device__ constexpr int64_t far_off(int k) { return k == 0 ? 0 : far_off(k - 1) + far_pts(k - 1); }
-constexpr int FAR_OWN = (NFS - 1) * NFT;
-constexpr int64_t FAR_EXT = far_off(NFL - 1) + far_pts(NFL - 1);
-static_assert(far_ns(NFS - 1) == NS && far_nt(0) == NT, "the rule FAR_OWN is the element's own nodes");
+__host__ __device__ constexpr int far_i0(bool closed) { return closed ? 0 : 2; }
+constexpr int FAR_OPEN_BASE = 2 * NFT;
+static_assert(far_ns(2) == NS && far_nt(0) == NT, "rule FAR_OPEN_BASE is an element's own nodes");
 
 // kernel pair of an evaluation: the Stokes single and double layers (Section
 // 2) or the Laplace ones (Section 4.1)
@@ -106,21 +106,21 @@ struct FarTile {
     int32_t pad_;
 };
 
-// Element chunks of the smooth sum: an element closed at an end (base rule
-// up_ns(0) x NT) is summed with the coarsest of its far_ns(i) x far_nt(j)
-// rules whose radii from the element's centre (one for the points in s, one
-// for the angles) the block's targets all lie beyond: the distances at which
-// the same error estimates that choose the candidates let the rule meet the
-// tolerance.
+// Element chunks of the smooth sum: an element is summed with the coarsest
+// of its far_ns(i) x far_nt(j) rules whose radii from the element's centre
+// (one for the points in s, one for the angles) the block's targets all lie
+// beyond: the distances at which the same error estimates that choose the
+// candidates let the rule meet the tolerance; else with its base rule.
 struct FarSplit {
     const int64_t* boff;    // element e's base rule: sources [boff[e], boff[e + 1])
-    const int64_t* xoff;    // its coarser rules: sources xoff[e] + far_off(k) .. (closed elements)
+    const int64_t* loff;    // rule k of element e: sources loff[k E + e] .. + far_pts(k) (-1: none)
     const double* rc;       // radii (+inf: never), or null: base rules only: rc[i E + e] for far_ns(i) points
                             // in s (i < NFS), rc[(NFS + j - 1) E + e] for far_nt(j) angles (0 < j < NFT)
     const ElemInfo* info;   // element centres
     int64_t* pairs;         // per block: source-target pairs summed (or null)
     int E;
 };
+
 // constants of the error estimates (calibrated against the CPU oracle)
 struct GateConsts {
     double tol;        // per-element quadrature tolerance

@@ -92,13 +92,14 @@ struct csbq_ctx {
     DBuf<ElemInfo> info;
     DBuf<double> cpy[NUP], cpn[NUP], cpw[NUP], Lup[NUP], upx[NUP], upw[NUP];
     int64_t Mtot[NUP] = {0, 0, 0};
-    // coarser far-field rules of elements closed at an end (every element's,
-    // far_pts(k) points; the own nodes aside) and density times weight on
-    // them; Lagrange matrices and Gauss tables per number of points in s
-    DBuf<double> cfy[NFL], cfn[NFL], cfw[NFL], swfar[NFL], Lfar[NFS], farx[NFS], farw[NFS];
-    int64_t Mfar[NFL] = {};
+    // coarser far-field rules: Lagrange matrices and Gauss tables per number
+    // of points in s; each element's rules sit in the base source set
+    // (rule k of element e at loff[k E + e], -1: none)
+    DBuf<double> Lfar[NFS], farx[NFS], farw[NFS];
+    DBuf<int64_t> loff;
+    bool far_used[NFL] = {};
     // far-field (base) source set
-    int64_t Nb = 0;         // base sources: the base rules, then the coarser rules of closed elements
+    int64_t Nb = 0;         // base sources: the base rules, then the elements' coarser far-field rules
     int64_t Nb_rules = 0;   // the base rules alone
     double mix_near2 = 0.0;   // squared radius of the FP64 near part of the mixed-precision far sum
     DBuf<int64_t> boff;

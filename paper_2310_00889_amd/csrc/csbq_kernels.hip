@@ -477,18 +477,20 @@ __global__ __launch_bounds__(512) void k_expand(int E, const double* __restrict_
     }
 }
 
-// Upsampled whole-panel tensor rule of tier k: ns_f Gauss-Legendre nodes on
-// the whole panel in s (gx_f, gw_f on [-1,1]) times nt_f uniform angles.
-// Block = one s-row (nt_f threads), grid = (E, ns_f); element e's points start
-// at e * ns_f * nt_f.
+// Upsampled whole-panel tensor rule of tier k (or a far-field rule): ns_f
+// Gauss-Legendre nodes on the whole panel in s (gx_f, gw_f on [-1,1]) times
+// nt_f uniform angles.  Block = one s-row (nt_f threads), grid = (E, ns_f);
+// element e's points start at e * ns_f * nt_f, or at eoff[e] (-1: none).
 __global__ __launch_bounds__(128) void k_expand_up(int E, int ns_f, int nt_f, const double* __restrict__ gx_f,
                                                    const double* __restrict__ gw_f, const double* __restrict__ clq,
                                                    const ElemInfo* __restrict__ info, double* __restrict__ cpy,
                                                    double* __restrict__ cpn, double* __restrict__ cpw,
-                                                   int64_t Mtot)
+                                                   int64_t Mtot, const int64_t* __restrict__ eoff)
 {
     const int e = blockIdx.x, p = blockIdx.y, q = threadIdx.x;
     const int64_t Mf = (int64_t)ns_f * nt_f;
+    const int64_t m0 = eoff ? eoff[e] : (int64_t)e * Mf;
+    if (m0 < 0) return;
     const ElemInfo inf = info[e];
     Frame fr;
     frame_at_x(clq + (int64_t)e * CLQ * NS, gx_f[p], fr);
@@ -499,7 +501,7 @@ __global__ __launch_bounds__(128) void k_expand_up(int E, int ns_f, int nt_f, co
     surface_at(fr, ct, st, y, ys, yt);
     cross3(yt, ys, jn);
     double J = sqrt(dot3(jn, jn));
-    const int64_t m = (int64_t)e * Mf + (int64_t)p * nt_f + q;
+    const int64_t m = m0 + (int64_t)p * nt_f + q;
     for (int d = 0; d < 3; ++d) {
         cpy[d * Mtot + m] = y[d];
         cpn[d * Mtot + m] = inf.sign * jn[d] / J;
@@ -509,15 +511,11 @@ __global__ __launch_bounds__(128) void k_expand_up(int E, int ns_f, int nt_f, co
 
 // Far-field (base) source set: each element contributes its own nodes (fb = 1)
 // or its tier-0 rule (fb = 2); boff[e] is the element's first base source.
-// An fb = 2 element's coarser far-field rules follow at xoff[e] (the smooth
-// sum's choice for targets far from it): the rules of fr in order, its own
-// nodes in the place of rule FAR_OWN.
 __global__ void k_base_build(int E, const ElemInfo* __restrict__ info, const int64_t* __restrict__ boff,
-                             const int64_t* __restrict__ xoff, const double* __restrict__ ny,
-                             const double* __restrict__ nn, const double* __restrict__ nw, int64_t N,
-                             const double* __restrict__ c0y, const double* __restrict__ c0n,
-                             const double* __restrict__ c0w, int64_t M0, FarRules fr, double* __restrict__ by,
-                             double* __restrict__ bn, double* __restrict__ bw, int64_t Nb)
+                             const double* __restrict__ ny, const double* __restrict__ nn,
+                             const double* __restrict__ nw, int64_t N, const double* __restrict__ c0y,
+                             const double* __restrict__ c0n, const double* __restrict__ c0w, int64_t M0,
+                             double* __restrict__ by, double* __restrict__ bn, double* __restrict__ bw, int64_t Nb)
 {
     const int e = blockIdx.x;
     const int fb = info[e].fb;
@@ -534,23 +532,6 @@ __global__ void k_base_build(int E, const ElemInfo* __restrict__ info, const int
             bn[d * Nb + o + k] = sn[d * ld + src];
         }
         bw[o + k] = swt[src];
-    }
-    if (fb != 2) return;
-    for (int r = 0; r < NFL; ++r) {
-        const int npt = (int)far_pts(r);
-        const bool own = r == FAR_OWN;
-        const double* sy = own ? ny : fr.y[r];
-        const double* sn = own ? nn : fr.n[r];
-        const double* swt = own ? nw : fr.w[r];
-        const int64_t ld = own ? N : fr.M[r];
-        for (int k = threadIdx.x; k < npt; k += blockDim.x) {
-            const int64_t src = (int64_t)e * npt + k, dst = xoff[e] + far_off(r) + k;
-            for (int d = 0; d < 3; ++d) {
-                by[d * Nb + dst] = sy[d * ld + src];
-                bn[d * Nb + dst] = sn[d * ld + src];
-            }
-            bw[dst] = swt[src];
-        }
     }
 }
 
@@ -639,10 +620,13 @@ __global__ __launch_bounds__(512) void k_prep_sigma(int E, const double* __restr
 // (Lup: ns_f x NS Lagrange matrix) and synthesised at t_q.
 __global__ __launch_bounds__(256) void k_sigma_up(int E, int ns_f, int nt_f, const double* __restrict__ sh,
                                                   const double* __restrict__ Lup, const double* __restrict__ cpw,
-                                                  double* __restrict__ swf, int64_t Mtot)
+                                                  double* __restrict__ swf, int64_t Mtot,
+                                                  const int64_t* __restrict__ eoff)
 {
     const int e = blockIdx.x, tid = threadIdx.x;
     const int64_t Mf = (int64_t)ns_f * nt_f;
+    const int64_t m0 = eoff ? eoff[e] : (int64_t)e * Mf;
+    if (m0 < 0) return;
     __shared__ double shl[NS * NSH];
     __shared__ double A[NS * NSH];
     for (int o = tid; o < NS * NSH; o += blockDim.x) shl[o] = sh[(int64_t)e * NS * NSH + o];
@@ -674,7 +658,7 @@ __global__ __launch_bounds__(256) void k_sigma_up(int E, int ns_f, int nt_f, con
                 v1 += ar[l * 6 + 1] * cl + ar[l * 6 + 4] * sl;
                 v2 += ar[l * 6 + 2] * cl + ar[l * 6 + 5] * sl;
             }
-            int64_t m = (int64_t)e * Mf + (int64_t)(rb + r) * nt_f + q;
+            int64_t m = m0 + (int64_t)(rb + r) * nt_f + q;
             double w = cpw[m];
             swf[0 * Mtot + m] = v0 * w;
             swf[1 * Mtot + m] = v1 * w;
@@ -686,9 +670,8 @@ __global__ __launch_bounds__(256) void k_sigma_up(int E, int ns_f, int nt_f, con
 
 // density times weight on the base (far-field) source set
 __global__ void k_sigma_base(int E, const ElemInfo* __restrict__ info, const int64_t* __restrict__ boff,
-                             const int64_t* __restrict__ xoff, const double* __restrict__ sw, int64_t N,
-                             const double* __restrict__ swf0, int64_t M0, FarRules fr, double* __restrict__ bsw,
-                             int64_t Nb)
+                             const double* __restrict__ sw, int64_t N, const double* __restrict__ swf0, int64_t M0,
+                             double* __restrict__ bsw, int64_t Nb)
 {
     const int e = blockIdx.x;
     const int fb = info[e].fb;
@@ -697,16 +680,6 @@ __global__ void k_sigma_base(int E, const ElemInfo* __restrict__ info, const int
     for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
         for (int d = 0; d < 3; ++d)
             bsw[d * Nb + o + k] = fb == 2 ? swf0[d * M0 + (int64_t)e * up_pts(0) + k] : sw[d * N + (int64_t)e * NPE + k];
-    }
-    if (fb != 2) return;
-    for (int r = 0; r < NFL; ++r) {
-        const int npt = (int)far_pts(r);
-        const bool own = r == FAR_OWN;
-        const double* ssw = own ? sw : fr.sw[r];
-        const int64_t ld = own ? N : fr.M[r];
-        for (int k = threadIdx.x; k < npt; k += blockDim.x)
-            for (int d = 0; d < 3; ++d)
-                bsw[d * Nb + xoff[e] + far_off(r) + k] = ssw[d * ld + (int64_t)e * npt + k];
     }
 }
 
@@ -806,15 +779,16 @@ __device__ __forceinline__ void far_segments(const FarTile& tl, const FarSplit& 
         const int e = tl.e0 + q0 + l;
         a = spl.boff[e];
         b = spl.boff[e + 1];
-        if (spl.rc && spl.rc[e] < INFINITY) {
+        if (spl.rc) {
             const ElemInfo& inf = spl.info[e];
             double g2 = 0.0;
             for (int d = 0; d < 3; ++d) {
                 const double g = fmax(0.0, fmax(lo[d] - inf.cen[d], inf.cen[d] - hi[d]));
                 g2 += g * g;
             }
-            // the radii grow as the rules coarsen: the coarsest admissible
-            // number of points in s, then of angles
+            // the radii grow as the rules coarsen (+inf outside the element's
+            // own range): the coarsest admissible number of points in s, then
+            // of angles
             int i = -1, j = 0;
             for (int ii = 0; ii < NFS; ++ii) {
                 const double r = spl.rc[(int64_t)ii * spl.E + e];
@@ -826,8 +800,11 @@ __device__ __forceinline__ void far_segments(const FarTile& tl, const FarSplit& 
             }
             if (i >= 0) {
                 const int k = i * NFT + j;
-                a = spl.xoff[e] + far_off(k);
-                b = a + far_pts(k);
+                const int64_t o = spl.loff[(int64_t)k * spl.E + e];
+                if (o >= 0) {   // else the element's base rule
+                    a = o;
+                    b = o + far_pts(k);
+                }
             }
         }
     }
@@ -1478,25 +1455,34 @@ __global__ void k_rnear(int E, const ElemInfo* __restrict__ info, const double* 
         ds = fmax(ds, 2.0 * inf.rad * cosh(fmin(imphi, 40.0)));
     }
     rnear[e] = 1.05 * fmax(dth, ds) + 1e-12;
-    // the distances from the centre beyond which an element closed at an end
-    // may use far_ns(i) Gauss points in s, and far_nt(j) angles, in the
-    // smooth sum, by the same estimates; at least the candidate radius (the
-    // base rule is the finest)
-    const bool ladder = inf.closed && inf.fb == 2;
+    // the distances from the centre beyond which the smooth sum may take
+    // far_ns(i) Gauss points in s, and far_nt(j) angles, for the element, by
+    // the same estimates; at least the candidate radius.  An element whose
+    // base rule is the 32-point rule (closed at an end) takes i in [0, 3),
+    // any other i in [2, 5) (its base is its own 16 points, the candidate
+    // radius).
+    const bool base32 = inf.fb == 2;
+    const int i0 = far_i0(base32);
     for (int i = 0; i < NFS; ++i) {
         double rc = INFINITY;
-        if (ladder) {
-            const double rq = pow(gc.cs / gc.tol, 1.0 / (double)(2 * far_ns(i) - Ms));
-            double dsi = inf.smax * h * 0.5 * (rq - 1.0 / rq);
-            dsi = fmax(dsi, 2.0 * inf.rad * cosh(fmin(3.14159265358979323846 * 0.25 * (rq - 1.0 / rq), 40.0)));
-            rc = inf.rad + fmax(1.05 * dsi + 1e-12, rnear[e]);
+        const int ex = 2 * far_ns(i) - Ms;
+        if (i >= i0 && i < i0 + FAR_NI && ex > 0) {
+            if (!base32 && i == i0) {
+                rc = inf.rad + rnear[e];
+            } else {
+                const double rq = pow(gc.cs / gc.tol, 1.0 / (double)ex);
+                double dsi = inf.smax * h * 0.5 * (rq - 1.0 / rq);
+                if (inf.closed)
+                    dsi = fmax(dsi, 2.0 * inf.rad * cosh(fmin(3.14159265358979323846 * 0.25 * (rq - 1.0 / rq), 40.0)));
+                rc = inf.rad + fmax(1.05 * dsi + 1e-12, rnear[e]);
+            }
         }
         rnear[(int64_t)(1 + i) * E + e] = rc;
     }
     for (int j = 1; j < NFT; ++j) {
         double rc = INFINITY;
         const int ex = far_nt(j) - Mt - gc.extra_modes;
-        if (ladder && ex > 0) {
+        if (ex > 0) {
             const double dtj = inf.eps_max * (exp(log(gc.ct / gc.tol) / (double)ex) - 1.0);
             rc = inf.rad + fmax(1.05 * dtj + 1e-12, rnear[e]);
         }
@@ -2596,21 +2582,21 @@ int launch_expand(hipStream_t st, int E, const double* xc, const double* eps, co
 }
 
 int launch_expand_up(hipStream_t st, int E, int ns_f, int nt_f, const double* gx_f, const double* gw_f,
-                     const double* clq, const ElemInfo* info, double* cpy, double* cpn, double* cpw, int64_t Mtot)
+                     const double* clq, const ElemInfo* info, double* cpy, double* cpn, double* cpw, int64_t Mtot,
+                     const int64_t* eoff)
 {
     hipLaunchKernelGGL(k_expand_up, dim3(E, ns_f), dim3(nt_f), 0, st, E, ns_f, nt_f, gx_f, gw_f, clq, info, cpy, cpn,
-                       cpw, Mtot);
+                       cpw, Mtot, eoff);
     LAUNCH_CHECK();
     return 0;
 }
 
-int launch_base_build(hipStream_t st, int E, const ElemInfo* info, const int64_t* boff, const int64_t* xoff,
-                      const double* ny, const double* nn, const double* nw, int64_t N, const double* c0y,
-                      const double* c0n, const double* c0w, int64_t M0, const FarRules& fr, double* by, double* bn,
-                      double* bw, int64_t Nb)
+int launch_base_build(hipStream_t st, int E, const ElemInfo* info, const int64_t* boff, const double* ny,
+                      const double* nn, const double* nw, int64_t N, const double* c0y, const double* c0n,
+                      const double* c0w, int64_t M0, double* by, double* bn, double* bw, int64_t Nb)
 {
-    hipLaunchKernelGGL(k_base_build, dim3(E), dim3(256), 0, st, E, info, boff, xoff, ny, nn, nw, N, c0y, c0n, c0w, M0,
-                       fr, by, bn, bw, Nb);
+    hipLaunchKernelGGL(k_base_build, dim3(E), dim3(256), 0, st, E, info, boff, ny, nn, nw, N, c0y, c0n, c0w, M0, by,
+                       bn, bw, Nb);
     LAUNCH_CHECK();
     return 0;
 }
@@ -2660,18 +2646,17 @@ int launch_fill_i32(hipStream_t st, int64_t n, int* v, int val)
 }
 
 int launch_sigma_up(hipStream_t st, int E, int ns_f, int nt_f, const double* sh, const double* Lup, const double* cpw,
-                    double* swf, int64_t Mtot)
+                    double* swf, int64_t Mtot, const int64_t* eoff)
 {
-    hipLaunchKernelGGL(k_sigma_up, dim3(E), dim3(256), 0, st, E, ns_f, nt_f, sh, Lup, cpw, swf, Mtot);
+    hipLaunchKernelGGL(k_sigma_up, dim3(E), dim3(256), 0, st, E, ns_f, nt_f, sh, Lup, cpw, swf, Mtot, eoff);
     LAUNCH_CHECK();
     return 0;
 }
 
-int launch_sigma_base(hipStream_t st, int E, const ElemInfo* info, const int64_t* boff, const int64_t* xoff,
-                      const double* sw, int64_t N, const double* swf0, int64_t M0, const FarRules& fr, double* bsw,
-                      int64_t Nb)
+int launch_sigma_base(hipStream_t st, int E, const ElemInfo* info, const int64_t* boff, const double* sw, int64_t N,
+                      const double* swf0, int64_t M0, double* bsw, int64_t Nb)
 {
-    hipLaunchKernelGGL(k_sigma_base, dim3(E), dim3(256), 0, st, E, info, boff, xoff, sw, N, swf0, M0, fr, bsw, Nb);
+    hipLaunchKernelGGL(k_sigma_base, dim3(E), dim3(256), 0, st, E, info, boff, sw, N, swf0, M0, bsw, Nb);
     LAUNCH_CHECK();
     return 0;
 }

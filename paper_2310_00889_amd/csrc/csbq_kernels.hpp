@@ -13,39 +13,27 @@ int upload_constants(const double* gx, const double* gw, const double* lam, cons
 int launch_expand(hipStream_t st, int E, const double* xc, const double* eps, const double* e1, const double* sa,
                   const double* sc, const int* esign, const int* ebody, const int* egroup, double* clq, double* circ,
                   ElemInfo* info, double* ny, double* nn, double* nw, int64_t N, int closed_fb);
+// eoff (optional): element e's first output point (-1: skip the element)
+// instead of e ns_f nt_f; Mtot is the arrays' leading dimension either way
 int launch_expand_up(hipStream_t st, int E, int ns_f, int nt_f, const double* gx_f, const double* gw_f,
-                     const double* clq, const ElemInfo* info, double* cpy, double* cpn, double* cpw, int64_t Mtot);
-// The coarser far-field rules of every element (rule k: far_pts(k) points
-// per element, SoA with leading dimension M[k] = E far_pts(k); the entry
-// FAR_OWN unused, the own nodes standing in): the points, normals and
-// weights, and sigma * w after the density preparation.
-struct FarRules {
-    const double* y[NFL];
-    const double* n[NFL];
-    const double* w[NFL];
-    const double* sw[NFL];
-    int64_t M[NFL];
-};
-// base (far-field) source set; xoff[e]: where an fb = 2 element's coarser
-// far-field rules follow the base rules (elements closed at an end)
-int launch_base_build(hipStream_t st, int E, const ElemInfo* info, const int64_t* boff, const int64_t* xoff,
-                      const double* ny, const double* nn, const double* nw, int64_t N, const double* c0y,
-                      const double* c0n, const double* c0w, int64_t M0, const FarRules& fr, double* by, double* bn,
-                      double* bw, int64_t Nb);
+                     const double* clq, const ElemInfo* info, double* cpy, double* cpn, double* cpw, int64_t Mtot,
+                     const int64_t* eoff = nullptr);
+int launch_base_build(hipStream_t st, int E, const ElemInfo* info, const int64_t* boff, const double* ny,
+                      const double* nn, const double* nw, int64_t N, const double* c0y, const double* c0n,
+                      const double* c0w, int64_t M0, double* by, double* bn, double* bw, int64_t Nb);
 // rnear (if not null, (NFS + NFT) E doubles): the candidate radius of each
-// element in [0, E), then the distances from its centre beyond which an
-// element closed at an end may use far_ns(i) Gauss points in s (i < NFS)
-// and far_nt(j) angles (0 < j < NFT) in the smooth sum (+inf: never)
+// element in [0, E), then the distances from its centre beyond which the
+// smooth sum may use far_ns(i) Gauss points in s (i < NFS) and far_nt(j)
+// angles (0 < j < NFT) for it (+inf: never)
 int launch_prep_sigma(hipStream_t st, int E, const double* sigma, const double* nw, int64_t N, double* sw,
                       double* sh, int* band, double eta, const ElemInfo* info, const double* circ, GateConsts gc,
                       double* rnear);
 int launch_band_check(hipStream_t st, int E, const int* band_new, const int* band_plan, int* err);
 int launch_fill_i32(hipStream_t st, int64_t n, int* v, int val);
 int launch_sigma_up(hipStream_t st, int E, int ns_f, int nt_f, const double* sh, const double* Lup, const double* cpw,
-                    double* swf, int64_t Mtot);
-int launch_sigma_base(hipStream_t st, int E, const ElemInfo* info, const int64_t* boff, const int64_t* xoff,
-                      const double* sw, int64_t N, const double* swf0, int64_t M0, const FarRules& fr, double* bsw,
-                      int64_t Nb);
+                    double* swf, int64_t Mtot, const int64_t* eoff = nullptr);
+int launch_sigma_base(hipStream_t st, int E, const ElemInfo* info, const int64_t* boff, const double* sw, int64_t N,
+                      const double* swf0, int64_t M0, double* bsw, int64_t Nb);
 int launch_targets(hipStream_t st, int64_t T, const double* x, const int64_t* tnode, const int* tgrp_in, int G,
                    const ElemInfo* info, const double* ny, int64_t N, double* xt, int* tgroup, int64_t* gstart,
                    int* err);
