@@ -123,17 +123,19 @@ typedef enum { CSBQ_KERNEL_STOKES = 0, CSBQ_KERNEL_LAPLACE = 1 } csbq_kernel;
    outside the rules' family, so their accuracy is not quad_tol's). */
 typedef enum { CSBQ_SRULE_AUTO = 0, CSBQ_SRULE_WHOLE = 1, CSBQ_SRULE_GENERAL = 2 } csbq_srule;
 
-/* Far-field rule of an element closed at an end (a sphere as one element in
-   its polar angle; Section 3.2.1's smooth rule).  Gauss-Legendre rules in
-   the polar angle converge slowly near such an element, so near it the
-   smooth sum uses a 32 x 32 rule (the first upsampled rule) that the local
-   corrections then subtract.  AUTO (default): a smooth-sum block of targets
-   sums the coarsest of the element's 24 x 32, 20 x 32 and own 16 x 32 rules
-   whose distance from the element's centre, at which the criterion's
-   estimates let it meet quad_tol for the density's measured band, all its
-   targets lie beyond; else the 32 x 32 rule.  Every candidate pair lies
-   inside those distances, so the corrections are unchanged.  BASE: the
-   32 x 32 rule for every target. */
+/* Far-field rules of the smooth sum (Section 3.2.1's smooth rule).  Each
+   element has a base rule: its own N_s x N_theta nodes, or for an element
+   closed at an end (a sphere as one element in its polar angle, where
+   Gauss-Legendre rules in that angle converge slowly nearby) a 32 x 32 rule
+   (the first upsampled rule); the local corrections subtract the base rule.
+   AUTO (default): a smooth-sum block of targets sums each element with n
+   Gauss points in s times m angles (a sphere: n in {24, 20, 16}; any other
+   element: n in {16, 12, 8}; m in {32, 24, 16}), each the smallest whose
+   distance from the element's centre, at which the criterion's estimates let
+   it meet quad_tol for the density's measured band, all the block's targets
+   lie beyond; else the base rule.  Every candidate pair lies inside those
+   distances, so the corrections are unchanged.  BASE: the base rules for
+   every target. */
 typedef enum { CSBQ_FAR_AUTO = 0, CSBQ_FAR_BASE = 1 } csbq_far_rule;
 
 typedef struct {
@@ -145,7 +147,7 @@ typedef struct {
     const char* table_dir; /* directory holding rules.bin (and srules.bin); NULL = the package's tables/ */
     int32_t kernel;        /* csbq_kernel: the Stokes layers, or the Laplace layers (FP64, criterion gate only) */
     int32_t srule;         /* csbq_srule: the own element's s-rule for on-surface targets */
-    int32_t far_rule;      /* csbq_far_rule: far-field rule of elements closed at an end */
+    int32_t far_rule;      /* csbq_far_rule: coarser far-field rules far from each element, or the base rules */
 } csbq_options;
 
 /* Fill *opt with defaults (quad_tol 1e-12, FP64, criterion gate, device 0,

@@ -141,11 +141,10 @@ class Evaluator:
         spheres as one element; the general rule elsewhere), "whole" (also
         the cylinder rules on every other open element with a tabulated
         aspect) or "general" (dyadic panels and the log-singular rule
-        everywhere).  far_rule: the far-field rule of elements closed at an
-        end (spheres): "auto" (for each block of targets the coarsest of
-        their 24 x 32, 20 x 32 and own 16 x 32 rules that meets quad_tol
-        there by the criterion's estimates, the 32 x 32 rule nearer) or
-        "base" (the 32 x 32 rule for every target)."""
+        everywhere).  far_rule: "auto" (for each block of targets, the
+        coarsest Gauss x trapezoid rule of every element that meets quad_tol
+        there by the criterion's estimates, else the element's base rule) or
+        "base" (the base rules: own nodes, 32 x 32 for spheres)."""
         lib = load_library()
         opt = _Options()
         lib.csbq_default_options(C.byref(opt))

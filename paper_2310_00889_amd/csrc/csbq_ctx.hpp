@@ -154,9 +154,14 @@ struct csbq_ctx {
     DBuf<int64_t> fpairs;         // per block of the last smooth sum: pairs summed (coarser rules where chosen)
     bool fpairs_ok = false;
     bool far_split = true;        // closed elements' coarser far-field rules where they suffice
-    // host copies of the smooth-sum block list outlive the asynchronous uploads
+    // host copies of the smooth-sum block list outlive the asynchronous uploads;
+    // the device copy is reused while geometry, targets and shape stay
     std::vector<FarTile> h_tiles;
     std::vector<int> h_gnc;
+    bool tiles_valid = false, tiles_native = false;
+    int tiles_tpt = 0, tiles_maxch = 0;
+    int64_t tiles_chunk = 0, tiles_T = -1;
+    std::vector<int64_t> tiles_tr;
     DBuf<unsigned char> cub_tmp;
     // statistics of the last evaluation
     Phase ph[kNPhase];

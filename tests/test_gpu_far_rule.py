@@ -1,10 +1,11 @@
-"""Far-field rules of elements closed at an end (spheres as one element): the
-smooth sum takes, for a block of targets, the coarsest of a sphere's tensor
-rules (24, 20 or its own 16 Gauss-Legendre points in s times 32, 24 or 16
-angles; else 32 x 32) whose distances, by the criterion's estimates, let it
-meet quad_tol beyond them (Section 3.2.1's smooth rule, with the error
-estimates of Section 3.3).  Checked against the oracle and against the same
-evaluation with the 32 x 32 rule everywhere (far_rule="base")."""
+"""Coarser far-field rules of the smooth sum: for a block of targets, each
+element is summed with the coarsest tensor rule whose distances, by the
+criterion's estimates, let it meet quad_tol beyond them (a sphere: 24, 20
+or its own 16 Gauss-Legendre points in s; a wall panel: 16, 12 or 8; times
+32, 24 or 16 angles), else with its base rule (Section 3.2.1's smooth rule,
+with the error estimates of Section 3.3).  Checked against the oracle and
+against the same evaluation with the base rules everywhere
+(far_rule="base")."""
 import numpy as np
 import pytest
 
