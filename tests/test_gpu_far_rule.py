@@ -105,6 +105,43 @@ def test_coarser_rules_on_separated_spheres_fp64(evs):
     assert _rel(uf, ufo) < GATE and np.abs(df - dfo).max() < GATE * smax and np.abs(df).max() < GATE * smax
 
 
+def test_coarser_rules_on_a_pipe_wall_fp64(evs):
+    """A 60-panel torus-arc pipe with a constant density (bands 0), FP64
+    quad_tol 1e-12: the wall panels' coarser rules (12 or 8 points in s, 24 or
+    16 angles) replace their own nodes far from the targets; every node within
+    1e-11 of the evaluation with the base rules, 60 on-surface and 20 interior
+    targets within 1e-10 of the oracle."""
+    ev, base = evs
+    b = synth.pipe_body(n_panels=60)
+    nn = b.n_panels * synth.NS * synth.NT
+    rng = np.random.default_rng(21)
+    sigma = np.tile(rng.standard_normal(3), (nn, 1))
+    sc = synth.Scene([b], synth.NS, synth.NT, sigma, np.zeros((nn, 3)), np.arange(nn, dtype=np.int64),
+                     np.zeros(nn, np.int32), ("wall",), "pipe60")
+    ev.set_geometry(sc)
+    base.set_geometry(sc)
+    us, ud = ev.eval(sc.sigma, None, sc.tgt_node)
+    st = ev.stats()
+    ub, db = base.eval(sc.sigma, None, sc.tgt_node)
+    print("far pairs", st["far_pairs"], "of", st["far_pairs_base"], flush=True)
+    assert st["far_pairs"] < 0.8 * st["far_pairs_base"]
+    assert ev.flags() == 0
+    print("coarser rules vs base rules:", _rel(us, ub), _rel(ud, db), flush=True)
+    assert _rel(us, ub) < 1e-11 and _rel(ud, db) < 1e-11
+    k = rng.choice(nn, 60, replace=False)
+    uso, udo = oracle.evaluate(sc, None, None, sc.tgt_node[k])
+    print("on-surface vs oracle:", _rel(us[k], uso), _rel(ud[k], udo), flush=True)
+    assert _rel(us[k], uso) < GATE and _rel(ud[k], udo) < GATE
+    phi = rng.uniform(0.05, np.pi - 0.05, 20)
+    off = rng.uniform(-0.6, 0.6, (20, 2))
+    x = np.stack([(5.0 + off[:, 0]) * np.cos(phi), (5.0 + off[:, 0]) * np.sin(phi), off[:, 1]], axis=1)
+    uf, df = ev.eval(sc.sigma, x, None)
+    assert ev.flags() == 0
+    ufo, dfo = oracle.evaluate(sc, None, x, -np.ones(len(x), np.int64))
+    print("interior targets vs oracle:", _rel(uf, ufo), _rel(df, dfo), flush=True)
+    assert _rel(uf, ufo) < GATE and _rel(df, dfo) < GATE
+
+
 def test_coarser_rules_under_a_plan(evs):
     """A frozen plan replays the rule choice of its evaluation: apply()
     with a density of the same band equals a fresh evaluation bit for bit
