@@ -1247,6 +1247,35 @@ __device__ inline double contact_root(const double* __restrict__ clq, const doub
     return bernstein_rho(z1.r, fabs(z1.i), -1.0, 1.0);
 }
 
+// The contact zero for a sphere given as one element in its polar angle
+// (x_c = c + a cos(pi t) A, eps = a sin(pi t), t the panel's normalised
+// parameter; the host's shape test admits only such elements): the circle
+// at u = pi t passes through x where D^2 + a^2 = 2 a D cos(u - phi), with
+// D = |x - c| and phi the polar angle of x - c about A, so the zero is
+// u = phi + i acosh(1 + (D - a)^2 / (2 a D)), at xn = 2 u / pi - 1 in the
+// panel's normalised variable: what the secant search converges to, without
+// its iterations.  The end circles give c and a A.  Returns the zero's
+// Bernstein parameter, or 1e300 where the zero is on the real axis (as the
+// search does).
+__device__ inline double sphere_contact_root(const double* __restrict__ cc, const double* x, double* zr, double* zi)
+{
+    const double* p0 = cc;                        // xn = -1 (t = 0): c + a A
+    const double* p1 = cc + (NCIRC - 1) * CIRQ;   // xn = +1 (t = 1): c - a A
+    double r[3], A[3];
+    for (int d = 0; d < 3; ++d) {
+        A[d] = 0.5 * (p0[d] - p1[d]);
+        r[d] = x[d] - 0.5 * (p0[d] + p1[d]);
+    }
+    const double a = sqrt(dot3(A, A)), D = sqrt(dot3(r, r));
+    if (!(a > 0.0) || !(D > 0.0)) return 1e300;
+    const double cphi = fmin(1.0, fmax(-1.0, dot3(r, A) / (a * D)));
+    const double im = 2.0 / PI * acosh1p((D - a) * (D - a) / (2.0 * a * D));
+    if (!(im > 1e-9)) return 1e300;
+    *zr = 2.0 / PI * acos(cphi) - 1.0;
+    *zi = im;
+    return bernstein_rho(*zr, im, -1.0, 1.0);
+}
+
 // normalised parameter of sampled circle k: the panel ends and the GL nodes
 __device__ __forceinline__ double circle_xn(int k)
 {
@@ -1400,7 +1429,8 @@ __global__ __launch_bounds__(128) void k_classify(int64_t P, const int* __restri
     double zr = xd, zi = dc / spd / half;
     const double rho_lin = bernstein_rho(zr, zi, -1.0, 1.0);
     double rr = xd, ri = zi;
-    double rho_root = contact_root(cq, x, xd, fmax(zi, 1e-6), &rr, &ri);
+    double rho_root = inf.shape == SHAPE_SPHERE ? sphere_contact_root(cc, x, &rr, &ri)
+                                                : contact_root(cq, x, xd, fmax(zi, 1e-6), &rr, &ri);
     if (rho_root < rho_lin) {
         zr = rr;
         zi = ri;
