@@ -39,6 +39,7 @@ def test_default_options_without_device():
     lib.csbq_default_options(C.byref(opt))
     assert opt.quad_tol == 1e-12 and opt.precision == 0 and opt.device == 0
     assert opt.kernel == pk.CSBQ_KERNEL_STOKES and opt.srule == pk.CSBQ_SRULE_AUTO
+    assert opt.far_rule == pk.CSBQ_FAR_AUTO
 
 
 def test_options_struct_matches_header():
@@ -58,3 +59,11 @@ def test_unknown_srule_refused_before_the_library():
         pytest.skip("libcsbq.so not built")
     with pytest.raises(pk.CsbqError):
         pk.Evaluator(srule="dyadic-only")
+
+
+def test_unknown_far_rule_refused_before_the_library():
+    import paper_2310_00889_amd as pk
+    if not os.path.exists(pk.LIB_PATH):
+        pytest.skip("libcsbq.so not built")
+    with pytest.raises(pk.CsbqError):
+        pk.Evaluator(far_rule="nearest")
