@@ -403,6 +403,81 @@ static int element_shape(const double* xc, const double* eps, const double* e1, 
     return SHAPE_CYLINDER;
 }
 
+// A torus-arc element (a section of a tube of constant radius r about a
+// circle of radius R > r): centerline x_c = C + R (cos psi U + sin psi V) with
+// psi = psi0 + psi1 xn linear in the panel's normalised variable xn.  Then
+// the classification's contact zero has a closed form.  out[TOR_Q]: C, U, V,
+// R, r, psi0, psi1 and a flag (1 = such an element, else all 0).
+static void element_torus(const double* xc, const double* eps, const double* gx, double* out)
+{
+    auto dot3 = [](const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; };
+    auto cross3 = [](const double* a, const double* b, double* c) {
+        c[0] = a[1] * b[2] - a[2] * b[1];
+        c[1] = a[2] * b[0] - a[0] * b[2];
+        c[2] = a[0] * b[1] - a[1] * b[0];
+    };
+    for (int k = 0; k < TOR_Q; ++k) out[k] = 0.0;
+    const double tol = 1e-11;
+    const double r = eps[0];
+    if (!(r > 0.0)) return;
+    for (int i = 1; i < NS; ++i)
+        if (std::fabs(eps[i] - r) > tol * r) return;
+    // the circle through the first, middle and last centerline points
+    const double* p0 = xc;
+    const double* pm = xc + 3 * (NS / 2);
+    const double* p1 = xc + 3 * (NS - 1);
+    double ab[3], ac[3], n[3];
+    for (int d = 0; d < 3; ++d) {
+        ab[d] = pm[d] - p0[d];
+        ac[d] = p1[d] - p0[d];
+    }
+    cross3(ab, ac, n);
+    const double nn = dot3(n, n);
+    if (!(nn > 1e-24 * dot3(ac, ac) * dot3(ac, ac))) return;   // (nearly) straight
+    double t1[3], t2[3], c[3];
+    cross3(n, ab, t1);
+    cross3(ac, n, t2);
+    for (int d = 0; d < 3; ++d) c[d] = p0[d] + (dot3(ac, ac) * t1[d] + dot3(ab, ab) * t2[d]) / (2.0 * nn);
+    double u[3], v[3], nz[3];
+    for (int d = 0; d < 3; ++d) u[d] = p0[d] - c[d];
+    const double R = std::sqrt(dot3(u, u));
+    if (!(R > r * (1.0 + 1e-6))) return;
+    for (int d = 0; d < 3; ++d) {
+        u[d] /= R;
+        nz[d] = n[d] / std::sqrt(nn);
+    }
+    cross3(nz, u, v);
+    // every point on that circle, at an angle linear in xn
+    double psi[NS], gm = 0.0, pmn = 0.0;
+    for (int i = 0; i < NS; ++i) {
+        double q[3];
+        for (int d = 0; d < 3; ++d) q[d] = xc[3 * i + d] - c[d];
+        if (std::fabs(dot3(q, nz)) > tol * R || std::fabs(std::sqrt(dot3(q, q)) - R) > tol * R) return;
+        psi[i] = std::atan2(dot3(q, v), dot3(q, u));
+        gm += gx[i] / NS;
+        pmn += psi[i] / NS;
+    }
+    double sxy = 0.0, sxx = 0.0;
+    for (int i = 0; i < NS; ++i) {
+        sxy += (gx[i] - gm) * (psi[i] - pmn);
+        sxx += (gx[i] - gm) * (gx[i] - gm);
+    }
+    const double psi1 = sxy / sxx, psi0 = pmn - psi1 * gm;
+    if (!(std::fabs(psi1) > 0.0) || std::fabs(psi1) > 1.5) return;   // an arc of at most 3 rad
+    for (int i = 0; i < NS; ++i)
+        if (std::fabs(psi[i] - (psi0 + psi1 * gx[i])) > tol) return;
+    for (int d = 0; d < 3; ++d) {
+        out[d] = c[d];
+        out[3 + d] = u[d];
+        out[6 + d] = v[d];
+    }
+    out[9] = R;
+    out[10] = r;
+    out[11] = psi0;
+    out[12] = psi1;
+    out[TOR_Q - 1] = 1.0;
+}
+
 int csbq_create(const csbq_options* opt, csbq_ctx** out)
 {
     if (!out) return CSBQ_EINVAL;
@@ -787,12 +862,18 @@ int csbq_set_geometry_batch(csbq_ctx* ctx, int32_t n_bodies, const int32_t* body
         HIPC(hipMemcpy(hinf.data(), ctx->info.p, (size_t)E * sizeof(ElemInfo), hipMemcpyDeviceToHost));
         // shapes with tabulated whole-element singular s-rules
         int64_t nshape[3] = {0, 0, 0};
+        std::vector<double> htor((size_t)E * TOR_Q);
         for (int64_t e = 0; e < E; ++e) {
+            element_torus(&h_xc[(size_t)e * NS * 3], &h_eps[(size_t)e * NS], ctx->gx, &htor[(size_t)e * TOR_Q]);
             hinf[e].shape = element_shape(&h_xc[(size_t)e * NS * 3], &h_eps[(size_t)e * NS], &h_e1[(size_t)e * NS * 3],
                                           ctx->gx, ctx->Dgl);
             ++nshape[hinf[e].shape];
         }
         HIPC(hipMemcpy(ctx->info.p, hinf.data(), (size_t)E * sizeof(ElemInfo), hipMemcpyHostToDevice));
+        ALLOC(ctx->tor, htor.size());
+        HIPC(hipMemcpy(ctx->tor.p, htor.data(), htor.size() * sizeof(double), hipMemcpyHostToDevice));
+        ctx->n_tor = 0;
+        for (int64_t e = 0; e < E; ++e) ctx->n_tor += htor[(size_t)e * TOR_Q + TOR_Q - 1] != 0.0;
         ctx->n_cyl = nshape[SHAPE_CYLINDER];
         ctx->n_sph = nshape[SHAPE_SPHERE];
         // the base rules, then each element's coarser far-field rules (rule k
@@ -1457,11 +1538,13 @@ int csbq_eval_batch(csbq_ctx* ctx, const double* sigma, int64_t T, const double*
         }
         ctx->last_esc = nsel;
         LCHK(launch_classify(st, nsel, ctx->gsel.p, ctx->pe.p, ctx->pt.p, ctx->xt.p, T, tn, ctx->clq.p,
-                             ctx->circ.p, ctx->gridc.p, ctx->info.p, ctx->band.p, ctx->gc, ctx->tier.p, ctx->cls.p));
+                             ctx->circ.p, ctx->gridc.p, ctx->info.p, ctx->tor.p, ctx->band.p, ctx->gc, ctx->tier.p,
+                             ctx->cls.p));
     } else {
         ctx->last_esc = -1;
         LCHK(launch_classify(st, P, ctx->perm.p, ctx->pe.p, ctx->pt.p, ctx->xt.p, T, tn, ctx->clq.p, ctx->circ.p,
-                             ctx->gridc.p, ctx->info.p, ctx->band.p, ctx->gc, ctx->tier.p, ctx->cls.p));
+                             ctx->gridc.p, ctx->info.p, ctx->tor.p, ctx->band.p, ctx->gc, ctx->tier.p,
+                             ctx->cls.p));
     }
     HIPC(hipEventRecord(ctx->ph[3].b, st));
     // buckets: pairs sorted by (tier, element); runs give the per-element segments
@@ -2095,8 +2178,9 @@ int csbq_stats(const csbq_ctx* ctx, char* buf, int64_t cap)
     s += ctx->opt.srule == CSBQ_SRULE_AUTO ? ", \"srule\": \"auto\""
          : ctx->opt.srule == CSBQ_SRULE_WHOLE ? ", \"srule\": \"whole\"" : ", \"srule\": \"general\"";
     if (ctx->have_geom) {
-        std::snprintf(tmp, sizeof tmp, ", \"elements_cylinder\": %lld, \"elements_sphere\": %lld",
-                      (long long)ctx->n_cyl, (long long)ctx->n_sph);
+        std::snprintf(tmp, sizeof tmp,
+                      ", \"elements_cylinder\": %lld, \"elements_sphere\": %lld, \"elements_torus_arc\": %lld",
+                      (long long)ctx->n_cyl, (long long)ctx->n_sph, (long long)ctx->n_tor);
         s += tmp;
     }
     if (ctx->plan.valid) {

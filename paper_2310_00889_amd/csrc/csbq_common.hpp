@@ -94,6 +94,10 @@ struct ElemInfo {
 // parametrisation with a constant e1
 enum : int { SHAPE_OTHER = 0, SHAPE_CYLINDER = 1, SHAPE_SPHERE = 2 };
 
+// per element, the parameters of a torus-arc element (see the host's test):
+// C(3), U(3), V(3), R, r, psi0, psi1, unused, flag (1: such an element)
+constexpr int TOR_Q = 16;
+
 // one block of the smooth sum: up to 256 x (targets per thread) consecutive
 // targets of one group against a chunk of that group's sources.  A chunk is
 // either a plain source range [s0, s0 + sn) or, when e1 > e0, the far-field

@@ -97,6 +97,8 @@ struct csbq_ctx {
     // (rule k of element e at loff[k E + e], -1: none)
     DBuf<double> Lfar[NFS], farx[NFS], farw[NFS];
     DBuf<int64_t> loff;
+    DBuf<double> tor;   // torus-arc parameters per element (TOR_Q), for the classification
+    int64_t n_tor = 0;
     bool far_used[NFL] = {};
     // far-field (base) source set
     int64_t Nb = 0;         // base sources: the base rules, then the elements' coarser far-field rules

@@ -1276,6 +1276,62 @@ __device__ inline double sphere_contact_root(const double* __restrict__ cc, cons
     return bernstein_rho(*zr, im, -1.0, 1.0);
 }
 
+__device__ __forceinline__ cx csqrt_(cx z)
+{
+    const double m = hypot(z.r, z.i);
+    return {sqrt(0.5 * (m + z.r)), copysign(sqrt(0.5 * fmax(m - z.r, 0.0)), z.i)};
+}
+
+// principal arccosine: -i log(z + i sqrt(1 - z^2))
+__device__ __forceinline__ cx cacos_(cx z)
+{
+    const cx s = csqrt_(csub({1.0, 0.0}, cmul(z, z)));
+    const cx t = {z.r - s.i, z.i + s.r};
+    return {atan2(t.i, t.r), -log(hypot(t.r, t.i))};
+}
+
+// The contact zero for a torus-arc element (centerline C + R (cos psi U +
+// sin psi V), psi = psi0 + psi1 xn, constant radius r; certified by the
+// host): with the target at azimuth psi_x, distance P from the axis through
+// C along U x V and height Z, the contact function is a quadratic in
+// w = P cos(psi - psi_x):
+//   4 (R^2 - r^2) w^2 - 4 R (A - 2 r^2) w + A^2 - 4 r^2 (R^2 + Z^2),
+//   A = P^2 + R^2 + Z^2 + r^2,
+// so its zeros are psi = psi_x +- arccos(w / P) for its two roots w.  Of
+// these, the one with the smallest Bernstein parameter in xn; 1e300 where
+// none is off the real axis (as the search does).
+__device__ inline double torus_contact_root(const double* __restrict__ tp, const double* x, double* zr, double* zi)
+{
+    const double R = tp[9], r = tp[10], psi0 = tp[11], psi1 = tp[12];
+    double dv[3], nz[3];
+    for (int d = 0; d < 3; ++d) dv[d] = x[d] - tp[d];
+    cross3(tp + 3, tp + 6, nz);
+    const double X = dot3(dv, tp + 3), Y = dot3(dv, tp + 6), Z = dot3(dv, nz);
+    const double P2 = X * X + Y * Y, P = sqrt(P2);
+    if (!(P > 1e-12 * R)) return 1e300;
+    const double psx = atan2(Y, X);
+    const double A = P2 + R * R + Z * Z + r * r;
+    const double a2 = 4.0 * (R * R - r * r), a1 = -4.0 * R * (A - 2.0 * r * r);
+    const double a0 = A * A - 4.0 * r * r * (R * R + Z * Z);
+    const cx sq = csqrt_({a1 * a1 - 4.0 * a2 * a0, 0.0});
+    double best = 1e300;
+    for (int k = 0; k < 2; ++k) {
+        const cx w = {(-a1 + (k ? -sq.r : sq.r)) / (2.0 * a2), (k ? -sq.i : sq.i) / (2.0 * a2)};
+        const cx al = cacos_({w.r / P, w.i / P});
+        for (int sg = -1; sg <= 1; sg += 2) {
+            const double xr = (psx + sg * al.r - psi0) / psi1, xi = fabs(sg * al.i / psi1);
+            if (!(xi > 1e-9)) continue;
+            const double rho = bernstein_rho(xr, xi, -1.0, 1.0);
+            if (rho < best) {
+                best = rho;
+                *zr = xr;
+                *zi = xi;
+            }
+        }
+    }
+    return best;
+}
+
 // normalised parameter of sampled circle k: the panel ends and the GL nodes
 __device__ __forceinline__ double circle_xn(int k)
 {
@@ -1316,8 +1372,9 @@ __global__ __launch_bounds__(128) void k_classify(int64_t P, const int* __restri
                            const int* __restrict__ pt, const double* __restrict__ xt, int64_t T,
                            const int64_t* __restrict__ tnode, const double* __restrict__ clq,
                            const double* __restrict__ circ, const double* __restrict__ grid,
-                           const ElemInfo* __restrict__ info, const int* __restrict__ band, GateConsts gc,
-                           int8_t* __restrict__ tier, double* __restrict__ cls)
+                           const ElemInfo* __restrict__ info, const double* __restrict__ tor,
+                           const int* __restrict__ band, GateConsts gc, int8_t* __restrict__ tier,
+                           double* __restrict__ cls)
 {
     const int64_t ii = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (ii >= P) return;
@@ -1429,7 +1486,9 @@ __global__ __launch_bounds__(128) void k_classify(int64_t P, const int* __restri
     double zr = xd, zi = dc / spd / half;
     const double rho_lin = bernstein_rho(zr, zi, -1.0, 1.0);
     double rr = xd, ri = zi;
+    const double* tp = tor + (int64_t)e * TOR_Q;
     double rho_root = inf.shape == SHAPE_SPHERE ? sphere_contact_root(cc, x, &rr, &ri)
+                      : tp[TOR_Q - 1] != 0.0    ? torus_contact_root(tp, x, &rr, &ri)
                                                 : contact_root(cq, x, xd, fmax(zi, 1e-6), &rr, &ri);
     if (rho_root < rho_lin) {
         zr = rr;
@@ -2753,11 +2812,11 @@ int launch_grid_circles(hipStream_t st, int E, const double* clq, double* grid)
 
 int launch_classify(hipStream_t st, int64_t P, const int* perm, const int* pe, const int* pt, const double* xt,
                     int64_t T, const int64_t* tnode, const double* clq, const double* circ, const double* grid,
-                    const ElemInfo* info, const int* band, GateConsts gc, int8_t* tier, double* cls)
+                    const ElemInfo* info, const double* tor, const int* band, GateConsts gc, int8_t* tier, double* cls)
 {
     if (P == 0) return 0;
     hipLaunchKernelGGL(k_classify, dim3((unsigned)((P + 127) / 128)), dim3(128), 0, st, P, perm, pe, pt, xt, T, tnode,
-                       clq, circ, grid, info, band, gc, tier, cls);
+                       clq, circ, grid, info, tor, band, gc, tier, cls);
     LAUNCH_CHECK();
     return 0;
 }

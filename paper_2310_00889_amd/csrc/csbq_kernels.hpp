@@ -48,7 +48,7 @@ int launch_search(hipStream_t st, int64_t T, const int* tgroup, const int* gel, 
 int launch_grid_circles(hipStream_t st, int E, const double* clq, double* grid);
 int launch_classify(hipStream_t st, int64_t P, const int* perm, const int* pe, const int* pt, const double* xt,
                     int64_t T, const int64_t* tnode, const double* clq, const double* circ, const double* grid,
-                    const ElemInfo* info,
+                    const ElemInfo* info, const double* tor,
                     const int* band, GateConsts gc, int8_t* tier, double* cls);
 int launch_iota(hipStream_t st, int64_t P, int* v);
 int launch_tier_keys(hipStream_t st, int64_t P, int E, const int8_t* tier, const int* pe, int* key, int* val);
