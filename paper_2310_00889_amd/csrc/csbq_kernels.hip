@@ -1332,6 +1332,32 @@ __device__ inline double torus_contact_root(const double* __restrict__ tp, const
     return best;
 }
 
+// Closest circle and fastest trapezoid decay for a sphere element (as in
+// sphere_contact_root: circles at u = pi t about the axis A through c, radius
+// a sin u).  The target's distance from the axis, rho, is the same for every
+// circle, so d^2(u) = (rho - a sin u)^2 + (z - a cos u)^2 (z its height along
+// A) is least at the target's polar angle, (D - a)^2, and
+// cosh a - 1 = d^2(u) / (2 rho a sin u) is least where cos u = 2 a z / (D^2 + a^2).
+__device__ inline void sphere_minima(const double* __restrict__ cc, const double* x, double* d2c, double* xd,
+                                     double* chac)
+{
+    const double* p0 = cc;                        // xn = -1: c + a A
+    const double* p1 = cc + (NCIRC - 1) * CIRQ;   // xn = +1: c - a A
+    double r[3], A[3];
+    for (int d = 0; d < 3; ++d) {
+        A[d] = 0.5 * (p0[d] - p1[d]);
+        r[d] = x[d] - 0.5 * (p0[d] + p1[d]);
+    }
+    const double a = sqrt(dot3(A, A)), D2 = dot3(r, r), D = sqrt(D2);
+    if (!(a > 0.0) || !(D > 0.0)) return;   // keep the sampled minima
+    const double z = dot3(r, A) / a, rho = sqrt(fmax(0.0, D2 - z * z));
+    *d2c = (D - a) * (D - a);
+    *xd = 2.0 / PI * acos(fmin(1.0, fmax(-1.0, z / D))) - 1.0;
+    const double cu = 2.0 * a * z / (D2 + a * a), su = sqrt(fmax(0.0, 1.0 - cu * cu));
+    const double dr = rho - a * su, dz = z - a * cu;
+    *chac = (rho > 0.0 && su > 0.0) ? (dr * dr + dz * dz) / (2.0 * rho * a * su) : 1e300;
+}
+
 // normalised parameter of sampled circle k: the panel ends and the GL nodes
 __device__ __forceinline__ double circle_xn(int k)
 {
@@ -1406,9 +1432,12 @@ __global__ __launch_bounds__(128) void k_classify(int64_t P, const int* __restri
     }
     // closest circle (minimum of d^2 over the two GL gaps around the sampled
     // minimum) and fastest trapezoid decay (minimum of cosh a - 1, likewise):
-    // for each, a 9-point grid over its bracket, then two parabolic steps
+    // for each, a 9-point grid over its bracket, then two parabolic steps; on
+    // a sphere element both minima in closed form
     double d2c = bd, chac = ba, xd = circle_xn(kd);
-    {
+    if (inf.shape == SHAPE_SPHERE) {
+        sphere_minima(cc, x, &d2c, &xd, &chac);
+    } else {
         auto eval = [&](double xn, double* d2, double* cha) {
             double X[3], tt[3], EE;
             circle_at_x(cq, xn, X, tt, &EE);
