@@ -1358,6 +1358,60 @@ __device__ inline void sphere_minima(const double* __restrict__ cc, const double
     *chac = (rho > 0.0 && su > 0.0) ? (dr * dr + dz * dz) / (2.0 * rho * a * su) : 1e300;
 }
 
+// Closest circle and fastest trapezoid decay for a torus-arc element (as in
+// torus_contact_root).  For the circle at psi = psi_x + delta, with
+// c = cos delta and q = |(P c - R, Z)| the target's distance from its centre
+// within its plane, d^2 = P^2 sin^2 delta + (q - r)^2 and cosh a - 1 =
+// d^2 / (2 q r) = (P^2 + R^2 + Z^2 + r^2 - 2 P R c) / (2 q r) - 1, whose only
+// critical point in c is P c - R = -2 R Z^2 / (P^2 - R^2 + Z^2 + r^2), while
+// d^2 is least at delta = 0.  The minima over the panel's angles are among
+// those points and the panel ends.
+__device__ inline void torus_minima(const double* __restrict__ tp, const double* x, double* d2c, double* xd,
+                                    double* chac)
+{
+    const double R = tp[9], r = tp[10], psi0 = tp[11], psi1 = tp[12];
+    double dv[3], nz[3];
+    for (int d = 0; d < 3; ++d) dv[d] = x[d] - tp[d];
+    cross3(tp + 3, tp + 6, nz);
+    const double X = dot3(dv, tp + 3), Y = dot3(dv, tp + 6), Z = dot3(dv, nz);
+    const double P = sqrt(X * X + Y * Y);
+    if (!(P > 1e-12 * R)) return;   // keep the sampled minima
+    const double psx = atan2(Y, X);
+    // the panel's angles relative to the target's, centred in (-pi, pi]
+    const double pm = psi0, hw = fabs(psi1);
+    const double dm = remainder(pm - psx, 2.0 * PI), da = dm - hw, db = dm + hw;
+    double cand[5];
+    int nc = 0;
+    cand[nc++] = da;
+    cand[nc++] = db;
+    if (da < 0.0 && db > 0.0) cand[nc++] = 0.0;
+    const double den = P * P - R * R + Z * Z + r * r;
+    if (den != 0.0) {
+        const double cs = (R - 2.0 * R * Z * Z / den) / P;
+        if (cs >= -1.0 && cs <= 1.0) {
+            const double al = acos(cs);
+            if (al >= da && al <= db) cand[nc++] = al;
+            if (-al >= da && -al <= db) cand[nc++] = -al;
+        }
+    }
+    double bd = 1e300, ba = 1e300, bdel = 0.0;
+    for (int k = 0; k < nc; ++k) {
+        double sn, c;
+        sincos(cand[k], &sn, &c);
+        const double q = hypot(P * c - R, Z), dq = q - r;
+        const double d2 = P * P * sn * sn + dq * dq;
+        const double cha = q > 0.0 ? d2 / (2.0 * q * r) : 1e300;
+        if (d2 < bd) {
+            bd = d2;
+            bdel = cand[k];
+        }
+        ba = fmin(ba, cha);
+    }
+    *d2c = bd;
+    *chac = ba;
+    *xd = fmin(1.0, fmax(-1.0, (bdel - dm) / psi1));
+}
+
 // normalised parameter of sampled circle k: the panel ends and the GL nodes
 __device__ __forceinline__ double circle_xn(int k)
 {
@@ -1435,8 +1489,11 @@ __global__ __launch_bounds__(128) void k_classify(int64_t P, const int* __restri
     // for each, a 9-point grid over its bracket, then two parabolic steps; on
     // a sphere element both minima in closed form
     double d2c = bd, chac = ba, xd = circle_xn(kd);
+    const double* tp = tor + (int64_t)e * TOR_Q;
     if (inf.shape == SHAPE_SPHERE) {
         sphere_minima(cc, x, &d2c, &xd, &chac);
+    } else if (tp[TOR_Q - 1] != 0.0) {
+        torus_minima(tp, x, &d2c, &xd, &chac);
     } else {
         auto eval = [&](double xn, double* d2, double* cha) {
             double X[3], tt[3], EE;
@@ -1515,7 +1572,6 @@ __global__ __launch_bounds__(128) void k_classify(int64_t P, const int* __restri
     double zr = xd, zi = dc / spd / half;
     const double rho_lin = bernstein_rho(zr, zi, -1.0, 1.0);
     double rr = xd, ri = zi;
-    const double* tp = tor + (int64_t)e * TOR_Q;
     double rho_root = inf.shape == SHAPE_SPHERE ? sphere_contact_root(cc, x, &rr, &ri)
                       : tp[TOR_Q - 1] != 0.0    ? torus_contact_root(tp, x, &rr, &ri)
                                                 : contact_root(cq, x, xd, fmax(zi, 1e-6), &rr, &ri);
