@@ -1516,8 +1516,8 @@ int csbq_eval_batch(csbq_ctx* ctx, const double* sigma, int64_t T, const double*
         ALLOC(ctx->gflag, (size_t)P + 1);
         ALLOC(ctx->gsel, (size_t)P + 1);
         ALLOC(ctx->gnsel, 1);
-        LCHK(launch_gate_features(st, P, ctx->pe.p, ctx->pt.p, ctx->xt.p, T, tn, ctx->circ.p, ctx->info.p,
-                                  ctx->band.p, (float)std::log10(ctx->gc.tol), ctx->gfeat.p));
+        LCHK(launch_gate_features(st, P, ctx->perm.p, ctx->pe.p, ctx->pt.p, ctx->xt.p, T, tn, ctx->circ.p,
+                                  ctx->info.p, ctx->band.p, (float)std::log10(ctx->gc.tol), ctx->gfeat.p));
         LCHK(launch_gate_mlp(st, P, ctx->gfeat.p, ctx->gate_wfrag.p, ctx->gate_bias.p, ctx->gate_tau, ctx->gtier.p,
                              ctx->gesc.p, nullptr));
         LCHK(launch_gate_select(st, P, ctx->perm.p, ctx->pe.p, ctx->info.p, ctx->gesc.p, ctx->gtier.p, ctx->tier.p,
@@ -2062,8 +2062,8 @@ int csbq_gate_dataset(csbq_ctx* ctx, const double* sigma, int64_t T, const doubl
     const int64_t* tn = tgt_node ? ctx->tn_d.p : nullptr;
     // features of every pair
     ALLOC(ctx->gfeat, (size_t)P * GATE_NF + GATE_NF);
-    LCHK(launch_gate_features(st, P, ctx->pe.p, ctx->pt.p, ctx->xt.p, T, tn, ctx->circ.p, ctx->info.p, ctx->band.p,
-                              (float)std::log10(ctx->gc.tol), ctx->gfeat.p));
+    LCHK(launch_gate_features(st, P, ctx->perm.p, ctx->pe.p, ctx->pt.p, ctx->xt.p, T, tn, ctx->circ.p, ctx->info.p,
+                              ctx->band.p, (float)std::log10(ctx->gc.tol), ctx->gfeat.p));
     // every pair through every tier: upsampled rules by element runs of the
     // element-major order, special quadrature on all
     std::vector<int> hperm((size_t)P), hpe((size_t)P);

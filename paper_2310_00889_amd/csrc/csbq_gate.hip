@@ -38,13 +38,15 @@ __device__ __forceinline__ float clampf(float v, float lo, float hi) { return fm
 // the position of the closest circle, the element's shape and the density's
 // band limits.  An on-surface target on its own element gets feature 11 = 1.
 // ---------------------------------------------------------------------------
-__global__ void k_gate_features(int64_t P, const int* __restrict__ pe, const int* __restrict__ pt,
-                                const double* __restrict__ xt, int64_t T, const int64_t* __restrict__ tnode,
-                                const double* __restrict__ circ, const ElemInfo* __restrict__ info,
-                                const int* __restrict__ band, float ltol, float* __restrict__ feat)
+__global__ void k_gate_features(int64_t P, const int* __restrict__ order, const int* __restrict__ pe,
+                                const int* __restrict__ pt, const double* __restrict__ xt, int64_t T,
+                                const int64_t* __restrict__ tnode, const double* __restrict__ circ,
+                                const ElemInfo* __restrict__ info, const int* __restrict__ band, float ltol,
+                                float* __restrict__ feat)
 {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P) return;
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= P) return;
+    const int64_t p = order ? (int64_t)order[q] : q;
     const int e = pe[p];
     const int64_t t = pt[p];
     const ElemInfo inf = info[e];
@@ -385,13 +387,13 @@ __global__ void k_gate_labels(int64_t P, const double* __restrict__ c1, const do
         if (e_ != hipSuccess) return (int)e_;           \
     } while (0)
 
-int launch_gate_features(hipStream_t st, int64_t P, const int* pe, const int* pt, const double* xt, int64_t T,
-                         const int64_t* tnode, const double* circ, const ElemInfo* info, const int* band, float ltol,
-                         float* feat)
+int launch_gate_features(hipStream_t st, int64_t P, const int* order, const int* pe, const int* pt, const double* xt,
+                         int64_t T, const int64_t* tnode, const double* circ, const ElemInfo* info, const int* band,
+                         float ltol, float* feat)
 {
     if (P == 0) return 0;
-    hipLaunchKernelGGL(k_gate_features, dim3((unsigned)((P + 127) / 128)), dim3(128), 0, st, P, pe, pt, xt, T, tnode,
-                       circ, info, band, ltol, feat);
+    hipLaunchKernelGGL(k_gate_features, dim3((unsigned)((P + 127) / 128)), dim3(128), 0, st, P, order, pe, pt, xt, T,
+                       tnode, circ, info, band, ltol, feat);
     GATE_LAUNCH_CHECK();
     return 0;
 }

@@ -39,9 +39,12 @@ constexpr int GATE_NFRAG = GATE_FRAG_W1 + 2 * GATE_FRAG_W2 + GATE_FRAG_W4;   // 
 constexpr int GATE_FRAG_ELEMS = 64 * 4;  // bf16 per fragment (4 per lane)
 constexpr int GATE_NBIAS = 3 * GATE_H + 16;
 
-int launch_gate_features(hipStream_t st, int64_t P, const int* pe, const int* pt, const double* xt, int64_t T,
-                         const int64_t* tnode, const double* circ, const ElemInfo* info, const int* band, float ltol,
-                         float* feat);
+// order (if not null): the pairs in the order the threads take them (the
+// element-major order, so a wavefront's lanes share the element's circles);
+// feat is indexed by pair either way
+int launch_gate_features(hipStream_t st, int64_t P, const int* order, const int* pe, const int* pt, const double* xt,
+                         int64_t T, const int64_t* tnode, const double* circ, const ElemInfo* info, const int* band,
+                         float ltol, float* feat);
 int launch_gate_mlp(hipStream_t st, int64_t P, const float* feat, const uint16_t* wfrag, const float* bias,
                     float tau_esc, int8_t* tier, uint8_t* esc, float* logits);
 int launch_gate_train_step(hipStream_t st, int nblk, int spb, int64_t off, int64_t n, const int64_t* perm,
