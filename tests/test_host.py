@@ -1,6 +1,6 @@
 """Host-side logic that runs without a GPU: batch assembly, the learned gate's
-weight files and constants, the measured-traffic record, and a clean failure
-when no device is present."""
+weight files and constants, the measured-traffic record, the benchmark's
+one-GPU check, and a clean failure when no device is present."""
 import json
 import os
 import re
@@ -79,6 +79,19 @@ def test_traffic_records_are_complete():
         assert os.path.basename(path) == f"traffic_{rec['kernel']}_pipe100_spheres200_{rec['precision']}.json"
         expect = rec["fetch_kib"] * 1024 / rec["fetch_factor"] + rec["write_kib"] * 1024 / rec["write_factor"]
         assert abs(expect - rec["traffic_bytes"]) < 1e-6 * expect
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark is a one-GPU measurement: --gpus N with N != 1 exits
+    with status 2 and a JSON error line before touching any device."""
+    import subprocess
+    import sys
+    for n in ("2", "8"):
+        r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", n], capture_output=True,
+                           text=True, timeout=120, cwd=ROOT)
+        assert r.returncode == 2, (n, r.returncode, r.stderr[-500:])
+        line = json.loads(r.stdout.strip().splitlines()[-1])
+        assert "one GPU" in line["error"]
 
 
 def test_binding_checks_sizes_and_types_before_the_c_abi():
