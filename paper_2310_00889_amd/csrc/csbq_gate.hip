@@ -105,6 +105,10 @@ __global__ void k_gate_features(int64_t P, const int* __restrict__ order, const 
 // fragments as one 8-byte load per lane.
 // ---------------------------------------------------------------------------
 constexpr int GM_WAVES = 4;
+// s_waitcnt immediate that waits for the wave's LDS operations only
+// (lgkmcnt 0; vmcnt and expcnt at their maxima, so a feature load in flight
+// is not waited for)
+constexpr int LDS_DONE = 0xC07F;
 
 __global__ __launch_bounds__(64 * GM_WAVES) void k_gate_mlp(int64_t P, const float* __restrict__ feat,
                                                             const uint16_t* __restrict__ wfrag,
@@ -122,15 +126,25 @@ __global__ __launch_bounds__(64 * GM_WAVES) void k_gate_mlp(int64_t P, const flo
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int r = lane & 15, q = lane >> 4;   // A row / B,D column; k quarter
     const v4s* wf = reinterpret_cast<const v4s*>(wl);
-    const int64_t ntile = (P + 15) / 16;
-    for (int64_t tile = (int64_t)blockIdx.x * GM_WAVES + wv; tile < ntile; tile += (int64_t)gridDim.x * GM_WAVES) {
+    const int64_t ntile = (P + 15) / 16, tstep = (int64_t)gridDim.x * GM_WAVES;
+    // lane (r, q) holds features 4q .. 4q + 3 of the tile's pair r; the next
+    // tile's are loaded while this one is computed
+    auto load_feat = [&](int64_t tl) {
+        const int64_t p = tl * 16 + r;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (tl < ntile && p < P) v = reinterpret_cast<const float4*>(feat + p * GATE_NF)[q];
+        return v;
+    };
+    float4 vnext = load_feat((int64_t)blockIdx.x * GM_WAVES + wv);
+    for (int64_t tile = (int64_t)blockIdx.x * GM_WAVES + wv; tile < ntile; tile += tstep) {
         const int64_t p0 = tile * 16;
+        const float4 v = vnext;
+        vnext = load_feat(tile + tstep);
+        // feature 11 (own element) of pair r sits in lane r + 32 (q = 2, w)
+        const float own = __shfl(v.w, r + 32, 64);
         // layer 1: A = features of the tile's 16 pairs
         v4s a;
         {
-            const int64_t p = p0 + r;
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (p < P) v = reinterpret_cast<const float4*>(feat + p * GATE_NF)[q];
             a[0] = (short)f2bf(v.x);
             a[1] = (short)f2bf(v.y);
             a[2] = (short)f2bf(v.z);
@@ -170,7 +184,7 @@ __global__ __launch_bounds__(64 * GM_WAVES) void k_gate_mlp(int64_t P, const flo
                     hl[wv][4 * q + i][nb * 16 + r] = f2bf(h);
                 }
             bo += GATE_H;
-            __builtin_amdgcn_s_waitcnt(0);
+            __builtin_amdgcn_s_waitcnt(LDS_DONE);
             __builtin_amdgcn_wave_barrier();
         }
         // output layer: 64 -> 16 (GATE_NO used)
@@ -182,7 +196,7 @@ __global__ __launch_bounds__(64 * GM_WAVES) void k_gate_mlp(int64_t P, const flo
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) zl[wv][4 * q + i][r] = z[i] + bl[bo + r];
-        __builtin_amdgcn_s_waitcnt(0);
+        __builtin_amdgcn_s_waitcnt(LDS_DONE);
         __builtin_amdgcn_wave_barrier();
         if (lane < 16) {
             const int64_t p = p0 + lane;
@@ -199,7 +213,7 @@ __global__ __launch_bounds__(64 * GM_WAVES) void k_gate_mlp(int64_t P, const flo
                     if (s[k] > 0.5f) tr = k + 1;
                 const bool up = tr < GATE_NO && s[tr] > tau_esc;   // risk that the tier is too low
                 tier[p] = (int8_t)tr;
-                esc[p] = (uint8_t)((up || tr == TIER_FULL || feat[p * GATE_NF + 11] > 0.5f) ? 1 : 0);
+                esc[p] = (uint8_t)((up || tr == TIER_FULL || own > 0.5f) ? 1 : 0);
             }
         }
         __builtin_amdgcn_wave_barrier();
